@@ -1,0 +1,317 @@
+"""fV-SRN CPU oracle (FP64) -- TEST INFRASTRUCTURE ONLY.
+
+ctypes front end of ``liboracle.so`` built from ``fvsrn_oracle.c``. Only the
+tests, the smoke check and the CPU-baseline leg of the benchmark may import
+this package. It shares no code with the GPU library: it takes plain numpy
+arrays and the plain-data input descriptions of
+``paper_2112_01579_amd.inputs`` and marshals them into its own FP64 structs.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fvsrn_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+ACT = {"sine": 0, "snakealt": 1, "identity": 2}
+FIELD_NET, FIELD_DENSE, FIELD_ML = 0, 1, 2
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with gcc (-O2, OpenMP, IEEE arithmetic)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(
+        os.path.getmtime(_SRC), os.path.getmtime(os.path.join(_HERE, "fvsrn_oracle.h"))
+    ):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-Wall", "-Wextra",
+             "-Wno-unused-parameter", "-o", tmp, _SRC, "-lm"]
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Net(C.Structure):
+    _fields_ = [("R", C.c_int32), ("F", C.c_int32), ("K", C.c_int32), ("L", C.c_int32),
+                ("c", C.c_int32), ("H", C.c_int32), ("act", C.c_int32), ("pad_", C.c_int32),
+                ("latent", C.POINTER(C.c_double)), ("weights", C.POINTER(C.c_double)),
+                ("key_times", C.POINTER(C.c_double))]
+
+
+class _TF(C.Structure):
+    _fields_ = [("n", C.c_int32), ("pad_", C.c_int32), ("density", C.c_double * 16),
+                ("rgba", (C.c_double * 4) * 16), ("opacity_scale", C.c_double)]
+
+
+class _Cam(C.Structure):
+    _fields_ = [("ortho", C.c_int32), ("width", C.c_int32), ("height", C.c_int32),
+                ("pad_", C.c_int32), ("eye", C.c_double * 3), ("target", C.c_double * 3),
+                ("up", C.c_double * 3), ("fov_y_deg", C.c_double),
+                ("ortho_half_extent", C.c_double), ("time", C.c_double)]
+
+
+class _March(C.Structure):
+    _fields_ = [("step", C.c_double), ("fixed_steps", C.c_int32), ("phong", C.c_int32),
+                ("ert_eps", C.c_double), ("ka", C.c_double), ("kd", C.c_double),
+                ("ks", C.c_double), ("shininess", C.c_double)]
+
+
+class _Field(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("net", C.POINTER(_Net)), ("vol", C.POINTER(C.c_double)),
+                ("ml_fm", C.c_double), ("ml_alpha", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        D, P, I64, I32 = C.c_double, C.POINTER(C.c_double), C.c_int64, C.c_int32
+        NP = C.POINTER(_Net)
+        sig = {
+            "orc_num_weights": (I64, [NP]),
+            "orc_input_width": (I32, [NP]),
+            "orc_latent": (C.c_int, [NP, P, D, P, P]),
+            "orc_features": (C.c_int, [NP, P, D, P, P]),
+            "orc_mlp_logit": (D, [NP, P]),
+            "orc_density": (D, [NP, P, D]),
+            "orc_density_grad_fwd": (D, [NP, P, D, P]),
+            "orc_density_grad_rev": (D, [NP, P, D, P]),
+            "orc_eval_points": (C.c_int, [NP, P, I64, D, P]),
+            "orc_grad_points": (C.c_int, [NP, P, I64, D, P, P]),
+            "orc_dense_sample": (D, [P, C.c_int, C.c_int, C.c_int, P]),
+            "orc_dense_eval_points": (C.c_int, [P, C.c_int, C.c_int, C.c_int, P, I64, P]),
+            "orc_marschner_lobb": (D, [D, D, P, P]),
+            "orc_field_density": (D, [C.POINTER(_Field), P, D, P]),
+            "orc_tf_eval": (C.c_int, [C.POINTER(_TF), D, P]),
+            "orc_camera_ray": (C.c_int, [C.POINTER(_Cam), C.c_int, C.c_int, P, P]),
+            "orc_box_clip": (C.c_int, [P, P, P, P]),
+            "orc_render": (C.c_int, [C.POINTER(_Field), C.POINTER(_TF), C.POINTER(_Cam), C.c_int,
+                                     C.POINTER(_March), P, C.POINTER(C.c_int64), I64,
+                                     C.POINTER(C.c_int64), C.c_int]),
+            "orc_train_grads": (C.c_int, [NP, P, I64, P, P, P, P, P]),
+            "orc_adam": (C.c_int, [P, P, P, P, I64, D, D, D, D, I32]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(_lib, name)
+            f.restype, f.argtypes = res, args
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+class Net:
+    """FP64 view of an fV-SRN: latent grid, packed weights, keyframe times."""
+
+    def __init__(self, spec, latent, weights, key_times=None):
+        self.spec = spec
+        self.latent = _f64(latent).reshape(-1)
+        self.weights = _f64(weights).reshape(-1)
+        self.key_times = _f64(key_times)
+        self._s = _Net(spec.R, spec.F, spec.K, spec.L, spec.c, spec.H, ACT[spec.act], 0,
+                       _dp(self.latent), _dp(self.weights), _dp(self.key_times))
+        self.K0 = lib().orc_input_width(C.byref(self._s))
+        self.n_weights = lib().orc_num_weights(C.byref(self._s))
+        assert self.weights.size == self.n_weights, (self.weights.size, self.n_weights)
+        assert self.latent.size == spec.K * spec.R ** 3 * spec.F
+
+    def ref(self):
+        return C.byref(self._s)
+
+
+def _p3(p):
+    return _f64(p).reshape(3)
+
+
+def latent(net: Net, p, t=0.0):
+    z = np.zeros(net.spec.F)
+    dz = np.zeros(net.spec.F * 3)
+    assert lib().orc_latent(net.ref(), _dp(_p3(p)), t, _dp(z), _dp(dz)) == 0
+    return z, dz.reshape(-1, 3)
+
+
+def features(net: Net, p, t=0.0):
+    v0 = np.zeros(net.K0)
+    dv = np.zeros(net.K0 * 3)
+    assert lib().orc_features(net.ref(), _dp(_p3(p)), t, _dp(v0), _dp(dv)) == 0
+    return v0, dv.reshape(-1, 3)
+
+
+def mlp_logit(net: Net, v0):
+    return lib().orc_mlp_logit(net.ref(), _dp(_f64(v0)))
+
+
+def density(net: Net, p, t=0.0):
+    return lib().orc_density(net.ref(), _dp(_p3(p)), t)
+
+
+def density_grad(net: Net, p, t=0.0, mode="fwd"):
+    g = np.zeros(3)
+    f = lib().orc_density_grad_fwd if mode == "fwd" else lib().orc_density_grad_rev
+    d = f(net.ref(), _dp(_p3(p)), t, _dp(g))
+    return d, g
+
+
+def eval_points(net: Net, xyz, t=0.0):
+    xyz = _f64(xyz).reshape(-1, 3)
+    out = np.zeros(xyz.shape[0])
+    assert lib().orc_eval_points(net.ref(), _dp(xyz), xyz.shape[0], t, _dp(out)) == 0
+    return out
+
+
+def grad_points(net: Net, xyz, t=0.0):
+    xyz = _f64(xyz).reshape(-1, 3)
+    d = np.zeros(xyz.shape[0])
+    g = np.zeros((xyz.shape[0], 3))
+    assert lib().orc_grad_points(net.ref(), _dp(xyz), xyz.shape[0], t, _dp(d), _dp(g)) == 0
+    return d, g
+
+
+def dense_sample(vol, p):
+    vol = _f64(vol)
+    nz, ny, nx = vol.shape
+    return lib().orc_dense_sample(_dp(vol), nx, ny, nz, _dp(_p3(p)))
+
+
+def dense_eval_points(vol, xyz):
+    vol = _f64(vol)
+    nz, ny, nx = vol.shape
+    xyz = _f64(xyz).reshape(-1, 3)
+    out = np.zeros(xyz.shape[0])
+    assert lib().orc_dense_eval_points(_dp(vol), nx, ny, nz, _dp(xyz), xyz.shape[0], _dp(out)) == 0
+    return out
+
+
+def marschner_lobb(p, fm=6.0, alpha=0.25):
+    g = np.zeros(3)
+    d = lib().orc_marschner_lobb(fm, alpha, _dp(_p3(p)), _dp(g))
+    return d, g
+
+
+def _tf_struct(tf):
+    s = _TF()
+    pts = tf.points
+    s.n = len(pts)
+    for i, (d, r, g, b, a) in enumerate(pts):
+        s.density[i] = d
+        s.rgba[i][0], s.rgba[i][1], s.rgba[i][2], s.rgba[i][3] = r, g, b, a
+    s.opacity_scale = tf.opacity_scale
+    return s
+
+
+def tf_eval(tf, d):
+    out = np.zeros(4)
+    s = _tf_struct(tf)
+    assert lib().orc_tf_eval(C.byref(s), float(d), _dp(out)) == 0
+    return out
+
+
+def _cam_struct(cam):
+    s = _Cam()
+    s.ortho = 1 if cam.ortho else 0
+    s.width, s.height = cam.width, cam.height
+    for a in range(3):
+        s.eye[a], s.target[a], s.up[a] = cam.eye[a], cam.target[a], cam.up[a]
+    s.fov_y_deg = cam.fov_y_deg
+    s.ortho_half_extent = cam.ortho_half_extent
+    s.time = cam.time
+    return s
+
+
+def camera_ray(cam, px, py):
+    o, d = np.zeros(3), np.zeros(3)
+    s = _cam_struct(cam)
+    lib().orc_camera_ray(C.byref(s), px, py, _dp(o), _dp(d))
+    return o, d
+
+
+def box_clip(o, d):
+    t0, t1 = C.c_double(), C.c_double()
+    hit = lib().orc_box_clip(_dp(_p3(o)), _dp(_p3(d)), C.byref(t0), C.byref(t1))
+    return bool(hit), t0.value, t1.value
+
+
+def _march_struct(m):
+    return _March(m.step, m.fixed_steps, 1 if m.phong else 0, m.ert_eps, m.ka, m.kd, m.ks,
+                  m.shininess)
+
+
+class Field:
+    """Density source for :func:`render`: a network, a dense grid or the
+    analytic Marschner-Lobb signal."""
+
+    def __init__(self, net: Net = None, vol=None, ml=None):
+        self._keep = []
+        if net is not None:
+            self._s = _Field(FIELD_NET, 0, 0, 0, C.pointer(net._s), None, 0.0, 0.0)
+            self._keep.append(net)
+        elif vol is not None:
+            v = _f64(vol)
+            nz, ny, nx = v.shape
+            self._s = _Field(FIELD_DENSE, nx, ny, nz, None, _dp(v), 0.0, 0.0)
+            self._keep.append(v)
+        else:
+            fm, alpha = ml
+            self._s = _Field(FIELD_ML, 0, 0, 0, None, None, fm, alpha)
+
+    def density(self, p, t=0.0, grad=False):
+        g = np.zeros(3)
+        d = lib().orc_field_density(C.byref(self._s), _dp(_p3(p)), t, _dp(g) if grad else None)
+        return (d, g) if grad else d
+
+
+def render(field: Field, tf, cams, march, pixels=None, threads=0):
+    """Returns (image [V][H][W][4] FP64, number of field evaluations). With
+    ``pixels`` (flat indices v*H*W + y*W + x) only those pixels are computed
+    and the rest of the image is zero."""
+    cams = list(cams)
+    V, W, H = len(cams), cams[0].width, cams[0].height
+    cs = (_Cam * V)(*[_cam_struct(c) for c in cams])
+    tfs = _tf_struct(tf)
+    ms = _march_struct(march)
+    out = np.zeros((V, H, W, 4))
+    samples = C.c_int64(0)
+    if pixels is not None:
+        px = np.ascontiguousarray(np.asarray(pixels, dtype=np.int64))
+        pp, npix = px.ctypes.data_as(C.POINTER(C.c_int64)), px.size
+    else:
+        pp, npix = None, 0
+    rc = lib().orc_render(C.byref(field._s), C.byref(tfs), cs, V, C.byref(ms), _dp(out), pp, npix,
+                          C.byref(samples), threads)
+    assert rc == 0, rc
+    return out, samples.value
+
+
+def train_grads(net: Net, xyz, target=None, dloss_dd=None):
+    """(d_latent, d_weights, loss) of the L1 loss (target given) or of the
+    linear functional sum_i dloss_dd_i * d_i."""
+    xyz = _f64(xyz).reshape(-1, 3)
+    dl = np.zeros(net.latent.size)
+    dw = np.zeros(net.weights.size)
+    loss = C.c_double()
+    rc = lib().orc_train_grads(net.ref(), _dp(xyz), xyz.shape[0], _dp(_f64(target)),
+                               _dp(_f64(dloss_dd)), _dp(dl), _dp(dw), C.byref(loss))
+    assert rc == 0, rc
+    return dl, dw, loss.value
+
+
+def adam(param, grad, m, v, lr, beta1, beta2, eps, t):
+    """In-place Adam step on FP64 arrays."""
+    for a in (param, grad, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    rc = lib().orc_adam(_dp(param), _dp(grad), _dp(m), _dp(v), param.size, lr, beta1, beta2, eps, t)
+    assert rc == 0

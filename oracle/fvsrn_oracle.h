@@ -1,0 +1,142 @@
+/*
+ * fV-SRN CPU oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow FP64 reference of what the fV-SRN ray-march path computes
+ * (Weiss, Hermueller, Westermann: "Fast Neural Representations for Direct
+ * Volume Rendering"). Only the tests, the smoke check and the CPU-baseline leg
+ * of the benchmark may load this library. It shares no source with the GPU
+ * library: its structs, layouts and arithmetic are written here from the paper.
+ *
+ * All arrays are host memory, FP64, owned by the caller. Functions return 0 on
+ * success and a negative value on an argument error.
+ *
+ * Conventions (readings of the paper, listed in the design doc):
+ *  - Domain [-1,1]^3. Latent grid: R vertices per axis, vertex i at
+ *    -1 + 2i/(R-1) (Sec. 4.2 defines R as vertices per axis). Layout
+ *    [K][z][y][x][F], channel fastest.
+ *  - Network input v0 = [x, y, z, latent(F), sin-block(3L), cos-block(3L)];
+ *    block entry 3k+a is sin/cos(pi * 2^k * p_a) (Eq. 1 and Eq. 2, with the
+ *    frequency pi*2^k of the benchmark configuration).
+ *  - Weights: for each layer i = 0..H, W_i[out][in] row-major then b_i[out].
+ *    Layer 0 maps K0 = 3+F+6L -> c, layers 1..H-1 map c -> c, layer H maps
+ *    c -> 1. Layers 0..H-1 use the activation, layer H the sigmoid (Sec. 3).
+ *
+ * parity pins: see tests/test_oracle_pins.py. Every function below is pinned
+ * by a closed form, an invariant or brute force there; none is "parity
+ * unpinned" except whole-image renders of random networks, which rest on the
+ * per-stage pins.
+ */
+#ifndef FVSRN_ORACLE_H
+#define FVSRN_ORACLE_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_ACT_SINE = 0, ORC_ACT_SNAKEALT = 1, ORC_ACT_IDENTITY = 2 };
+
+typedef struct {
+  int32_t R, F, K;          /* latent vertices per axis, channels, keyframes */
+  int32_t L;                /* Fourier octaves */
+  int32_t c, H;             /* hidden width, activated layers */
+  int32_t act;              /* ORC_ACT_* */
+  int32_t pad_;
+  const double* latent;     /* [K][R][R][R][F] */
+  const double* weights;    /* packed, see header comment */
+  const double* key_times;  /* [K] ascending (NULL when K == 1) */
+} orc_net;
+
+typedef struct {            /* piecewise-linear transfer function */
+  int32_t n;                /* 2..16 control points */
+  int32_t pad_;
+  double density[16];       /* ascending */
+  double rgba[16][4];
+  double opacity_scale;     /* extinction per world unit at alpha = 1 */
+} orc_tf;
+
+typedef struct {
+  int32_t ortho, width, height, pad_;
+  double eye[3], target[3], up[3];
+  double fov_y_deg;         /* perspective */
+  double ortho_half_extent; /* orthographic: half height of the view window */
+  double time;              /* keyframe time of this view */
+} orc_camera;
+
+typedef struct {
+  double step;              /* world units; used when fixed_steps == 0 */
+  int32_t fixed_steps;      /* > 0: that many equal segments per ray */
+  int32_t phong;            /* 1: shade with the density gradient */
+  double ert_eps;           /* stop once transmittance < eps (0 = never) */
+  double ka, kd, ks, shininess;
+} orc_march;
+
+/* Source of density for the renderer. */
+enum { ORC_FIELD_NET = 0, ORC_FIELD_DENSE = 1, ORC_FIELD_MARSCHNER_LOBB = 2 };
+typedef struct {
+  int32_t kind;
+  int32_t nx, ny, nz;       /* dense grid vertices per axis */
+  const orc_net* net;
+  const double* vol;        /* dense [nz][ny][nx] */
+  double ml_fm, ml_alpha;   /* Marschner-Lobb parameters */
+} orc_field;
+
+int64_t orc_num_weights(const orc_net* net);
+int32_t orc_input_width(const orc_net* net);
+
+/* Trilinear latent vector at p and keyframe time t; dz (nullable) gets
+   dz[f*3+a] = d z_f / d p_a. */
+int orc_latent(const orc_net* net, const double p[3], double t, double* z, double* dz);
+/* Network input v0 (K0 values); dv (nullable) gets dv[j*3+a] = d v0_j / d p_a. */
+int orc_features(const orc_net* net, const double p[3], double t, double* v0, double* dv);
+/* Network output before the sigmoid, from an input vector. */
+double orc_mlp_logit(const orc_net* net, const double* v0);
+/* Density d = sigmoid(logit) at p. */
+double orc_density(const orc_net* net, const double p[3], double t);
+/* Density and gradient by forward-mode (tangent) propagation. */
+double orc_density_grad_fwd(const orc_net* net, const double p[3], double t, double g[3]);
+/* Density and gradient by reverse-mode (adjoint) propagation. */
+double orc_density_grad_rev(const orc_net* net, const double p[3], double t, double g[3]);
+
+int orc_eval_points(const orc_net* net, const double* xyz, int64_t n, double t, double* out);
+int orc_grad_points(const orc_net* net, const double* xyz, int64_t n, double t, double* out_d,
+                    double* out_g);
+
+/* Dense grid, same vertex-centred convention over [-1,1]^3. */
+double orc_dense_sample(const double* vol, int nx, int ny, int nz, const double p[3]);
+int orc_dense_eval_points(const double* vol, int nx, int ny, int nz, const double* xyz,
+                          int64_t n, double* out);
+double orc_marschner_lobb(double fm, double alpha, const double p[3], double g[3]);
+
+/* Density and gradient of any field source (network: forward mode; dense:
+   central differences with one-voxel step; Marschner-Lobb: analytic). */
+double orc_field_density(const orc_field* f, const double p[3], double t, double g[3]);
+
+int orc_tf_eval(const orc_tf* tf, double d, double rgba[4]);
+/* Ray through the centre of pixel (px, py), row 0 at the top. */
+int orc_camera_ray(const orc_camera* cam, int px, int py, double o[3], double dir[3]);
+/* Entry/exit of the ray in [-1,1]^3; returns 0 on a miss. */
+int orc_box_clip(const double o[3], const double dir[3], double* t0, double* t1);
+
+/* Render n_views images [V][H][W][4] (premultiplied RGBA). pixels (nullable):
+   list of n_pix flat indices (v*H*W + y*W + x) to render; other pixels are
+   left untouched. samples (nullable) receives the number of field
+   evaluations. threads <= 0: OpenMP default. */
+int orc_render(const orc_field* field, const orc_tf* tf, const orc_camera* cams, int n_views,
+               const orc_march* m, double* out, const int64_t* pixels, int64_t n_pix,
+               int64_t* samples, int threads);
+
+/* Training (Sec. 3 world-space fitting). Gradients of
+     L1 mode  (target != NULL): loss = mean_i |d(x_i) - target_i|
+     VJP mode (target == NULL): loss = sum_i dloss_dd_i * d(x_i)
+   with respect to the latent grid (K == 1) and all weights; the gradient
+   arrays are overwritten. sign(0) = 0 in L1 mode. */
+int orc_train_grads(const orc_net* net, const double* xyz, int64_t n, const double* target,
+                    const double* dloss_dd, double* d_latent, double* d_weights, double* loss);
+/* One bias-corrected Adam update of n parameters at step t >= 1. */
+int orc_adam(double* param, const double* grad, double* m, double* v, int64_t n, double lr,
+             double beta1, double beta2, double eps, int32_t t);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
