@@ -1,0 +1,218 @@
+/*
+ * fvsrn.h -- C ABI of the MI355X (gfx950) fV-SRN hot path.
+ *
+ * fV-SRN (Weiss, Hermueller, Westermann, "Fast Neural Representations for
+ * Direct Volume Rendering") represents a scalar volume V: R^3 -> R as a small
+ * fully connected network fed with the position, octave Fourier features of
+ * the position (Sec. 3, Eq. 1 and Eq. 2) and a latent vector trilinearly
+ * interpolated from a coarse grid (Sec. 4.2). Rendering evaluates the network
+ * at every sample of every view ray inside one fused kernel (Sec. 4), maps the
+ * predicted density through a transfer function and composites front to back.
+ *
+ * General rules for every entry point:
+ *  - Pointers are DEVICE pointers unless marked [host]. The caller owns every
+ *    buffer; the library allocates nothing and keeps no state beyond cached
+ *    device properties.
+ *  - Device buffers must be 16-byte aligned.
+ *  - Calls are asynchronous on `stream` (a hipStream_t passed as void*; NULL
+ *    is the default stream). Argument errors are detected on the host before
+ *    anything is launched and leave outputs untouched. Device faults surface
+ *    at the caller's next synchronisation.
+ *  - n == 0 (or an empty image) is a successful no-op.
+ *  - Functions never throw; the status says what went wrong and
+ *    fvsrn_last_error() (thread-local) gives the detail.
+ *
+ * Geometry and numerics (shared by every entry point):
+ *  - Domain [-1,1]^3. A grid with R vertices per axis has vertex i at
+ *    -1 + 2i/(R-1) (Sec. 4.2 defines R as vertices per axis); coordinates are
+ *    clamped to the domain before interpolation and the cell index is capped at
+ *    R-2, so p = 1 hits the last vertex exactly.
+ *  - Latent grid layout [K][R_z][R_y][R_x][F]: channel fastest, then x, y, z,
+ *    then keyframe.
+ *  - Network input v0 = [x, y, z, latent(F), sin-block(3L), cos-block(3L)];
+ *    block entry 3k+a is sin / cos(pi * 2^k * p_a), k = 0..L-1 (Eq. 1 with the
+ *    octave frequencies pi*2^k, Eq. 2's concatenation).
+ *  - Weights (FP32 master copy, the layout the trainer updates): for each
+ *    layer i = 0..H, W_i[out][in] row-major, then b_i[out]. Layer 0 maps
+ *    K0 = 3 + F + 6L inputs to c channels, layers 1..H-1 map c to c, layer H
+ *    maps c to 1. Layers 0..H-1 apply the activation (sine: sin(x);
+ *    SnakeAlt: 0.5x + sin^2(x), Sec. 5 Eq. 3), layer H the sigmoid, giving a
+ *    density in (0,1) (Sec. 3).
+ */
+#ifndef FVSRN_H
+#define FVSRN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FVSRN_OK = 0,
+  FVSRN_ERR_INVALID_ARGUMENT = 1, /* null pointer, bad size, misalignment, bad struct field */
+  FVSRN_ERR_UNSUPPORTED = 2,      /* valid request outside the compiled configurations */
+  FVSRN_ERR_WORKSPACE = 3,        /* workspace missing or too small */
+  FVSRN_ERR_DEVICE = 4            /* HIP error at launch */
+} fvsrn_status;
+
+typedef enum { FVSRN_F32 = 0, FVSRN_F16 = 1, FVSRN_BF16 = 2 } fvsrn_dtype;
+typedef enum { FVSRN_ACT_SINE = 0, FVSRN_ACT_SNAKEALT = 1, FVSRN_ACT_IDENTITY = 2 } fvsrn_act;
+
+/* Network and latent-grid shape (Sec. 3, Sec. 4.2). Supported: F in {8, 16},
+   L in {4, 8} with (F, L) = (8, 4) or (16, 8); c in {32, 48}; 1 <= H <= 8;
+   2 <= R <= 512; 1 <= K <= 64. */
+typedef struct {
+  int32_t grid_res;      /* R: latent vertices per axis */
+  int32_t grid_channels; /* F: latent channels */
+  int32_t grid_dtype;    /* FVSRN_F32 or FVSRN_F16 storage of the latent grid */
+  int32_t num_keyframes; /* K >= 1; K > 1 interpolates latent grids in time (Sec. 8) */
+  int32_t num_freqs;     /* L: Fourier octaves */
+  int32_t hidden_width;  /* c */
+  int32_t hidden_layers; /* H activated layers, followed by the c -> 1 output layer */
+  int32_t activation;    /* fvsrn_act */
+  int32_t precision;     /* network arithmetic: FVSRN_F32 (FP32 MFMA), FVSRN_F16 or
+                            FVSRN_BF16 (MFMA with FP32 accumulation). Interpolation,
+                            phases, sigmoid, TF and compositing are FP32 always. */
+} fvsrn_net_desc;
+
+typedef struct {
+  const void* latent;       /* [K][R][R][R][F] in grid_dtype */
+  const float* weights;     /* FP32 packed weights (layout above) */
+  const float* key_times;   /* [host] [K] strictly ascending keyframe times; NULL if K == 1.
+                               A time t is clamped to [key_times[0], key_times[K-1]] and the
+                               two neighbouring keyframe latents are blended linearly. */
+} fvsrn_params;
+
+/* [host] Piecewise-linear transfer function: density -> (r, g, b, alpha),
+   constant beyond the first and last control point. Extinction per world
+   unit is opacity_scale * alpha. 2 <= n <= 16, densities strictly ascending. */
+typedef struct {
+  int32_t n;
+  float density[16];
+  float rgba[16][4];
+  float opacity_scale;
+} fvsrn_tf;
+
+/* [host] Look-at camera. forward = normalize(target - eye),
+   right = normalize(forward x up), true up = right x forward. Pixel (x, y),
+   row 0 at the top, has NDC ((2x+1)/W - 1, 1 - (2y+1)/H). Perspective rays
+   start at eye with direction forward + tan(fov_y/2)(aspect ndc_x right +
+   ndc_y up); orthographic rays start at eye + h(aspect ndc_x right + ndc_y up)
+   with direction forward, h = ortho_half_extent. `time` selects the keyframe
+   blend of this view. */
+typedef struct {
+  int32_t ortho;
+  float eye[3], target[3], up[3];
+  float fov_y_deg, ortho_half_extent;
+  int32_t width, height;
+  float time;
+} fvsrn_camera;
+
+/* [host] Ray-march settings. The ray's chord [t0, t1] inside [-1,1]^3
+   (t0 >= 0) is cut into fixed_steps equal segments (fixed_steps > 0), else
+   into segments of length `step` with the last one clipped at t1. Each
+   segment is sampled at its midpoint. With extinction kappa and length ds:
+   a = 1 - exp(-kappa ds), C += T a rgb, A += T a, T *= exp(-kappa ds); the
+   march stops after a sample once T < ert_eps (0 disables early ray
+   termination). phong != 0 shades rgb with a headlight Blinn-Phong term from
+   the normalized density gradient n: rgb (ka + kd |n.l|) + ks |n.l|^shininess
+   (Sec. 6), gradients below 1e-6 in length leave rgb unshaded. */
+typedef struct {
+  float step;
+  int32_t fixed_steps;
+  float ert_eps;
+  int32_t phong;
+  float ka, kd, ks, shininess;
+} fvsrn_march;
+
+/* Render n_views images of the fV-SRN with one launch (Sec. 4, Sec. 5.1):
+   out_rgba [n_views][H][W][4] FP32, premultiplied colour and opacity over a
+   transparent background. All cameras must share width and height.
+   stats (nullable, device, 2 x u64, accumulated -- the caller zeroes it):
+   [0] += samples composited, [1] += rays that hit the domain. Phong shading
+   needs the forward-mode density gradient (Sec. 6). */
+fvsrn_status fvsrn_render(const fvsrn_net_desc* desc, const fvsrn_params* params,
+                          const fvsrn_tf* tf, const fvsrn_camera* cams, int32_t n_views,
+                          const fvsrn_march* march, float* out_rgba,
+                          unsigned long long* stats, void* stream);
+
+/* Density of the fV-SRN at n arbitrary points (Sec. 3: each position is
+   evaluated independently; Sec. 7 times 10^6 random reconstructions).
+   xyz [n][3] FP32, out_density [n] FP32; time selects the keyframe blend. */
+fvsrn_status fvsrn_eval_points(const fvsrn_net_desc* desc, const fvsrn_params* params,
+                               const float* xyz, int64_t n, float time, float* out_density,
+                               void* stream);
+
+/* Density and its gradient d density / d p at n points by forward-mode
+   differentiation through the network, the Fourier features and the
+   trilinear interpolation (Sec. 6). out_density nullable [n]; out_grad [n][3]. */
+fvsrn_status fvsrn_grad_points(const fvsrn_net_desc* desc, const fvsrn_params* params,
+                               const float* xyz, int64_t n, float time, float* out_density,
+                               float* out_grad, void* stream);
+
+/* [host] Adam state for fvsrn_train_step (bias-corrected; PyTorch's form
+   p -= lr/(1-b1^t) * m / (sqrt(v)/sqrt(1-b2^t) + eps)). */
+typedef struct {
+  float lr_grid, lr_mlp, beta1, beta2, eps;
+  int32_t step;          /* t >= 1 of this update */
+  float* m_latent;       /* device [R^3 F] */
+  float* v_latent;
+  float* m_weights;      /* device [n_weights] */
+  float* v_weights;
+} fvsrn_adam;
+
+/* One world-space training step on n points (Sec. 3, Sec. 5: L1 loss, Adam).
+   FP32 latent grid (K == 1) and FP32 weights, FP32 arithmetic.
+     L1 mode  (target != NULL): loss = mean |d(x_i) - target_i|, sign(0) = 0.
+     VJP mode (target == NULL): loss = sum dloss_dy_i * d(x_i) (the gradient
+       of any downstream loss, e.g. from autograd).
+   d_latent [R^3 F] and d_weights [n_weights] are overwritten with the
+   gradients. With adam != NULL the latent grid and the weights are then
+   updated in place (lr_grid for the latent grid, lr_mlp for the weights).
+   out_loss (nullable, device FP32 scalar) receives the loss. workspace must
+   hold fvsrn_train_workspace_size(desc, n) bytes. */
+fvsrn_status fvsrn_train_step(const fvsrn_net_desc* desc, float* latent, float* weights,
+                              float* d_latent, float* d_weights, const float* xyz, int64_t n,
+                              const float* target, const float* dloss_dy,
+                              const fvsrn_adam* adam, float* out_loss, void* workspace,
+                              size_t workspace_bytes, void* stream);
+size_t fvsrn_train_workspace_size(const fvsrn_net_desc* desc, int64_t n);
+
+/* Plain dense-grid DVR with the same rays, transfer function and compositor
+   (the uncompressed reference the paper renders, Sec. 5): vol [nz][ny][nx]
+   FP32, vertex-centred over [-1,1]^3, trilinear lookup. Phong uses central
+   differences with a one-voxel step (Sec. 6). */
+fvsrn_status fvsrn_render_dense(const float* vol, int32_t nx, int32_t ny, int32_t nz,
+                                const fvsrn_tf* tf, const fvsrn_camera* cams, int32_t n_views,
+                                const fvsrn_march* march, float* out_rgba,
+                                unsigned long long* stats, void* stream);
+
+/* Trilinear samples of a dense grid at n points (training targets drawn from
+   the original volume, Sec. 3). */
+fvsrn_status fvsrn_dense_eval_points(const float* vol, int32_t nx, int32_t ny, int32_t nz,
+                                     const float* xyz, int64_t n, float* out, void* stream);
+
+/* n uniform points in [-1,1)^3 from a Philox4x32-10 counter-based generator
+   (Salmon et al., SC'11): point i uses counter (i, counter_lo, counter_hi, 0)
+   and key (seed_lo, seed_hi); its three coordinates come from the first three
+   32-bit outputs u as -1 + (u >> 8) * 2^-23. xyz [n][3]. */
+fvsrn_status fvsrn_sample_points(uint64_t seed, uint64_t counter, int64_t n, float* xyz,
+                                 void* stream);
+
+/* Round an FP32 array to FP16 or BF16 (round to nearest even), e.g. to store
+   the latent grid in FP16. dst_dtype FVSRN_F16 or FVSRN_BF16. */
+fvsrn_status fvsrn_cast_grid(const float* src, void* dst, int64_t count, int32_t dst_dtype,
+                             void* stream);
+
+/* Number of FP32 weights of a network description (0 if invalid). */
+int64_t fvsrn_num_weights(const fvsrn_net_desc* desc);
+
+const char* fvsrn_status_str(fvsrn_status s);
+const char* fvsrn_last_error(void); /* thread-local detail of the last failing call */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FVSRN_H */

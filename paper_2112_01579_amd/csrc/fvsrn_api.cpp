@@ -1,0 +1,385 @@
+// C ABI of the fV-SRN hot path: argument validation, host-side precomputation
+// (camera bases, transfer-function segments, keyframe blends) and dispatch to
+// the gfx950 kernels. Nothing here allocates device memory.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "../../include/fvsrn.h"
+#include "fvsrn_launch.h"
+
+using namespace fvsrn_detail;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+fvsrn_status fail(fvsrn_status s, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+int64_t num_weights(const fvsrn_net_desc& d) {
+  const int64_t K0 = 3 + d.grid_channels + 6 * (int64_t)d.num_freqs, c = d.hidden_width;
+  return c * K0 + c + (int64_t)(d.hidden_layers - 1) * (c * c + c) + c + 1;
+}
+
+fvsrn_status check_desc(const fvsrn_net_desc* d) {
+  if (!d) return fail(FVSRN_ERR_INVALID_ARGUMENT, "desc is NULL");
+  if (d->grid_res < 2 || d->grid_res > 512)
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "grid_res %d outside [2, 512]", d->grid_res);
+  if (d->grid_channels < 1 || d->num_freqs < 0 || d->hidden_width < 1 || d->hidden_layers < 1)
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "non-positive network dimension");
+  if (d->num_keyframes < 1 || d->num_keyframes > 64)
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "num_keyframes %d outside [1, 64]", d->num_keyframes);
+  if (d->grid_dtype != FVSRN_F32 && d->grid_dtype != FVSRN_F16)
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "grid_dtype must be FVSRN_F32 or FVSRN_F16");
+  if (d->precision < FVSRN_F32 || d->precision > FVSRN_BF16)
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "precision %d unknown", d->precision);
+  if (d->activation < FVSRN_ACT_SINE || d->activation > FVSRN_ACT_IDENTITY)
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "activation %d unknown", d->activation);
+  const bool fl = (d->grid_channels == 8 && d->num_freqs == 4) || (d->grid_channels == 16 && d->num_freqs == 8);
+  if (!fl)
+    return fail(FVSRN_ERR_UNSUPPORTED, "(F, L) = (%d, %d) not compiled; supported (8, 4) and (16, 8)",
+                d->grid_channels, d->num_freqs);
+  if (d->hidden_width != 32 && d->hidden_width != 48)
+    return fail(FVSRN_ERR_UNSUPPORTED, "hidden_width %d not compiled; supported 32, 48", d->hidden_width);
+  if (d->hidden_layers > 8) return fail(FVSRN_ERR_UNSUPPORTED, "hidden_layers %d > 8", d->hidden_layers);
+  return FVSRN_OK;
+}
+
+fvsrn_status check_params(const fvsrn_net_desc* d, const fvsrn_params* p) {
+  if (!p) return fail(FVSRN_ERR_INVALID_ARGUMENT, "params is NULL");
+  if (!p->latent || !p->weights) return fail(FVSRN_ERR_INVALID_ARGUMENT, "latent or weights is NULL");
+  if (!aligned16(p->latent) || !aligned16(p->weights))
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "latent and weights must be 16-byte aligned");
+  if (d->num_keyframes > 1) {
+    if (!p->key_times) return fail(FVSRN_ERR_INVALID_ARGUMENT, "key_times required when K > 1");
+    for (int k = 1; k < d->num_keyframes; ++k)
+      if (!(p->key_times[k] > p->key_times[k - 1]))
+        return fail(FVSRN_ERR_INVALID_ARGUMENT, "key_times must be strictly ascending");
+  }
+  return FVSRN_OK;
+}
+
+NetDev make_net(const fvsrn_net_desc* d, const void* latent, const float* weights) {
+  NetDev n;
+  n.latent = latent;
+  n.weights = weights;
+  n.R = d->grid_res;
+  n.F = d->grid_channels;
+  n.K = d->num_keyframes;
+  n.L = d->num_freqs;
+  n.C = d->hidden_width;
+  n.H = d->hidden_layers;
+  n.act = d->activation;
+  n.grid_f16 = d->grid_dtype == FVSRN_F16;
+  n.key_stride = (long long)d->grid_res * d->grid_res * d->grid_res * d->grid_channels;
+  return n;
+}
+
+// Keyframe pair and blend weight for time t (clamped to the keyframe range).
+void key_blend(const fvsrn_net_desc* d, const fvsrn_params* p, float t, int* key, float* w) {
+  *key = 0;
+  *w = 0.0f;
+  const int K = d->num_keyframes;
+  if (K <= 1) return;
+  const float* kt = p->key_times;
+  if (t <= kt[0]) return;
+  if (t >= kt[K - 1]) {
+    *key = K - 2;
+    *w = 1.0f;
+    return;
+  }
+  int j = 0;
+  while (j + 1 < K - 1 && kt[j + 1] <= t) ++j;
+  *key = j;
+  *w = (float)(((double)t - kt[j]) / ((double)kt[j + 1] - kt[j]));
+}
+
+fvsrn_status make_tf(const fvsrn_tf* tf, TFDev* out) {
+  if (!tf) return fail(FVSRN_ERR_INVALID_ARGUMENT, "tf is NULL");
+  if (tf->n < 2 || tf->n > 16) return fail(FVSRN_ERR_INVALID_ARGUMENT, "tf.n %d outside [2, 16]", tf->n);
+  for (int j = 1; j < tf->n; ++j)
+    if (!(tf->density[j] > tf->density[j - 1]))
+      return fail(FVSRN_ERR_INVALID_ARGUMENT, "tf densities must be strictly ascending");
+  if (!(tf->opacity_scale >= 0.0f)) return fail(FVSRN_ERR_INVALID_ARGUMENT, "tf.opacity_scale < 0");
+  memset(out, 0, sizeof(*out));
+  out->n_seg = tf->n - 1;
+  const double s = tf->opacity_scale;
+  for (int q = 0; q < 4; ++q) out->base[q] = (float)(tf->rgba[0][q] * (q == 3 ? s : 1.0));
+  for (int j = 0; j + 1 < tf->n; ++j) {
+    const double inv = 1.0 / ((double)tf->density[j + 1] - tf->density[j]);
+    out->inv[j] = (float)inv;
+    out->off[j] = (float)(-(double)tf->density[j] * inv);
+    for (int q = 0; q < 4; ++q)
+      out->delta[j][q] = (float)(((double)tf->rgba[j + 1][q] - tf->rgba[j][q]) * (q == 3 ? s : 1.0));
+  }
+  return FVSRN_OK;
+}
+
+fvsrn_status make_views(const fvsrn_camera* cams, int n_views, int first, int count,
+                        const fvsrn_net_desc* d, const fvsrn_params* p, ViewBatch* vb) {
+  memset(vb, 0, sizeof(*vb));
+  vb->n_views = count;
+  vb->width = cams[0].width;
+  vb->height = cams[0].height;
+  (void)n_views;
+  for (int v = 0; v < count; ++v) {
+    const fvsrn_camera& c = cams[first + v];
+    CamDev& o = vb->cam[v];
+    double f[3] = {(double)c.target[0] - c.eye[0], (double)c.target[1] - c.eye[1],
+                   (double)c.target[2] - c.eye[2]};
+    double fl = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    if (!(fl > 0.0)) return fail(FVSRN_ERR_INVALID_ARGUMENT, "camera %d: eye == target", first + v);
+    for (int a = 0; a < 3; ++a) f[a] /= fl;
+    double r[3] = {f[1] * c.up[2] - f[2] * c.up[1], f[2] * c.up[0] - f[0] * c.up[2],
+                   f[0] * c.up[1] - f[1] * c.up[0]};
+    double rl = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    if (!(rl > 0.0)) return fail(FVSRN_ERR_INVALID_ARGUMENT, "camera %d: up parallel to view", first + v);
+    for (int a = 0; a < 3; ++a) r[a] /= rl;
+    double u[3] = {r[1] * f[2] - r[2] * f[1], r[2] * f[0] - r[0] * f[2], r[0] * f[1] - r[1] * f[0]};
+    for (int a = 0; a < 3; ++a) {
+      o.eye[a] = c.eye[a];
+      o.fwd[a] = (float)f[a];
+      o.right[a] = (float)r[a];
+      o.up[a] = (float)u[a];
+    }
+    o.tan_half = (float)tan((double)c.fov_y_deg * M_PI / 360.0);
+    o.half_extent = c.ortho_half_extent;
+    o.aspect = (float)((double)c.width / (double)c.height);
+    o.ortho = c.ortho ? 1 : 0;
+    if (d && p) key_blend(d, p, c.time, &o.key, &o.key_w);
+  }
+  return FVSRN_OK;
+}
+
+fvsrn_status check_cams(const fvsrn_camera* cams, int32_t n_views, const fvsrn_march* m) {
+  if (!cams || !m) return fail(FVSRN_ERR_INVALID_ARGUMENT, "cams or march is NULL");
+  if (n_views <= 0) return fail(FVSRN_ERR_INVALID_ARGUMENT, "n_views must be positive");
+  for (int v = 0; v < n_views; ++v) {
+    if (cams[v].width <= 0 || cams[v].height <= 0 || cams[v].width > 16384 || cams[v].height > 16384)
+      return fail(FVSRN_ERR_INVALID_ARGUMENT, "camera %d: image size out of range", v);
+    if (cams[v].width != cams[0].width || cams[v].height != cams[0].height)
+      return fail(FVSRN_ERR_INVALID_ARGUMENT, "all cameras must share width and height");
+    if (!cams[v].ortho && !(cams[v].fov_y_deg > 0.0f && cams[v].fov_y_deg < 180.0f))
+      return fail(FVSRN_ERR_INVALID_ARGUMENT, "camera %d: fov_y_deg outside (0, 180)", v);
+  }
+  if (m->fixed_steps < 0 || m->fixed_steps > (1 << 20))
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "fixed_steps outside [0, 2^20]");
+  // a ray crosses at most 2 sqrt(3) world units: this bounds a march to ~2.3e5 steps
+  if (m->fixed_steps == 0 && !(m->step >= 1.0f / 65536.0f))
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "step must be >= 2^-16 world units");
+  if (!(m->ert_eps >= 0.0f) || m->ert_eps > 1.0f) return fail(FVSRN_ERR_INVALID_ARGUMENT, "ert_eps outside [0, 1]");
+  return FVSRN_OK;
+}
+
+MarchDev make_march(const fvsrn_march* m) {
+  MarchDev o;
+  o.step = m->step;
+  o.fixed_steps = m->fixed_steps;
+  o.ert_eps = m->ert_eps;
+  o.phong = m->phong ? 1 : 0;
+  o.ka = m->ka;
+  o.kd = m->kd;
+  o.ks = m->ks;
+  o.shininess = m->shininess;
+  return o;
+}
+
+fvsrn_status launch_status(int rc, const char* what) {
+  if (rc == 0) return FVSRN_OK;
+  if (rc == 1) return fail(FVSRN_ERR_UNSUPPORTED, "%s: configuration not compiled", what);
+  return fail(FVSRN_ERR_DEVICE, "%s: launch failed: %s", what, last_hip_error());
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t fvsrn_num_weights(const fvsrn_net_desc* desc) {
+  if (!desc || desc->hidden_layers < 1 || desc->hidden_width < 1 || desc->grid_channels < 0 ||
+      desc->num_freqs < 0)
+    return 0;
+  return num_weights(*desc);
+}
+
+const char* fvsrn_status_str(fvsrn_status s) {
+  switch (s) {
+    case FVSRN_OK: return "ok";
+    case FVSRN_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case FVSRN_ERR_UNSUPPORTED: return "unsupported configuration";
+    case FVSRN_ERR_WORKSPACE: return "workspace too small";
+    case FVSRN_ERR_DEVICE: return "device error";
+  }
+  return "unknown status";
+}
+
+const char* fvsrn_last_error(void) { return g_err; }
+
+fvsrn_status fvsrn_render(const fvsrn_net_desc* desc, const fvsrn_params* params, const fvsrn_tf* tf,
+                          const fvsrn_camera* cams, int32_t n_views, const fvsrn_march* march,
+                          float* out_rgba, unsigned long long* stats, void* stream) {
+  g_err[0] = 0;
+  fvsrn_status s;
+  if ((s = check_desc(desc)) != FVSRN_OK) return s;
+  if ((s = check_params(desc, params)) != FVSRN_OK) return s;
+  if ((s = check_cams(cams, n_views, march)) != FVSRN_OK) return s;
+  if (!out_rgba || !aligned16(out_rgba)) return fail(FVSRN_ERR_INVALID_ARGUMENT, "out_rgba NULL or misaligned");
+  if (stats && ((uintptr_t)stats & 7u)) return fail(FVSRN_ERR_INVALID_ARGUMENT, "stats misaligned");
+  TFDev tfd;
+  if ((s = make_tf(tf, &tfd)) != FVSRN_OK) return s;
+  const NetDev nd = make_net(desc, params->latent, params->weights);
+  const MarchDev md = make_march(march);
+  const long long per_view = (long long)cams[0].width * cams[0].height * 4;
+  for (int v0 = 0; v0 < n_views; v0 += kMaxViewsPerLaunch) {
+    const int cnt = n_views - v0 < kMaxViewsPerLaunch ? n_views - v0 : kMaxViewsPerLaunch;
+    ViewBatch vb;
+    if ((s = make_views(cams, n_views, v0, cnt, desc, params, &vb)) != FVSRN_OK) return s;
+    const int rc = launch_render(nd, desc->precision, tfd, vb, md, out_rgba + v0 * per_view, stats, stream);
+    if ((s = launch_status(rc, "fvsrn_render")) != FVSRN_OK) return s;
+  }
+  return FVSRN_OK;
+}
+
+fvsrn_status fvsrn_eval_points(const fvsrn_net_desc* desc, const fvsrn_params* params, const float* xyz,
+                               int64_t n, float time, float* out_density, void* stream) {
+  g_err[0] = 0;
+  if (n > 0 && !out_density) return fail(FVSRN_ERR_INVALID_ARGUMENT, "out_density is NULL");
+  fvsrn_status s;
+  if ((s = check_desc(desc)) != FVSRN_OK) return s;
+  if ((s = check_params(desc, params)) != FVSRN_OK) return s;
+  if (n < 0) return fail(FVSRN_ERR_INVALID_ARGUMENT, "n < 0");
+  if (n == 0) return FVSRN_OK;
+  if (!xyz || !aligned16(xyz) || !aligned16(out_density))
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "xyz / out_density NULL or misaligned");
+  int key;
+  float kw;
+  key_blend(desc, params, time, &key, &kw);
+  const NetDev nd = make_net(desc, params->latent, params->weights);
+  return launch_status(launch_points(nd, desc->precision, xyz, n, key, kw, out_density, nullptr, stream),
+                       "fvsrn_eval_points");
+}
+
+fvsrn_status fvsrn_grad_points(const fvsrn_net_desc* desc, const fvsrn_params* params, const float* xyz,
+                               int64_t n, float time, float* out_density, float* out_grad, void* stream) {
+  g_err[0] = 0;
+  if (n > 0 && !out_grad) return fail(FVSRN_ERR_INVALID_ARGUMENT, "out_grad is NULL");
+  fvsrn_status s;
+  if ((s = check_desc(desc)) != FVSRN_OK) return s;
+  if ((s = check_params(desc, params)) != FVSRN_OK) return s;
+  if (n < 0) return fail(FVSRN_ERR_INVALID_ARGUMENT, "n < 0");
+  if (n == 0) return FVSRN_OK;
+  if (!xyz || !aligned16(xyz) || !aligned16(out_grad) || (out_density && !aligned16(out_density)))
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "xyz / outputs NULL or misaligned");
+  int key;
+  float kw;
+  key_blend(desc, params, time, &key, &kw);
+  const NetDev nd = make_net(desc, params->latent, params->weights);
+  return launch_status(launch_points(nd, desc->precision, xyz, n, key, kw, out_density, out_grad, stream),
+                       "fvsrn_grad_points");
+}
+
+size_t fvsrn_train_workspace_size(const fvsrn_net_desc* desc, int64_t n) {
+  if (check_desc(desc) != FVSRN_OK || n < 0) return 0;
+  const NetDev nd = make_net(desc, nullptr, nullptr);
+  return train_workspace_bytes(nd, n);
+}
+
+fvsrn_status fvsrn_train_step(const fvsrn_net_desc* desc, float* latent, float* weights, float* d_latent,
+                              float* d_weights, const float* xyz, int64_t n, const float* target,
+                              const float* dloss_dy, const fvsrn_adam* adam, float* out_loss, void* workspace,
+                              size_t workspace_bytes, void* stream) {
+  g_err[0] = 0;
+  fvsrn_status s;
+  if ((s = check_desc(desc)) != FVSRN_OK) return s;
+  if (desc->num_keyframes != 1) return fail(FVSRN_ERR_UNSUPPORTED, "training needs K == 1");
+  if (desc->grid_dtype != FVSRN_F32) return fail(FVSRN_ERR_UNSUPPORTED, "training needs an FP32 latent grid");
+  if (desc->precision != FVSRN_F32) return fail(FVSRN_ERR_UNSUPPORTED, "training runs in FP32");
+  if (!latent || !weights || !d_latent || !d_weights)
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "latent, weights, d_latent, d_weights must be non-NULL");
+  if (!aligned16(latent) || !aligned16(weights) || !aligned16(d_latent) || !aligned16(d_weights))
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "parameter buffers must be 16-byte aligned");
+  if (n < 0) return fail(FVSRN_ERR_INVALID_ARGUMENT, "n < 0");
+  if (n > 0 && (!xyz || !aligned16(xyz))) return fail(FVSRN_ERR_INVALID_ARGUMENT, "xyz NULL or misaligned");
+  if (n > 0 && !target && !dloss_dy) return fail(FVSRN_ERR_INVALID_ARGUMENT, "target or dloss_dy required");
+  if (adam) {
+    if (adam->step < 1) return fail(FVSRN_ERR_INVALID_ARGUMENT, "adam.step must be >= 1");
+    if (!adam->m_latent || !adam->v_latent || !adam->m_weights || !adam->v_weights)
+      return fail(FVSRN_ERR_INVALID_ARGUMENT, "adam moment buffers must be non-NULL");
+  }
+  const NetDev nd = make_net(desc, latent, weights);
+  const size_t need = train_workspace_bytes(nd, n);
+  if (need > 0 && (!workspace || workspace_bytes < need))
+    return fail(FVSRN_ERR_WORKSPACE, "workspace of %zu bytes required", need);
+  const int rc = launch_train(nd, latent, weights, d_latent, d_weights, xyz, n, target, dloss_dy, adam != nullptr,
+                              adam ? adam->lr_grid : 0.f, adam ? adam->lr_mlp : 0.f, adam ? adam->beta1 : 0.f,
+                              adam ? adam->beta2 : 0.f, adam ? adam->eps : 0.f, adam ? adam->step : 0,
+                              adam ? adam->m_latent : nullptr, adam ? adam->v_latent : nullptr,
+                              adam ? adam->m_weights : nullptr, adam ? adam->v_weights : nullptr, out_loss,
+                              workspace, workspace_bytes, stream);
+  return launch_status(rc, "fvsrn_train_step");
+}
+
+fvsrn_status fvsrn_render_dense(const float* vol, int32_t nx, int32_t ny, int32_t nz, const fvsrn_tf* tf,
+                                const fvsrn_camera* cams, int32_t n_views, const fvsrn_march* march,
+                                float* out_rgba, unsigned long long* stats, void* stream) {
+  g_err[0] = 0;
+  fvsrn_status s;
+  if (!vol || !aligned16(vol)) return fail(FVSRN_ERR_INVALID_ARGUMENT, "vol NULL or misaligned");
+  if (nx < 2 || ny < 2 || nz < 2) return fail(FVSRN_ERR_INVALID_ARGUMENT, "volume needs >= 2 vertices per axis");
+  if ((s = check_cams(cams, n_views, march)) != FVSRN_OK) return s;
+  if (!out_rgba || !aligned16(out_rgba)) return fail(FVSRN_ERR_INVALID_ARGUMENT, "out_rgba NULL or misaligned");
+  if (stats && ((uintptr_t)stats & 7u)) return fail(FVSRN_ERR_INVALID_ARGUMENT, "stats misaligned");
+  TFDev tfd;
+  if ((s = make_tf(tf, &tfd)) != FVSRN_OK) return s;
+  const MarchDev md = make_march(march);
+  const long long per_view = (long long)cams[0].width * cams[0].height * 4;
+  for (int v0 = 0; v0 < n_views; v0 += kMaxViewsPerLaunch) {
+    const int cnt = n_views - v0 < kMaxViewsPerLaunch ? n_views - v0 : kMaxViewsPerLaunch;
+    ViewBatch vb;
+    if ((s = make_views(cams, n_views, v0, cnt, nullptr, nullptr, &vb)) != FVSRN_OK) return s;
+    const int rc = launch_render_dense(vol, nx, ny, nz, tfd, vb, md, out_rgba + v0 * per_view, stats, stream);
+    if ((s = launch_status(rc, "fvsrn_render_dense")) != FVSRN_OK) return s;
+  }
+  return FVSRN_OK;
+}
+
+fvsrn_status fvsrn_dense_eval_points(const float* vol, int32_t nx, int32_t ny, int32_t nz, const float* xyz,
+                                     int64_t n, float* out, void* stream) {
+  g_err[0] = 0;
+  if (!vol || !aligned16(vol)) return fail(FVSRN_ERR_INVALID_ARGUMENT, "vol NULL or misaligned");
+  if (nx < 2 || ny < 2 || nz < 2) return fail(FVSRN_ERR_INVALID_ARGUMENT, "volume needs >= 2 vertices per axis");
+  if (n < 0) return fail(FVSRN_ERR_INVALID_ARGUMENT, "n < 0");
+  if (n == 0) return FVSRN_OK;
+  if (!xyz || !out || !aligned16(xyz) || !aligned16(out))
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "xyz / out NULL or misaligned");
+  return launch_status(launch_dense_points(vol, nx, ny, nz, xyz, n, out, stream), "fvsrn_dense_eval_points");
+}
+
+fvsrn_status fvsrn_sample_points(uint64_t seed, uint64_t counter, int64_t n, float* xyz, void* stream) {
+  g_err[0] = 0;
+  if (n < 0) return fail(FVSRN_ERR_INVALID_ARGUMENT, "n < 0");
+  if (n == 0) return FVSRN_OK;
+  if (!xyz || !aligned16(xyz)) return fail(FVSRN_ERR_INVALID_ARGUMENT, "xyz NULL or misaligned");
+  return launch_status(launch_sample_points(seed, counter, n, xyz, stream), "fvsrn_sample_points");
+}
+
+fvsrn_status fvsrn_cast_grid(const float* src, void* dst, int64_t count, int32_t dst_dtype, void* stream) {
+  g_err[0] = 0;
+  if (count < 0) return fail(FVSRN_ERR_INVALID_ARGUMENT, "count < 0");
+  if (dst_dtype != FVSRN_F16 && dst_dtype != FVSRN_BF16)
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "dst_dtype must be FVSRN_F16 or FVSRN_BF16");
+  if (count == 0) return FVSRN_OK;
+  if (!src || !dst || !aligned16(src) || !aligned16(dst))
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "src / dst NULL or misaligned");
+  return launch_status(launch_cast(src, dst, count, dst_dtype, stream), "fvsrn_cast_grid");
+}
+
+}  // extern "C"

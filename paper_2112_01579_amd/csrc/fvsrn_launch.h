@@ -1,0 +1,79 @@
+// Internal launch interface between the C ABI (fvsrn_api.cpp) and the gfx950
+// kernels (fvsrn_kernels.hip). Host-side structs are plain data; everything
+// the kernels need is precomputed here once per call.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fvsrn_detail {
+
+constexpr int kMaxViewsPerLaunch = 16;
+constexpr int kMaxTFPoints = 16;
+
+// Transfer function in telescoping form: f(d) = base + sum_j
+// clamp(d * inv_j + off_j, 0, 1) * delta_j; alpha already multiplied by the
+// opacity scale (so the fourth channel is the extinction kappa).
+struct TFDev {
+  int n_seg;
+  float base[4];
+  float inv[kMaxTFPoints - 1];
+  float off[kMaxTFPoints - 1];
+  float delta[kMaxTFPoints - 1][4];
+};
+
+// Camera with its orthonormal basis precomputed on the host.
+struct CamDev {
+  float eye[3], fwd[3], right[3], up[3];
+  float tan_half, half_extent, aspect;
+  int ortho;
+  int key;        // first keyframe of the latent blend
+  float key_w;    // weight of keyframe key + 1
+};
+
+struct MarchDev {
+  float step;
+  int fixed_steps;
+  float ert_eps;
+  int phong;
+  float ka, kd, ks, shininess;
+};
+
+struct NetDev {
+  const void* latent;
+  const float* weights;
+  int R, F, K, L, C, H, act, grid_f16;
+  long long key_stride;  // elements between keyframe grids
+};
+
+struct ViewBatch {
+  int n_views, width, height;
+  CamDev cam[kMaxViewsPerLaunch];
+};
+
+enum Prec { kF32 = 0, kF16 = 1, kBF16 = 2 };
+
+// All launchers return 0 on success, 1 if the configuration is not compiled,
+// 2 on a HIP launch error. `stream` is a hipStream_t.
+int launch_render(const NetDev& net, int prec, const TFDev& tf, const ViewBatch& views,
+                  const MarchDev& m, float* out, unsigned long long* stats, void* stream);
+int launch_points(const NetDev& net, int prec, const float* xyz, long long n, int key,
+                  float key_w, float* out_d, float* out_g, void* stream);
+int launch_render_dense(const float* vol, int nx, int ny, int nz, const TFDev& tf,
+                        const ViewBatch& views, const MarchDev& m, float* out,
+                        unsigned long long* stats, void* stream);
+int launch_dense_points(const float* vol, int nx, int ny, int nz, const float* xyz, long long n,
+                        float* out, void* stream);
+int launch_sample_points(uint64_t seed, uint64_t counter, long long n, float* xyz, void* stream);
+int launch_cast(const float* src, void* dst, long long count, int dst_dtype, void* stream);
+
+// Training (FP32). Workspace layout is owned by the kernels file.
+size_t train_workspace_bytes(const NetDev& net, long long n);
+int launch_train(const NetDev& net, float* latent, float* weights, float* d_latent,
+                 float* d_weights, const float* xyz, long long n, const float* target,
+                 const float* dloss_dy, int use_adam, float lr_grid, float lr_mlp, float beta1,
+                 float beta2, float eps, int step, float* m_lat, float* v_lat, float* m_w,
+                 float* v_w, float* out_loss, void* workspace, size_t ws_bytes, void* stream);
+
+const char* last_hip_error();
+
+}  // namespace fvsrn_detail

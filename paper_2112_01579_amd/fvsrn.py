@@ -1,0 +1,295 @@
+"""ctypes binding of the C ABI in ``include/fvsrn.h``.
+
+Argument marshalling only: every step of the path runs in the HIP library
+``libfvsrn.so``. torch tensors provide device memory and streams. The library
+must have been built (``paper_2112_01579_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import Optional, Sequence
+
+import torch
+
+from . import inputs as I
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfvsrn.so")
+
+F32, F16, BF16 = 0, 1, 2
+ACT = {"sine": 0, "snakealt": 1, "identity": 2}
+PREC = {"f32": F32, "fp32": F32, "f16": F16, "fp16": F16, "bf16": BF16}
+
+OK, ERR_INVALID_ARGUMENT, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_DEVICE = 0, 1, 2, 3, 4
+
+EXPORTS = (
+    "fvsrn_render", "fvsrn_eval_points", "fvsrn_grad_points", "fvsrn_train_step",
+    "fvsrn_train_workspace_size", "fvsrn_render_dense", "fvsrn_dense_eval_points",
+    "fvsrn_sample_points", "fvsrn_cast_grid", "fvsrn_num_weights", "fvsrn_status_str",
+    "fvsrn_last_error",
+)
+
+
+class FvsrnError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(msg)
+        self.status = status
+
+
+class NetDesc(C.Structure):
+    _fields_ = [("grid_res", C.c_int32), ("grid_channels", C.c_int32), ("grid_dtype", C.c_int32),
+                ("num_keyframes", C.c_int32), ("num_freqs", C.c_int32), ("hidden_width", C.c_int32),
+                ("hidden_layers", C.c_int32), ("activation", C.c_int32), ("precision", C.c_int32)]
+
+
+class Params(C.Structure):
+    _fields_ = [("latent", C.c_void_p), ("weights", C.c_void_p), ("key_times", C.POINTER(C.c_float))]
+
+
+class TFStruct(C.Structure):
+    _fields_ = [("n", C.c_int32), ("density", C.c_float * 16), ("rgba", (C.c_float * 4) * 16),
+                ("opacity_scale", C.c_float)]
+
+
+class CameraStruct(C.Structure):
+    _fields_ = [("ortho", C.c_int32), ("eye", C.c_float * 3), ("target", C.c_float * 3),
+                ("up", C.c_float * 3), ("fov_y_deg", C.c_float), ("ortho_half_extent", C.c_float),
+                ("width", C.c_int32), ("height", C.c_int32), ("time", C.c_float)]
+
+
+class MarchStruct(C.Structure):
+    _fields_ = [("step", C.c_float), ("fixed_steps", C.c_int32), ("ert_eps", C.c_float),
+                ("phong", C.c_int32), ("ka", C.c_float), ("kd", C.c_float), ("ks", C.c_float),
+                ("shininess", C.c_float)]
+
+
+class AdamStruct(C.Structure):
+    _fields_ = [("lr_grid", C.c_float), ("lr_mlp", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("step", C.c_int32),
+                ("m_latent", C.c_void_p), ("v_latent", C.c_void_p), ("m_weights", C.c_void_p),
+                ("v_weights", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfvsrn.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libfvsrn.so is not built; run paper_2112_01579_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+        st = C.c_int
+        sig = {
+            "fvsrn_render": (st, [vp, vp, vp, vp, i32, vp, vp, vp, vp]),
+            "fvsrn_eval_points": (st, [vp, vp, vp, i64, C.c_float, vp, vp]),
+            "fvsrn_grad_points": (st, [vp, vp, vp, i64, C.c_float, vp, vp, vp]),
+            "fvsrn_train_step": (st, [vp, vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, sz, vp]),
+            "fvsrn_train_workspace_size": (sz, [vp, i64]),
+            "fvsrn_render_dense": (st, [vp, i32, i32, i32, vp, vp, i32, vp, vp, vp, vp]),
+            "fvsrn_dense_eval_points": (st, [vp, i32, i32, i32, vp, i64, vp, vp]),
+            "fvsrn_sample_points": (st, [C.c_uint64, C.c_uint64, i64, vp, vp]),
+            "fvsrn_cast_grid": (st, [vp, vp, i64, i32, vp]),
+            "fvsrn_num_weights": (i64, [vp]),
+            "fvsrn_status_str": (C.c_char_p, [st]),
+            "fvsrn_last_error": (C.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype, f.argtypes = res, args
+        _lib = L
+    return _lib
+
+
+def _check(status: int, what: str):
+    if status != OK:
+        L = lib()
+        raise FvsrnError(status, "%s: %s (%s)" % (what, L.fvsrn_status_str(status).decode(),
+                                                  L.fvsrn_last_error().decode()))
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+# ----------------------------------------------------------- structs
+
+def net_desc(spec: I.NetSpec, precision="f32", grid_dtype=F32) -> NetDesc:
+    return NetDesc(spec.R, spec.F, grid_dtype, spec.K, spec.L, spec.c, spec.H, ACT[spec.act],
+                   PREC[precision] if isinstance(precision, str) else precision)
+
+
+def tf_struct(tf: I.TF) -> TFStruct:
+    s = TFStruct()
+    s.n = len(tf.points)
+    for i, (d, r, g, b, a) in enumerate(tf.points):
+        s.density[i] = d
+        s.rgba[i][0], s.rgba[i][1], s.rgba[i][2], s.rgba[i][3] = r, g, b, a
+    s.opacity_scale = tf.opacity_scale
+    return s
+
+
+def camera_structs(cams: Sequence[I.Camera]):
+    arr = (CameraStruct * len(cams))()
+    for k, c in enumerate(cams):
+        s = arr[k]
+        s.ortho = 1 if c.ortho else 0
+        for a in range(3):
+            s.eye[a], s.target[a], s.up[a] = c.eye[a], c.target[a], c.up[a]
+        s.fov_y_deg, s.ortho_half_extent = c.fov_y_deg, c.ortho_half_extent
+        s.width, s.height, s.time = c.width, c.height, c.time
+    return arr
+
+
+def march_struct(m: I.March) -> MarchStruct:
+    return MarchStruct(m.step, m.fixed_steps, m.ert_eps, 1 if m.phong else 0, m.ka, m.kd, m.ks,
+                       m.shininess)
+
+
+class Network:
+    """Device-resident fV-SRN: latent grid (FP32 or FP16), FP32 weights and
+    (host) keyframe times."""
+
+    def __init__(self, spec: I.NetSpec, latent, weights, key_times=None, device="cuda",
+                 grid_dtype=F32):
+        self.spec = spec
+        lat = torch.as_tensor(latent, dtype=torch.float32).reshape(-1).contiguous().to(device)
+        if grid_dtype == F16:
+            half = torch.empty(lat.numel(), dtype=torch.float16, device=device)
+            fvsrn_cast_grid(lat, half, F16)
+            lat = half
+        self.latent = lat
+        self.grid_dtype = grid_dtype
+        self.weights = torch.as_tensor(weights, dtype=torch.float32).reshape(-1).contiguous().to(device)
+        if spec.K > 1:
+            kt = list(key_times)
+            self._kt = (C.c_float * len(kt))(*kt)
+        else:
+            self._kt = None
+        assert self.weights.numel() == spec.n_weights
+        assert self.latent.numel() == spec.n_latent
+
+    def desc(self, precision="f32") -> NetDesc:
+        return net_desc(self.spec, precision, self.grid_dtype)
+
+    def params(self) -> Params:
+        return Params(self.latent.data_ptr(), self.weights.data_ptr(),
+                      C.cast(self._kt, C.POINTER(C.c_float)) if self._kt is not None else None)
+
+
+# ----------------------------------------------------------- calls
+
+def fvsrn_render(net: Network, tf: I.TF, cams: Sequence[I.Camera], march: I.March,
+                 precision="f32", out: Optional[torch.Tensor] = None,
+                 stats: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    cams = list(cams)
+    if out is None:
+        out = torch.empty((len(cams), cams[0].height, cams[0].width, 4), dtype=torch.float32,
+                          device=net.weights.device)
+    d, p, t, cs, m = net.desc(precision), net.params(), tf_struct(tf), camera_structs(cams), march_struct(march)
+    _check(lib().fvsrn_render(C.byref(d), C.byref(p), C.byref(t), cs, len(cams), C.byref(m), _ptr(out),
+                              _ptr(stats), _stream(stream)), "fvsrn_render")
+    return out
+
+
+def fvsrn_eval_points(net: Network, xyz: torch.Tensor, time: float = 0.0, precision="f32",
+                      out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    n = xyz.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=xyz.device)
+    d, p = net.desc(precision), net.params()
+    _check(lib().fvsrn_eval_points(C.byref(d), C.byref(p), _ptr(xyz), n, time, _ptr(out), _stream(stream)),
+           "fvsrn_eval_points")
+    return out
+
+
+def fvsrn_grad_points(net: Network, xyz: torch.Tensor, time: float = 0.0, precision="f32",
+                      stream=None):
+    n = xyz.shape[0]
+    dens = torch.empty(n, dtype=torch.float32, device=xyz.device)
+    grad = torch.empty((n, 3), dtype=torch.float32, device=xyz.device)
+    d, p = net.desc(precision), net.params()
+    _check(lib().fvsrn_grad_points(C.byref(d), C.byref(p), _ptr(xyz), n, time, _ptr(dens), _ptr(grad),
+                                   _stream(stream)), "fvsrn_grad_points")
+    return dens, grad
+
+
+def fvsrn_render_dense(vol: torch.Tensor, tf: I.TF, cams: Sequence[I.Camera], march: I.March,
+                       out: Optional[torch.Tensor] = None, stats: Optional[torch.Tensor] = None,
+                       stream=None) -> torch.Tensor:
+    cams = list(cams)
+    nz, ny, nx = vol.shape
+    if out is None:
+        out = torch.empty((len(cams), cams[0].height, cams[0].width, 4), dtype=torch.float32,
+                          device=vol.device)
+    t, cs, m = tf_struct(tf), camera_structs(cams), march_struct(march)
+    _check(lib().fvsrn_render_dense(_ptr(vol), nx, ny, nz, C.byref(t), cs, len(cams), C.byref(m), _ptr(out),
+                                    _ptr(stats), _stream(stream)), "fvsrn_render_dense")
+    return out
+
+
+def fvsrn_dense_eval_points(vol: torch.Tensor, xyz: torch.Tensor, out=None, stream=None):
+    nz, ny, nx = vol.shape
+    n = xyz.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=xyz.device)
+    _check(lib().fvsrn_dense_eval_points(_ptr(vol), nx, ny, nz, _ptr(xyz), n, _ptr(out), _stream(stream)),
+           "fvsrn_dense_eval_points")
+    return out
+
+
+def fvsrn_sample_points(seed: int, counter: int, n: int, out=None, device="cuda", stream=None):
+    if out is None:
+        out = torch.empty((n, 3), dtype=torch.float32, device=device)
+    _check(lib().fvsrn_sample_points(seed, counter, n, _ptr(out), _stream(stream)), "fvsrn_sample_points")
+    return out
+
+
+def fvsrn_cast_grid(src: torch.Tensor, dst: torch.Tensor, dtype: int = F16, stream=None):
+    _check(lib().fvsrn_cast_grid(_ptr(src), _ptr(dst), src.numel(), dtype, _stream(stream)),
+           "fvsrn_cast_grid")
+    return dst
+
+
+def fvsrn_num_weights(spec: I.NetSpec) -> int:
+    d = net_desc(spec)
+    return lib().fvsrn_num_weights(C.byref(d))
+
+
+def fvsrn_train_workspace_size(spec: I.NetSpec, n: int) -> int:
+    d = net_desc(spec)
+    return lib().fvsrn_train_workspace_size(C.byref(d), n)
+
+
+def fvsrn_train_step(net: Network, d_latent: torch.Tensor, d_weights: torch.Tensor, xyz: torch.Tensor,
+                     target: Optional[torch.Tensor] = None, dloss_dy: Optional[torch.Tensor] = None,
+                     adam: Optional[dict] = None, out_loss: Optional[torch.Tensor] = None,
+                     workspace: Optional[torch.Tensor] = None, stream=None):
+    """One training step on ``net`` (FP32 latent grid, K == 1). ``adam`` is a
+    dict with lr_grid, lr_mlp, beta1, beta2, eps, step and the four moment
+    tensors m_latent, v_latent, m_weights, v_weights; None computes gradients
+    only."""
+    n = xyz.shape[0]
+    d = net.desc("f32")
+    if workspace is None:
+        ws = lib().fvsrn_train_workspace_size(C.byref(d), n)
+        workspace = torch.empty(max(ws, 16), dtype=torch.uint8, device=xyz.device)
+    a = None
+    if adam is not None:
+        a = AdamStruct(adam["lr_grid"], adam["lr_mlp"], adam.get("beta1", 0.9), adam.get("beta2", 0.999),
+                       adam.get("eps", 1e-8), adam["step"], adam["m_latent"].data_ptr(),
+                       adam["v_latent"].data_ptr(), adam["m_weights"].data_ptr(), adam["v_weights"].data_ptr())
+    _check(lib().fvsrn_train_step(C.byref(d), _ptr(net.latent), _ptr(net.weights), _ptr(d_latent),
+                                  _ptr(d_weights), _ptr(xyz), n, _ptr(target), _ptr(dloss_dy),
+                                  C.byref(a) if a is not None else None, _ptr(out_loss), _ptr(workspace),
+                                  workspace.numel(), _stream(stream)), "fvsrn_train_step")

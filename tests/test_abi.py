@@ -1,0 +1,147 @@
+"""The C ABI without a GPU: the library loads, exports every function that
+include/fvsrn.h declares, and rejects bad arguments on the host before any
+launch (so these calls are safe on a machine without a GPU)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2112_01579_amd import fvsrn as FV
+from paper_2112_01579_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _built():
+    return os.path.exists(FV.LIB_PATH)
+
+
+pytestmark = pytest.mark.skipif(not _built(), reason="libfvsrn.so not built")
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "fvsrn.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(fvsrn_[a-z_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 12
+    L = FV.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(FV.EXPORTS) == set(names)
+
+
+def test_num_weights_matches_layout():
+    for spec in (I.CFG1, I.CFG2, I.CFG4):
+        assert FV.fvsrn_num_weights(spec) == spec.n_weights
+    assert FV.fvsrn_num_weights(I.CFG1) == 3297
+    assert FV.fvsrn_num_weights(I.CFG2) == 5377
+
+
+def test_status_strings():
+    L = FV.lib()
+    for s in range(5):
+        assert L.fvsrn_status_str(s)
+
+
+FAKE = 0x10000  # aligned, never dereferenced: validation fails first
+
+
+def _desc(**kw):
+    d = FV.net_desc(I.CFG1)
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+def _params(lat=FAKE, w=FAKE):
+    return FV.Params(lat, w, None)
+
+
+def _render(d, p=None, tf=None, cams=None, nv=1, m=None, out=FAKE):
+    tf = tf or FV.tf_struct(I.ramp_tf())
+    cams = cams if cams is not None else FV.camera_structs([I.ortho_camera(8, 8)])
+    m = m or FV.march_struct(I.cfg1_march())
+    p = p or _params()
+    return FV.lib().fvsrn_render(C.byref(d), C.byref(p), C.byref(tf), cams, nv, C.byref(m),
+                                 C.c_void_p(out) if out else None, None, None)
+
+
+def test_render_argument_errors():
+    L = FV.lib()
+    assert _render(_desc(grid_res=1)) == FV.ERR_INVALID_ARGUMENT
+    assert _render(_desc(hidden_width=40)) == FV.ERR_UNSUPPORTED
+    assert _render(_desc(grid_channels=16)) == FV.ERR_UNSUPPORTED      # (16, 4) not compiled
+    assert _render(_desc(precision=7)) == FV.ERR_INVALID_ARGUMENT
+    assert _render(_desc(activation=9)) == FV.ERR_INVALID_ARGUMENT
+    assert _render(_desc(), p=_params(lat=0)) == FV.ERR_INVALID_ARGUMENT
+    assert _render(_desc(), p=_params(w=FAKE + 4)) == FV.ERR_INVALID_ARGUMENT  # misaligned
+    assert b"aligned" in L.fvsrn_last_error()
+    assert _render(_desc(), nv=0) == FV.ERR_INVALID_ARGUMENT
+    assert _render(_desc(), out=0) == FV.ERR_INVALID_ARGUMENT
+    bad_tf = FV.tf_struct(I.TF(points=((0.5, 0, 0, 0, 0), (0.2, 1, 1, 1, 1))))
+    assert _render(_desc(), tf=bad_tf) == FV.ERR_INVALID_ARGUMENT
+    one_pt = FV.tf_struct(I.TF(points=((0.5, 0, 0, 0, 0),)))
+    assert _render(_desc(), tf=one_pt) == FV.ERR_INVALID_ARGUMENT
+    cams = FV.camera_structs([I.ortho_camera(8, 8), I.ortho_camera(8, 9)])
+    assert _render(_desc(), cams=cams, nv=2) == FV.ERR_INVALID_ARGUMENT
+    m = FV.march_struct(I.March(step=0.0, fixed_steps=0))
+    assert _render(_desc(), m=m) == FV.ERR_INVALID_ARGUMENT
+    m = FV.march_struct(I.March(step=0.1, ert_eps=-1.0))
+    assert _render(_desc(), m=m) == FV.ERR_INVALID_ARGUMENT
+    # time-varying needs ascending key times
+    d = _desc(num_keyframes=2)
+    kt = (C.c_float * 2)(1.0, 1.0)
+    p = FV.Params(FAKE, FAKE, C.cast(kt, C.POINTER(C.c_float)))
+    assert _render(d, p=p) == FV.ERR_INVALID_ARGUMENT
+    p = FV.Params(FAKE, FAKE, None)
+    assert _render(d, p=p) == FV.ERR_INVALID_ARGUMENT
+
+
+def test_points_argument_errors_and_empty_noop():
+    L = FV.lib()
+    d, p = _desc(), _params()
+    assert L.fvsrn_eval_points(C.byref(d), C.byref(p), C.c_void_p(FAKE), -1, 0.0, C.c_void_p(FAKE), None) \
+        == FV.ERR_INVALID_ARGUMENT
+    # n == 0 is a no-op that touches nothing
+    assert L.fvsrn_eval_points(C.byref(d), C.byref(p), None, 0, 0.0, None, None) == FV.OK
+    assert L.fvsrn_grad_points(C.byref(d), C.byref(p), None, 0, 0.0, None, None, None) == FV.OK
+    assert L.fvsrn_eval_points(C.byref(d), C.byref(p), C.c_void_p(FAKE + 8), 5, 0.0, C.c_void_p(FAKE), None) \
+        == FV.ERR_INVALID_ARGUMENT
+    assert L.fvsrn_grad_points(C.byref(d), C.byref(p), C.c_void_p(FAKE), 5, 0.0, None, None, None) \
+        == FV.ERR_INVALID_ARGUMENT
+    assert L.fvsrn_dense_eval_points(C.c_void_p(FAKE), 1, 4, 4, C.c_void_p(FAKE), 3, C.c_void_p(FAKE), None) \
+        == FV.ERR_INVALID_ARGUMENT
+    assert L.fvsrn_dense_eval_points(C.c_void_p(FAKE), 4, 4, 4, None, 0, None, None) == FV.OK
+    assert L.fvsrn_sample_points(1, 2, 0, None, None) == FV.OK
+    assert L.fvsrn_sample_points(1, 2, -3, None, None) == FV.ERR_INVALID_ARGUMENT
+    assert L.fvsrn_cast_grid(C.c_void_p(FAKE), C.c_void_p(FAKE), 4, 0, None) == FV.ERR_INVALID_ARGUMENT
+    assert L.fvsrn_cast_grid(None, None, 0, 1, None) == FV.OK
+
+
+def test_train_argument_errors():
+    L = FV.lib()
+    d = _desc()
+    args = [C.c_void_p(FAKE)] * 4
+    # FP16 latent grids and reduced precision are not trainable
+    d16 = _desc(grid_dtype=1)
+    assert L.fvsrn_train_step(C.byref(d16), *args, C.c_void_p(FAKE), 4, C.c_void_p(FAKE), None, None, None,
+                              None, 0, None) == FV.ERR_UNSUPPORTED
+    dk = _desc(num_keyframes=2)
+    assert L.fvsrn_train_step(C.byref(dk), *args, C.c_void_p(FAKE), 4, C.c_void_p(FAKE), None, None, None,
+                              None, 0, None) == FV.ERR_UNSUPPORTED
+    # neither target nor upstream gradient
+    assert L.fvsrn_train_step(C.byref(d), *args, C.c_void_p(FAKE), 4, None, None, None, None, None, 0, None) \
+        == FV.ERR_INVALID_ARGUMENT
+    # missing Adam moments
+    a = FV.AdamStruct(1e-2, 1e-3, 0.9, 0.999, 1e-8, 1, FAKE, None, FAKE, FAKE)
+    assert L.fvsrn_train_step(C.byref(d), *args, C.c_void_p(FAKE), 4, C.c_void_p(FAKE), None, C.byref(a), None,
+                              None, 0, None) == FV.ERR_INVALID_ARGUMENT
+    a = FV.AdamStruct(1e-2, 1e-3, 0.9, 0.999, 1e-8, 0, FAKE, FAKE, FAKE, FAKE)
+    assert L.fvsrn_train_step(C.byref(d), *args, C.c_void_p(FAKE), 4, C.c_void_p(FAKE), None, C.byref(a), None,
+                              None, 0, None) == FV.ERR_INVALID_ARGUMENT

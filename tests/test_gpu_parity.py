@@ -1,0 +1,285 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs. Tolerances:
+  * FP32 network path: image max abs error <= 1e-5 with early ray termination
+    off; densities <= 1e-5.
+  * FP16 MFMA path: <= 3e-3 per RGBA channel and per density.
+  * BF16 MFMA path: reported; asserted against a loose 3e-2 bound (8-bit
+    mantissa on 5 layers).
+Dense-grid DVR and the utilities are checked at FP32 rounding level or bit
+for bit."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2112_01579_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+FP16_TOL = 3e-3
+BF16_TOL = 3e-2
+
+
+@pytest.fixture(scope="module")
+def FV():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2112_01579_amd import fvsrn
+    fvsrn.lib()
+    return fvsrn
+
+
+def _nets(FV, spec, seed, key_times=None, grid_dtype=0):
+    lat, w = I.net_params(spec, seed)
+    gnet = FV.Network(spec, lat, w, key_times=key_times, grid_dtype=grid_dtype)
+    if grid_dtype == FV.F16:
+        lat = lat.astype(np.float16).astype(np.float64)   # the oracle reads what the GPU reads
+    onet = O.Net(spec, lat, w, key_times)
+    return gnet, onet
+
+
+def _report(name, err):
+    print("%s max abs err %.3g" % (name, err), flush=True)
+
+
+# --------------------------------------------------------------- cfg1
+
+@pytest.fixture(scope="module")
+def cfg1(FV):
+    gnet, onet = _nets(FV, I.CFG1, I.SEED[1])
+    tf, cams, m = I.ramp_tf(), [I.ortho_camera(64, 64)], I.cfg1_march()
+    ref, ns = O.render(O.Field(net=onet), tf, cams, m)
+    return gnet, onet, tf, cams, m, ref, ns
+
+
+def test_cfg1_render_fp32(FV, cfg1):
+    gnet, onet, tf, cams, m, ref, ns = cfg1
+    stats = torch.zeros(2, dtype=torch.int64, device="cuda")
+    img = FV.fvsrn_render(gnet, tf, cams, m, "f32", stats=stats).cpu().numpy()
+    err = np.abs(img - ref).max()
+    _report("cfg1 fp32 render", err)
+    assert err <= FP32_TOL
+    assert stats[0].item() == ns == 64 * 64 * 128
+    assert stats[1].item() == 64 * 64
+
+
+@pytest.mark.parametrize("prec,tol", [("f16", FP16_TOL), ("bf16", BF16_TOL)])
+def test_cfg1_render_reduced_precision(FV, cfg1, prec, tol):
+    gnet, onet, tf, cams, m, ref, ns = cfg1
+    img = FV.fvsrn_render(gnet, tf, cams, m, prec).cpu().numpy()
+    err = np.abs(img - ref).max()
+    _report("cfg1 %s render" % prec, err)
+    assert err <= tol
+
+
+def test_render_is_deterministic(FV, cfg1):
+    gnet, onet, tf, cams, m, ref, ns = cfg1
+    a = FV.fvsrn_render(gnet, tf, cams, m, "f16")
+    b = FV.fvsrn_render(gnet, tf, cams, m, "f16")
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", FP32_TOL), ("f16", FP16_TOL), ("bf16", BF16_TOL)])
+@pytest.mark.parametrize("spec_name", ["CFG1", "CFG2", "CFG4"])
+def test_eval_points(FV, spec_name, prec, tol):
+    spec = getattr(I, spec_name)
+    gnet, onet = _nets(FV, spec, 77)
+    # several tiles and a ragged tail; a few points outside the box (clamped latent)
+    xyz = I.uniform_points(64 * 37 + 13, 5, -1.05, 1.05)
+    ref = O.eval_points(onet, xyz)
+    out = FV.fvsrn_eval_points(gnet, torch.from_numpy(xyz).cuda(), 0.0, prec).cpu().numpy()
+    err = np.abs(out - ref).max()
+    _report("eval %s %s" % (spec_name, prec), err)
+    assert err <= tol
+
+
+def test_eval_points_fp16_grid(FV):
+    gnet, onet = _nets(FV, I.CFG2, 12, grid_dtype=1)
+    xyz = I.uniform_points(5000, 6)
+    ref = O.eval_points(onet, xyz)
+    for prec, tol in (("f32", FP32_TOL), ("f16", FP16_TOL)):
+        out = FV.fvsrn_eval_points(gnet, torch.from_numpy(xyz).cuda(), 0.0, prec).cpu().numpy()
+        assert np.abs(out - ref).max() <= tol
+
+
+def test_eval_points_activations(FV):
+    for act in ("snakealt", "identity"):
+        spec = I.NetSpec(R=16, F=8, L=4, c=32, H=3, act=act)
+        lat, w = I.net_params(spec, 3)
+        if act == "identity":
+            w = w * 0.5
+        gnet = FV.Network(spec, lat, w)
+        onet = O.Net(spec, lat, w)
+        xyz = I.uniform_points(3000, 8)
+        ref = O.eval_points(onet, xyz)
+        out = FV.fvsrn_eval_points(gnet, torch.from_numpy(xyz).cuda(), 0.0, "f32").cpu().numpy()
+        _report("eval act=%s" % act, np.abs(out - ref).max())
+        assert np.abs(out - ref).max() <= FP32_TOL
+
+
+def test_eval_points_edge_sizes(FV):
+    gnet, onet = _nets(FV, I.CFG1, 4)
+    for n in (1, 63, 64, 65):
+        xyz = I.uniform_points(n, n)
+        ref = O.eval_points(onet, xyz)
+        out = FV.fvsrn_eval_points(gnet, torch.from_numpy(xyz).cuda()).cpu().numpy()
+        assert out.shape == (n,) and np.abs(out - ref).max() <= FP32_TOL
+    out = FV.fvsrn_eval_points(gnet, torch.empty((0, 3), device="cuda"))
+    assert out.numel() == 0
+
+
+# -------------------------------------------------- cfg2-shaped renders
+
+def test_cfg2_render_small_ragged(FV):
+    """cfg2 network, 4-view orbit at 37x29 (ragged 8x8 tiles), step 1/256."""
+    gnet, onet = _nets(FV, I.CFG2, I.SEED[2])
+    tf = I.ramp_tf()
+    cams = I.orbit_cameras(4, 37, 29)
+    m = I.March(step=1 / 256, ert_eps=0.0)
+    ref, ns = O.render(O.Field(net=onet), tf, cams, m)
+    stats = torch.zeros(2, dtype=torch.int64, device="cuda")
+    img = FV.fvsrn_render(gnet, tf, cams, m, "f32", stats=stats).cpu().numpy()
+    err = np.abs(img - ref).max()
+    _report("cfg2 small fp32", err)
+    assert err <= FP32_TOL
+    assert abs(stats[0].item() - ns) <= 0.001 * ns
+    for prec, tol in (("f16", FP16_TOL), ("bf16", BF16_TOL)):
+        img = FV.fvsrn_render(gnet, tf, cams, m, prec).cpu().numpy()
+        err = np.abs(img - ref).max()
+        _report("cfg2 small %s" % prec, err)
+        assert err <= tol
+
+
+def test_cfg2_full_size_sampled_pixels(FV):
+    """The benchmark launch (8 views x 1024^2, ERT 1e-3) against the oracle on
+    sampled pixels."""
+    gnet, onet = _nets(FV, I.CFG2, I.SEED[2], grid_dtype=1)
+    tf = I.ramp_tf()
+    cams = I.cfg2_cameras(1024, 1024, 8)
+    m = I.cfg2_march(1e-3)
+    rng = np.random.default_rng(3)
+    pix = rng.choice(8 * 1024 * 1024, 192, replace=False)
+    ref, _ = O.render(O.Field(net=onet), tf, cams, m, pixels=pix)
+    img = FV.fvsrn_render(gnet, tf, cams, m, "f16").cpu().numpy().reshape(-1, 4)
+    err = np.abs(img[pix] - ref.reshape(-1, 4)[pix]).max()
+    _report("cfg2 full-size f16 sampled", err)
+    assert err <= FP16_TOL
+
+
+def test_c48_render(FV):
+    spec = I.NetSpec(R=32, F=16, L=8, c=48, H=4)
+    gnet, onet = _nets(FV, spec, 9)
+    tf = I.ramp_tf()
+    cams = I.orbit_cameras(2, 24, 16)
+    m = I.March(step=1 / 128)
+    ref, _ = O.render(O.Field(net=onet), tf, cams, m)
+    for prec, tol in (("f32", FP32_TOL), ("f16", FP16_TOL)):
+        img = FV.fvsrn_render(gnet, tf, cams, m, prec).cpu().numpy()
+        err = np.abs(img - ref).max()
+        _report("c48 %s" % prec, err)
+        assert err <= tol
+
+
+def test_time_varying_render(FV):
+    spec = I.NetSpec(R=16, F=16, L=8, c=32, H=4, K=4)
+    kt = I.CFG5_KEY_TIMES
+    gnet, onet = _nets(FV, spec, 13, key_times=kt)
+    tf = I.ramp_tf()
+    cams = I.orbit_cameras(4, 16, 16, times=[-1.0, 2.5, 7.0, 20.0])
+    m = I.March(step=1 / 64)
+    ref, _ = O.render(O.Field(net=onet), tf, cams, m)
+    img = FV.fvsrn_render(gnet, tf, cams, m, "f32").cpu().numpy()
+    err = np.abs(img - ref).max()
+    _report("time-varying fp32", err)
+    assert err <= FP32_TOL
+    xyz = I.uniform_points(1000, 2)
+    for t in (0.0, 5.5, 11.9):
+        out = FV.fvsrn_eval_points(gnet, torch.from_numpy(xyz).cuda(), t).cpu().numpy()
+        assert np.abs(out - O.eval_points(onet, xyz, t)).max() <= FP32_TOL
+
+
+def test_render_misses_and_ert(FV):
+    gnet, onet = _nets(FV, I.CFG1, 5)
+    tf = I.ramp_tf()
+    # camera looking away from the box: every ray misses
+    away = I.Camera(ortho=False, eye=(0.0, 0.0, 3.0), target=(0.0, 0.0, 6.0), up=(0.0, 1.0, 0.0),
+                    width=9, height=7)
+    stats = torch.zeros(2, dtype=torch.int64, device="cuda")
+    img = FV.fvsrn_render(gnet, tf, [away], I.March(step=0.01), stats=stats)
+    assert torch.count_nonzero(img).item() == 0 and stats.sum().item() == 0
+    # ERT: counts match the oracle's
+    m = I.March(step=1 / 100, ert_eps=1e-2)
+    cams = I.orbit_cameras(1, 16, 16)
+    ref, ns = O.render(O.Field(net=onet), tf, cams, m)
+    stats.zero_()
+    img = FV.fvsrn_render(gnet, tf, cams, m, "f32", stats=stats).cpu().numpy()
+    assert abs(stats[0].item() - ns) <= 0.002 * ns + 2
+    # a lane stopping one step apart from the oracle changes its pixel by < eps
+    assert np.abs(img - ref).max() <= 1e-2
+
+
+# ------------------------------------------------------------ dense DVR
+
+def test_dense_render_and_points(FV):
+    vol = I.gaussian_volume(40, 12, seed=5)
+    tvol = torch.from_numpy(vol).cuda()
+    tf = I.ramp_tf()
+    cams = I.orbit_cameras(3, 33, 20)
+    for m in (I.March(step=1 / 64), I.March(step=1 / 64, phong=True), I.March(fixed_steps=50, step=0.0)):
+        ref, ns = O.render(O.Field(vol=vol), tf, cams, m)
+        stats = torch.zeros(2, dtype=torch.int64, device="cuda")
+        img = FV.fvsrn_render_dense(tvol, tf, cams, m, stats=stats).cpu().numpy()
+        err = np.abs(img - ref).max()
+        _report("dense render phong=%s" % m.phong, err)
+        assert err <= FP32_TOL
+        assert abs(stats[0].item() - ns) <= 0.001 * ns
+    xyz = I.uniform_points(10000, 3, -1.1, 1.1)
+    out = FV.fvsrn_dense_eval_points(tvol, torch.from_numpy(xyz).cuda()).cpu().numpy()
+    assert np.abs(out - O.dense_eval_points(vol, xyz)).max() <= 1e-6
+
+
+# ------------------------------------------------------------ utilities
+
+def _philox4x32_10(ctr, key):
+    """Philox4x32-10 (Salmon et al., SC'11) in numpy uint64 arithmetic."""
+    M0, M1 = np.uint64(0xD2511F53), np.uint64(0xCD9E8D57)
+    W0, W1 = np.uint64(0x9E3779B9), np.uint64(0xBB67AE85)
+    mask = np.uint64(0xFFFFFFFF)
+    c = [x.astype(np.uint64) for x in ctr]
+    k0, k1 = np.uint64(key[0]), np.uint64(key[1])
+    for r in range(10):
+        if r:
+            k0 = (k0 + W0) & mask
+            k1 = (k1 + W1) & mask
+        p0 = M0 * c[0]
+        p1 = M1 * c[2]
+        hi0, lo0 = p0 >> np.uint64(32), p0 & mask
+        hi1, lo1 = p1 >> np.uint64(32), p1 & mask
+        c = [hi1 ^ c[1] ^ k0, lo1, hi0 ^ c[3] ^ k1, lo0]
+    return c
+
+
+def test_sample_points_bit_exact(FV):
+    n, seed, counter = 100003, 0x123456789ABCDEF, 42
+    xyz = FV.fvsrn_sample_points(seed, counter, n).cpu().numpy()
+    i = np.arange(n, dtype=np.uint64)
+    ctr = [i & np.uint64(0xFFFFFFFF), i >> np.uint64(32), np.full(n, counter, np.uint64),
+           np.zeros(n, np.uint64)]
+    c = _philox4x32_10(ctr, (seed & 0xFFFFFFFF, seed >> 32))
+    want = np.stack([-1.0 + (c[a] >> np.uint64(8)).astype(np.float64) * 2.0 ** -23 for a in range(3)], 1)
+    assert np.array_equal(xyz.astype(np.float64), want)
+    assert xyz.min() >= -1.0 and xyz.max() < 1.0
+    assert abs(xyz.mean()) < 0.01
+
+
+def test_cast_grid_round_to_nearest_even(FV):
+    x = torch.randn(100001, device="cuda") * 3
+    h = torch.empty(x.numel(), dtype=torch.float16, device="cuda")
+    FV.fvsrn_cast_grid(x, h, FV.F16)
+    assert torch.equal(h, x.half())
+    b = torch.empty(x.numel(), dtype=torch.bfloat16, device="cuda")
+    FV.fvsrn_cast_grid(x, b, FV.BF16)
+    assert torch.equal(b, x.bfloat16())
