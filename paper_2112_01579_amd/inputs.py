@@ -165,7 +165,7 @@ def gaussian_volume(D: int = 256, n: int = 64, seed: int = 1001, sigma=(0.02, 0.
     (z, y, x)."""
     rng = np.random.default_rng(seed)
     ax = _axis(D)
-    vol = np.zeros((D, D, D), dtype=np.float64)
+    vol = np.zeros((D, D, D), dtype=np.float32)
     for _ in range(n):
         cen = rng.uniform(-centre_extent, centre_extent, size=3)
         sig = rng.uniform(sigma[0], sigma[1], size=3)
@@ -181,11 +181,15 @@ def gaussian_volume(D: int = 256, n: int = 64, seed: int = 1001, sigma=(0.02, 0.
         (x0, x1), (y0, y1), (z0, z1) = sl
         if x1 <= x0 or y1 <= y0 or z1 <= z0:
             continue
-        Z, Y, X = np.meshgrid(ax[z0:z1] - cen[2], ax[y0:y1] - cen[1], ax[x0:x1] - cen[0],
-                              indexing="ij")
-        d = np.stack([X, Y, Z], axis=-1) @ rot   # rotated offsets R^T (x - c)
-        e = (d[..., 0] / sig[0]) ** 2 + (d[..., 1] / sig[1]) ** 2 + (d[..., 2] / sig[2]) ** 2
-        vol[z0:z1, y0:y1, x0:x1] += a * np.exp(-0.5 * e)
+        # quadratic form (x-c)^T M (x-c) with M = R S^-2 R^T, evaluated by broadcasting
+        M = (rot / sig[None, :] ** 2) @ rot.T
+        X = (ax[x0:x1] - cen[0]).astype(np.float32)[None, None, :]
+        Y = (ax[y0:y1] - cen[1]).astype(np.float32)[None, :, None]
+        Z = (ax[z0:z1] - cen[2]).astype(np.float32)[:, None, None]
+        M = M.astype(np.float32)
+        e = (M[0, 0] * X * X + M[1, 1] * Y * Y) + (M[2, 2] * Z * Z + 2 * M[0, 1] * X * Y)
+        e = e + (2 * M[0, 2] * X * Z + 2 * M[1, 2] * Y * Z)
+        vol[z0:z1, y0:y1, x0:x1] += np.float32(a) * np.exp(np.float32(-0.5) * e)
     vol /= vol.max()
     return vol.astype(np.float32)
 
