@@ -99,7 +99,7 @@ def main():
     cams = I.cfg2_cameras(1024, 1024, 8)
     march = I.cfg2_march(1e-3)
     out = torch.empty((8, 1024, 1024, 4), dtype=torch.float32, device=dev)
-    stats = torch.zeros(2, dtype=torch.int64, device=dev)
+    stats = torch.zeros(3, dtype=torch.int64, device=dev)
 
     def step(n=net, prec="f16"):
         FV.fvsrn_render(n, tf, cams, march, prec, out=out, stats=stats)
@@ -108,7 +108,7 @@ def main():
     stats.zero_()
     step()
     torch.cuda.synchronize()
-    samples, rays = int(stats[0].item()), int(stats[1].item())
+    samples, rays, slots = int(stats[0].item()), int(stats[1].item()), int(stats[2].item())
 
     per, wall = time_launches(step, args.steps, args.warmup)
     ms_launch = float(np.mean(per))
@@ -134,6 +134,7 @@ def main():
                         "weights), 8-view 1024x1024 perspective orbit, step 1/256, ERT 1e-3, one launch",
             "views": len(cams), "width": 1024, "height": 1024, "step": 1 / 256, "ert_eps": 1e-3,
             "samples_per_step": samples, "rays_hit_per_step": rays,
+            "tile_occupancy": samples / max(slots, 1),
             "flop_per_sample": fps,
         },
         "roofline": {

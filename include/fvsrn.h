@@ -130,9 +130,11 @@ typedef struct {
 /* Render n_views images of the fV-SRN with one launch (Sec. 4, Sec. 5.1):
    out_rgba [n_views][H][W][4] FP32, premultiplied colour and opacity over a
    transparent background. All cameras must share width and height.
-   stats (nullable, device, 2 x u64, accumulated -- the caller zeroes it):
-   [0] += samples composited, [1] += rays that hit the domain. Phong shading
-   needs the forward-mode density gradient (Sec. 6). */
+   stats (nullable, device, 3 x u64, accumulated -- the caller zeroes it):
+   [0] += samples composited, [1] += rays that hit the domain, [2] += network
+   evaluation slots issued (lanes x march steps, idle lanes included; [0]/[2]
+   is the occupancy of the matrix tiles). Phong shading needs the density
+   gradient, computed by forward-mode differentiation (Sec. 6). */
 fvsrn_status fvsrn_render(const fvsrn_net_desc* desc, const fvsrn_params* params,
                           const fvsrn_tf* tf, const fvsrn_camera* cams, int32_t n_views,
                           const fvsrn_march* march, float* out_rgba,
@@ -183,7 +185,8 @@ size_t fvsrn_train_workspace_size(const fvsrn_net_desc* desc, int64_t n);
 /* Plain dense-grid DVR with the same rays, transfer function and compositor
    (the uncompressed reference the paper renders, Sec. 5): vol [nz][ny][nx]
    FP32, vertex-centred over [-1,1]^3, trilinear lookup. Phong uses central
-   differences with a one-voxel step (Sec. 6). */
+   differences with a one-voxel step (Sec. 6). stats as for fvsrn_render
+   ([2] counts one slot per composited sample). */
 fvsrn_status fvsrn_render_dense(const float* vol, int32_t nx, int32_t ny, int32_t nz,
                                 const fvsrn_tf* tf, const fvsrn_camera* cams, int32_t n_views,
                                 const fvsrn_march* march, float* out_rgba,

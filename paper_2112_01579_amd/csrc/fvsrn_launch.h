@@ -76,4 +76,20 @@ int launch_train(const NetDev& net, float* latent, float* weights, float* d_late
 
 const char* last_hip_error();
 
+// Shared host helpers (defined in fvsrn_misc.hip).
+int check_launch();                                   // 0 or 2 after a launch
+int grid_blocks(long long work, int per_block, int cap);
+int device_cus();
+
+// Per-precision network launchers (fvsrn_march.hip compiled per precision).
+int launch_render_p0(const NetDev&, const TFDev&, const ViewBatch&, const MarchDev&, float*, unsigned long long*,
+                     void*);
+int launch_render_p1(const NetDev&, const TFDev&, const ViewBatch&, const MarchDev&, float*, unsigned long long*,
+                     void*);
+int launch_render_p2(const NetDev&, const TFDev&, const ViewBatch&, const MarchDev&, float*, unsigned long long*,
+                     void*);
+int launch_points_p0(const NetDev&, const float*, long long, int, float, float*, float*, void*);
+int launch_points_p1(const NetDev&, const float*, long long, int, float, float*, float*, void*);
+int launch_points_p2(const NetDev&, const float*, long long, int, float, float*, float*, void*);
+
 }  // namespace fvsrn_detail

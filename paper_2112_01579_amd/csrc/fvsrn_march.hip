@@ -1,0 +1,411 @@
+// Fused fV-SRN ray-march and point-evaluation kernels for one network
+// precision (compiled once per precision with FVSRN_PREC = 0 FP32, 1 FP16,
+// 2 BF16).
+//
+// Render: one wavefront owns a tile of rays -- 8x8 pixels in value mode, 4x4
+// pixels (four lanes per ray) in gradient mode. Per march step every lane
+// builds its input row, the wave runs the MLP on the matrix cores, and the
+// ray-owning lanes map the density through the transfer function and
+// composite front to back (Sec. 3, Sec. 4), stopping when the transmittance
+// falls below the termination threshold.
+#include "fvsrn_net.hpp"
+
+#ifndef FVSRN_PREC
+#error "FVSRN_PREC must be defined (0 FP32, 1 FP16, 2 BF16)"
+#endif
+
+namespace fvsrn_detail {
+
+namespace {
+
+// Value mode fits 3 waves per SIMD (<= 168 VGPRs); the gradient mode's
+// extra tangent state needs more registers and runs 2 per SIMD.
+template <bool GRAD>
+constexpr int max_waves() {
+  return GRAD ? 8 : 12;
+}
+constexpr int kLdsBytes = 160 * 1024;
+
+// Waves per workgroup: as many as the LDS holds (weights once plus one input
+// tile per wave), at most max_waves.
+template <class CF, bool GRAD>
+int waves_per_block(int H) {
+  using G = typename CF::G;
+  const int w = (kLdsBytes - G::weight_bytes(H)) / G::FEAT_BYTES;
+  return w < 1 ? 0 : (w > max_waves<GRAD>() ? max_waves<GRAD>() : w);
+}
+
+// ----------------------------------------------------- TF, camera, march
+
+__device__ inline void tf_eval(const TFDev& tf, float d, float rgba[4]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) rgba[q] = tf.base[q];
+  for (int j = 0; j < tf.n_seg; ++j) {
+    const float w = __builtin_amdgcn_fmed3f(fmaf(d, tf.inv[j], tf.off[j]), 0.0f, 1.0f);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rgba[q] = fmaf(w, tf.delta[j][q], rgba[q]);
+  }
+}
+
+struct Ray {
+  float o[3], d[3];
+  float t0, t1, ds;
+  int nseg;
+  bool hit;
+};
+
+__device__ inline Ray make_ray(const CamDev& cam, int px, int py, int W, int H, const MarchDev& m) {
+  Ray r;
+  const float nx = (2.0f * px + 1.0f) / (float)W - 1.0f;
+  const float ny = 1.0f - (2.0f * py + 1.0f) / (float)H;
+  const float sx = cam.aspect * nx;
+  if (cam.ortho) {
+    const float h = cam.half_extent;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      r.o[a] = cam.eye[a] + h * (sx * cam.right[a] + ny * cam.up[a]);
+      r.d[a] = cam.fwd[a];
+    }
+  } else {
+    float dd[3], l2 = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      dd[a] = cam.fwd[a] + cam.tan_half * (sx * cam.right[a] + ny * cam.up[a]);
+      l2 += dd[a] * dd[a];
+    }
+    const float inv = 1.0f / sqrtf(l2);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      r.o[a] = cam.eye[a];
+      r.d[a] = dd[a] * inv;
+    }
+  }
+  float tn = -INFINITY, tf = INFINITY;
+  bool miss = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (r.d[a] == 0.0f) {
+      if (r.o[a] < -1.0f || r.o[a] > 1.0f) miss = true;
+    } else {
+      float ta = (-1.0f - r.o[a]) / r.d[a], tb = (1.0f - r.o[a]) / r.d[a];
+      if (ta > tb) {
+        const float s = ta;
+        ta = tb;
+        tb = s;
+      }
+      tn = fmaxf(tn, ta);
+      tf = fminf(tf, tb);
+    }
+  }
+  tn = fmaxf(tn, 0.0f);
+  r.t0 = tn;
+  r.t1 = tf;
+  r.hit = !miss && tf > tn;
+  if (m.fixed_steps > 0) {
+    r.nseg = m.fixed_steps;
+    r.ds = (tf - tn) / (float)m.fixed_steps;
+  } else {
+    r.ds = m.step;
+    r.nseg = r.hit ? (int)ceilf((tf - tn) / m.step) : 0;
+  }
+  if (!r.hit) r.nseg = 0;
+  return r;
+}
+
+// Segment i of a ray: midpoint parameter and length (last one clipped).
+__device__ inline void segment(const Ray& r, int i, bool fixed, float& tm, float& len) {
+  const float a0 = r.t0 + (float)i * r.ds;
+  float a1 = r.t0 + (float)(i + 1) * r.ds;
+  if (!fixed) a1 = fminf(a1, r.t1);
+  len = a1 - a0;
+  tm = 0.5f * (a0 + a1);
+}
+
+// Blocks are dealt round-robin to the 8 XCDs; remap so that each XCD works
+// on one contiguous range of tiles (neighbouring screen regions share its L2).
+__device__ inline int xcd_block(int nblocks) {
+  const int b = blockIdx.x;
+  if (nblocks % 8 != 0) return b;
+  const int per = nblocks / 8;
+  return (b % 8) * per + b / 8;
+}
+
+// Headlight Blinn-Phong (Sec. 6): light and view along -dir, normal = the
+// normalized density gradient.
+__device__ inline void phong(float rgba[4], float gx, float gy, float gz, const float dir[3], const MarchDev& m) {
+  const float gl = sqrtf(gx * gx + gy * gy + gz * gz);
+  if (gl >= 1e-6f) {
+    const float ndl = fabsf(gx * dir[0] + gy * dir[1] + gz * dir[2]) / gl;
+    const float spec = m.ks * powf(ndl, m.shininess);
+    const float k = m.ka + m.kd * ndl;
+    rgba[0] = fmaf(rgba[0], k, spec);
+    rgba[1] = fmaf(rgba[1], k, spec);
+    rgba[2] = fmaf(rgba[2], k, spec);
+  }
+}
+
+// Front-to-back compositing of one segment (exact Beer-Lambert).
+struct Accum {
+  float T, C[3], A;
+};
+
+__device__ inline void composite(Accum& acc, const float rgba[4], float len) {
+  const float trn = fast_exp(-rgba[3] * len);
+  const float ta = acc.T * (1.0f - trn);
+  acc.C[0] = fmaf(ta, rgba[0], acc.C[0]);
+  acc.C[1] = fmaf(ta, rgba[1], acc.C[1]);
+  acc.C[2] = fmaf(ta, rgba[2], acc.C[2]);
+  acc.A += ta;
+  acc.T *= trn;
+}
+
+// ------------------------------------------------------------- kernels
+
+template <class CF, bool GRAD>
+__global__ __launch_bounds__(max_waves<GRAD>() * 64) void march_kernel(NetDev nd, TFDev tf, ViewBatch vb, MarchDev m,
+                                                               float* out, unsigned long long* stats,
+                                                               int tiles_x, int tiles_y) {
+  using G = typename CF::G;
+  using E = typename CF::E;
+  constexpr int TW = GRAD ? 4 : 8;  // tile edge in pixels
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  stage_weights<CF>(nd, smem);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tiles_per_view = tiles_x * tiles_y;
+  const int tile = xcd_block(gridDim.x) * (int)(blockDim.x >> 6) + wave;
+  if (tile >= tiles_per_view * vb.n_views) return;
+  const int v = tile / tiles_per_view;
+  const int tr = tile % tiles_per_view;
+  const int rl = GRAD ? lane >> 2 : lane;  // ray within the tile
+  const int px = (tr % tiles_x) * TW + (rl % TW);
+  const int py = (tr / tiles_x) * TW + (rl / TW);
+  const LaneRole role = GRAD ? grad_role(lane & 3) : value_role();
+  const CamDev& cam = vb.cam[v];
+  const LatentSrc ls = make_latent_src(nd, cam.key, cam.key_w);
+  const bool in_img = px < vb.width && py < vb.height;
+  const Ray ray = make_ray(cam, in_img ? px : 0, in_img ? py : 0, vb.width, vb.height, m);
+  bool active = in_img && ray.hit && ray.nseg > 0;
+  const bool fixed = m.fixed_steps > 0;
+  E* feat = reinterpret_cast<E*>(smem + G::weight_bytes(nd.H) + wave * G::FEAT_BYTES);
+  E* myrow = feat + lane * G::ROW;
+  Accum acc = {1.0f, {0.0f, 0.0f, 0.0f}, 0.0f};
+  int i = 0;
+  unsigned long long iters = 0;
+  while (__builtin_amdgcn_ballot_w64(active)) {
+    ++iters;
+    float tm, len;
+    segment(ray, i, fixed, tm, len);
+    if (!active) tm = 0.0f;
+    const float sx = active ? ray.o[0] + tm * ray.d[0] : 0.0f;
+    const float sy = active ? ray.o[1] + tm * ray.d[1] : 0.0f;
+    const float sz = active ? ray.o[2] + tm * ray.d[2] : 0.0f;
+    write_features<CF, GRAD>(myrow, ls, role, sx, sy, sz);
+    wave_lds_sync();
+    const float y = mlp_tile<CF, GRAD>(smem, feat, nd.H, role);
+    wave_lds_sync();
+    float dens, gx = 0.0f, gy = 0.0f, gz = 0.0f;
+    if constexpr (GRAD) {
+      // the quad's value lane holds the logit, lanes 1..3 its derivatives
+      const float y0 = quad_bcast0(y);
+      const float t1 = quad_bcast<1>(y), t2 = quad_bcast<2>(y), t3 = quad_bcast<3>(y);
+      dens = sigmoid_f(y0);
+      const float s = dens * (1.0f - dens);
+      gx = s * t1;
+      gy = s * t2;
+      gz = s * t3;
+    } else {
+      dens = sigmoid_f(y);
+    }
+    if (active) {
+      if (len <= 0.0f) {
+        active = false;
+      } else {
+        float rgba[4];
+        tf_eval(tf, dens, rgba);
+        if (m.phong) phong(rgba, gx, gy, gz, ray.d, m);
+        composite(acc, rgba, len);
+        ++i;
+        if (acc.T < m.ert_eps || i >= ray.nseg) active = false;
+      }
+    }
+  }
+  const bool owner = GRAD ? (lane & 3) == 0 : true;
+  if (in_img && owner) {
+    float4* o = reinterpret_cast<float4*>(out) + ((long long)v * vb.height + py) * vb.width + px;
+    *o = make_float4(acc.C[0], acc.C[1], acc.C[2], acc.A);
+  }
+  if (stats) {
+    unsigned long long mine = owner ? (unsigned long long)i : 0ull;
+    unsigned long long hit = (owner && in_img && ray.hit && ray.nseg > 0) ? 1ull : 0ull;
+    for (int off = 32; off > 0; off >>= 1) {
+      mine += __shfl_xor(mine, off, 64);
+      hit += __shfl_xor(hit, off, 64);
+    }
+    if (lane == 0) {
+      atomicAdd(stats, mine);
+      atomicAdd(stats + 1, hit);
+      atomicAdd(stats + 2, iters * (GRAD ? 16ull : 64ull));
+    }
+  }
+}
+
+template <class CF, bool GRAD>
+__global__ __launch_bounds__(max_waves<GRAD>() * 64) void points_kernel(NetDev nd, const float* xyz, long long n, int key,
+                                                                float key_w, float* out_d, float* out_g) {
+  using G = typename CF::G;
+  using E = typename CF::E;
+  constexpr int PER = GRAD ? 16 : 64;  // points per wave step
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  stage_weights<CF>(nd, smem);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  E* feat = reinterpret_cast<E*>(smem + G::weight_bytes(nd.H) + wave * G::FEAT_BYTES);
+  E* myrow = feat + lane * G::ROW;
+  const LaneRole role = GRAD ? grad_role(lane & 3) : value_role();
+  const LatentSrc ls = make_latent_src(nd, key, key_w);
+  const long long nchunks = (n + PER - 1) / PER;
+  const int waves = blockDim.x >> 6;
+  for (long long c = (long long)blockIdx.x * waves + wave; c < nchunks; c += (long long)gridDim.x * waves) {
+    const long long idx = c * PER + (GRAD ? (lane >> 2) : lane);
+    const bool ok = idx < n;
+    float x = 0.0f, y = 0.0f, z = 0.0f;
+    if (ok) {
+      x = xyz[3 * idx];
+      y = xyz[3 * idx + 1];
+      z = xyz[3 * idx + 2];
+    }
+    write_features<CF, GRAD>(myrow, ls, role, x, y, z);
+    wave_lds_sync();
+    const float o = mlp_tile<CF, GRAD>(smem, feat, nd.H, role);
+    wave_lds_sync();
+    if constexpr (GRAD) {
+      const float d = sigmoid_f(quad_bcast0(o));
+      if (ok) {
+        if (role.is_val) {
+          if (out_d) out_d[idx] = d;
+        } else {
+          out_g[3 * idx + role.axis] = d * (1.0f - d) * o;
+        }
+      }
+    } else {
+      if (ok) out_d[idx] = sigmoid_f(o);
+    }
+  }
+}
+
+// ------------------------------------------------------------ launchers
+
+template <class CF, bool GRAD>
+int launch_render_t(const NetDev& nd, const TFDev& tf, const ViewBatch& vb, const MarchDev& m, float* out,
+                    unsigned long long* stats, hipStream_t st) {
+  using G = typename CF::G;
+  constexpr int TW = GRAD ? 4 : 8;
+  const int tx = (vb.width + TW - 1) / TW, ty = (vb.height + TW - 1) / TW;
+  const long long tiles = (long long)tx * ty * vb.n_views;
+  const int wpb = waves_per_block<CF, GRAD>(nd.H);
+  if (wpb < 1) return 1;
+  long long blocks = (tiles + wpb - 1) / wpb;
+  if (blocks % 8) blocks += 8 - blocks % 8;
+  const size_t shm = (size_t)G::weight_bytes(nd.H) + (size_t)wpb * G::FEAT_BYTES;
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)march_kernel<CF, GRAD>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kLdsBytes);
+    attr = true;
+  }
+  hipLaunchKernelGGL((march_kernel<CF, GRAD>), dim3((unsigned)blocks), dim3(wpb * 64), shm, st, nd, tf, vb, m, out,
+                     stats, tx, ty);
+  return check_launch();
+}
+
+template <class CF, bool GRAD>
+int launch_points_t(const NetDev& nd, const float* xyz, long long n, int key, float key_w, float* out_d,
+                    float* out_g, hipStream_t st) {
+  using G = typename CF::G;
+  constexpr int PER = GRAD ? 16 : 64;
+  const int wpb = waves_per_block<CF, GRAD>(nd.H);
+  if (wpb < 1) return 1;
+  const size_t shm = (size_t)G::weight_bytes(nd.H) + (size_t)wpb * G::FEAT_BYTES;
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)points_kernel<CF, GRAD>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kLdsBytes);
+    attr = true;
+  }
+  // each wave walks several chunks so that the weight staging is amortised
+  const int blocks = grid_blocks((n + PER - 1) / PER, wpb * 8, device_cus() * 4);
+  hipLaunchKernelGGL((points_kernel<CF, GRAD>), dim3(blocks), dim3(wpb * 64), shm, st, nd, xyz, n, key, key_w,
+                     out_d, out_g);
+  return check_launch();
+}
+
+template <int C, int F, int L, int ACT, bool GRAD>
+struct Entry {
+  using CF = Cfg<FVSRN_PREC, C, F, L, ACT>;
+  static int render(const NetDev& nd, const TFDev& tf, const ViewBatch& vb, const MarchDev& m, float* out,
+                    unsigned long long* stats, hipStream_t st) {
+    return launch_render_t<CF, GRAD>(nd, tf, vb, m, out, stats, st);
+  }
+  static int points(const NetDev& nd, const float* xyz, long long n, int key, float key_w, float* out_d,
+                    float* out_g, hipStream_t st) {
+    return launch_points_t<CF, GRAD>(nd, xyz, n, key, key_w, out_d, out_g, st);
+  }
+};
+
+// Gradient mode is compiled for FP32 and FP16 networks.
+constexpr bool kGradCompiled = FVSRN_PREC != kBF16;
+
+#define FV_NETS(X, ACT, GRAD) \
+  X(32, 8, 4, ACT, GRAD)      \
+  X(32, 16, 8, ACT, GRAD)     \
+  X(48, 8, 4, ACT, GRAD)      \
+  X(48, 16, 8, ACT, GRAD)
+
+#define FV_ALL(X)                \
+  FV_NETS(X, kSine, false)       \
+  FV_NETS(X, kSnakeAlt, false)   \
+  FV_NETS(X, kIdentity, false)
+
+#define FV_ALL_GRAD(X)           \
+  FV_NETS(X, kSine, true)        \
+  FV_NETS(X, kSnakeAlt, true)    \
+  FV_NETS(X, kIdentity, true)
+
+}  // namespace
+
+#define FV_PASTE2(a, b) a##b
+#define FV_PASTE(a, b) FV_PASTE2(a, b)
+
+int FV_PASTE(launch_render_p, FVSRN_PREC)(const NetDev& nd, const TFDev& tf, const ViewBatch& vb, const MarchDev& m,
+                                          float* out, unsigned long long* stats, void* stream) {
+  const bool grad = m.phong != 0;
+  const hipStream_t st = (hipStream_t)stream;
+#define X(C_, F_, L_, ACT_, GRAD_)                                               \
+  if (nd.C == C_ && nd.F == F_ && nd.L == L_ && nd.act == ACT_ && grad == GRAD_) \
+    return Entry<C_, F_, L_, ACT_, GRAD_>::render(nd, tf, vb, m, out, stats, st);
+  FV_ALL(X)
+#if FVSRN_PREC != 2
+  FV_ALL_GRAD(X)
+#endif
+#undef X
+  (void)kGradCompiled;
+  return 1;
+}
+
+int FV_PASTE(launch_points_p, FVSRN_PREC)(const NetDev& nd, const float* xyz, long long n, int key, float key_w,
+                                          float* out_d, float* out_g, void* stream) {
+  const bool grad = out_g != nullptr;
+  const hipStream_t st = (hipStream_t)stream;
+#define X(C_, F_, L_, ACT_, GRAD_)                                               \
+  if (nd.C == C_ && nd.F == F_ && nd.L == L_ && nd.act == ACT_ && grad == GRAD_) \
+    return Entry<C_, F_, L_, ACT_, GRAD_>::points(nd, xyz, n, key, key_w, out_d, out_g, st);
+  FV_ALL(X)
+#if FVSRN_PREC != 2
+  FV_ALL_GRAD(X)
+#endif
+#undef X
+  return 1;
+}
+
+}  // namespace fvsrn_detail

@@ -1,0 +1,333 @@
+// Dense-grid DVR (the uncompressed reference renderer), dense point sampling,
+// Philox point sampling, grid casts, and the precision dispatch of the
+// network launchers.
+#include <stdio.h>
+
+#include "fvsrn_common.hpp"
+
+namespace fvsrn_detail {
+
+namespace {
+
+__device__ inline void tf_eval_d(const TFDev& tf, float d, float rgba[4]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) rgba[q] = tf.base[q];
+  for (int j = 0; j < tf.n_seg; ++j) {
+    const float w = __builtin_amdgcn_fmed3f(fmaf(d, tf.inv[j], tf.off[j]), 0.0f, 1.0f);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rgba[q] = fmaf(w, tf.delta[j][q], rgba[q]);
+  }
+}
+
+struct DRay {
+  float o[3], d[3];
+  float t0, t1, ds;
+  int nseg;
+  bool hit;
+};
+
+__device__ inline DRay make_dray(const CamDev& cam, int px, int py, int W, int H, const MarchDev& m) {
+  DRay r;
+  const float nx = (2.0f * px + 1.0f) / (float)W - 1.0f;
+  const float ny = 1.0f - (2.0f * py + 1.0f) / (float)H;
+  const float sx = cam.aspect * nx;
+  if (cam.ortho) {
+    const float h = cam.half_extent;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      r.o[a] = cam.eye[a] + h * (sx * cam.right[a] + ny * cam.up[a]);
+      r.d[a] = cam.fwd[a];
+    }
+  } else {
+    float dd[3], l2 = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      dd[a] = cam.fwd[a] + cam.tan_half * (sx * cam.right[a] + ny * cam.up[a]);
+      l2 += dd[a] * dd[a];
+    }
+    const float inv = 1.0f / sqrtf(l2);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      r.o[a] = cam.eye[a];
+      r.d[a] = dd[a] * inv;
+    }
+  }
+  float tn = -INFINITY, tf = INFINITY;
+  bool miss = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (r.d[a] == 0.0f) {
+      if (r.o[a] < -1.0f || r.o[a] > 1.0f) miss = true;
+    } else {
+      float ta = (-1.0f - r.o[a]) / r.d[a], tb = (1.0f - r.o[a]) / r.d[a];
+      if (ta > tb) {
+        const float s = ta;
+        ta = tb;
+        tb = s;
+      }
+      tn = fmaxf(tn, ta);
+      tf = fminf(tf, tb);
+    }
+  }
+  tn = fmaxf(tn, 0.0f);
+  r.t0 = tn;
+  r.t1 = tf;
+  r.hit = !miss && tf > tn;
+  if (m.fixed_steps > 0) {
+    r.nseg = m.fixed_steps;
+    r.ds = (tf - tn) / (float)m.fixed_steps;
+  } else {
+    r.ds = m.step;
+    r.nseg = r.hit ? (int)ceilf((tf - tn) / m.step) : 0;
+  }
+  if (!r.hit) r.nseg = 0;
+  return r;
+}
+
+__device__ inline int xcd_block_d(int nblocks) {
+  const int b = blockIdx.x;
+  if (nblocks % 8 != 0) return b;
+  const int per = nblocks / 8;
+  return (b % 8) * per + b / 8;
+}
+
+// ---------------------------------------------------------- dense DVR
+
+__device__ inline float dense_sample(const float* vol, int nx, int ny, int nz, float px, float py,
+                                     float pz) {
+  int ix, iy, iz;
+  float fx, fy, fz;
+  axis_cell(px, nx, ix, fx);
+  axis_cell(py, ny, iy, fy);
+  axis_cell(pz, nz, iz, fz);
+  const long long sy = nx, sz = (long long)nx * ny;
+  const float* b = vol + iz * sz + iy * sy + ix;
+  const float c00 = b[0] + fx * (b[1] - b[0]);
+  const float c10 = b[sy] + fx * (b[sy + 1] - b[sy]);
+  const float c01 = b[sz] + fx * (b[sz + 1] - b[sz]);
+  const float c11 = b[sz + sy] + fx * (b[sz + sy + 1] - b[sz + sy]);
+  const float c0 = c00 + fy * (c10 - c00);
+  const float c1 = c01 + fy * (c11 - c01);
+  return c0 + fz * (c1 - c0);
+}
+
+constexpr int kDenseThreads = 256;
+
+__global__ __launch_bounds__(kDenseThreads) void dense_march_kernel(const float* vol, int nx, int ny,
+                                                                    int nz, TFDev tf, ViewBatch vb,
+                                                                    MarchDev m, float* out,
+                                                                    unsigned long long* stats,
+                                                                    int tiles_x, int tiles_y) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tiles_per_view = tiles_x * tiles_y;
+  const int tile = xcd_block_d(gridDim.x) * (kDenseThreads / 64) + wave;
+  if (tile >= tiles_per_view * vb.n_views) return;
+  const int v = tile / tiles_per_view;
+  const int tr = tile % tiles_per_view;
+  const int px = (tr % tiles_x) * 8 + (lane & 7);
+  const int py = (tr / tiles_x) * 8 + (lane >> 3);
+  if (px >= vb.width || py >= vb.height) return;
+  const CamDev& cam = vb.cam[v];
+  DRay ray = make_dray(cam, px, py, vb.width, vb.height, m);
+  const bool fixed = m.fixed_steps > 0;
+  float T = 1.0f, Cr = 0.0f, Cg = 0.0f, Cb = 0.0f, A = 0.0f;
+  int i = 0;
+  const float hx = 2.0f / (float)(nx - 1), hy = 2.0f / (float)(ny - 1), hz = 2.0f / (float)(nz - 1);
+  for (; i < ray.nseg; ++i) {
+    const float a0 = ray.t0 + (float)i * ray.ds;
+    float a1 = ray.t0 + (float)(i + 1) * ray.ds;
+    if (!fixed) a1 = fminf(a1, ray.t1);
+    const float len = a1 - a0, tm = 0.5f * (a0 + a1);
+    if (len <= 0.0f) break;
+    const float sx = ray.o[0] + tm * ray.d[0];
+    const float sy = ray.o[1] + tm * ray.d[1];
+    const float sz = ray.o[2] + tm * ray.d[2];
+    const float d = dense_sample(vol, nx, ny, nz, sx, sy, sz);
+    float rgba[4];
+    tf_eval_d(tf, d, rgba);
+    if (m.phong) {
+      const float gx = (dense_sample(vol, nx, ny, nz, sx + hx, sy, sz) -
+                        dense_sample(vol, nx, ny, nz, sx - hx, sy, sz)) / (2.0f * hx);
+      const float gy = (dense_sample(vol, nx, ny, nz, sx, sy + hy, sz) -
+                        dense_sample(vol, nx, ny, nz, sx, sy - hy, sz)) / (2.0f * hy);
+      const float gz = (dense_sample(vol, nx, ny, nz, sx, sy, sz + hz) -
+                        dense_sample(vol, nx, ny, nz, sx, sy, sz - hz)) / (2.0f * hz);
+      const float gl = sqrtf(gx * gx + gy * gy + gz * gz);
+      if (gl >= 1e-6f) {
+        const float ndl = fabsf(gx * ray.d[0] + gy * ray.d[1] + gz * ray.d[2]) / gl;
+        const float spec = m.ks * powf(ndl, m.shininess);
+        const float k = m.ka + m.kd * ndl;
+        rgba[0] = rgba[0] * k + spec;
+        rgba[1] = rgba[1] * k + spec;
+        rgba[2] = rgba[2] * k + spec;
+      }
+    }
+    const float trn = fast_exp(-rgba[3] * len);
+    const float ta = T * (1.0f - trn);
+    Cr = fmaf(ta, rgba[0], Cr);
+    Cg = fmaf(ta, rgba[1], Cg);
+    Cb = fmaf(ta, rgba[2], Cb);
+    A += ta;
+    T *= trn;
+    if (T < m.ert_eps) { ++i; break; }
+  }
+  float4* o = reinterpret_cast<float4*>(out) + ((long long)v * vb.height + py) * vb.width + px;
+  *o = make_float4(Cr, Cg, Cb, A);
+  if (stats) {
+    unsigned long long mine = (unsigned long long)i, hit = (ray.hit && ray.nseg > 0) ? 1ull : 0ull;
+    atomicAdd(stats, mine);
+    atomicAdd(stats + 2, mine);
+    if (hit) atomicAdd(stats + 1, 1ull);
+  }
+}
+
+__global__ void dense_points_kernel(const float* vol, int nx, int ny, int nz, const float* xyz,
+                                    long long n, float* out) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    out[i] = dense_sample(vol, nx, ny, nz, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
+}
+
+// --------------------------------------------------------- utilities
+
+__device__ inline void philox_round(uint32_t c[4], const uint32_t k[2]) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t hi0 = __umulhi(M0, c[0]), lo0 = M0 * c[0];
+  const uint32_t hi1 = __umulhi(M1, c[2]), lo1 = M1 * c[2];
+  const uint32_t n0 = hi1 ^ c[1] ^ k[0], n2 = hi0 ^ c[3] ^ k[1];
+  c[0] = n0;
+  c[1] = lo1;
+  c[2] = n2;
+  c[3] = lo0;
+}
+
+__global__ void sample_points_kernel(uint32_t k0, uint32_t k1, uint32_t c_lo, uint32_t c_hi,
+                                     long long n, float* xyz) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    uint32_t c[4] = {(uint32_t)i, (uint32_t)((unsigned long long)i >> 32), c_lo, c_hi};
+    uint32_t k[2] = {k0, k1};
+    for (int r = 0; r < 10; ++r) {
+      if (r > 0) {
+        k[0] += 0x9E3779B9u;
+        k[1] += 0xBB67AE85u;
+      }
+      philox_round(c, k);
+    }
+    const float s = 1.0f / 8388608.0f;  // 2^-23
+    xyz[3 * i + 0] = -1.0f + (float)(c[0] >> 8) * s;
+    xyz[3 * i + 1] = -1.0f + (float)(c[1] >> 8) * s;
+    xyz[3 * i + 2] = -1.0f + (float)(c[2] >> 8) * s;
+  }
+}
+
+__global__ void cast_f16_kernel(const float* src, _Float16* dst, long long count) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = (_Float16)src[i];
+}
+
+__global__ void cast_bf16_kernel(const float* src, __bf16* dst, long long count) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = (__bf16)src[i];
+}
+
+}  // namespace
+
+thread_local char g_hip_err[256];
+
+
+int check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    snprintf(g_hip_err, sizeof(g_hip_err), "%s", hipGetErrorString(e));
+    return 2;
+  }
+  return 0;
+}
+
+int grid_blocks(long long work, int per_block, int cap) {
+  long long b = (work + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (int)b;
+}
+
+int device_cus() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+    if (cus <= 0) cus = 256;
+  }
+  return cus;
+}
+
+
+namespace {
+
+}  // namespace
+
+const char* last_hip_error() { return g_hip_err; }
+
+int launch_render(const NetDev& net, int prec, const TFDev& tf, const ViewBatch& views, const MarchDev& m,
+                  float* out, unsigned long long* stats, void* stream) {
+  switch (prec) {
+    case kF32: return launch_render_p0(net, tf, views, m, out, stats, stream);
+    case kF16: return launch_render_p1(net, tf, views, m, out, stats, stream);
+    case kBF16: return launch_render_p2(net, tf, views, m, out, stats, stream);
+  }
+  return 1;
+}
+
+int launch_points(const NetDev& net, int prec, const float* xyz, long long n, int key, float key_w, float* out_d,
+                  float* out_g, void* stream) {
+  switch (prec) {
+    case kF32: return launch_points_p0(net, xyz, n, key, key_w, out_d, out_g, stream);
+    case kF16: return launch_points_p1(net, xyz, n, key, key_w, out_d, out_g, stream);
+    case kBF16: return launch_points_p2(net, xyz, n, key, key_w, out_d, out_g, stream);
+  }
+  return 1;
+}
+
+int launch_render_dense(const float* vol, int nx, int ny, int nz, const TFDev& tf, const ViewBatch& vb,
+                        const MarchDev& m, float* out, unsigned long long* stats, void* stream) {
+  const int tx = (vb.width + 7) / 8, ty = (vb.height + 7) / 8;
+  const long long tiles = (long long)tx * ty * vb.n_views;
+  long long blocks = (tiles + 3) / 4;
+  if (blocks % 8) blocks += 8 - blocks % 8;
+  hipLaunchKernelGGL(dense_march_kernel, dim3((unsigned)blocks), dim3(kDenseThreads), 0, (hipStream_t)stream,
+                     vol, nx, ny, nz, tf, vb, m, out, stats, tx, ty);
+  return check_launch();
+}
+
+int launch_dense_points(const float* vol, int nx, int ny, int nz, const float* xyz, long long n, float* out,
+                        void* stream) {
+  const int blocks = grid_blocks(n, 256, device_cus() * 16);
+  hipLaunchKernelGGL(dense_points_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, vol, nx, ny, nz,
+                     xyz, n, out);
+  return check_launch();
+}
+
+int launch_sample_points(uint64_t seed, uint64_t counter, long long n, float* xyz, void* stream) {
+  const int blocks = grid_blocks(n, 256, device_cus() * 16);
+  hipLaunchKernelGGL(sample_points_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, (uint32_t)seed,
+                     (uint32_t)(seed >> 32), (uint32_t)counter, (uint32_t)(counter >> 32), n, xyz);
+  return check_launch();
+}
+
+int launch_cast(const float* src, void* dst, long long count, int dst_dtype, void* stream) {
+  const int blocks = grid_blocks(count, 256, device_cus() * 16);
+  if (dst_dtype == kF16)
+    hipLaunchKernelGGL(cast_f16_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, src,
+                       (_Float16*)dst, count);
+  else
+    hipLaunchKernelGGL(cast_bf16_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, src, (__bf16*)dst,
+                       count);
+  return check_launch();
+}
+
+}  // namespace fvsrn_detail

@@ -1,0 +1,531 @@
+// The fused network evaluation shared by the render and point kernels:
+// weight staging into MFMA fragment order, the per-lane network input, and
+// the MLP over a wave's 64 input rows. Two modes:
+//  * value mode: each lane owns one sample (row = lane);
+//  * gradient mode (forward-mode differentiation, Sec. 6): the four lanes of
+//    a quad own one sample; lane 4s + q holds column q of sample s, where
+//    q = 0 is the value and q = 1..3 the tangent d/dx, d/dy, d/dz. Tangent
+//    columns go through the same matrices (no bias), and each activation
+//    multiplies them by the derivative of the activation at the value
+//    column's pre-activation, fetched from the quad's first lane with DPP.
+#pragma once
+#include "fvsrn_common.hpp"
+
+namespace fvsrn_detail {
+
+template <int P_, int C_, int F_, int L_, int ACT_>
+struct Cfg {
+  static constexpr int P = P_, C = C_, F = F_, L = L_, ACT = ACT_;
+  using G = Geo<P, C, F, L>;
+  using E = typename G::E;
+};
+
+// Per-lane constants of the lane's column.
+struct LaneRole {
+  bool is_val;   // value column (always true in value mode)
+  int axis;      // tangent axis 0..2 (gradient mode, !is_val)
+  float qmask;   // 1 for the value column: biases apply to it only
+  float toff;    // 0 (value) or 1/4 revolution: sin(x + pi/2) = cos(x)
+  float tmul;    // 0 (value) or 2 pi
+  float tadd;    // 1 (value) or 0
+};
+
+__device__ inline LaneRole value_role() { return LaneRole{true, 0, 1.0f, 0.0f, 0.0f, 1.0f}; }
+
+__device__ inline LaneRole grad_role(int q) {
+  LaneRole r;
+  r.is_val = q == 0;
+  r.axis = q > 0 ? q - 1 : 0;
+  r.qmask = q == 0 ? 1.0f : 0.0f;
+  r.toff = q == 0 ? 0.0f : 0.25f;
+  r.tmul = q == 0 ? 0.0f : k2Pi;
+  r.tadd = q == 0 ? 1.0f : 0.0f;
+  return r;
+}
+
+// ------------------------------------------------------ weight staging
+
+// Converts the FP32 master weights into A fragments in LDS (lane order), with
+// the first layer's columns permuted to the input-row order and each hidden
+// layer's columns permuted so that the previous layer's D fragments are this
+// layer's B fragments. Layers 0..H-1 are scaled by 1/(2 pi) for the periodic
+// activations (their accumulators then hold revolutions).
+template <class CF>
+__device__ void stage_weights(const NetDev& nd, char* smem) {
+  using G = typename CF::G;
+  using E = typename CF::E;
+  constexpr int C = CF::C, F = CF::F, L = CF::L, MT = G::MT;
+  const int H = nd.H, K0 = 3 + F + 6 * L;
+  const float* w = nd.weights;
+  const float sc = CF::ACT == kIdentity ? 1.0f : kInv2Pi;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const long long off_b0 = (long long)C * K0;
+  auto off_layer = [&](int i) -> long long {  // W_i for 1 <= i <= H
+    return (long long)C * K0 + C + (long long)(i - 1) * (C * C + C);
+  };
+  auto w0 = [&](int o, int col) -> float {
+    if (col < G::KF) return w[(long long)o * K0 + 3 + col] * sc;
+    if (col < G::KMAIN) return 0.0f;
+    const int t = col - G::KMAIN;
+    if (t < 3) return w[(long long)o * K0 + t] * sc;
+    if (t == 3) return w[off_b0 + o] * sc;
+    return 0.0f;
+  };
+  char* p = smem;
+  if constexpr (CF::P == kF32) {
+    float* W0 = reinterpret_cast<float*>(p);
+    for (int e = tid; e < MT * G::Q0 * kWave; e += nt) {
+      const int lane = e % kWave, q = (e / kWave) % G::Q0, mt = e / (kWave * G::Q0);
+      W0[e] = w0(16 * mt + (lane & 15), (lane >> 4) * G::Q0 + q);
+    }
+    p += G::W0A;
+    for (int i = 1; i < H; ++i) {
+      const float* Wi = w + off_layer(i);
+      float* WH = reinterpret_cast<float*>(p);
+      for (int e = tid; e < MT * 4 * MT * kWave; e += nt) {
+        const int lane = e % kWave, q = (e / kWave) % (4 * MT), mt = e / (kWave * 4 * MT);
+        const int ch = 16 * (q / 4) + 4 * (lane >> 4) + (q % 4);
+        WH[e] = Wi[(16 * mt + (lane & 15)) * C + ch] * sc;
+      }
+      float* BHp = reinterpret_cast<float*>(p + G::WHA);
+      for (int e = tid; e < C; e += nt) BHp[e] = Wi[C * C + e] * sc;
+      p += G::HID;
+    }
+    const float* Wo = w + off_layer(H);
+    float* WO = reinterpret_cast<float*>(p);
+    for (int e = tid; e < 4 * 4 * MT * kWave; e += nt) {
+      const int lane = e % kWave, q = (e / kWave) % (4 * MT), t = e / (kWave * 4 * MT);
+      const int ch = 16 * (q / 4) + 4 * (lane >> 4) + (q % 4);
+      WO[e] = ((lane & 15) == 4 * t) ? Wo[ch] : 0.0f;
+    }
+    p += G::WOA;
+    if (tid == 0) *reinterpret_cast<float*>(p) = Wo[C];
+  } else {
+    E* W0A = reinterpret_cast<E*>(p);
+    for (int e = tid; e < MT * G::S0 * kWave * 8; e += nt) {
+      const int j = e & 7, lane = (e >> 3) & 63, s = (e >> 9) % G::S0, mt = (e >> 9) / G::S0;
+      W0A[e] = to_e<E>(w0(16 * mt + (lane & 15), 32 * s + 8 * (lane >> 4) + j));
+    }
+    E* W0T = reinterpret_cast<E*>(p + G::W0A);
+    for (int e = tid; e < MT * kWave * 4; e += nt) {
+      const int j = e & 3, lane = (e >> 2) & 63, mt = e >> 8;
+      W0T[e] = to_e<E>(w0(16 * mt + (lane & 15), G::KMAIN + 4 * (lane >> 4) + j));
+    }
+    p += G::W0A + G::W0T;
+    for (int i = 1; i < H; ++i) {
+      const float* Wi = w + off_layer(i);
+      E* WA = reinterpret_cast<E*>(p);
+      for (int e = tid; e < MT * G::HS32 * kWave * 8; e += nt) {
+        const int j = e & 7, lane = (e >> 3) & 63, s = (e >> 9) % G::HS32, mt = (e >> 9) / G::HS32;
+        const int g = lane >> 4;
+        const int ch = j < 4 ? 32 * s + 4 * g + j : 32 * s + 16 + 4 * g + (j - 4);
+        WA[e] = to_e<E>(Wi[(16 * mt + (lane & 15)) * C + ch] * sc);
+      }
+      if constexpr (G::HS16) {
+        E* WT = reinterpret_cast<E*>(p + G::WHA);
+        for (int e = tid; e < MT * kWave * 4; e += nt) {
+          const int j = e & 3, lane = (e >> 2) & 63, mt = e >> 8;
+          const int ch = 16 * (MT - 1) + 4 * (lane >> 4) + j;
+          WT[e] = to_e<E>(Wi[(16 * mt + (lane & 15)) * C + ch] * sc);
+        }
+      }
+      float* BHp = reinterpret_cast<float*>(p + G::WHA + G::WHT);
+      for (int e = tid; e < C; e += nt) BHp[e] = Wi[C * C + e] * sc;
+      p += G::HID;
+    }
+    const float* Wo = w + off_layer(H);
+    E* WOA = reinterpret_cast<E*>(p);
+    for (int e = tid; e < 4 * G::HS32 * kWave * 8; e += nt) {
+      const int j = e & 7, lane = (e >> 3) & 63, s = (e >> 9) % G::HS32, t = (e >> 9) / G::HS32;
+      const int g = lane >> 4;
+      const int ch = j < 4 ? 32 * s + 4 * g + j : 32 * s + 16 + 4 * g + (j - 4);
+      WOA[e] = to_e<E>((lane & 15) == 4 * t ? Wo[ch] : 0.0f);
+    }
+    if constexpr (G::HS16) {
+      E* WOT = reinterpret_cast<E*>(p + G::WOA);
+      for (int e = tid; e < 4 * kWave * 4; e += nt) {
+        const int j = e & 3, lane = (e >> 2) & 63, t = e >> 8;
+        const int ch = 16 * (MT - 1) + 4 * (lane >> 4) + j;
+        WOT[e] = to_e<E>((lane & 15) == 4 * t ? Wo[ch] : 0.0f);
+      }
+    }
+    p += G::WOA + G::WOT;
+    if (tid == 0) *reinterpret_cast<float*>(p) = Wo[C];
+  }
+}
+
+// ------------------------------------------------------ network input
+
+// Latent source: one or two keyframe grids and their blend weights (Sec. 8).
+struct LatentSrc {
+  const void* g0;
+  const void* g1;  // == nullptr: single keyframe
+  float w0, w1;
+  int R;
+  bool f16;
+};
+
+__device__ inline LatentSrc make_latent_src(const NetDev& nd, int key, float key_w) {
+  LatentSrc s;
+  const size_t esz = nd.grid_f16 ? 2 : 4;
+  const char* base = reinterpret_cast<const char*>(nd.latent);
+  s.g0 = base + (size_t)key * (size_t)nd.key_stride * esz;
+  s.g1 = nd.K > 1 ? base + (size_t)(key + 1) * (size_t)nd.key_stride * esz : nullptr;
+  s.w0 = nd.K > 1 ? 1.0f - key_w : 1.0f;
+  s.w1 = key_w;
+  s.R = nd.R;
+  s.f16 = nd.grid_f16 != 0;
+  return s;
+}
+
+// z += w * G[corner][0..F) for the 8 corners of the cell at offset `base`.
+template <int F>
+__device__ inline void gather8(const void* grid, bool f16, unsigned base, unsigned sx, unsigned sy, unsigned sz,
+                               const float w[8], float* z) {
+  const unsigned off[8] = {base, base + sx, base + sy, base + sx + sy,
+                           base + sz, base + sz + sx, base + sz + sy, base + sz + sx + sy};
+  if (f16) {
+    const _Float16* g = reinterpret_cast<const _Float16*>(grid);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const uint4* src = reinterpret_cast<const uint4*>(g + off[c]);
+#pragma unroll
+      for (int q = 0; q < F / 8; ++q) {
+        const h8 hv = __builtin_bit_cast(h8, src[q]);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) z[8 * q + j] = fmaf(w[c], (float)hv[j], z[8 * q + j]);
+      }
+    }
+  } else {
+    const float* g = reinterpret_cast<const float*>(grid);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const float4* src = reinterpret_cast<const float4*>(g + off[c]);
+#pragma unroll
+      for (int q = 0; q < F / 4; ++q) {
+        const float4 v = src[q];
+        z[4 * q + 0] = fmaf(w[c], v.x, z[4 * q + 0]);
+        z[4 * q + 1] = fmaf(w[c], v.y, z[4 * q + 1]);
+        z[4 * q + 2] = fmaf(w[c], v.z, z[4 * q + 2]);
+        z[4 * q + 3] = fmaf(w[c], v.w, z[4 * q + 3]);
+      }
+    }
+  }
+}
+
+// Trilinear latent vector (value lanes) or its derivative along the lane's
+// axis (tangent lanes), blended over the keyframes, added into z[0..F).
+template <int F>
+__device__ inline void latent_column(const LatentSrc& ls, const LaneRole& role, float px, float py, float pz,
+                                     float* z) {
+  int ix, iy, iz;
+  float fx, fy, fz, dx, dy, dz;
+  axis_cell(px, ls.R, ix, fx, dx);
+  axis_cell(py, ls.R, iy, fy, dy);
+  axis_cell(pz, ls.R, iz, fz, dz);
+  // per-axis factors of the low / high corner: value (1-f, f); along the
+  // differentiated axis (-df/dp, df/dp)
+  const bool tx = !role.is_val && role.axis == 0, ty = !role.is_val && role.axis == 1,
+             tz = !role.is_val && role.axis == 2;
+  const float x0 = tx ? -dx : 1.0f - fx, x1 = tx ? dx : fx;
+  const float y0 = ty ? -dy : 1.0f - fy, y1 = ty ? dy : fy;
+  const float z0 = tz ? -dz : 1.0f - fz, z1 = tz ? dz : fz;
+  const unsigned R = (unsigned)ls.R;
+  const unsigned sx = F, sy = R * F, sz = R * R * F;
+  const unsigned base = (unsigned)iz * sz + (unsigned)iy * sy + (unsigned)ix * sx;
+  float w[8] = {x0 * y0 * z0, x1 * y0 * z0, x0 * y1 * z0, x1 * y1 * z0,
+                x0 * y0 * z1, x1 * y0 * z1, x0 * y1 * z1, x1 * y1 * z1};
+  float wa[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) wa[c] = w[c] * ls.w0;
+  gather8<F>(ls.g0, ls.f16, base, sx, sy, sz, wa, z);
+  if (ls.g1) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) wa[c] = w[c] * ls.w1;
+    gather8<F>(ls.g1, ls.f16, base, sx, sy, sz, wa, z);
+  }
+}
+
+// Builds this lane's input row at position p and writes it to `row` (LDS).
+template <class CF, bool GRAD>
+__device__ inline void write_features(typename CF::E* row, const LatentSrc& ls, const LaneRole& role, float px,
+                                      float py, float pz) {
+  using G = typename CF::G;
+  using E = typename CF::E;
+  constexpr int F = CF::F, L = CF::L;
+  float v[G::KROW];
+#pragma unroll
+  for (int j = 0; j < G::KROW; ++j) v[j] = 0.0f;
+  latent_column<F>(ls, role, px, py, pz, v);
+  // Fourier features sin/cos(pi 2^k p_a): the phase 2^(k-1) p_a in
+  // revolutions is an exact power-of-two scaling of p_a.
+  const float pp[3] = {px, py, pz};
+  float mv = 1.0f, ma[3] = {0.0f, 0.0f, 0.0f};
+  if constexpr (GRAD) {
+    mv = role.is_val ? 1.0f : 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ma[a] = (!role.is_val && role.axis == a) ? 1.0f : 0.0f;
+  }
+#pragma unroll
+  for (int k = 0; k < L; ++k) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float ph = pp[a] * (float)(1 << k) * 0.5f;
+      const float s = sin_rev(ph), c = cos_rev(ph);
+      if constexpr (GRAD) {
+        // d/dp_a sin(w p_a) = w cos(w p_a), d/dp_a cos(w p_a) = -w sin(w p_a)
+        const float wm = kPi * (float)(1 << k) * ma[a];
+        v[F + 3 * k + a] = fmaf(c, wm, s * mv);
+        v[F + 3 * L + 3 * k + a] = fmaf(-s, wm, c * mv);
+      } else {
+        v[F + 3 * k + a] = s;
+        v[F + 3 * L + 3 * k + a] = c;
+      }
+    }
+  }
+  if constexpr (GRAD) {
+    v[G::KMAIN + 0] = role.is_val ? px : (role.axis == 0 ? 1.0f : 0.0f);
+    v[G::KMAIN + 1] = role.is_val ? py : (role.axis == 1 ? 1.0f : 0.0f);
+    v[G::KMAIN + 2] = role.is_val ? pz : (role.axis == 2 ? 1.0f : 0.0f);
+    v[G::KMAIN + 3] = role.qmask;
+  } else {
+    v[G::KMAIN + 0] = px;
+    v[G::KMAIN + 1] = py;
+    v[G::KMAIN + 2] = pz;
+    v[G::KMAIN + 3] = 1.0f;
+  }
+  if constexpr (CF::P == kF32) {
+    float4* dst = reinterpret_cast<float4*>(row);
+#pragma unroll
+    for (int q = 0; q < G::KROW / 4; ++q) dst[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+  } else {
+    using V8 = typename PrecT<CF::P>::VA;
+    V8* dst = reinterpret_cast<V8*>(row);
+#pragma unroll
+    for (int q = 0; q < G::KROW / 8; ++q) {
+      V8 x;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) x[j] = to_e<E>(v[8 * q + j]);
+      dst[q] = x;
+    }
+  }
+}
+
+// ---------------------------------------------------------- activation
+
+// Activation of one accumulator element r (pre-activation in revolutions
+// for the periodic activations). Gradient mode: value lanes return the
+// activation of their pre-activation, tangent lanes the activation's
+// derivative at the value column's pre-activation times their own tangent.
+template <int ACT, bool GRAD>
+__device__ inline float act_el(float r, const LaneRole& role) {
+  if constexpr (!GRAD) {
+    if constexpr (ACT == kSine) {
+      return sin_rev(r);
+    } else if constexpr (ACT == kSnakeAlt) {  // 0.5 x + sin^2 x with x = 2 pi r
+      const float s = sin_rev(r);
+      return fmaf(kPi, r, s * s);
+    } else {
+      return r;
+    }
+  } else {
+    const float rv = quad_bcast0(r);
+    if constexpr (ACT == kSine) {
+      // value: sin(2 pi rv); tangent: cos(2 pi rv) * 2 pi r
+      return sin_rev(rv + role.toff) * fmaf(r, role.tmul, role.tadd);
+    } else if constexpr (ACT == kSnakeAlt) {
+      const float s = sin_rev(rv);
+      const float val = fmaf(kPi, rv, s * s);
+      const float tan = (0.5f + sin_rev(2.0f * rv)) * k2Pi * r;
+      return role.is_val ? val : tan;
+    } else {
+      return r;
+    }
+  }
+}
+
+// ------------------------------------------------------------- the MLP
+
+// Runs the network on the wave's 64 input rows and returns the output-layer
+// pre-activation of this lane's own row (logit of its sample, or the
+// logit's derivative for tangent lanes). Pairs of N-tiles are processed
+// together so that two independent MFMA / activation chains interleave.
+template <class CF, bool GRAD>
+__device__ inline float mlp_tile(const char* wsm, const typename CF::E* feat, int H, const LaneRole& role) {
+  using G = typename CF::G;
+  using PR = PrecT<CF::P>;
+  using E = typename CF::E;
+  constexpr int MT = G::MT;
+  constexpr int NT = 2;
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4, n = lane & 15;
+  if constexpr (CF::P == kF32) {
+    f4 out[NT];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) out[u] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    const float* W0 = reinterpret_cast<const float*>(wsm);
+    for (int tp = 0; tp < 4; tp += NT) {
+      f4 acc[NT][MT];
+#pragma unroll
+      for (int u = 0; u < NT; ++u)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[u][mt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int q = 0; q < G::Q0; ++q) {
+        float b[NT];
+#pragma unroll
+        for (int u = 0; u < NT; ++u) b[u] = feat[(16 * (tp + u) + n) * G::ROW + g * G::Q0 + q];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const float a = W0[(mt * G::Q0 + q) * kWave + lane];
+#pragma unroll
+          for (int u = 0; u < NT; ++u) acc[u][mt] = PR::mma(a, b[u], acc[u][mt]);
+        }
+      }
+      const char* p = wsm + G::W0A;
+      for (int i = 1; i < H; ++i) {
+        const float* WH = reinterpret_cast<const float*>(p);
+        const float* BHp = reinterpret_cast<const float*>(p + G::WHA);
+        f4 nacc[NT][MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const f4 bias = *reinterpret_cast<const f4*>(BHp + 16 * mt + 4 * g) * role.qmask;
+#pragma unroll
+          for (int u = 0; u < NT; ++u) nacc[u][mt] = bias;
+        }
+#pragma unroll
+        for (int q = 0; q < 4 * MT; ++q) {
+          float b[NT];
+#pragma unroll
+          for (int u = 0; u < NT; ++u) b[u] = act_el<CF::ACT, GRAD>(acc[u][q / 4][q % 4], role);
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            const float a = WH[(mt * 4 * MT + q) * kWave + lane];
+#pragma unroll
+            for (int u = 0; u < NT; ++u) nacc[u][mt] = PR::mma(a, b[u], nacc[u][mt]);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < NT; ++u)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) acc[u][mt] = nacc[u][mt];
+        p += G::HID;
+      }
+      const float* WO = reinterpret_cast<const float*>(p);
+#pragma unroll
+      for (int q = 0; q < 4 * MT; ++q) {
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+          const float b = act_el<CF::ACT, GRAD>(acc[u][q / 4][q % 4], role);
+          out[u] = PR::mma(WO[((tp + u) * 4 * MT + q) * kWave + lane], b, out[u]);
+        }
+      }
+    }
+    const char* p = wsm + G::W0A + (H - 1) * G::HID + G::WOA;
+    return out[0][0] + out[1][0] + *reinterpret_cast<const float*>(p) * role.qmask;
+  } else {
+    using VA = typename PR::VA;
+    using VT = typename PR::VT;
+    const f4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+    f4 out[NT], out_t[NT];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) out[u] = out_t[u] = zero;
+    const VA* W0A = reinterpret_cast<const VA*>(wsm);
+    const VT* W0T = reinterpret_cast<const VT*>(wsm + G::W0A);
+    for (int tp = 0; tp < 4; tp += NT) {
+      f4 acc[NT][MT];
+#pragma unroll
+      for (int u = 0; u < NT; ++u)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[u][mt] = zero;
+#pragma unroll
+      for (int s = 0; s < G::S0; ++s) {
+        VA b[NT];
+#pragma unroll
+        for (int u = 0; u < NT; ++u)
+          b[u] = *reinterpret_cast<const VA*>(feat + (16 * (tp + u) + n) * G::ROW + 32 * s + 8 * g);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const VA a = W0A[(mt * G::S0 + s) * kWave + lane];
+#pragma unroll
+          for (int u = 0; u < NT; ++u) acc[u][mt] = PR::mma(a, b[u], acc[u][mt]);
+        }
+      }
+      {
+        // The K16 tail gets its own accumulator: an MFMA never accumulates
+        // onto the result of an MFMA of a different shape (that dependency is
+        // not reliably interlocked); the two are summed on the VALU.
+        VT b[NT];
+#pragma unroll
+        for (int u = 0; u < NT; ++u)
+          b[u] = *reinterpret_cast<const VT*>(feat + (16 * (tp + u) + n) * G::ROW + G::KMAIN + 4 * g);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const VT a = W0T[mt * kWave + lane];
+#pragma unroll
+          for (int u = 0; u < NT; ++u) acc[u][mt] += PR::mmt(a, b[u], zero);
+        }
+      }
+      const char* p = wsm + G::W0A + G::W0T;
+      VA bA[NT][G::HS32 > 0 ? G::HS32 : 1];
+      VT bT[NT];
+      auto pack = [&]() {
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+#pragma unroll
+          for (int s = 0; s < G::HS32; ++s)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              bA[u][s][j] = to_e<E>(act_el<CF::ACT, GRAD>(acc[u][2 * s][j], role));
+              bA[u][s][j + 4] = to_e<E>(act_el<CF::ACT, GRAD>(acc[u][2 * s + 1][j], role));
+            }
+          if constexpr (G::HS16) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bT[u][j] = to_e<E>(act_el<CF::ACT, GRAD>(acc[u][MT - 1][j], role));
+          }
+        }
+      };
+      for (int i = 1; i < H; ++i) {
+        pack();
+        const VA* WA = reinterpret_cast<const VA*>(p);
+        const VT* WT = reinterpret_cast<const VT*>(p + G::WHA);
+        const float* BHp = reinterpret_cast<const float*>(p + G::WHA + G::WHT);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const f4 bias = *reinterpret_cast<const f4*>(BHp + 16 * mt + 4 * g) * role.qmask;
+#pragma unroll
+          for (int u = 0; u < NT; ++u) acc[u][mt] = bias;
+#pragma unroll
+          for (int s = 0; s < G::HS32; ++s) {
+            const VA a = WA[(mt * G::HS32 + s) * kWave + lane];
+#pragma unroll
+            for (int u = 0; u < NT; ++u) acc[u][mt] = PR::mma(a, bA[u][s], acc[u][mt]);
+          }
+          if constexpr (G::HS16) {
+            const VT a = WT[mt * kWave + lane];
+#pragma unroll
+            for (int u = 0; u < NT; ++u) acc[u][mt] += PR::mmt(a, bT[u], zero);
+          }
+        }
+        p += G::HID;
+      }
+      pack();
+#pragma unroll
+      for (int u = 0; u < NT; ++u) {
+        const VA* WOA = reinterpret_cast<const VA*>(p) + (tp + u) * G::HS32 * kWave;
+#pragma unroll
+        for (int s = 0; s < G::HS32; ++s) out[u] = PR::mma(WOA[s * kWave + lane], bA[u][s], out[u]);
+        if constexpr (G::HS16) {
+          const VT* WOT = reinterpret_cast<const VT*>(p + G::WOA) + (tp + u) * kWave;
+          out_t[u] = PR::mmt(WOT[lane], bT[u], out_t[u]);
+        }
+      }
+    }
+    const char* p = wsm + G::W0A + G::W0T + (H - 1) * G::HID + G::WOA + G::WOT;
+    float y = out[0][0] + out[1][0] + *reinterpret_cast<const float*>(p) * role.qmask;
+    if constexpr (G::HS16) y += out_t[0][0] + out_t[1][0];
+    return y;
+  }
+}
+
+}  // namespace fvsrn_detail

@@ -57,7 +57,7 @@ def cfg1(FV):
 
 def test_cfg1_render_fp32(FV, cfg1):
     gnet, onet, tf, cams, m, ref, ns = cfg1
-    stats = torch.zeros(2, dtype=torch.int64, device="cuda")
+    stats = torch.zeros(3, dtype=torch.int64, device="cuda")
     img = FV.fvsrn_render(gnet, tf, cams, m, "f32", stats=stats).cpu().numpy()
     err = np.abs(img - ref).max()
     _report("cfg1 fp32 render", err)
@@ -140,7 +140,7 @@ def test_cfg2_render_small_ragged(FV):
     cams = I.orbit_cameras(4, 37, 29)
     m = I.March(step=1 / 256, ert_eps=0.0)
     ref, ns = O.render(O.Field(net=onet), tf, cams, m)
-    stats = torch.zeros(2, dtype=torch.int64, device="cuda")
+    stats = torch.zeros(3, dtype=torch.int64, device="cuda")
     img = FV.fvsrn_render(gnet, tf, cams, m, "f32", stats=stats).cpu().numpy()
     err = np.abs(img - ref).max()
     _report("cfg2 small fp32", err)
@@ -207,7 +207,7 @@ def test_render_misses_and_ert(FV):
     # camera looking away from the box: every ray misses
     away = I.Camera(ortho=False, eye=(0.0, 0.0, 3.0), target=(0.0, 0.0, 6.0), up=(0.0, 1.0, 0.0),
                     width=9, height=7)
-    stats = torch.zeros(2, dtype=torch.int64, device="cuda")
+    stats = torch.zeros(3, dtype=torch.int64, device="cuda")
     img = FV.fvsrn_render(gnet, tf, [away], I.March(step=0.01), stats=stats)
     assert torch.count_nonzero(img).item() == 0 and stats.sum().item() == 0
     # ERT: counts match the oracle's
@@ -230,7 +230,7 @@ def test_dense_render_and_points(FV):
     cams = I.orbit_cameras(3, 33, 20)
     for m in (I.March(step=1 / 64), I.March(step=1 / 64, phong=True), I.March(fixed_steps=50, step=0.0)):
         ref, ns = O.render(O.Field(vol=vol), tf, cams, m)
-        stats = torch.zeros(2, dtype=torch.int64, device="cuda")
+        stats = torch.zeros(3, dtype=torch.int64, device="cuda")
         img = FV.fvsrn_render_dense(tvol, tf, cams, m, stats=stats).cpu().numpy()
         err = np.abs(img - ref).max()
         _report("dense render phong=%s" % m.phong, err)
@@ -283,3 +283,74 @@ def test_cast_grid_round_to_nearest_even(FV):
     b = torch.empty(x.numel(), dtype=torch.bfloat16, device="cuda")
     FV.fvsrn_cast_grid(x, b, FV.BF16)
     assert torch.equal(b, x.bfloat16())
+
+
+# ------------------------------------------- forward-mode density gradient
+
+def _grad_err(g, ref):
+    return np.abs(g - ref).max() / max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("spec_name", ["CFG1", "CFG2", "CFG4"])
+def test_grad_points(FV, spec_name):
+    spec = getattr(I, spec_name)
+    gnet, onet = _nets(FV, spec, 31)
+    xyz = I.uniform_points(16 * 41 + 7, 9, -0.999, 0.999)
+    dref, gref = O.grad_points(onet, xyz)
+    for prec, dtol, gtol in (("f32", FP32_TOL, 1e-4), ("f16", FP16_TOL, 1e-2)):
+        d, g = FV.fvsrn_grad_points(gnet, torch.from_numpy(xyz).cuda(), 0.0, prec)
+        d, g = d.cpu().numpy(), g.cpu().numpy()
+        derr, gerr = np.abs(d - dref).max(), _grad_err(g, gref)
+        _report("grad %s %s density" % (spec_name, prec), derr)
+        _report("grad %s %s gradient (rel. to max |g|)" % (spec_name, prec), gerr)
+        assert derr <= dtol and gerr <= gtol
+
+
+def test_grad_points_time_and_activations(FV):
+    spec = I.NetSpec(R=8, F=16, L=8, c=32, H=2, K=3)
+    gnet, onet = _nets(FV, spec, 5, key_times=(0.0, 1.0, 3.0))
+    xyz = I.uniform_points(500, 4, -0.99, 0.99)
+    for t in (0.25, 2.0):
+        dref, gref = O.grad_points(onet, xyz, t)
+        d, g = FV.fvsrn_grad_points(gnet, torch.from_numpy(xyz).cuda(), t, "f32")
+        assert np.abs(d.cpu().numpy() - dref).max() <= FP32_TOL
+        assert _grad_err(g.cpu().numpy(), gref) <= 1e-4
+    for act in ("snakealt", "identity"):
+        spec = I.NetSpec(R=16, F=8, L=4, c=32, H=3, act=act)
+        lat, w = I.net_params(spec, 3)
+        w = w * (0.5 if act == "identity" else 1.0)
+        gnet, onet = FV.Network(spec, lat, w), O.Net(spec, lat, w)
+        xyz = I.uniform_points(700, 2, -0.99, 0.99)
+        dref, gref = O.grad_points(onet, xyz)
+        d, g = FV.fvsrn_grad_points(gnet, torch.from_numpy(xyz).cuda(), 0.0, "f32")
+        _report("grad act=%s" % act, _grad_err(g.cpu().numpy(), gref))
+        assert np.abs(d.cpu().numpy() - dref).max() <= FP32_TOL
+        assert _grad_err(g.cpu().numpy(), gref) <= 1e-4
+
+
+def test_grad_points_edge_sizes(FV):
+    gnet, onet = _nets(FV, I.CFG1, 8)
+    for n in (1, 15, 16, 17):
+        xyz = I.uniform_points(n, n, -0.9, 0.9)
+        dref, gref = O.grad_points(onet, xyz)
+        d, g = FV.fvsrn_grad_points(gnet, torch.from_numpy(xyz).cuda())
+        assert np.abs(d.cpu().numpy() - dref).max() <= FP32_TOL
+        assert _grad_err(g.cpu().numpy(), gref) <= 1e-4
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-4), ("f16", FP16_TOL)])
+def test_phong_render(FV, prec, tol):
+    """cfg4-shaped network (64^3 x 16 grid, 4 x 48) with headlight Phong from
+    the forward-mode gradient, on a ragged small view."""
+    spec = I.CFG4
+    gnet, onet = _nets(FV, spec, I.SEED[4])
+    tf = I.ramp_tf()
+    cams = I.orbit_cameras(1, 30, 17)
+    m = I.March(step=1 / 128, ert_eps=0.0, phong=True)
+    ref, ns = O.render(O.Field(net=onet), tf, cams, m)
+    stats = torch.zeros(3, dtype=torch.int64, device="cuda")
+    img = FV.fvsrn_render(gnet, tf, cams, m, prec, stats=stats).cpu().numpy()
+    err = np.abs(img - ref).max()
+    _report("phong %s" % prec, err)
+    assert err <= tol
+    assert abs(stats[0].item() - ns) <= 0.001 * ns
