@@ -1,14 +1,552 @@
-// Training kernels (placeholder until the trainer lands).
-#include "fvsrn_common.hpp"
+// Training step of the fV-SRN (world-space fitting with L1 loss and Adam,
+// Sec. 3 and Sec. 5), FP32 throughout.
+//
+// fwd_bwd_kernel: each wave takes chunks of 64 points (fixed, grid-independent
+// assignment: chunk c goes to wave c mod n_waves). Per chunk:
+//   1. every lane writes its point's input row to LDS (as in evaluation);
+//   2. forward through the layers on 16x16x4 FP32 MFMA, keeping every
+//      pre-activation a_i in LDS (sample-major);
+//   3. output sigmoid, loss and dL/dy;
+//   4. backward: delta_i = (W_{i+1}^T delta_{i+1}) * act'(a_i) on MFMA with
+//      transposed weight fragments; dW_i = delta_i h_i^T as an MFMA GEMM over
+//      the 64 samples (A = delta, B = layer input, both read from LDS);
+//   5. dL/dz = W_0[:, latent]^T delta_0, scattered into the latent gradient
+//      with the trilinear weights (hardware float atomics).
+// dW tiles are added into the wave's private workspace slice (no atomics, so
+// dW is bitwise reproducible). reduce_kernel then sums the slices in a fixed
+// order into the packed gradient; adam_kernel applies the update.
+#include "fvsrn_net.hpp"
 
 namespace fvsrn_detail {
 
-size_t train_workspace_bytes(const NetDev&, long long) { return 0; }
+namespace {
 
-int launch_train(const NetDev&, float*, float*, float*, float*, const float*, long long, const float*, const float*,
-                 int, float, float, float, float, float, int, float*, float*, float*, float*, float*, void*, size_t,
-                 void*) {
-  return 1;
+constexpr int kTrainMaxWaves = 1024;  // fixed number of waves (deterministic partition)
+
+template <int C, int F, int L, int ACT>
+struct TrainCfg {
+  using CF = Cfg<kF32, C, F, L, ACT>;
+  using G = typename CF::G;
+  static constexpr int MT = G::MT;
+  static constexpr int NK0 = (G::KROW + 15) / 16;   // N-tiles of layer 0's input row
+  static constexpr int AS = C + 4;                  // sample-major row stride (floats)
+  static constexpr int ZS = 20;                     // latent-gradient row stride
+  // per-wave LDS (bytes)
+  static constexpr int FEAT = G::FEAT_BYTES;
+  __host__ __device__ static int abuf_bytes(int H) { return H * 64 * AS * 4; }
+  static constexpr int DBUF = 64 * AS * 4;
+  static constexpr int DY = 64 * 4;
+  static constexpr int ZBUF = 64 * ZS * 4;
+  __host__ __device__ static int wave_bytes(int H) { return FEAT + abuf_bytes(H) + DBUF + DY + ZBUF; }
+  // backward weight fragments (block-level, after the forward ones)
+  static constexpr int WB = MT * 4 * MT * 64 * 4;   // one hidden layer's W^T
+  static constexpr int WZ = 4 * MT * 64 * 4;        // latent columns of W_0, transposed
+  __host__ __device__ static int back_bytes(int H) { return (H - 1) * WB + WZ; }
+  __host__ __device__ static int block_bytes(int H, int waves) { return G::weight_bytes(H) + back_bytes(H) + waves * wave_bytes(H); }
+  // workspace slice (floats)
+  __host__ __device__ static int tiles(int H) { return MT * NK0 + (H - 1) * MT * MT + MT + (H - 1) * MT; }
+  __host__ __device__ static int slice(int H) { return tiles(H) * 256 + 128; }
+  __host__ __device__ static int tile_l0(int mo, int nk) { return mo * NK0 + nk; }
+  __host__ __device__ static int tile_h(int H, int i, int mo, int nk) { return MT * NK0 + (i - 1) * MT * MT + mo * MT + nk; }
+  __host__ __device__ static int tile_out(int H, int nk) { return MT * NK0 + (H - 1) * MT * MT + nk; }
+  __host__ __device__ static int tile_bias(int H, int i, int mt) { return MT * NK0 + (H - 1) * MT * MT + MT + (i - 1) * MT + mt; }
+};
+
+template <int ACT>
+__device__ inline float act_d(float a) {  // d act / d x at pre-activation a (revolutions for periodic acts)
+  if constexpr (ACT == kSine) return cos_rev(a);
+  else if constexpr (ACT == kSnakeAlt) return 0.5f + sin_rev(2.0f * a);
+  else return 1.0f;
+}
+
+// Backward weight fragments: W_i^T for i = 1..H-1 and the latent columns of W_0
+// transposed. The forward fragments hold W scaled by 1/(2 pi) for periodic
+// activations; the transposed ones here are unscaled, since the chain rule in
+// x units is delta_h = W^T (delta_a).
+template <class TC, int ACT>
+__device__ void stage_backward(const NetDev& nd, char* p) {
+  constexpr int C = TC::CF::C, F = TC::CF::F, L = TC::CF::L, MT = TC::MT;
+  const int H = nd.H, K0 = 3 + F + 6 * L;
+  const float* w = nd.weights;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int i = 1; i < H; ++i) {
+    const float* Wi = w + (long long)C * K0 + C + (long long)(i - 1) * (C * C + C);
+    float* WB = reinterpret_cast<float*>(p + (i - 1) * TC::WB);
+    for (int e = tid; e < MT * 4 * MT * 64; e += nt) {
+      const int lane = e & 63, q = (e >> 6) % (4 * MT), mk = (e >> 6) / (4 * MT);
+      const int o = 16 * (q / 4) + 4 * (lane >> 4) + (q % 4);
+      WB[e] = Wi[o * C + 16 * mk + (lane & 15)];
+    }
+  }
+  float* WZ = reinterpret_cast<float*>(p + (H - 1) * TC::WB);
+  for (int e = tid; e < 4 * MT * 64; e += nt) {
+    const int lane = e & 63, q = e >> 6, m = lane & 15;
+    const int o = 16 * (q / 4) + 4 * (lane >> 4) + (q % 4);
+    WZ[e] = m < F ? w[(long long)o * K0 + 3 + m] : 0.0f;
+  }
+}
+
+template <int C, int F, int L, int ACT>
+__global__ __launch_bounds__(256) void fwd_bwd_kernel(NetDev nd, const float* xyz, long long n, const float* target,
+                                                      const float* dloss, float* d_latent, float* ws, int n_waves,
+                                                      float inv_n) {
+  using TC = TrainCfg<C, F, L, ACT>;
+  using CF = typename TC::CF;
+  using G = typename TC::G;
+  using PR = PrecT<kF32>;
+  constexpr int MT = TC::MT, AS = TC::AS;
+  const int H = nd.H;
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  stage_weights<CF>(nd, smem);
+  char* back = smem + G::weight_bytes(H);
+  stage_backward<TC, ACT>(nd, back);
+  __syncthreads();
+  const int wave_l = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * (blockDim.x >> 6) + wave_l;
+  if (wave >= n_waves) return;
+  const int g = lane >> 4, nn = lane & 15;
+  char* wbase = back + TC::back_bytes(H) + wave_l * TC::wave_bytes(H);
+  float* feat = reinterpret_cast<float*>(wbase);
+  float* abuf = reinterpret_cast<float*>(wbase + TC::FEAT);
+  float* dbuf = reinterpret_cast<float*>(wbase + TC::FEAT + TC::abuf_bytes(H));
+  float* dy = reinterpret_cast<float*>(wbase + TC::FEAT + TC::abuf_bytes(H) + TC::DBUF);
+  float* zbuf = reinterpret_cast<float*>(wbase + TC::FEAT + TC::abuf_bytes(H) + TC::DBUF + TC::DY);
+  float* slice = ws + (size_t)wave * TC::slice(H);
+  const float* W0 = reinterpret_cast<const float*>(smem);
+  const char* wout_p = smem + G::W0A + (H - 1) * G::HID;
+  const float* WO = reinterpret_cast<const float*>(wout_p);
+  const float b_out = *reinterpret_cast<const float*>(wout_p + G::WOA);
+  // output weights (unscaled) straight from global memory, in D-layout order
+  const float* w_out = nd.weights + (long long)C * (3 + F + 6 * L) + C + (long long)(H - 1) * (C * C + C);
+  const LatentSrc ls = make_latent_src(nd, 0, 0.0f);
+  float loss_acc = 0.0f, dbo_acc = 0.0f;
+  const long long nchunks = (n + 63) / 64;
+  bool first = true;
+  auto add_tile = [&](int tile, f4 v) {
+    f4* dst = reinterpret_cast<f4*>(slice + tile * 256) + lane;
+    if (first) *dst = v;
+    else *dst = *dst + v;
+  };
+  for (long long c = wave; c < nchunks; c += n_waves) {
+    const long long idx = c * 64 + lane;
+    const bool ok = idx < n;
+    float px = 0.0f, py = 0.0f, pz = 0.0f;
+    if (ok) {
+      px = xyz[3 * idx];
+      py = xyz[3 * idx + 1];
+      pz = xyz[3 * idx + 2];
+    }
+    write_features<CF, false>(feat + lane * G::ROW, ls, value_role(), px, py, pz);
+    wave_lds_sync();
+    // ---------------- forward: store pre-activations a_i[s][o]
+    f4 out = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int t = 0; t < 4; ++t) {
+      f4 acc[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[mt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int q = 0; q < G::Q0; ++q) {
+        const float b = feat[(16 * t + nn) * G::ROW + g * G::Q0 + q];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[mt] = PR::mma(W0[(mt * G::Q0 + q) * kWave + lane], b, acc[mt]);
+      }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) *reinterpret_cast<f4*>(abuf + (16 * t + nn) * AS + 16 * mt + 4 * g) = acc[mt];
+      const char* p = smem + G::W0A;
+      for (int i = 1; i < H; ++i) {
+        const float* WH = reinterpret_cast<const float*>(p);
+        const float* BHp = reinterpret_cast<const float*>(p + G::WHA);
+        f4 nacc[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) nacc[mt] = *reinterpret_cast<const f4*>(BHp + 16 * mt + 4 * g);
+#pragma unroll
+        for (int q = 0; q < 4 * MT; ++q) {
+          const float b = act_el<ACT, false>(acc[q / 4][q % 4], value_role());
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) nacc[mt] = PR::mma(WH[(mt * 4 * MT + q) * kWave + lane], b, nacc[mt]);
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          acc[mt] = nacc[mt];
+          *reinterpret_cast<f4*>(abuf + i * 64 * AS + (16 * t + nn) * AS + 16 * mt + 4 * g) = acc[mt];
+        }
+        p += G::HID;
+      }
+#pragma unroll
+      for (int q = 0; q < 4 * MT; ++q) {
+        const float b = act_el<ACT, false>(acc[q / 4][q % 4], value_role());
+        out = PR::mma(WO[(t * 4 * MT + q) * kWave + lane], b, out);
+      }
+    }
+    // ---------------- loss and dL/dy for this lane's own sample
+    const float y = out[0] + b_out;
+    const float d = sigmoid_f(y);
+    float gy = 0.0f;
+    if (ok) {
+      if (target) {
+        const float r = d - target[idx];
+        loss_acc += fabsf(r);
+        gy = (r > 0.0f ? 1.0f : (r < 0.0f ? -1.0f : 0.0f)) * inv_n;
+      } else {
+        loss_acc += dloss[idx] * d;
+        gy = dloss[idx];
+      }
+    }
+    const float dyv = gy * d * (1.0f - d);
+    dbo_acc += dyv;
+    dy[lane] = dyv;
+    wave_lds_sync();
+    // ---------------- output layer weights: dW_H[0][k] = sum_s dy[s] h[k][s]
+    const float* alast = abuf + (H - 1) * 64 * AS;
+#pragma unroll
+    for (int nk = 0; nk < MT; ++nk) {
+      f4 dw = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int s = 4 * q + g;
+        const float a = nn == 0 ? dy[s] : 0.0f;
+        const float b = act_el<ACT, false>(alast[s * AS + 16 * nk + nn], value_role());
+        dw = PR::mma(a, b, dw);
+      }
+      add_tile(TC::tile_out(H, nk), dw);
+    }
+    // ---------------- backward through the activated layers
+    f4 dh[4][MT];  // d L / d h_i in D layout, per N-tile
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const float dys = dy[16 * t + nn];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const f4 wo = {w_out[16 * mt + 4 * g + 0], w_out[16 * mt + 4 * g + 1], w_out[16 * mt + 4 * g + 2],
+                       w_out[16 * mt + 4 * g + 3]};
+        dh[t][mt] = wo * dys;
+      }
+    }
+    for (int i = H - 1; i >= 0; --i) {
+      const float* ai = abuf + i * 64 * AS;
+      // delta_i = d L / d x_i = (d L / d h_i) * act'(x_i), x = W h + b in
+      // world units (a_i holds x / (2 pi) for the periodic activations)
+      f4 dbias[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) dbias[mt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const f4 a = *reinterpret_cast<const f4*>(ai + (16 * t + nn) * AS + 16 * mt + 4 * g);
+          f4 da;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) da[j] = dh[t][mt][j] * act_d<ACT>(a[j]);
+          dh[t][mt] = da;
+          *reinterpret_cast<f4*>(dbuf + (16 * t + nn) * AS + 16 * mt + 4 * g) = da;
+          dbias[mt] += da;
+        }
+      if (i >= 1) {
+        // partial bias gradient of this lane's 4 samples (summed over lanes by the reduction)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) add_tile(TC::tile_bias(H, i, mt), dbias[mt]);
+      }
+      wave_lds_sync();
+      // dW_i = delta_i h_i^T over the 64 samples
+      if (i == 0) {
+#pragma unroll
+        for (int mo = 0; mo < MT; ++mo)
+#pragma unroll
+          for (int nk = 0; nk < TC::NK0; ++nk) {
+            f4 dw = {0.0f, 0.0f, 0.0f, 0.0f};
+            const int col = 16 * nk + nn;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+              const int s = 4 * q + g;
+              const float a = dbuf[s * AS + 16 * mo + nn];
+              const float b = col < G::KROW ? feat[s * G::ROW + col] : 0.0f;
+              dw = PR::mma(a, b, dw);
+            }
+            add_tile(TC::tile_l0(mo, nk), dw);
+          }
+      } else {
+        const float* ap = abuf + (i - 1) * 64 * AS;
+#pragma unroll
+        for (int mo = 0; mo < MT; ++mo)
+#pragma unroll
+          for (int nk = 0; nk < MT; ++nk) {
+            f4 dw = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+              const int s = 4 * q + g;
+              const float a = dbuf[s * AS + 16 * mo + nn];
+              const float b = act_el<ACT, false>(ap[s * AS + 16 * nk + nn], value_role());
+              dw = PR::mma(a, b, dw);
+            }
+            add_tile(TC::tile_h(H, i, mo, nk), dw);
+          }
+      }
+      if (i >= 1) {
+        // d L / d h_{i-1} = W_i^T delta_i (MFMA, B = delta in D layout)
+        const float* WB = reinterpret_cast<const float*>(back + (i - 1) * TC::WB);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          f4 nd2[MT];
+#pragma unroll
+          for (int mk = 0; mk < MT; ++mk) nd2[mk] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+          for (int q = 0; q < 4 * MT; ++q) {
+            const float b = dh[t][q / 4][q % 4];
+#pragma unroll
+            for (int mk = 0; mk < MT; ++mk) nd2[mk] = PR::mma(WB[(mk * 4 * MT + q) * kWave + lane], b, nd2[mk]);
+          }
+#pragma unroll
+          for (int mk = 0; mk < MT; ++mk) dh[t][mk] = nd2[mk];
+        }
+      } else {
+        // d L / d z = W_0[:, latent]^T delta_0 -> zbuf[s][f]
+        const float* WZ = reinterpret_cast<const float*>(back + (H - 1) * TC::WB);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          f4 dz = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+          for (int q = 0; q < 4 * MT; ++q) dz = PR::mma(WZ[q * kWave + lane], dh[t][q / 4][q % 4], dz);
+          if (4 * g < F) *reinterpret_cast<f4*>(zbuf + (16 * t + nn) * TC::ZS + 4 * g) = dz;
+        }
+      }
+      wave_lds_sync();
+    }
+    // ---------------- latent scatter with the trilinear weights
+    if (ok) {
+      int ix, iy, iz;
+      float fx, fy, fz;
+      axis_cell(px, nd.R, ix, fx);
+      axis_cell(py, nd.R, iy, fy);
+      axis_cell(pz, nd.R, iz, fz);
+      const unsigned R = (unsigned)nd.R;
+      const unsigned sx = F, sy = R * F, sz = R * R * F;
+      const unsigned base = (unsigned)iz * sz + (unsigned)iy * sy + (unsigned)ix * sx;
+      const float gx = 1.0f - fx, gy2 = 1.0f - fy, gz = 1.0f - fz;
+      const float w8[8] = {gx * gy2 * gz, fx * gy2 * gz, gx * fy * gz, fx * fy * gz,
+                           gx * gy2 * fz, fx * gy2 * fz, gx * fy * fz, fx * fy * fz};
+      const unsigned off[8] = {base, base + sx, base + sy, base + sx + sy,
+                               base + sz, base + sz + sx, base + sz + sy, base + sz + sx + sy};
+      float z[F];
+#pragma unroll
+      for (int f = 0; f < F; ++f) z[f] = zbuf[lane * TC::ZS + f];
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc)
+#pragma unroll
+        for (int f = 0; f < F; ++f) unsafeAtomicAdd(d_latent + off[cc] + f, w8[cc] * z[f]);
+    }
+    first = false;
+  }
+  // ---------------- per-wave partials of the output bias and the loss
+  slice[TC::tiles(H) * 256 + lane] = dbo_acc;
+  slice[TC::tiles(H) * 256 + 64 + lane] = loss_acc;
+}
+
+// Sums the wave slices in a fixed order into the packed gradient.
+template <int C, int F, int L, int ACT>
+__global__ void reduce_kernel(int H, const float* ws, int n_waves, float* d_weights, float* out_loss, float loss_scale) {
+  using TC = TrainCfg<C, F, L, ACT>;
+  using G = typename TC::G;
+  const int K0 = 3 + F + 6 * L;
+  const long long nw = (long long)C * K0 + C + (long long)(H - 1) * (C * C + C) + C + 1;
+  const int SL = TC::slice(H);
+  for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < nw + 1;
+       j += (long long)gridDim.x * blockDim.x) {
+    // locate weight j: a list of (offset within slice) terms to add
+    int base = -1, count = 0, stride = 0;
+    if (j == nw) {  // loss
+      base = TC::tiles(H) * 256 + 64;
+      count = 64;
+      stride = 1;
+    } else {
+      long long r = j;
+      const long long l0 = (long long)C * K0;
+      if (r < l0 + C) {
+        int o, col;
+        if (r < l0) {
+          o = (int)(r / K0);
+          const int k = (int)(r % K0);
+          col = k < 3 ? G::KMAIN + k : k - 3;
+        } else {
+          o = (int)(r - l0);
+          col = G::KMAIN + 3;
+        }
+        const int tile = TC::tile_l0(o / 16, col / 16);
+        base = tile * 256 + (16 * ((o % 16) / 4) + col % 16) * 4 + o % 4;
+        count = 1;
+      } else {
+        r -= l0 + C;
+        const long long per = (long long)C * C + C;
+        const int i = 1 + (int)(r / per);
+        if (i < H) {
+          r %= per;
+          if (r < (long long)C * C) {
+            const int o = (int)(r / C), k = (int)(r % C);
+            base = TC::tile_h(H, i, o / 16, k / 16) * 256 + (16 * ((o % 16) / 4) + k % 16) * 4 + o % 4;
+            count = 1;
+          } else {
+            const int o = (int)(r - (long long)C * C);
+            base = TC::tile_bias(H, i, o / 16) * 256 + (16 * ((o % 16) / 4)) * 4 + o % 4;
+            count = 16;
+            stride = 4;
+          }
+        } else {
+          r -= (long long)(H - 1) * per;
+          if (r < C) {
+            const int k = (int)r;
+            base = TC::tile_out(H, k / 16) * 256 + (k % 16) * 4;
+            count = 1;
+          } else {
+            base = TC::tiles(H) * 256;
+            count = 64;
+            stride = 1;
+          }
+        }
+      }
+    }
+    float s = 0.0f;
+    for (int w = 0; w < n_waves; ++w) {
+      const float* sl = ws + (size_t)w * SL + base;
+      for (int c = 0; c < count; ++c) s += sl[c * stride];
+    }
+    if (j == nw) {
+      if (out_loss) *out_loss = s * loss_scale;
+    } else {
+      d_weights[j] = s;
+    }
+  }
+}
+
+__global__ void fill_kernel(float* p, long long n, float v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// Bias-corrected Adam (PyTorch's form): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+// p -= lr / bc1 * m / (sqrt(v) / sqrt(bc2) + eps).
+__global__ void adam_kernel(float* p, const float* g, float* m, float* v, long long n, float lr_bc1, float b1,
+                            float b2, float inv_sqrt_bc2, float eps) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr_bc1 * mi / (sqrtf(vi) * inv_sqrt_bc2 + eps);
+  }
+}
+
+template <int C, int F, int L, int ACT>
+struct TrainEntry {
+  using TC = TrainCfg<C, F, L, ACT>;
+  static int waves_per_block(int H) {
+    const int fixed = TC::G::weight_bytes(H) + TC::back_bytes(H);
+    int w = (160 * 1024 - fixed) / TC::wave_bytes(H);
+    return w < 1 ? 0 : (w > 4 ? 4 : w);
+  }
+  static int n_waves(long long n) {
+    const long long c = (n + 63) / 64;
+    return (int)(c < kTrainMaxWaves ? (c < 1 ? 1 : c) : kTrainMaxWaves);
+  }
+  static size_t ws_bytes(const NetDev& nd, long long n) {
+    return (size_t)n_waves(n) * TC::slice(nd.H) * sizeof(float);
+  }
+  static int run(const NetDev& nd, float* latent, float* d_latent, float* d_weights, const float* xyz, long long n,
+                 const float* target, const float* dloss, float* out_loss, void* ws, hipStream_t st) {
+    const int H = nd.H;
+    const int wpb = waves_per_block(H);
+    if (wpb < 1) return 1;
+    const long long nlat = (long long)nd.R * nd.R * nd.R * nd.F;
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_blocks(nlat, 256, device_cus() * 8)), dim3(256), 0, st, d_latent,
+                       nlat, 0.0f);
+    int rc = check_launch();
+    if (rc) return rc;
+    const int nw = n_waves(n);
+    const size_t shm = (size_t)TC::block_bytes(H, wpb);
+    static bool attr = false;
+    if (!attr) {
+      (void)hipFuncSetAttribute((const void*)fwd_bwd_kernel<C, F, L, ACT>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      attr = true;
+    }
+    NetDev nd2 = nd;
+    nd2.latent = latent;
+    nd2.grid_f16 = 0;
+    nd2.K = 1;
+    if (n > 0) {
+      hipLaunchKernelGGL((fwd_bwd_kernel<C, F, L, ACT>), dim3((nw + wpb - 1) / wpb), dim3(wpb * 64), shm, st, nd2,
+                         xyz, n, target, dloss, d_latent, (float*)ws, nw, 1.0f / (float)n);
+      rc = check_launch();
+      if (rc) return rc;
+    } else {
+      // no points: every slice is zero
+      hipLaunchKernelGGL(fill_kernel, dim3(grid_blocks((long long)nw * TC::slice(H), 256, device_cus() * 8)),
+                         dim3(256), 0, st, (float*)ws, (long long)nw * TC::slice(H), 0.0f);
+      rc = check_launch();
+      if (rc) return rc;
+    }
+    const long long nwts = (long long)C * (3 + F + 6 * L) + C + (long long)(H - 1) * (C * C + C) + C + 1;
+    hipLaunchKernelGGL((reduce_kernel<C, F, L, ACT>), dim3(grid_blocks(nwts + 1, 128, 1024)), dim3(128), 0, st, H,
+                       (const float*)ws, nw, d_weights, out_loss, target && n > 0 ? 1.0f / (float)n : 1.0f);
+    return check_launch();
+  }
+};
+
+#define FV_TRAIN_CASES(X) \
+  X(32, 8, 4)             \
+  X(32, 16, 8)            \
+  X(48, 8, 4)             \
+  X(48, 16, 8)
+
+}  // namespace
+
+size_t train_workspace_bytes(const NetDev& nd, long long n) {
+#define X(C_, F_, L_)                                                            \
+  if (nd.C == C_ && nd.F == F_ && nd.L == L_) {                                  \
+    if (nd.act == kSine) return TrainEntry<C_, F_, L_, kSine>::ws_bytes(nd, n);  \
+    if (nd.act == kSnakeAlt) return TrainEntry<C_, F_, L_, kSnakeAlt>::ws_bytes(nd, n); \
+    return TrainEntry<C_, F_, L_, kIdentity>::ws_bytes(nd, n);                   \
+  }
+  FV_TRAIN_CASES(X)
+#undef X
+  return 0;
+}
+
+int launch_train(const NetDev& nd, float* latent, float* weights, float* d_latent, float* d_weights, const float* xyz,
+                 long long n, const float* target, const float* dloss_dy, int use_adam, float lr_grid, float lr_mlp,
+                 float beta1, float beta2, float eps, int step, float* m_lat, float* v_lat, float* m_w, float* v_w,
+                 float* out_loss, void* workspace, size_t ws_bytes, void* stream) {
+  const hipStream_t st = (hipStream_t)stream;
+  NetDev net = nd;
+  net.weights = weights;
+  int rc = 1;
+#define X(C_, F_, L_)                                                                                           \
+  if (nd.C == C_ && nd.F == F_ && nd.L == L_) {                                                                 \
+    if (nd.act == kSine)                                                                                        \
+      rc = TrainEntry<C_, F_, L_, kSine>::run(net, latent, d_latent, d_weights, xyz, n, target, dloss_dy,       \
+                                              out_loss, workspace, st);                                         \
+    else if (nd.act == kSnakeAlt)                                                                               \
+      rc = TrainEntry<C_, F_, L_, kSnakeAlt>::run(net, latent, d_latent, d_weights, xyz, n, target, dloss_dy,   \
+                                                  out_loss, workspace, st);                                     \
+    else                                                                                                        \
+      rc = TrainEntry<C_, F_, L_, kIdentity>::run(net, latent, d_latent, d_weights, xyz, n, target, dloss_dy,   \
+                                                  out_loss, workspace, st);                                     \
+  }
+  FV_TRAIN_CASES(X)
+#undef X
+  (void)ws_bytes;
+  if (rc != 0 || !use_adam) return rc;
+  const double bc1 = 1.0 - pow((double)beta1, (double)step);
+  const double bc2 = 1.0 - pow((double)beta2, (double)step);
+  const long long nlat = (long long)nd.R * nd.R * nd.R * nd.F;
+  const long long nw = (long long)nd.C * (3 + nd.F + 6 * nd.L) + nd.C + (long long)(nd.H - 1) * (nd.C * nd.C + nd.C) +
+                       nd.C + 1;
+  hipLaunchKernelGGL(adam_kernel, dim3(grid_blocks(nlat, 256, device_cus() * 8)), dim3(256), 0, st, latent, d_latent,
+                     m_lat, v_lat, nlat, (float)(lr_grid / bc1), beta1, beta2, (float)(1.0 / sqrt(bc2)), eps);
+  rc = check_launch();
+  if (rc) return rc;
+  hipLaunchKernelGGL(adam_kernel, dim3(grid_blocks(nw, 256, device_cus() * 8)), dim3(256), 0, st, weights, d_weights,
+                     m_w, v_w, nw, (float)(lr_mlp / bc1), beta1, beta2, (float)(1.0 / sqrt(bc2)), eps);
+  return check_launch();
 }
 
 }  // namespace fvsrn_detail

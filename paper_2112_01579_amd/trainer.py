@@ -1,0 +1,95 @@
+"""World-space fitting of an fV-SRN on the GPU (Sec. 3, Sec. 5): uniform
+random positions, targets sampled trilinearly from the original dense grid,
+L1 loss and Adam with separate learning rates for the latent grid and the
+network. Every step runs in the HIP library: point sampling, target lookup,
+the fused forward/backward kernel, the gradient reduction and Adam.
+
+Also provides ``FvsrnPoints``, a torch.autograd.Function whose forward is
+fvsrn_eval_points and whose backward is fvsrn_train_step in VJP mode, so the
+fV-SRN can sit inside any torch loss.
+"""
+from __future__ import annotations
+
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import fvsrn as FV
+from . import inputs as I
+
+
+class Trainer:
+    """Adam training of ``net`` (FP32 latent grid, one keyframe) on a dense
+    volume ``vol`` [nz][ny][nx] (device FP32)."""
+
+    def __init__(self, net: FV.Network, vol: torch.Tensor, batch: int = 1 << 18, lr_grid: float = 1e-2,
+                 lr_mlp: float = 1e-3, betas=(0.9, 0.999), eps: float = 1e-8, seed: int = 0):
+        assert net.grid_dtype == FV.F32 and net.spec.K == 1
+        self.net, self.vol, self.batch, self.seed = net, vol, batch, seed
+        dev = net.weights.device
+        self.opt = dict(lr_grid=lr_grid, lr_mlp=lr_mlp, beta1=betas[0], beta2=betas[1], eps=eps, step=0,
+                        m_latent=torch.zeros_like(net.latent), v_latent=torch.zeros_like(net.latent),
+                        m_weights=torch.zeros_like(net.weights), v_weights=torch.zeros_like(net.weights))
+        self.d_latent = torch.empty_like(net.latent)
+        self.d_weights = torch.empty_like(net.weights)
+        self.xyz = torch.empty((batch, 3), dtype=torch.float32, device=dev)
+        self.target = torch.empty(batch, dtype=torch.float32, device=dev)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        ws = FV.fvsrn_train_workspace_size(net.spec, batch)
+        self.workspace = torch.empty(max(ws, 16), dtype=torch.uint8, device=dev)
+
+    def step(self) -> torch.Tensor:
+        """One training step; returns the L1 loss of the batch (device scalar)."""
+        self.opt["step"] += 1
+        FV.fvsrn_sample_points(self.seed, self.opt["step"], self.batch, out=self.xyz)
+        FV.fvsrn_dense_eval_points(self.vol, self.xyz, out=self.target)
+        FV.fvsrn_train_step(self.net, self.d_latent, self.d_weights, self.xyz, target=self.target, adam=self.opt,
+                            out_loss=self.loss, workspace=self.workspace)
+        return self.loss
+
+    def state_dict(self) -> dict:
+        o = self.opt
+        return {"latent": self.net.latent.cpu().numpy(), "weights": self.net.weights.cpu().numpy(),
+                "m_latent": o["m_latent"].cpu().numpy(), "v_latent": o["v_latent"].cpu().numpy(),
+                "m_weights": o["m_weights"].cpu().numpy(), "v_weights": o["v_weights"].cpu().numpy(),
+                "step": np.int64(o["step"]), "seed": np.int64(self.seed)}
+
+    def save(self, path: str):
+        np.savez(path, **self.state_dict())
+
+    def load(self, path: str):
+        d = np.load(path)
+        self.net.latent.copy_(torch.from_numpy(d["latent"]))
+        self.net.weights.copy_(torch.from_numpy(d["weights"]))
+        for k in ("m_latent", "v_latent", "m_weights", "v_weights"):
+            self.opt[k].copy_(torch.from_numpy(d[k]))
+        self.opt["step"] = int(d["step"])
+        self.seed = int(d["seed"])
+
+
+class FvsrnPoints(torch.autograd.Function):
+    """density = fV-SRN(xyz) with gradients for the latent grid and weights.
+
+    ``latent`` and ``weights`` are the network's own tensors (passed so that
+    autograd tracks them); gradients w.r.t. ``xyz`` are not provided."""
+
+    @staticmethod
+    def forward(ctx, xyz: torch.Tensor, latent: torch.Tensor, weights: torch.Tensor, net: FV.Network):
+        assert latent.data_ptr() == net.latent.data_ptr() and weights.data_ptr() == net.weights.data_ptr()
+        ctx.net = net
+        ctx.save_for_backward(xyz)
+        return FV.fvsrn_eval_points(net, xyz.contiguous(), 0.0, "f32")
+
+    @staticmethod
+    def backward(ctx, grad_out: torch.Tensor):
+        (xyz,) = ctx.saved_tensors
+        net = ctx.net
+        d_lat = torch.empty_like(net.latent)
+        d_w = torch.empty_like(net.weights)
+        FV.fvsrn_train_step(net, d_lat, d_w, xyz.contiguous(), dloss_dy=grad_out.contiguous().float())
+        return None, d_lat, d_w, None
+
+
+def fvsrn_points(net: FV.Network, xyz: torch.Tensor) -> torch.Tensor:
+    return FvsrnPoints.apply(xyz, net.latent, net.weights, net)

@@ -1,0 +1,141 @@
+"""GPU training step (fwd/bwd kernel, gradient reduction, Adam) against the
+FP64 oracle. Tolerances: gradients within 1e-4 of the largest |gradient|
+(FP32 sums over thousands of points); loss within 1e-5 relative; one Adam
+update within 1e-6 of the oracle's update of the same gradients."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2112_01579_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def FV():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2112_01579_amd import fvsrn
+    fvsrn.lib()
+    return fvsrn
+
+
+def _setup(FV, spec, seed, n):
+    lat, w = I.net_params(spec, seed)
+    gnet = FV.Network(spec, lat, w)
+    onet = O.Net(spec, lat, w)
+    xyz = I.uniform_points(n, seed + 1, -0.99, 0.99)
+    return gnet, onet, xyz
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)
+
+
+@pytest.mark.parametrize("spec_name", ["CFG1", "CFG2"])
+def test_train_gradients_l1(FV, spec_name):
+    spec = getattr(I, spec_name)
+    n = 64 * 37 + 13
+    gnet, onet, xyz = _setup(FV, spec, 11, n)
+    d = O.eval_points(onet, xyz)
+    rng = np.random.default_rng(2)
+    # targets away from the prediction so that sign(d - t) is the same in FP32 and FP64
+    off = rng.uniform(0.01, 0.3, n) * rng.choice([-1, 1], n)
+    target = (d + off).astype(np.float32)
+    dl_ref, dw_ref, loss_ref = O.train_grads(onet, xyz, target=target.astype(np.float64))
+    d_lat = torch.empty_like(gnet.latent)
+    d_w = torch.empty_like(gnet.weights)
+    loss = torch.zeros(1, device="cuda")
+    FV.fvsrn_train_step(gnet, d_lat, d_w, torch.from_numpy(xyz).cuda(), target=torch.from_numpy(target).cuda(),
+                        out_loss=loss)
+    e_w, e_l = _rel(d_w.cpu().numpy(), dw_ref), _rel(d_lat.cpu().numpy(), dl_ref)
+    print("train %s L1: dW rel err %.3g, dG rel err %.3g, loss %.6g vs %.6g" % (spec_name, e_w, e_l,
+                                                                                  loss.item(), loss_ref), flush=True)
+    assert e_w <= 1e-4 and e_l <= 1e-4
+    # the mean of |d - t| inherits the FP32 rounding of each density (~2e-7)
+    assert abs(loss.item() - loss_ref) <= 1e-5 * abs(loss_ref) + 1e-7
+
+
+@pytest.mark.parametrize("act", ["sine", "snakealt", "identity"])
+def test_train_gradients_vjp(FV, act):
+    spec = I.NetSpec(R=16, F=8, L=4, c=32, H=3, act=act)
+    n = 1000
+    lat, w = I.net_params(spec, 4)
+    if act == "identity":
+        w = w * 0.5
+    gnet, onet = FV.Network(spec, lat, w), O.Net(spec, lat, w)
+    xyz = I.uniform_points(n, 6, -0.99, 0.99)
+    up = np.random.default_rng(1).normal(size=n).astype(np.float32)
+    dl_ref, dw_ref, loss_ref = O.train_grads(onet, xyz, dloss_dd=up.astype(np.float64))
+    d_lat = torch.empty_like(gnet.latent)
+    d_w = torch.empty_like(gnet.weights)
+    loss = torch.zeros(1, device="cuda")
+    FV.fvsrn_train_step(gnet, d_lat, d_w, torch.from_numpy(xyz).cuda(), dloss_dy=torch.from_numpy(up).cuda(),
+                        out_loss=loss)
+    e_w, e_l = _rel(d_w.cpu().numpy(), dw_ref), _rel(d_lat.cpu().numpy(), dl_ref)
+    print("train act=%s VJP: dW rel err %.3g, dG rel err %.3g" % (act, e_w, e_l), flush=True)
+    assert e_w <= 1e-4 and e_l <= 1e-4
+    assert abs(loss.item() - loss_ref) <= 1e-5 * max(1.0, abs(loss_ref))
+
+
+def test_train_gradients_deterministic_and_empty(FV):
+    gnet, onet, xyz = _setup(FV, I.CFG1, 3, 5000)
+    up = torch.randn(5000, device="cuda")
+    a = [torch.empty_like(gnet.weights) for _ in range(2)]
+    for k in range(2):
+        FV.fvsrn_train_step(gnet, torch.empty_like(gnet.latent), a[k], torch.from_numpy(xyz).cuda(), dloss_dy=up)
+    assert torch.equal(a[0], a[1])
+    d_lat = torch.full_like(gnet.latent, 7.0)
+    d_w = torch.full_like(gnet.weights, 7.0)
+    loss = torch.full((1,), 7.0, device="cuda")
+    FV.fvsrn_train_step(gnet, d_lat, d_w, torch.empty((0, 3), device="cuda"), target=torch.empty(0, device="cuda"),
+                        out_loss=loss)
+    assert torch.count_nonzero(d_lat).item() == 0 and torch.count_nonzero(d_w).item() == 0 and loss.item() == 0.0
+
+
+def test_adam_step_matches_oracle(FV):
+    gnet, onet, xyz = _setup(FV, I.CFG1, 5, 3000)
+    target = np.random.default_rng(0).uniform(0, 1, 3000).astype(np.float32)
+    opt = dict(lr_grid=1e-2, lr_mlp=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, step=0,
+               m_latent=torch.zeros_like(gnet.latent), v_latent=torch.zeros_like(gnet.latent),
+               m_weights=torch.zeros_like(gnet.weights), v_weights=torch.zeros_like(gnet.weights))
+    lat0, w0 = gnet.latent.cpu().numpy().astype(np.float64), gnet.weights.cpu().numpy().astype(np.float64)
+    d_lat, d_w = torch.empty_like(gnet.latent), torch.empty_like(gnet.weights)
+    ml, vl, mw, vw = (np.zeros_like(lat0), np.zeros_like(lat0), np.zeros_like(w0), np.zeros_like(w0))
+    for t in (1, 2):
+        opt["step"] = t
+        FV.fvsrn_train_step(gnet, d_lat, d_w, torch.from_numpy(xyz).cuda(), target=torch.from_numpy(target).cuda(),
+                            adam=opt)
+        # the oracle applies Adam to the gradients the GPU produced in this step,
+        # with the hyperparameters as the FP32 values the C ABI receives
+        f = lambda x: float(np.float32(x))
+        O.adam(lat0, d_lat.cpu().numpy().astype(np.float64), ml, vl, f(1e-2), f(0.9), f(0.999), f(1e-8), t)
+        O.adam(w0, d_w.cpu().numpy().astype(np.float64), mw, vw, f(1e-3), f(0.9), f(0.999), f(1e-8), t)
+        assert np.abs(gnet.latent.cpu().numpy() - lat0).max() <= 1e-6
+        assert np.abs(gnet.weights.cpu().numpy() - w0).max() <= 1e-6
+        assert np.abs(opt["v_weights"].cpu().numpy() - vw).max() <= 1e-6 * max(1e-12, np.abs(vw).max()) + 1e-12
+
+
+def test_training_reduces_loss_and_autograd(FV):
+    from paper_2112_01579_amd.trainer import Trainer, fvsrn_points
+    vol = torch.from_numpy(I.power_law_volume(48, 64, seed=3)).cuda()
+    lat, w = I.net_params(I.CFG1, 7)
+    net = FV.Network(I.CFG1, lat, w)
+    tr = Trainer(net, vol, batch=1 << 14)
+    losses = [tr.step().item() for _ in range(150)]
+    print("loss first/last: %.4f %.4f" % (np.mean(losses[:10]), np.mean(losses[-10:])), flush=True)
+    assert np.mean(losses[-10:]) < 0.6 * np.mean(losses[:10])
+    # autograd: the gradient of sum(density * u) equals the VJP-mode train step
+    xyz = torch.from_numpy(I.uniform_points(777, 1)).cuda()
+    lat_p = net.latent.requires_grad_(True)
+    w_p = net.weights.requires_grad_(True)
+    u = torch.randn(777, device="cuda")
+    dens = fvsrn_points(net, xyz)
+    (dens * u).sum().backward()
+    d_lat, d_w = torch.empty_like(net.latent), torch.empty_like(net.weights)
+    FV.fvsrn_train_step(net, d_lat, d_w, xyz, dloss_dy=u)
+    assert torch.equal(w_p.grad, d_w)
+    assert torch.allclose(lat_p.grad, d_lat, rtol=1e-5, atol=1e-9)
+    net.latent.requires_grad_(False)
+    net.weights.requires_grad_(False)
