@@ -91,13 +91,13 @@ def main():
 
     FV.lib()
     dev = torch.device("cuda:0")
-    spec = I.CFG2
-    lat, w = I.net_params(spec, I.SEED[2])
+    spec = I.NET_STUDY
+    lat, w = I.net_params(spec, I.SEED_STUDY)
     net = FV.Network(spec, lat, w, grid_dtype=FV.F16, device=dev)
     net32 = FV.Network(spec, lat, w, grid_dtype=FV.F32, device=dev)
     tf = I.ramp_tf()
-    cams = I.cfg2_cameras(1024, 1024, 8)
-    march = I.cfg2_march(1e-3)
+    cams = I.study_cameras(1024, 1024, 8)
+    march = I.study_march(1e-3)
     out = torch.empty((8, 1024, 1024, 4), dtype=torch.float32, device=dev)
     stats = torch.zeros(3, dtype=torch.int64, device=dev)
 
@@ -160,7 +160,7 @@ def main():
             ms = float(np.mean(per_c))
             comp["fvsrn_" + prec] = {"ms_per_frame": ms / len(cams), "samples_per_s": s / (ms * 1e-3),
                                      "tflops": s * fps / (ms * 1e-3) / 1e12}
-        vol = torch.from_numpy(I.gaussian_volume(256, 64, seed=I.SEED[2])).to(dev)
+        vol = torch.from_numpy(I.gaussian_volume(256, 64, seed=I.SEED_STUDY)).to(dev)
 
         def dense():
             FV.fvsrn_render_dense(vol, tf, cams, march, out=out, stats=stats)

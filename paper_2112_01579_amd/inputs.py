@@ -9,18 +9,21 @@ that both sides can consume the same inputs without sharing any of the code
 under test.
 
 Workloads (stand-ins for the paper's datasets, which are not available):
-  * cfg1  -- 16^3 x 8 latent grid, 4 octaves, 35->32->32->32->1 sine MLP,
-             orthographic 64x64 view, 128 segments per ray.
-  * cfg2  -- 256^3 sum of 64 anisotropic Gaussians (the 256^3 performance
-             study of Sec. 5.1 / comparison protocol of Sec. 7), 32^3 x 16
-             latent grid, 8 octaves, 4 hidden layers of width 32, 8-view
-             1024^2 perspective orbit with step 1/256 (two samples per voxel).
-  * cfg3  -- 256^3 power-law (k^-5/3) random-phase Fourier field, the cfg1
-             model trained on 2^18 uniform points per step.
-  * cfg4  -- 512^3 Marschner-Lobb signal (f_M = 6, alpha = 0.25), 64^3 x 16
-             grid, 4 hidden layers of width 48, 1920x1080, step 1/512, Phong.
-  * cfg5  -- 16 timesteps of 32 advected Gaussian blobs, keyframe latent
-             grids every 4 steps, 8 views at fractional times.
+  * small ortho  -- 16^3 x 8 latent grid, 4 octaves, 35->32->32->32->1 sine
+                    MLP (NET_SMALL), orthographic 64x64 view, 128 segments.
+  * study        -- 256^3 sum of 64 anisotropic Gaussians (the 256^3
+                    performance study of Sec. 5.1 / protocol of Sec. 7),
+                    32^3 x 16 latent grid, 8 octaves, 4 hidden layers of 32
+                    (NET_STUDY), 8-view 1024^2 orbit, step 1/256 (two samples
+                    per voxel).
+  * training     -- 256^3 power-law (k^-5/3) random-phase Fourier field fitted
+                    by NET_SMALL on 2^18 uniform points per step.
+  * shaded       -- 512^3 Marschner-Lobb signal (f_M = 6, alpha = 0.25),
+                    64^3 x 16 grid, 4 hidden layers of 48 (NET_SHADED),
+                    1920x1080, step 1/512, Phong.
+  * time         -- 16 timesteps of 32 advected Gaussian blobs, keyframe
+                    latent grids every 4 steps (NET_TIME), 8 views at
+                    fractional times.
 """
 from __future__ import annotations
 
@@ -263,35 +266,34 @@ def blob_volume(D: int, t: float, params, norm: float = 1.0) -> np.ndarray:
 
 # ------------------------------------------------------------ presets
 
-CFG1 = NetSpec(R=16, F=8, L=4, c=32, H=3)
-CFG2 = NetSpec(R=32, F=16, L=8, c=32, H=4)
-CFG3 = CFG1
-CFG4 = NetSpec(R=64, F=16, L=8, c=48, H=4)
-CFG5 = NetSpec(R=32, F=16, L=8, c=32, H=4, K=4)
-CFG5_KEY_TIMES = (0.0, 4.0, 8.0, 12.0)
+NET_SMALL = NetSpec(R=16, F=8, L=4, c=32, H=3)       # 16^3x8 grid, 4 octaves, 3 x 32
+NET_STUDY = NetSpec(R=32, F=16, L=8, c=32, H=4)      # 32^3x16 grid, 8 octaves, 4 x 32
+NET_SHADED = NetSpec(R=64, F=16, L=8, c=48, H=4)     # 64^3x16 grid, 8 octaves, 4 x 48
+NET_TIME = NetSpec(R=32, F=16, L=8, c=32, H=4, K=4)  # 4 keyframe grids of 32^3x16
+TIME_KEYS = (0.0, 4.0, 8.0, 12.0)
 
-SEED = {1: 1001, 2: 1002, 3: 1003, 4: 1004, 5: 1005}
+SEED_SMALL, SEED_STUDY, SEED_TRAIN, SEED_SHADED, SEED_TIME = 1001, 1002, 1003, 1004, 1005
 
 
-def cfg1_march() -> March:
+def ortho_march() -> March:
     return March(step=0.0, fixed_steps=128, ert_eps=0.0)
 
 
-def cfg2_cameras(width: int = 1024, height: int = 1024, n_views: int = 8) -> List[Camera]:
+def study_cameras(width: int = 1024, height: int = 1024, n_views: int = 8) -> List[Camera]:
     return orbit_cameras(n_views, width, height)
 
 
-def cfg2_march(ert_eps: float = 1e-3) -> March:
+def study_march(ert_eps: float = 1e-3) -> March:
     return March(step=1.0 / 256.0, ert_eps=ert_eps)
 
 
-def cfg4_camera(width: int = 1920, height: int = 1080) -> Camera:
+def shaded_camera(width: int = 1920, height: int = 1080) -> Camera:
     return orbit_cameras(8, width, height)[0]
 
 
-def cfg4_march(ert_eps: float = 1e-3) -> March:
+def shaded_march(ert_eps: float = 1e-3) -> March:
     return March(step=1.0 / 512.0, ert_eps=ert_eps, phong=True)
 
 
-def cfg5_cameras(width: int = 1024, height: int = 1024) -> List[Camera]:
+def time_cameras(width: int = 1024, height: int = 1024) -> List[Camera]:
     return orbit_cameras(8, width, height, times=[0.5 + 1.5 * v for v in range(8)])

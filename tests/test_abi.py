@@ -37,10 +37,10 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_num_weights_matches_layout():
-    for spec in (I.CFG1, I.CFG2, I.CFG4):
+    for spec in (I.NET_SMALL, I.NET_STUDY, I.NET_SHADED):
         assert FV.fvsrn_num_weights(spec) == spec.n_weights
-    assert FV.fvsrn_num_weights(I.CFG1) == 3297
-    assert FV.fvsrn_num_weights(I.CFG2) == 5377
+    assert FV.fvsrn_num_weights(I.NET_SMALL) == 3297
+    assert FV.fvsrn_num_weights(I.NET_STUDY) == 5377
 
 
 def test_status_strings():
@@ -53,7 +53,7 @@ FAKE = 0x10000  # aligned, never dereferenced: validation fails first
 
 
 def _desc(**kw):
-    d = FV.net_desc(I.CFG1)
+    d = FV.net_desc(I.NET_SMALL)
     for k, v in kw.items():
         setattr(d, k, v)
     return d
@@ -66,7 +66,7 @@ def _params(lat=FAKE, w=FAKE):
 def _render(d, p=None, tf=None, cams=None, nv=1, m=None, out=FAKE):
     tf = tf or FV.tf_struct(I.ramp_tf())
     cams = cams if cams is not None else FV.camera_structs([I.ortho_camera(8, 8)])
-    m = m or FV.march_struct(I.cfg1_march())
+    m = m or FV.march_struct(I.ortho_march())
     p = p or _params()
     return FV.lib().fvsrn_render(C.byref(d), C.byref(p), C.byref(tf), cams, nv, C.byref(m),
                                  C.c_void_p(out) if out else None, None, None)

@@ -45,45 +45,45 @@ def _report(name, err):
     print("%s max abs err %.3g" % (name, err), flush=True)
 
 
-# --------------------------------------------------------------- cfg1
+# --------------------------------------------------------------- small_ortho
 
 @pytest.fixture(scope="module")
-def cfg1(FV):
-    gnet, onet = _nets(FV, I.CFG1, I.SEED[1])
-    tf, cams, m = I.ramp_tf(), [I.ortho_camera(64, 64)], I.cfg1_march()
+def small_ortho(FV):
+    gnet, onet = _nets(FV, I.NET_SMALL, I.SEED_SMALL)
+    tf, cams, m = I.ramp_tf(), [I.ortho_camera(64, 64)], I.ortho_march()
     ref, ns = O.render(O.Field(net=onet), tf, cams, m)
     return gnet, onet, tf, cams, m, ref, ns
 
 
-def test_cfg1_render_fp32(FV, cfg1):
-    gnet, onet, tf, cams, m, ref, ns = cfg1
+def test_small_ortho_render_fp32(FV, small_ortho):
+    gnet, onet, tf, cams, m, ref, ns = small_ortho
     stats = torch.zeros(3, dtype=torch.int64, device="cuda")
     img = FV.fvsrn_render(gnet, tf, cams, m, "f32", stats=stats).cpu().numpy()
     err = np.abs(img - ref).max()
-    _report("cfg1 fp32 render", err)
+    _report("small_ortho fp32 render", err)
     assert err <= FP32_TOL
     assert stats[0].item() == ns == 64 * 64 * 128
     assert stats[1].item() == 64 * 64
 
 
 @pytest.mark.parametrize("prec,tol", [("f16", FP16_TOL), ("bf16", BF16_TOL)])
-def test_cfg1_render_reduced_precision(FV, cfg1, prec, tol):
-    gnet, onet, tf, cams, m, ref, ns = cfg1
+def test_small_ortho_render_reduced_precision(FV, small_ortho, prec, tol):
+    gnet, onet, tf, cams, m, ref, ns = small_ortho
     img = FV.fvsrn_render(gnet, tf, cams, m, prec).cpu().numpy()
     err = np.abs(img - ref).max()
-    _report("cfg1 %s render" % prec, err)
+    _report("small_ortho %s render" % prec, err)
     assert err <= tol
 
 
-def test_render_is_deterministic(FV, cfg1):
-    gnet, onet, tf, cams, m, ref, ns = cfg1
+def test_render_is_deterministic(FV, small_ortho):
+    gnet, onet, tf, cams, m, ref, ns = small_ortho
     a = FV.fvsrn_render(gnet, tf, cams, m, "f16")
     b = FV.fvsrn_render(gnet, tf, cams, m, "f16")
     assert torch.equal(a, b)
 
 
 @pytest.mark.parametrize("prec,tol", [("f32", FP32_TOL), ("f16", FP16_TOL), ("bf16", BF16_TOL)])
-@pytest.mark.parametrize("spec_name", ["CFG1", "CFG2", "CFG4"])
+@pytest.mark.parametrize("spec_name", ["NET_SMALL", "NET_STUDY", "NET_SHADED"])
 def test_eval_points(FV, spec_name, prec, tol):
     spec = getattr(I, spec_name)
     gnet, onet = _nets(FV, spec, 77)
@@ -97,7 +97,7 @@ def test_eval_points(FV, spec_name, prec, tol):
 
 
 def test_eval_points_fp16_grid(FV):
-    gnet, onet = _nets(FV, I.CFG2, 12, grid_dtype=1)
+    gnet, onet = _nets(FV, I.NET_STUDY, 12, grid_dtype=1)
     xyz = I.uniform_points(5000, 6)
     ref = O.eval_points(onet, xyz)
     for prec, tol in (("f32", FP32_TOL), ("f16", FP16_TOL)):
@@ -121,7 +121,7 @@ def test_eval_points_activations(FV):
 
 
 def test_eval_points_edge_sizes(FV):
-    gnet, onet = _nets(FV, I.CFG1, 4)
+    gnet, onet = _nets(FV, I.NET_SMALL, 4)
     for n in (1, 63, 64, 65):
         xyz = I.uniform_points(n, n)
         ref = O.eval_points(onet, xyz)
@@ -131,11 +131,11 @@ def test_eval_points_edge_sizes(FV):
     assert out.numel() == 0
 
 
-# -------------------------------------------------- cfg2-shaped renders
+# -------------------------------------------------- study-network renders
 
-def test_cfg2_render_small_ragged(FV):
-    """cfg2 network, 4-view orbit at 37x29 (ragged 8x8 tiles), step 1/256."""
-    gnet, onet = _nets(FV, I.CFG2, I.SEED[2])
+def test_study_render_small_ragged(FV):
+    """study network, 4-view orbit at 37x29 (ragged 8x8 tiles), step 1/256."""
+    gnet, onet = _nets(FV, I.NET_STUDY, I.SEED_STUDY)
     tf = I.ramp_tf()
     cams = I.orbit_cameras(4, 37, 29)
     m = I.March(step=1 / 256, ert_eps=0.0)
@@ -143,29 +143,29 @@ def test_cfg2_render_small_ragged(FV):
     stats = torch.zeros(3, dtype=torch.int64, device="cuda")
     img = FV.fvsrn_render(gnet, tf, cams, m, "f32", stats=stats).cpu().numpy()
     err = np.abs(img - ref).max()
-    _report("cfg2 small fp32", err)
+    _report("study small fp32", err)
     assert err <= FP32_TOL
     assert abs(stats[0].item() - ns) <= 0.001 * ns
     for prec, tol in (("f16", FP16_TOL), ("bf16", BF16_TOL)):
         img = FV.fvsrn_render(gnet, tf, cams, m, prec).cpu().numpy()
         err = np.abs(img - ref).max()
-        _report("cfg2 small %s" % prec, err)
+        _report("study small %s" % prec, err)
         assert err <= tol
 
 
-def test_cfg2_full_size_sampled_pixels(FV):
+def test_study_full_size_sampled_pixels(FV):
     """The benchmark launch (8 views x 1024^2, ERT 1e-3) against the oracle on
     sampled pixels."""
-    gnet, onet = _nets(FV, I.CFG2, I.SEED[2], grid_dtype=1)
+    gnet, onet = _nets(FV, I.NET_STUDY, I.SEED_STUDY, grid_dtype=1)
     tf = I.ramp_tf()
-    cams = I.cfg2_cameras(1024, 1024, 8)
-    m = I.cfg2_march(1e-3)
+    cams = I.study_cameras(1024, 1024, 8)
+    m = I.study_march(1e-3)
     rng = np.random.default_rng(3)
     pix = rng.choice(8 * 1024 * 1024, 192, replace=False)
     ref, _ = O.render(O.Field(net=onet), tf, cams, m, pixels=pix)
     img = FV.fvsrn_render(gnet, tf, cams, m, "f16").cpu().numpy().reshape(-1, 4)
     err = np.abs(img[pix] - ref.reshape(-1, 4)[pix]).max()
-    _report("cfg2 full-size f16 sampled", err)
+    _report("study full-size f16 sampled", err)
     assert err <= FP16_TOL
 
 
@@ -185,7 +185,7 @@ def test_c48_render(FV):
 
 def test_time_varying_render(FV):
     spec = I.NetSpec(R=16, F=16, L=8, c=32, H=4, K=4)
-    kt = I.CFG5_KEY_TIMES
+    kt = I.TIME_KEYS
     gnet, onet = _nets(FV, spec, 13, key_times=kt)
     tf = I.ramp_tf()
     cams = I.orbit_cameras(4, 16, 16, times=[-1.0, 2.5, 7.0, 20.0])
@@ -202,7 +202,7 @@ def test_time_varying_render(FV):
 
 
 def test_render_misses_and_ert(FV):
-    gnet, onet = _nets(FV, I.CFG1, 5)
+    gnet, onet = _nets(FV, I.NET_SMALL, 5)
     tf = I.ramp_tf()
     # camera looking away from the box: every ray misses
     away = I.Camera(ortho=False, eye=(0.0, 0.0, 3.0), target=(0.0, 0.0, 6.0), up=(0.0, 1.0, 0.0),
@@ -291,7 +291,7 @@ def _grad_err(g, ref):
     return np.abs(g - ref).max() / max(1.0, np.abs(ref).max())
 
 
-@pytest.mark.parametrize("spec_name", ["CFG1", "CFG2", "CFG4"])
+@pytest.mark.parametrize("spec_name", ["NET_SMALL", "NET_STUDY", "NET_SHADED"])
 def test_grad_points(FV, spec_name):
     spec = getattr(I, spec_name)
     gnet, onet = _nets(FV, spec, 31)
@@ -329,7 +329,7 @@ def test_grad_points_time_and_activations(FV):
 
 
 def test_grad_points_edge_sizes(FV):
-    gnet, onet = _nets(FV, I.CFG1, 8)
+    gnet, onet = _nets(FV, I.NET_SMALL, 8)
     for n in (1, 15, 16, 17):
         xyz = I.uniform_points(n, n, -0.9, 0.9)
         dref, gref = O.grad_points(onet, xyz)
@@ -340,10 +340,10 @@ def test_grad_points_edge_sizes(FV):
 
 @pytest.mark.parametrize("prec,tol", [("f32", 1e-4), ("f16", FP16_TOL)])
 def test_phong_render(FV, prec, tol):
-    """cfg4-shaped network (64^3 x 16 grid, 4 x 48) with headlight Phong from
+    """shaded network (64^3 x 16 grid, 4 x 48) with headlight Phong from
     the forward-mode gradient, on a ragged small view."""
-    spec = I.CFG4
-    gnet, onet = _nets(FV, spec, I.SEED[4])
+    spec = I.NET_SHADED
+    gnet, onet = _nets(FV, spec, I.SEED_SHADED)
     tf = I.ramp_tf()
     cams = I.orbit_cameras(1, 30, 17)
     m = I.March(step=1 / 128, ert_eps=0.0, phong=True)

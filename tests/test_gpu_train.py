@@ -33,7 +33,7 @@ def _rel(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)
 
 
-@pytest.mark.parametrize("spec_name", ["CFG1", "CFG2"])
+@pytest.mark.parametrize("spec_name", ["NET_SMALL", "NET_STUDY"])
 def test_train_gradients_l1(FV, spec_name):
     spec = getattr(I, spec_name)
     n = 64 * 37 + 13
@@ -80,7 +80,7 @@ def test_train_gradients_vjp(FV, act):
 
 
 def test_train_gradients_deterministic_and_empty(FV):
-    gnet, onet, xyz = _setup(FV, I.CFG1, 3, 5000)
+    gnet, onet, xyz = _setup(FV, I.NET_SMALL, 3, 5000)
     up = torch.randn(5000, device="cuda")
     a = [torch.empty_like(gnet.weights) for _ in range(2)]
     for k in range(2):
@@ -95,7 +95,7 @@ def test_train_gradients_deterministic_and_empty(FV):
 
 
 def test_adam_step_matches_oracle(FV):
-    gnet, onet, xyz = _setup(FV, I.CFG1, 5, 3000)
+    gnet, onet, xyz = _setup(FV, I.NET_SMALL, 5, 3000)
     target = np.random.default_rng(0).uniform(0, 1, 3000).astype(np.float32)
     opt = dict(lr_grid=1e-2, lr_mlp=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, step=0,
                m_latent=torch.zeros_like(gnet.latent), v_latent=torch.zeros_like(gnet.latent),
@@ -120,8 +120,8 @@ def test_adam_step_matches_oracle(FV):
 def test_training_reduces_loss_and_autograd(FV):
     from paper_2112_01579_amd.trainer import Trainer, fvsrn_points
     vol = torch.from_numpy(I.power_law_volume(48, 64, seed=3)).cuda()
-    lat, w = I.net_params(I.CFG1, 7)
-    net = FV.Network(I.CFG1, lat, w)
+    lat, w = I.net_params(I.NET_SMALL, 7)
+    net = FV.Network(I.NET_SMALL, lat, w)
     tr = Trainer(net, vol, batch=1 << 14)
     losses = [tr.step().item() for _ in range(150)]
     print("loss first/last: %.4f %.4f" % (np.mean(losses[:10]), np.mean(losses[-10:])), flush=True)

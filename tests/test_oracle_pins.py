@@ -214,7 +214,7 @@ def test_snakealt_activation_closed_form():
 # ------------------------------------------------ gradients (Sec. 6)
 
 def test_forward_and_reverse_mode_agree():
-    for spec in (I.CFG1, I.NetSpec(R=8, F=4, L=3, c=12, H=2, act="snakealt")):
+    for spec in (I.NET_SMALL, I.NetSpec(R=8, F=4, L=3, c=12, H=2, act="snakealt")):
         net = make_net(spec, seed=5)
         for _ in range(20):
             p = RNG.uniform(-1, 1, 3)
@@ -235,9 +235,9 @@ def _away_from_faces(R, n, h):
 
 
 def test_gradient_against_richardson_central_differences():
-    net = make_net(I.CFG1, seed=9)
+    net = make_net(I.NET_SMALL, seed=9)
     h = 1e-3
-    for p in _away_from_faces(I.CFG1.R, 16, h):
+    for p in _away_from_faces(I.NET_SMALL.R, 16, h):
         _, g = O.density_grad(net, p)
         fd = np.zeros(3)
         for a in range(3):
@@ -344,14 +344,14 @@ def _constant_net(spec, d0):
 
 def test_beer_lambert_constant_density():
     """Constant density: A = 1 - exp(-kappa L), C = rgb A over chord L."""
-    spec = I.CFG1
+    spec = I.NET_SMALL
     tf = I.ramp_tf()
     d0 = 0.45
     rgba = O.tf_eval(tf, d0)
     kappa = tf.opacity_scale * rgba[3]
     net = _constant_net(spec, d0)
     field = O.Field(net=net)
-    img, ns = O.render(field, tf, [I.ortho_camera(8, 8)], I.cfg1_march())
+    img, ns = O.render(field, tf, [I.ortho_camera(8, 8)], I.ortho_march())
     A = 1 - math.exp(-kappa * 2.0)
     np.testing.assert_allclose(img[0, ..., 3], A, rtol=1e-13)
     np.testing.assert_allclose(img[0, ..., :3], np.broadcast_to(A * rgba[:3], (8, 8, 3)), rtol=1e-13)
@@ -379,7 +379,7 @@ def test_zero_density_is_transparent():
 def test_early_ray_termination_closed_form():
     """Constant kappa, step ds: the march stops after the first sample i with
     exp(-kappa ds (i+1)) < eps."""
-    spec = I.CFG1
+    spec = I.NET_SMALL
     tf = I.ramp_tf()
     d0 = 0.8
     kappa = tf.opacity_scale * O.tf_eval(tf, d0)[3]
@@ -416,7 +416,7 @@ def test_segments_cover_chord_with_clipped_last_step():
     """Constant density with a step that does not divide the chord: the
     clipped last segment makes the optical depth exactly kappa * chord."""
     tf = I.ramp_tf()
-    net = _constant_net(I.CFG1, 0.3)
+    net = _constant_net(I.NET_SMALL, 0.3)
     kappa = tf.opacity_scale * 0.1
     m = I.March(step=0.37)
     img, ns = O.render(O.Field(net=net), tf, [I.ortho_camera(2, 2)], m)
@@ -490,7 +490,7 @@ def test_dense_gradient_is_one_voxel_central_difference():
 def test_l1_gradient_of_output_bias_closed_form():
     """Zero weights: d = sigmoid(b) for every point, so
     dL/db = mean(sign(d - t)) d (1 - d) and every other gradient is 0."""
-    spec = I.CFG1
+    spec = I.NET_SMALL
     w = np.zeros(spec.n_weights)
     w[-1] = 0.4
     net = make_net(spec, weights=w)
