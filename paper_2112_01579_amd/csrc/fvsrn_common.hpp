@@ -11,6 +11,7 @@ namespace fvsrn_detail {
 
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 typedef __bf16 b4 __attribute__((ext_vector_type(4)));
 typedef short s4 __attribute__((ext_vector_type(4)));
@@ -33,7 +34,7 @@ template <>
 struct PrecT<kF16> {
   using E = _Float16;
   static constexpr int KC = 32;  // K of the main MFMA step
-  static constexpr int KT = 16;  // K of the tail step (position + bias column)
+  static constexpr int KT = 8;   // input-row columns of the tail (x y z 1 0 0 0 0)
   using VA = h8;
   using VT = h4;
   __device__ static f4 mma(VA a, VA b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
@@ -44,7 +45,7 @@ template <>
 struct PrecT<kBF16> {
   using E = __bf16;
   static constexpr int KC = 32;
-  static constexpr int KT = 16;
+  static constexpr int KT = 8;
   using VA = b8;
   using VT = b4;
   __device__ static f4 mma(VA a, VA b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
@@ -70,7 +71,8 @@ struct PrecT<kF32> {
 // Layer 0's input row, one per sample, lives in LDS in the order
 //   [latent F | sin 3L | cos 3L | zero pad to KMAIN | x y z 1 | zero pad to KROW]
 // so its first KF columns are the packed FP32 inputs 3.. in order and the
-// constant-1 column carries the first layer's bias.
+// constant-1 column carries the first layer's bias. For FP16/BF16 the tail
+// (8 columns) is a K32 MFMA step whose A operand is zero beyond column 7.
 template <int P, int C, int F, int L>
 struct Geo {
   using PR = PrecT<P>;
@@ -81,14 +83,16 @@ struct Geo {
   static constexpr int KROW = KMAIN + PR::KT;
   static constexpr int S0 = KMAIN / PR::KC;               // main K steps of layer 0 (f16/bf16)
   static constexpr int Q0 = KROW / 4;                     // K4 steps of layer 0 (f32)
-  // LDS row stride: 16-byte reads of 8 consecutive rows land on distinct banks
-  static constexpr int ROW_DW = ((KROW * (int)sizeof(E) / 4 + 7) / 8) * 8 + 4;
+  // LDS row stride in dwords: the smallest >= the row with stride = 4 (mod 8),
+  // so that 16-byte reads of 8 consecutive rows land on distinct banks
+  static constexpr int RAW_DW = KROW * (int)sizeof(E) / 4;
+  static constexpr int ROW_DW = RAW_DW + ((4 - RAW_DW % 8) + 8) % 8;
   static constexpr int ROW = ROW_DW * 4 / (int)sizeof(E);  // elements
   static constexpr int HS32 = MT / 2, HS16 = MT % 2;      // K steps of a hidden layer (f16/bf16)
   static constexpr bool kF32Path = (P == kF32);
   // byte sizes of the staged weight regions (A fragments in lane order)
   static constexpr int W0A = kF32Path ? MT * Q0 * kWave * 4 : MT * S0 * kWave * 16;
-  static constexpr int W0T = kF32Path ? 0 : MT * kWave * 8;
+  static constexpr int W0T = kF32Path ? 0 : MT * kWave * 16;
   static constexpr int WHA = kF32Path ? MT * 4 * MT * kWave * 4 : MT * HS32 * kWave * 16;
   static constexpr int WHT = kF32Path ? 0 : MT * HS16 * kWave * 8;
   static constexpr int BH = C * 4;

@@ -18,11 +18,12 @@ namespace fvsrn_detail {
 
 namespace {
 
-// Value mode fits 3 waves per SIMD (<= 168 VGPRs); the gradient mode's
-// extra tangent state needs more registers and runs 2 per SIMD.
-template <bool GRAD>
+// Waves per workgroup cap (sets the VGPR budget through the launch bounds):
+// value mode with the packed FP16 latent path fits 4 waves per SIMD (<= 128
+// VGPRs), other value modes 3 (<= 168), gradient mode 2.
+template <bool GRAD, bool G16>
 constexpr int max_waves() {
-  return GRAD ? 8 : 12;
+  return GRAD ? 8 : (G16 ? 16 : 12);
 }
 constexpr int kLdsBytes = 160 * 1024;
 
@@ -31,8 +32,9 @@ constexpr int kLdsBytes = 160 * 1024;
 template <class CF, bool GRAD>
 int waves_per_block(int H) {
   using G = typename CF::G;
+  constexpr int cap = max_waves<GRAD, CF::G16>();
   const int w = (kLdsBytes - G::weight_bytes(H)) / G::FEAT_BYTES;
-  return w < 1 ? 0 : (w > max_waves<GRAD>() ? max_waves<GRAD>() : w);
+  return w < 1 ? 0 : (w > cap ? cap : w);
 }
 
 // ----------------------------------------------------- TF, camera, march
@@ -162,7 +164,7 @@ __device__ inline void composite(Accum& acc, const float rgba[4], float len) {
 // ------------------------------------------------------------- kernels
 
 template <class CF, bool GRAD>
-__global__ __launch_bounds__(max_waves<GRAD>() * 64) void march_kernel(NetDev nd, TFDev tf, ViewBatch vb, MarchDev m,
+__global__ __launch_bounds__((max_waves<GRAD, CF::G16>() * 64)) void march_kernel(NetDev nd, TFDev tf, ViewBatch vb, MarchDev m,
                                                                float* out, unsigned long long* stats,
                                                                int tiles_x, int tiles_y) {
   using G = typename CF::G;
@@ -251,7 +253,7 @@ __global__ __launch_bounds__(max_waves<GRAD>() * 64) void march_kernel(NetDev nd
 }
 
 template <class CF, bool GRAD>
-__global__ __launch_bounds__(max_waves<GRAD>() * 64) void points_kernel(NetDev nd, const float* xyz, long long n, int key,
+__global__ __launch_bounds__((max_waves<GRAD, CF::G16>() * 64)) void points_kernel(NetDev nd, const float* xyz, long long n, int key,
                                                                 float key_w, float* out_d, float* out_g) {
   using G = typename CF::G;
   using E = typename CF::E;
@@ -340,9 +342,9 @@ int launch_points_t(const NetDev& nd, const float* xyz, long long n, int key, fl
   return check_launch();
 }
 
-template <int C, int F, int L, int ACT, bool GRAD>
+template <int C, int F, int L, int ACT, bool GRAD, bool G16>
 struct Entry {
-  using CF = Cfg<FVSRN_PREC, C, F, L, ACT>;
+  using CF = Cfg<FVSRN_PREC, C, F, L, ACT, G16>;
   static int render(const NetDev& nd, const TFDev& tf, const ViewBatch& vb, const MarchDev& m, float* out,
                     unsigned long long* stats, hipStream_t st) {
     return launch_render_t<CF, GRAD>(nd, tf, vb, m, out, stats, st);
@@ -356,11 +358,18 @@ struct Entry {
 // Gradient mode is compiled for FP32 and FP16 networks.
 constexpr bool kGradCompiled = FVSRN_PREC != kBF16;
 
-#define FV_NETS(X, ACT, GRAD) \
-  X(32, 8, 4, ACT, GRAD)      \
-  X(32, 16, 8, ACT, GRAD)     \
-  X(48, 8, 4, ACT, GRAD)      \
-  X(48, 16, 8, ACT, GRAD)
+// The FP16 network has separate instantiations for FP16 and FP32 latent grids.
+#if FVSRN_PREC == 1
+#define FV_G16S(X, C, F, L, ACT, GRAD) X(C, F, L, ACT, GRAD, false) X(C, F, L, ACT, GRAD, true)
+#else
+#define FV_G16S(X, C, F, L, ACT, GRAD) X(C, F, L, ACT, GRAD, false)
+#endif
+
+#define FV_NETS(X, ACT, GRAD)           \
+  FV_G16S(X, 32, 8, 4, ACT, GRAD)       \
+  FV_G16S(X, 32, 16, 8, ACT, GRAD)      \
+  FV_G16S(X, 48, 8, 4, ACT, GRAD)       \
+  FV_G16S(X, 48, 16, 8, ACT, GRAD)
 
 #define FV_ALL(X)                \
   FV_NETS(X, kSine, false)       \
@@ -380,10 +389,11 @@ constexpr bool kGradCompiled = FVSRN_PREC != kBF16;
 int FV_PASTE(launch_render_p, FVSRN_PREC)(const NetDev& nd, const TFDev& tf, const ViewBatch& vb, const MarchDev& m,
                                           float* out, unsigned long long* stats, void* stream) {
   const bool grad = m.phong != 0;
+  const bool g16 = FVSRN_PREC == 1 && nd.grid_f16 != 0;
   const hipStream_t st = (hipStream_t)stream;
-#define X(C_, F_, L_, ACT_, GRAD_)                                               \
-  if (nd.C == C_ && nd.F == F_ && nd.L == L_ && nd.act == ACT_ && grad == GRAD_) \
-    return Entry<C_, F_, L_, ACT_, GRAD_>::render(nd, tf, vb, m, out, stats, st);
+#define X(C_, F_, L_, ACT_, GRAD_, G16_)                                                          \
+  if (nd.C == C_ && nd.F == F_ && nd.L == L_ && nd.act == ACT_ && grad == GRAD_ && g16 == G16_) \
+    return Entry<C_, F_, L_, ACT_, GRAD_, G16_>::render(nd, tf, vb, m, out, stats, st);
   FV_ALL(X)
 #if FVSRN_PREC != 2
   FV_ALL_GRAD(X)
@@ -396,10 +406,11 @@ int FV_PASTE(launch_render_p, FVSRN_PREC)(const NetDev& nd, const TFDev& tf, con
 int FV_PASTE(launch_points_p, FVSRN_PREC)(const NetDev& nd, const float* xyz, long long n, int key, float key_w,
                                           float* out_d, float* out_g, void* stream) {
   const bool grad = out_g != nullptr;
+  const bool g16 = FVSRN_PREC == 1 && nd.grid_f16 != 0;
   const hipStream_t st = (hipStream_t)stream;
-#define X(C_, F_, L_, ACT_, GRAD_)                                               \
-  if (nd.C == C_ && nd.F == F_ && nd.L == L_ && nd.act == ACT_ && grad == GRAD_) \
-    return Entry<C_, F_, L_, ACT_, GRAD_>::points(nd, xyz, n, key, key_w, out_d, out_g, st);
+#define X(C_, F_, L_, ACT_, GRAD_, G16_)                                                          \
+  if (nd.C == C_ && nd.F == F_ && nd.L == L_ && nd.act == ACT_ && grad == GRAD_ && g16 == G16_) \
+    return Entry<C_, F_, L_, ACT_, GRAD_, G16_>::points(nd, xyz, n, key, key_w, out_d, out_g, st);
   FV_ALL(X)
 #if FVSRN_PREC != 2
   FV_ALL_GRAD(X)

@@ -13,9 +13,13 @@
 
 namespace fvsrn_detail {
 
-template <int P_, int C_, int F_, int L_, int ACT_>
+// G16: the latent grid is FP16 and the network FP16, so the latent vector is
+// accumulated in packed FP16 (one gather path per instantiation keeps the
+// register peak down).
+template <int P_, int C_, int F_, int L_, int ACT_, bool G16_ = false>
 struct Cfg {
   static constexpr int P = P_, C = C_, F = F_, L = L_, ACT = ACT_;
+  static constexpr bool G16 = G16_;
   using G = Geo<P, C, F, L>;
   using E = typename G::E;
 };
@@ -106,10 +110,11 @@ __device__ void stage_weights(const NetDev& nd, char* smem) {
       const int j = e & 7, lane = (e >> 3) & 63, s = (e >> 9) % G::S0, mt = (e >> 9) / G::S0;
       W0A[e] = to_e<E>(w0(16 * mt + (lane & 15), 32 * s + 8 * (lane >> 4) + j));
     }
+    // tail step: K32 fragments over [x y z 1 0 0 0 0] (w0 is zero past column KMAIN + 3)
     E* W0T = reinterpret_cast<E*>(p + G::W0A);
-    for (int e = tid; e < MT * kWave * 4; e += nt) {
-      const int j = e & 3, lane = (e >> 2) & 63, mt = e >> 8;
-      W0T[e] = to_e<E>(w0(16 * mt + (lane & 15), G::KMAIN + 4 * (lane >> 4) + j));
+    for (int e = tid; e < MT * kWave * 8; e += nt) {
+      const int j = e & 7, lane = (e >> 3) & 63, mt = e >> 9;
+      W0T[e] = to_e<E>(w0(16 * mt + (lane & 15), G::KMAIN + 8 * (lane >> 4) + j));
     }
     p += G::W0A + G::W0T;
     for (int i = 1; i < H; ++i) {
@@ -246,6 +251,55 @@ __device__ inline void latent_column(const LatentSrc& ls, const LaneRole& role, 
   }
 }
 
+// FP16 variant of latent_column for an FP16 grid feeding an FP16 network:
+// the eight corner products are accumulated pairwise in packed FP16 (each
+// corner is one v_pk_fma per two channels) and land in the input row without
+// a conversion. The row is rounded to FP16 for the MFMA in any case.
+template <int F>
+__device__ inline void latent_column_h(const LatentSrc& ls, const LaneRole& role, float px, float py, float pz,
+                                       h2* z2) {
+  int ix, iy, iz;
+  float fx, fy, fz, dx, dy, dz;
+  axis_cell(px, ls.R, ix, fx, dx);
+  axis_cell(py, ls.R, iy, fy, dy);
+  axis_cell(pz, ls.R, iz, fz, dz);
+  const bool tx = !role.is_val && role.axis == 0, ty = !role.is_val && role.axis == 1,
+             tz = !role.is_val && role.axis == 2;
+  const float x0 = tx ? -dx : 1.0f - fx, x1 = tx ? dx : fx;
+  const float y0 = ty ? -dy : 1.0f - fy, y1 = ty ? dy : fy;
+  const float z0 = tz ? -dz : 1.0f - fz, z1 = tz ? dz : fz;
+  const unsigned R = (unsigned)ls.R;
+  const unsigned sx = F, sy = R * F, sz = R * R * F;
+  const unsigned base = (unsigned)iz * sz + (unsigned)iy * sy + (unsigned)ix * sx;
+  const unsigned off[8] = {base, base + sx, base + sy, base + sx + sy,
+                           base + sz, base + sz + sx, base + sz + sy, base + sz + sx + sy};
+  const float w[8] = {x0 * y0 * z0, x1 * y0 * z0, x0 * y1 * z0, x1 * y1 * z0,
+                      x0 * y0 * z1, x1 * y0 * z1, x0 * y1 * z1, x1 * y1 * z1};
+#pragma unroll
+  for (int j = 0; j < F / 2; ++j) z2[j] = h2{(_Float16)0.0f, (_Float16)0.0f};
+#pragma unroll
+  for (int key = 0; key < 2; ++key) {
+    const _Float16* g = reinterpret_cast<const _Float16*>(key == 0 ? ls.g0 : ls.g1);
+    if (key == 1 && !g) break;
+    const float kw = key == 0 ? ls.w0 : ls.w1;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const _Float16 wh = (_Float16)(w[c] * kw);
+      const h2 w2 = {wh, wh};
+      const uint4* src = reinterpret_cast<const uint4*>(g + off[c]);
+#pragma unroll
+      for (int q = 0; q < F / 8; ++q) {
+        const h8 hv = __builtin_bit_cast(h8, src[q]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const h2 v2 = {hv[2 * j], hv[2 * j + 1]};
+          z2[4 * q + j] = w2 * v2 + z2[4 * q + j];
+        }
+      }
+    }
+  }
+}
+
 // Builds this lane's input row at position p and writes it to `row` (LDS).
 template <class CF, bool GRAD>
 __device__ inline void write_features(typename CF::E* row, const LatentSrc& ls, const LaneRole& role, float px,
@@ -256,9 +310,18 @@ __device__ inline void write_features(typename CF::E* row, const LatentSrc& ls, 
   float v[G::KROW];
 #pragma unroll
   for (int j = 0; j < G::KROW; ++j) v[j] = 0.0f;
-  latent_column<F>(ls, role, px, py, pz, v);
-  // Fourier features sin/cos(pi 2^k p_a): the phase 2^(k-1) p_a in
-  // revolutions is an exact power-of-two scaling of p_a.
+  constexpr bool packed_latent = CF::P == kF16 && CF::G16;
+  h2 zh[F / 2];
+  if constexpr (packed_latent) {
+    latent_column_h<F>(ls, role, px, py, pz, zh);
+  } else {
+    latent_column<F>(ls, role, px, py, pz, v);
+  }
+  // Fourier features sin/cos(pi 2^k p_a). FP32 network: each octave from the
+  // exact power-of-two phase 2^(k-1) p_a (revolutions). FP16/BF16 networks:
+  // octave 0 directly, the others by the double-angle identities
+  // sin 2x = 2 sin x cos x, cos 2x = 1 - 2 sin^2 x (error ~2^k * 1e-7, far
+  // below the FP16 rounding of the row).
   const float pp[3] = {px, py, pz};
   float mv = 1.0f, ma[3] = {0.0f, 0.0f, 0.0f};
   if constexpr (GRAD) {
@@ -266,12 +329,32 @@ __device__ inline void write_features(typename CF::E* row, const LatentSrc& ls, 
 #pragma unroll
     for (int a = 0; a < 3; ++a) ma[a] = (!role.is_val && role.axis == a) ? 1.0f : 0.0f;
   }
+  float sd[3], cd[3];
+  if constexpr (CF::P != kF32) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      sd[a] = sin_rev(0.5f * pp[a]);
+      cd[a] = cos_rev(0.5f * pp[a]);
+    }
+  }
 #pragma unroll
   for (int k = 0; k < L; ++k) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const float ph = pp[a] * (float)(1 << k) * 0.5f;
-      const float s = sin_rev(ph), c = cos_rev(ph);
+      float s, c;
+      if constexpr (CF::P == kF32) {
+        const float ph = pp[a] * (float)(1 << k) * 0.5f;
+        s = sin_rev(ph);
+        c = cos_rev(ph);
+      } else {
+        s = sd[a];
+        c = cd[a];
+        if (k + 1 < L) {
+          const float s2 = s + s;
+          sd[a] = s2 * c;
+          cd[a] = fmaf(-s2, s, 1.0f);
+        }
+      }
       if constexpr (GRAD) {
         // d/dp_a sin(w p_a) = w cos(w p_a), d/dp_a cos(w p_a) = -w sin(w p_a)
         const float wm = kPi * (float)(1 << k) * ma[a];
@@ -304,8 +387,21 @@ __device__ inline void write_features(typename CF::E* row, const LatentSrc& ls, 
 #pragma unroll
     for (int q = 0; q < G::KROW / 8; ++q) {
       V8 x;
+      bool done = false;
+      if constexpr (packed_latent) {
+        if (q < F / 8) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) x[j] = to_e<E>(v[8 * q + j]);
+          for (int j = 0; j < 4; ++j) {
+            x[2 * j] = zh[4 * q + j][0];
+            x[2 * j + 1] = zh[4 * q + j][1];
+          }
+          done = true;
+        }
+      }
+      if (!done) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) x[j] = to_e<E>(v[8 * q + j]);
+      }
       dst[q] = x;
     }
   }
@@ -431,7 +527,7 @@ __device__ inline float mlp_tile(const char* wsm, const typename CF::E* feat, in
 #pragma unroll
     for (int u = 0; u < NT; ++u) out[u] = out_t[u] = zero;
     const VA* W0A = reinterpret_cast<const VA*>(wsm);
-    const VT* W0T = reinterpret_cast<const VT*>(wsm + G::W0A);
+    const VA* W0T = reinterpret_cast<const VA*>(wsm + G::W0A);
     for (int tp = 0; tp < 4; tp += NT) {
       f4 acc[NT][MT];
 #pragma unroll
@@ -452,18 +548,20 @@ __device__ inline float mlp_tile(const char* wsm, const typename CF::E* feat, in
         }
       }
       {
-        // The K16 tail gets its own accumulator: an MFMA never accumulates
-        // onto the result of an MFMA of a different shape (that dependency is
-        // not reliably interlocked); the two are summed on the VALU.
-        VT b[NT];
+        // Tail step [x y z 1 0 0 0 0] as one more K32 step on the same
+        // accumulators (lanes g > 0 read the same 8 columns; their A slots
+        // are zero). Keeping one MFMA shape per accumulator matters: a
+        // 16x16x32 result used as the accumulator of the next 16x16x16 MFMA
+        // is not reliably interlocked.
+        VA b[NT];
 #pragma unroll
         for (int u = 0; u < NT; ++u)
-          b[u] = *reinterpret_cast<const VT*>(feat + (16 * (tp + u) + n) * G::ROW + G::KMAIN + 4 * g);
+          b[u] = *reinterpret_cast<const VA*>(feat + (16 * (tp + u) + n) * G::ROW + G::KMAIN);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-          const VT a = W0T[mt * kWave + lane];
+          const VA a = W0T[mt * kWave + lane];
 #pragma unroll
-          for (int u = 0; u < NT; ++u) acc[u][mt] += PR::mmt(a, b[u], zero);
+          for (int u = 0; u < NT; ++u) acc[u][mt] = PR::mma(a, b[u], acc[u][mt]);
         }
       }
       const char* p = wsm + G::W0A + G::W0T;
