@@ -2,12 +2,14 @@
 """Benchmark of the fV-SRN ray-march hot path on one MI355X.
 
 Workload (the inference precision study): an fV-SRN with a 32^3 x 16 FP16
-latent grid, 8 Fourier octaves and 4 hidden layers of width 32 renders an
-8-view 1024x1024 perspective orbit with step 1/256 (two samples per voxel of
-the 256^3 reference volume) and early ray termination at 1e-3, all 8 views in
-one launch. One step = one such launch. The same frames are also timed with
-the FP32 and BF16 network paths and with plain dense-grid DVR of the 256^3
-synthetic Gaussian volume.
+latent grid, 8 Fourier octaves and 4 hidden layers of width 32, first fitted
+to a synthetic 256^3 volume (sum of 64 anisotropic Gaussians) by the
+library's trainer (L1 + Adam, 2^18 points per step), renders an 8-view
+1024x1024 perspective orbit with step 1/256 (two samples per voxel of the
+256^3 volume) and early ray termination at 1e-3, all 8 views in one launch.
+One step = one such launch. The same frames are also timed with the FP32 and
+BF16 network paths and with plain dense-grid DVR of the 256^3 volume, which
+is also the reference of the reported image RMSE.
 
 Prints one JSON line. ``value`` is network samples composited per second by
 the FP16-MFMA path, inputs resident in HBM.
@@ -79,6 +81,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--train-steps", type=int, default=2000,
+                    help="Adam steps (2^18 points each) fitting the network before timing")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the fV-SRN path is single-GPU (rays and points are "
@@ -92,7 +96,24 @@ def main():
     FV.lib()
     dev = torch.device("cuda:0")
     spec = I.NET_STUDY
+    vol = torch.from_numpy(I.gaussian_volume(256, 64, seed=I.SEED_STUDY)).to(dev)
     lat, w = I.net_params(spec, I.SEED_STUDY)
+    train_info = None
+    if args.train_steps > 0:
+        # fit the network to the dense volume with the library's own trainer
+        from paper_2112_01579_amd.trainer import Trainer
+        tnet = FV.Network(spec, lat, w, grid_dtype=FV.F32, device=dev)
+        tr = Trainer(tnet, vol, batch=1 << 18, seed=I.SEED_TRAIN)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.train_steps):
+            tr.step()
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        lat = tnet.latent.cpu().numpy().reshape(lat.shape)
+        w = tnet.weights.cpu().numpy()
+        train_info = {"steps": args.train_steps, "batch": 1 << 18, "final_l1": float(tr.loss.item()),
+                      "ms_per_step": t_train / args.train_steps * 1e3}
     net = FV.Network(spec, lat, w, grid_dtype=FV.F16, device=dev)
     net32 = FV.Network(spec, lat, w, grid_dtype=FV.F32, device=dev)
     tf = I.ramp_tf()
@@ -130,8 +151,10 @@ def main():
         "dtype": "f16",
         "data": "synthetic",
         "config": {
-            "workload": "fV-SRN 32^3x16 FP16 latent grid, 8 octaves, 4x32 sine MLP (seeded Xavier "
-                        "weights), 8-view 1024x1024 perspective orbit, step 1/256, ERT 1e-3, one launch",
+            "workload": "fV-SRN 32^3x16 FP16 latent grid, 8 octaves, 4x32 sine MLP fitted to a 256^3 "
+                        "sum of 64 Gaussians, 8-view 1024x1024 perspective orbit, step 1/256, ERT 1e-3, "
+                        "one launch",
+            "training": train_info,
             "views": len(cams), "width": 1024, "height": 1024, "step": 1 / 256, "ert_eps": 1e-3,
             "samples_per_step": samples, "rays_hit_per_step": rays,
             "tile_occupancy": samples / max(slots, 1),
@@ -151,19 +174,11 @@ def main():
 
     if not args.no_compare:
         comp = {}
-        for prec, n in (("f32", net32), ("bf16", net)):
-            stats.zero_()
-            step(n, prec)
-            torch.cuda.synchronize()
-            s = int(stats[0].item())
-            per_c, _ = time_launches(lambda: step(n, prec), max(3, args.steps // 4), 1)
-            ms = float(np.mean(per_c))
-            comp["fvsrn_" + prec] = {"ms_per_frame": ms / len(cams), "samples_per_s": s / (ms * 1e-3),
-                                     "tflops": s * fps / (ms * 1e-3) / 1e12}
-        vol = torch.from_numpy(I.gaussian_volume(256, 64, seed=I.SEED_STUDY)).to(dev)
+        # dense-grid DVR of the original 256^3 volume: the judge of image quality
+        ref = torch.empty_like(out)
 
         def dense():
-            FV.fvsrn_render_dense(vol, tf, cams, march, out=out, stats=stats)
+            FV.fvsrn_render_dense(vol, tf, cams, march, out=ref, stats=stats)
         stats.zero_()
         dense()
         torch.cuda.synchronize()
@@ -172,8 +187,23 @@ def main():
         ms = float(np.mean(per_c))
         comp["dense_dvr_256"] = {"ms_per_frame": ms / len(cams), "samples_per_s": s / (ms * 1e-3),
                                  "algorithmic_GBps": s * 32 / (ms * 1e-3) / 1e9}
+
+        def rmse(img):
+            return float(torch.sqrt(torch.mean((img - ref) ** 2)).item())
+        step()
+        torch.cuda.synchronize()
         comp["fvsrn_f16"] = {"ms_per_frame": ms_launch / len(cams), "samples_per_s": samples / (ms_launch * 1e-3),
-                             "tflops": achieved}
+                             "tflops": achieved, "image_rmse_vs_dense": rmse(out)}
+        for prec, n in (("f32", net32), ("bf16", net)):
+            stats.zero_()
+            step(n, prec)
+            torch.cuda.synchronize()
+            s = int(stats[0].item())
+            e = rmse(out)
+            per_c, _ = time_launches(lambda: step(n, prec), max(3, args.steps // 4), 1)
+            ms = float(np.mean(per_c))
+            comp["fvsrn_" + prec] = {"ms_per_frame": ms / len(cams), "samples_per_s": s / (ms * 1e-3),
+                                     "tflops": s * fps / (ms * 1e-3) / 1e12, "image_rmse_vs_dense": e}
         result["compare"] = comp
 
     if not args.no_cpu_baseline:
