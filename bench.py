@@ -58,6 +58,57 @@ def time_launches(fn, steps, warmup):
     return per, wall
 
 
+def kernel_source_hash() -> str:
+    """sha256 of the sources the render kernel is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("fvsrn_common.hpp", "fvsrn_net.hpp", "fvsrn_march.hip", "fvsrn_launch.h"):
+        with open(os.path.join(ROOT, "paper_2112_01579_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP16 render from the committed rocprofv3
+    counter record, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "march_f16_study_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_sha256") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def torch_layerwise(spec, lat, w, xyz, dtype):
+    """The same fV-SRN evaluated the way a framework would (the comparison of
+    Sec. 5.1): grid_sample for the latent vector, elementwise Fourier
+    features, one GEMM + activation per layer, every intermediate in HBM."""
+    import torch
+    import torch.nn.functional as Fn
+    dev = xyz.device
+    R, F = spec.R, spec.F
+    grid = torch.as_tensor(lat, device=dev).reshape(R, R, R, F).permute(3, 0, 1, 2).unsqueeze(0).to(dtype)
+    mats, off = [], 0
+    wt = torch.as_tensor(w, device=dev)
+    for o, i in spec.layer_shapes():
+        mats.append((wt[off:off + o * i].reshape(o, i).to(dtype), wt[off + o * i:off + o * i + o].to(dtype)))
+        off += o * i + o
+    k = torch.pi * (2.0 ** torch.arange(spec.L, device=dev, dtype=torch.float32))
+
+    def run():
+        z = Fn.grid_sample(grid, xyz.to(dtype).view(1, 1, 1, -1, 3), mode="bilinear", padding_mode="border",
+                           align_corners=True).view(F, -1).t()
+        ph = (xyz.unsqueeze(1) * k.view(1, -1, 1)).reshape(-1, 3 * spec.L)
+        h = torch.cat([xyz.to(dtype), z, torch.sin(ph).to(dtype), torch.cos(ph).to(dtype)], 1)
+        for i, (W, b) in enumerate(mats):
+            h = Fn.linear(h, W, b)
+            h = torch.sin(h) if i < len(mats) - 1 else torch.sigmoid(h)
+        return h
+    return run
+
+
 def cpu_baseline(spec, lat16, w, tf, cams, march):
     """The FP64 oracle on the host cores, on a 256x256 centre crop of view 0."""
     import oracle as O
@@ -81,12 +132,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device-to-device copy (reference for rocprofv3 byte counters)")
     ap.add_argument("--train-steps", type=int, default=2000,
                     help="Adam steps (2^18 points each) fitting the network before timing")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the fV-SRN path is single-GPU (rays and points are "
-              "independent; see DESIGN.md for how it would shard). Run with --gpus 1.", file=sys.stderr)
+              "independent). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -136,6 +189,8 @@ def main():
     ms_step = wall / args.steps
     fps = flops_per_sample(spec)
     achieved = samples * fps / (ms_launch * 1e-3) / 1e12
+    # unique bytes a launch must move: FP16 latent grid + FP32 weights in, RGBA image out
+    algo_bytes = net.latent.numel() * 2 + net.weights.numel() * 4 + out.numel() * 4
     result = {
         "metric": "ms/frame 1024^2 + samples/s: FP16-MFMA fV-SRN vs FP32 vs dense-grid DVR",
         "value": samples / (ms_step * 1e-3),
@@ -167,7 +222,9 @@ def main():
             "peak": P16_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / P16_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "algorithmic_bytes": algo_bytes,
             "launch_ms": ms_launch,
         },
     }
@@ -204,8 +261,46 @@ def main():
             ms = float(np.mean(per_c))
             comp["fvsrn_" + prec] = {"ms_per_frame": ms / len(cams), "samples_per_s": s / (ms * 1e-3),
                                      "tflops": s * fps / (ms * 1e-3) / 1e12, "image_rmse_vs_dense": e}
+        # gradient strategies for Phong shading (Sec. 6): no shading, forward
+        # mode, central differences with a one-voxel step of the 256^3 volume;
+        # image error against dense DVR shaded with one-voxel central differences
+        import dataclasses
+        shade = {}
+        m_dense = dataclasses.replace(march, phong=True)
+        FV.fvsrn_render_dense(vol, tf, cams, m_dense, out=ref)
+        for name, m in (("none", march), ("forward", m_dense),
+                        ("central", dataclasses.replace(m_dense, grad_mode=1, fd_step=2.0 / 255))):
+            FV.fvsrn_render(net, tf, cams, m, "f16", out=out)
+            torch.cuda.synchronize()
+            e = rmse(out)
+            per_c, _ = time_launches(lambda: FV.fvsrn_render(net, tf, cams, m, "f16", out=out), 3, 1)
+            shade[name] = {"ms_per_frame": float(np.mean(per_c)) / len(cams)}
+            if m.phong:
+                shade[name]["image_rmse_vs_dense_phong"] = e
+        shade["central_over_forward"] = shade["central"]["ms_per_frame"] / shade["forward"]["ms_per_frame"]
+        comp["shading_f16"] = shade
+        # fused point evaluation vs the framework-style layer-by-layer network (2^24 points)
+        npts = 1 << 24
+        xyz = torch.rand((npts, 3), device=dev) * 2 - 1
+        dens = torch.empty(npts, device=dev)
+        for prec, n in (("f32", net32), ("f16", net)):
+            per_c, _ = time_launches(lambda: FV.fvsrn_eval_points(n, xyz, 0.0, prec, out=dens), 5, 1)
+            comp["eval_points_fused_" + prec] = {"points_per_s": npts / (float(np.mean(per_c)) * 1e-3)}
+        for name, dt in (("f32", torch.float32), ("f16", torch.float16)):
+            run = torch_layerwise(spec, lat, w, xyz, dt)
+            per_c, _ = time_launches(run, 3, 1)
+            pts = npts / (float(np.mean(per_c)) * 1e-3)
+            comp["eval_points_torch_layerwise_" + name] = {
+                "points_per_s": pts,
+                "fused_speedup": comp["eval_points_fused_" + name]["points_per_s"] / pts}
         result["compare"] = comp
 
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        result["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(spec, lat.astype(np.float16), w, tf, cams, march)
     print(json.dumps(result))

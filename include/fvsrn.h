@@ -62,7 +62,8 @@ typedef enum { FVSRN_ACT_SINE = 0, FVSRN_ACT_SNAKEALT = 1, FVSRN_ACT_IDENTITY = 
 
 /* Network and latent-grid shape (Sec. 3, Sec. 4.2). Supported: F in {8, 16},
    L in {4, 8} with (F, L) = (8, 4) or (16, 8); c in {32, 48}; 1 <= H <= 8;
-   2 <= R <= 512; 1 <= K <= 64. */
+   2 <= R <= 512 with one keyframe grid (R^3 F elements) below 2^31 bytes;
+   1 <= K <= 64. */
 typedef struct {
   int32_t grid_res;      /* R: latent vertices per axis */
   int32_t grid_channels; /* F: latent channels */
@@ -118,23 +119,35 @@ typedef struct {
    march stops after a sample once T < ert_eps (0 disables early ray
    termination). phong != 0 shades rgb with a headlight Blinn-Phong term from
    the normalized density gradient n: rgb (ka + kd |n.l|) + ks |n.l|^shininess
-   (Sec. 6), gradients below 1e-6 in length leave rgb unshaded. */
+   (Sec. 6), gradients below 1e-6 in length leave rgb unshaded. For the
+   network, grad_mode selects how the gradient is obtained (Sec. 6):
+   FVSRN_GRAD_FORWARD differentiates the network in forward mode;
+   FVSRN_GRAD_CENTRAL takes central differences of the network density with
+   step fd_step (> 0, world units): seven network evaluations per sample.
+   Dense-grid rendering always uses one-voxel central differences. */
+typedef enum { FVSRN_GRAD_FORWARD = 0, FVSRN_GRAD_CENTRAL = 1 } fvsrn_grad_mode;
 typedef struct {
   float step;
   int32_t fixed_steps;
   float ert_eps;
   int32_t phong;
   float ka, kd, ks, shininess;
+  int32_t grad_mode;
+  float fd_step;
 } fvsrn_march;
 
 /* Render n_views images of the fV-SRN with one launch (Sec. 4, Sec. 5.1):
    out_rgba [n_views][H][W][4] FP32, premultiplied colour and opacity over a
    transparent background. All cameras must share width and height.
    stats (nullable, device, 3 x u64, accumulated -- the caller zeroes it):
-   [0] += samples composited, [1] += rays that hit the domain, [2] += network
-   evaluation slots issued (lanes x march steps, idle lanes included; [0]/[2]
-   is the occupancy of the matrix tiles). Phong shading needs the density
-   gradient, computed by forward-mode differentiation (Sec. 6). */
+   [0] += samples composited, [1] += rays that hit the domain, [2] += sample
+   slots issued (rays per wave x march steps of the wave, idle rays included;
+   [0]/[2] is the occupancy of the matrix tiles). A wave marches 64 rays
+   without shading, 16 with forward-mode gradients and 8 with central
+   differences. Phong shading needs the density gradient, obtained as
+   march->grad_mode selects (Sec. 6). Central differences are built for the
+   sine activation and FP32/FP16 networks; other combinations return
+   FVSRN_ERR_UNSUPPORTED. */
 fvsrn_status fvsrn_render(const fvsrn_net_desc* desc, const fvsrn_params* params,
                           const fvsrn_tf* tf, const fvsrn_camera* cams, int32_t n_views,
                           const fvsrn_march* march, float* out_rgba,

@@ -58,7 +58,8 @@ class _Cam(C.Structure):
 class _March(C.Structure):
     _fields_ = [("step", C.c_double), ("fixed_steps", C.c_int32), ("phong", C.c_int32),
                 ("ert_eps", C.c_double), ("ka", C.c_double), ("kd", C.c_double),
-                ("ks", C.c_double), ("shininess", C.c_double)]
+                ("ks", C.c_double), ("shininess", C.c_double), ("grad_fd", C.c_int32),
+                ("pad_", C.c_int32), ("fd_step", C.c_double)]
 
 
 class _Field(C.Structure):
@@ -247,7 +248,7 @@ def box_clip(o, d):
 
 def _march_struct(m):
     return _March(m.step, m.fixed_steps, 1 if m.phong else 0, m.ert_eps, m.ka, m.kd, m.ks,
-                  m.shininess)
+                  m.shininess, 1 if m.grad_mode == 1 else 0, 0, m.fd_step)
 
 
 class Field:

@@ -507,7 +507,21 @@ static void render_pixel(const orc_field* field, const orc_tf* tf, const orc_cam
     double tm = 0.5 * (a0 + a1);
     double p[3] = {o[0] + tm * dir[0], o[1] + tm * dir[1], o[2] + tm * dir[2]};
     double g[3];
-    double d = orc_field_density(field, p, cam->time, m->phong ? g : NULL);
+    double d;
+    if (m->phong && m->grad_fd && field->kind == ORC_FIELD_NET) {
+      /* finite differences of the network density: the centre and six
+         central-difference samples, seven evaluations (Sec. 6) */
+      d = orc_density(field->net, p, cam->time);
+      for (int a = 0; a < 3; ++a) {
+        double pp[3] = {p[0], p[1], p[2]}, pm[3] = {p[0], p[1], p[2]};
+        pp[a] += m->fd_step;
+        pm[a] -= m->fd_step;
+        g[a] = (orc_density(field->net, pp, cam->time) - orc_density(field->net, pm, cam->time)) /
+               (2.0 * m->fd_step);
+      }
+    } else {
+      d = orc_field_density(field, p, cam->time, m->phong ? g : NULL);
+    }
     double rgba[4];
     orc_tf_eval(tf, d, rgba);
     if (m->phong) {

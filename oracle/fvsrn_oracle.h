@@ -68,6 +68,10 @@ typedef struct {
   int32_t phong;            /* 1: shade with the density gradient */
   double ert_eps;           /* stop once transmittance < eps (0 = never) */
   double ka, kd, ks, shininess;
+  int32_t grad_fd;          /* network field: 0 = analytic (forward mode),
+                               1 = central differences with step fd_step */
+  int32_t pad_;
+  double fd_step;
 } orc_march;
 
 /* Source of density for the renderer. */

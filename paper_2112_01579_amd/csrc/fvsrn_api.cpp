@@ -51,6 +51,12 @@ fvsrn_status check_desc(const fvsrn_net_desc* d) {
   if (d->hidden_width != 32 && d->hidden_width != 48)
     return fail(FVSRN_ERR_UNSUPPORTED, "hidden_width %d not compiled; supported 32, 48", d->hidden_width);
   if (d->hidden_layers > 8) return fail(FVSRN_ERR_UNSUPPORTED, "hidden_layers %d > 8", d->hidden_layers);
+  // the kernels address one keyframe grid with 32-bit byte offsets
+  const long long grid_bytes = (long long)d->grid_res * d->grid_res * d->grid_res * d->grid_channels *
+                               (d->grid_dtype == FVSRN_F16 ? 2 : 4);
+  if (grid_bytes >= (1LL << 31))
+    return fail(FVSRN_ERR_UNSUPPORTED, "one keyframe's latent grid is %lld bytes; at most 2^31 - 1 supported",
+                grid_bytes);
   return FVSRN_OK;
 }
 
@@ -177,6 +183,10 @@ fvsrn_status check_cams(const fvsrn_camera* cams, int32_t n_views, const fvsrn_m
   if (m->fixed_steps == 0 && !(m->step >= 1.0f / 65536.0f))
     return fail(FVSRN_ERR_INVALID_ARGUMENT, "step must be >= 2^-16 world units");
   if (!(m->ert_eps >= 0.0f) || m->ert_eps > 1.0f) return fail(FVSRN_ERR_INVALID_ARGUMENT, "ert_eps outside [0, 1]");
+  if (m->grad_mode != FVSRN_GRAD_FORWARD && m->grad_mode != FVSRN_GRAD_CENTRAL)
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "grad_mode unknown");
+  if (m->phong && m->grad_mode == FVSRN_GRAD_CENTRAL && !(m->fd_step > 0.0f && m->fd_step < 1.0f))
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "fd_step must be in (0, 1) for central differences");
   return FVSRN_OK;
 }
 
@@ -190,6 +200,8 @@ MarchDev make_march(const fvsrn_march* m) {
   o.kd = m->kd;
   o.ks = m->ks;
   o.shininess = m->shininess;
+  o.grad_mode = m->grad_mode;
+  o.fd_step = m->fd_step;
   return o;
 }
 

@@ -36,6 +36,8 @@ struct MarchDev {
   float ert_eps;
   int phong;
   float ka, kd, ks, shininess;
+  int grad_mode;  // 0 forward mode, 1 central differences (network renders)
+  float fd_step;
 };
 
 struct NetDev {

@@ -2,8 +2,10 @@
 // precision (compiled once per precision with FVSRN_PREC = 0 FP32, 1 FP16,
 // 2 BF16).
 //
-// Render: one wavefront owns a tile of rays -- 8x8 pixels in value mode, 4x4
-// pixels (four lanes per ray) in gradient mode. Per march step every lane
+// Render: one wavefront owns a tile of rays -- 8x8 pixels without shading,
+// 4x4 pixels (four lanes per ray: value and three tangents) for forward-mode
+// gradients, 4x2 pixels (eight lanes per ray: centre and six central-difference
+// neighbours) for finite-difference gradients. Per march step every lane
 // builds its input row, the wave runs the MLP on the matrix cores, and the
 // ray-owning lanes map the density through the transfer function and
 // composite front to back (Sec. 3, Sec. 4), stopping when the transmittance
@@ -18,21 +20,42 @@ namespace fvsrn_detail {
 
 namespace {
 
+// Shading modes of the render kernel: none, forward-mode gradient, central
+// differences (Sec. 6).
+enum { kShadeNone = 0, kShadeFwd = 1, kShadeFD = 2 };
+
 // Waves per workgroup cap (sets the VGPR budget through the launch bounds):
-// value mode with the packed FP16 latent path fits 4 waves per SIMD (<= 128
-// VGPRs), other value modes 3 (<= 168), gradient mode 2.
-template <bool GRAD, bool G16>
+// value-mode networks with the packed FP16 latent path fit 4 waves per SIMD
+// (<= 128 VGPRs), other value-mode networks 3 (<= 168), forward mode 2.
+// Central differences add the neighbour offsets and the gradient gather to
+// the value-mode network; with F = 16 channels gathered in FP32 (c = 48, or
+// an FP16 network on an FP32 grid) that needs 2 waves per SIMD, c = 48 with
+// the packed latent path 3.
+template <class CF, int MODE>
 constexpr int max_waves() {
-  return GRAD ? 8 : (G16 ? 16 : 12);
+  if (MODE == kShadeFwd) return 8;
+  if (MODE == kShadeFD) {
+    if (CF::F == 16 && (CF::C == 48 || (CF::P == kF16 && !CF::G16))) return 8;
+    return (CF::G16 && CF::C == 32) ? 16 : 12;
+  }
+  return CF::G16 ? 16 : 12;
 }
+
+// Render tile geometry per shading mode: lanes per ray and tile edges.
+template <int MODE>
+struct TileShape {
+  static constexpr int LPR = MODE == kShadeNone ? 1 : (MODE == kShadeFwd ? 4 : 8);
+  static constexpr int TW = MODE == kShadeNone ? 8 : 4;
+  static constexpr int TH = 64 / LPR / TW;
+};
 constexpr int kLdsBytes = 160 * 1024;
 
 // Waves per workgroup: as many as the LDS holds (weights once plus one input
 // tile per wave), at most max_waves.
-template <class CF, bool GRAD>
+template <class CF, int MODE>
 int waves_per_block(int H) {
   using G = typename CF::G;
-  constexpr int cap = max_waves<GRAD, CF::G16>();
+  constexpr int cap = max_waves<CF, MODE>();
   const int w = (kLdsBytes - G::weight_bytes(H)) / G::FEAT_BYTES;
   return w < 1 ? 0 : (w > cap ? cap : w);
 }
@@ -123,15 +146,6 @@ __device__ inline void segment(const Ray& r, int i, bool fixed, float& tm, float
   tm = 0.5f * (a0 + a1);
 }
 
-// Blocks are dealt round-robin to the 8 XCDs; remap so that each XCD works
-// on one contiguous range of tiles (neighbouring screen regions share its L2).
-__device__ inline int xcd_block(int nblocks) {
-  const int b = blockIdx.x;
-  if (nblocks % 8 != 0) return b;
-  const int per = nblocks / 8;
-  return (b % 8) * per + b / 8;
-}
-
 // Headlight Blinn-Phong (Sec. 6): light and view along -dir, normal = the
 // normalized density gradient.
 __device__ inline void phong(float rgba[4], float gx, float gy, float gz, const float dir[3], const MarchDev& m) {
@@ -163,97 +177,126 @@ __device__ inline void composite(Accum& acc, const float rgba[4], float len) {
 
 // ------------------------------------------------------------- kernels
 
-template <class CF, bool GRAD>
-__global__ __launch_bounds__((max_waves<GRAD, CF::G16>() * 64)) void march_kernel(NetDev nd, TFDev tf, ViewBatch vb, MarchDev m,
-                                                               float* out, unsigned long long* stats,
-                                                               int tiles_x, int tiles_y) {
+// Persistent: each wave walks its own sequence of tiles until the batch is
+// done (a workgroup holds its LDS until its last wave finishes, so one tile
+// per wave would leave SIMD slots idle behind long rays). Tiles are dealt
+// round-robin over all waves of the grid, so every wave's share mixes all
+// views and screen regions and the per-wave work evens out; the latent grid
+// (a few MiB at most) is resident in every XCD's L2, so no XCD-local tile
+// ranges are needed here.
+template <class CF, int MODE>
+__global__ __launch_bounds__((max_waves<CF, MODE>() * 64)) void march_kernel(NetDev nd, TFDev tf, ViewBatch vb,
+                                                                                  MarchDev m, float* out,
+                                                                                  unsigned long long* stats,
+                                                                                  int tiles_x, int tiles_y) {
   using G = typename CF::G;
   using E = typename CF::E;
-  constexpr int TW = GRAD ? 4 : 8;  // tile edge in pixels
+  constexpr bool GRAD = MODE == kShadeFwd;  // network run in forward (tangent) mode
+  constexpr bool FD = MODE == kShadeFD;
+  constexpr int LPR = TileShape<MODE>::LPR, TW = TileShape<MODE>::TW;
   extern __shared__ __attribute__((aligned(16))) char smem[];
   stage_weights<CF>(nd, smem);
   __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the wave index is wave-uniform; saying so keeps the tile, its camera and
+  // the latent grid's buffer resource in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int wpb = blockDim.x >> 6;
   const int tiles_per_view = tiles_x * tiles_y;
-  const int tile = xcd_block(gridDim.x) * (int)(blockDim.x >> 6) + wave;
-  if (tile >= tiles_per_view * vb.n_views) return;
-  const int v = tile / tiles_per_view;
-  const int tr = tile % tiles_per_view;
-  const int rl = GRAD ? lane >> 2 : lane;  // ray within the tile
-  const int px = (tr % tiles_x) * TW + (rl % TW);
-  const int py = (tr / tiles_x) * TW + (rl / TW);
-  const LaneRole role = GRAD ? grad_role(lane & 3) : value_role();
-  const CamDev& cam = vb.cam[v];
-  const LatentSrc ls = make_latent_src(nd, cam.key, cam.key_w);
-  const bool in_img = px < vb.width && py < vb.height;
-  const Ray ray = make_ray(cam, in_img ? px : 0, in_img ? py : 0, vb.width, vb.height, m);
-  bool active = in_img && ray.hit && ray.nseg > 0;
+  const int n_tiles = tiles_per_view * vb.n_views;
+  const int n_waves = gridDim.x * wpb;
+  const int rl = lane / LPR;  // ray within the tile
+  const int q = lane % LPR;   // role of the lane within its ray
+  const LaneRole role = GRAD ? grad_role(q) : value_role();
+  // central differences: lane q = 1..6 evaluates the sample moved by +-h along
+  // axis (q-1)/2 (odd q: +h); q = 0 and 7 evaluate the sample itself
+  const float fh = (q & 1) ? m.fd_step : -m.fd_step;
+  const float fd_off[3] = {FD && (q == 1 || q == 2) ? fh : 0.0f, FD && (q == 3 || q == 4) ? fh : 0.0f,
+                           FD && (q == 5 || q == 6) ? fh : 0.0f};
+  const float inv_2h = FD ? 0.5f / m.fd_step : 0.0f;
   const bool fixed = m.fixed_steps > 0;
   E* feat = reinterpret_cast<E*>(smem + G::weight_bytes(nd.H) + wave * G::FEAT_BYTES);
   E* myrow = feat + lane * G::ROW;
-  Accum acc = {1.0f, {0.0f, 0.0f, 0.0f}, 0.0f};
-  int i = 0;
-  unsigned long long iters = 0;
-  while (__builtin_amdgcn_ballot_w64(active)) {
-    ++iters;
-    float tm, len;
-    segment(ray, i, fixed, tm, len);
-    if (!active) tm = 0.0f;
-    const float sx = active ? ray.o[0] + tm * ray.d[0] : 0.0f;
-    const float sy = active ? ray.o[1] + tm * ray.d[1] : 0.0f;
-    const float sz = active ? ray.o[2] + tm * ray.d[2] : 0.0f;
-    write_features<CF, GRAD>(myrow, ls, role, sx, sy, sz);
-    wave_lds_sync();
-    const float y = mlp_tile<CF, GRAD>(smem, feat, nd.H, role);
-    wave_lds_sync();
-    float dens, gx = 0.0f, gy = 0.0f, gz = 0.0f;
-    if constexpr (GRAD) {
-      // the quad's value lane holds the logit, lanes 1..3 its derivatives
-      const float y0 = quad_bcast0(y);
-      const float t1 = quad_bcast<1>(y), t2 = quad_bcast<2>(y), t3 = quad_bcast<3>(y);
-      dens = sigmoid_f(y0);
-      const float s = dens * (1.0f - dens);
-      gx = s * t1;
-      gy = s * t2;
-      gz = s * t3;
-    } else {
-      dens = sigmoid_f(y);
-    }
-    if (active) {
-      if (len <= 0.0f) {
-        active = false;
+  unsigned long long n_samp = 0, n_hit = 0, iters = 0;
+  for (int tile = blockIdx.x * wpb + wave; tile < n_tiles; tile += n_waves) {
+    const int v = tile / tiles_per_view;
+    const int tr = tile % tiles_per_view;
+    const int px = (tr % tiles_x) * TW + (rl % TW);
+    const int py = (tr / tiles_x) * TileShape<MODE>::TH + (rl / TW);
+    const CamDev& cam = vb.cam[v];
+    const LatentSrc ls = make_latent_src(nd, cam.key, cam.key_w);
+    const bool in_img = px < vb.width && py < vb.height;
+    const Ray ray = make_ray(cam, in_img ? px : 0, in_img ? py : 0, vb.width, vb.height, m);
+    bool active = in_img && ray.hit && ray.nseg > 0;
+    Accum acc = {1.0f, {0.0f, 0.0f, 0.0f}, 0.0f};
+    int i = 0;
+    while (__builtin_amdgcn_ballot_w64(active)) {
+      ++iters;
+      float tm, len;
+      segment(ray, i, fixed, tm, len);
+      const float sx = active ? ray.o[0] + tm * ray.d[0] + fd_off[0] : 0.0f;
+      const float sy = active ? ray.o[1] + tm * ray.d[1] + fd_off[1] : 0.0f;
+      const float sz = active ? ray.o[2] + tm * ray.d[2] + fd_off[2] : 0.0f;
+      write_features<CF, GRAD>(myrow, ls, role, sx, sy, sz);
+      wave_lds_sync();
+      const float y = mlp_tile<CF, GRAD>(smem, feat, nd.H, role);
+      wave_lds_sync();
+      float dens, gx = 0.0f, gy = 0.0f, gz = 0.0f;
+      if constexpr (GRAD) {
+        // the quad's value lane holds the logit, lanes 1..3 its derivatives
+        const float y0 = quad_bcast0(y);
+        const float t1 = quad_bcast<1>(y), t2 = quad_bcast<2>(y), t3 = quad_bcast<3>(y);
+        dens = sigmoid_f(y0);
+        const float sg = dens * (1.0f - dens);
+        gx = sg * t1;
+        gy = sg * t2;
+        gz = sg * t3;
+      } else if constexpr (FD) {
+        // gather the seven densities of the ray's lane group
+        const float dl = sigmoid_f(y);
+        const int b = lane & ~7;
+        dens = __shfl(dl, b, 64);
+        gx = (__shfl(dl, b + 1, 64) - __shfl(dl, b + 2, 64)) * inv_2h;
+        gy = (__shfl(dl, b + 3, 64) - __shfl(dl, b + 4, 64)) * inv_2h;
+        gz = (__shfl(dl, b + 5, 64) - __shfl(dl, b + 6, 64)) * inv_2h;
       } else {
-        float rgba[4];
-        tf_eval(tf, dens, rgba);
-        if (m.phong) phong(rgba, gx, gy, gz, ray.d, m);
-        composite(acc, rgba, len);
-        ++i;
-        if (acc.T < m.ert_eps || i >= ray.nseg) active = false;
+        dens = sigmoid_f(y);
+      }
+      if (active) {
+        if (len <= 0.0f) {
+          active = false;
+        } else {
+          float rgba[4];
+          tf_eval(tf, dens, rgba);
+          if (m.phong) phong(rgba, gx, gy, gz, ray.d, m);
+          composite(acc, rgba, len);
+          ++i;
+          if (acc.T < m.ert_eps || i >= ray.nseg) active = false;
+        }
       }
     }
-  }
-  const bool owner = GRAD ? (lane & 3) == 0 : true;
-  if (in_img && owner) {
-    float4* o = reinterpret_cast<float4*>(out) + ((long long)v * vb.height + py) * vb.width + px;
-    *o = make_float4(acc.C[0], acc.C[1], acc.C[2], acc.A);
+    const bool owner = q == 0;
+    if (in_img && owner) {
+      float4* o = reinterpret_cast<float4*>(out) + ((long long)v * vb.height + py) * vb.width + px;
+      *o = make_float4(acc.C[0], acc.C[1], acc.C[2], acc.A);
+    }
+    n_samp += owner ? (unsigned long long)i : 0ull;
+    n_hit += (owner && in_img && ray.hit && ray.nseg > 0) ? 1ull : 0ull;
   }
   if (stats) {
-    unsigned long long mine = owner ? (unsigned long long)i : 0ull;
-    unsigned long long hit = (owner && in_img && ray.hit && ray.nseg > 0) ? 1ull : 0ull;
     for (int off = 32; off > 0; off >>= 1) {
-      mine += __shfl_xor(mine, off, 64);
-      hit += __shfl_xor(hit, off, 64);
+      n_samp += __shfl_xor(n_samp, off, 64);
+      n_hit += __shfl_xor(n_hit, off, 64);
     }
-    if (lane == 0) {
-      atomicAdd(stats, mine);
-      atomicAdd(stats + 1, hit);
-      atomicAdd(stats + 2, iters * (GRAD ? 16ull : 64ull));
+    if (lane == 0 && (n_samp | n_hit | iters)) {
+      atomicAdd(stats, n_samp);
+      atomicAdd(stats + 1, n_hit);
+      atomicAdd(stats + 2, iters * (unsigned long long)(64 / LPR));
     }
   }
 }
 
 template <class CF, bool GRAD>
-__global__ __launch_bounds__((max_waves<GRAD, CF::G16>() * 64)) void points_kernel(NetDev nd, const float* xyz, long long n, int key,
+__global__ __launch_bounds__((max_waves<CF, GRAD ? kShadeFwd : kShadeNone>() * 64)) void points_kernel(NetDev nd, const float* xyz, long long n, int key,
                                                                 float key_w, float* out_d, float* out_g) {
   using G = typename CF::G;
   using E = typename CF::E;
@@ -298,25 +341,32 @@ __global__ __launch_bounds__((max_waves<GRAD, CF::G16>() * 64)) void points_kern
 
 // ------------------------------------------------------------ launchers
 
-template <class CF, bool GRAD>
+template <class CF, int MODE>
 int launch_render_t(const NetDev& nd, const TFDev& tf, const ViewBatch& vb, const MarchDev& m, float* out,
                     unsigned long long* stats, hipStream_t st) {
   using G = typename CF::G;
-  constexpr int TW = GRAD ? 4 : 8;
-  const int tx = (vb.width + TW - 1) / TW, ty = (vb.height + TW - 1) / TW;
+  constexpr int TW = TileShape<MODE>::TW, TH = TileShape<MODE>::TH;
+  const int tx = (vb.width + TW - 1) / TW, ty = (vb.height + TH - 1) / TH;
   const long long tiles = (long long)tx * ty * vb.n_views;
-  const int wpb = waves_per_block<CF, GRAD>(nd.H);
+  if (tiles > 0x7fffffffLL) return 1;
+  const int wpb = waves_per_block<CF, MODE>(nd.H);
   if (wpb < 1) return 1;
-  long long blocks = (tiles + wpb - 1) / wpb;
-  if (blocks % 8) blocks += 8 - blocks % 8;
   const size_t shm = (size_t)G::weight_bytes(nd.H) + (size_t)wpb * G::FEAT_BYTES;
+  // persistent grid: as many workgroups as fit on the device at once (LDS and
+  // the 32-wave-per-CU limit), never more than the tiles need
+  long long per_cu = (long long)(kLdsBytes / shm);
+  if (per_cu * wpb > 32) per_cu = 32 / wpb;
+  if (per_cu < 1) per_cu = 1;
+  long long blocks = (long long)device_cus() * per_cu;
+  const long long need = (tiles + wpb - 1) / wpb;
+  if (blocks > need) blocks = need;
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute((const void*)march_kernel<CF, GRAD>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)march_kernel<CF, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kLdsBytes);
     attr = true;
   }
-  hipLaunchKernelGGL((march_kernel<CF, GRAD>), dim3((unsigned)blocks), dim3(wpb * 64), shm, st, nd, tf, vb, m, out,
+  hipLaunchKernelGGL((march_kernel<CF, MODE>), dim3((unsigned)blocks), dim3(wpb * 64), shm, st, nd, tf, vb, m, out,
                      stats, tx, ty);
   return check_launch();
 }
@@ -326,7 +376,7 @@ int launch_points_t(const NetDev& nd, const float* xyz, long long n, int key, fl
                     float* out_g, hipStream_t st) {
   using G = typename CF::G;
   constexpr int PER = GRAD ? 16 : 64;
-  const int wpb = waves_per_block<CF, GRAD>(nd.H);
+  const int wpb = waves_per_block<CF, GRAD ? kShadeFwd : kShadeNone>(nd.H);
   if (wpb < 1) return 1;
   const size_t shm = (size_t)G::weight_bytes(nd.H) + (size_t)wpb * G::FEAT_BYTES;
   static bool attr = false;
@@ -342,44 +392,46 @@ int launch_points_t(const NetDev& nd, const float* xyz, long long n, int key, fl
   return check_launch();
 }
 
-template <int C, int F, int L, int ACT, bool GRAD, bool G16>
+template <int C, int F, int L, int ACT, int MODE, bool G16>
 struct Entry {
   using CF = Cfg<FVSRN_PREC, C, F, L, ACT, G16>;
   static int render(const NetDev& nd, const TFDev& tf, const ViewBatch& vb, const MarchDev& m, float* out,
                     unsigned long long* stats, hipStream_t st) {
-    return launch_render_t<CF, GRAD>(nd, tf, vb, m, out, stats, st);
+    return launch_render_t<CF, MODE>(nd, tf, vb, m, out, stats, st);
   }
   static int points(const NetDev& nd, const float* xyz, long long n, int key, float key_w, float* out_d,
                     float* out_g, hipStream_t st) {
-    return launch_points_t<CF, GRAD>(nd, xyz, n, key, key_w, out_d, out_g, st);
+    return launch_points_t<CF, MODE == kShadeFwd>(nd, xyz, n, key, key_w, out_d, out_g, st);
   }
 };
 
-// Gradient mode is compiled for FP32 and FP16 networks.
-constexpr bool kGradCompiled = FVSRN_PREC != kBF16;
+// Gradient modes are compiled for FP32 and FP16 networks; central differences
+// for the sine activation only.
 
 // The FP16 network has separate instantiations for FP16 and FP32 latent grids.
 #if FVSRN_PREC == 1
-#define FV_G16S(X, C, F, L, ACT, GRAD) X(C, F, L, ACT, GRAD, false) X(C, F, L, ACT, GRAD, true)
+#define FV_G16S(X, C, F, L, ACT, MODE) X(C, F, L, ACT, MODE, false) X(C, F, L, ACT, MODE, true)
 #else
-#define FV_G16S(X, C, F, L, ACT, GRAD) X(C, F, L, ACT, GRAD, false)
+#define FV_G16S(X, C, F, L, ACT, MODE) X(C, F, L, ACT, MODE, false)
 #endif
 
-#define FV_NETS(X, ACT, GRAD)           \
-  FV_G16S(X, 32, 8, 4, ACT, GRAD)       \
-  FV_G16S(X, 32, 16, 8, ACT, GRAD)      \
-  FV_G16S(X, 48, 8, 4, ACT, GRAD)       \
-  FV_G16S(X, 48, 16, 8, ACT, GRAD)
+#define FV_NETS(X, ACT, MODE)           \
+  FV_G16S(X, 32, 8, 4, ACT, MODE)       \
+  FV_G16S(X, 32, 16, 8, ACT, MODE)      \
+  FV_G16S(X, 48, 8, 4, ACT, MODE)       \
+  FV_G16S(X, 48, 16, 8, ACT, MODE)
 
-#define FV_ALL(X)                \
-  FV_NETS(X, kSine, false)       \
-  FV_NETS(X, kSnakeAlt, false)   \
-  FV_NETS(X, kIdentity, false)
+#define FV_ALL(X)                    \
+  FV_NETS(X, kSine, kShadeNone)      \
+  FV_NETS(X, kSnakeAlt, kShadeNone)  \
+  FV_NETS(X, kIdentity, kShadeNone)
 
-#define FV_ALL_GRAD(X)           \
-  FV_NETS(X, kSine, true)        \
-  FV_NETS(X, kSnakeAlt, true)    \
-  FV_NETS(X, kIdentity, true)
+#define FV_ALL_GRAD(X)              \
+  FV_NETS(X, kSine, kShadeFwd)      \
+  FV_NETS(X, kSnakeAlt, kShadeFwd)  \
+  FV_NETS(X, kIdentity, kShadeFwd)
+
+#define FV_ALL_FD(X) FV_NETS(X, kSine, kShadeFD)
 
 }  // namespace
 
@@ -388,29 +440,29 @@ constexpr bool kGradCompiled = FVSRN_PREC != kBF16;
 
 int FV_PASTE(launch_render_p, FVSRN_PREC)(const NetDev& nd, const TFDev& tf, const ViewBatch& vb, const MarchDev& m,
                                           float* out, unsigned long long* stats, void* stream) {
-  const bool grad = m.phong != 0;
+  const int mode = !m.phong ? kShadeNone : (m.grad_mode == 1 ? kShadeFD : kShadeFwd);
   const bool g16 = FVSRN_PREC == 1 && nd.grid_f16 != 0;
   const hipStream_t st = (hipStream_t)stream;
-#define X(C_, F_, L_, ACT_, GRAD_, G16_)                                                          \
-  if (nd.C == C_ && nd.F == F_ && nd.L == L_ && nd.act == ACT_ && grad == GRAD_ && g16 == G16_) \
-    return Entry<C_, F_, L_, ACT_, GRAD_, G16_>::render(nd, tf, vb, m, out, stats, st);
+#define X(C_, F_, L_, ACT_, MODE_, G16_)                                                          \
+  if (nd.C == C_ && nd.F == F_ && nd.L == L_ && nd.act == ACT_ && mode == MODE_ && g16 == G16_) \
+    return Entry<C_, F_, L_, ACT_, MODE_, G16_>::render(nd, tf, vb, m, out, stats, st);
   FV_ALL(X)
 #if FVSRN_PREC != 2
   FV_ALL_GRAD(X)
+  FV_ALL_FD(X)
 #endif
 #undef X
-  (void)kGradCompiled;
   return 1;
 }
 
 int FV_PASTE(launch_points_p, FVSRN_PREC)(const NetDev& nd, const float* xyz, long long n, int key, float key_w,
                                           float* out_d, float* out_g, void* stream) {
-  const bool grad = out_g != nullptr;
+  const int mode = out_g != nullptr ? kShadeFwd : kShadeNone;
   const bool g16 = FVSRN_PREC == 1 && nd.grid_f16 != 0;
   const hipStream_t st = (hipStream_t)stream;
-#define X(C_, F_, L_, ACT_, GRAD_, G16_)                                                          \
-  if (nd.C == C_ && nd.F == F_ && nd.L == L_ && nd.act == ACT_ && grad == GRAD_ && g16 == G16_) \
-    return Entry<C_, F_, L_, ACT_, GRAD_, G16_>::points(nd, xyz, n, key, key_w, out_d, out_g, st);
+#define X(C_, F_, L_, ACT_, MODE_, G16_)                                                          \
+  if (nd.C == C_ && nd.F == F_ && nd.L == L_ && nd.act == ACT_ && mode == MODE_ && g16 == G16_) \
+    return Entry<C_, F_, L_, ACT_, MODE_, G16_>::points(nd, xyz, n, key, key_w, out_d, out_g, st);
   FV_ALL(X)
 #if FVSRN_PREC != 2
   FV_ALL_GRAD(X)

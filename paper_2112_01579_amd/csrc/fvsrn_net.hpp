@@ -67,8 +67,13 @@ __device__ void stage_weights(const NetDev& nd, char* smem) {
   auto off_layer = [&](int i) -> long long {  // W_i for 1 <= i <= H
     return (long long)C * K0 + C + (long long)(i - 1) * (C * C + C);
   };
+  // FP16/BF16 networks receive 2 cos(.) in the Fourier cosine block (see
+  // write_features); their cosine columns carry half the weight.
   auto w0 = [&](int o, int col) -> float {
-    if (col < G::KF) return w[(long long)o * K0 + 3 + col] * sc;
+    if (col < G::KF) {
+      const float half = (CF::P != kF32 && col >= F + 3 * L) ? 0.5f : 1.0f;
+      return w[(long long)o * K0 + 3 + col] * sc * half;
+    }
     if (col < G::KMAIN) return 0.0f;
     const int t = col - G::KMAIN;
     if (t < 3) return w[(long long)o * K0 + t] * sc;
@@ -168,7 +173,20 @@ struct LatentSrc {
   float w0, w1;
   int R;
   bool f16;
+  unsigned bytes;  // one keyframe grid (< 2^31, checked by the host)
 };
+
+// Buffer resource over one keyframe grid. The corner fetches then address
+// the grid as (per-lane cell offset) + (wave-uniform corner offset, held in
+// an SGPR) + (immediate for the second 16 bytes), so a sample's eight corners
+// cost no per-lane address arithmetic beyond the cell offset.
+__device__ inline __amdgpu_buffer_rsrc_t grid_rsrc(const void* g, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(g), 0, (int)bytes, 0x00020000);
+}
+
+__device__ inline uint4 load16(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
 
 __device__ inline LatentSrc make_latent_src(const NetDev& nd, int key, float key_w) {
   LatentSrc s;
@@ -180,35 +198,45 @@ __device__ inline LatentSrc make_latent_src(const NetDev& nd, int key, float key
   s.w1 = key_w;
   s.R = nd.R;
   s.f16 = nd.grid_f16 != 0;
+  s.bytes = (unsigned)((size_t)nd.key_stride * esz);
   return s;
+}
+
+// Corner offsets of a cell in elements: x fastest, then y, then z.
+__device__ inline void corner_offsets(unsigned sx, unsigned sy, unsigned sz, unsigned off[8]) {
+  off[0] = 0;
+  off[1] = sx;
+  off[2] = sy;
+  off[3] = sx + sy;
+  off[4] = sz;
+  off[5] = sz + sx;
+  off[6] = sz + sy;
+  off[7] = sz + sx + sy;
 }
 
 // z += w * G[corner][0..F) for the 8 corners of the cell at offset `base`.
 template <int F>
-__device__ inline void gather8(const void* grid, bool f16, unsigned base, unsigned sx, unsigned sy, unsigned sz,
-                               const float w[8], float* z) {
-  const unsigned off[8] = {base, base + sx, base + sy, base + sx + sy,
-                           base + sz, base + sz + sx, base + sz + sy, base + sz + sx + sy};
+__device__ inline void gather8(const void* grid, bool f16, unsigned bytes, unsigned base, unsigned sx, unsigned sy,
+                               unsigned sz, const float w[8], float* z) {
+  unsigned off[8];
+  corner_offsets(sx, sy, sz, off);
+  const __amdgpu_buffer_rsrc_t r = grid_rsrc(grid, bytes);
   if (f16) {
-    const _Float16* g = reinterpret_cast<const _Float16*>(grid);
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-      const uint4* src = reinterpret_cast<const uint4*>(g + off[c]);
 #pragma unroll
       for (int q = 0; q < F / 8; ++q) {
-        const h8 hv = __builtin_bit_cast(h8, src[q]);
+        const h8 hv = __builtin_bit_cast(h8, load16(r, base * 2u + 16u * q, off[c] * 2u));
 #pragma unroll
         for (int j = 0; j < 8; ++j) z[8 * q + j] = fmaf(w[c], (float)hv[j], z[8 * q + j]);
       }
     }
   } else {
-    const float* g = reinterpret_cast<const float*>(grid);
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-      const float4* src = reinterpret_cast<const float4*>(g + off[c]);
 #pragma unroll
       for (int q = 0; q < F / 4; ++q) {
-        const float4 v = src[q];
+        const float4 v = __builtin_bit_cast(float4, load16(r, base * 4u + 16u * q, off[c] * 4u));
         z[4 * q + 0] = fmaf(w[c], v.x, z[4 * q + 0]);
         z[4 * q + 1] = fmaf(w[c], v.y, z[4 * q + 1]);
         z[4 * q + 2] = fmaf(w[c], v.z, z[4 * q + 2]);
@@ -243,11 +271,11 @@ __device__ inline void latent_column(const LatentSrc& ls, const LaneRole& role, 
   float wa[8];
 #pragma unroll
   for (int c = 0; c < 8; ++c) wa[c] = w[c] * ls.w0;
-  gather8<F>(ls.g0, ls.f16, base, sx, sy, sz, wa, z);
+  gather8<F>(ls.g0, ls.f16, ls.bytes, base, sx, sy, sz, wa, z);
   if (ls.g1) {
 #pragma unroll
     for (int c = 0; c < 8; ++c) wa[c] = w[c] * ls.w1;
-    gather8<F>(ls.g1, ls.f16, base, sx, sy, sz, wa, z);
+    gather8<F>(ls.g1, ls.f16, ls.bytes, base, sx, sy, sz, wa, z);
   }
 }
 
@@ -271,25 +299,25 @@ __device__ inline void latent_column_h(const LatentSrc& ls, const LaneRole& role
   const unsigned R = (unsigned)ls.R;
   const unsigned sx = F, sy = R * F, sz = R * R * F;
   const unsigned base = (unsigned)iz * sz + (unsigned)iy * sy + (unsigned)ix * sx;
-  const unsigned off[8] = {base, base + sx, base + sy, base + sx + sy,
-                           base + sz, base + sz + sx, base + sz + sy, base + sz + sx + sy};
+  unsigned off[8];
+  corner_offsets(sx, sy, sz, off);
   const float w[8] = {x0 * y0 * z0, x1 * y0 * z0, x0 * y1 * z0, x1 * y1 * z0,
                       x0 * y0 * z1, x1 * y0 * z1, x0 * y1 * z1, x1 * y1 * z1};
 #pragma unroll
   for (int j = 0; j < F / 2; ++j) z2[j] = h2{(_Float16)0.0f, (_Float16)0.0f};
 #pragma unroll
   for (int key = 0; key < 2; ++key) {
-    const _Float16* g = reinterpret_cast<const _Float16*>(key == 0 ? ls.g0 : ls.g1);
+    const void* g = key == 0 ? ls.g0 : ls.g1;
     if (key == 1 && !g) break;
+    const __amdgpu_buffer_rsrc_t r = grid_rsrc(g, ls.bytes);
     const float kw = key == 0 ? ls.w0 : ls.w1;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const _Float16 wh = (_Float16)(w[c] * kw);
       const h2 w2 = {wh, wh};
-      const uint4* src = reinterpret_cast<const uint4*>(g + off[c]);
 #pragma unroll
       for (int q = 0; q < F / 8; ++q) {
-        const h8 hv = __builtin_bit_cast(h8, src[q]);
+        const h8 hv = __builtin_bit_cast(h8, load16(r, base * 2u + 16u * q, off[c] * 2u));
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const h2 v2 = {hv[2 * j], hv[2 * j + 1]};
@@ -319,9 +347,11 @@ __device__ inline void write_features(typename CF::E* row, const LatentSrc& ls, 
   }
   // Fourier features sin/cos(pi 2^k p_a). FP32 network: each octave from the
   // exact power-of-two phase 2^(k-1) p_a (revolutions). FP16/BF16 networks:
-  // octave 0 directly, the others by the double-angle identities
-  // sin 2x = 2 sin x cos x, cos 2x = 1 - 2 sin^2 x (error ~2^k * 1e-7, far
-  // below the FP16 rounding of the row).
+  // octave 0 directly, the others by the double-angle identities written for
+  // g = 2 cos x: sin 2x = sin x * g, g(2x) = g^2 - 2 -- one multiply and one
+  // FMA per octave (error ~2^k * 1e-7, far below the FP16 rounding of the
+  // row). The row then holds 2 cos in the cosine block; the staged weights of
+  // those columns are halved.
   const float pp[3] = {px, py, pz};
   float mv = 1.0f, ma[3] = {0.0f, 0.0f, 0.0f};
   if constexpr (GRAD) {
@@ -329,37 +359,37 @@ __device__ inline void write_features(typename CF::E* row, const LatentSrc& ls, 
 #pragma unroll
     for (int a = 0; a < 3; ++a) ma[a] = (!role.is_val && role.axis == a) ? 1.0f : 0.0f;
   }
-  float sd[3], cd[3];
+  constexpr float cs = CF::P == kF32 ? 1.0f : 2.0f;  // scale of the cosine block
+  float sd[3], gd[3];
   if constexpr (CF::P != kF32) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       sd[a] = sin_rev(0.5f * pp[a]);
-      cd[a] = cos_rev(0.5f * pp[a]);
+      gd[a] = 2.0f * cos_rev(0.5f * pp[a]);
     }
   }
 #pragma unroll
   for (int k = 0; k < L; ++k) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      float s, c;
+      float s, c;  // sin and cs * cos of the octave's phase
       if constexpr (CF::P == kF32) {
         const float ph = pp[a] * (float)(1 << k) * 0.5f;
         s = sin_rev(ph);
         c = cos_rev(ph);
       } else {
         s = sd[a];
-        c = cd[a];
+        c = gd[a];
         if (k + 1 < L) {
-          const float s2 = s + s;
-          sd[a] = s2 * c;
-          cd[a] = fmaf(-s2, s, 1.0f);
+          sd[a] = s * c;
+          gd[a] = fmaf(c, c, -2.0f);
         }
       }
       if constexpr (GRAD) {
         // d/dp_a sin(w p_a) = w cos(w p_a), d/dp_a cos(w p_a) = -w sin(w p_a)
         const float wm = kPi * (float)(1 << k) * ma[a];
-        v[F + 3 * k + a] = fmaf(c, wm, s * mv);
-        v[F + 3 * L + 3 * k + a] = fmaf(-s, wm, c * mv);
+        v[F + 3 * k + a] = fmaf(c, wm * (1.0f / cs), s * mv);
+        v[F + 3 * L + 3 * k + a] = fmaf(-s, wm * cs, c * mv);
       } else {
         v[F + 3 * k + a] = s;
         v[F + 3 * L + 3 * k + a] = c;

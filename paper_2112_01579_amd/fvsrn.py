@@ -62,7 +62,7 @@ class CameraStruct(C.Structure):
 class MarchStruct(C.Structure):
     _fields_ = [("step", C.c_float), ("fixed_steps", C.c_int32), ("ert_eps", C.c_float),
                 ("phong", C.c_int32), ("ka", C.c_float), ("kd", C.c_float), ("ks", C.c_float),
-                ("shininess", C.c_float)]
+                ("shininess", C.c_float), ("grad_mode", C.c_int32), ("fd_step", C.c_float)]
 
 
 class AdamStruct(C.Structure):
@@ -153,7 +153,7 @@ def camera_structs(cams: Sequence[I.Camera]):
 
 def march_struct(m: I.March) -> MarchStruct:
     return MarchStruct(m.step, m.fixed_steps, m.ert_eps, 1 if m.phong else 0, m.ka, m.kd, m.ks,
-                       m.shininess)
+                       m.shininess, m.grad_mode, m.fd_step)
 
 
 class Network:

@@ -95,6 +95,8 @@ class March:
     kd: float = 0.7
     ks: float = 0.2
     shininess: float = 32.0
+    grad_mode: int = 0      # Phong gradient: 0 forward mode, 1 central differences
+    fd_step: float = 0.0    # central-difference step (world units)
 
 
 # ------------------------------------------------------- random parameters

@@ -77,6 +77,9 @@ def test_render_argument_errors():
     assert _render(_desc(grid_res=1)) == FV.ERR_INVALID_ARGUMENT
     assert _render(_desc(hidden_width=40)) == FV.ERR_UNSUPPORTED
     assert _render(_desc(grid_channels=16)) == FV.ERR_UNSUPPORTED      # (16, 4) not compiled
+    # one keyframe grid must stay below 2^31 bytes (512^3 x 8 FP32 = 4 GiB)
+    assert _render(_desc(grid_res=512)) == FV.ERR_UNSUPPORTED
+    assert b"2^31" in L.fvsrn_last_error()
     assert _render(_desc(precision=7)) == FV.ERR_INVALID_ARGUMENT
     assert _render(_desc(activation=9)) == FV.ERR_INVALID_ARGUMENT
     assert _render(_desc(), p=_params(lat=0)) == FV.ERR_INVALID_ARGUMENT
@@ -94,6 +97,12 @@ def test_render_argument_errors():
     assert _render(_desc(), m=m) == FV.ERR_INVALID_ARGUMENT
     m = FV.march_struct(I.March(step=0.1, ert_eps=-1.0))
     assert _render(_desc(), m=m) == FV.ERR_INVALID_ARGUMENT
+    m = FV.march_struct(I.March(step=0.1, grad_mode=5))
+    assert _render(_desc(), m=m) == FV.ERR_INVALID_ARGUMENT
+    for h in (0.0, -0.1, 1.5, float("nan")):
+        m = FV.march_struct(I.March(step=0.1, phong=True, grad_mode=1, fd_step=h))
+        assert _render(_desc(), m=m) == FV.ERR_INVALID_ARGUMENT
+        assert b"fd_step" in L.fvsrn_last_error()
     # time-varying needs ascending key times
     d = _desc(num_keyframes=2)
     kt = (C.c_float * 2)(1.0, 1.0)

@@ -338,6 +338,30 @@ def test_grad_points_edge_sizes(FV):
         assert _grad_err(g.cpu().numpy(), gref) <= 1e-4
 
 
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_phong_render_central_differences(FV, prec):
+    """Phong shading from central differences of the network (Sec. 6: seven
+    evaluations per sample), c = 32 and c = 48 networks, ragged views. The
+    density error e of the precision enters each gradient component as at
+    most e/h, so the FP16 tolerance scales FP16's by 1/h relative to the
+    one-voxel step; FP32 keeps the forward-mode bound."""
+    h = 1.0 / 32
+    for spec, seed in ((I.NET_SHADED, I.SEED_SHADED), (I.NET_STUDY, I.SEED_STUDY)):
+        gnet, onet = _nets(FV, spec, seed)
+        tf = I.ramp_tf()
+        cams = I.orbit_cameras(2, 21, 13)
+        m = I.March(step=1 / 96, ert_eps=0.0, phong=True, grad_mode=1, fd_step=h)
+        ref, ns = O.render(O.Field(net=onet), tf, cams, m)
+        stats = torch.zeros(3, dtype=torch.int64, device="cuda")
+        img = FV.fvsrn_render(gnet, tf, cams, m, prec, stats=stats).cpu().numpy()
+        err = np.abs(img - ref).max()
+        _report("phong FD c=%d %s" % (spec.c, prec), err)
+        assert err <= (1e-4 if prec == "f32" else 10 * FP16_TOL)
+        assert abs(stats[0].item() - ns) <= 0.001 * ns
+        # eight evaluation lanes per ray sample
+        assert stats[2].item() % 8 == 0
+
+
 @pytest.mark.parametrize("prec,tol", [("f32", 1e-4), ("f16", FP16_TOL)])
 def test_phong_render(FV, prec, tol):
     """shaded network (64^3 x 16 grid, 4 x 48) with headlight Phong from

@@ -588,6 +588,29 @@ def test_phong_headlight_closed_form():
     np.testing.assert_allclose(img[0, ..., :3], np.repeat(0.6 * m.ka * img[0, ..., 3:4], 3, -1), rtol=1e-12)
 
 
+def test_fd_shading_converges_to_forward_mode_at_second_order():
+    """Central-difference shading (Sec. 6: the centre plus six neighbours) of a
+    network tends to the forward-mode gradient shading as h -> 0, and its
+    truncation error is O(h^2): halving h quarters the image difference. A
+    wrong sign, axis or step factor in the difference breaks the limit; a
+    one-sided difference breaks the order."""
+    spec = I.NetSpec(R=6, F=4, L=2, c=8, H=2)
+    lat, w = I.net_params(spec, 77)
+    net = O.Net(spec, lat, w)
+    tf = I.ramp_tf()
+    cams = I.orbit_cameras(1, 7, 5)
+    base = I.March(step=0.05, phong=True)
+    ref, n_ref = O.render(O.Field(net=net), tf, cams, base)
+    errs = []
+    for h in (1e-2, 5e-3, 1e-5):
+        img, n = O.render(O.Field(net=net), tf, cams, dataclasses_replace(base, grad_mode=1, fd_step=h))
+        assert n == n_ref
+        errs.append(np.abs(img - ref).max())
+    assert errs[2] < 1e-8
+    assert errs[0] > 1e-7
+    assert 3.0 < errs[0] / errs[1] < 5.0, errs
+
+
 def test_render_time_uses_interpolated_latent():
     """The network is linear in the latent vector's source grid only through
     interpolation: rendering a 2-keyframe net at time t equals rendering a
