@@ -7,7 +7,9 @@ utility kernels into one shared library.
 from __future__ import annotations
 
 import concurrent.futures as cf
+import glob
 import os
+import re
 import subprocess
 import sys
 
@@ -47,10 +49,118 @@ def _sources():
     return out
 
 
-def _run(cmd):
-    res = subprocess.run(cmd, capture_output=True, text=True)
+def _run(cmd, cwd=None):
+    res = subprocess.run(cmd, capture_output=True, text=True, cwd=cwd)
     text = "\n".join(l for l in (res.stdout + res.stderr).splitlines() if "packed-fp32-ops" not in l)
     return res.returncode, text
+
+
+_REG = re.compile(r"([va])\[(\d+):(\d+)\]|([va])(\d+)$")
+
+
+def _reg_range(tok):
+    m = _REG.match(tok.strip())
+    if not m:
+        return None
+    if m.group(1):
+        return m.group(1), int(m.group(2)), int(m.group(3))
+    return m.group(4), int(m.group(5)), int(m.group(5))
+
+
+def mfma_partial_overlaps(asm: str):
+    """MFMA instructions of a gfx950 assembly listing whose result registers
+    partially overlap their accumulator input (equal or disjoint is fine).
+    Returns (function, line) pairs."""
+    bad, fn = [], "?"
+    for line in asm.splitlines():
+        if line.startswith("_Z") and ":" in line:
+            fn = line.split(":", 1)[0]
+        if "v_mfma" not in line:
+            continue
+        ops = line.strip().split(None, 1)[1].split(";")[0].split(",")
+        if len(ops) < 4:
+            continue
+        d, c = _reg_range(ops[0]), _reg_range(ops[3])
+        if d and c and d[0] == c[0] and (d[1], d[2]) != (c[1], c[2]) and not (d[2] < c[1] or c[2] < d[1]):
+            bad.append((fn, line.strip()))
+    return bad
+
+
+_VMEM = ("global_", "buffer_", "flat_", "scratch_")
+_REGS = re.compile(r"\b([va])\[(\d+):(\d+)\]|\b([va])(\d+)\b")
+
+
+def _reg_set(text):
+    out = set()
+    for m in _REGS.finditer(text):
+        if m.group(1):
+            out |= {(m.group(1), i) for i in range(int(m.group(2)), int(m.group(3)) + 1)}
+        else:
+            out.add((m.group(4), int(m.group(5))))
+    return out
+
+
+def mfma_early_vmem_reads(asm: str):
+    """Memory instructions that read an MFMA result fewer wait states after
+    the MFMA than the result needs (passes + 3: 11 for the 16x16 shapes, 19
+    for 32x32), on any path through the listing's branches (one function or
+    several). The compiler pads VALU and LDS readers of MFMA results, but a
+    global store of a result reached through a taken branch was issued right
+    after the MFMA. Returns (function, mfma, reader) triples."""
+    funcs, cur = [], None
+    for line in asm.splitlines():
+        if line.startswith("_Z") and ":" in line:
+            cur = (line.split(":", 1)[0], [])
+            funcs.append(cur)
+        elif cur is not None:
+            cur[1].append(line)
+    bad = []
+    for fn, lines in funcs:
+        ins, labels = [], {}
+        for raw in lines:
+            l = raw.split(";")[0].rstrip()
+            if not l.strip():
+                continue
+            m = re.match(r"^(\.LBB\w+):", l)
+            if m:
+                labels[m.group(1)] = len(ins)
+            elif l[0].isspace() and not l.strip().startswith("."):
+                t = l.strip()
+                op = t.split()[0]
+                ins.append((op, t[len(op):]))
+        for i, (op, rest) in enumerate(ins):
+            if not op.startswith("v_mfma"):
+                continue
+            dst = _reg_set(rest.split(",")[0])
+            need = 19 if "32x32" in op else 11
+            stack, seen = [(i + 1, 0)], set()
+            while stack:
+                j, w = stack.pop()
+                while j < len(ins) and w < need and (j, w) not in seen:
+                    seen.add((j, w))
+                    o, r = ins[j]
+                    # registers the memory instruction reads: a load's first
+                    # operand is its destination
+                    src = r.split(",", 1)[1] if ("_load" in o and "," in r) else r
+                    if o.startswith(_VMEM) and _reg_set(src) & dst:
+                        bad.append((fn, "%s%s" % ins[i], "%s%s" % ins[j]))
+                        break
+                    if o.startswith("v_mfma") and _reg_set(r.split(",")[0]) >= dst:
+                        break
+                    w += int(r.strip(), 0) + 1 if o == "s_nop" else 1
+                    if o == "s_branch":
+                        j = labels[r.strip()]
+                        continue
+                    if o.startswith("s_cbranch"):
+                        stack.append((labels[r.strip()], w))
+                    if o in ("s_endpgm", "s_setpc_b64"):
+                        break
+                    j += 1
+    return bad
+
+
+def device_asm_files():
+    return sorted(glob.glob(os.path.join(BUILD, "*", "*-hip-amdgcn-amd-amdhsa-gfx950.s")))
 
 
 def build(force: bool = True, verbose: bool = False, jobs: int = 0) -> str:
@@ -62,16 +172,36 @@ def build(force: bool = True, verbose: bool = False, jobs: int = 0) -> str:
     units = [u for u in UNITS if os.path.exists(os.path.join(CSRC, u[0]))]
     cmds = []
     for src, defs, obj in units:
-        cmds.append([hipcc()] + HIPCC_FLAGS + defs + ["-I", os.path.join(ROOT, "include"), "-c",
-                                                      os.path.join(CSRC, src), "-o", os.path.join(BUILD, obj)])
+        # each unit keeps its intermediate files (device assembly included) in
+        # a folder of its own
+        tmp = os.path.join(BUILD, obj[:-2])
+        os.makedirs(tmp, exist_ok=True)
+        extra = ["-save-temps=cwd"] if src.endswith(".hip") else []
+        cmds.append(([hipcc()] + HIPCC_FLAGS + defs + extra + ["-I", os.path.join(ROOT, "include"), "-c",
+                                                               os.path.join(CSRC, src), "-o",
+                                                               os.path.join(BUILD, obj)], tmp))
     jobs = jobs or min(len(cmds), os.cpu_count() or 1)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        results = list(ex.map(_run, cmds))
+        results = list(ex.map(lambda c: _run(c[0], cwd=c[1]), cmds))
     for (src, _, obj), (rc, text) in zip(units, results):
         if rc != 0:
             raise RuntimeError("hipcc failed on %s:\n%s" % (src, text))
         if verbose and text.strip():
             print(text, file=sys.stderr)
+    # refuse a library with MFMA placements that gave wrong results on gfx950:
+    # result registers partially overlapping the accumulator input, and
+    # memory instructions reading a result before it is complete
+    for path in device_asm_files():
+        with open(path) as fh:
+            text = fh.read()
+        bad = mfma_partial_overlaps(text)
+        if bad:
+            raise RuntimeError("%s: MFMA result partially overlaps its accumulator:\n%s" %
+                               (path, "\n".join("%s: %s" % b for b in bad[:10])))
+        bad = mfma_early_vmem_reads(text)
+        if bad:
+            raise RuntimeError("%s: memory instruction reads an MFMA result too early:\n%s" %
+                               (path, "\n".join("%s: %s -> %s" % b for b in bad[:10])))
     tmp = LIB + ".tmp%d" % os.getpid()
     rc, text = _run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] +
                     [os.path.join(BUILD, u[2]) for u in units])

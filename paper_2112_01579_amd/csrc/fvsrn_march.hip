@@ -233,9 +233,15 @@ __global__ __launch_bounds__((max_waves<CF, MODE>() * 64)) void march_kernel(Net
       ++iters;
       float tm, len;
       segment(ray, i, fixed, tm, len);
-      const float sx = active ? ray.o[0] + tm * ray.d[0] + fd_off[0] : 0.0f;
-      const float sy = active ? ray.o[1] + tm * ray.d[1] + fd_off[1] : 0.0f;
-      const float sz = active ? ray.o[2] + tm * ray.d[2] + fd_off[2] : 0.0f;
+      float sx = ray.o[0] + tm * ray.d[0], sy = ray.o[1] + tm * ray.d[1], sz = ray.o[2] + tm * ray.d[2];
+      if constexpr (FD) {
+        sx += fd_off[0];
+        sy += fd_off[1];
+        sz += fd_off[2];
+      }
+      sx = active ? sx : 0.0f;
+      sy = active ? sy : 0.0f;
+      sz = active ? sz : 0.0f;
       write_features<CF, GRAD>(myrow, ls, role, sx, sy, sz);
       wave_lds_sync();
       const float y = mlp_tile<CF, GRAD>(smem, feat, nd.H, role);

@@ -1,42 +1,48 @@
 // Training step of the fV-SRN (world-space fitting with L1 loss and Adam,
 // Sec. 3 and Sec. 5), FP32 throughout.
 //
-// fwd_bwd_kernel: each wave takes chunks of 64 points (fixed, grid-independent
-// assignment: chunk c goes to wave c mod n_waves). Per chunk:
+// fwd_bwd_kernel: each wave takes chunks of S = 16 points (fixed,
+// grid-independent assignment: chunk c goes to wave c mod n_waves; one MFMA
+// N-tile per chunk keeps the per-wave LDS small enough for six waves per CU).
+// Per chunk:
 //   1. every lane writes its point's input row to LDS (as in evaluation);
 //   2. forward through the layers on 16x16x4 FP32 MFMA, keeping every
 //      pre-activation a_i in LDS (sample-major);
 //   3. output sigmoid, loss and dL/dy;
 //   4. backward: delta_i = (W_{i+1}^T delta_{i+1}) * act'(a_i) on MFMA with
 //      transposed weight fragments; dW_i = delta_i h_i^T as an MFMA GEMM over
-//      the 64 samples (A = delta, B = layer input, both read from LDS);
+//      the chunk's samples (A = delta, B = layer input, both read from LDS);
 //   5. dL/dz = W_0[:, latent]^T delta_0, scattered into the latent gradient
 //      with the trilinear weights (hardware float atomics).
 // dW tiles are added into the wave's private workspace slice (no atomics, so
-// dW is bitwise reproducible). reduce_kernel then sums the slices in a fixed
-// order into the packed gradient; adam_kernel applies the update.
+// dW is bitwise reproducible). slice_sum_kernel and gather_kernel then sum the
+// slices in a fixed order into the packed gradient; adam_kernel applies the
+// update.
 #include "fvsrn_net.hpp"
 
 namespace fvsrn_detail {
 
 namespace {
 
-constexpr int kTrainMaxWaves = 1024;  // fixed number of waves (deterministic partition)
+constexpr int kTrainMaxWaves = 2048;  // fixed number of waves (deterministic partition)
+constexpr int kTrainWavesPerBlock = 8;
 
 template <int C, int F, int L, int ACT>
 struct TrainCfg {
   using CF = Cfg<kF32, C, F, L, ACT>;
   using G = typename CF::G;
+  static constexpr int S = 16;                      // points per wave chunk (one N-tile)
+  static constexpr int NTC = S / 16;
   static constexpr int MT = G::MT;
   static constexpr int NK0 = (G::KROW + 15) / 16;   // N-tiles of layer 0's input row
   static constexpr int AS = C + 4;                  // sample-major row stride (floats)
   static constexpr int ZS = 20;                     // latent-gradient row stride
   // per-wave LDS (bytes)
-  static constexpr int FEAT = G::FEAT_BYTES;
-  __host__ __device__ static int abuf_bytes(int H) { return H * 64 * AS * 4; }
-  static constexpr int DBUF = 64 * AS * 4;
+  static constexpr int FEAT = S * G::ROW * 4;
+  __host__ __device__ static int abuf_bytes(int H) { return H * S * AS * 4; }
+  static constexpr int DBUF = S * AS * 4;
   static constexpr int DY = 64 * 4;
-  static constexpr int ZBUF = 64 * ZS * 4;
+  static constexpr int ZBUF = S * ZS * 4;
   __host__ __device__ static int wave_bytes(int H) { return FEAT + abuf_bytes(H) + DBUF + DY + ZBUF; }
   // backward weight fragments (block-level, after the forward ones)
   static constexpr int WB = MT * 4 * MT * 64 * 4;   // one hidden layer's W^T
@@ -87,14 +93,14 @@ __device__ void stage_backward(const NetDev& nd, char* p) {
 }
 
 template <int C, int F, int L, int ACT>
-__global__ __launch_bounds__(256) void fwd_bwd_kernel(NetDev nd, const float* xyz, long long n, const float* target,
+__global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDev nd, const float* xyz, long long n, const float* target,
                                                       const float* dloss, float* d_latent, float* ws, int n_waves,
                                                       float inv_n) {
   using TC = TrainCfg<C, F, L, ACT>;
   using CF = typename TC::CF;
   using G = typename TC::G;
   using PR = PrecT<kF32>;
-  constexpr int MT = TC::MT, AS = TC::AS;
+  constexpr int MT = TC::MT, AS = TC::AS, S = TC::S, NTC = TC::NTC;
   const int H = nd.H;
   extern __shared__ __attribute__((aligned(16))) char smem[];
   stage_weights<CF>(nd, smem);
@@ -120,27 +126,36 @@ __global__ __launch_bounds__(256) void fwd_bwd_kernel(NetDev nd, const float* xy
   const float* w_out = nd.weights + (long long)C * (3 + F + 6 * L) + C + (long long)(H - 1) * (C * C + C);
   const LatentSrc ls = make_latent_src(nd, 0, 0.0f);
   float loss_acc = 0.0f, dbo_acc = 0.0f;
-  const long long nchunks = (n + 63) / 64;
+  const long long nchunks = (n + S - 1) / S;
   bool first = true;
+  // Branch-free on purpose: the stored value is always produced by a VALU
+  // select, never by the MFMA directly. (A global store of an MFMA result
+  // reached through a branch was issued without the wait states the result
+  // needs and stored a partly written tile.) The first chunk's load reads
+  // stale workspace and is discarded by the select.
   auto add_tile = [&](int tile, f4 v) {
     f4* dst = reinterpret_cast<f4*>(slice + tile * 256) + lane;
-    if (first) *dst = v;
-    else *dst = *dst + v;
+    const f4 old = *dst;
+    f4 r;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) r[j] = first ? v[j] : old[j] + v[j];
+    *dst = r;
   };
   for (long long c = wave; c < nchunks; c += n_waves) {
-    const long long idx = c * 64 + lane;
-    const bool ok = idx < n;
+    // lane l < S owns point c * S + l
+    const long long idx = c * S + lane;
+    const bool ok = lane < S && idx < n;
     float px = 0.0f, py = 0.0f, pz = 0.0f;
     if (ok) {
       px = xyz[3 * idx];
       py = xyz[3 * idx + 1];
       pz = xyz[3 * idx + 2];
     }
-    write_features<CF, false>(feat + lane * G::ROW, ls, value_role(), px, py, pz);
+    if (lane < S) write_features<CF, false>(feat + lane * G::ROW, ls, value_role(), px, py, pz);
     wave_lds_sync();
     // ---------------- forward: store pre-activations a_i[s][o]
     f4 out = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < NTC; ++t) {
       f4 acc[MT];
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) acc[mt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -168,7 +183,7 @@ __global__ __launch_bounds__(256) void fwd_bwd_kernel(NetDev nd, const float* xy
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
           acc[mt] = nacc[mt];
-          *reinterpret_cast<f4*>(abuf + i * 64 * AS + (16 * t + nn) * AS + 16 * mt + 4 * g) = acc[mt];
+          *reinterpret_cast<f4*>(abuf + i * S * AS + (16 * t + nn) * AS + 16 * mt + 4 * g) = acc[mt];
         }
         p += G::HID;
       }
@@ -197,12 +212,12 @@ __global__ __launch_bounds__(256) void fwd_bwd_kernel(NetDev nd, const float* xy
     dy[lane] = dyv;
     wave_lds_sync();
     // ---------------- output layer weights: dW_H[0][k] = sum_s dy[s] h[k][s]
-    const float* alast = abuf + (H - 1) * 64 * AS;
+    const float* alast = abuf + (H - 1) * S * AS;
 #pragma unroll
     for (int nk = 0; nk < MT; ++nk) {
       f4 dw = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
+      for (int q = 0; q < S / 4; ++q) {
         const int s = 4 * q + g;
         const float a = nn == 0 ? dy[s] : 0.0f;
         const float b = act_el<ACT, false>(alast[s * AS + 16 * nk + nn], value_role());
@@ -211,9 +226,9 @@ __global__ __launch_bounds__(256) void fwd_bwd_kernel(NetDev nd, const float* xy
       add_tile(TC::tile_out(H, nk), dw);
     }
     // ---------------- backward through the activated layers
-    f4 dh[4][MT];  // d L / d h_i in D layout, per N-tile
+    f4 dh[NTC][MT];  // d L / d h_i in D layout, per N-tile
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < NTC; ++t) {
       const float dys = dy[16 * t + nn];
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
@@ -223,14 +238,14 @@ __global__ __launch_bounds__(256) void fwd_bwd_kernel(NetDev nd, const float* xy
       }
     }
     for (int i = H - 1; i >= 0; --i) {
-      const float* ai = abuf + i * 64 * AS;
+      const float* ai = abuf + i * S * AS;
       // delta_i = d L / d x_i = (d L / d h_i) * act'(x_i), x = W h + b in
       // world units (a_i holds x / (2 pi) for the periodic activations)
       f4 dbias[MT];
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) dbias[mt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
+      for (int t = 0; t < NTC; ++t)
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
           const f4 a = *reinterpret_cast<const f4*>(ai + (16 * t + nn) * AS + 16 * mt + 4 * g);
@@ -247,7 +262,7 @@ __global__ __launch_bounds__(256) void fwd_bwd_kernel(NetDev nd, const float* xy
         for (int mt = 0; mt < MT; ++mt) add_tile(TC::tile_bias(H, i, mt), dbias[mt]);
       }
       wave_lds_sync();
-      // dW_i = delta_i h_i^T over the 64 samples
+      // dW_i = delta_i h_i^T over the chunk's samples
       if (i == 0) {
 #pragma unroll
         for (int mo = 0; mo < MT; ++mo)
@@ -256,7 +271,7 @@ __global__ __launch_bounds__(256) void fwd_bwd_kernel(NetDev nd, const float* xy
             f4 dw = {0.0f, 0.0f, 0.0f, 0.0f};
             const int col = 16 * nk + nn;
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
+            for (int q = 0; q < S / 4; ++q) {
               const int s = 4 * q + g;
               const float a = dbuf[s * AS + 16 * mo + nn];
               const float b = col < G::KROW ? feat[s * G::ROW + col] : 0.0f;
@@ -265,14 +280,14 @@ __global__ __launch_bounds__(256) void fwd_bwd_kernel(NetDev nd, const float* xy
             add_tile(TC::tile_l0(mo, nk), dw);
           }
       } else {
-        const float* ap = abuf + (i - 1) * 64 * AS;
+        const float* ap = abuf + (i - 1) * S * AS;
 #pragma unroll
         for (int mo = 0; mo < MT; ++mo)
 #pragma unroll
           for (int nk = 0; nk < MT; ++nk) {
             f4 dw = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
+            for (int q = 0; q < S / 4; ++q) {
               const int s = 4 * q + g;
               const float a = dbuf[s * AS + 16 * mo + nn];
               const float b = act_el<ACT, false>(ap[s * AS + 16 * nk + nn], value_role());
@@ -285,7 +300,7 @@ __global__ __launch_bounds__(256) void fwd_bwd_kernel(NetDev nd, const float* xy
         // d L / d h_{i-1} = W_i^T delta_i (MFMA, B = delta in D layout)
         const float* WB = reinterpret_cast<const float*>(back + (i - 1) * TC::WB);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
+        for (int t = 0; t < NTC; ++t) {
           f4 nd2[MT];
 #pragma unroll
           for (int mk = 0; mk < MT; ++mk) nd2[mk] = f4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -302,7 +317,7 @@ __global__ __launch_bounds__(256) void fwd_bwd_kernel(NetDev nd, const float* xy
         // d L / d z = W_0[:, latent]^T delta_0 -> zbuf[s][f]
         const float* WZ = reinterpret_cast<const float*>(back + (H - 1) * TC::WB);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
+        for (int t = 0; t < NTC; ++t) {
           f4 dz = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
           for (int q = 0; q < 4 * MT; ++q) dz = PR::mma(WZ[q * kWave + lane], dh[t][q / 4][q % 4], dz);
@@ -341,9 +356,27 @@ __global__ __launch_bounds__(256) void fwd_bwd_kernel(NetDev nd, const float* xy
   slice[TC::tiles(H) * 256 + 64 + lane] = loss_acc;
 }
 
-// Sums the wave slices in a fixed order into the packed gradient.
+// Sums the wave slices in a fixed order into the packed gradient, in two
+// stages so that the reads are coalesced and plenty of them are in flight:
+// slice_sum_kernel adds groups of kGroup consecutive slices element-wise
+// (partial[g][e], threads along e), gather_kernel then locates every weight's
+// terms in the slice layout and adds them over the groups. Both orders are
+// fixed, so the result is bitwise reproducible.
+constexpr int kGroup = 32;
+
+__global__ void slice_sum_kernel(const float* ws, int n_waves, int sl, float* partial) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = blockIdx.y;
+  if (e >= sl) return;
+  const int w0 = g * kGroup, w1 = min(w0 + kGroup, n_waves);
+  float s = 0.0f;
+  for (int w = w0; w < w1; ++w) s += ws[(size_t)w * sl + e];
+  partial[(size_t)g * sl + e] = s;
+}
+
 template <int C, int F, int L, int ACT>
-__global__ void reduce_kernel(int H, const float* ws, int n_waves, float* d_weights, float* out_loss, float loss_scale) {
+__global__ void gather_kernel(int H, const float* partial, int n_groups, float* d_weights, float* out_loss,
+                              float loss_scale) {
   using TC = TrainCfg<C, F, L, ACT>;
   using G = typename TC::G;
   const int K0 = 3 + F + 6 * L;
@@ -404,9 +437,9 @@ __global__ void reduce_kernel(int H, const float* ws, int n_waves, float* d_weig
       }
     }
     float s = 0.0f;
-    for (int w = 0; w < n_waves; ++w) {
-      const float* sl = ws + (size_t)w * SL + base;
-      for (int c = 0; c < count; ++c) s += sl[c * stride];
+    for (int g = 0; g < n_groups; ++g) {
+      const float* pg = partial + (size_t)g * SL + base;
+      for (int c = 0; c < count; ++c) s += pg[c * stride];
     }
     if (j == nw) {
       if (out_loss) *out_loss = s * loss_scale;
@@ -441,14 +474,16 @@ struct TrainEntry {
   static int waves_per_block(int H) {
     const int fixed = TC::G::weight_bytes(H) + TC::back_bytes(H);
     int w = (160 * 1024 - fixed) / TC::wave_bytes(H);
-    return w < 1 ? 0 : (w > 4 ? 4 : w);
+    return w < 1 ? 0 : (w > kTrainWavesPerBlock ? kTrainWavesPerBlock : w);
   }
   static int n_waves(long long n) {
-    const long long c = (n + 63) / 64;
+    const long long c = (n + TC::S - 1) / TC::S;
     return (int)(c < kTrainMaxWaves ? (c < 1 ? 1 : c) : kTrainMaxWaves);
   }
+  static int n_groups(long long n) { return (n_waves(n) + kGroup - 1) / kGroup; }
+  // wave slices, then the group partials of the reduction
   static size_t ws_bytes(const NetDev& nd, long long n) {
-    return (size_t)n_waves(n) * TC::slice(nd.H) * sizeof(float);
+    return (size_t)(n_waves(n) + n_groups(n)) * TC::slice(nd.H) * sizeof(float);
   }
   static int run(const NetDev& nd, float* latent, float* d_latent, float* d_weights, const float* xyz, long long n,
                  const float* target, const float* dloss, float* out_loss, void* ws, hipStream_t st) {
@@ -484,9 +519,15 @@ struct TrainEntry {
       rc = check_launch();
       if (rc) return rc;
     }
+    const int sl = TC::slice(H), ng = n_groups(n);
+    float* partial = (float*)ws + (size_t)nw * sl;
+    hipLaunchKernelGGL(slice_sum_kernel, dim3((sl + 255) / 256, ng), dim3(256), 0, st, (const float*)ws, nw, sl,
+                       partial);
+    rc = check_launch();
+    if (rc) return rc;
     const long long nwts = (long long)C * (3 + F + 6 * L) + C + (long long)(H - 1) * (C * C + C) + C + 1;
-    hipLaunchKernelGGL((reduce_kernel<C, F, L, ACT>), dim3(grid_blocks(nwts + 1, 128, 1024)), dim3(128), 0, st, H,
-                       (const float*)ws, nw, d_weights, out_loss, target && n > 0 ? 1.0f / (float)n : 1.0f);
+    hipLaunchKernelGGL((gather_kernel<C, F, L, ACT>), dim3(grid_blocks(nwts + 1, 128, 1024)), dim3(128), 0, st, H,
+                       (const float*)partial, ng, d_weights, out_loss, target && n > 0 ? 1.0f / (float)n : 1.0f);
     return check_launch();
   }
 };

@@ -33,7 +33,7 @@ def _rel(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)
 
 
-@pytest.mark.parametrize("spec_name", ["NET_SMALL", "NET_STUDY"])
+@pytest.mark.parametrize("spec_name", ["NET_SMALL", "NET_STUDY", "NET_SHADED"])
 def test_train_gradients_l1(FV, spec_name):
     spec = getattr(I, spec_name)
     n = 64 * 37 + 13
@@ -54,6 +54,27 @@ def test_train_gradients_l1(FV, spec_name):
                                                                                   loss.item(), loss_ref), flush=True)
     assert e_w <= 1e-4 and e_l <= 1e-4
     # the mean of |d - t| inherits the FP32 rounding of each density (~2e-7)
+    assert abs(loss.item() - loss_ref) <= 1e-5 * abs(loss_ref) + 1e-7
+
+
+def test_train_gradients_many_chunks_per_wave(FV):
+    """More points than waves x chunk: waves walk several chunks and the
+    reduction runs over every group of wave slices."""
+    spec = I.NET_SMALL
+    n = 16 * 2048 * 2 + 16 * 300 + 7
+    gnet, onet, xyz = _setup(FV, spec, 21, n)
+    d = O.eval_points(onet, xyz)
+    rng = np.random.default_rng(5)
+    target = (d + rng.uniform(0.01, 0.3, n) * rng.choice([-1, 1], n)).astype(np.float32)
+    dl_ref, dw_ref, loss_ref = O.train_grads(onet, xyz, target=target.astype(np.float64))
+    d_lat = torch.empty_like(gnet.latent)
+    d_w = torch.empty_like(gnet.weights)
+    loss = torch.zeros(1, device="cuda")
+    FV.fvsrn_train_step(gnet, d_lat, d_w, torch.from_numpy(xyz).cuda(), target=torch.from_numpy(target).cuda(),
+                        out_loss=loss)
+    e_w, e_l = _rel(d_w.cpu().numpy(), dw_ref), _rel(d_lat.cpu().numpy(), dl_ref)
+    print("train many chunks: dW rel err %.3g, dG rel err %.3g" % (e_w, e_l), flush=True)
+    assert e_w <= 1e-4 and e_l <= 1e-4
     assert abs(loss.item() - loss_ref) <= 1e-5 * abs(loss_ref) + 1e-7
 
 
