@@ -55,37 +55,6 @@ def _run(cmd, cwd=None):
     return res.returncode, text
 
 
-_REG = re.compile(r"([va])\[(\d+):(\d+)\]|([va])(\d+)$")
-
-
-def _reg_range(tok):
-    m = _REG.match(tok.strip())
-    if not m:
-        return None
-    if m.group(1):
-        return m.group(1), int(m.group(2)), int(m.group(3))
-    return m.group(4), int(m.group(5)), int(m.group(5))
-
-
-def mfma_partial_overlaps(asm: str):
-    """MFMA instructions of a gfx950 assembly listing whose result registers
-    partially overlap their accumulator input (equal or disjoint is fine).
-    Returns (function, line) pairs."""
-    bad, fn = [], "?"
-    for line in asm.splitlines():
-        if line.startswith("_Z") and ":" in line:
-            fn = line.split(":", 1)[0]
-        if "v_mfma" not in line:
-            continue
-        ops = line.strip().split(None, 1)[1].split(";")[0].split(",")
-        if len(ops) < 4:
-            continue
-        d, c = _reg_range(ops[0]), _reg_range(ops[3])
-        if d and c and d[0] == c[0] and (d[1], d[2]) != (c[1], c[2]) and not (d[2] < c[1] or c[2] < d[1]):
-            bad.append((fn, line.strip()))
-    return bad
-
-
 _VMEM = ("global_", "buffer_", "flat_", "scratch_")
 _REGS = re.compile(r"\b([va])\[(\d+):(\d+)\]|\b([va])(\d+)\b")
 
@@ -188,16 +157,11 @@ def build(force: bool = True, verbose: bool = False, jobs: int = 0) -> str:
             raise RuntimeError("hipcc failed on %s:\n%s" % (src, text))
         if verbose and text.strip():
             print(text, file=sys.stderr)
-    # refuse a library with MFMA placements that gave wrong results on gfx950:
-    # result registers partially overlapping the accumulator input, and
-    # memory instructions reading a result before it is complete
+    # refuse a library in which a memory instruction reads an MFMA result
+    # before it is complete (such a store wrote partly stale tiles on gfx950)
     for path in device_asm_files():
         with open(path) as fh:
             text = fh.read()
-        bad = mfma_partial_overlaps(text)
-        if bad:
-            raise RuntimeError("%s: MFMA result partially overlaps its accumulator:\n%s" %
-                               (path, "\n".join("%s: %s" % b for b in bad[:10])))
         bad = mfma_early_vmem_reads(text)
         if bad:
             raise RuntimeError("%s: memory instruction reads an MFMA result too early:\n%s" %

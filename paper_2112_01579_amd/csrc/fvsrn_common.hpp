@@ -27,17 +27,6 @@ enum Act { kSine = 0, kSnakeAlt = 1, kIdentity = 2 };
 
 // ------------------------------------------------------------- precision
 
-// Every MFMA goes through mfma_keep: the accumulator input stays live until
-// after the instruction, so the register allocator never gives the result
-// registers that partially overlap the accumulator input. Results of MFMAs
-// whose destination was shifted by two registers against their accumulator
-// (v[n:n+3] <- ..., v[n+2:n+5]) came back wrong on gfx950; a build-time
-// check of the assembly (tests) keeps such placements out.
-__device__ inline f4 mfma_keep(f4 d, f4 c) {
-  asm volatile("" : "+v"(d) : "v"(c));  // ordered after the MFMA (reads d), uses c
-  return d;
-}
-
 template <int P>
 struct PrecT;
 
@@ -48,12 +37,8 @@ struct PrecT<kF16> {
   static constexpr int KT = 8;   // input-row columns of the tail (x y z 1 0 0 0 0)
   using VA = h8;
   using VT = h4;
-  __device__ static f4 mma(VA a, VA b, f4 c) {
-    return mfma_keep(__builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0), c);
-  }
-  __device__ static f4 mmt(VT a, VT b, f4 c) {
-    return mfma_keep(__builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0), c);
-  }
+  __device__ static f4 mma(VA a, VA b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
+  __device__ static f4 mmt(VT a, VT b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0); }
 };
 
 template <>
@@ -63,13 +48,10 @@ struct PrecT<kBF16> {
   static constexpr int KT = 8;
   using VA = b8;
   using VT = b4;
-  __device__ static f4 mma(VA a, VA b, f4 c) {
-    return mfma_keep(__builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0), c);
-  }
+  __device__ static f4 mma(VA a, VA b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
   __device__ static f4 mmt(VT a, VT b, f4 c) {
-    return mfma_keep(__builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4, a), __builtin_bit_cast(s4, b),
-                                                               c, 0, 0, 0),
-                     c);
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4, a), __builtin_bit_cast(s4, b), c, 0,
+                                                     0, 0);
   }
 };
 
@@ -80,9 +62,7 @@ struct PrecT<kF32> {
   static constexpr int KT = 4;
   using VA = float;
   using VT = float;
-  __device__ static f4 mma(float a, float b, f4 c) {
-    return mfma_keep(__builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0), c);
-  }
+  __device__ static f4 mma(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 };
 
 // Compile-time geometry of one network configuration (precision P, hidden

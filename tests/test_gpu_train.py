@@ -156,7 +156,11 @@ def test_training_reduces_loss_and_autograd(FV):
     (dens * u).sum().backward()
     d_lat, d_w = torch.empty_like(net.latent), torch.empty_like(net.weights)
     FV.fvsrn_train_step(net, d_lat, d_w, xyz, dloss_dy=u)
+    # dW is reduced in a fixed order (bitwise equal); the latent gradient is
+    # scattered with float atomics, whose order varies between launches, so
+    # the two agree to FP32 rounding of the largest entries
     assert torch.equal(w_p.grad, d_w)
-    assert torch.allclose(lat_p.grad, d_lat, rtol=1e-5, atol=1e-9)
+    scale = d_lat.abs().max().item()
+    assert torch.allclose(lat_p.grad, d_lat, rtol=0.0, atol=1e-6 * scale)
     net.latent.requires_grad_(False)
     net.weights.requires_grad_(False)

@@ -1,26 +1,14 @@
 """Checks of the gfx950 assembly the library is built from (no GPU needed).
 
-Two MFMA placements gave wrong results on the device: result registers that
-partially overlap the accumulator input, and a global store of a result
-reached through a branch right after the MFMA (the store read a partly
-written tile). The build refuses both; these tests pin the checks."""
+A global store of an MFMA result reached through a branch right after the
+MFMA was issued without the wait states the result needs and wrote partly
+stale tiles on the device. The build refuses such code; these tests pin the
+check."""
 import os
 
 import pytest
 
 from paper_2112_01579_amd import build as B
-
-
-def test_partial_overlap_detector():
-    bad = "\tv_mfma_f32_16x16x4_f32 v[84:87], v84, v82, v[86:89]\n"
-    same = "\tv_mfma_f32_16x16x4_f32 v[8:11], v83, v79, v[8:11]\n"
-    apart = "\tv_mfma_f32_16x16x32_f16 v[8:11], v[32:35], v[36:39], v[12:15]\n"
-    zero = "\tv_mfma_f32_16x16x4_f32 v[86:89], v79, v80, 0\n"
-    agpr = "\tv_mfma_f32_16x16x16_f16 a[0:3], v[30:31], v[38:39], a[2:5]\n"
-    fn = "_Zkernel:\n"
-    assert B.mfma_partial_overlaps(fn + bad) == [("_Zkernel", bad.strip())]
-    assert B.mfma_partial_overlaps(fn + same + apart + zero) == []
-    assert len(B.mfma_partial_overlaps(agpr)) == 1
 
 
 def test_early_vmem_read_detector():
@@ -50,7 +38,7 @@ def test_early_vmem_read_detector():
     assert B.mfma_early_vmem_reads("\n".join(chain)) == []
 
 
-def test_built_kernels_have_no_partial_mfma_overlap():
+def test_built_kernels_read_mfma_results_late_enough():
     files = B.device_asm_files()
     if not files:
         pytest.skip("library not built in this tree")
@@ -59,6 +47,5 @@ def test_built_kernels_have_no_partial_mfma_overlap():
         with open(path) as fh:
             text = fh.read()
         n_mfma += text.count("v_mfma")
-        assert B.mfma_partial_overlaps(text) == [], os.path.basename(path)
         assert B.mfma_early_vmem_reads(text) == [], os.path.basename(path)
     assert n_mfma > 1000
