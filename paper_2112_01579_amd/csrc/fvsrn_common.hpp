@@ -140,9 +140,9 @@ __device__ inline float quad_bcast(float x) {
 // capped at R-2. dfdp = d frac / d p.
 __device__ inline void axis_cell(float p, int R, int& i, float& f, float& dfdp) {
   const float scale = 0.5f * (float)(R - 1);
-  float u = (p + 1.0f) * scale;
   dfdp = (p < -1.0f || p > 1.0f) ? 0.0f : scale;
-  u = fminf(fmaxf(u, 0.0f), (float)(R - 1));
+  // u = (p + 1) (R - 1) / 2 clamped to [0, R - 1]
+  const float u = __builtin_amdgcn_fmed3f(fmaf(p, scale, scale), 0.0f, (float)(R - 1));
   int ii = (int)u;
   ii = ii > R - 2 ? R - 2 : ii;
   i = ii;

@@ -311,9 +311,10 @@ __device__ inline void latent_column_h(const LatentSrc& ls, const LaneRole& role
     if (key == 1 && !g) break;
     const __amdgpu_buffer_rsrc_t r = grid_rsrc(g, ls.bytes);
     const float kw = key == 0 ? ls.w0 : ls.w1;
+    const bool blend = ls.g1 != nullptr;  // one keyframe: its weight is 1
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-      const _Float16 wh = (_Float16)(w[c] * kw);
+      const _Float16 wh = (_Float16)(blend ? w[c] * kw : w[c]);
       const h2 w2 = {wh, wh};
 #pragma unroll
       for (int q = 0; q < F / 8; ++q) {
@@ -383,6 +384,10 @@ __device__ inline void write_features(typename CF::E* row, const LatentSrc& ls, 
         if (k + 1 < L) {
           sd[a] = s * c;
           gd[a] = fmaf(c, c, -2.0f);
+          // keep the value itself for the row: otherwise the compiler redoes
+          // the FMA inside a one-value mixed-precision conversion instead of
+          // converting pairs
+          asm("" : "+v"(gd[a]));
         }
       }
       if constexpr (GRAD) {
