@@ -172,24 +172,31 @@ fvsrn_status fvsrn_grad_points(const fvsrn_net_desc* desc, const fvsrn_params* p
 typedef struct {
   float lr_grid, lr_mlp, beta1, beta2, eps;
   int32_t step;          /* t >= 1 of this update */
-  float* m_latent;       /* device [R^3 F] */
+  float* m_latent;       /* device [K R^3 F] */
   float* v_latent;
   float* m_weights;      /* device [n_weights] */
   float* v_weights;
 } fvsrn_adam;
 
-/* One world-space training step on n points (Sec. 3, Sec. 5: L1 loss, Adam).
-   FP32 latent grid (K == 1) and FP32 weights, FP32 arithmetic.
-     L1 mode  (target != NULL): loss = mean |d(x_i) - target_i|, sign(0) = 0.
-     VJP mode (target == NULL): loss = sum dloss_dy_i * d(x_i) (the gradient
-       of any downstream loss, e.g. from autograd).
-   d_latent [R^3 F] and d_weights [n_weights] are overwritten with the
-   gradients. With adam != NULL the latent grid and the weights are then
-   updated in place (lr_grid for the latent grid, lr_mlp for the weights).
+/* One world-space training step on n points (Sec. 3, Sec. 5: L1 loss, Adam;
+   Sec. 8 for keyframe grids). FP32 latent grids and FP32 weights, FP32
+   arithmetic.
+     L1 mode  (target != NULL): loss = mean |d(x_i, t_i) - target_i|, sign(0) = 0.
+     VJP mode (target == NULL): loss = sum dloss_dy_i * d(x_i, t_i) (the
+       gradient of any downstream loss, e.g. from autograd).
+   latent [K][R^3 F]; key_times [host, K] strictly ascending (NULL when
+   K == 1); times (device [n], nullable: all 0) is each point's time, which
+   blends the two neighbouring keyframes as in rendering, so a point's latent
+   gradient goes to both with the blend weights.
+   d_latent [K R^3 F] and d_weights [n_weights] are overwritten with the
+   gradients (d_weights bitwise reproducible; d_latent summed with float
+   atomics). With adam != NULL the latent grids and the weights are then
+   updated in place (lr_grid for the latent grids, lr_mlp for the weights).
    out_loss (nullable, device FP32 scalar) receives the loss. workspace must
    hold fvsrn_train_workspace_size(desc, n) bytes. */
 fvsrn_status fvsrn_train_step(const fvsrn_net_desc* desc, float* latent, float* weights,
-                              float* d_latent, float* d_weights, const float* xyz, int64_t n,
+                              const float* key_times, float* d_latent, float* d_weights,
+                              const float* xyz, const float* times, int64_t n,
                               const float* target, const float* dloss_dy,
                               const fvsrn_adam* adam, float* out_loss, void* workspace,
                               size_t workspace_bytes, void* stream);

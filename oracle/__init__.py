@@ -98,7 +98,7 @@ def lib():
             "orc_render": (C.c_int, [C.POINTER(_Field), C.POINTER(_TF), C.POINTER(_Cam), C.c_int,
                                      C.POINTER(_March), P, C.POINTER(C.c_int64), I64,
                                      C.POINTER(C.c_int64), C.c_int]),
-            "orc_train_grads": (C.c_int, [NP, P, I64, P, P, P, P, P]),
+            "orc_train_grads": (C.c_int, [NP, P, P, I64, P, P, P, P, P]),
             "orc_adam": (C.c_int, [P, P, P, P, I64, D, D, D, D, I32]),
         }
         for name, (res, args) in sig.items():
@@ -297,14 +297,17 @@ def render(field: Field, tf, cams, march, pixels=None, threads=0):
     return out, samples.value
 
 
-def train_grads(net: Net, xyz, target=None, dloss_dd=None):
+def train_grads(net: Net, xyz, target=None, dloss_dd=None, times=None):
     """(d_latent, d_weights, loss) of the L1 loss (target given) or of the
-    linear functional sum_i dloss_dd_i * d_i."""
+    linear functional sum_i dloss_dd_i * d_i; times (optional) holds each
+    point's keyframe time."""
     xyz = _f64(xyz).reshape(-1, 3)
+    tt = None if times is None else _f64(times).reshape(-1)
+    assert tt is None or tt.size == xyz.shape[0]
     dl = np.zeros(net.latent.size)
     dw = np.zeros(net.weights.size)
     loss = C.c_double()
-    rc = lib().orc_train_grads(net.ref(), _dp(xyz), xyz.shape[0], _dp(_f64(target)),
+    rc = lib().orc_train_grads(net.ref(), _dp(xyz), _dp(tt), xyz.shape[0], _dp(_f64(target)),
                                _dp(_f64(dloss_dd)), _dp(dl), _dp(dw), C.byref(loss))
     assert rc == 0, rc
     return dl, dw, loss.value

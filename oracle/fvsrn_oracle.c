@@ -585,13 +585,14 @@ int orc_render(const orc_field* field, const orc_tf* tf, const orc_camera* cams,
 /* World-space fitting (Sec. 3, Sec. 5): one forward pass per point keeping
    the layer inputs and pre-activations, then the chain rule backwards through
    the sigmoid, the layers (W_i^T) and the trilinear latent interpolation. */
-int orc_train_grads(const orc_net* net, const double* xyz, int64_t n, const double* target,
-                    const double* dloss_dd, double* d_latent, double* d_weights, double* loss) {
-  if (!net_ok(net) || net->K != 1 || n < 0 || !d_latent || !d_weights) return -1;
+int orc_train_grads(const orc_net* net, const double* xyz, const double* times, int64_t n,
+                    const double* target, const double* dloss_dd, double* d_latent, double* d_weights,
+                    double* loss) {
+  if (!net_ok(net) || n < 0 || !d_latent || !d_weights) return -1;
   if (n > 0 && (!xyz || (!target && !dloss_dd))) return -1;
   const int c = net->c, H = net->H, F = net->F, R = net->R, K0 = orc_input_width(net);
   const int64_t nw = orc_num_weights(net);
-  const int64_t ng = (int64_t)R * R * R * F;
+  const int64_t ng = (int64_t)net->K * R * R * R * F;
   memset(d_weights, 0, sizeof(double) * (size_t)nw);
   memset(d_latent, 0, sizeof(double) * (size_t)ng);
   const int mx = K0 > c ? K0 : c;
@@ -603,7 +604,8 @@ int orc_train_grads(const orc_net* net, const double* xyz, int64_t n, const doub
   double total = 0.0;
   for (int64_t q = 0; q < n; ++q) {
     const double* p = xyz + 3 * q;
-    orc_features(net, p, 0.0, hs, NULL);
+    const double t = times ? times[q] : 0.0;
+    orc_features(net, p, t, hs, NULL);
     /* forward */
     int width = K0;
     double* hin = hs;
@@ -661,19 +663,29 @@ int orc_train_grads(const orc_net* net, const double* xyz, int64_t n, const doub
       }
       memcpy(delta, dnext, sizeof(double) * (size_t)win);
     }
-    /* latent: delta[3..3+F) = dL/dz; scatter with the trilinear weights */
+    /* latent: delta[3..3+F) = dL/dz; scatter with the trilinear weights into
+       the two keyframes the point's time interpolates (Sec. 8), each scaled by
+       its blend weight (one keyframe, weight 1, when K == 1) */
     if (F > 0) {
       int ic[3];
       double fr[3], df;
       for (int a = 0; a < 3; ++a) axis_cell(p[a], R, &ic[a], &fr[a], &df);
-      for (int cz = 0; cz < 2; ++cz)
-        for (int cy = 0; cy < 2; ++cy)
-          for (int cx = 0; cx < 2; ++cx) {
-            double w = (cx ? fr[0] : 1.0 - fr[0]) * (cy ? fr[1] : 1.0 - fr[1]) *
-                       (cz ? fr[2] : 1.0 - fr[2]);
-            double* gd = d_latent + ((((int64_t)(ic[2] + cz) * R + (ic[1] + cy)) * R + (ic[0] + cx)) * F);
-            for (int ch = 0; ch < F; ++ch) gd[ch] += w * delta[3 + ch];
-          }
+      int key;
+      double kw;
+      key_pair(net, t, &key, &kw);
+      const int nkeys = net->K > 1 ? 2 : 1;
+      for (int kk = 0; kk < nkeys; ++kk) {
+        const double bw = net->K > 1 ? (kk ? kw : 1.0 - kw) : 1.0;
+        double* gk = d_latent + (int64_t)(key + kk) * R * R * R * F;
+        for (int cz = 0; cz < 2; ++cz)
+          for (int cy = 0; cy < 2; ++cy)
+            for (int cx = 0; cx < 2; ++cx) {
+              double w = (cx ? fr[0] : 1.0 - fr[0]) * (cy ? fr[1] : 1.0 - fr[1]) *
+                         (cz ? fr[2] : 1.0 - fr[2]);
+              double* gd = gk + ((((int64_t)(ic[2] + cz) * R + (ic[1] + cy)) * R + (ic[0] + cx)) * F);
+              for (int ch = 0; ch < F; ++ch) gd[ch] += bw * w * delta[3 + ch];
+            }
+      }
     }
   }
   free(hs);

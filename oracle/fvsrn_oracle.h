@@ -129,13 +129,15 @@ int orc_render(const orc_field* field, const orc_tf* tf, const orc_camera* cams,
                const orc_march* m, double* out, const int64_t* pixels, int64_t n_pix,
                int64_t* samples, int threads);
 
-/* Training (Sec. 3 world-space fitting). Gradients of
-     L1 mode  (target != NULL): loss = mean_i |d(x_i) - target_i|
-     VJP mode (target == NULL): loss = sum_i dloss_dd_i * d(x_i)
-   with respect to the latent grid (K == 1) and all weights; the gradient
-   arrays are overwritten. sign(0) = 0 in L1 mode. */
-int orc_train_grads(const orc_net* net, const double* xyz, int64_t n, const double* target,
-                    const double* dloss_dd, double* d_latent, double* d_weights, double* loss);
+/* Training (Sec. 3 world-space fitting; Sec. 8 for keyframe grids). Gradients of
+     L1 mode  (target != NULL): loss = mean_i |d(x_i, t_i) - target_i|
+     VJP mode (target == NULL): loss = sum_i dloss_dd_i * d(x_i, t_i)
+   with respect to all K latent grids and all weights; the gradient arrays are
+   overwritten. times (nullable: all 0) gives each point's keyframe time.
+   sign(0) = 0 in L1 mode. */
+int orc_train_grads(const orc_net* net, const double* xyz, const double* times, int64_t n,
+                    const double* target, const double* dloss_dd, double* d_latent, double* d_weights,
+                    double* loss);
 /* One bias-corrected Adam update of n parameters at step t >= 1. */
 int orc_adam(double* param, const double* grad, double* m, double* v, int64_t n, double lr,
              double beta1, double beta2, double eps, int32_t t);

@@ -304,14 +304,21 @@ size_t fvsrn_train_workspace_size(const fvsrn_net_desc* desc, int64_t n) {
   return train_workspace_bytes(nd, n);
 }
 
-fvsrn_status fvsrn_train_step(const fvsrn_net_desc* desc, float* latent, float* weights, float* d_latent,
-                              float* d_weights, const float* xyz, int64_t n, const float* target,
-                              const float* dloss_dy, const fvsrn_adam* adam, float* out_loss, void* workspace,
-                              size_t workspace_bytes, void* stream) {
+fvsrn_status fvsrn_train_step(const fvsrn_net_desc* desc, float* latent, float* weights, const float* key_times,
+                              float* d_latent, float* d_weights, const float* xyz, const float* times, int64_t n,
+                              const float* target, const float* dloss_dy, const fvsrn_adam* adam, float* out_loss,
+                              void* workspace, size_t workspace_bytes, void* stream) {
   g_err[0] = 0;
   fvsrn_status s;
   if ((s = check_desc(desc)) != FVSRN_OK) return s;
-  if (desc->num_keyframes != 1) return fail(FVSRN_ERR_UNSUPPORTED, "training needs K == 1");
+  const fvsrn_params kp = {latent, weights, key_times};
+  if ((s = check_params(desc, &kp)) != FVSRN_OK) return s;
+  if (n > 0 && times && ((uintptr_t)times & 3u)) return fail(FVSRN_ERR_INVALID_ARGUMENT, "times misaligned");
+  // a point's keyframe pair is selected per lane: the K grids are addressed
+  // with 32-bit byte offsets from the first one
+  const long long all_bytes = (long long)desc->num_keyframes * desc->grid_res * desc->grid_res * desc->grid_res *
+                              desc->grid_channels * 4;
+  if (all_bytes >= (1LL << 31)) return fail(FVSRN_ERR_UNSUPPORTED, "training: K latent grids above 2^31 bytes");
   if (desc->grid_dtype != FVSRN_F32) return fail(FVSRN_ERR_UNSUPPORTED, "training needs an FP32 latent grid");
   if (desc->precision != FVSRN_F32) return fail(FVSRN_ERR_UNSUPPORTED, "training runs in FP32");
   if (!latent || !weights || !d_latent || !d_weights)
@@ -330,7 +337,11 @@ fvsrn_status fvsrn_train_step(const fvsrn_net_desc* desc, float* latent, float* 
   const size_t need = train_workspace_bytes(nd, n);
   if (need > 0 && (!workspace || workspace_bytes < need))
     return fail(FVSRN_ERR_WORKSPACE, "workspace of %zu bytes required", need);
-  const int rc = launch_train(nd, latent, weights, d_latent, d_weights, xyz, n, target, dloss_dy, adam != nullptr,
+  KeyTimes kt;
+  kt.K = desc->num_keyframes;
+  for (int k = 0; k < kMaxKeyframes; ++k) kt.t[k] = (k < kt.K && key_times) ? key_times[k] : 0.0f;
+  const int rc = launch_train(nd, kt, latent, weights, d_latent, d_weights, xyz, times, n, target, dloss_dy,
+                              adam != nullptr,
                               adam ? adam->lr_grid : 0.f, adam ? adam->lr_mlp : 0.f, adam ? adam->beta1 : 0.f,
                               adam ? adam->beta2 : 0.f, adam ? adam->eps : 0.f, adam ? adam->step : 0,
                               adam ? adam->m_latent : nullptr, adam ? adam->v_latent : nullptr,

@@ -8,6 +8,13 @@
 namespace fvsrn_detail {
 
 constexpr int kMaxViewsPerLaunch = 16;
+constexpr int kMaxKeyframes = 64;
+
+// Keyframe times for per-point keyframe selection in training.
+struct KeyTimes {
+  int K;
+  float t[kMaxKeyframes];
+};
 constexpr int kMaxTFPoints = 16;
 
 // Transfer function in telescoping form: f(d) = base + sum_j
@@ -70,11 +77,11 @@ int launch_cast(const float* src, void* dst, long long count, int dst_dtype, voi
 
 // Training (FP32). Workspace layout is owned by the kernels file.
 size_t train_workspace_bytes(const NetDev& net, long long n);
-int launch_train(const NetDev& net, float* latent, float* weights, float* d_latent,
-                 float* d_weights, const float* xyz, long long n, const float* target,
-                 const float* dloss_dy, int use_adam, float lr_grid, float lr_mlp, float beta1,
-                 float beta2, float eps, int step, float* m_lat, float* v_lat, float* m_w,
-                 float* v_w, float* out_loss, void* workspace, size_t ws_bytes, void* stream);
+int launch_train(const NetDev& net, const KeyTimes& kt, float* latent, float* weights, float* d_latent,
+                 float* d_weights, const float* xyz, const float* times, long long n, const float* target,
+                 const float* dloss_dy, int use_adam, float lr_grid, float lr_mlp, float beta1, float beta2,
+                 float eps, int step, float* m_lat, float* v_lat, float* m_w, float* v_w, float* out_loss,
+                 void* workspace, size_t ws_bytes, void* stream);
 
 const char* last_hip_error();
 

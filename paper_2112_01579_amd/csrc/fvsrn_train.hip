@@ -93,7 +93,9 @@ __device__ void stage_backward(const NetDev& nd, char* p) {
 }
 
 template <int C, int F, int L, int ACT>
-__global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDev nd, const float* xyz, long long n, const float* target,
+__global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDev nd, KeyTimes kt, const float* xyz,
+                                                                            const float* times, long long n,
+                                                                            const float* target,
                                                       const float* dloss, float* d_latent, float* ws, int n_waves,
                                                       float inv_n) {
   using TC = TrainCfg<C, F, L, ACT>;
@@ -124,7 +126,6 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
   const float b_out = *reinterpret_cast<const float*>(wout_p + G::WOA);
   // output weights (unscaled) straight from global memory, in D-layout order
   const float* w_out = nd.weights + (long long)C * (3 + F + 6 * L) + C + (long long)(H - 1) * (C * C + C);
-  const LatentSrc ls = make_latent_src(nd, 0, 0.0f);
   float loss_acc = 0.0f, dbo_acc = 0.0f;
   const long long nchunks = (n + S - 1) / S;
   bool first = true;
@@ -145,13 +146,38 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
     // lane l < S owns point c * S + l
     const long long idx = c * S + lane;
     const bool ok = lane < S && idx < n;
-    float px = 0.0f, py = 0.0f, pz = 0.0f;
+    float px = 0.0f, py = 0.0f, pz = 0.0f, pt = 0.0f;
     if (ok) {
       px = xyz[3 * idx];
       py = xyz[3 * idx + 1];
       pz = xyz[3 * idx + 2];
+      if (times) pt = times[idx];
     }
-    if (lane < S) write_features<CF, false>(feat + lane * G::ROW, ls, value_role(), px, py, pz);
+    // this point's keyframe pair (Sec. 8): the time clamped to the key range,
+    // linear between the neighbouring keyframes
+    int key = 0;
+    float kw = 0.0f;
+    if (nd.K > 1) {
+      if (pt <= kt.t[0]) {
+        key = 0;
+        kw = 0.0f;
+      } else if (pt >= kt.t[nd.K - 1]) {
+        key = nd.K - 2;
+        kw = 1.0f;
+      } else {
+        while (key + 1 < nd.K - 1 && kt.t[key + 1] <= pt) ++key;
+        kw = (pt - kt.t[key]) / (kt.t[key + 1] - kt.t[key]);
+      }
+    }
+    if (lane < S) {
+      if (nd.K == 1) {
+        write_features<CF, false>(feat + lane * G::ROW, make_latent_src(nd, 0, 0.0f), value_role(), px, py, pz);
+      } else {
+        // per-lane keyframes: the buffer loads of the gather then run once
+        // per distinct keyframe present in the wave
+        write_features<CF, false>(feat + lane * G::ROW, make_latent_src(nd, key, kw), value_role(), px, py, pz);
+      }
+    }
     wave_lds_sync();
     // ---------------- forward: store pre-activations a_i[s][o]
     f4 out = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -347,7 +373,16 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
 #pragma unroll
       for (int cc = 0; cc < 8; ++cc)
 #pragma unroll
-        for (int f = 0; f < F; ++f) unsafeAtomicAdd(d_latent + off[cc] + f, w8[cc] * z[f]);
+        for (int f = 0; f < F; ++f) {
+          const float gz = w8[cc] * z[f];
+          if (nd.K > 1) {
+            // both keyframes around the point's time, with the blend weights
+            unsafeAtomicAdd(d_latent + (size_t)key * nd.key_stride + off[cc] + f, (1.0f - kw) * gz);
+            unsafeAtomicAdd(d_latent + (size_t)(key + 1) * nd.key_stride + off[cc] + f, kw * gz);
+          } else {
+            unsafeAtomicAdd(d_latent + off[cc] + f, gz);
+          }
+        }
     }
     first = false;
   }
@@ -485,12 +520,13 @@ struct TrainEntry {
   static size_t ws_bytes(const NetDev& nd, long long n) {
     return (size_t)(n_waves(n) + n_groups(n)) * TC::slice(nd.H) * sizeof(float);
   }
-  static int run(const NetDev& nd, float* latent, float* d_latent, float* d_weights, const float* xyz, long long n,
+  static int run(const NetDev& nd, const KeyTimes& kt, float* latent, float* d_latent, float* d_weights,
+                 const float* xyz, const float* times, long long n,
                  const float* target, const float* dloss, float* out_loss, void* ws, hipStream_t st) {
     const int H = nd.H;
     const int wpb = waves_per_block(H);
     if (wpb < 1) return 1;
-    const long long nlat = (long long)nd.R * nd.R * nd.R * nd.F;
+    const long long nlat = (long long)nd.K * nd.R * nd.R * nd.R * nd.F;
     hipLaunchKernelGGL(fill_kernel, dim3(grid_blocks(nlat, 256, device_cus() * 8)), dim3(256), 0, st, d_latent,
                        nlat, 0.0f);
     int rc = check_launch();
@@ -506,10 +542,9 @@ struct TrainEntry {
     NetDev nd2 = nd;
     nd2.latent = latent;
     nd2.grid_f16 = 0;
-    nd2.K = 1;
     if (n > 0) {
       hipLaunchKernelGGL((fwd_bwd_kernel<C, F, L, ACT>), dim3((nw + wpb - 1) / wpb), dim3(wpb * 64), shm, st, nd2,
-                         xyz, n, target, dloss, d_latent, (float*)ws, nw, 1.0f / (float)n);
+                         kt, xyz, times, n, target, dloss, d_latent, (float*)ws, nw, 1.0f / (float)n);
       rc = check_launch();
       if (rc) return rc;
     } else {
@@ -552,10 +587,11 @@ size_t train_workspace_bytes(const NetDev& nd, long long n) {
   return 0;
 }
 
-int launch_train(const NetDev& nd, float* latent, float* weights, float* d_latent, float* d_weights, const float* xyz,
-                 long long n, const float* target, const float* dloss_dy, int use_adam, float lr_grid, float lr_mlp,
-                 float beta1, float beta2, float eps, int step, float* m_lat, float* v_lat, float* m_w, float* v_w,
-                 float* out_loss, void* workspace, size_t ws_bytes, void* stream) {
+int launch_train(const NetDev& nd, const KeyTimes& kt, float* latent, float* weights, float* d_latent,
+                 float* d_weights, const float* xyz, const float* times, long long n, const float* target,
+                 const float* dloss_dy, int use_adam, float lr_grid, float lr_mlp, float beta1, float beta2,
+                 float eps, int step, float* m_lat, float* v_lat, float* m_w, float* v_w, float* out_loss,
+                 void* workspace, size_t ws_bytes, void* stream) {
   const hipStream_t st = (hipStream_t)stream;
   NetDev net = nd;
   net.weights = weights;
@@ -563,14 +599,14 @@ int launch_train(const NetDev& nd, float* latent, float* weights, float* d_laten
 #define X(C_, F_, L_)                                                                                           \
   if (nd.C == C_ && nd.F == F_ && nd.L == L_) {                                                                 \
     if (nd.act == kSine)                                                                                        \
-      rc = TrainEntry<C_, F_, L_, kSine>::run(net, latent, d_latent, d_weights, xyz, n, target, dloss_dy,       \
-                                              out_loss, workspace, st);                                         \
+      rc = TrainEntry<C_, F_, L_, kSine>::run(net, kt, latent, d_latent, d_weights, xyz, times, n, target,      \
+                                              dloss_dy, out_loss, workspace, st);                               \
     else if (nd.act == kSnakeAlt)                                                                               \
-      rc = TrainEntry<C_, F_, L_, kSnakeAlt>::run(net, latent, d_latent, d_weights, xyz, n, target, dloss_dy,   \
-                                                  out_loss, workspace, st);                                     \
+      rc = TrainEntry<C_, F_, L_, kSnakeAlt>::run(net, kt, latent, d_latent, d_weights, xyz, times, n, target,  \
+                                                  dloss_dy, out_loss, workspace, st);                           \
     else                                                                                                        \
-      rc = TrainEntry<C_, F_, L_, kIdentity>::run(net, latent, d_latent, d_weights, xyz, n, target, dloss_dy,   \
-                                                  out_loss, workspace, st);                                     \
+      rc = TrainEntry<C_, F_, L_, kIdentity>::run(net, kt, latent, d_latent, d_weights, xyz, times, n, target,  \
+                                                  dloss_dy, out_loss, workspace, st);                           \
   }
   FV_TRAIN_CASES(X)
 #undef X
@@ -578,7 +614,7 @@ int launch_train(const NetDev& nd, float* latent, float* weights, float* d_laten
   if (rc != 0 || !use_adam) return rc;
   const double bc1 = 1.0 - pow((double)beta1, (double)step);
   const double bc2 = 1.0 - pow((double)beta2, (double)step);
-  const long long nlat = (long long)nd.R * nd.R * nd.R * nd.F;
+  const long long nlat = (long long)nd.K * nd.R * nd.R * nd.R * nd.F;
   const long long nw = (long long)nd.C * (3 + nd.F + 6 * nd.L) + nd.C + (long long)(nd.H - 1) * (nd.C * nd.C + nd.C) +
                        nd.C + 1;
   hipLaunchKernelGGL(adam_kernel, dim3(grid_blocks(nlat, 256, device_cus() * 8)), dim3(256), 0, st, latent, d_latent,

@@ -88,7 +88,8 @@ def lib():
             "fvsrn_render": (st, [vp, vp, vp, vp, i32, vp, vp, vp, vp]),
             "fvsrn_eval_points": (st, [vp, vp, vp, i64, C.c_float, vp, vp]),
             "fvsrn_grad_points": (st, [vp, vp, vp, i64, C.c_float, vp, vp, vp]),
-            "fvsrn_train_step": (st, [vp, vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, sz, vp]),
+            "fvsrn_train_step": (st, [vp, vp, vp, C.POINTER(C.c_float), vp, vp, vp, vp, i64, vp, vp, vp, vp, vp,
+                                      sz, vp]),
             "fvsrn_train_workspace_size": (sz, [vp, i64]),
             "fvsrn_render_dense": (st, [vp, i32, i32, i32, vp, vp, i32, vp, vp, vp, vp]),
             "fvsrn_dense_eval_points": (st, [vp, i32, i32, i32, vp, i64, vp, vp]),
@@ -274,11 +275,11 @@ def fvsrn_train_workspace_size(spec: I.NetSpec, n: int) -> int:
 def fvsrn_train_step(net: Network, d_latent: torch.Tensor, d_weights: torch.Tensor, xyz: torch.Tensor,
                      target: Optional[torch.Tensor] = None, dloss_dy: Optional[torch.Tensor] = None,
                      adam: Optional[dict] = None, out_loss: Optional[torch.Tensor] = None,
-                     workspace: Optional[torch.Tensor] = None, stream=None):
-    """One training step on ``net`` (FP32 latent grid, K == 1). ``adam`` is a
-    dict with lr_grid, lr_mlp, beta1, beta2, eps, step and the four moment
-    tensors m_latent, v_latent, m_weights, v_weights; None computes gradients
-    only."""
+                     workspace: Optional[torch.Tensor] = None, times: Optional[torch.Tensor] = None, stream=None):
+    """One training step on ``net`` (FP32 latent grids). ``times`` (device
+    [n], optional) holds each point's keyframe time. ``adam`` is a dict with
+    lr_grid, lr_mlp, beta1, beta2, eps, step and the four moment tensors
+    m_latent, v_latent, m_weights, v_weights; None computes gradients only."""
     n = xyz.shape[0]
     d = net.desc("f32")
     if workspace is None:
@@ -289,7 +290,8 @@ def fvsrn_train_step(net: Network, d_latent: torch.Tensor, d_weights: torch.Tens
         a = AdamStruct(adam["lr_grid"], adam["lr_mlp"], adam.get("beta1", 0.9), adam.get("beta2", 0.999),
                        adam.get("eps", 1e-8), adam["step"], adam["m_latent"].data_ptr(),
                        adam["v_latent"].data_ptr(), adam["m_weights"].data_ptr(), adam["v_weights"].data_ptr())
-    _check(lib().fvsrn_train_step(C.byref(d), _ptr(net.latent), _ptr(net.weights), _ptr(d_latent),
-                                  _ptr(d_weights), _ptr(xyz), n, _ptr(target), _ptr(dloss_dy),
+    kt = C.cast(net._kt, C.POINTER(C.c_float)) if net._kt is not None else None
+    _check(lib().fvsrn_train_step(C.byref(d), _ptr(net.latent), _ptr(net.weights), kt, _ptr(d_latent),
+                                  _ptr(d_weights), _ptr(xyz), _ptr(times), n, _ptr(target), _ptr(dloss_dy),
                                   C.byref(a) if a is not None else None, _ptr(out_loss), _ptr(workspace),
                                   workspace.numel(), _stream(stream)), "fvsrn_train_step")

@@ -20,14 +20,31 @@ from . import inputs as I
 
 
 class Trainer:
-    """Adam training of ``net`` (FP32 latent grid, one keyframe) on a dense
-    volume ``vol`` [nz][ny][nx] (device FP32)."""
+    """Adam training of ``net`` (FP32 latent grids) on a dense volume ``vol``
+    [nz][ny][nx] (device FP32), or, for a time-varying network (K keyframe
+    grids, Sec. 8), on a sequence ``vol`` = [(time, volume), ...]: every step
+    splits the batch evenly over the timesteps, each part drawing its targets
+    from its own volume at its own time, so the keyframe grids around each
+    time and the shared network learn together."""
 
-    def __init__(self, net: FV.Network, vol: torch.Tensor, batch: int = 1 << 18, lr_grid: float = 1e-2,
+    def __init__(self, net: FV.Network, vol, batch: int = 1 << 18, lr_grid: float = 1e-2,
                  lr_mlp: float = 1e-3, betas=(0.9, 0.999), eps: float = 1e-8, seed: int = 0):
-        assert net.grid_dtype == FV.F32 and net.spec.K == 1
-        self.net, self.vol, self.batch, self.seed = net, vol, batch, seed
+        assert net.grid_dtype == FV.F32
+        if isinstance(vol, torch.Tensor):
+            vol = [(0.0, vol)]
+        self.frames = list(vol)
+        assert len(self.frames) >= 1 and (net.spec.K > 1 or len(self.frames) == 1)
+        self.net, self.vol, self.batch, self.seed = net, self.frames[0][1], batch, seed
         dev = net.weights.device
+        # points of timestep j occupy rows [bounds[j], bounds[j + 1]) of the
+        # batch (multiples of 4 rows keep every slice 16-byte aligned)
+        T = len(self.frames)
+        self.bounds = [(batch * j // T) // 4 * 4 for j in range(T)] + [batch]
+        self.times = None
+        if net.spec.K > 1:
+            tt = np.concatenate([np.full(self.bounds[j + 1] - self.bounds[j], self.frames[j][0], np.float32)
+                                 for j in range(T)])
+            self.times = torch.from_numpy(tt).to(dev)
         self.opt = dict(lr_grid=lr_grid, lr_mlp=lr_mlp, beta1=betas[0], beta2=betas[1], eps=eps, step=0,
                         m_latent=torch.zeros_like(net.latent), v_latent=torch.zeros_like(net.latent),
                         m_weights=torch.zeros_like(net.weights), v_weights=torch.zeros_like(net.weights))
@@ -43,9 +60,11 @@ class Trainer:
         """One training step; returns the L1 loss of the batch (device scalar)."""
         self.opt["step"] += 1
         FV.fvsrn_sample_points(self.seed, self.opt["step"], self.batch, out=self.xyz)
-        FV.fvsrn_dense_eval_points(self.vol, self.xyz, out=self.target)
+        for j, (_, v) in enumerate(self.frames):
+            a, b = self.bounds[j], self.bounds[j + 1]
+            FV.fvsrn_dense_eval_points(v, self.xyz[a:b], out=self.target[a:b])
         FV.fvsrn_train_step(self.net, self.d_latent, self.d_weights, self.xyz, target=self.target, adam=self.opt,
-                            out_loss=self.loss, workspace=self.workspace)
+                            out_loss=self.loss, workspace=self.workspace, times=self.times)
         return self.loss
 
     def state_dict(self) -> dict:

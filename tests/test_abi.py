@@ -133,24 +133,39 @@ def test_points_argument_errors_and_empty_noop():
     assert L.fvsrn_cast_grid(None, None, 0, 1, None) == FV.OK
 
 
+def _train(d, key_times=None, xyz=FAKE, times=None, n=4, target=FAKE, dloss=None, adam=None):
+    L = FV.lib()
+    P = C.c_void_p
+    return L.fvsrn_train_step(C.byref(d), P(FAKE), P(FAKE), key_times, P(FAKE), P(FAKE),
+                              P(xyz) if xyz else None, P(times) if times else None, n,
+                              P(target) if target else None, P(dloss) if dloss else None,
+                              C.byref(adam) if adam is not None else None, None, None, 0, None)
+
+
 def test_train_argument_errors():
     L = FV.lib()
     d = _desc()
-    args = [C.c_void_p(FAKE)] * 4
     # FP16 latent grids and reduced precision are not trainable
-    d16 = _desc(grid_dtype=1)
-    assert L.fvsrn_train_step(C.byref(d16), *args, C.c_void_p(FAKE), 4, C.c_void_p(FAKE), None, None, None,
-                              None, 0, None) == FV.ERR_UNSUPPORTED
+    assert _train(_desc(grid_dtype=1)) == FV.ERR_UNSUPPORTED
+    assert _train(_desc(precision=1)) == FV.ERR_UNSUPPORTED
+    # keyframe grids need ascending key times
     dk = _desc(num_keyframes=2)
-    assert L.fvsrn_train_step(C.byref(dk), *args, C.c_void_p(FAKE), 4, C.c_void_p(FAKE), None, None, None,
-                              None, 0, None) == FV.ERR_UNSUPPORTED
+    assert _train(dk) == FV.ERR_INVALID_ARGUMENT
+    kt = (C.c_float * 2)(1.0, 1.0)
+    assert _train(dk, key_times=C.cast(kt, C.POINTER(C.c_float))) == FV.ERR_INVALID_ARGUMENT
+    # ... and all K grids within 2^31 bytes (8 x 256^3 x 8 FP32 = 4 GiB)
+    kt8 = (C.c_float * 8)(*range(8))
+    assert _train(_desc(num_keyframes=8, grid_res=256), key_times=C.cast(kt8, C.POINTER(C.c_float))) \
+        == FV.ERR_UNSUPPORTED
+    assert b"2^31" in L.fvsrn_last_error()
+    # misaligned times
+    assert _train(d, times=FAKE + 2) == FV.ERR_INVALID_ARGUMENT
     # neither target nor upstream gradient
-    assert L.fvsrn_train_step(C.byref(d), *args, C.c_void_p(FAKE), 4, None, None, None, None, None, 0, None) \
-        == FV.ERR_INVALID_ARGUMENT
-    # missing Adam moments
+    assert _train(d, target=None) == FV.ERR_INVALID_ARGUMENT
+    # missing Adam moments, Adam step 0
     a = FV.AdamStruct(1e-2, 1e-3, 0.9, 0.999, 1e-8, 1, FAKE, None, FAKE, FAKE)
-    assert L.fvsrn_train_step(C.byref(d), *args, C.c_void_p(FAKE), 4, C.c_void_p(FAKE), None, C.byref(a), None,
-                              None, 0, None) == FV.ERR_INVALID_ARGUMENT
+    assert _train(d, adam=a) == FV.ERR_INVALID_ARGUMENT
     a = FV.AdamStruct(1e-2, 1e-3, 0.9, 0.999, 1e-8, 0, FAKE, FAKE, FAKE, FAKE)
-    assert L.fvsrn_train_step(C.byref(d), *args, C.c_void_p(FAKE), 4, C.c_void_p(FAKE), None, C.byref(a), None,
-                              None, 0, None) == FV.ERR_INVALID_ARGUMENT
+    assert _train(d, adam=a) == FV.ERR_INVALID_ARGUMENT
+    # a workspace is required once there are points
+    assert _train(d) == FV.ERR_WORKSPACE

@@ -531,6 +531,54 @@ def test_train_gradients_against_central_differences():
         assert abs(dl[idx] - c1) < 1e-8 * max(1, abs(dl[idx]))
 
 
+def test_keyframe_train_gradients_against_central_differences():
+    """Keyframe grids (Sec. 8): each point's latent gradient lands in the two
+    keyframes around its time with the blend weights (clamped outside the key
+    range, a single keyframe at a key time). Checked by Richardson central
+    differences of sum_i w_i d(x_i, t_i) on latent entries of every keyframe
+    and on weights."""
+    spec = I.NetSpec(R=4, F=3, L=2, c=6, H=2, K=4)
+    keys = [0.0, 4.0, 8.0, 12.0]
+    lat, w = I.net_params(spec, 33)
+    net = O.Net(spec, lat, w, key_times=keys)
+    tset = np.array([-1.0, 0.0, 1.5, 4.0, 6.3, 11.0, 13.0])
+    n = 21
+    xyz = RNG.uniform(-1, 1, size=(n, 3))
+    times = tset[np.arange(n) % len(tset)]
+    wv = RNG.normal(size=n)
+    dl, dw, _ = O.train_grads(net, xyz, dloss_dd=wv, times=times)
+
+    def functional(lat_, w_):
+        n2 = O.Net(spec, lat_, w_, key_times=keys)
+        tot = 0.0
+        for t in tset:
+            sel = times == t
+            tot += float(np.dot(wv[sel], O.eval_points(n2, xyz[sel], t)))
+        return tot
+
+    h = 1e-4
+
+    def richardson(f, base, e):
+        c1 = (f(base + h * e) - f(base - h * e)) / (2 * h)
+        c2 = (f(base + h / 2 * e) - f(base - h / 2 * e)) / h
+        return (4 * c2 - c1) / 3
+
+    per_key = spec.R ** 3 * spec.F
+    for k in range(spec.K):
+        for idx in RNG.choice(per_key, 6, replace=False):
+            e = np.zeros(net.latent.size)
+            e[k * per_key + idx] = 1
+            want = richardson(lambda L_: functional(L_, net.weights), net.latent, e)
+            assert abs(dl[k * per_key + idx] - want) < 1e-8 * max(1, abs(want))
+    for idx in RNG.choice(spec.n_weights, 10, replace=False):
+        e = np.zeros(spec.n_weights)
+        e[idx] = 1
+        want = richardson(lambda W_: functional(net.latent, W_), net.weights, e)
+        assert abs(dw[idx] - want) < 1e-8 * max(1, abs(want))
+    # the last keyframe receives gradient only from times in (8, 12]
+    assert np.abs(dl[3 * per_key:]).max() > 0
+
+
 def test_latent_gradient_scatter_weights_sum_to_upstream():
     """Each point scatters dL/dz with trilinear weights that sum to one:
     summing dL/dG over all vertices equals summing dL/dz over all points,
