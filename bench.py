@@ -279,6 +279,47 @@ def main():
                 shade[name]["image_rmse_vs_dense_phong"] = e
         shade["central_over_forward"] = shade["central"]["ms_per_frame"] / shade["forward"]["ms_per_frame"]
         comp["shading_f16"] = shade
+        # time-varying workload (Sec. 8): keyframe latent grids every 4 timesteps
+        # trained on all 16 timesteps of the 256^3 advected-blob field, then 8
+        # views at fractional times in one launch; judged against dense DVR of
+        # the field at each view's time
+        if args.train_steps > 0:
+            from paper_2112_01579_amd.trainer import Trainer
+            prm = I.blob_sequence_params(seed=I.SEED_TIME)
+            raw = [I.blob_volume_torch(256, float(t), prm, device=dev) for t in range(16)]
+            norm = max(float(v.max().item()) for v in raw)
+            frames = [(float(t), v / norm) for t, v in enumerate(raw)]
+            del raw
+            tspec = I.NET_TIME
+            tlat, tw = I.net_params(tspec, I.SEED_TIME)
+            tnet32 = FV.Network(tspec, tlat, tw, key_times=I.TIME_KEYS, grid_dtype=FV.F32, device=dev)
+            ttr = Trainer(tnet32, frames, batch=1 << 18, seed=I.SEED_TIME)
+            tsteps = max(1, args.train_steps // 2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(tsteps):
+                ttr.step()
+            torch.cuda.synchronize()
+            t_train = time.perf_counter() - t0
+            tnet = FV.Network(tspec, tnet32.latent.cpu().numpy(), tnet32.weights.cpu().numpy(),
+                              key_times=I.TIME_KEYS, grid_dtype=FV.F16, device=dev)
+            tcams = I.time_cameras(1024, 1024)
+            stats.zero_()
+            FV.fvsrn_render(tnet, tf, tcams, march, "f16", out=out, stats=stats)
+            torch.cuda.synchronize()
+            ts = int(stats[0].item())
+            per_c, _ = time_launches(lambda: FV.fvsrn_render(tnet, tf, tcams, march, "f16", out=out), 3, 1)
+            ms = float(np.mean(per_c))
+            for v, cam in enumerate(tcams):
+                vt = I.blob_volume_torch(256, cam.time, prm, norm, device=dev)
+                FV.fvsrn_render_dense(vt, tf, [cam], march, out=ref[v:v + 1])
+            comp["time_varying_f16"] = {
+                "ms_per_frame": ms / len(tcams), "samples_per_s": ts / (ms * 1e-3),
+                "tflops": ts * fps / (ms * 1e-3) / 1e12, "image_rmse_vs_dense": rmse(out),
+                "view_times": [c.time for c in tcams],
+                "training": {"steps": tsteps, "batch": 1 << 18, "timesteps": 16, "final_l1": float(ttr.loss.item()),
+                             "ms_per_step": t_train / tsteps * 1e3}}
+            del frames, ttr, tnet32
         # fused point evaluation vs the framework-style layer-by-layer network (2^24 points)
         npts = 1 << 24
         xyz = torch.rand((npts, 3), device=dev) * 2 - 1

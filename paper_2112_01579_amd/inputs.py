@@ -266,6 +266,19 @@ def blob_volume(D: int, t: float, params, norm: float = 1.0) -> np.ndarray:
     return (vol / norm).astype(np.float32)
 
 
+def blob_volume_torch(D: int, t: float, params, norm: float = 1.0, device="cuda"):
+    """``blob_volume`` evaluated with torch on ``device`` (FP64, returned as
+    FP32): the same separable sum of blobs, for volumes too large to build
+    quickly on the host."""
+    import torch
+    c0, vel, sig, amp = (torch.as_tensor(a, dtype=torch.float64, device=device) for a in params)
+    ax = torch.linspace(-1.0, 1.0, D, dtype=torch.float64, device=device)
+    c = c0 + vel * t                                                  # [B, 3]
+    g = torch.exp(-0.5 * ((ax[None, None, :] - c[:, :, None]) / sig[:, None, None]) ** 2)  # [B, 3, D]
+    vol = torch.einsum("b,bz,by,bx->zyx", amp, g[:, 2], g[:, 1], g[:, 0])
+    return (vol / norm).float().contiguous()
+
+
 # ------------------------------------------------------------ presets
 
 NET_SMALL = NetSpec(R=16, F=8, L=4, c=32, H=3)       # 16^3x8 grid, 4 octaves, 3 x 32
