@@ -40,7 +40,8 @@ class _Net(C.Structure):
     _fields_ = [("R", C.c_int32), ("F", C.c_int32), ("K", C.c_int32), ("L", C.c_int32),
                 ("c", C.c_int32), ("H", C.c_int32), ("act", C.c_int32), ("pad_", C.c_int32),
                 ("latent", C.POINTER(C.c_double)), ("weights", C.POINTER(C.c_double)),
-                ("key_times", C.POINTER(C.c_double))]
+                ("key_times", C.POINTER(C.c_double)), ("latent_u8", C.POINTER(C.c_uint8)),
+                ("dequant", C.POINTER(C.c_double))]
 
 
 class _TF(C.Structure):
@@ -100,6 +101,8 @@ def lib():
                                      C.POINTER(C.c_int64), C.c_int]),
             "orc_train_grads": (C.c_int, [NP, P, P, I64, P, P, P, P, P]),
             "orc_adam": (C.c_int, [P, P, P, P, I64, D, D, D, D, I32]),
+            "orc_quantize_grid": (C.c_int, [C.POINTER(C.c_float), I64, I32, C.POINTER(C.c_uint8),
+                                            C.POINTER(C.c_float)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(_lib, name)
@@ -118,17 +121,28 @@ def _f64(a):
 class Net:
     """FP64 view of an fV-SRN: latent grid, packed weights, keyframe times."""
 
-    def __init__(self, spec, latent, weights, key_times=None):
+    def __init__(self, spec, latent, weights, key_times=None, codes=None, dequant=None):
+        """latent: FP values; or codes (uint8 [K][R^3][F]) with dequant
+        ([K][F][2] offset, scale) for a uint8 grid (latent may then be None)."""
         self.spec = spec
-        self.latent = _f64(latent).reshape(-1)
         self.weights = _f64(weights).reshape(-1)
         self.key_times = _f64(key_times)
+        if codes is not None:
+            self.codes = np.ascontiguousarray(np.asarray(codes, dtype=np.uint8)).reshape(-1)
+            self.dequant = _f64(dequant).reshape(-1)
+            assert self.codes.size == spec.K * spec.R ** 3 * spec.F and self.dequant.size == spec.K * spec.F * 2
+            self.latent = None
+            lat_p, cod_p = None, self.codes.ctypes.data_as(C.POINTER(C.c_uint8))
+        else:
+            self.latent = _f64(latent).reshape(-1)
+            assert self.latent.size == spec.K * spec.R ** 3 * spec.F
+            self.codes = self.dequant = None
+            lat_p, cod_p = _dp(self.latent), None
         self._s = _Net(spec.R, spec.F, spec.K, spec.L, spec.c, spec.H, ACT[spec.act], 0,
-                       _dp(self.latent), _dp(self.weights), _dp(self.key_times))
+                       lat_p, _dp(self.weights), _dp(self.key_times), cod_p, _dp(self.dequant))
         self.K0 = lib().orc_input_width(C.byref(self._s))
         self.n_weights = lib().orc_num_weights(C.byref(self._s))
         assert self.weights.size == self.n_weights, (self.weights.size, self.n_weights)
-        assert self.latent.size == spec.K * spec.R ** 3 * spec.F
 
     def ref(self):
         return C.byref(self._s)
@@ -311,6 +325,19 @@ def train_grads(net: Net, xyz, target=None, dloss_dd=None, times=None):
                                _dp(_f64(dloss_dd)), _dp(dl), _dp(dw), C.byref(loss))
     assert rc == 0, rc
     return dl, dw, loss.value
+
+
+def quantize_grid(grid, F):
+    """(codes uint8 [n][F], dequant float32 [F][2]) of one keyframe grid given
+    as FP32 values [..., F]."""
+    src = np.ascontiguousarray(np.asarray(grid, dtype=np.float32)).reshape(-1, F)
+    codes = np.zeros(src.shape, dtype=np.uint8)
+    dq = np.zeros((F, 2), dtype=np.float32)
+    rc = lib().orc_quantize_grid(src.ctypes.data_as(C.POINTER(C.c_float)), src.shape[0], F,
+                                 codes.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                 dq.ctypes.data_as(C.POINTER(C.c_float)))
+    assert rc == 0
+    return codes, dq
 
 
 def adam(param, grad, m, v, lr, beta1, beta2, eps, t):

@@ -38,7 +38,7 @@ int64_t orc_num_weights(const orc_net* net) { return layer_offset(net, net->H + 
 
 static int net_ok(const orc_net* net) {
   return net && net->R >= 2 && net->F >= 0 && net->K >= 1 && net->L >= 0 && net->c >= 1 &&
-         net->H >= 1 && net->weights && (net->F == 0 || net->latent) &&
+         net->H >= 1 && net->weights && (net->F == 0 || net->latent || (net->latent_u8 && net->dequant)) &&
          (net->K == 1 || net->key_times);
 }
 
@@ -70,7 +70,10 @@ static void latent_one(const orc_net* net, int key, const double p[3], double* z
     z[ch] = 0.0;
     if (dz) dz[ch * 3 + 0] = dz[ch * 3 + 1] = dz[ch * 3 + 2] = 0.0;
   }
-  const double* G = net->latent + (int64_t)key * R * R * R * F;
+  const int64_t kbase = (int64_t)key * R * R * R * F;
+  const double* G = net->latent_u8 ? NULL : net->latent + kbase;
+  const uint8_t* Gq = net->latent_u8 ? net->latent_u8 + kbase : NULL;
+  const double* dq = net->latent_u8 ? net->dequant + (int64_t)key * F * 2 : NULL;
   for (int cz = 0; cz < 2; ++cz)
     for (int cy = 0; cy < 2; ++cy)
       for (int cx = 0; cx < 2; ++cx) {
@@ -80,14 +83,15 @@ static void latent_one(const orc_net* net, int key, const double p[3], double* z
         double dwx = (cx ? 1.0 : -1.0) * df[0];
         double dwy = (cy ? 1.0 : -1.0) * df[1];
         double dwz = (cz ? 1.0 : -1.0) * df[2];
-        const double* g =
-            G + ((((int64_t)(i[2] + cz) * R + (i[1] + cy)) * R + (i[0] + cx)) * F);
+        const int64_t v = (((int64_t)(i[2] + cz) * R + (i[1] + cy)) * R + (i[0] + cx)) * F;
         for (int ch = 0; ch < F; ++ch) {
-          z[ch] += wx * wy * wz * g[ch];
+          /* the vertex value: stored, or de-quantised from its code */
+          const double g = G ? G[v + ch] : dq[2 * ch] + dq[2 * ch + 1] * (double)Gq[v + ch];
+          z[ch] += wx * wy * wz * g;
           if (dz) {
-            dz[ch * 3 + 0] += dwx * wy * wz * g[ch];
-            dz[ch * 3 + 1] += wx * dwy * wz * g[ch];
-            dz[ch * 3 + 2] += wx * wy * dwz * g[ch];
+            dz[ch * 3 + 0] += dwx * wy * wz * g;
+            dz[ch * 3 + 1] += wx * dwy * wz * g;
+            dz[ch * 3 + 2] += wx * wy * dwz * g;
           }
         }
       }
@@ -690,6 +694,31 @@ int orc_train_grads(const orc_net* net, const double* xyz, const double* times, 
   }
   free(hs);
   if (loss) *loss = target ? (n > 0 ? total / (double)n : 0.0) : total;
+  return 0;
+}
+
+int orc_quantize_grid(const float* src, int64_t n, int32_t F, uint8_t* codes, float* dequant) {
+  if (n < 1 || F < 1 || !src || !codes || !dequant) return -1;
+  for (int ch = 0; ch < F; ++ch) {
+    float lo = src[ch], hi = src[ch];
+    for (int64_t i = 1; i < n; ++i) {
+      const float x = src[i * F + ch];
+      if (x < lo) lo = x;
+      if (x > hi) hi = x;
+    }
+    const float scale = (hi - lo) / 255.0f;
+    dequant[2 * ch] = lo;
+    dequant[2 * ch + 1] = scale;
+    for (int64_t i = 0; i < n; ++i) {
+      float q = 0.0f;
+      if (scale > 0.0f) {
+        q = nearbyintf((src[i * F + ch] - lo) / scale); /* default rounding: half to even */
+        if (q < 0.0f) q = 0.0f;
+        if (q > 255.0f) q = 255.0f;
+      }
+      codes[i * F + ch] = (uint8_t)q;
+    }
+  }
   return 0;
 }
 

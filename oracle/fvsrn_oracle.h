@@ -44,6 +44,10 @@ typedef struct {
   const double* latent;     /* [K][R][R][R][F] */
   const double* weights;    /* packed, see header comment */
   const double* key_times;  /* [K] ascending (NULL when K == 1) */
+  /* uint8 latent grid (Sec. 4.2), used instead of `latent` when non-NULL:
+     vertex value = dequant[k][f][0] + dequant[k][f][1] * code[k][vertex][f] */
+  const uint8_t* latent_u8;   /* [K][R][R][R][F] codes */
+  const double* dequant;      /* [K][F][2] (offset, scale) */
 } orc_net;
 
 typedef struct {            /* piecewise-linear transfer function */
@@ -102,6 +106,14 @@ double orc_density_grad_fwd(const orc_net* net, const double p[3], double t, dou
 double orc_density_grad_rev(const orc_net* net, const double p[3], double t, double g[3]);
 
 int orc_eval_points(const orc_net* net, const double* xyz, int64_t n, double t, double* out);
+
+/* uint8 quantisation of one keyframe grid (Sec. 4.2: per-channel minimum and
+   maximum mapped to [0, 1], 8 bits), in FP32 arithmetic so that the codes are
+   reproducible bit for bit: lo, hi = channel min and max; scale = (hi - lo) /
+   255 (0 for a constant channel, whose codes are 0); code = round-half-even of
+   (x - lo) / scale, clamped to [0, 255]. src [n][F] FP32; codes [n][F];
+   dequant [F][2] = (lo, scale) as FP32 values. */
+int orc_quantize_grid(const float* src, int64_t n, int32_t F, uint8_t* codes, float* dequant);
 int orc_grad_points(const orc_net* net, const double* xyz, int64_t n, double t, double* out_d,
                     double* out_g);
 

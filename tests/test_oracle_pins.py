@@ -659,6 +659,52 @@ def test_fd_shading_converges_to_forward_mode_at_second_order():
     assert 3.0 < errs[0] / errs[1] < 5.0, errs
 
 
+def test_uint8_quantizer_definition():
+    """Sec. 4.2's uint8 grid: per channel, the minimum maps to code 0 and the
+    maximum to 255; every value is within half a step of its de-quantised
+    code; ties round to even; a constant channel has scale 0 and code 0."""
+    rng = np.random.default_rng(8)
+    F = 3
+    g = rng.normal(0, 0.1, size=(500, F)).astype(np.float32)
+    g[:, 2] = 0.25                                      # constant channel
+    g[7, 1] = 0.0                                       # exact tie case below
+    codes, dq = O.quantize_grid(g, F)
+    for ch in range(2):
+        lo, sc = float(dq[ch, 0]), float(dq[ch, 1])
+        assert lo == g[:, ch].min() and codes[np.argmin(g[:, ch]), ch] == 0
+        assert codes[np.argmax(g[:, ch]), ch] == 255
+        deq = lo + sc * codes[:, ch].astype(np.float64)
+        assert np.abs(deq - g[:, ch]).max() <= 0.5 * sc * (1 + 1e-5)
+    assert dq[2, 1] == 0 and np.all(codes[:, 2] == 0) and dq[2, 0] == np.float32(0.25)
+    # lo = 0, hi = 255 gives scale 1: 2.5 -> 2 and 3.5 -> 4 (half to even)
+    t = np.array([[0.0], [255.0], [2.5], [3.5], [254.5]], dtype=np.float32)
+    c, d = O.quantize_grid(t, 1)
+    assert d[0, 1] == 1.0 and list(c[:, 0]) == [0, 255, 2, 4, 254]
+
+
+def test_uint8_network_equals_float_network_on_dequantised_grid():
+    """The uint8 grid path de-quantises each vertex: a network on codes and
+    (offset, scale) evaluates exactly like one on the de-quantised values."""
+    spec = I.NetSpec(R=6, F=4, L=2, c=8, H=2, K=2)
+    lat, w = I.net_params(spec, 41)
+    codes, dqs = [], []
+    for k in range(spec.K):
+        c, d = O.quantize_grid(lat[k].reshape(-1, spec.F), spec.F)
+        codes.append(c)
+        dqs.append(d)
+    codes = np.stack(codes)
+    dqs = np.stack(dqs).astype(np.float64)
+    deq = dqs[:, None, :, 0] + dqs[:, None, :, 1] * codes.astype(np.float64)
+    keys = [0.0, 1.0]
+    nq = O.Net(spec, None, w, key_times=keys, codes=codes, dequant=dqs)
+    nf = O.Net(spec, deq.reshape(lat.shape), w, key_times=keys)
+    xyz = RNG.uniform(-1.1, 1.1, size=(40, 3))
+    for t in (0.0, 0.3, 1.0):
+        np.testing.assert_array_equal(O.eval_points(nq, xyz, t), O.eval_points(nf, xyz, t))
+    # and the quantisation error itself stays below half a step per channel
+    assert np.abs(deq.reshape(lat.shape) - lat).max() <= 0.5 * dqs[..., 1].max() * (1 + 1e-5)
+
+
 def test_render_time_uses_interpolated_latent():
     """The network is linear in the latent vector's source grid only through
     interpolation: rendering a 2-keyframe net at time t equals rendering a
