@@ -251,7 +251,9 @@ def main():
         torch.cuda.synchronize()
         comp["fvsrn_f16"] = {"ms_per_frame": ms_launch / len(cams), "samples_per_s": samples / (ms_launch * 1e-3),
                              "tflops": achieved, "image_rmse_vs_dense": rmse(out)}
-        for prec, n in (("f32", net32), ("bf16", net)):
+        net_u8 = FV.Network(spec, lat, w, grid_dtype=FV.U8, device=dev)
+        for prec, n, name in (("f32", net32, "fvsrn_f32"), ("bf16", net, "fvsrn_bf16"),
+                              ("f16", net_u8, "fvsrn_f16_uint8_grid")):
             stats.zero_()
             step(n, prec)
             torch.cuda.synchronize()
@@ -259,8 +261,8 @@ def main():
             e = rmse(out)
             per_c, _ = time_launches(lambda: step(n, prec), max(3, args.steps // 4), 1)
             ms = float(np.mean(per_c))
-            comp["fvsrn_" + prec] = {"ms_per_frame": ms / len(cams), "samples_per_s": s / (ms * 1e-3),
-                                     "tflops": s * fps / (ms * 1e-3) / 1e12, "image_rmse_vs_dense": e}
+            comp[name] = {"ms_per_frame": ms / len(cams), "samples_per_s": s / (ms * 1e-3),
+                          "tflops": s * fps / (ms * 1e-3) / 1e12, "image_rmse_vs_dense": e}
         # gradient strategies for Phong shading (Sec. 6): no shading, forward
         # mode, central differences with a one-voxel step of the 256^3 volume;
         # image error against dense DVR shaded with one-voxel central differences

@@ -57,17 +57,19 @@ typedef enum {
   FVSRN_ERR_DEVICE = 4            /* HIP error at launch */
 } fvsrn_status;
 
-typedef enum { FVSRN_F32 = 0, FVSRN_F16 = 1, FVSRN_BF16 = 2 } fvsrn_dtype;
+/* FVSRN_U8 is a latent-grid storage type only (uint8 codes with a per-channel
+   offset and scale, Sec. 4.2). */
+typedef enum { FVSRN_F32 = 0, FVSRN_F16 = 1, FVSRN_BF16 = 2, FVSRN_U8 = 3 } fvsrn_dtype;
 typedef enum { FVSRN_ACT_SINE = 0, FVSRN_ACT_SNAKEALT = 1, FVSRN_ACT_IDENTITY = 2 } fvsrn_act;
 
 /* Network and latent-grid shape (Sec. 3, Sec. 4.2). Supported: F in {8, 16},
    L in {4, 8} with (F, L) = (8, 4) or (16, 8); c in {32, 48}; 1 <= H <= 8;
    2 <= R <= 512 with one keyframe grid (R^3 F elements) below 2^31 bytes;
-   1 <= K <= 64. */
+   1 <= K <= 64. uint8 grids need F in {8, 16}. */
 typedef struct {
   int32_t grid_res;      /* R: latent vertices per axis */
   int32_t grid_channels; /* F: latent channels */
-  int32_t grid_dtype;    /* FVSRN_F32 or FVSRN_F16 storage of the latent grid */
+  int32_t grid_dtype;    /* FVSRN_F32, FVSRN_F16 or FVSRN_U8 storage of the latent grid */
   int32_t num_keyframes; /* K >= 1; K > 1 interpolates latent grids in time (Sec. 8) */
   int32_t num_freqs;     /* L: Fourier octaves */
   int32_t hidden_width;  /* c */
@@ -84,6 +86,9 @@ typedef struct {
   const float* key_times;   /* [host] [K] strictly ascending keyframe times; NULL if K == 1.
                                A time t is clamped to [key_times[0], key_times[K-1]] and the
                                two neighbouring keyframe latents are blended linearly. */
+  const float* latent_dequant; /* FVSRN_U8 grids: device [K][F][2] (offset, scale); vertex
+                               value = offset + scale * code (fvsrn_quantize_grid makes both).
+                               Ignored for other grid types. */
 } fvsrn_params;
 
 /* [host] Piecewise-linear transfer function: density -> (r, g, b, alpha),
@@ -228,6 +233,16 @@ fvsrn_status fvsrn_sample_points(uint64_t seed, uint64_t counter, int64_t n, flo
    the latent grid in FP16. dst_dtype FVSRN_F16 or FVSRN_BF16. */
 fvsrn_status fvsrn_cast_grid(const float* src, void* dst, int64_t count, int32_t dst_dtype,
                              void* stream);
+
+/* uint8 quantisation of one keyframe grid (Sec. 4.2: per channel, the
+   minimum and maximum are mapped to [0, 1] and stored in 8 bits). src
+   [n_vertices][channels] FP32 (device); codes [n_vertices][channels] uint8;
+   dequant [channels][2] = (lo, scale) FP32 with scale = (hi - lo) / 255 and
+   code = round-half-even((x - lo) / scale) clamped to [0, 255] (0 when a
+   channel is constant), all in FP32 arithmetic. For K keyframes call it once
+   per keyframe with the pointers advanced. 1 <= channels <= 64. */
+fvsrn_status fvsrn_quantize_grid(const float* src, int64_t n_vertices, int32_t channels, uint8_t* codes,
+                                 float* dequant, void* stream);
 
 /* Number of FP32 weights of a network description (0 if invalid). */
 int64_t fvsrn_num_weights(const fvsrn_net_desc* desc);

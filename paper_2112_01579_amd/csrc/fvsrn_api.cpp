@@ -38,8 +38,8 @@ fvsrn_status check_desc(const fvsrn_net_desc* d) {
     return fail(FVSRN_ERR_INVALID_ARGUMENT, "non-positive network dimension");
   if (d->num_keyframes < 1 || d->num_keyframes > 64)
     return fail(FVSRN_ERR_INVALID_ARGUMENT, "num_keyframes %d outside [1, 64]", d->num_keyframes);
-  if (d->grid_dtype != FVSRN_F32 && d->grid_dtype != FVSRN_F16)
-    return fail(FVSRN_ERR_INVALID_ARGUMENT, "grid_dtype must be FVSRN_F32 or FVSRN_F16");
+  if (d->grid_dtype != FVSRN_F32 && d->grid_dtype != FVSRN_F16 && d->grid_dtype != FVSRN_U8)
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "grid_dtype must be FVSRN_F32, FVSRN_F16 or FVSRN_U8");
   if (d->precision < FVSRN_F32 || d->precision > FVSRN_BF16)
     return fail(FVSRN_ERR_INVALID_ARGUMENT, "precision %d unknown", d->precision);
   if (d->activation < FVSRN_ACT_SINE || d->activation > FVSRN_ACT_IDENTITY)
@@ -53,7 +53,7 @@ fvsrn_status check_desc(const fvsrn_net_desc* d) {
   if (d->hidden_layers > 8) return fail(FVSRN_ERR_UNSUPPORTED, "hidden_layers %d > 8", d->hidden_layers);
   // the kernels address one keyframe grid with 32-bit byte offsets
   const long long grid_bytes = (long long)d->grid_res * d->grid_res * d->grid_res * d->grid_channels *
-                               (d->grid_dtype == FVSRN_F16 ? 2 : 4);
+                               (d->grid_dtype == FVSRN_U8 ? 1 : (d->grid_dtype == FVSRN_F16 ? 2 : 4));
   if (grid_bytes >= (1LL << 31))
     return fail(FVSRN_ERR_UNSUPPORTED, "one keyframe's latent grid is %lld bytes; at most 2^31 - 1 supported",
                 grid_bytes);
@@ -65,6 +65,8 @@ fvsrn_status check_params(const fvsrn_net_desc* d, const fvsrn_params* p) {
   if (!p->latent || !p->weights) return fail(FVSRN_ERR_INVALID_ARGUMENT, "latent or weights is NULL");
   if (!aligned16(p->latent) || !aligned16(p->weights))
     return fail(FVSRN_ERR_INVALID_ARGUMENT, "latent and weights must be 16-byte aligned");
+  if (d->grid_dtype == FVSRN_U8 && (!p->latent_dequant || ((uintptr_t)p->latent_dequant & 7u)))
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "uint8 grids need an 8-byte aligned latent_dequant");
   if (d->num_keyframes > 1) {
     if (!p->key_times) return fail(FVSRN_ERR_INVALID_ARGUMENT, "key_times required when K > 1");
     for (int k = 1; k < d->num_keyframes; ++k)
@@ -74,7 +76,8 @@ fvsrn_status check_params(const fvsrn_net_desc* d, const fvsrn_params* p) {
   return FVSRN_OK;
 }
 
-NetDev make_net(const fvsrn_net_desc* d, const void* latent, const float* weights) {
+NetDev make_net(const fvsrn_net_desc* d, const void* latent, const float* weights,
+                const float* dequant = nullptr) {
   NetDev n;
   n.latent = latent;
   n.weights = weights;
@@ -87,6 +90,8 @@ NetDev make_net(const fvsrn_net_desc* d, const void* latent, const float* weight
   n.act = d->activation;
   n.grid_f16 = d->grid_dtype == FVSRN_F16;
   n.key_stride = (long long)d->grid_res * d->grid_res * d->grid_res * d->grid_channels;
+  n.grid_u8 = d->grid_dtype == FVSRN_U8;
+  n.dequant = n.grid_u8 ? dequant : nullptr;
   return n;
 }
 
@@ -247,7 +252,7 @@ fvsrn_status fvsrn_render(const fvsrn_net_desc* desc, const fvsrn_params* params
   if (stats && ((uintptr_t)stats & 7u)) return fail(FVSRN_ERR_INVALID_ARGUMENT, "stats misaligned");
   TFDev tfd;
   if ((s = make_tf(tf, &tfd)) != FVSRN_OK) return s;
-  const NetDev nd = make_net(desc, params->latent, params->weights);
+  const NetDev nd = make_net(desc, params->latent, params->weights, params->latent_dequant);
   const MarchDev md = make_march(march);
   const long long per_view = (long long)cams[0].width * cams[0].height * 4;
   for (int v0 = 0; v0 < n_views; v0 += kMaxViewsPerLaunch) {
@@ -274,7 +279,7 @@ fvsrn_status fvsrn_eval_points(const fvsrn_net_desc* desc, const fvsrn_params* p
   int key;
   float kw;
   key_blend(desc, params, time, &key, &kw);
-  const NetDev nd = make_net(desc, params->latent, params->weights);
+  const NetDev nd = make_net(desc, params->latent, params->weights, params->latent_dequant);
   return launch_status(launch_points(nd, desc->precision, xyz, n, key, kw, out_density, nullptr, stream),
                        "fvsrn_eval_points");
 }
@@ -293,7 +298,7 @@ fvsrn_status fvsrn_grad_points(const fvsrn_net_desc* desc, const fvsrn_params* p
   int key;
   float kw;
   key_blend(desc, params, time, &key, &kw);
-  const NetDev nd = make_net(desc, params->latent, params->weights);
+  const NetDev nd = make_net(desc, params->latent, params->weights, params->latent_dequant);
   return launch_status(launch_points(nd, desc->precision, xyz, n, key, kw, out_density, out_grad, stream),
                        "fvsrn_grad_points");
 }
@@ -311,7 +316,7 @@ fvsrn_status fvsrn_train_step(const fvsrn_net_desc* desc, float* latent, float* 
   g_err[0] = 0;
   fvsrn_status s;
   if ((s = check_desc(desc)) != FVSRN_OK) return s;
-  const fvsrn_params kp = {latent, weights, key_times};
+  const fvsrn_params kp = {latent, weights, key_times, nullptr};
   if ((s = check_params(desc, &kp)) != FVSRN_OK) return s;
   if (n > 0 && times && ((uintptr_t)times & 3u)) return fail(FVSRN_ERR_INVALID_ARGUMENT, "times misaligned");
   // a point's keyframe pair is selected per lane: the K grids are addressed
@@ -348,6 +353,16 @@ fvsrn_status fvsrn_train_step(const fvsrn_net_desc* desc, float* latent, float* 
                               adam ? adam->m_weights : nullptr, adam ? adam->v_weights : nullptr, out_loss,
                               workspace, workspace_bytes, stream);
   return launch_status(rc, "fvsrn_train_step");
+}
+
+fvsrn_status fvsrn_quantize_grid(const float* src, int64_t n_vertices, int32_t channels, uint8_t* codes,
+                                 float* dequant, void* stream) {
+  g_err[0] = 0;
+  if (n_vertices < 1) return fail(FVSRN_ERR_INVALID_ARGUMENT, "n_vertices < 1");
+  if (channels < 1 || channels > 64) return fail(FVSRN_ERR_INVALID_ARGUMENT, "channels outside [1, 64]");
+  if (!src || !codes || !dequant || ((uintptr_t)src & 3u) || ((uintptr_t)dequant & 7u))
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "src, codes, dequant NULL or misaligned");
+  return launch_status(launch_quantize(src, n_vertices, channels, codes, dequant, stream), "fvsrn_quantize_grid");
 }
 
 fvsrn_status fvsrn_render_dense(const float* vol, int32_t nx, int32_t ny, int32_t nz, const fvsrn_tf* tf,

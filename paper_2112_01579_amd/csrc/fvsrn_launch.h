@@ -52,6 +52,8 @@ struct NetDev {
   const float* weights;
   int R, F, K, L, C, H, act, grid_f16;
   long long key_stride;  // elements between keyframe grids
+  int grid_u8;           // uint8 codes; dequant holds (offset, scale) [K][F][2]
+  const float* dequant;
 };
 
 struct ViewBatch {
@@ -59,7 +61,7 @@ struct ViewBatch {
   CamDev cam[kMaxViewsPerLaunch];
 };
 
-enum Prec { kF32 = 0, kF16 = 1, kBF16 = 2 };
+enum Prec { kF32 = 0, kF16 = 1, kBF16 = 2, kU8 = 3 };
 
 // All launchers return 0 on success, 1 if the configuration is not compiled,
 // 2 on a HIP launch error. `stream` is a hipStream_t.
@@ -74,6 +76,7 @@ int launch_dense_points(const float* vol, int nx, int ny, int nz, const float* x
                         float* out, void* stream);
 int launch_sample_points(uint64_t seed, uint64_t counter, long long n, float* xyz, void* stream);
 int launch_cast(const float* src, void* dst, long long count, int dst_dtype, void* stream);
+int launch_quantize(const float* src, long long n, int channels, unsigned char* codes, float* dequant, void* stream);
 
 // Training (FP32). Workspace layout is owned by the kernels file.
 size_t train_workspace_bytes(const NetDev& net, long long n);

@@ -403,9 +403,9 @@ int launch_points_t(const NetDev& nd, const float* xyz, long long n, int key, fl
   return check_launch();
 }
 
-template <int C, int F, int L, int ACT, int MODE, bool G16>
+template <int C, int F, int L, int ACT, int MODE, int GK>
 struct Entry {
-  using CF = Cfg<FVSRN_PREC, C, F, L, ACT, G16>;
+  using CF = Cfg<FVSRN_PREC, C, F, L, ACT, GK>;
   static int render(const NetDev& nd, const TFDev& tf, const ViewBatch& vb, const MarchDev& m, float* out,
                     unsigned long long* stats, hipStream_t st) {
     return launch_render_t<CF, MODE>(nd, tf, vb, m, out, stats, st);
@@ -419,11 +419,12 @@ struct Entry {
 // Gradient modes are compiled for FP32 and FP16 networks; central differences
 // for the sine activation only.
 
-// The FP16 network has separate instantiations for FP16 and FP32 latent grids.
+// The FP16 network has separate instantiations for FP32 (generic), FP16 and
+// uint8 latent grids.
 #if FVSRN_PREC == 1
-#define FV_G16S(X, C, F, L, ACT, MODE) X(C, F, L, ACT, MODE, false) X(C, F, L, ACT, MODE, true)
+#define FV_G16S(X, C, F, L, ACT, MODE) X(C, F, L, ACT, MODE, 0) X(C, F, L, ACT, MODE, 1) X(C, F, L, ACT, MODE, 2)
 #else
-#define FV_G16S(X, C, F, L, ACT, MODE) X(C, F, L, ACT, MODE, false)
+#define FV_G16S(X, C, F, L, ACT, MODE) X(C, F, L, ACT, MODE, 0)
 #endif
 
 #define FV_NETS(X, ACT, MODE)           \
@@ -452,11 +453,12 @@ struct Entry {
 int FV_PASTE(launch_render_p, FVSRN_PREC)(const NetDev& nd, const TFDev& tf, const ViewBatch& vb, const MarchDev& m,
                                           float* out, unsigned long long* stats, void* stream) {
   const int mode = !m.phong ? kShadeNone : (m.grad_mode == 1 ? kShadeFD : kShadeFwd);
-  const bool g16 = FVSRN_PREC == 1 && nd.grid_f16 != 0;
+  // packed FP16 gathers for an FP16 network on an FP16 or uint8 grid
+  const int gk = FVSRN_PREC != 1 ? 0 : (nd.grid_u8 ? 2 : (nd.grid_f16 ? 1 : 0));
   const hipStream_t st = (hipStream_t)stream;
-#define X(C_, F_, L_, ACT_, MODE_, G16_)                                                          \
-  if (nd.C == C_ && nd.F == F_ && nd.L == L_ && nd.act == ACT_ && mode == MODE_ && g16 == G16_) \
-    return Entry<C_, F_, L_, ACT_, MODE_, G16_>::render(nd, tf, vb, m, out, stats, st);
+#define X(C_, F_, L_, ACT_, MODE_, GK_)                                                           \
+  if (nd.C == C_ && nd.F == F_ && nd.L == L_ && nd.act == ACT_ && mode == MODE_ && gk == GK_) \
+    return Entry<C_, F_, L_, ACT_, MODE_, GK_>::render(nd, tf, vb, m, out, stats, st);
   FV_ALL(X)
 #if FVSRN_PREC != 2
   FV_ALL_GRAD(X)
@@ -469,11 +471,12 @@ int FV_PASTE(launch_render_p, FVSRN_PREC)(const NetDev& nd, const TFDev& tf, con
 int FV_PASTE(launch_points_p, FVSRN_PREC)(const NetDev& nd, const float* xyz, long long n, int key, float key_w,
                                           float* out_d, float* out_g, void* stream) {
   const int mode = out_g != nullptr ? kShadeFwd : kShadeNone;
-  const bool g16 = FVSRN_PREC == 1 && nd.grid_f16 != 0;
+  // packed FP16 gathers for an FP16 network on an FP16 or uint8 grid
+  const int gk = FVSRN_PREC != 1 ? 0 : (nd.grid_u8 ? 2 : (nd.grid_f16 ? 1 : 0));
   const hipStream_t st = (hipStream_t)stream;
-#define X(C_, F_, L_, ACT_, MODE_, G16_)                                                          \
-  if (nd.C == C_ && nd.F == F_ && nd.L == L_ && nd.act == ACT_ && mode == MODE_ && g16 == G16_) \
-    return Entry<C_, F_, L_, ACT_, MODE_, G16_>::points(nd, xyz, n, key, key_w, out_d, out_g, st);
+#define X(C_, F_, L_, ACT_, MODE_, GK_)                                                           \
+  if (nd.C == C_ && nd.F == F_ && nd.L == L_ && nd.act == ACT_ && mode == MODE_ && gk == GK_) \
+    return Entry<C_, F_, L_, ACT_, MODE_, GK_>::points(nd, xyz, n, key, key_w, out_d, out_g, st);
   FV_ALL(X)
 #if FVSRN_PREC != 2
   FV_ALL_GRAD(X)

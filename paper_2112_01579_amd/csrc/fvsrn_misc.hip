@@ -233,6 +233,48 @@ __global__ void cast_bf16_kernel(const float* src, __bf16* dst, long long count)
     dst[i] = (__bf16)src[i];
 }
 
+// uint8 quantisation (Sec. 4.2). One workgroup per channel finds the
+// channel's minimum and maximum (order-independent, so exact) and writes
+// (lo, (hi - lo) / 255); then every value is encoded as
+// round-half-even((x - lo) / scale), clamped to [0, 255], in FP32.
+__global__ __launch_bounds__(256) void channel_range_kernel(const float* src, long long n, int channels,
+                                                            float* dequant) {
+  __shared__ float s_lo[256], s_hi[256];
+  const int ch = blockIdx.x, t = threadIdx.x;
+  float lo = src[ch], hi = src[ch];
+  for (long long i = t; i < n; i += blockDim.x) {
+    const float x = src[i * channels + ch];
+    lo = fminf(lo, x);
+    hi = fmaxf(hi, x);
+  }
+  s_lo[t] = lo;
+  s_hi[t] = hi;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (t < h) {
+      s_lo[t] = fminf(s_lo[t], s_lo[t + h]);
+      s_hi[t] = fmaxf(s_hi[t], s_hi[t + h]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    dequant[2 * ch] = s_lo[0];
+    dequant[2 * ch + 1] = (s_hi[0] - s_lo[0]) / 255.0f;
+  }
+}
+
+__global__ void encode_u8_kernel(const float* src, long long count, int channels, const float* dequant,
+                                 unsigned char* codes) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int ch = (int)(i % channels);
+    const float lo = dequant[2 * ch], scale = dequant[2 * ch + 1];
+    float q = 0.0f;
+    if (scale > 0.0f) q = fminf(fmaxf(rintf((src[i] - lo) / scale), 0.0f), 255.0f);
+    codes[i] = (unsigned char)q;
+  }
+}
+
 }  // namespace
 
 thread_local char g_hip_err[256];
@@ -316,6 +358,18 @@ int launch_sample_points(uint64_t seed, uint64_t counter, long long n, float* xy
   const int blocks = grid_blocks(n, 256, device_cus() * 16);
   hipLaunchKernelGGL(sample_points_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, (uint32_t)seed,
                      (uint32_t)(seed >> 32), (uint32_t)counter, (uint32_t)(counter >> 32), n, xyz);
+  return check_launch();
+}
+
+int launch_quantize(const float* src, long long n, int channels, unsigned char* codes, float* dequant,
+                    void* stream) {
+  hipLaunchKernelGGL(channel_range_kernel, dim3(channels), dim3(256), 0, (hipStream_t)stream, src, n, channels,
+                     dequant);
+  int rc = check_launch();
+  if (rc) return rc;
+  const long long count = n * channels;
+  hipLaunchKernelGGL(encode_u8_kernel, dim3(grid_blocks(count, 256, device_cus() * 16)), dim3(256), 0,
+                     (hipStream_t)stream, src, count, channels, (const float*)dequant, codes);
   return check_launch();
 }
 

@@ -13,13 +13,15 @@
 
 namespace fvsrn_detail {
 
-// G16: the latent grid is FP16 and the network FP16, so the latent vector is
-// accumulated in packed FP16 (one gather path per instantiation keeps the
-// register peak down).
-template <int P_, int C_, int F_, int L_, int ACT_, bool G16_ = false>
+// GK selects the latent gather of an FP16 network: 0 generic (FP32
+// accumulation, grid type chosen at run time), 1 FP16 grid and 2 uint8 grid,
+// both accumulated in packed FP16 (one gather path per instantiation keeps
+// the register peak down). G16 says that a packed path is used.
+template <int P_, int C_, int F_, int L_, int ACT_, int GK_ = 0>
 struct Cfg {
   static constexpr int P = P_, C = C_, F = F_, L = L_, ACT = ACT_;
-  static constexpr bool G16 = G16_;
+  static constexpr int GK = GK_;
+  static constexpr bool G16 = GK_ != 0;
   using G = Geo<P, C, F, L>;
   using E = typename G::E;
 };
@@ -62,6 +64,11 @@ __device__ void stage_weights(const NetDev& nd, char* smem) {
   const int H = nd.H, K0 = 3 + F + 6 * L;
   const float* w = nd.weights;
   const float sc = CF::ACT == kIdentity ? 1.0f : kInv2Pi;
+  // a single uint8 keyframe on the packed path: the de-quantisation is folded
+  // into layer 0 (latent columns times the channel scale, the channel offsets
+  // into the bias), so the input row carries the weighted code sums
+  const bool fold = CF::GK == 2 && nd.grid_u8 && nd.K == 1;
+  const float* dq = nd.dequant;
   const int tid = threadIdx.x, nt = blockDim.x;
   const long long off_b0 = (long long)C * K0;
   auto off_layer = [&](int i) -> long long {  // W_i for 1 <= i <= H
@@ -72,12 +79,18 @@ __device__ void stage_weights(const NetDev& nd, char* smem) {
   auto w0 = [&](int o, int col) -> float {
     if (col < G::KF) {
       const float half = (CF::P != kF32 && col >= F + 3 * L) ? 0.5f : 1.0f;
-      return w[(long long)o * K0 + 3 + col] * sc * half;
+      const float qs = (fold && col < F) ? dq[2 * col + 1] : 1.0f;
+      return w[(long long)o * K0 + 3 + col] * qs * sc * half;
     }
     if (col < G::KMAIN) return 0.0f;
     const int t = col - G::KMAIN;
     if (t < 3) return w[(long long)o * K0 + t] * sc;
-    if (t == 3) return w[off_b0 + o] * sc;
+    if (t == 3) {
+      float b = w[off_b0 + o];
+      if (fold)
+        for (int ch = 0; ch < F; ++ch) b = fmaf(w[(long long)o * K0 + 3 + ch], dq[2 * ch], b);
+      return b * sc;
+    }
     return 0.0f;
   };
   char* p = smem;
@@ -172,8 +185,10 @@ struct LatentSrc {
   const void* g1;  // == nullptr: single keyframe
   float w0, w1;
   int R;
-  bool f16;
-  unsigned bytes;  // one keyframe grid (< 2^31, checked by the host)
+  int dtype;              // storage: kF32, kF16 or kU8
+  unsigned bytes;         // one keyframe grid (< 2^31, checked by the host)
+  const float* dq0;       // uint8 grids: (offset, scale) per channel of each keyframe
+  const float* dq1;
 };
 
 // Buffer resource over one keyframe grid. The corner fetches then address
@@ -188,17 +203,40 @@ __device__ inline uint4 load16(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned
   return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
 
+__device__ inline uint2 load8(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+// The F uint8 codes of one vertex as F/4 dwords (F = 8 or 16).
+template <int F>
+__device__ inline void load_codes(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, unsigned d[F / 4]) {
+  if constexpr (F == 16) {
+    const uint4 q = load16(r, voff, soff);
+    d[0] = q.x;
+    d[1] = q.y;
+    d[2] = q.z;
+    d[3] = q.w;
+  } else {
+    static_assert(F == 8, "uint8 grids: F = 8 or 16");
+    const uint2 q = load8(r, voff, soff);
+    d[0] = q.x;
+    d[1] = q.y;
+  }
+}
+
 __device__ inline LatentSrc make_latent_src(const NetDev& nd, int key, float key_w) {
   LatentSrc s;
-  const size_t esz = nd.grid_f16 ? 2 : 4;
+  const size_t esz = nd.grid_u8 ? 1 : (nd.grid_f16 ? 2 : 4);
   const char* base = reinterpret_cast<const char*>(nd.latent);
   s.g0 = base + (size_t)key * (size_t)nd.key_stride * esz;
   s.g1 = nd.K > 1 ? base + (size_t)(key + 1) * (size_t)nd.key_stride * esz : nullptr;
   s.w0 = nd.K > 1 ? 1.0f - key_w : 1.0f;
   s.w1 = key_w;
   s.R = nd.R;
-  s.f16 = nd.grid_f16 != 0;
+  s.dtype = nd.grid_u8 ? kU8 : (nd.grid_f16 ? kF16 : kF32);
   s.bytes = (unsigned)((size_t)nd.key_stride * esz);
+  s.dq0 = nd.grid_u8 ? nd.dequant + (size_t)key * nd.F * 2 : nullptr;
+  s.dq1 = (nd.grid_u8 && nd.K > 1) ? s.dq0 + nd.F * 2 : nullptr;
   return s;
 }
 
@@ -215,13 +253,35 @@ __device__ inline void corner_offsets(unsigned sx, unsigned sy, unsigned sz, uns
 }
 
 // z += w * G[corner][0..F) for the 8 corners of the cell at offset `base`.
+// A uint8 grid adds sum_c w_c (offset + scale * code_c) per channel, i.e. the
+// de-quantised vertex values (Sec. 4.2), as scale * (sum_c w_c code_c) +
+// offset * (sum_c w_c).
 template <int F>
-__device__ inline void gather8(const void* grid, bool f16, unsigned bytes, unsigned base, unsigned sx, unsigned sy,
-                               unsigned sz, const float w[8], float* z) {
+__device__ inline void gather8(const void* grid, int dtype, unsigned bytes, unsigned base, unsigned sx, unsigned sy,
+                               unsigned sz, const float w[8], float* z, const float* dq) {
   unsigned off[8];
   corner_offsets(sx, sy, sz, off);
   const __amdgpu_buffer_rsrc_t r = grid_rsrc(grid, bytes);
-  if (f16) {
+  if (dtype == kU8) {
+    float acc[F], wsum = 0.0f;
+#pragma unroll
+    for (int j = 0; j < F; ++j) acc[j] = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      unsigned d[F / 4];
+      load_codes<F>(r, base, off[c], d);
+#pragma unroll
+      for (int q = 0; q < F / 4; ++q) {
+        acc[4 * q + 0] = fmaf(w[c], (float)((d[q] >> 0) & 0xffu), acc[4 * q + 0]);
+        acc[4 * q + 1] = fmaf(w[c], (float)((d[q] >> 8) & 0xffu), acc[4 * q + 1]);
+        acc[4 * q + 2] = fmaf(w[c], (float)((d[q] >> 16) & 0xffu), acc[4 * q + 2]);
+        acc[4 * q + 3] = fmaf(w[c], (float)((d[q] >> 24) & 0xffu), acc[4 * q + 3]);
+      }
+      wsum += w[c];
+    }
+#pragma unroll
+    for (int j = 0; j < F; ++j) z[j] += fmaf(dq[2 * j + 1], acc[j], dq[2 * j] * wsum);
+  } else if (dtype == kF16) {
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
 #pragma unroll
@@ -271,11 +331,11 @@ __device__ inline void latent_column(const LatentSrc& ls, const LaneRole& role, 
   float wa[8];
 #pragma unroll
   for (int c = 0; c < 8; ++c) wa[c] = w[c] * ls.w0;
-  gather8<F>(ls.g0, ls.f16, ls.bytes, base, sx, sy, sz, wa, z);
+  gather8<F>(ls.g0, ls.dtype, ls.bytes, base, sx, sy, sz, wa, z, ls.dq0);
   if (ls.g1) {
 #pragma unroll
     for (int c = 0; c < 8; ++c) wa[c] = w[c] * ls.w1;
-    gather8<F>(ls.g1, ls.f16, ls.bytes, base, sx, sy, sz, wa, z);
+    gather8<F>(ls.g1, ls.dtype, ls.bytes, base, sx, sy, sz, wa, z, ls.dq1);
   }
 }
 
@@ -329,6 +389,78 @@ __device__ inline void latent_column_h(const LatentSrc& ls, const LaneRole& role
   }
 }
 
+// uint8 variant of latent_column_h (Sec. 4.2's quantised grid) for an FP16
+// network: each code pair is unpacked into FP16 as 1024 + code (a byte
+// permute next to the exponent byte 0x64) and 1024 subtracted exactly; the
+// weighted code sums accumulate in packed FP16 (at most 255, so the sum keeps
+// 1/8 of a code). With one keyframe they go to the row as they are (layer 0
+// holds the de-quantisation); with two they are de-quantised and blended.
+template <int F>
+__device__ inline void latent_column_q(const LatentSrc& ls, const LaneRole& role, float px, float py, float pz,
+                                       h2* z2) {
+  int ix, iy, iz;
+  float fx, fy, fz, dx, dy, dz;
+  axis_cell(px, ls.R, ix, fx, dx);
+  axis_cell(py, ls.R, iy, fy, dy);
+  axis_cell(pz, ls.R, iz, fz, dz);
+  const bool tx = !role.is_val && role.axis == 0, ty = !role.is_val && role.axis == 1,
+             tz = !role.is_val && role.axis == 2;
+  const float x0 = tx ? -dx : 1.0f - fx, x1 = tx ? dx : fx;
+  const float y0 = ty ? -dy : 1.0f - fy, y1 = ty ? dy : fy;
+  const float z0 = tz ? -dz : 1.0f - fz, z1 = tz ? dz : fz;
+  const unsigned R = (unsigned)ls.R;
+  const unsigned sx = F, sy = R * F, sz = R * R * F;
+  const unsigned base = (unsigned)iz * sz + (unsigned)iy * sy + (unsigned)ix * sx;
+  unsigned off[8];
+  corner_offsets(sx, sy, sz, off);
+  const float w[8] = {x0 * y0 * z0, x1 * y0 * z0, x0 * y1 * z0, x1 * y1 * z0,
+                      x0 * y0 * z1, x1 * y0 * z1, x0 * y1 * z1, x1 * y1 * z1};
+  const h2 bias = {(_Float16)-1024.0f, (_Float16)-1024.0f};
+  float zf[F];
+#pragma unroll
+  for (int j = 0; j < F; ++j) zf[j] = 0.0f;
+#pragma unroll
+  for (int key = 0; key < 2; ++key) {
+    const void* g = key == 0 ? ls.g0 : ls.g1;
+    if (key == 1 && !g) break;
+    const __amdgpu_buffer_rsrc_t r = grid_rsrc(g, ls.bytes);
+    const float kw = ls.g1 != nullptr ? (key == 0 ? ls.w0 : ls.w1) : 1.0f;
+    const float* dq = key == 0 ? ls.dq0 : ls.dq1;
+    h2 acc[F / 2];
+#pragma unroll
+    for (int j = 0; j < F / 2; ++j) acc[j] = h2{(_Float16)0.0f, (_Float16)0.0f};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const _Float16 wh = (_Float16)w[c];
+      const h2 w2 = {wh, wh};
+      unsigned d[F / 4];
+      load_codes<F>(r, base, off[c], d);
+#pragma unroll
+      for (int q = 0; q < F / 4; ++q) {
+        const h2 lo = __builtin_bit_cast(h2, __builtin_amdgcn_perm(0x64646464u, d[q], 0x04010400u)) + bias;
+        const h2 hi = __builtin_bit_cast(h2, __builtin_amdgcn_perm(0x64646464u, d[q], 0x04030402u)) + bias;
+        acc[2 * q] = w2 * lo + acc[2 * q];
+        acc[2 * q + 1] = w2 * hi + acc[2 * q + 1];
+      }
+    }
+    if (!ls.g1) {
+      // one keyframe: layer 0 holds the de-quantisation (see stage_weights)
+#pragma unroll
+      for (int j = 0; j < F / 2; ++j) z2[j] = acc[j];
+      return;
+    }
+    // de-quantise: offset * sum(w) + scale * sum(w code), blended over keyframes
+    const float wsum = ((w[0] + w[1]) + (w[2] + w[3])) + ((w[4] + w[5]) + (w[6] + w[7]));
+#pragma unroll
+    for (int j = 0; j < F / 2; ++j) {
+      zf[2 * j] = fmaf(kw, fmaf(dq[4 * j + 1], (float)acc[j][0], dq[4 * j] * wsum), zf[2 * j]);
+      zf[2 * j + 1] = fmaf(kw, fmaf(dq[4 * j + 3], (float)acc[j][1], dq[4 * j + 2] * wsum), zf[2 * j + 1]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < F / 2; ++j) z2[j] = h2{(_Float16)zf[2 * j], (_Float16)zf[2 * j + 1]};
+}
+
 // Builds this lane's input row at position p and writes it to `row` (LDS).
 template <class CF, bool GRAD>
 __device__ inline void write_features(typename CF::E* row, const LatentSrc& ls, const LaneRole& role, float px,
@@ -341,7 +473,9 @@ __device__ inline void write_features(typename CF::E* row, const LatentSrc& ls, 
   for (int j = 0; j < G::KROW; ++j) v[j] = 0.0f;
   constexpr bool packed_latent = CF::P == kF16 && CF::G16;
   h2 zh[F / 2];
-  if constexpr (packed_latent) {
+  if constexpr (packed_latent && CF::GK == 2) {
+    latent_column_q<F>(ls, role, px, py, pz, zh);
+  } else if constexpr (packed_latent) {
     latent_column_h<F>(ls, role, px, py, pz, zh);
   } else {
     latent_column<F>(ls, role, px, py, pz, v);

@@ -18,7 +18,7 @@ from . import inputs as I
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfvsrn.so")
 
-F32, F16, BF16 = 0, 1, 2
+F32, F16, BF16, U8 = 0, 1, 2, 3
 ACT = {"sine": 0, "snakealt": 1, "identity": 2}
 PREC = {"f32": F32, "fp32": F32, "f16": F16, "fp16": F16, "bf16": BF16}
 
@@ -27,8 +27,8 @@ OK, ERR_INVALID_ARGUMENT, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_DEVICE = 0, 1, 2, 
 EXPORTS = (
     "fvsrn_render", "fvsrn_eval_points", "fvsrn_grad_points", "fvsrn_train_step",
     "fvsrn_train_workspace_size", "fvsrn_render_dense", "fvsrn_dense_eval_points",
-    "fvsrn_sample_points", "fvsrn_cast_grid", "fvsrn_num_weights", "fvsrn_status_str",
-    "fvsrn_last_error",
+    "fvsrn_sample_points", "fvsrn_cast_grid", "fvsrn_quantize_grid", "fvsrn_num_weights",
+    "fvsrn_status_str", "fvsrn_last_error",
 )
 
 
@@ -45,7 +45,8 @@ class NetDesc(C.Structure):
 
 
 class Params(C.Structure):
-    _fields_ = [("latent", C.c_void_p), ("weights", C.c_void_p), ("key_times", C.POINTER(C.c_float))]
+    _fields_ = [("latent", C.c_void_p), ("weights", C.c_void_p), ("key_times", C.POINTER(C.c_float)),
+                ("latent_dequant", C.c_void_p)]
 
 
 class TFStruct(C.Structure):
@@ -95,6 +96,7 @@ def lib():
             "fvsrn_dense_eval_points": (st, [vp, i32, i32, i32, vp, i64, vp, vp]),
             "fvsrn_sample_points": (st, [C.c_uint64, C.c_uint64, i64, vp, vp]),
             "fvsrn_cast_grid": (st, [vp, vp, i64, i32, vp]),
+            "fvsrn_quantize_grid": (st, [vp, i64, i32, vp, vp, vp]),
             "fvsrn_num_weights": (i64, [vp]),
             "fvsrn_status_str": (C.c_char_p, [st]),
             "fvsrn_last_error": (C.c_char_p, []),
@@ -158,17 +160,26 @@ def march_struct(m: I.March) -> MarchStruct:
 
 
 class Network:
-    """Device-resident fV-SRN: latent grid (FP32 or FP16), FP32 weights and
-    (host) keyframe times."""
+    """Device-resident fV-SRN: latent grid (FP32, FP16 or uint8 codes with a
+    per-channel offset and scale), FP32 weights and (host) keyframe times."""
 
     def __init__(self, spec: I.NetSpec, latent, weights, key_times=None, device="cuda",
                  grid_dtype=F32):
         self.spec = spec
         lat = torch.as_tensor(latent, dtype=torch.float32).reshape(-1).contiguous().to(device)
+        self.dequant = None
         if grid_dtype == F16:
             half = torch.empty(lat.numel(), dtype=torch.float16, device=device)
             fvsrn_cast_grid(lat, half, F16)
             lat = half
+        elif grid_dtype == U8:
+            per = lat.numel() // spec.K
+            codes = torch.empty(lat.numel(), dtype=torch.uint8, device=device)
+            self.dequant = torch.empty((spec.K, spec.F, 2), dtype=torch.float32, device=device)
+            for k in range(spec.K):
+                fvsrn_quantize_grid(lat[k * per:(k + 1) * per], spec.F, codes[k * per:(k + 1) * per],
+                                    self.dequant[k])
+            lat = codes
         self.latent = lat
         self.grid_dtype = grid_dtype
         self.weights = torch.as_tensor(weights, dtype=torch.float32).reshape(-1).contiguous().to(device)
@@ -185,7 +196,8 @@ class Network:
 
     def params(self) -> Params:
         return Params(self.latent.data_ptr(), self.weights.data_ptr(),
-                      C.cast(self._kt, C.POINTER(C.c_float)) if self._kt is not None else None)
+                      C.cast(self._kt, C.POINTER(C.c_float)) if self._kt is not None else None,
+                      self.dequant.data_ptr() if self.dequant is not None else None)
 
 
 # ----------------------------------------------------------- calls
@@ -260,6 +272,20 @@ def fvsrn_cast_grid(src: torch.Tensor, dst: torch.Tensor, dtype: int = F16, stre
     _check(lib().fvsrn_cast_grid(_ptr(src), _ptr(dst), src.numel(), dtype, _stream(stream)),
            "fvsrn_cast_grid")
     return dst
+
+
+def fvsrn_quantize_grid(src: torch.Tensor, channels: int, codes: Optional[torch.Tensor] = None,
+                        dequant: Optional[torch.Tensor] = None, stream=None):
+    """uint8 codes and (offset, scale) per channel of one keyframe grid
+    (src FP32 [..., channels] on the device)."""
+    n = src.numel() // channels
+    if codes is None:
+        codes = torch.empty(src.numel(), dtype=torch.uint8, device=src.device)
+    if dequant is None:
+        dequant = torch.empty((channels, 2), dtype=torch.float32, device=src.device)
+    _check(lib().fvsrn_quantize_grid(_ptr(src), n, channels, _ptr(codes), _ptr(dequant), _stream(stream)),
+           "fvsrn_quantize_grid")
+    return codes, dequant
 
 
 def fvsrn_num_weights(spec: I.NetSpec) -> int:

@@ -9,6 +9,8 @@ Dense-grid DVR and the utilities are checked at FP32 rounding level or bit
 for bit."""
 import math
 
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -35,6 +37,10 @@ def FV():
 def _nets(FV, spec, seed, key_times=None, grid_dtype=0):
     lat, w = I.net_params(spec, seed)
     gnet = FV.Network(spec, lat, w, key_times=key_times, grid_dtype=grid_dtype)
+    if grid_dtype == FV.U8:
+        # the oracle reads the codes and (offset, scale) its own quantiser makes
+        codes, dq = zip(*[O.quantize_grid(lat[k].reshape(-1, spec.F), spec.F) for k in range(spec.K)])
+        return gnet, O.Net(spec, None, w, key_times, codes=np.stack(codes), dequant=np.stack(dq))
     if grid_dtype == FV.F16:
         lat = lat.astype(np.float16).astype(np.float64)   # the oracle reads what the GPU reads
     onet = O.Net(spec, lat, w, key_times)
@@ -103,6 +109,59 @@ def test_eval_points_fp16_grid(FV):
     for prec, tol in (("f32", FP32_TOL), ("f16", FP16_TOL)):
         out = FV.fvsrn_eval_points(gnet, torch.from_numpy(xyz).cuda(), 0.0, prec).cpu().numpy()
         assert np.abs(out - ref).max() <= tol
+
+
+@pytest.mark.parametrize("spec_name", ["NET_SMALL", "NET_STUDY"])
+def test_quantize_grid_bit_exact(FV, spec_name):
+    """uint8 codes and (offset, scale) of the GPU quantiser equal the
+    oracle's bit for bit (both decide every code in FP32)."""
+    spec = getattr(I, spec_name)
+    lat, _ = I.net_params(spec, 13)
+    src = torch.from_numpy(lat.reshape(-1).astype(np.float32)).cuda()
+    codes, dq = FV.fvsrn_quantize_grid(src, spec.F)
+    c_ref, d_ref = O.quantize_grid(lat.reshape(-1, spec.F), spec.F)
+    assert np.array_equal(codes.cpu().numpy(), c_ref.reshape(-1))
+    assert np.array_equal(dq.cpu().numpy(), d_ref)
+
+
+@pytest.mark.parametrize("spec_name", ["NET_SMALL", "NET_STUDY"])
+def test_eval_points_uint8_grid(FV, spec_name):
+    """uint8 latent grid (Sec. 4.2): FP32, FP16 (packed gather with the
+    de-quantisation folded into layer 0) and BF16 networks against the oracle
+    reading the same codes."""
+    spec = getattr(I, spec_name)
+    gnet, onet = _nets(FV, spec, 14, grid_dtype=FV.U8)
+    xyz = I.uniform_points(5000, 7, -1.05, 1.05)
+    ref = O.eval_points(onet, xyz)
+    for prec, tol in (("f32", FP32_TOL), ("f16", FP16_TOL), ("bf16", BF16_TOL)):
+        out = FV.fvsrn_eval_points(gnet, torch.from_numpy(xyz).cuda(), 0.0, prec).cpu().numpy()
+        _report("eval uint8 %s %s" % (spec_name, prec), np.abs(out - ref).max())
+        assert np.abs(out - ref).max() <= tol
+
+
+def test_uint8_grid_keyframes_render_and_gradients(FV):
+    """uint8 keyframe grids blended in time (de-quantised per keyframe in the
+    gather), rendered and differentiated, against the oracle."""
+    spec = I.NetSpec(R=16, F=16, L=8, c=32, H=3, K=2)
+    gnet, onet = _nets(FV, spec, 15, key_times=[0.0, 1.0], grid_dtype=FV.U8)
+    xyz = I.uniform_points(3000, 9)
+    for t in (0.0, 0.35, 1.0):
+        ref = O.eval_points(onet, xyz, t)
+        for prec, tol in (("f32", FP32_TOL), ("f16", FP16_TOL)):
+            out = FV.fvsrn_eval_points(gnet, torch.from_numpy(xyz).cuda(), t, prec).cpu().numpy()
+            assert np.abs(out - ref).max() <= tol
+    dref, gref = O.grad_points(onet, xyz, 0.35)
+    d, g = FV.fvsrn_grad_points(gnet, torch.from_numpy(xyz).cuda(), 0.35, "f32")
+    assert np.abs(d.cpu().numpy() - dref).max() <= FP32_TOL
+    assert _grad_err(g.cpu().numpy(), gref) <= 1e-4
+    cams = [dataclasses.replace(c, time=0.6) for c in I.orbit_cameras(1, 23, 19)]
+    tf = I.ramp_tf()
+    m = I.March(step=1 / 64, ert_eps=0.0)
+    ref, _ = O.render(O.Field(net=onet), tf, cams, m)
+    for prec, tol in (("f32", 1e-5), ("f16", FP16_TOL)):
+        img = FV.fvsrn_render(gnet, tf, cams, m, prec).cpu().numpy()
+        _report("uint8 keyframe render %s" % prec, np.abs(img - ref).max())
+        assert np.abs(img - ref).max() <= tol
 
 
 def test_eval_points_activations(FV):
