@@ -247,10 +247,13 @@ def main():
 
         def rmse(img):
             return float(torch.sqrt(torch.mean((img - ref) ** 2)).item())
+
+        def ssim(img):
+            return FV.fvsrn_ssim(img, ref)
         step()
         torch.cuda.synchronize()
         comp["fvsrn_f16"] = {"ms_per_frame": ms_launch / len(cams), "samples_per_s": samples / (ms_launch * 1e-3),
-                             "tflops": achieved, "image_rmse_vs_dense": rmse(out)}
+                             "tflops": achieved, "image_rmse_vs_dense": rmse(out), "image_ssim_vs_dense": ssim(out)}
         net_u8 = FV.Network(spec, lat, w, grid_dtype=FV.U8, device=dev)
         for prec, n, name in (("f32", net32, "fvsrn_f32"), ("bf16", net, "fvsrn_bf16"),
                               ("f16", net_u8, "fvsrn_f16_uint8_grid")):
@@ -258,11 +261,12 @@ def main():
             step(n, prec)
             torch.cuda.synchronize()
             s = int(stats[0].item())
-            e = rmse(out)
+            e, q = rmse(out), ssim(out)
             per_c, _ = time_launches(lambda: step(n, prec), max(3, args.steps // 4), 1)
             ms = float(np.mean(per_c))
             comp[name] = {"ms_per_frame": ms / len(cams), "samples_per_s": s / (ms * 1e-3),
-                          "tflops": s * fps / (ms * 1e-3) / 1e12, "image_rmse_vs_dense": e}
+                          "tflops": s * fps / (ms * 1e-3) / 1e12, "image_rmse_vs_dense": e,
+                          "image_ssim_vs_dense": q}
         # gradient strategies for Phong shading (Sec. 6): no shading, forward
         # mode, central differences with a one-voxel step of the 256^3 volume;
         # image error against dense DVR shaded with one-voxel central differences
@@ -274,11 +278,12 @@ def main():
                         ("central", dataclasses.replace(m_dense, grad_mode=1, fd_step=2.0 / 255))):
             FV.fvsrn_render(net, tf, cams, m, "f16", out=out)
             torch.cuda.synchronize()
-            e = rmse(out)
+            e, q = rmse(out), ssim(out)
             per_c, _ = time_launches(lambda: FV.fvsrn_render(net, tf, cams, m, "f16", out=out), 3, 1)
             shade[name] = {"ms_per_frame": float(np.mean(per_c)) / len(cams)}
             if m.phong:
                 shade[name]["image_rmse_vs_dense_phong"] = e
+                shade[name]["image_ssim_vs_dense_phong"] = q
         shade["central_over_forward"] = shade["central"]["ms_per_frame"] / shade["forward"]["ms_per_frame"]
         comp["shading_f16"] = shade
         # time-varying workload (Sec. 8): keyframe latent grids every 4 timesteps
@@ -318,6 +323,7 @@ def main():
             comp["time_varying_f16"] = {
                 "ms_per_frame": ms / len(tcams), "samples_per_s": ts / (ms * 1e-3),
                 "tflops": ts * fps / (ms * 1e-3) / 1e12, "image_rmse_vs_dense": rmse(out),
+                "image_ssim_vs_dense": ssim(out),
                 "view_times": [c.time for c in tcams],
                 "training": {"steps": tsteps, "batch": 1 << 18, "timesteps": 16, "final_l1": float(ttr.loss.item()),
                              "ms_per_step": t_train / tsteps * 1e3}}

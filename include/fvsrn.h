@@ -244,6 +244,17 @@ fvsrn_status fvsrn_cast_grid(const float* src, void* dst, int64_t count, int32_t
 fvsrn_status fvsrn_quantize_grid(const float* src, int64_t n_vertices, int32_t channels, uint8_t* codes,
                                  float* dequant, void* stream);
 
+/* Structural similarity map of image pairs (the image statistic of Sec. 5,
+   defined by Wang et al. 2004): a, b [n_images][height][width][4] RGBA FP32
+   (device); per colour channel (R, G, B), Gaussian-window statistics (11 x 11,
+   sigma 1.5, normalised) give
+   ((2 mu_a mu_b + C1)(2 s_ab + C2)) / ((mu_a^2 + mu_b^2 + C1)(s_a^2 + s_b^2 + C2)),
+   C1 = 0.01^2, C2 = 0.03^2 (data range 1); out_map [n_images][height-10][width-10]
+   (device) receives its mean over the three channels at every pixel whose
+   window fits. The SSIM of an image is the mean of its map. width, height >= 11. */
+fvsrn_status fvsrn_ssim_map(const float* a, const float* b, int32_t width, int32_t height, int32_t n_images,
+                            float* out_map, void* stream);
+
 /* Number of FP32 weights of a network description (0 if invalid). */
 int64_t fvsrn_num_weights(const fvsrn_net_desc* desc);
 

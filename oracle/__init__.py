@@ -101,6 +101,7 @@ def lib():
                                      C.POINTER(C.c_int64), C.c_int]),
             "orc_train_grads": (C.c_int, [NP, P, P, I64, P, P, P, P, P]),
             "orc_adam": (C.c_int, [P, P, P, P, I64, D, D, D, D, I32]),
+            "orc_ssim": (D, [P, P, C.c_int, C.c_int, P]),
             "orc_quantize_grid": (C.c_int, [C.POINTER(C.c_float), I64, I32, C.POINTER(C.c_uint8),
                                             C.POINTER(C.c_float)]),
         }
@@ -325,6 +326,17 @@ def train_grads(net: Net, xyz, target=None, dloss_dd=None, times=None):
                                _dp(_f64(dloss_dd)), _dp(dl), _dp(dw), C.byref(loss))
     assert rc == 0, rc
     return dl, dw, loss.value
+
+
+def ssim(a, b, with_map=False):
+    """SSIM of two [H][W][4] images (mean over the valid window positions and
+    the RGB channels); with_map also returns the [H-10][W-10] map."""
+    a, b = _f64(a), _f64(b)
+    H, W = a.shape[0], a.shape[1]
+    m = np.zeros((H - 10, W - 10)) if with_map else None
+    v = lib().orc_ssim(_dp(a), _dp(b), H, W, _dp(m))
+    assert v != -1.0
+    return (v, m) if with_map else v
 
 
 def quantize_grid(grid, F):

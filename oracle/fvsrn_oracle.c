@@ -722,6 +722,44 @@ int orc_quantize_grid(const float* src, int64_t n, int32_t F, uint8_t* codes, fl
   return 0;
 }
 
+double orc_ssim(const double* a, const double* b, int H, int W, double* map) {
+  const int r = 5;
+  if (!a || !b || H < 2 * r + 1 || W < 2 * r + 1) return -1.0;
+  double g[2 * r + 1][2 * r + 1], gs = 0.0;
+  for (int i = -r; i <= r; ++i)
+    for (int j = -r; j <= r; ++j) {
+      g[i + r][j + r] = exp(-(double)(i * i + j * j) / (2.0 * 1.5 * 1.5));
+      gs += g[i + r][j + r];
+    }
+  const double C1 = 0.01 * 0.01, C2 = 0.03 * 0.03;
+  double total = 0.0;
+  const int HO = H - 2 * r, WO = W - 2 * r;
+  for (int y = 0; y < HO; ++y)
+    for (int x = 0; x < WO; ++x) {
+      double s = 0.0;
+      for (int ch = 0; ch < 3; ++ch) {
+        double mx = 0.0, my = 0.0, xx = 0.0, yy = 0.0, xy = 0.0;
+        for (int i = 0; i <= 2 * r; ++i)
+          for (int j = 0; j <= 2 * r; ++j) {
+            const double w = g[i][j] / gs;
+            const double va = a[((int64_t)(y + i) * W + (x + j)) * 4 + ch];
+            const double vb = b[((int64_t)(y + i) * W + (x + j)) * 4 + ch];
+            mx += w * va;
+            my += w * vb;
+            xx += w * va * va;
+            yy += w * vb * vb;
+            xy += w * va * vb;
+          }
+        const double sx = xx - mx * mx, sy = yy - my * my, sxy = xy - mx * my;
+        s += ((2.0 * mx * my + C1) * (2.0 * sxy + C2)) / ((mx * mx + my * my + C1) * (sx + sy + C2));
+      }
+      s /= 3.0;
+      if (map) map[(int64_t)y * WO + x] = s;
+      total += s;
+    }
+  return total / ((double)HO * WO);
+}
+
 /* Adam (Kingma and Ba) with bias correction, as used for training in Sec. 5:
    m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
    p -= lr / (1 - b1^t) * m / (sqrt(v) / sqrt(1 - b2^t) + eps). */

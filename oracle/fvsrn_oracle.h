@@ -141,6 +141,16 @@ int orc_render(const orc_field* field, const orc_tf* tf, const orc_camera* cams,
                const orc_march* m, double* out, const int64_t* pixels, int64_t n_pix,
                int64_t* samples, int threads);
 
+/* Structural similarity of two [H][W][4] RGBA images (the image statistic of
+   Sec. 5, defined by Wang et al. 2004): per colour channel (R, G, B; alpha is
+   not compared), local means, variances and covariance under an 11 x 11
+   Gaussian window with sigma 1.5 (weights normalised to sum 1);
+   SSIM = (2 mu_x mu_y + C1)(2 s_xy + C2) / ((mu_x^2 + mu_y^2 + C1)(s_x^2 + s_y^2 + C2))
+   with C1 = 0.01^2, C2 = 0.03^2 (data range 1). map [H-10][W-10] (nullable)
+   gets the mean over the three channels at every pixel whose window fits;
+   returns the mean of the map (or -1 on an argument error). */
+double orc_ssim(const double* a, const double* b, int H, int W, double* map);
+
 /* Training (Sec. 3 world-space fitting; Sec. 8 for keyframe grids). Gradients of
      L1 mode  (target != NULL): loss = mean_i |d(x_i, t_i) - target_i|
      VJP mode (target == NULL): loss = sum_i dloss_dd_i * d(x_i, t_i)

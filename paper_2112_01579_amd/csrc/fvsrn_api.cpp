@@ -355,6 +355,17 @@ fvsrn_status fvsrn_train_step(const fvsrn_net_desc* desc, float* latent, float* 
   return launch_status(rc, "fvsrn_train_step");
 }
 
+fvsrn_status fvsrn_ssim_map(const float* a, const float* b, int32_t width, int32_t height, int32_t n_images,
+                            float* out_map, void* stream) {
+  g_err[0] = 0;
+  if (width < 11 || height < 11) return fail(FVSRN_ERR_INVALID_ARGUMENT, "images need at least 11 x 11 pixels");
+  if (n_images < 0) return fail(FVSRN_ERR_INVALID_ARGUMENT, "n_images < 0");
+  if (n_images == 0) return FVSRN_OK;
+  if (!a || !b || !out_map || !aligned16(a) || !aligned16(b) || ((uintptr_t)out_map & 3u))
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "a, b, out_map NULL or misaligned");
+  return launch_status(launch_ssim(a, b, width, height, n_images, out_map, stream), "fvsrn_ssim_map");
+}
+
 fvsrn_status fvsrn_quantize_grid(const float* src, int64_t n_vertices, int32_t channels, uint8_t* codes,
                                  float* dequant, void* stream) {
   g_err[0] = 0;

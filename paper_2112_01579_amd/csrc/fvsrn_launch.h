@@ -76,6 +76,7 @@ int launch_dense_points(const float* vol, int nx, int ny, int nz, const float* x
                         float* out, void* stream);
 int launch_sample_points(uint64_t seed, uint64_t counter, long long n, float* xyz, void* stream);
 int launch_cast(const float* src, void* dst, long long count, int dst_dtype, void* stream);
+int launch_ssim(const float* a, const float* b, int width, int height, int n_images, float* out, void* stream);
 int launch_quantize(const float* src, long long n, int channels, unsigned char* codes, float* dequant, void* stream);
 
 // Training (FP32). Workspace layout is owned by the kernels file.

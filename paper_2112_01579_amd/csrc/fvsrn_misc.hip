@@ -233,6 +233,46 @@ __global__ void cast_bf16_kernel(const float* src, __bf16* dst, long long count)
     dst[i] = (__bf16)src[i];
 }
 
+// SSIM map (Wang et al. 2004), one thread per output pixel; the 11 x 11
+// Gaussian window is the outer product of the normalised 1-D weights.
+struct Window11 {
+  float g[11];
+};
+
+__global__ void ssim_kernel(const float4* a, const float4* b, int W, int H, int n, Window11 win, float* out) {
+  const int WO = W - 10, HO = H - 10;
+  const long long total = (long long)n * HO * WO;
+  for (long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x; o < total;
+       o += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(o % WO), y = (int)((o / WO) % HO), img = (int)(o / ((long long)WO * HO));
+    float m[3][5] = {};
+    for (int i = 0; i < 11; ++i)
+      for (int j = 0; j < 11; ++j) {
+        const float w = win.g[i] * win.g[j];
+        const long long p = ((long long)img * H + (y + i)) * W + (x + j);
+        const float4 va = a[p], vb = b[p];
+        const float pa[3] = {va.x, va.y, va.z}, pb[3] = {vb.x, vb.y, vb.z};
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          m[ch][0] = fmaf(w, pa[ch], m[ch][0]);
+          m[ch][1] = fmaf(w, pb[ch], m[ch][1]);
+          m[ch][2] = fmaf(w, pa[ch] * pa[ch], m[ch][2]);
+          m[ch][3] = fmaf(w, pb[ch] * pb[ch], m[ch][3]);
+          m[ch][4] = fmaf(w, pa[ch] * pb[ch], m[ch][4]);
+        }
+      }
+    const float C1 = 1e-4f, C2 = 9e-4f;
+    float s = 0.0f;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      const float mx = m[ch][0], my = m[ch][1];
+      const float sx = m[ch][2] - mx * mx, sy = m[ch][3] - my * my, sxy = m[ch][4] - mx * my;
+      s += ((2.0f * mx * my + C1) * (2.0f * sxy + C2)) / ((mx * mx + my * my + C1) * (sx + sy + C2));
+    }
+    out[o] = s * (1.0f / 3.0f);
+  }
+}
+
 // uint8 quantisation (Sec. 4.2). One workgroup per channel finds the
 // channel's minimum and maximum (order-independent, so exact) and writes
 // (lo, (hi - lo) / 255); then every value is encoded as
@@ -358,6 +398,20 @@ int launch_sample_points(uint64_t seed, uint64_t counter, long long n, float* xy
   const int blocks = grid_blocks(n, 256, device_cus() * 16);
   hipLaunchKernelGGL(sample_points_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, (uint32_t)seed,
                      (uint32_t)(seed >> 32), (uint32_t)counter, (uint32_t)(counter >> 32), n, xyz);
+  return check_launch();
+}
+
+int launch_ssim(const float* a, const float* b, int width, int height, int n_images, float* out, void* stream) {
+  Window11 win;
+  double g[11], sum = 0.0;
+  for (int i = 0; i < 11; ++i) {
+    g[i] = exp(-(double)((i - 5) * (i - 5)) / (2.0 * 1.5 * 1.5));
+    sum += g[i];
+  }
+  for (int i = 0; i < 11; ++i) win.g[i] = (float)(g[i] / sum);
+  const long long total = (long long)n_images * (height - 10) * (width - 10);
+  hipLaunchKernelGGL(ssim_kernel, dim3(grid_blocks(total, 256, device_cus() * 16)), dim3(256), 0,
+                     (hipStream_t)stream, (const float4*)a, (const float4*)b, width, height, n_images, win, out);
   return check_launch();
 }
 

@@ -27,7 +27,7 @@ OK, ERR_INVALID_ARGUMENT, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_DEVICE = 0, 1, 2, 
 EXPORTS = (
     "fvsrn_render", "fvsrn_eval_points", "fvsrn_grad_points", "fvsrn_train_step",
     "fvsrn_train_workspace_size", "fvsrn_render_dense", "fvsrn_dense_eval_points",
-    "fvsrn_sample_points", "fvsrn_cast_grid", "fvsrn_quantize_grid", "fvsrn_num_weights",
+    "fvsrn_sample_points", "fvsrn_cast_grid", "fvsrn_quantize_grid", "fvsrn_ssim_map", "fvsrn_num_weights",
     "fvsrn_status_str", "fvsrn_last_error",
 )
 
@@ -97,6 +97,7 @@ def lib():
             "fvsrn_sample_points": (st, [C.c_uint64, C.c_uint64, i64, vp, vp]),
             "fvsrn_cast_grid": (st, [vp, vp, i64, i32, vp]),
             "fvsrn_quantize_grid": (st, [vp, i64, i32, vp, vp, vp]),
+            "fvsrn_ssim_map": (st, [vp, vp, i32, i32, i32, vp, vp]),
             "fvsrn_num_weights": (i64, [vp]),
             "fvsrn_status_str": (C.c_char_p, [st]),
             "fvsrn_last_error": (C.c_char_p, []),
@@ -272,6 +273,21 @@ def fvsrn_cast_grid(src: torch.Tensor, dst: torch.Tensor, dtype: int = F16, stre
     _check(lib().fvsrn_cast_grid(_ptr(src), _ptr(dst), src.numel(), dtype, _stream(stream)),
            "fvsrn_cast_grid")
     return dst
+
+
+def fvsrn_ssim_map(a: torch.Tensor, b: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None):
+    """SSIM maps of [n][H][W][4] (or [H][W][4]) image pairs: [n][H-10][W-10]."""
+    a4 = a.reshape(-1, a.shape[-3], a.shape[-2], 4)
+    n, H, W = a4.shape[0], a4.shape[1], a4.shape[2]
+    if out is None:
+        out = torch.empty((n, H - 10, W - 10), dtype=torch.float32, device=a.device)
+    _check(lib().fvsrn_ssim_map(_ptr(a), _ptr(b), W, H, n, _ptr(out), _stream(stream)), "fvsrn_ssim_map")
+    return out
+
+
+def fvsrn_ssim(a: torch.Tensor, b: torch.Tensor) -> float:
+    """Mean SSIM of an image pair (or of a batch of views, pooled)."""
+    return float(fvsrn_ssim_map(a, b).mean().item())
 
 
 def fvsrn_quantize_grid(src: torch.Tensor, channels: int, codes: Optional[torch.Tensor] = None,

@@ -437,3 +437,27 @@ def test_phong_render(FV, prec, tol):
     _report("phong %s" % prec, err)
     assert err <= tol
     assert abs(stats[0].item() - ns) <= 0.001 * ns
+
+
+def test_ssim_map_against_oracle(FV):
+    """SSIM maps of image pairs (random, and an FP16 fV-SRN render against
+    the FP32 one) against the FP64 oracle; FP32 window sums keep every map
+    value, and so the mean, within 1e-5."""
+    rng = np.random.default_rng(21)
+    a = rng.uniform(0, 1, (2, 29, 37, 4)).astype(np.float32)
+    b = np.clip(a + rng.normal(0, 0.05, a.shape), 0, 1).astype(np.float32)
+    m = FV.fvsrn_ssim_map(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()).cpu().numpy()
+    for i in range(2):
+        ref, rmap = O.ssim(a[i], b[i], with_map=True)
+        assert np.abs(m[i] - rmap).max() <= 1e-5
+        assert abs(m[i].mean() - ref) <= 1e-6
+    gnet, _ = _nets(FV, I.NET_SMALL, I.SEED_SMALL)
+    cams = I.orbit_cameras(1, 48, 40)
+    tf = I.ramp_tf()
+    mm = I.March(step=1 / 64, ert_eps=0.0)
+    i32 = FV.fvsrn_render(gnet, tf, cams, mm, "f32")
+    i16 = FV.fvsrn_render(gnet, tf, cams, mm, "f16")
+    got = FV.fvsrn_ssim(i16, i32)
+    want = O.ssim(i16[0].cpu().numpy(), i32[0].cpu().numpy())
+    _report("ssim f16 vs f32 render (%.6f)" % want, abs(got - want))
+    assert abs(got - want) <= 1e-5 and want > 0.99

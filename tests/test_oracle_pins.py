@@ -726,3 +726,32 @@ def test_render_time_uses_interpolated_latent():
 def dataclasses_replace(obj, **kw):
     import dataclasses
     return dataclasses.replace(obj, **kw)
+
+
+def test_ssim_against_scipy_gaussian_filtering():
+    """The oracle's windowed SSIM (direct 11 x 11 sums) against the same
+    statistics computed by scipy's separable Gaussian filter (sigma 1.5,
+    radius 5, normalised), cropped to the positions where the window fits;
+    plus SSIM(x, x) = 1 and the closed form for constant images."""
+    from scipy.ndimage import gaussian_filter
+    rng = np.random.default_rng(12)
+    a = rng.uniform(0, 1, (37, 45, 4))
+    b = np.clip(a + rng.normal(0, 0.1, a.shape), 0, 1)
+    val, m = O.ssim(a, b, with_map=True)
+
+    def filt(x):
+        return gaussian_filter(x, 1.5, truncate=5 / 1.5, mode="nearest")[5:-5, 5:-5]
+
+    C1, C2 = 0.01 ** 2, 0.03 ** 2
+    ref = 0.0
+    for ch in range(3):
+        x, y = a[..., ch], b[..., ch]
+        mx, my = filt(x), filt(y)
+        sx, sy, sxy = filt(x * x) - mx * mx, filt(y * y) - my * my, filt(x * y) - mx * my
+        ref = ref + ((2 * mx * my + C1) * (2 * sxy + C2)) / ((mx * mx + my * my + C1) * (sx + sy + C2))
+    ref = ref / 3
+    np.testing.assert_allclose(m, ref, rtol=1e-10, atol=1e-12)
+    assert abs(val - ref.mean()) < 1e-12
+    assert O.ssim(a, a) == 1.0
+    ca, cb = np.full((20, 20, 4), 0.3), np.full((20, 20, 4), 0.6)
+    assert abs(O.ssim(ca, cb) - (2 * 0.3 * 0.6 + C1) / (0.09 + 0.36 + C1)) < 1e-12
