@@ -38,7 +38,7 @@ def build(force: bool = False) -> str:
 
 class _Net(C.Structure):
     _fields_ = [("R", C.c_int32), ("F", C.c_int32), ("K", C.c_int32), ("L", C.c_int32),
-                ("c", C.c_int32), ("H", C.c_int32), ("act", C.c_int32), ("pad_", C.c_int32),
+                ("c", C.c_int32), ("H", C.c_int32), ("act", C.c_int32), ("outputs", C.c_int32),
                 ("latent", C.POINTER(C.c_double)), ("weights", C.POINTER(C.c_double)),
                 ("key_times", C.POINTER(C.c_double)), ("latent_u8", C.POINTER(C.c_uint8)),
                 ("dequant", C.POINTER(C.c_double))]
@@ -87,6 +87,7 @@ def lib():
             "orc_density": (D, [NP, P, D]),
             "orc_density_grad_fwd": (D, [NP, P, D, P]),
             "orc_density_grad_rev": (D, [NP, P, D, P]),
+            "orc_density_grad_pred": (D, [NP, P, D, P]),
             "orc_eval_points": (C.c_int, [NP, P, I64, D, P]),
             "orc_grad_points": (C.c_int, [NP, P, I64, D, P, P]),
             "orc_dense_sample": (D, [P, C.c_int, C.c_int, C.c_int, P]),
@@ -99,7 +100,7 @@ def lib():
             "orc_render": (C.c_int, [C.POINTER(_Field), C.POINTER(_TF), C.POINTER(_Cam), C.c_int,
                                      C.POINTER(_March), P, C.POINTER(C.c_int64), I64,
                                      C.POINTER(C.c_int64), C.c_int]),
-            "orc_train_grads": (C.c_int, [NP, P, P, I64, P, P, P, P, P]),
+            "orc_train_grads": (C.c_int, [NP, P, P, I64, P, P, D, P, P, P, P]),
             "orc_adam": (C.c_int, [P, P, P, P, I64, D, D, D, D, I32]),
             "orc_ssim": (D, [P, P, C.c_int, C.c_int, P]),
             "orc_quantize_grid": (C.c_int, [C.POINTER(C.c_float), I64, I32, C.POINTER(C.c_uint8),
@@ -139,7 +140,7 @@ class Net:
             assert self.latent.size == spec.K * spec.R ** 3 * spec.F
             self.codes = self.dequant = None
             lat_p, cod_p = _dp(self.latent), None
-        self._s = _Net(spec.R, spec.F, spec.K, spec.L, spec.c, spec.H, ACT[spec.act], 0,
+        self._s = _Net(spec.R, spec.F, spec.K, spec.L, spec.c, spec.H, ACT[spec.act], getattr(spec, "outputs", 1),
                        lat_p, _dp(self.weights), _dp(self.key_times), cod_p, _dp(self.dequant))
         self.K0 = lib().orc_input_width(C.byref(self._s))
         self.n_weights = lib().orc_num_weights(C.byref(self._s))
@@ -177,7 +178,8 @@ def density(net: Net, p, t=0.0):
 
 def density_grad(net: Net, p, t=0.0, mode="fwd"):
     g = np.zeros(3)
-    f = lib().orc_density_grad_fwd if mode == "fwd" else lib().orc_density_grad_rev
+    f = {"fwd": lib().orc_density_grad_fwd, "rev": lib().orc_density_grad_rev,
+         "pred": lib().orc_density_grad_pred}[mode]
     d = f(net.ref(), _dp(_p3(p)), t, _dp(g))
     return d, g
 
@@ -263,7 +265,7 @@ def box_clip(o, d):
 
 def _march_struct(m):
     return _March(m.step, m.fixed_steps, 1 if m.phong else 0, m.ert_eps, m.ka, m.kd, m.ks,
-                  m.shininess, 1 if m.grad_mode == 1 else 0, 0, m.fd_step)
+                  m.shininess, int(m.grad_mode), 0, m.fd_step)
 
 
 class Field:
@@ -312,18 +314,21 @@ def render(field: Field, tf, cams, march, pixels=None, threads=0):
     return out, samples.value
 
 
-def train_grads(net: Net, xyz, target=None, dloss_dd=None, times=None):
-    """(d_latent, d_weights, loss) of the L1 loss (target given) or of the
-    linear functional sum_i dloss_dd_i * d_i; times (optional) holds each
-    point's keyframe time."""
+def train_grads(net: Net, xyz, target=None, dloss_dd=None, times=None, target_grad=None, grad_weight=0.0):
+    """(d_latent, d_weights, loss) of the L1 loss (target given; plus
+    grad_weight/3 times the L1 error of the predicted gradient when
+    target_grad is given for a 4-output network) or of the linear functional
+    sum_i dloss_dd_i * d_i; times (optional) holds each point's keyframe
+    time."""
     xyz = _f64(xyz).reshape(-1, 3)
     tt = None if times is None else _f64(times).reshape(-1)
     assert tt is None or tt.size == xyz.shape[0]
     dl = np.zeros(net.latent.size)
     dw = np.zeros(net.weights.size)
     loss = C.c_double()
-    rc = lib().orc_train_grads(net.ref(), _dp(xyz), _dp(tt), xyz.shape[0], _dp(_f64(target)),
-                               _dp(_f64(dloss_dd)), _dp(dl), _dp(dw), C.byref(loss))
+    tg = None if target_grad is None else _f64(target_grad).reshape(-1, 3)
+    rc = lib().orc_train_grads(net.ref(), _dp(xyz), _dp(tt), xyz.shape[0], _dp(_f64(target)), _dp(tg),
+                               float(grad_weight), _dp(_f64(dloss_dd)), _dp(dl), _dp(dw), C.byref(loss))
     assert rc == 0, rc
     return dl, dw, loss.value
 

@@ -25,7 +25,8 @@
 int32_t orc_input_width(const orc_net* net) { return 3 + net->F + 6 * net->L; }
 
 static int layer_in(const orc_net* net, int i) { return i == 0 ? orc_input_width(net) : net->c; }
-static int layer_out(const orc_net* net, int i) { return i == net->H ? 1 : net->c; }
+static int n_outputs(const orc_net* net) { return net->outputs > 1 ? net->outputs : 1; }
+static int layer_out(const orc_net* net, int i) { return i == net->H ? n_outputs(net) : net->c; }
 
 /* Offset of W_i in the packed weight array; b_i follows W_i. */
 static int64_t layer_offset(const orc_net* net, int i) {
@@ -38,6 +39,7 @@ int64_t orc_num_weights(const orc_net* net) { return layer_offset(net, net->H + 
 
 static int net_ok(const orc_net* net) {
   return net && net->R >= 2 && net->F >= 0 && net->K >= 1 && net->L >= 0 && net->c >= 1 &&
+         (net->outputs <= 1 || net->outputs == 4) &&
          net->H >= 1 && net->weights && (net->F == 0 || net->latent || (net->latent_u8 && net->dequant)) &&
          (net->K == 1 || net->key_times);
 }
@@ -186,9 +188,11 @@ static double act_df(int act, double x) {
 static double sigmoid(double y) { return 1.0 / (1.0 + exp(-y)); }
 
 /* v_{i+1} = a(W_i v_i + b_i) for the H activated layers, then the output
-   layer without activation (its sigmoid is applied by the caller). Keeps the
-   pre-activations a_i (H*c values) when pre != NULL. */
-static double mlp_forward(const orc_net* net, const double* v0, double* pre) {
+   layer without activation (the density's sigmoid is applied by the caller).
+   Keeps the pre-activations a_i (H*c values) when pre != NULL and the last
+   hidden layer's output when hlast != NULL; writes all outputs to y (when
+   non-NULL) and returns output 0, the density logit. */
+static double mlp_outputs(const orc_net* net, const double* v0, double* pre, double* hlast, double* y) {
   const int c = net->c, H = net->H;
   int width = orc_input_width(net);
   double* h = (double*)malloc(sizeof(double) * (size_t)(width > c ? width : c) * 2);
@@ -206,11 +210,22 @@ static double mlp_forward(const orc_net* net, const double* v0, double* pre) {
     memcpy(h, hn, sizeof(double) * (size_t)c);
     width = c;
   }
+  const int no = n_outputs(net);
   const double* W = net->weights + layer_offset(net, H);
-  double y = W[c];
-  for (int k = 0; k < c; ++k) y += W[k] * h[k];
+  double y0 = 0.0;
+  for (int j = 0; j < no; ++j) {
+    double s = W[(int64_t)no * c + j];
+    for (int k = 0; k < c; ++k) s += W[(int64_t)j * c + k] * h[k];
+    if (y) y[j] = s;
+    if (j == 0) y0 = s;
+  }
+  if (hlast) memcpy(hlast, h, sizeof(double) * (size_t)c);
   free(h);
-  return y;
+  return y0;
+}
+
+static double mlp_forward(const orc_net* net, const double* v0, double* pre) {
+  return mlp_outputs(net, v0, pre, NULL, NULL);
 }
 
 double orc_mlp_logit(const orc_net* net, const double* v0) {
@@ -258,7 +273,7 @@ double orc_density_grad_fwd(const orc_net* net, const double p[3], double t, dou
     width = c;
   }
   const double* W = net->weights + layer_offset(net, H);
-  double y = W[c], ty[3] = {0.0, 0.0, 0.0};
+  double y = W[(int64_t)n_outputs(net) * c], ty[3] = {0.0, 0.0, 0.0};
   for (int k = 0; k < c; ++k) {
     y += W[k] * h[k];
     for (int a = 0; a < 3; ++a) ty[a] += W[k] * th[k * 3 + a];
@@ -303,6 +318,17 @@ double orc_density_grad_rev(const orc_net* net, const double p[3], double t, dou
   }
   free(v0);
   return d;
+}
+
+double orc_density_grad_pred(const orc_net* net, const double p[3], double t, double g[3]) {
+  if (!net_ok(net) || !g || n_outputs(net) != 4) return NAN;
+  double* v0 = (double*)malloc(sizeof(double) * (size_t)orc_input_width(net));
+  orc_features(net, p, t, v0, NULL);
+  double y[4];
+  mlp_outputs(net, v0, NULL, NULL, y);
+  free(v0);
+  for (int a = 0; a < 3; ++a) g[a] = y[1 + a];
+  return sigmoid(y[0]);
 }
 
 int orc_eval_points(const orc_net* net, const double* xyz, int64_t n, double t, double* out) {
@@ -512,7 +538,10 @@ static void render_pixel(const orc_field* field, const orc_tf* tf, const orc_cam
     double p[3] = {o[0] + tm * dir[0], o[1] + tm * dir[1], o[2] + tm * dir[2]};
     double g[3];
     double d;
-    if (m->phong && m->grad_fd && field->kind == ORC_FIELD_NET) {
+    if (m->phong && m->grad_fd == 2 && field->kind == ORC_FIELD_NET) {
+      /* the network's own gradient outputs (Sec. 6) */
+      d = orc_density_grad_pred(field->net, p, cam->time, g);
+    } else if (m->phong && m->grad_fd == 1 && field->kind == ORC_FIELD_NET) {
       /* finite differences of the network density: the centre and six
          central-difference samples, seven evaluations (Sec. 6) */
       d = orc_density(field->net, p, cam->time);
@@ -590,8 +619,8 @@ int orc_render(const orc_field* field, const orc_tf* tf, const orc_camera* cams,
    the layer inputs and pre-activations, then the chain rule backwards through
    the sigmoid, the layers (W_i^T) and the trilinear latent interpolation. */
 int orc_train_grads(const orc_net* net, const double* xyz, const double* times, int64_t n,
-                    const double* target, const double* dloss_dd, double* d_latent, double* d_weights,
-                    double* loss) {
+                    const double* target, const double* target_grad, double grad_weight,
+                    const double* dloss_dd, double* d_latent, double* d_weights, double* loss) {
   if (!net_ok(net) || n < 0 || !d_latent || !d_weights) return -1;
   if (n > 0 && (!xyz || (!target && !dloss_dd))) return -1;
   const int c = net->c, H = net->H, F = net->F, R = net->R, K0 = orc_input_width(net);
@@ -626,28 +655,41 @@ int orc_train_grads(const orc_net* net, const double* xyz, const double* times, 
       hin = hout;
       width = c;
     }
+    const int no = n_outputs(net);
     const double* Wout = net->weights + layer_offset(net, H);
-    double y = Wout[c];
-    for (int k = 0; k < c; ++k) y += Wout[k] * hin[k];
-    double d = sigmoid(y);
-    /* upstream dL/dd */
-    double g;
+    double yo[4];
+    for (int j = 0; j < no; ++j) {
+      yo[j] = Wout[(int64_t)no * c + j];
+      for (int k = 0; k < c; ++k) yo[j] += Wout[(int64_t)j * c + k] * hin[k];
+    }
+    double d = sigmoid(yo[0]);
+    /* upstream dL/d output: the density through its sigmoid; the predicted
+       gradient outputs (4-output networks with gradient targets) directly */
+    double dy[4] = {0.0, 0.0, 0.0, 0.0};
     if (target) {
       double r = d - target[q];
       total += fabs(r);
-      g = (r > 0.0 ? 1.0 : (r < 0.0 ? -1.0 : 0.0)) / (double)n;
+      dy[0] = (r > 0.0 ? 1.0 : (r < 0.0 ? -1.0 : 0.0)) / (double)n * d * (1.0 - d);
+      if (no == 4 && target_grad)
+        for (int a = 0; a < 3; ++a) {
+          const double rg = yo[1 + a] - target_grad[3 * q + a];
+          total += grad_weight / 3.0 * fabs(rg);
+          dy[1 + a] = grad_weight / 3.0 * (rg > 0.0 ? 1.0 : (rg < 0.0 ? -1.0 : 0.0)) / (double)n;
+        }
     } else {
       total += dloss_dd[q] * d;
-      g = dloss_dd[q];
+      dy[0] = dloss_dd[q] * d * (1.0 - d);
     }
-    double dy = g * d * (1.0 - d);
     /* output layer */
     double* dWout = d_weights + layer_offset(net, H);
-    for (int k = 0; k < c; ++k) {
-      dWout[k] += dy * hin[k];
-      delta[k] = dy * Wout[k];
+    for (int k = 0; k < c; ++k) delta[k] = 0.0;
+    for (int j = 0; j < no; ++j) {
+      for (int k = 0; k < c; ++k) {
+        dWout[(int64_t)j * c + k] += dy[j] * hin[k];
+        delta[k] += dy[j] * Wout[(int64_t)j * c + k];
+      }
+      dWout[(int64_t)no * c + j] += dy[j];
     }
-    dWout[c] += dy;
     /* activated layers, last to first */
     for (int i = H - 1; i >= 0; --i) {
       const int win = layer_in(net, i);

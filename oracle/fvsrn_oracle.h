@@ -19,7 +19,9 @@
  *    frequency pi*2^k of the benchmark configuration).
  *  - Weights: for each layer i = 0..H, W_i[out][in] row-major then b_i[out].
  *    Layer 0 maps K0 = 3+F+6L -> c, layers 1..H-1 map c -> c, layer H maps
- *    c -> 1. Layers 0..H-1 use the activation, layer H the sigmoid (Sec. 3).
+ *    c -> outputs. Layers 0..H-1 use the activation; output 0 of layer H goes
+ *    through the sigmoid (Sec. 3), outputs 1..3 (when present) are the
+ *    predicted density gradient in world units (Sec. 6), used as they are.
  *
  * parity pins: see tests/test_oracle_pins.py. Every function below is pinned
  * by a closed form, an invariant or brute force there; none is "parity
@@ -40,7 +42,8 @@ typedef struct {
   int32_t L;                /* Fourier octaves */
   int32_t c, H;             /* hidden width, activated layers */
   int32_t act;              /* ORC_ACT_* */
-  int32_t pad_;
+  int32_t outputs;          /* 1 (density), or 4: density logit and the predicted
+                               gradient d density / d p (Sec. 6); 0 means 1 */
   const double* latent;     /* [K][R][R][R][F] */
   const double* weights;    /* packed, see header comment */
   const double* key_times;  /* [K] ascending (NULL when K == 1) */
@@ -73,7 +76,8 @@ typedef struct {
   double ert_eps;           /* stop once transmittance < eps (0 = never) */
   double ka, kd, ks, shininess;
   int32_t grad_fd;          /* network field: 0 = analytic (forward mode),
-                               1 = central differences with step fd_step */
+                               1 = central differences with step fd_step,
+                               2 = the network's predicted gradient */
   int32_t pad_;
   double fd_step;
 } orc_march;
@@ -104,6 +108,8 @@ double orc_density(const orc_net* net, const double p[3], double t);
 double orc_density_grad_fwd(const orc_net* net, const double p[3], double t, double g[3]);
 /* Density and gradient by reverse-mode (adjoint) propagation. */
 double orc_density_grad_rev(const orc_net* net, const double p[3], double t, double g[3]);
+/* Density and the gradient the network predicts (outputs 1..3; Sec. 6). */
+double orc_density_grad_pred(const orc_net* net, const double p[3], double t, double g[3]);
 
 int orc_eval_points(const orc_net* net, const double* xyz, int64_t n, double t, double* out);
 
@@ -151,15 +157,18 @@ int orc_render(const orc_field* field, const orc_tf* tf, const orc_camera* cams,
    returns the mean of the map (or -1 on an argument error). */
 double orc_ssim(const double* a, const double* b, int H, int W, double* map);
 
-/* Training (Sec. 3 world-space fitting; Sec. 8 for keyframe grids). Gradients of
+/* Training (Sec. 3 world-space fitting; Sec. 8 for keyframe grids; Sec. 6
+   for gradient-predicting networks). Gradients of
      L1 mode  (target != NULL): loss = mean_i |d(x_i, t_i) - target_i|
+                 + grad_weight / 3 * mean_i sum_a |g_a(x_i, t_i) - target_grad_ia|
+               (the second term only for 4-output networks with target_grad)
      VJP mode (target == NULL): loss = sum_i dloss_dd_i * d(x_i, t_i)
    with respect to all K latent grids and all weights; the gradient arrays are
    overwritten. times (nullable: all 0) gives each point's keyframe time.
    sign(0) = 0 in L1 mode. */
 int orc_train_grads(const orc_net* net, const double* xyz, const double* times, int64_t n,
-                    const double* target, const double* dloss_dd, double* d_latent, double* d_weights,
-                    double* loss);
+                    const double* target, const double* target_grad, double grad_weight,
+                    const double* dloss_dd, double* d_latent, double* d_weights, double* loss);
 /* One bias-corrected Adam update of n parameters at step t >= 1. */
 int orc_adam(double* param, const double* grad, double* m, double* v, int64_t n, double lr,
              double beta1, double beta2, double eps, int32_t t);

@@ -42,9 +42,10 @@ class NetSpec:
     F: int            # latent channels
     L: int            # Fourier octaves
     c: int            # hidden width
-    H: int            # activated (hidden) layers; one c->1 output layer follows
+    H: int            # activated (hidden) layers; one c->outputs output layer follows
     K: int = 1        # latent keyframes
     act: str = "sine"
+    outputs: int = 1  # 1 (density) or 4 (density and its predicted gradient)
 
     @property
     def K0(self) -> int:
@@ -52,7 +53,7 @@ class NetSpec:
 
     def layer_shapes(self) -> List[Tuple[int, int]]:
         """(out, in) of every weight matrix, input layer first."""
-        shapes = [(self.c, self.K0)] + [(self.c, self.c)] * (self.H - 1) + [(1, self.c)]
+        shapes = [(self.c, self.K0)] + [(self.c, self.c)] * (self.H - 1) + [(self.outputs, self.c)]
         return shapes
 
     @property

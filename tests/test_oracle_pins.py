@@ -755,3 +755,95 @@ def test_ssim_against_scipy_gaussian_filtering():
     assert O.ssim(a, a) == 1.0
     ca, cb = np.full((20, 20, 4), 0.3), np.full((20, 20, 4), 0.6)
     assert abs(O.ssim(ca, cb) - (2 * 0.3 * 0.6 + C1) / (0.09 + 0.36 + C1)) < 1e-12
+
+
+def _four_output(spec1, lat, w1, rows, biases):
+    """A 4-output network: the 1-output network's layers, its output row and
+    bias as output 0, and the given rows/biases as outputs 1..3."""
+    spec4 = dataclasses_replace(spec1, outputs=4)
+    c = spec1.c
+    body = w1[:-(c + 1)]
+    w_out0, b0 = w1[-(c + 1):-1], w1[-1]
+    w4 = np.concatenate([body, w_out0, np.asarray(rows, dtype=np.float64).reshape(-1),
+                         [b0], np.asarray(biases, dtype=np.float64)])
+    assert w4.size == spec4.n_weights
+    return spec4, O.Net(spec4, lat, w4)
+
+
+def test_four_output_network_density_and_predicted_gradient():
+    """Output 0 of a 4-output network is the density of the 1-output network
+    with the same layers; outputs 1..3 (the predicted gradient, Sec. 6) are
+    the logits that 1-output networks with those rows and biases produce."""
+    spec = I.NetSpec(R=5, F=3, L=2, c=8, H=2)
+    lat, w = I.net_params(spec, 51)
+    w = w.astype(np.float64)
+    rng = np.random.default_rng(52)
+    rows, biases = rng.normal(size=(3, spec.c)), rng.normal(size=3)
+    spec4, n4 = _four_output(spec, lat, w, rows, biases)
+    n1 = O.Net(spec, lat, w)
+    xyz = RNG.uniform(-1, 1, size=(25, 3))
+    np.testing.assert_array_equal(O.eval_points(n4, xyz), O.eval_points(n1, xyz))
+    for a in range(3):
+        wa = w.copy()
+        wa[-(spec.c + 1):-1] = rows[a]
+        wa[-1] = biases[a]
+        na = O.Net(spec, lat, wa)
+        for p in xyz[:5]:
+            v0, _ = O.features(na, p)
+            _, g = O.density_grad(n4, p, mode="pred")
+            assert abs(g[a] - O.mlp_logit(na, v0)) < 1e-13
+
+
+def test_predicted_gradient_phong_closed_form():
+    """Constant predicted gradient (0, 0, 1) (zero gradient rows, biases
+    (0, 0, 1)) seen by an orthographic camera along -z: |n.l| = 1, so the
+    shaded image is (ka + kd) * C + ks * A of the unshaded one."""
+    spec = I.NetSpec(R=5, F=3, L=2, c=8, H=2)
+    lat, w = I.net_params(spec, 53)
+    spec4, n4 = _four_output(spec, lat, w.astype(np.float64), np.zeros((3, spec.c)), [0.0, 0.0, 1.0])
+    tf = I.ramp_tf()
+    cam = I.ortho_camera(9, 7)
+    m = I.March(fixed_steps=40, step=0.0)
+    plain, _ = O.render(O.Field(net=n4), tf, [cam], m)
+    shaded, _ = O.render(O.Field(net=n4), tf, [cam], dataclasses_replace(m, phong=True, grad_mode=2))
+    want = (m.ka + m.kd) * plain[..., :3] + m.ks * plain[..., 3:4]
+    np.testing.assert_allclose(shaded[..., :3], want, rtol=1e-12, atol=1e-15)
+    np.testing.assert_array_equal(shaded[..., 3], plain[..., 3])
+
+
+def test_gradient_target_training_against_central_differences():
+    """L1 training with gradient targets (density error plus grad_weight/3 of
+    the predicted-gradient error): weights and latent gradients against
+    Richardson central differences of the loss computed from evaluations,
+    targets kept away from the predictions so every sign is stable."""
+    spec = I.NetSpec(R=4, F=3, L=2, c=6, H=2, outputs=4)
+    lat, w = I.net_params(spec, 54)
+    net = O.Net(spec, lat, w)
+    n = 15
+    xyz = RNG.uniform(-1, 1, size=(n, 3))
+    d = O.eval_points(net, xyz)
+    gp = np.array([O.density_grad(net, p, mode="pred")[1] for p in xyz])
+    rng = np.random.default_rng(55)
+    tgt = d + rng.uniform(0.05, 0.2, n) * rng.choice([-1, 1], n)
+    tg = gp + rng.uniform(0.05, 0.2, (n, 3)) * rng.choice([-1, 1], (n, 3))
+    lam = 0.7
+    dl, dw, loss = O.train_grads(net, xyz, target=tgt, target_grad=tg, grad_weight=lam)
+
+    def L(lat_, w_):
+        nn_ = O.Net(spec, lat_, w_)
+        dd = O.eval_points(nn_, xyz)
+        gg = np.array([O.density_grad(nn_, p, mode="pred")[1] for p in xyz])
+        return np.abs(dd - tgt).mean() + lam / 3 * np.abs(gg - tg).sum(1).mean()
+
+    assert abs(loss - L(net.latent, net.weights)) < 1e-13
+    h = 1e-5
+    for idx in RNG.choice(spec.n_weights, 20, replace=False):
+        e = np.zeros(spec.n_weights)
+        e[idx] = 1
+        fd = (L(net.latent, net.weights + h * e) - L(net.latent, net.weights - h * e)) / (2 * h)
+        assert abs(dw[idx] - fd) < 1e-8 * max(1, abs(fd))
+    for idx in RNG.choice(net.latent.size, 12, replace=False):
+        e = np.zeros(net.latent.size)
+        e[idx] = 1
+        fd = (L(net.latent + h * e, net.weights) - L(net.latent - h * e, net.weights)) / (2 * h)
+        assert abs(dl[idx] - fd) < 1e-8 * max(1, abs(fd))
