@@ -30,6 +30,9 @@ sys.path.insert(0, ROOT)
 P16_TFLOPS = 2516.6     # MI355X dense FP16/BF16 MFMA
 P32_TFLOPS = 157.3      # MI355X FP32 (matrix and vector)
 HBM_GBS = 8000.0
+# weight of the predicted gradient's L1 term next to the density's when the
+# four-output network is fitted (gradients of the unit-range volume are O(1-10))
+PRED_GRAD_WEIGHT = 0.1
 
 
 def flops_per_sample(spec) -> int:
@@ -285,6 +288,36 @@ def main():
                 shade[name]["image_rmse_vs_dense_phong"] = e
                 shade[name]["image_ssim_vs_dense_phong"] = q
         shade["central_over_forward"] = shade["central"]["ms_per_frame"] / shade["forward"]["ms_per_frame"]
+        if args.train_steps > 0:
+            # the network predicts its own gradient (four outputs, Sec. 6):
+            # the same architecture fitted to densities and to one-voxel
+            # central differences of the volume, shaded from outputs 1..3
+            from paper_2112_01579_amd.trainer import Trainer
+            spec4 = dataclasses.replace(spec, outputs=4)
+            lat4, w4 = I.net_params(spec4, I.SEED_STUDY)
+            p32 = FV.Network(spec4, lat4, w4, grid_dtype=FV.F32, device=dev)
+            ptr = Trainer(p32, vol, batch=1 << 18, seed=I.SEED_TRAIN, grad_weight=PRED_GRAD_WEIGHT)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.train_steps):
+                ptr.step()
+            torch.cuda.synchronize()
+            t_train = time.perf_counter() - t0
+            pnet = FV.Network(spec4, p32.latent.cpu().numpy(), p32.weights.cpu().numpy(), grid_dtype=FV.F16,
+                              device=dev)
+            m_pred = dataclasses.replace(m_dense, grad_mode=2)
+            FV.fvsrn_render(pnet, tf, cams, m_pred, "f16", out=out)
+            torch.cuda.synchronize()
+            e, q = rmse(out), ssim(out)
+            per_c, _ = time_launches(lambda: FV.fvsrn_render(pnet, tf, cams, m_pred, "f16", out=out), 3, 1)
+            shade["predicted"] = {"ms_per_frame": float(np.mean(per_c)) / len(cams),
+                                  "image_rmse_vs_dense_phong": e, "image_ssim_vs_dense_phong": q,
+                                  "training": {"steps": args.train_steps, "batch": 1 << 18,
+                                               "grad_weight": PRED_GRAD_WEIGHT, "final_loss": float(ptr.loss.item()),
+                                               "ms_per_step": t_train / args.train_steps * 1e3}}
+            for k in ("forward", "central"):
+                shade[k + "_over_predicted"] = shade[k]["ms_per_frame"] / shade["predicted"]["ms_per_frame"]
+            del ptr, p32, pnet
         comp["shading_f16"] = shade
         # time-varying workload (Sec. 8): keyframe latent grids every 4 timesteps
         # trained on all 16 timesteps of the 256^3 advected-blob field, then 8

@@ -35,9 +35,9 @@
  *  - Weights (FP32 master copy, the layout the trainer updates): for each
  *    layer i = 0..H, W_i[out][in] row-major, then b_i[out]. Layer 0 maps
  *    K0 = 3 + F + 6L inputs to c channels, layers 1..H-1 map c to c, layer H
- *    maps c to 1. Layers 0..H-1 apply the activation (sine: sin(x);
- *    SnakeAlt: 0.5x + sin^2(x), Sec. 5 Eq. 3), layer H the sigmoid, giving a
- *    density in (0,1) (Sec. 3).
+ *    maps c to num_outputs (1, or 4 for a predicted gradient). Layers 0..H-1
+ *    apply the activation (sine: sin(x); SnakeAlt: 0.5x + sin^2(x), Sec. 5
+ *    Eq. 3); the sigmoid of output 0 is the density in (0,1) (Sec. 3).
  */
 #ifndef FVSRN_H
 #define FVSRN_H
@@ -73,11 +73,15 @@ typedef struct {
   int32_t num_keyframes; /* K >= 1; K > 1 interpolates latent grids in time (Sec. 8) */
   int32_t num_freqs;     /* L: Fourier octaves */
   int32_t hidden_width;  /* c */
-  int32_t hidden_layers; /* H activated layers, followed by the c -> 1 output layer */
+  int32_t hidden_layers; /* H activated layers, followed by the c -> num_outputs output layer */
   int32_t activation;    /* fvsrn_act */
   int32_t precision;     /* network arithmetic: FVSRN_F32 (FP32 MFMA), FVSRN_F16 or
                             FVSRN_BF16 (MFMA with FP32 accumulation). Interpolation,
                             phases, sigmoid, TF and compositing are FP32 always. */
+  int32_t num_outputs;   /* 1: the density logit; 4: the logit followed by a predicted
+                            density gradient d density / d p (Sec. 6). 0 means 1. The
+                            output layer holds W_out [num_outputs][c] then b_out
+                            [num_outputs]; the density is the sigmoid of output 0. */
 } fvsrn_net_desc;
 
 typedef struct {
@@ -128,9 +132,11 @@ typedef struct {
    network, grad_mode selects how the gradient is obtained (Sec. 6):
    FVSRN_GRAD_FORWARD differentiates the network in forward mode;
    FVSRN_GRAD_CENTRAL takes central differences of the network density with
-   step fd_step (> 0, world units): seven network evaluations per sample.
+   step fd_step (> 0, world units): seven network evaluations per sample;
+   FVSRN_GRAD_PREDICTED uses outputs 1..3 of a num_outputs == 4 network as the
+   gradient (one evaluation per sample, no differentiation).
    Dense-grid rendering always uses one-voxel central differences. */
-typedef enum { FVSRN_GRAD_FORWARD = 0, FVSRN_GRAD_CENTRAL = 1 } fvsrn_grad_mode;
+typedef enum { FVSRN_GRAD_FORWARD = 0, FVSRN_GRAD_CENTRAL = 1, FVSRN_GRAD_PREDICTED = 2 } fvsrn_grad_mode;
 typedef struct {
   float step;
   int32_t fixed_steps;
@@ -150,9 +156,10 @@ typedef struct {
    [0]/[2] is the occupancy of the matrix tiles). A wave marches 64 rays
    without shading, 16 with forward-mode gradients and 8 with central
    differences. Phong shading needs the density gradient, obtained as
-   march->grad_mode selects (Sec. 6). Central differences are built for the
-   sine activation and FP32/FP16 networks; other combinations return
-   FVSRN_ERR_UNSUPPORTED. */
+   march->grad_mode selects (Sec. 6). Forward mode and central differences
+   are built for FP32/FP16 networks (central differences and predicted
+   gradients for the sine activation only); other combinations return
+   FVSRN_ERR_UNSUPPORTED. Predicted gradients need num_outputs == 4. */
 fvsrn_status fvsrn_render(const fvsrn_net_desc* desc, const fvsrn_params* params,
                           const fvsrn_tf* tf, const fvsrn_camera* cams, int32_t n_views,
                           const fvsrn_march* march, float* out_rgba,
@@ -172,6 +179,13 @@ fvsrn_status fvsrn_grad_points(const fvsrn_net_desc* desc, const fvsrn_params* p
                                const float* xyz, int64_t n, float time, float* out_density,
                                float* out_grad, void* stream);
 
+/* Density and the network's own gradient prediction (outputs 1..3 of a
+   num_outputs == 4 network, Sec. 6) at n points, one plain evaluation each.
+   out_density nullable [n]; out_grad [n][3]. */
+fvsrn_status fvsrn_pred_grad_points(const fvsrn_net_desc* desc, const fvsrn_params* params,
+                                    const float* xyz, int64_t n, float time, float* out_density,
+                                    float* out_grad, void* stream);
+
 /* [host] Adam state for fvsrn_train_step (bias-corrected; PyTorch's form
    p -= lr/(1-b1^t) * m / (sqrt(v)/sqrt(1-b2^t) + eps)). */
 typedef struct {
@@ -187,6 +201,9 @@ typedef struct {
    Sec. 8 for keyframe grids). FP32 latent grids and FP32 weights, FP32
    arithmetic.
      L1 mode  (target != NULL): loss = mean |d(x_i, t_i) - target_i|, sign(0) = 0.
+       For a num_outputs == 4 network with target_grad != NULL ([n][3]) the
+       predicted gradient g_i (outputs 1..3) is fitted as well (Sec. 6):
+       loss += grad_weight / 3 * mean sum_a |g_i,a - target_grad_i,a|.
      VJP mode (target == NULL): loss = sum dloss_dy_i * d(x_i, t_i) (the
        gradient of any downstream loss, e.g. from autograd).
    latent [K][R^3 F]; key_times [host, K] strictly ascending (NULL when
@@ -202,8 +219,8 @@ typedef struct {
 fvsrn_status fvsrn_train_step(const fvsrn_net_desc* desc, float* latent, float* weights,
                               const float* key_times, float* d_latent, float* d_weights,
                               const float* xyz, const float* times, int64_t n,
-                              const float* target, const float* dloss_dy,
-                              const fvsrn_adam* adam, float* out_loss, void* workspace,
+                              const float* target, const float* target_grad, float grad_weight,
+                              const float* dloss_dy, const fvsrn_adam* adam, float* out_loss, void* workspace,
                               size_t workspace_bytes, void* stream);
 size_t fvsrn_train_workspace_size(const fvsrn_net_desc* desc, int64_t n);
 
@@ -221,6 +238,14 @@ fvsrn_status fvsrn_render_dense(const float* vol, int32_t nx, int32_t ny, int32_
    the original volume, Sec. 3). */
 fvsrn_status fvsrn_dense_eval_points(const float* vol, int32_t nx, int32_t ny, int32_t nz,
                                      const float* xyz, int64_t n, float* out, void* stream);
+
+/* Trilinear samples and their gradient by central differences with a
+   one-voxel step per axis (2 / (n_axis - 1) world units, as the dense
+   renderer shades, Sec. 6): the gradient targets of predicted-gradient
+   training. out_density nullable [n]; out_grad [n][3]. */
+fvsrn_status fvsrn_dense_grad_points(const float* vol, int32_t nx, int32_t ny, int32_t nz,
+                                     const float* xyz, int64_t n, float* out_density,
+                                     float* out_grad, void* stream);
 
 /* n uniform points in [-1,1)^3 from a Philox4x32-10 counter-based generator
    (Salmon et al., SC'11): point i uses counter (i, counter_lo, counter_hi, 0)

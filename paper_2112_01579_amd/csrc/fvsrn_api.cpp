@@ -25,9 +25,11 @@ fvsrn_status fail(fvsrn_status s, const char* fmt, ...) {
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
+int n_outputs(const fvsrn_net_desc& d) { return d.num_outputs == 0 ? 1 : d.num_outputs; }
+
 int64_t num_weights(const fvsrn_net_desc& d) {
-  const int64_t K0 = 3 + d.grid_channels + 6 * (int64_t)d.num_freqs, c = d.hidden_width;
-  return c * K0 + c + (int64_t)(d.hidden_layers - 1) * (c * c + c) + c + 1;
+  const int64_t K0 = 3 + d.grid_channels + 6 * (int64_t)d.num_freqs, c = d.hidden_width, no = n_outputs(d);
+  return c * K0 + c + (int64_t)(d.hidden_layers - 1) * (c * c + c) + no * c + no;
 }
 
 fvsrn_status check_desc(const fvsrn_net_desc* d) {
@@ -51,6 +53,8 @@ fvsrn_status check_desc(const fvsrn_net_desc* d) {
   if (d->hidden_width != 32 && d->hidden_width != 48)
     return fail(FVSRN_ERR_UNSUPPORTED, "hidden_width %d not compiled; supported 32, 48", d->hidden_width);
   if (d->hidden_layers > 8) return fail(FVSRN_ERR_UNSUPPORTED, "hidden_layers %d > 8", d->hidden_layers);
+  if (d->num_outputs != 0 && d->num_outputs != 1 && d->num_outputs != 4)
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "num_outputs %d: must be 1 or 4 (0 means 1)", d->num_outputs);
   // the kernels address one keyframe grid with 32-bit byte offsets
   const long long grid_bytes = (long long)d->grid_res * d->grid_res * d->grid_res * d->grid_channels *
                                (d->grid_dtype == FVSRN_U8 ? 1 : (d->grid_dtype == FVSRN_F16 ? 2 : 4));
@@ -92,6 +96,7 @@ NetDev make_net(const fvsrn_net_desc* d, const void* latent, const float* weight
   n.key_stride = (long long)d->grid_res * d->grid_res * d->grid_res * d->grid_channels;
   n.grid_u8 = d->grid_dtype == FVSRN_U8;
   n.dequant = n.grid_u8 ? dequant : nullptr;
+  n.NO = n_outputs(*d);
   return n;
 }
 
@@ -188,7 +193,8 @@ fvsrn_status check_cams(const fvsrn_camera* cams, int32_t n_views, const fvsrn_m
   if (m->fixed_steps == 0 && !(m->step >= 1.0f / 65536.0f))
     return fail(FVSRN_ERR_INVALID_ARGUMENT, "step must be >= 2^-16 world units");
   if (!(m->ert_eps >= 0.0f) || m->ert_eps > 1.0f) return fail(FVSRN_ERR_INVALID_ARGUMENT, "ert_eps outside [0, 1]");
-  if (m->grad_mode != FVSRN_GRAD_FORWARD && m->grad_mode != FVSRN_GRAD_CENTRAL)
+  if (m->grad_mode != FVSRN_GRAD_FORWARD && m->grad_mode != FVSRN_GRAD_CENTRAL &&
+      m->grad_mode != FVSRN_GRAD_PREDICTED)
     return fail(FVSRN_ERR_INVALID_ARGUMENT, "grad_mode unknown");
   if (m->phong && m->grad_mode == FVSRN_GRAD_CENTRAL && !(m->fd_step > 0.0f && m->fd_step < 1.0f))
     return fail(FVSRN_ERR_INVALID_ARGUMENT, "fd_step must be in (0, 1) for central differences");
@@ -248,6 +254,8 @@ fvsrn_status fvsrn_render(const fvsrn_net_desc* desc, const fvsrn_params* params
   if ((s = check_desc(desc)) != FVSRN_OK) return s;
   if ((s = check_params(desc, params)) != FVSRN_OK) return s;
   if ((s = check_cams(cams, n_views, march)) != FVSRN_OK) return s;
+  if (march->phong && march->grad_mode == FVSRN_GRAD_PREDICTED && n_outputs(*desc) != 4)
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "predicted gradients need a network with num_outputs == 4");
   if (!out_rgba || !aligned16(out_rgba)) return fail(FVSRN_ERR_INVALID_ARGUMENT, "out_rgba NULL or misaligned");
   if (stats && ((uintptr_t)stats & 7u)) return fail(FVSRN_ERR_INVALID_ARGUMENT, "stats misaligned");
   TFDev tfd;
@@ -280,7 +288,7 @@ fvsrn_status fvsrn_eval_points(const fvsrn_net_desc* desc, const fvsrn_params* p
   float kw;
   key_blend(desc, params, time, &key, &kw);
   const NetDev nd = make_net(desc, params->latent, params->weights, params->latent_dequant);
-  return launch_status(launch_points(nd, desc->precision, xyz, n, key, kw, out_density, nullptr, stream),
+  return launch_status(launch_points(nd, desc->precision, xyz, n, key, kw, out_density, nullptr, 0, stream),
                        "fvsrn_eval_points");
 }
 
@@ -299,8 +307,29 @@ fvsrn_status fvsrn_grad_points(const fvsrn_net_desc* desc, const fvsrn_params* p
   float kw;
   key_blend(desc, params, time, &key, &kw);
   const NetDev nd = make_net(desc, params->latent, params->weights, params->latent_dequant);
-  return launch_status(launch_points(nd, desc->precision, xyz, n, key, kw, out_density, out_grad, stream),
+  return launch_status(launch_points(nd, desc->precision, xyz, n, key, kw, out_density, out_grad, 0, stream),
                        "fvsrn_grad_points");
+}
+
+fvsrn_status fvsrn_pred_grad_points(const fvsrn_net_desc* desc, const fvsrn_params* params, const float* xyz,
+                                    int64_t n, float time, float* out_density, float* out_grad, void* stream) {
+  g_err[0] = 0;
+  if (n > 0 && !out_grad) return fail(FVSRN_ERR_INVALID_ARGUMENT, "out_grad is NULL");
+  fvsrn_status s;
+  if ((s = check_desc(desc)) != FVSRN_OK) return s;
+  if ((s = check_params(desc, params)) != FVSRN_OK) return s;
+  if (n_outputs(*desc) != 4)
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "predicted gradients need a network with num_outputs == 4");
+  if (n < 0) return fail(FVSRN_ERR_INVALID_ARGUMENT, "n < 0");
+  if (n == 0) return FVSRN_OK;
+  if (!xyz || !aligned16(xyz) || !aligned16(out_grad) || (out_density && !aligned16(out_density)))
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "xyz / outputs NULL or misaligned");
+  int key;
+  float kw;
+  key_blend(desc, params, time, &key, &kw);
+  const NetDev nd = make_net(desc, params->latent, params->weights, params->latent_dequant);
+  return launch_status(launch_points(nd, desc->precision, xyz, n, key, kw, out_density, out_grad, 1, stream),
+                       "fvsrn_pred_grad_points");
 }
 
 size_t fvsrn_train_workspace_size(const fvsrn_net_desc* desc, int64_t n) {
@@ -311,7 +340,8 @@ size_t fvsrn_train_workspace_size(const fvsrn_net_desc* desc, int64_t n) {
 
 fvsrn_status fvsrn_train_step(const fvsrn_net_desc* desc, float* latent, float* weights, const float* key_times,
                               float* d_latent, float* d_weights, const float* xyz, const float* times, int64_t n,
-                              const float* target, const float* dloss_dy, const fvsrn_adam* adam, float* out_loss,
+                              const float* target, const float* target_grad, float grad_weight,
+                              const float* dloss_dy, const fvsrn_adam* adam, float* out_loss,
                               void* workspace, size_t workspace_bytes, void* stream) {
   g_err[0] = 0;
   fvsrn_status s;
@@ -333,6 +363,14 @@ fvsrn_status fvsrn_train_step(const fvsrn_net_desc* desc, float* latent, float* 
   if (n < 0) return fail(FVSRN_ERR_INVALID_ARGUMENT, "n < 0");
   if (n > 0 && (!xyz || !aligned16(xyz))) return fail(FVSRN_ERR_INVALID_ARGUMENT, "xyz NULL or misaligned");
   if (n > 0 && !target && !dloss_dy) return fail(FVSRN_ERR_INVALID_ARGUMENT, "target or dloss_dy required");
+  if (target_grad) {
+    if (!target) return fail(FVSRN_ERR_INVALID_ARGUMENT, "target_grad needs target (L1 mode)");
+    if (n_outputs(*desc) != 4)
+      return fail(FVSRN_ERR_INVALID_ARGUMENT, "target_grad needs a network with num_outputs == 4");
+    if (!(grad_weight >= 0.0f) || grad_weight > 1e30f)
+      return fail(FVSRN_ERR_INVALID_ARGUMENT, "grad_weight must be finite and >= 0");
+    if ((uintptr_t)target_grad & 3u) return fail(FVSRN_ERR_INVALID_ARGUMENT, "target_grad misaligned");
+  }
   if (adam) {
     if (adam->step < 1) return fail(FVSRN_ERR_INVALID_ARGUMENT, "adam.step must be >= 1");
     if (!adam->m_latent || !adam->v_latent || !adam->m_weights || !adam->v_weights)
@@ -345,8 +383,8 @@ fvsrn_status fvsrn_train_step(const fvsrn_net_desc* desc, float* latent, float* 
   KeyTimes kt;
   kt.K = desc->num_keyframes;
   for (int k = 0; k < kMaxKeyframes; ++k) kt.t[k] = (k < kt.K && key_times) ? key_times[k] : 0.0f;
-  const int rc = launch_train(nd, kt, latent, weights, d_latent, d_weights, xyz, times, n, target, dloss_dy,
-                              adam != nullptr,
+  const int rc = launch_train(nd, kt, latent, weights, d_latent, d_weights, xyz, times, n, target, target_grad,
+                              target_grad ? grad_weight : 0.0f, dloss_dy, adam != nullptr,
                               adam ? adam->lr_grid : 0.f, adam ? adam->lr_mlp : 0.f, adam ? adam->beta1 : 0.f,
                               adam ? adam->beta2 : 0.f, adam ? adam->eps : 0.f, adam ? adam->step : 0,
                               adam ? adam->m_latent : nullptr, adam ? adam->v_latent : nullptr,
@@ -409,7 +447,22 @@ fvsrn_status fvsrn_dense_eval_points(const float* vol, int32_t nx, int32_t ny, i
   if (n == 0) return FVSRN_OK;
   if (!xyz || !out || !aligned16(xyz) || !aligned16(out))
     return fail(FVSRN_ERR_INVALID_ARGUMENT, "xyz / out NULL or misaligned");
-  return launch_status(launch_dense_points(vol, nx, ny, nz, xyz, n, out, stream), "fvsrn_dense_eval_points");
+  return launch_status(launch_dense_points(vol, nx, ny, nz, xyz, n, out, nullptr, stream),
+                       "fvsrn_dense_eval_points");
+}
+
+fvsrn_status fvsrn_dense_grad_points(const float* vol, int32_t nx, int32_t ny, int32_t nz, const float* xyz,
+                                     int64_t n, float* out_density, float* out_grad, void* stream) {
+  g_err[0] = 0;
+  if (!vol || !aligned16(vol)) return fail(FVSRN_ERR_INVALID_ARGUMENT, "vol NULL or misaligned");
+  if (nx < 2 || ny < 2 || nz < 2) return fail(FVSRN_ERR_INVALID_ARGUMENT, "volume needs >= 2 vertices per axis");
+  if (n < 0) return fail(FVSRN_ERR_INVALID_ARGUMENT, "n < 0");
+  if (n == 0) return FVSRN_OK;
+  if (!xyz || !out_grad || !aligned16(xyz) || ((uintptr_t)out_grad & 3u) ||
+      (out_density && ((uintptr_t)out_density & 3u)))
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "xyz / out_grad NULL or misaligned");
+  return launch_status(launch_dense_points(vol, nx, ny, nz, xyz, n, out_density, out_grad, stream),
+                       "fvsrn_dense_grad_points");
 }
 
 fvsrn_status fvsrn_sample_points(uint64_t seed, uint64_t counter, int64_t n, float* xyz, void* stream) {

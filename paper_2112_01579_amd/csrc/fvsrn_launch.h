@@ -54,6 +54,7 @@ struct NetDev {
   long long key_stride;  // elements between keyframe grids
   int grid_u8;           // uint8 codes; dequant holds (offset, scale) [K][F][2]
   const float* dequant;
+  int NO;                // outputs: 1 (density) or 4 (density, predicted gradient)
 };
 
 struct ViewBatch {
@@ -67,13 +68,16 @@ enum Prec { kF32 = 0, kF16 = 1, kBF16 = 2, kU8 = 3 };
 // 2 on a HIP launch error. `stream` is a hipStream_t.
 int launch_render(const NetDev& net, int prec, const TFDev& tf, const ViewBatch& views,
                   const MarchDev& m, float* out, unsigned long long* stats, void* stream);
+// pred: out_g receives outputs 1..3 of a 4-output network (value mode);
+// otherwise a non-null out_g asks for the forward-mode gradient.
 int launch_points(const NetDev& net, int prec, const float* xyz, long long n, int key,
-                  float key_w, float* out_d, float* out_g, void* stream);
+                  float key_w, float* out_d, float* out_g, int pred, void* stream);
 int launch_render_dense(const float* vol, int nx, int ny, int nz, const TFDev& tf,
                         const ViewBatch& views, const MarchDev& m, float* out,
                         unsigned long long* stats, void* stream);
+// out nullable; out_g (nullable) receives one-voxel central differences
 int launch_dense_points(const float* vol, int nx, int ny, int nz, const float* xyz, long long n,
-                        float* out, void* stream);
+                        float* out, float* out_g, void* stream);
 int launch_sample_points(uint64_t seed, uint64_t counter, long long n, float* xyz, void* stream);
 int launch_cast(const float* src, void* dst, long long count, int dst_dtype, void* stream);
 int launch_ssim(const float* a, const float* b, int width, int height, int n_images, float* out, void* stream);
@@ -83,7 +87,7 @@ int launch_quantize(const float* src, long long n, int channels, unsigned char* 
 size_t train_workspace_bytes(const NetDev& net, long long n);
 int launch_train(const NetDev& net, const KeyTimes& kt, float* latent, float* weights, float* d_latent,
                  float* d_weights, const float* xyz, const float* times, long long n, const float* target,
-                 const float* dloss_dy, int use_adam, float lr_grid, float lr_mlp, float beta1, float beta2,
+                 const float* target_grad, float grad_weight, const float* dloss_dy, int use_adam, float lr_grid, float lr_mlp, float beta1, float beta2,
                  float eps, int step, float* m_lat, float* v_lat, float* m_w, float* v_w, float* out_loss,
                  void* workspace, size_t ws_bytes, void* stream);
 
@@ -101,8 +105,8 @@ int launch_render_p1(const NetDev&, const TFDev&, const ViewBatch&, const MarchD
                      void*);
 int launch_render_p2(const NetDev&, const TFDev&, const ViewBatch&, const MarchDev&, float*, unsigned long long*,
                      void*);
-int launch_points_p0(const NetDev&, const float*, long long, int, float, float*, float*, void*);
-int launch_points_p1(const NetDev&, const float*, long long, int, float, float*, float*, void*);
-int launch_points_p2(const NetDev&, const float*, long long, int, float, float*, float*, void*);
+int launch_points_p0(const NetDev&, const float*, long long, int, float, float*, float*, int, void*);
+int launch_points_p1(const NetDev&, const float*, long long, int, float, float*, float*, int, void*);
+int launch_points_p2(const NetDev&, const float*, long long, int, float, float*, float*, int, void*);
 
 }  // namespace fvsrn_detail

@@ -5,7 +5,9 @@
 // Render: one wavefront owns a tile of rays -- 8x8 pixels without shading,
 // 4x4 pixels (four lanes per ray: value and three tangents) for forward-mode
 // gradients, 4x2 pixels (eight lanes per ray: centre and six central-difference
-// neighbours) for finite-difference gradients. Per march step every lane
+// neighbours) for finite-difference gradients; a network that predicts its
+// own gradient (four outputs) shades from 8x8 tiles like the unshaded render.
+// Per march step every lane
 // builds its input row, the wave runs the MLP on the matrix cores, and the
 // ray-owning lanes map the density through the transfer function and
 // composite front to back (Sec. 3, Sec. 4), stopping when the transmittance
@@ -21,8 +23,8 @@ namespace fvsrn_detail {
 namespace {
 
 // Shading modes of the render kernel: none, forward-mode gradient, central
-// differences (Sec. 6).
-enum { kShadeNone = 0, kShadeFwd = 1, kShadeFD = 2 };
+// differences, the network's predicted gradient (Sec. 6).
+enum { kShadeNone = 0, kShadeFwd = 1, kShadeFD = 2, kShadePred = 3 };
 
 // Waves per workgroup cap (sets the VGPR budget through the launch bounds):
 // value-mode networks with the packed FP16 latent path fit 4 waves per SIMD
@@ -44,8 +46,8 @@ constexpr int max_waves() {
 // Render tile geometry per shading mode: lanes per ray and tile edges.
 template <int MODE>
 struct TileShape {
-  static constexpr int LPR = MODE == kShadeNone ? 1 : (MODE == kShadeFwd ? 4 : 8);
-  static constexpr int TW = MODE == kShadeNone ? 8 : 4;
+  static constexpr int LPR = (MODE == kShadeNone || MODE == kShadePred) ? 1 : (MODE == kShadeFwd ? 4 : 8);
+  static constexpr int TW = LPR == 1 ? 8 : 4;
   static constexpr int TH = 64 / LPR / TW;
 };
 constexpr int kLdsBytes = 160 * 1024;
@@ -255,10 +257,17 @@ __global__ __launch_bounds__((max_waves<CF, MODE>() * 64)) void march_kernel(Net
       sz = active ? sz : 0.0f;
       write_features<CF, GRAD>(myrow, ls, role, sx, sy, sz);
       wave_lds_sync();
-      const float y = mlp_tile<CF, GRAD>(smem, feat, nd.H, role);
+      const f4 yo = mlp_tile<CF, GRAD>(smem, feat, nd.H, role);
       wave_lds_sync();
+      const float y = yo[0];
       float dens, gx = 0.0f, gy = 0.0f, gz = 0.0f;
-      if constexpr (GRAD) {
+      if constexpr (MODE == kShadePred) {
+        // outputs 1..3 are the gradient itself
+        dens = sigmoid_f(y);
+        gx = yo[1];
+        gy = yo[2];
+        gz = yo[3];
+      } else if constexpr (GRAD) {
         // the quad's value lane holds the logit, lanes 1..3 its derivatives
         const float y0 = quad_bcast0(y);
         const float t1 = quad_bcast<1>(y), t2 = quad_bcast<2>(y), t3 = quad_bcast<3>(y);
@@ -312,6 +321,8 @@ __global__ __launch_bounds__((max_waves<CF, MODE>() * 64)) void march_kernel(Net
   }
 }
 
+// Point evaluation: density only, forward-mode gradient (GRAD), or the
+// predicted gradient of a 4-output network (value mode with out_g set).
 template <class CF, bool GRAD>
 __global__ __launch_bounds__((max_waves<CF, GRAD ? kShadeFwd : kShadeNone>() * 64)) void points_kernel(NetDev nd, const float* xyz, long long n, int key,
                                                                 float key_w, float* out_d, float* out_g) {
@@ -339,8 +350,9 @@ __global__ __launch_bounds__((max_waves<CF, GRAD ? kShadeFwd : kShadeNone>() * 6
     }
     write_features<CF, GRAD>(myrow, ls, role, x, y, z);
     wave_lds_sync();
-    const float o = mlp_tile<CF, GRAD>(smem, feat, nd.H, role);
+    const f4 oo = mlp_tile<CF, GRAD>(smem, feat, nd.H, role);
     wave_lds_sync();
+    const float o = oo[0];
     if constexpr (GRAD) {
       const float d = sigmoid_f(quad_bcast0(o));
       if (ok) {
@@ -350,8 +362,13 @@ __global__ __launch_bounds__((max_waves<CF, GRAD ? kShadeFwd : kShadeNone>() * 6
           out_g[3 * idx + role.axis] = d * (1.0f - d) * o;
         }
       }
-    } else {
-      if (ok) out_d[idx] = sigmoid_f(o);
+    } else if (ok) {
+      if (out_d) out_d[idx] = sigmoid_f(o);
+      if (out_g) {
+        out_g[3 * idx] = oo[1];
+        out_g[3 * idx + 1] = oo[2];
+        out_g[3 * idx + 2] = oo[3];
+      }
     }
   }
 }
@@ -412,6 +429,7 @@ struct Entry {
   }
   static int points(const NetDev& nd, const float* xyz, long long n, int key, float key_w, float* out_d,
                     float* out_g, hipStream_t st) {
+    // predicted gradients use the value-mode kernel (its out_g holds outputs 1..3)
     return launch_points_t<CF, MODE == kShadeFwd>(nd, xyz, n, key, key_w, out_d, out_g, st);
   }
 };
@@ -444,6 +462,7 @@ struct Entry {
   FV_NETS(X, kIdentity, kShadeFwd)
 
 #define FV_ALL_FD(X) FV_NETS(X, kSine, kShadeFD)
+#define FV_ALL_PRED(X) FV_NETS(X, kSine, kShadePred)
 
 }  // namespace
 
@@ -452,7 +471,7 @@ struct Entry {
 
 int FV_PASTE(launch_render_p, FVSRN_PREC)(const NetDev& nd, const TFDev& tf, const ViewBatch& vb, const MarchDev& m,
                                           float* out, unsigned long long* stats, void* stream) {
-  const int mode = !m.phong ? kShadeNone : (m.grad_mode == 1 ? kShadeFD : kShadeFwd);
+  const int mode = !m.phong ? kShadeNone : (m.grad_mode == 1 ? kShadeFD : (m.grad_mode == 2 ? kShadePred : kShadeFwd));
   // packed FP16 gathers for an FP16 network on an FP16 or uint8 grid
   const int gk = FVSRN_PREC != 1 ? 0 : (nd.grid_u8 ? 2 : (nd.grid_f16 ? 1 : 0));
   const hipStream_t st = (hipStream_t)stream;
@@ -460,6 +479,7 @@ int FV_PASTE(launch_render_p, FVSRN_PREC)(const NetDev& nd, const TFDev& tf, con
   if (nd.C == C_ && nd.F == F_ && nd.L == L_ && nd.act == ACT_ && mode == MODE_ && gk == GK_) \
     return Entry<C_, F_, L_, ACT_, MODE_, GK_>::render(nd, tf, vb, m, out, stats, st);
   FV_ALL(X)
+  FV_ALL_PRED(X)
 #if FVSRN_PREC != 2
   FV_ALL_GRAD(X)
   FV_ALL_FD(X)
@@ -469,8 +489,8 @@ int FV_PASTE(launch_render_p, FVSRN_PREC)(const NetDev& nd, const TFDev& tf, con
 }
 
 int FV_PASTE(launch_points_p, FVSRN_PREC)(const NetDev& nd, const float* xyz, long long n, int key, float key_w,
-                                          float* out_d, float* out_g, void* stream) {
-  const int mode = out_g != nullptr ? kShadeFwd : kShadeNone;
+                                          float* out_d, float* out_g, int pred, void* stream) {
+  const int mode = (out_g != nullptr && !pred) ? kShadeFwd : kShadeNone;
   // packed FP16 gathers for an FP16 network on an FP16 or uint8 grid
   const int gk = FVSRN_PREC != 1 ? 0 : (nd.grid_u8 ? 2 : (nd.grid_f16 ? 1 : 0));
   const hipStream_t st = (hipStream_t)stream;

@@ -181,11 +181,24 @@ __global__ __launch_bounds__(kDenseThreads) void dense_march_kernel(const float*
   }
 }
 
+// Samples (out, nullable) and one-voxel central-difference gradients (out_g,
+// nullable) of the dense grid, as the dense renderer shades.
 __global__ void dense_points_kernel(const float* vol, int nx, int ny, int nz, const float* xyz,
-                                    long long n, float* out) {
+                                    long long n, float* out, float* out_g) {
+  const float hx = 2.0f / (float)(nx - 1), hy = 2.0f / (float)(ny - 1), hz = 2.0f / (float)(nz - 1);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x)
-    out[i] = dense_sample(vol, nx, ny, nz, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
+       i += (long long)gridDim.x * blockDim.x) {
+    const float x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
+    if (out) out[i] = dense_sample(vol, nx, ny, nz, x, y, z);
+    if (out_g) {
+      out_g[3 * i] = (dense_sample(vol, nx, ny, nz, x + hx, y, z) - dense_sample(vol, nx, ny, nz, x - hx, y, z)) /
+                     (2.0f * hx);
+      out_g[3 * i + 1] =
+          (dense_sample(vol, nx, ny, nz, x, y + hy, z) - dense_sample(vol, nx, ny, nz, x, y - hy, z)) / (2.0f * hy);
+      out_g[3 * i + 2] =
+          (dense_sample(vol, nx, ny, nz, x, y, z + hz) - dense_sample(vol, nx, ny, nz, x, y, z - hz)) / (2.0f * hz);
+    }
+  }
 }
 
 // --------------------------------------------------------- utilities
@@ -366,11 +379,11 @@ int launch_render(const NetDev& net, int prec, const TFDev& tf, const ViewBatch&
 }
 
 int launch_points(const NetDev& net, int prec, const float* xyz, long long n, int key, float key_w, float* out_d,
-                  float* out_g, void* stream) {
+                  float* out_g, int pred, void* stream) {
   switch (prec) {
-    case kF32: return launch_points_p0(net, xyz, n, key, key_w, out_d, out_g, stream);
-    case kF16: return launch_points_p1(net, xyz, n, key, key_w, out_d, out_g, stream);
-    case kBF16: return launch_points_p2(net, xyz, n, key, key_w, out_d, out_g, stream);
+    case kF32: return launch_points_p0(net, xyz, n, key, key_w, out_d, out_g, pred, stream);
+    case kF16: return launch_points_p1(net, xyz, n, key, key_w, out_d, out_g, pred, stream);
+    case kBF16: return launch_points_p2(net, xyz, n, key, key_w, out_d, out_g, pred, stream);
   }
   return 1;
 }
@@ -387,10 +400,10 @@ int launch_render_dense(const float* vol, int nx, int ny, int nz, const TFDev& t
 }
 
 int launch_dense_points(const float* vol, int nx, int ny, int nz, const float* xyz, long long n, float* out,
-                        void* stream) {
+                        float* out_g, void* stream) {
   const int blocks = grid_blocks(n, 256, device_cus() * 16);
   hipLaunchKernelGGL(dense_points_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, vol, nx, ny, nz,
-                     xyz, n, out);
+                     xyz, n, out, out_g);
   return check_launch();
 }
 

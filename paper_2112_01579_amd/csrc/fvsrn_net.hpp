@@ -61,7 +61,7 @@ __device__ void stage_weights(const NetDev& nd, char* smem) {
   using G = typename CF::G;
   using E = typename CF::E;
   constexpr int C = CF::C, F = CF::F, L = CF::L, MT = G::MT;
-  const int H = nd.H, K0 = 3 + F + 6 * L;
+  const int H = nd.H, K0 = 3 + F + 6 * L, NO = nd.NO;
   const float* w = nd.weights;
   const float sc = CF::ACT == kIdentity ? 1.0f : kInv2Pi;
   // a single uint8 keyframe on the packed path: the de-quantisation is folded
@@ -118,10 +118,11 @@ __device__ void stage_weights(const NetDev& nd, char* smem) {
     for (int e = tid; e < 4 * 4 * MT * kWave; e += nt) {
       const int lane = e % kWave, q = (e / kWave) % (4 * MT), t = e / (kWave * 4 * MT);
       const int ch = 16 * (q / 4) + 4 * (lane >> 4) + (q % 4);
-      WO[e] = ((lane & 15) == 4 * t) ? Wo[ch] : 0.0f;
+      const int o = (lane & 15) - 4 * t;  // output o of N-tile t sits in row 4t + o
+      WO[e] = (o >= 0 && o < NO) ? Wo[o * C + ch] : 0.0f;
     }
     p += G::WOA;
-    if (tid == 0) *reinterpret_cast<float*>(p) = Wo[C];
+    if (tid < 4) reinterpret_cast<float*>(p)[tid] = tid < NO ? Wo[NO * C + tid] : 0.0f;
   } else {
     E* W0A = reinterpret_cast<E*>(p);
     for (int e = tid; e < MT * G::S0 * kWave * 8; e += nt) {
@@ -162,18 +163,20 @@ __device__ void stage_weights(const NetDev& nd, char* smem) {
       const int j = e & 7, lane = (e >> 3) & 63, s = (e >> 9) % G::HS32, t = (e >> 9) / G::HS32;
       const int g = lane >> 4;
       const int ch = j < 4 ? 32 * s + 4 * g + j : 32 * s + 16 + 4 * g + (j - 4);
-      WOA[e] = to_e<E>((lane & 15) == 4 * t ? Wo[ch] : 0.0f);
+      const int o = (lane & 15) - 4 * t;  // output o of N-tile t sits in row 4t + o
+      WOA[e] = to_e<E>((o >= 0 && o < NO) ? Wo[o * C + ch] : 0.0f);
     }
     if constexpr (G::HS16) {
       E* WOT = reinterpret_cast<E*>(p + G::WOA);
       for (int e = tid; e < 4 * kWave * 4; e += nt) {
         const int j = e & 3, lane = (e >> 2) & 63, t = e >> 8;
         const int ch = 16 * (MT - 1) + 4 * (lane >> 4) + j;
-        WOT[e] = to_e<E>((lane & 15) == 4 * t ? Wo[ch] : 0.0f);
+        const int o = (lane & 15) - 4 * t;
+        WOT[e] = to_e<E>((o >= 0 && o < NO) ? Wo[o * C + ch] : 0.0f);
       }
     }
     p += G::WOA + G::WOT;
-    if (tid == 0) *reinterpret_cast<float*>(p) = Wo[C];
+    if (tid < 4) reinterpret_cast<float*>(p)[tid] = tid < NO ? Wo[NO * C + tid] : 0.0f;
   }
 }
 
@@ -616,7 +619,7 @@ __device__ inline float act_el(float r, const LaneRole& role) {
 // logit's derivative for tangent lanes). Pairs of N-tiles are processed
 // together so that two independent MFMA / activation chains interleave.
 template <class CF, bool GRAD>
-__device__ inline float mlp_tile(const char* wsm, const typename CF::E* feat, int H, const LaneRole& role) {
+__device__ inline f4 mlp_tile(const char* wsm, const typename CF::E* feat, int H, const LaneRole& role) {
   using G = typename CF::G;
   using PR = PrecT<CF::P>;
   using E = typename CF::E;
@@ -686,8 +689,8 @@ __device__ inline float mlp_tile(const char* wsm, const typename CF::E* feat, in
         }
       }
     }
-    const char* p = wsm + G::W0A + (H - 1) * G::HID + G::WOA;
-    return out[0][0] + out[1][0] + *reinterpret_cast<const float*>(p) * role.qmask;
+    const f4 bo = *reinterpret_cast<const f4*>(wsm + G::W0A + (H - 1) * G::HID + G::WOA);
+    return out[0] + out[1] + bo * role.qmask;
   } else {
     using VA = typename PR::VA;
     using VT = typename PR::VT;
@@ -788,9 +791,9 @@ __device__ inline float mlp_tile(const char* wsm, const typename CF::E* feat, in
         }
       }
     }
-    const char* p = wsm + G::W0A + G::W0T + (H - 1) * G::HID + G::WOA + G::WOT;
-    float y = out[0][0] + out[1][0] + *reinterpret_cast<const float*>(p) * role.qmask;
-    if constexpr (G::HS16) y += out_t[0][0] + out_t[1][0];
+    const f4 bo = *reinterpret_cast<const f4*>(wsm + G::W0A + G::W0T + (H - 1) * G::HID + G::WOA + G::WOT);
+    f4 y = out[0] + out[1] + bo * role.qmask;
+    if constexpr (G::HS16) y += out_t[0] + out_t[1];
     return y;
   }
 }

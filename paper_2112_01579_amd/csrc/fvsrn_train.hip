@@ -8,7 +8,8 @@
 //   1. every lane writes its point's input row to LDS (as in evaluation);
 //   2. forward through the layers on 16x16x4 FP32 MFMA, keeping every
 //      pre-activation a_i in LDS (sample-major);
-//   3. output sigmoid, loss and dL/dy;
+//   3. output sigmoid, loss and dL/dy (for a 4-output network fitted with
+//      gradient targets, also the L1 terms of the predicted gradient, Sec. 6);
 //   4. backward: delta_i = (W_{i+1}^T delta_{i+1}) * act'(a_i) on MFMA with
 //      transposed weight fragments; dW_i = delta_i h_i^T as an MFMA GEMM over
 //      the chunk's samples (A = delta, B = layer input, both read from LDS);
@@ -41,7 +42,8 @@ struct TrainCfg {
   static constexpr int FEAT = S * G::ROW * 4;
   __host__ __device__ static int abuf_bytes(int H) { return H * S * AS * 4; }
   static constexpr int DBUF = S * AS * 4;
-  static constexpr int DY = 64 * 4;
+  static constexpr int DY = 64 * 4;                 // dL/dy [output][sample]
+  static_assert(4 * S <= 64, "four outputs of S samples must fit the dL/dy buffer");
   static constexpr int ZBUF = S * ZS * 4;
   __host__ __device__ static int wave_bytes(int H) { return FEAT + abuf_bytes(H) + DBUF + DY + ZBUF; }
   // backward weight fragments (block-level, after the forward ones)
@@ -51,7 +53,8 @@ struct TrainCfg {
   __host__ __device__ static int block_bytes(int H, int waves) { return G::weight_bytes(H) + back_bytes(H) + waves * wave_bytes(H); }
   // workspace slice (floats)
   __host__ __device__ static int tiles(int H) { return MT * NK0 + (H - 1) * MT * MT + MT + (H - 1) * MT; }
-  __host__ __device__ static int slice(int H) { return tiles(H) * 256 + 128; }
+  // after the tiles: per-lane partials of the four output biases, then of the loss
+  __host__ __device__ static int slice(int H) { return tiles(H) * 256 + 5 * 64; }
   __host__ __device__ static int tile_l0(int mo, int nk) { return mo * NK0 + nk; }
   __host__ __device__ static int tile_h(int H, int i, int mo, int nk) { return MT * NK0 + (i - 1) * MT * MT + mo * MT + nk; }
   __host__ __device__ static int tile_out(int H, int nk) { return MT * NK0 + (H - 1) * MT * MT + nk; }
@@ -96,6 +99,7 @@ template <int C, int F, int L, int ACT>
 __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDev nd, KeyTimes kt, const float* xyz,
                                                                             const float* times, long long n,
                                                                             const float* target,
+                                                                            const float* target_grad, float gw3,
                                                       const float* dloss, float* d_latent, float* ws, int n_waves,
                                                       float inv_n) {
   using TC = TrainCfg<C, F, L, ACT>;
@@ -103,7 +107,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
   using G = typename TC::G;
   using PR = PrecT<kF32>;
   constexpr int MT = TC::MT, AS = TC::AS, S = TC::S, NTC = TC::NTC;
-  const int H = nd.H;
+  const int H = nd.H, NO = nd.NO;
   extern __shared__ __attribute__((aligned(16))) char smem[];
   stage_weights<CF>(nd, smem);
   char* back = smem + G::weight_bytes(H);
@@ -123,10 +127,11 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
   const float* W0 = reinterpret_cast<const float*>(smem);
   const char* wout_p = smem + G::W0A + (H - 1) * G::HID;
   const float* WO = reinterpret_cast<const float*>(wout_p);
-  const float b_out = *reinterpret_cast<const float*>(wout_p + G::WOA);
-  // output weights (unscaled) straight from global memory, in D-layout order
+  const f4 b_out = *reinterpret_cast<const f4*>(wout_p + G::WOA);
+  // output weights W_out[o][k] (unscaled) straight from global memory
   const float* w_out = nd.weights + (long long)C * (3 + F + 6 * L) + C + (long long)(H - 1) * (C * C + C);
-  float loss_acc = 0.0f, dbo_acc = 0.0f;
+  float loss_acc = 0.0f;
+  f4 dbo_acc = {0.0f, 0.0f, 0.0f, 0.0f};
   const long long nchunks = (n + S - 1) / S;
   bool first = true;
   // Branch-free on purpose: the stored value is always produced by a VALU
@@ -219,25 +224,39 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
         out = PR::mma(WO[(t * 4 * MT + q) * kWave + lane], b, out);
       }
     }
-    // ---------------- loss and dL/dy for this lane's own sample
-    const float y = out[0] + b_out;
-    const float d = sigmoid_f(y);
+    // ---------------- loss and dL/dy for this lane's own sample (lanes < S
+    // hold its outputs in out[0..NO))
+    const f4 yv = out + b_out;
+    const float d = sigmoid_f(yv[0]);
     float gy = 0.0f;
+    f4 dyo = {0.0f, 0.0f, 0.0f, 0.0f};
     if (ok) {
       if (target) {
         const float r = d - target[idx];
         loss_acc += fabsf(r);
         gy = (r > 0.0f ? 1.0f : (r < 0.0f ? -1.0f : 0.0f)) * inv_n;
+        if (target_grad) {
+          // predicted gradient (outputs 1..3) against its targets, weighted L1
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const float rg = yv[1 + a] - target_grad[3 * idx + a];
+            loss_acc += gw3 * fabsf(rg);
+            dyo[1 + a] = (rg > 0.0f ? gw3 : (rg < 0.0f ? -gw3 : 0.0f)) * inv_n;
+          }
+        }
       } else {
         loss_acc += dloss[idx] * d;
         gy = dloss[idx];
       }
     }
-    const float dyv = gy * d * (1.0f - d);
-    dbo_acc += dyv;
-    dy[lane] = dyv;
+    dyo[0] = gy * d * (1.0f - d);
+    dbo_acc += dyo;
+    if (lane < S) {
+#pragma unroll
+      for (int o = 0; o < 4; ++o) dy[o * S + lane] = dyo[o];
+    }
     wave_lds_sync();
-    // ---------------- output layer weights: dW_H[0][k] = sum_s dy[s] h[k][s]
+    // ---------------- output layer weights: dW_H[o][k] = sum_s dy[o][s] h[k][s]
     const float* alast = abuf + (H - 1) * S * AS;
 #pragma unroll
     for (int nk = 0; nk < MT; ++nk) {
@@ -245,7 +264,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
 #pragma unroll
       for (int q = 0; q < S / 4; ++q) {
         const int s = 4 * q + g;
-        const float a = nn == 0 ? dy[s] : 0.0f;
+        const float a = nn < NO ? dy[nn * S + s] : 0.0f;
         const float b = act_el<ACT, false>(alast[s * AS + 16 * nk + nn], value_role());
         dw = PR::mma(a, b, dw);
       }
@@ -255,12 +274,17 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
     f4 dh[NTC][MT];  // d L / d h_i in D layout, per N-tile
 #pragma unroll
     for (int t = 0; t < NTC; ++t) {
-      const float dys = dy[16 * t + nn];
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const f4 wo = {w_out[16 * mt + 4 * g + 0], w_out[16 * mt + 4 * g + 1], w_out[16 * mt + 4 * g + 2],
-                       w_out[16 * mt + 4 * g + 3]};
-        dh[t][mt] = wo * dys;
+      for (int mt = 0; mt < MT; ++mt) dh[t][mt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+      for (int o = 0; o < NO; ++o) {
+        const float dys = dy[o * S + 16 * t + nn];
+        const float* wr = w_out + o * C;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const f4 wo = {wr[16 * mt + 4 * g + 0], wr[16 * mt + 4 * g + 1], wr[16 * mt + 4 * g + 2],
+                         wr[16 * mt + 4 * g + 3]};
+          dh[t][mt] += wo * dys;
+        }
       }
     }
     for (int i = H - 1; i >= 0; --i) {
@@ -386,9 +410,10 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
     }
     first = false;
   }
-  // ---------------- per-wave partials of the output bias and the loss
-  slice[TC::tiles(H) * 256 + lane] = dbo_acc;
-  slice[TC::tiles(H) * 256 + 64 + lane] = loss_acc;
+  // ---------------- per-wave partials of the output biases and the loss
+#pragma unroll
+  for (int o = 0; o < 4; ++o) slice[TC::tiles(H) * 256 + 64 * o + lane] = dbo_acc[o];
+  slice[TC::tiles(H) * 256 + 256 + lane] = loss_acc;
 }
 
 // Sums the wave slices in a fixed order into the packed gradient, in two
@@ -410,19 +435,19 @@ __global__ void slice_sum_kernel(const float* ws, int n_waves, int sl, float* pa
 }
 
 template <int C, int F, int L, int ACT>
-__global__ void gather_kernel(int H, const float* partial, int n_groups, float* d_weights, float* out_loss,
+__global__ void gather_kernel(int H, int NO, const float* partial, int n_groups, float* d_weights, float* out_loss,
                               float loss_scale) {
   using TC = TrainCfg<C, F, L, ACT>;
   using G = typename TC::G;
   const int K0 = 3 + F + 6 * L;
-  const long long nw = (long long)C * K0 + C + (long long)(H - 1) * (C * C + C) + C + 1;
+  const long long nw = (long long)C * K0 + C + (long long)(H - 1) * (C * C + C) + (long long)NO * (C + 1);
   const int SL = TC::slice(H);
   for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < nw + 1;
        j += (long long)gridDim.x * blockDim.x) {
     // locate weight j: a list of (offset within slice) terms to add
     int base = -1, count = 0, stride = 0;
     if (j == nw) {  // loss
-      base = TC::tiles(H) * 256 + 64;
+      base = TC::tiles(H) * 256 + 256;
       count = 64;
       stride = 1;
     } else {
@@ -459,12 +484,13 @@ __global__ void gather_kernel(int H, const float* partial, int n_groups, float* 
           }
         } else {
           r -= (long long)(H - 1) * per;
-          if (r < C) {
-            const int k = (int)r;
-            base = TC::tile_out(H, k / 16) * 256 + (k % 16) * 4;
+          if (r < (long long)NO * C) {
+            // W_out[o][k]: row o of the output tile, held by lane k % 16
+            const int o = (int)(r / C), k = (int)(r % C);
+            base = TC::tile_out(H, k / 16) * 256 + (k % 16) * 4 + o;
             count = 1;
           } else {
-            base = TC::tiles(H) * 256;
+            base = TC::tiles(H) * 256 + 64 * (int)(r - (long long)NO * C);
             count = 64;
             stride = 1;
           }
@@ -521,8 +547,9 @@ struct TrainEntry {
     return (size_t)(n_waves(n) + n_groups(n)) * TC::slice(nd.H) * sizeof(float);
   }
   static int run(const NetDev& nd, const KeyTimes& kt, float* latent, float* d_latent, float* d_weights,
-                 const float* xyz, const float* times, long long n,
-                 const float* target, const float* dloss, float* out_loss, void* ws, hipStream_t st) {
+                 const float* xyz, const float* times, long long n, const float* target,
+                 const float* target_grad, float grad_weight, const float* dloss, float* out_loss, void* ws,
+                 hipStream_t st) {
     const int H = nd.H;
     const int wpb = waves_per_block(H);
     if (wpb < 1) return 1;
@@ -544,7 +571,8 @@ struct TrainEntry {
     nd2.grid_f16 = 0;
     if (n > 0) {
       hipLaunchKernelGGL((fwd_bwd_kernel<C, F, L, ACT>), dim3((nw + wpb - 1) / wpb), dim3(wpb * 64), shm, st, nd2,
-                         kt, xyz, times, n, target, dloss, d_latent, (float*)ws, nw, 1.0f / (float)n);
+                         kt, xyz, times, n, target, target_grad, grad_weight / 3.0f, dloss, d_latent, (float*)ws, nw,
+                         1.0f / (float)n);
       rc = check_launch();
       if (rc) return rc;
     } else {
@@ -560,9 +588,10 @@ struct TrainEntry {
                        partial);
     rc = check_launch();
     if (rc) return rc;
-    const long long nwts = (long long)C * (3 + F + 6 * L) + C + (long long)(H - 1) * (C * C + C) + C + 1;
+    const long long nwts = (long long)C * (3 + F + 6 * L) + C + (long long)(H - 1) * (C * C + C) +
+                           (long long)nd.NO * (C + 1);
     hipLaunchKernelGGL((gather_kernel<C, F, L, ACT>), dim3(grid_blocks(nwts + 1, 128, 1024)), dim3(128), 0, st, H,
-                       (const float*)partial, ng, d_weights, out_loss, target && n > 0 ? 1.0f / (float)n : 1.0f);
+                       nd.NO, (const float*)partial, ng, d_weights, out_loss, target && n > 0 ? 1.0f / (float)n : 1.0f);
     return check_launch();
   }
 };
@@ -589,7 +618,7 @@ size_t train_workspace_bytes(const NetDev& nd, long long n) {
 
 int launch_train(const NetDev& nd, const KeyTimes& kt, float* latent, float* weights, float* d_latent,
                  float* d_weights, const float* xyz, const float* times, long long n, const float* target,
-                 const float* dloss_dy, int use_adam, float lr_grid, float lr_mlp, float beta1, float beta2,
+                 const float* target_grad, float grad_weight, const float* dloss_dy, int use_adam, float lr_grid, float lr_mlp, float beta1, float beta2,
                  float eps, int step, float* m_lat, float* v_lat, float* m_w, float* v_w, float* out_loss,
                  void* workspace, size_t ws_bytes, void* stream) {
   const hipStream_t st = (hipStream_t)stream;
@@ -600,13 +629,13 @@ int launch_train(const NetDev& nd, const KeyTimes& kt, float* latent, float* wei
   if (nd.C == C_ && nd.F == F_ && nd.L == L_) {                                                                 \
     if (nd.act == kSine)                                                                                        \
       rc = TrainEntry<C_, F_, L_, kSine>::run(net, kt, latent, d_latent, d_weights, xyz, times, n, target,      \
-                                              dloss_dy, out_loss, workspace, st);                               \
+                                              target_grad, grad_weight, dloss_dy, out_loss, workspace, st);                               \
     else if (nd.act == kSnakeAlt)                                                                               \
       rc = TrainEntry<C_, F_, L_, kSnakeAlt>::run(net, kt, latent, d_latent, d_weights, xyz, times, n, target,  \
-                                                  dloss_dy, out_loss, workspace, st);                           \
+                                                  target_grad, grad_weight, dloss_dy, out_loss, workspace, st);                           \
     else                                                                                                        \
       rc = TrainEntry<C_, F_, L_, kIdentity>::run(net, kt, latent, d_latent, d_weights, xyz, times, n, target,  \
-                                                  dloss_dy, out_loss, workspace, st);                           \
+                                                  target_grad, grad_weight, dloss_dy, out_loss, workspace, st);                           \
   }
   FV_TRAIN_CASES(X)
 #undef X
@@ -616,7 +645,7 @@ int launch_train(const NetDev& nd, const KeyTimes& kt, float* latent, float* wei
   const double bc2 = 1.0 - pow((double)beta2, (double)step);
   const long long nlat = (long long)nd.K * nd.R * nd.R * nd.R * nd.F;
   const long long nw = (long long)nd.C * (3 + nd.F + 6 * nd.L) + nd.C + (long long)(nd.H - 1) * (nd.C * nd.C + nd.C) +
-                       nd.C + 1;
+                       (long long)nd.NO * (nd.C + 1);
   hipLaunchKernelGGL(adam_kernel, dim3(grid_blocks(nlat, 256, device_cus() * 8)), dim3(256), 0, st, latent, d_latent,
                      m_lat, v_lat, nlat, (float)(lr_grid / bc1), beta1, beta2, (float)(1.0 / sqrt(bc2)), eps);
   rc = check_launch();

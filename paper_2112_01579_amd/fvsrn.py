@@ -25,8 +25,8 @@ PREC = {"f32": F32, "fp32": F32, "f16": F16, "fp16": F16, "bf16": BF16}
 OK, ERR_INVALID_ARGUMENT, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_DEVICE = 0, 1, 2, 3, 4
 
 EXPORTS = (
-    "fvsrn_render", "fvsrn_eval_points", "fvsrn_grad_points", "fvsrn_train_step",
-    "fvsrn_train_workspace_size", "fvsrn_render_dense", "fvsrn_dense_eval_points",
+    "fvsrn_render", "fvsrn_eval_points", "fvsrn_grad_points", "fvsrn_pred_grad_points", "fvsrn_train_step",
+    "fvsrn_train_workspace_size", "fvsrn_render_dense", "fvsrn_dense_eval_points", "fvsrn_dense_grad_points",
     "fvsrn_sample_points", "fvsrn_cast_grid", "fvsrn_quantize_grid", "fvsrn_ssim_map", "fvsrn_num_weights",
     "fvsrn_status_str", "fvsrn_last_error",
 )
@@ -41,7 +41,8 @@ class FvsrnError(RuntimeError):
 class NetDesc(C.Structure):
     _fields_ = [("grid_res", C.c_int32), ("grid_channels", C.c_int32), ("grid_dtype", C.c_int32),
                 ("num_keyframes", C.c_int32), ("num_freqs", C.c_int32), ("hidden_width", C.c_int32),
-                ("hidden_layers", C.c_int32), ("activation", C.c_int32), ("precision", C.c_int32)]
+                ("hidden_layers", C.c_int32), ("activation", C.c_int32), ("precision", C.c_int32),
+                ("num_outputs", C.c_int32)]
 
 
 class Params(C.Structure):
@@ -89,11 +90,13 @@ def lib():
             "fvsrn_render": (st, [vp, vp, vp, vp, i32, vp, vp, vp, vp]),
             "fvsrn_eval_points": (st, [vp, vp, vp, i64, C.c_float, vp, vp]),
             "fvsrn_grad_points": (st, [vp, vp, vp, i64, C.c_float, vp, vp, vp]),
-            "fvsrn_train_step": (st, [vp, vp, vp, C.POINTER(C.c_float), vp, vp, vp, vp, i64, vp, vp, vp, vp, vp,
-                                      sz, vp]),
+            "fvsrn_pred_grad_points": (st, [vp, vp, vp, i64, C.c_float, vp, vp, vp]),
+            "fvsrn_train_step": (st, [vp, vp, vp, C.POINTER(C.c_float), vp, vp, vp, vp, i64, vp, vp, C.c_float,
+                                      vp, vp, vp, vp, sz, vp]),
             "fvsrn_train_workspace_size": (sz, [vp, i64]),
             "fvsrn_render_dense": (st, [vp, i32, i32, i32, vp, vp, i32, vp, vp, vp, vp]),
             "fvsrn_dense_eval_points": (st, [vp, i32, i32, i32, vp, i64, vp, vp]),
+            "fvsrn_dense_grad_points": (st, [vp, i32, i32, i32, vp, i64, vp, vp, vp]),
             "fvsrn_sample_points": (st, [C.c_uint64, C.c_uint64, i64, vp, vp]),
             "fvsrn_cast_grid": (st, [vp, vp, i64, i32, vp]),
             "fvsrn_quantize_grid": (st, [vp, i64, i32, vp, vp, vp]),
@@ -130,7 +133,7 @@ def _stream(stream=None):
 
 def net_desc(spec: I.NetSpec, precision="f32", grid_dtype=F32) -> NetDesc:
     return NetDesc(spec.R, spec.F, grid_dtype, spec.K, spec.L, spec.c, spec.H, ACT[spec.act],
-                   PREC[precision] if isinstance(precision, str) else precision)
+                   PREC[precision] if isinstance(precision, str) else precision, spec.outputs)
 
 
 def tf_struct(tf: I.TF) -> TFStruct:
@@ -238,6 +241,18 @@ def fvsrn_grad_points(net: Network, xyz: torch.Tensor, time: float = 0.0, precis
     return dens, grad
 
 
+def fvsrn_pred_grad_points(net: Network, xyz: torch.Tensor, time: float = 0.0, precision="f32",
+                           stream=None):
+    """Density and the predicted gradient (outputs 1..3) of a 4-output network."""
+    n = xyz.shape[0]
+    dens = torch.empty(n, dtype=torch.float32, device=xyz.device)
+    grad = torch.empty((n, 3), dtype=torch.float32, device=xyz.device)
+    d, p = net.desc(precision), net.params()
+    _check(lib().fvsrn_pred_grad_points(C.byref(d), C.byref(p), _ptr(xyz), n, time, _ptr(dens), _ptr(grad),
+                                        _stream(stream)), "fvsrn_pred_grad_points")
+    return dens, grad
+
+
 def fvsrn_render_dense(vol: torch.Tensor, tf: I.TF, cams: Sequence[I.Camera], march: I.March,
                        out: Optional[torch.Tensor] = None, stats: Optional[torch.Tensor] = None,
                        stream=None) -> torch.Tensor:
@@ -260,6 +275,17 @@ def fvsrn_dense_eval_points(vol: torch.Tensor, xyz: torch.Tensor, out=None, stre
     _check(lib().fvsrn_dense_eval_points(_ptr(vol), nx, ny, nz, _ptr(xyz), n, _ptr(out), _stream(stream)),
            "fvsrn_dense_eval_points")
     return out
+
+
+def fvsrn_dense_grad_points(vol: torch.Tensor, xyz: torch.Tensor, out=None, out_grad=None, stream=None):
+    """Trilinear samples of a dense grid and their one-voxel central-difference gradients."""
+    nz, ny, nx = vol.shape
+    n = xyz.shape[0]
+    dens = out if out is not None else torch.empty(n, dtype=torch.float32, device=xyz.device)
+    grad = out_grad if out_grad is not None else torch.empty((n, 3), dtype=torch.float32, device=xyz.device)
+    _check(lib().fvsrn_dense_grad_points(_ptr(vol), nx, ny, nz, _ptr(xyz), n, _ptr(dens), _ptr(grad),
+                                         _stream(stream)), "fvsrn_dense_grad_points")
+    return dens, grad
 
 
 def fvsrn_sample_points(seed: int, counter: int, n: int, out=None, device="cuda", stream=None):
@@ -317,9 +343,12 @@ def fvsrn_train_workspace_size(spec: I.NetSpec, n: int) -> int:
 def fvsrn_train_step(net: Network, d_latent: torch.Tensor, d_weights: torch.Tensor, xyz: torch.Tensor,
                      target: Optional[torch.Tensor] = None, dloss_dy: Optional[torch.Tensor] = None,
                      adam: Optional[dict] = None, out_loss: Optional[torch.Tensor] = None,
-                     workspace: Optional[torch.Tensor] = None, times: Optional[torch.Tensor] = None, stream=None):
+                     workspace: Optional[torch.Tensor] = None, times: Optional[torch.Tensor] = None,
+                     target_grad: Optional[torch.Tensor] = None, grad_weight: float = 0.0, stream=None):
     """One training step on ``net`` (FP32 latent grids). ``times`` (device
-    [n], optional) holds each point's keyframe time. ``adam`` is a dict with
+    [n], optional) holds each point's keyframe time; ``target_grad`` ([n][3],
+    4-output networks, L1 mode) the gradient targets of the predicted
+    gradient, weighted by ``grad_weight``. ``adam`` is a dict with
     lr_grid, lr_mlp, beta1, beta2, eps, step and the four moment tensors
     m_latent, v_latent, m_weights, v_weights; None computes gradients only."""
     n = xyz.shape[0]
@@ -334,6 +363,7 @@ def fvsrn_train_step(net: Network, d_latent: torch.Tensor, d_weights: torch.Tens
                        adam["v_latent"].data_ptr(), adam["m_weights"].data_ptr(), adam["v_weights"].data_ptr())
     kt = C.cast(net._kt, C.POINTER(C.c_float)) if net._kt is not None else None
     _check(lib().fvsrn_train_step(C.byref(d), _ptr(net.latent), _ptr(net.weights), kt, _ptr(d_latent),
-                                  _ptr(d_weights), _ptr(xyz), _ptr(times), n, _ptr(target), _ptr(dloss_dy),
+                                  _ptr(d_weights), _ptr(xyz), _ptr(times), n, _ptr(target), _ptr(target_grad),
+                                  float(grad_weight), _ptr(dloss_dy),
                                   C.byref(a) if a is not None else None, _ptr(out_loss), _ptr(workspace),
                                   workspace.numel(), _stream(stream)), "fvsrn_train_step")

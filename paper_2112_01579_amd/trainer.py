@@ -25,11 +25,18 @@ class Trainer:
     grids, Sec. 8), on a sequence ``vol`` = [(time, volume), ...]: every step
     splits the batch evenly over the timesteps, each part drawing its targets
     from its own volume at its own time, so the keyframe grids around each
-    time and the shared network learn together."""
+    time and the shared network learn together.
+
+    A 4-output network (density and predicted gradient, Sec. 6) trained with
+    ``grad_weight`` > 0 also fits its gradient outputs to one-voxel central
+    differences of the volume (the gradients the dense renderer shades with),
+    weighted L1 next to the density's L1."""
 
     def __init__(self, net: FV.Network, vol, batch: int = 1 << 18, lr_grid: float = 1e-2,
-                 lr_mlp: float = 1e-3, betas=(0.9, 0.999), eps: float = 1e-8, seed: int = 0):
+                 lr_mlp: float = 1e-3, betas=(0.9, 0.999), eps: float = 1e-8, seed: int = 0,
+                 grad_weight: float = 0.0):
         assert net.grid_dtype == FV.F32
+        assert grad_weight == 0.0 or net.spec.outputs == 4
         if isinstance(vol, torch.Tensor):
             vol = [(0.0, vol)]
         self.frames = list(vol)
@@ -52,6 +59,8 @@ class Trainer:
         self.d_weights = torch.empty_like(net.weights)
         self.xyz = torch.empty((batch, 3), dtype=torch.float32, device=dev)
         self.target = torch.empty(batch, dtype=torch.float32, device=dev)
+        self.grad_weight = float(grad_weight)
+        self.target_grad = torch.empty((batch, 3), dtype=torch.float32, device=dev) if grad_weight else None
         self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
         ws = FV.fvsrn_train_workspace_size(net.spec, batch)
         self.workspace = torch.empty(max(ws, 16), dtype=torch.uint8, device=dev)
@@ -62,9 +71,13 @@ class Trainer:
         FV.fvsrn_sample_points(self.seed, self.opt["step"], self.batch, out=self.xyz)
         for j, (_, v) in enumerate(self.frames):
             a, b = self.bounds[j], self.bounds[j + 1]
-            FV.fvsrn_dense_eval_points(v, self.xyz[a:b], out=self.target[a:b])
+            if self.target_grad is None:
+                FV.fvsrn_dense_eval_points(v, self.xyz[a:b], out=self.target[a:b])
+            else:
+                FV.fvsrn_dense_grad_points(v, self.xyz[a:b], out=self.target[a:b], out_grad=self.target_grad[a:b])
         FV.fvsrn_train_step(self.net, self.d_latent, self.d_weights, self.xyz, target=self.target, adam=self.opt,
-                            out_loss=self.loss, workspace=self.workspace, times=self.times)
+                            out_loss=self.loss, workspace=self.workspace, times=self.times,
+                            target_grad=self.target_grad, grad_weight=self.grad_weight)
         return self.loss
 
     def state_dict(self) -> dict:

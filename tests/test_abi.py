@@ -41,6 +41,9 @@ def test_num_weights_matches_layout():
         assert FV.fvsrn_num_weights(spec) == spec.n_weights
     assert FV.fvsrn_num_weights(I.NET_SMALL) == 3297
     assert FV.fvsrn_num_weights(I.NET_STUDY) == 5377
+    # four outputs add three output rows and three biases
+    spec4 = I.NetSpec(R=32, F=16, L=8, c=32, H=4, outputs=4)
+    assert FV.fvsrn_num_weights(spec4) == spec4.n_weights == 5377 + 3 * 33
 
 
 def test_status_strings():
@@ -99,6 +102,12 @@ def test_render_argument_errors():
     assert _render(_desc(), m=m) == FV.ERR_INVALID_ARGUMENT
     m = FV.march_struct(I.March(step=0.1, grad_mode=5))
     assert _render(_desc(), m=m) == FV.ERR_INVALID_ARGUMENT
+    # network outputs: 1 or 4; predicted-gradient shading needs 4
+    for no in (2, 3, 5, -1):
+        assert _render(_desc(num_outputs=no)) == FV.ERR_INVALID_ARGUMENT
+    m = FV.march_struct(I.March(step=0.1, phong=True, grad_mode=2))
+    assert _render(_desc(), m=m) == FV.ERR_INVALID_ARGUMENT
+    assert b"num_outputs" in L.fvsrn_last_error()
     for h in (0.0, -0.1, 1.5, float("nan")):
         m = FV.march_struct(I.March(step=0.1, phong=True, grad_mode=1, fd_step=h))
         assert _render(_desc(), m=m) == FV.ERR_INVALID_ARGUMENT
@@ -127,18 +136,33 @@ def test_points_argument_errors_and_empty_noop():
     assert L.fvsrn_dense_eval_points(C.c_void_p(FAKE), 1, 4, 4, C.c_void_p(FAKE), 3, C.c_void_p(FAKE), None) \
         == FV.ERR_INVALID_ARGUMENT
     assert L.fvsrn_dense_eval_points(C.c_void_p(FAKE), 4, 4, 4, None, 0, None, None) == FV.OK
+    assert L.fvsrn_dense_grad_points(C.c_void_p(FAKE), 4, 4, 4, None, 0, None, None, None) == FV.OK
+    assert L.fvsrn_dense_grad_points(C.c_void_p(FAKE), 4, 4, 4, C.c_void_p(FAKE), 3, None, None, None) \
+        == FV.ERR_INVALID_ARGUMENT
+    assert L.fvsrn_dense_grad_points(C.c_void_p(FAKE), 4, 1, 4, C.c_void_p(FAKE), 3, None, C.c_void_p(FAKE),
+                                     None) == FV.ERR_INVALID_ARGUMENT
+    # predicted gradients need a 4-output network
+    assert L.fvsrn_pred_grad_points(C.byref(d), C.byref(p), C.c_void_p(FAKE), 5, 0.0, None, C.c_void_p(FAKE),
+                                    None) == FV.ERR_INVALID_ARGUMENT
+    assert b"num_outputs" in L.fvsrn_last_error()
+    d4 = _desc(num_outputs=4)
+    assert L.fvsrn_pred_grad_points(C.byref(d4), C.byref(p), None, 0, 0.0, None, None, None) == FV.OK
+    assert L.fvsrn_pred_grad_points(C.byref(d4), C.byref(p), C.c_void_p(FAKE), 5, 0.0, None, None, None) \
+        == FV.ERR_INVALID_ARGUMENT
     assert L.fvsrn_sample_points(1, 2, 0, None, None) == FV.OK
     assert L.fvsrn_sample_points(1, 2, -3, None, None) == FV.ERR_INVALID_ARGUMENT
     assert L.fvsrn_cast_grid(C.c_void_p(FAKE), C.c_void_p(FAKE), 4, 0, None) == FV.ERR_INVALID_ARGUMENT
     assert L.fvsrn_cast_grid(None, None, 0, 1, None) == FV.OK
 
 
-def _train(d, key_times=None, xyz=FAKE, times=None, n=4, target=FAKE, dloss=None, adam=None):
+def _train(d, key_times=None, xyz=FAKE, times=None, n=4, target=FAKE, dloss=None, adam=None, target_grad=None,
+           grad_weight=0.0):
     L = FV.lib()
     P = C.c_void_p
     return L.fvsrn_train_step(C.byref(d), P(FAKE), P(FAKE), key_times, P(FAKE), P(FAKE),
                               P(xyz) if xyz else None, P(times) if times else None, n,
-                              P(target) if target else None, P(dloss) if dloss else None,
+                              P(target) if target else None, P(target_grad) if target_grad else None,
+                              grad_weight, P(dloss) if dloss else None,
                               C.byref(adam) if adam is not None else None, None, None, 0, None)
 
 
@@ -169,3 +193,12 @@ def test_train_argument_errors():
     assert _train(d, adam=a) == FV.ERR_INVALID_ARGUMENT
     # a workspace is required once there are points
     assert _train(d) == FV.ERR_WORKSPACE
+    # gradient targets: 4-output networks in L1 mode, finite non-negative weight
+    assert _train(d, target_grad=FAKE, grad_weight=1.0) == FV.ERR_INVALID_ARGUMENT
+    assert b"num_outputs" in L.fvsrn_last_error()
+    d4 = _desc(num_outputs=4)
+    assert _train(d4, target_grad=FAKE, grad_weight=1.0) == FV.ERR_WORKSPACE
+    assert _train(d4, target=None, dloss=FAKE, target_grad=FAKE) == FV.ERR_INVALID_ARGUMENT
+    for w in (-1.0, float("nan"), float("inf")):
+        assert _train(d4, target_grad=FAKE, grad_weight=w) == FV.ERR_INVALID_ARGUMENT
+    assert _train(d4, target_grad=FAKE + 2, grad_weight=1.0) == FV.ERR_INVALID_ARGUMENT

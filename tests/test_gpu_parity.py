@@ -461,3 +461,101 @@ def test_ssim_map_against_oracle(FV):
     want = O.ssim(i16[0].cpu().numpy(), i32[0].cpu().numpy())
     _report("ssim f16 vs f32 render (%.6f)" % want, abs(got - want))
     assert abs(got - want) <= 1e-5 and want > 0.99
+
+
+# ------------------------------------- networks predicting their gradient
+
+SPEC4_SMALL = I.NetSpec(R=16, F=8, L=4, c=32, H=3, outputs=4)
+SPEC4_STUDY = I.NetSpec(R=32, F=16, L=8, c=32, H=4, outputs=4)
+SPEC4_WIDE = I.NetSpec(R=24, F=16, L=8, c=48, H=4, outputs=4)
+
+
+def _pred_ref(onet, xyz, t=0.0):
+    d = np.empty(len(xyz))
+    g = np.empty((len(xyz), 3))
+    for i, p in enumerate(xyz):
+        d[i], g[i] = O.density_grad(onet, p, t, mode="pred")
+    return d, g
+
+
+@pytest.mark.parametrize("spec", [SPEC4_SMALL, SPEC4_STUDY, SPEC4_WIDE], ids=["c32F8", "c32F16", "c48F16"])
+def test_pred_grad_points(FV, spec):
+    """Four-output networks (Sec. 6): density = sigmoid(output 0) and the
+    predicted gradient = outputs 1..3, on a ragged point count, every
+    precision and latent storage; the plain density and the forward-mode
+    gradient of output 0 are unchanged by the extra outputs. The gradient
+    outputs are linear, so their error is bounded relative to max |g|."""
+    xyz = I.uniform_points(64 * 9 + 23, 17, -0.999, 0.999)
+    for gd in (FV.F32, FV.F16, FV.U8):
+        gnet, onet = _nets(FV, spec, 41, grid_dtype=gd)
+        dref, gref = _pred_ref(onet, xyz)
+        for prec, dtol, gtol in (("f32", FP32_TOL, 1e-5), ("f16", FP16_TOL, 3e-3), ("bf16", BF16_TOL, 3e-2)):
+            d, g = FV.fvsrn_pred_grad_points(gnet, torch.from_numpy(xyz).cuda(), 0.0, prec)
+            derr, gerr = np.abs(d.cpu().numpy() - dref).max(), _grad_err(g.cpu().numpy(), gref)
+            _report("pred c=%d F=%d grid %d %s density" % (spec.c, spec.F, gd, prec), derr)
+            _report("pred c=%d F=%d grid %d %s gradient (rel.)" % (spec.c, spec.F, gd, prec), gerr)
+            assert derr <= dtol and gerr <= gtol
+            dd = FV.fvsrn_eval_points(gnet, torch.from_numpy(xyz).cuda(), 0.0, prec).cpu().numpy()
+            assert np.abs(dd - dref).max() <= dtol
+    gnet, onet = _nets(FV, spec, 41)
+    fref, fgref = O.grad_points(onet, xyz)
+    d, g = FV.fvsrn_grad_points(gnet, torch.from_numpy(xyz).cuda(), 0.0, "f32")
+    assert np.abs(d.cpu().numpy() - fref).max() <= FP32_TOL
+    assert _grad_err(g.cpu().numpy(), fgref) <= 1e-4
+
+
+def test_pred_grad_points_keyframes_and_edges(FV):
+    spec = I.NetSpec(R=8, F=8, L=4, c=32, H=2, K=3, outputs=4)
+    gnet, onet = _nets(FV, spec, 6, key_times=(0.0, 1.0, 3.0))
+    for n in (1, 63, 64, 65):
+        xyz = I.uniform_points(n, n, -0.99, 0.99)
+        for t in (0.5, 2.5):
+            dref, gref = _pred_ref(onet, xyz, t)
+            d, g = FV.fvsrn_pred_grad_points(gnet, torch.from_numpy(xyz).cuda(), t, "f32")
+            assert np.abs(d.cpu().numpy() - dref).max() <= FP32_TOL
+            assert _grad_err(g.cpu().numpy(), gref) <= 1e-5
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-4), ("f16", 10 * FP16_TOL), ("bf16", 0.1)])
+def test_phong_render_predicted(FV, prec, tol):
+    """Phong shading from the predicted gradient (one evaluation per sample)
+    on c = 32 and c = 48 four-output networks, ragged views; then forward
+    mode and central differences on the same network, which differentiate
+    output 0 only. The gradient error e of the precision moves the shading by
+    about e / |g|, hence the wider FP16 bound; BF16 is reported against a
+    loose bound."""
+    for spec, seed in ((SPEC4_STUDY, 12), (SPEC4_WIDE, 13)):
+        gnet, onet = _nets(FV, spec, seed)
+        tf = I.ramp_tf()
+        cams = I.orbit_cameras(2, 27, 19)
+        modes = [(2, prec)] + ([(0, prec), (1, prec)] if prec == "f32" else [])
+        for gm, pr in modes:
+            m = I.March(step=1 / 96, ert_eps=0.0, phong=True, grad_mode=gm, fd_step=1 / 32)
+            ref, ns = O.render(O.Field(net=onet), tf, cams, m)
+            stats = torch.zeros(3, dtype=torch.int64, device="cuda")
+            img = FV.fvsrn_render(gnet, tf, cams, m, pr, stats=stats).cpu().numpy()
+            err = np.abs(img - ref).max()
+            _report("phong grad_mode %d c=%d %s" % (gm, spec.c, pr), err)
+            assert err <= tol
+            assert abs(stats[0].item() - ns) <= 0.001 * ns
+            if gm == 2:
+                # one lane per ray: the unshaded tile shape
+                assert stats[2].item() % 64 == 0
+
+
+def test_dense_grad_points(FV):
+    """One-voxel central differences of the trilinear dense grid (the
+    gradient targets of predicted-gradient training) against the oracle's
+    dense field, including points whose stencil leaves the domain."""
+    rng = np.random.default_rng(3)
+    vol = rng.uniform(0, 1, (9, 13, 11)).astype(np.float32)
+    xyz = np.concatenate([I.uniform_points(1000, 5, -1.0, 1.0),
+                          np.array([[1, 1, 1], [-1, -1, -1], [0.99, -0.99, 0.0]], np.float32)])
+    d, g = FV.fvsrn_dense_grad_points(torch.from_numpy(vol).cuda(), torch.from_numpy(xyz).cuda())
+    f = O.Field(vol=vol)
+    ref = [f.density(p, grad=True) for p in xyz]
+    dref = np.array([r[0] for r in ref])
+    gref = np.array([r[1] for r in ref])
+    assert np.abs(d.cpu().numpy() - dref).max() <= 1e-6
+    # each component differences two FP32 samples over 2h (h >= 1/6 here)
+    assert np.abs(g.cpu().numpy() - gref).max() <= 1e-5

@@ -228,3 +228,83 @@ def test_time_varying_training_gain(FV):
     print("time-varying L1 between keyframes: %s" % res, flush=True)
     assert res["all"] < 0.5 * res["untrained"]
     assert res["all"] < res["keys"]
+
+
+@pytest.mark.parametrize("spec", [I.NetSpec(R=16, F=8, L=4, c=32, H=3, outputs=4),
+                                  I.NetSpec(R=16, F=16, L=8, c=48, H=3, K=2, outputs=4)],
+                         ids=["c32", "c48_keyframes"])
+def test_train_gradients_predicted_gradient_targets(FV, spec):
+    """Four-output network fitted to densities and gradient targets (Sec. 6):
+    L1 on the density plus grad_weight/3 times the L1 of the predicted
+    gradient; dW (all four output rows and biases), the latent gradient and
+    the loss against the oracle. Then the same network in L1 mode without
+    gradient targets and in VJP mode, where the gradient outputs get no
+    gradient."""
+    n = 64 * 21 + 9
+    lat, w = I.net_params(spec, 8)
+    kt = (0.0, 1.0) if spec.K > 1 else None
+    gnet, onet = FV.Network(spec, lat, w, key_times=kt), O.Net(spec, lat, w, kt)
+    xyz = I.uniform_points(n, 9, -0.99, 0.99)
+    times = np.random.default_rng(4).uniform(-0.2, 1.2, n).astype(np.float32) if spec.K > 1 else None
+    rng = np.random.default_rng(2)
+    dref = np.empty(n)
+    gref = np.empty((n, 3))
+    for i in range(n):
+        dref[i], gref[i] = O.density_grad(onet, xyz[i], 0.0 if times is None else float(times[i]), mode="pred")
+    # targets away from the predictions so that every sign agrees in FP32 and FP64
+    target = (dref + rng.uniform(0.01, 0.3, n) * rng.choice([-1, 1], n)).astype(np.float32)
+    tgrad = (gref + rng.uniform(0.01, 0.5, (n, 3)) * rng.choice([-1, 1], (n, 3))).astype(np.float32)
+    tt = None if times is None else torch.from_numpy(times).cuda()
+    for tg, gw in ((tgrad, 0.7), (None, 0.0)):
+        dl_ref, dw_ref, loss_ref = O.train_grads(onet, xyz, target=target.astype(np.float64), times=times,
+                                                 target_grad=tg, grad_weight=gw)
+        d_lat = torch.empty_like(gnet.latent)
+        d_w = torch.empty_like(gnet.weights)
+        loss = torch.zeros(1, device="cuda")
+        FV.fvsrn_train_step(gnet, d_lat, d_w, torch.from_numpy(xyz).cuda(), target=torch.from_numpy(target).cuda(),
+                            out_loss=loss, times=tt, target_grad=None if tg is None else torch.from_numpy(tg).cuda(),
+                            grad_weight=gw)
+        e_w, e_l = _rel(d_w.cpu().numpy(), dw_ref), _rel(d_lat.cpu().numpy(), dl_ref)
+        print("train 4-output c=%d grad targets %s: dW rel err %.3g, dG rel err %.3g, loss %.6g vs %.6g" %
+              (spec.c, tg is not None, e_w, e_l, loss.item(), loss_ref), flush=True)
+        assert e_w <= 1e-4 and e_l <= 1e-4
+        assert abs(loss.item() - loss_ref) <= 1e-5 * abs(loss_ref) + 1e-7
+        if tg is None:
+            # the gradient outputs' rows and biases receive nothing
+            out_rows = d_w.cpu().numpy()[-4 * (spec.c + 1):]
+            assert np.count_nonzero(out_rows[spec.c:4 * spec.c]) == 0
+            assert np.count_nonzero(out_rows[4 * spec.c + 1:]) == 0
+    up = rng.normal(size=n).astype(np.float32)
+    dl_ref, dw_ref, loss_ref = O.train_grads(onet, xyz, dloss_dd=up.astype(np.float64), times=times)
+    d_lat = torch.empty_like(gnet.latent)
+    d_w = torch.empty_like(gnet.weights)
+    FV.fvsrn_train_step(gnet, d_lat, d_w, torch.from_numpy(xyz).cuda(), dloss_dy=torch.from_numpy(up).cuda(),
+                        times=tt)
+    assert _rel(d_w.cpu().numpy(), dw_ref) <= 1e-4 and _rel(d_lat.cpu().numpy(), dl_ref) <= 1e-4
+
+
+def test_trainer_learns_predicted_gradients(FV):
+    """A four-output network trained with gradient targets on the blob field
+    predicts gradients closer to the volume's central differences than at
+    initialisation, and its density error still falls."""
+    from paper_2112_01579_amd.trainer import Trainer
+    spec = I.NetSpec(R=16, F=8, L=4, c=32, H=3, outputs=4)
+    v = I.blob_volume(48, 0.0, I.blob_sequence_params(seed=I.SEED_TIME))
+    vol = torch.from_numpy(v / v.max()).cuda()
+    lat, w = I.net_params(spec, 1)
+    net = FV.Network(spec, lat, w)
+    xyz = FV.fvsrn_sample_points(99, 1, 1 << 14)
+    dref, gref = FV.fvsrn_dense_grad_points(vol, xyz)
+
+    def errs():
+        d, g = FV.fvsrn_pred_grad_points(net, xyz)
+        return torch.mean(torch.abs(d - dref)).item(), torch.mean(torch.abs(g - gref)).item()
+
+    e0 = errs()
+    tr = Trainer(net, vol, batch=1 << 14, lr_grid=1e-2, lr_mlp=2e-3, grad_weight=0.5)
+    for _ in range(150):
+        tr.step()
+    e1 = errs()
+    print("predicted-gradient training: density L1 %.4f, gradient L1 %.4f -> density %.4f, gradient %.4f" %
+          (e0 + e1), flush=True)
+    assert e1[0] < 0.5 * e0[0] and e1[1] < 0.7 * e0[1]
