@@ -538,7 +538,11 @@ static void render_pixel(const orc_field* field, const orc_tf* tf, const orc_cam
     double p[3] = {o[0] + tm * dir[0], o[1] + tm * dir[1], o[2] + tm * dir[2]};
     double g[3];
     double d;
-    if (m->phong && m->grad_fd == 2 && field->kind == ORC_FIELD_NET) {
+    if (m->phong && m->grad_fd == 3 && field->kind == ORC_FIELD_NET) {
+      /* backpropagation through the network to the position (the adjoint
+         strategy of Sec. 6) */
+      d = orc_density_grad_rev(field->net, p, cam->time, g);
+    } else if (m->phong && m->grad_fd == 2 && field->kind == ORC_FIELD_NET) {
       /* the network's own gradient outputs (Sec. 6) */
       d = orc_density_grad_pred(field->net, p, cam->time, g);
     } else if (m->phong && m->grad_fd == 1 && field->kind == ORC_FIELD_NET) {

@@ -77,7 +77,8 @@ typedef struct {
   double ka, kd, ks, shininess;
   int32_t grad_fd;          /* network field: 0 = analytic (forward mode),
                                1 = central differences with step fd_step,
-                               2 = the network's predicted gradient */
+                               2 = the network's predicted gradient,
+                               3 = reverse mode (the adjoint method) */
   int32_t pad_;
   double fd_step;
 } orc_march;

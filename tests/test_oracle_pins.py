@@ -659,6 +659,30 @@ def test_fd_shading_converges_to_forward_mode_at_second_order():
     assert 3.0 < errs[0] / errs[1] < 5.0, errs
 
 
+def test_adjoint_shading_equals_forward_mode_and_differs_unshaded():
+    """Reverse-mode (adjoint) shading reaches the forward-mode gradient by
+    the transposed chain rule, so the two shaded images agree to rounding,
+    while shading changes the image (the gradient enters at all), and the
+    reverse gradient itself matches central differences of the density."""
+    spec = I.NetSpec(R=6, F=4, L=2, c=8, H=3)
+    lat, w = I.net_params(spec, 78)
+    net = O.Net(spec, lat, w)
+    tf = I.ramp_tf()
+    cams = I.orbit_cameras(1, 9, 6)
+    base = I.March(step=0.05, phong=True)
+    fwd, n0 = O.render(O.Field(net=net), tf, cams, base)
+    adj, n1 = O.render(O.Field(net=net), tf, cams, dataclasses_replace(base, grad_mode=3))
+    plain, _ = O.render(O.Field(net=net), tf, cams, dataclasses_replace(base, phong=False))
+    assert n0 == n1
+    assert np.abs(adj - fwd).max() < 1e-12
+    assert np.abs(adj - plain).max() > 1e-3
+    for p in RNG.uniform(-0.9, 0.9, (5, 3)):
+        d, g = O.density_grad(net, p, mode="rev")
+        h = 1e-6
+        fd = [(O.density(net, p + h * e) - O.density(net, p - h * e)) / (2 * h) for e in np.eye(3)]
+        np.testing.assert_allclose(g, fd, rtol=1e-6, atol=1e-9)
+
+
 def test_uint8_quantizer_definition():
     """Sec. 4.2's uint8 grid: per channel, the minimum maps to code 0 and the
     maximum to 255; every value is within half a step of its de-quantised
