@@ -278,7 +278,8 @@ def main():
         m_dense = dataclasses.replace(march, phong=True)
         FV.fvsrn_render_dense(vol, tf, cams, m_dense, out=ref)
         for name, m in (("none", march), ("forward", m_dense),
-                        ("central", dataclasses.replace(m_dense, grad_mode=1, fd_step=2.0 / 255))):
+                        ("central", dataclasses.replace(m_dense, grad_mode=1, fd_step=2.0 / 255)),
+                        ("adjoint", dataclasses.replace(m_dense, grad_mode=3))):
             FV.fvsrn_render(net, tf, cams, m, "f16", out=out)
             torch.cuda.synchronize()
             e, q = rmse(out), ssim(out)
@@ -288,6 +289,7 @@ def main():
                 shade[name]["image_rmse_vs_dense_phong"] = e
                 shade[name]["image_ssim_vs_dense_phong"] = q
         shade["central_over_forward"] = shade["central"]["ms_per_frame"] / shade["forward"]["ms_per_frame"]
+        shade["forward_over_adjoint"] = shade["forward"]["ms_per_frame"] / shade["adjoint"]["ms_per_frame"]
         if args.train_steps > 0:
             # the network predicts its own gradient (four outputs, Sec. 6):
             # the same architecture fitted to densities and to one-voxel
@@ -315,7 +317,7 @@ def main():
                                   "training": {"steps": args.train_steps, "batch": 1 << 18,
                                                "grad_weight": PRED_GRAD_WEIGHT, "final_loss": float(ptr.loss.item()),
                                                "ms_per_step": t_train / args.train_steps * 1e3}}
-            for k in ("forward", "central"):
+            for k in ("forward", "central", "adjoint"):
                 shade[k + "_over_predicted"] = shade[k]["ms_per_frame"] / shade["predicted"]["ms_per_frame"]
             del ptr, p32, pnet
         comp["shading_f16"] = shade

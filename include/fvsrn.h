@@ -134,9 +134,16 @@ typedef struct {
    FVSRN_GRAD_CENTRAL takes central differences of the network density with
    step fd_step (> 0, world units): seven network evaluations per sample;
    FVSRN_GRAD_PREDICTED uses outputs 1..3 of a num_outputs == 4 network as the
-   gradient (one evaluation per sample, no differentiation).
+   gradient (one evaluation per sample, no differentiation);
+   FVSRN_GRAD_ADJOINT backpropagates through the network to the position
+   (reverse mode: one forward and one transposed pass per sample).
    Dense-grid rendering always uses one-voxel central differences. */
-typedef enum { FVSRN_GRAD_FORWARD = 0, FVSRN_GRAD_CENTRAL = 1, FVSRN_GRAD_PREDICTED = 2 } fvsrn_grad_mode;
+typedef enum {
+  FVSRN_GRAD_FORWARD = 0,
+  FVSRN_GRAD_CENTRAL = 1,
+  FVSRN_GRAD_PREDICTED = 2,
+  FVSRN_GRAD_ADJOINT = 3
+} fvsrn_grad_mode;
 typedef struct {
   float step;
   int32_t fixed_steps;
@@ -156,10 +163,11 @@ typedef struct {
    [0]/[2] is the occupancy of the matrix tiles). A wave marches 64 rays
    without shading, 16 with forward-mode gradients and 8 with central
    differences. Phong shading needs the density gradient, obtained as
-   march->grad_mode selects (Sec. 6). Forward mode and central differences
-   are built for FP32/FP16 networks (central differences and predicted
-   gradients for the sine activation only); other combinations return
-   FVSRN_ERR_UNSUPPORTED. Predicted gradients need num_outputs == 4. */
+   march->grad_mode selects (Sec. 6). Forward mode, central differences and
+   the adjoint are built for FP32/FP16 networks (central differences,
+   predicted gradients and the adjoint for the sine activation only, the
+   adjoint for H <= 4); other combinations return FVSRN_ERR_UNSUPPORTED.
+   Predicted gradients need num_outputs == 4. */
 fvsrn_status fvsrn_render(const fvsrn_net_desc* desc, const fvsrn_params* params,
                           const fvsrn_tf* tf, const fvsrn_camera* cams, int32_t n_views,
                           const fvsrn_march* march, float* out_rgba,
@@ -172,19 +180,16 @@ fvsrn_status fvsrn_eval_points(const fvsrn_net_desc* desc, const fvsrn_params* p
                                const float* xyz, int64_t n, float time, float* out_density,
                                void* stream);
 
-/* Density and its gradient d density / d p at n points by forward-mode
-   differentiation through the network, the Fourier features and the
-   trilinear interpolation (Sec. 6). out_density nullable [n]; out_grad [n][3]. */
+/* Density and its gradient d density / d p at n points (Sec. 6), by
+   grad_mode: FVSRN_GRAD_FORWARD differentiates through the network, the
+   Fourier features and the trilinear interpolation in forward mode;
+   FVSRN_GRAD_ADJOINT does the same in reverse mode (same availability as in
+   fvsrn_render); FVSRN_GRAD_PREDICTED returns outputs 1..3 of a
+   num_outputs == 4 network (one plain evaluation). FVSRN_GRAD_CENTRAL is not
+   offered here. out_density nullable [n]; out_grad [n][3]. */
 fvsrn_status fvsrn_grad_points(const fvsrn_net_desc* desc, const fvsrn_params* params,
-                               const float* xyz, int64_t n, float time, float* out_density,
-                               float* out_grad, void* stream);
-
-/* Density and the network's own gradient prediction (outputs 1..3 of a
-   num_outputs == 4 network, Sec. 6) at n points, one plain evaluation each.
-   out_density nullable [n]; out_grad [n][3]. */
-fvsrn_status fvsrn_pred_grad_points(const fvsrn_net_desc* desc, const fvsrn_params* params,
-                                    const float* xyz, int64_t n, float time, float* out_density,
-                                    float* out_grad, void* stream);
+                               const float* xyz, int64_t n, float time, int32_t grad_mode,
+                               float* out_density, float* out_grad, void* stream);
 
 /* [host] Adam state for fvsrn_train_step (bias-corrected; PyTorch's form
    p -= lr/(1-b1^t) * m / (sqrt(v)/sqrt(1-b2^t) + eps)). */

@@ -1,8 +1,9 @@
 """Builds the gfx950 HIP library ``libfvsrn.so`` in-tree with hipcc.
 
 The network kernels are compiled once per precision (FP32, FP16, BF16) as
-separate translation units, in parallel, then linked with the C ABI and the
-utility kernels into one shared library.
+separate translation units (the adjoint-gradient kernels in units of their
+own), in parallel, then linked with the C ABI and the utility kernels into
+one shared library.
 """
 from __future__ import annotations
 
@@ -26,6 +27,8 @@ UNITS = [
     ("fvsrn_march.hip", ["-DFVSRN_PREC=0"], "march_f32.o"),
     ("fvsrn_march.hip", ["-DFVSRN_PREC=1"], "march_f16.o"),
     ("fvsrn_march.hip", ["-DFVSRN_PREC=2"], "march_bf16.o"),
+    ("fvsrn_adjoint.hip", ["-DFVSRN_PREC=0"], "adj_f32.o"),
+    ("fvsrn_adjoint.hip", ["-DFVSRN_PREC=1"], "adj_f16.o"),
     ("fvsrn_train.hip", [], "train.o"),
 ]
 

@@ -194,7 +194,7 @@ fvsrn_status check_cams(const fvsrn_camera* cams, int32_t n_views, const fvsrn_m
     return fail(FVSRN_ERR_INVALID_ARGUMENT, "step must be >= 2^-16 world units");
   if (!(m->ert_eps >= 0.0f) || m->ert_eps > 1.0f) return fail(FVSRN_ERR_INVALID_ARGUMENT, "ert_eps outside [0, 1]");
   if (m->grad_mode != FVSRN_GRAD_FORWARD && m->grad_mode != FVSRN_GRAD_CENTRAL &&
-      m->grad_mode != FVSRN_GRAD_PREDICTED)
+      m->grad_mode != FVSRN_GRAD_PREDICTED && m->grad_mode != FVSRN_GRAD_ADJOINT)
     return fail(FVSRN_ERR_INVALID_ARGUMENT, "grad_mode unknown");
   if (m->phong && m->grad_mode == FVSRN_GRAD_CENTRAL && !(m->fd_step > 0.0f && m->fd_step < 1.0f))
     return fail(FVSRN_ERR_INVALID_ARGUMENT, "fd_step must be in (0, 1) for central differences");
@@ -293,32 +293,16 @@ fvsrn_status fvsrn_eval_points(const fvsrn_net_desc* desc, const fvsrn_params* p
 }
 
 fvsrn_status fvsrn_grad_points(const fvsrn_net_desc* desc, const fvsrn_params* params, const float* xyz,
-                               int64_t n, float time, float* out_density, float* out_grad, void* stream) {
+                               int64_t n, float time, int32_t grad_mode, float* out_density, float* out_grad,
+                               void* stream) {
   g_err[0] = 0;
   if (n > 0 && !out_grad) return fail(FVSRN_ERR_INVALID_ARGUMENT, "out_grad is NULL");
   fvsrn_status s;
   if ((s = check_desc(desc)) != FVSRN_OK) return s;
   if ((s = check_params(desc, params)) != FVSRN_OK) return s;
-  if (n < 0) return fail(FVSRN_ERR_INVALID_ARGUMENT, "n < 0");
-  if (n == 0) return FVSRN_OK;
-  if (!xyz || !aligned16(xyz) || !aligned16(out_grad) || (out_density && !aligned16(out_density)))
-    return fail(FVSRN_ERR_INVALID_ARGUMENT, "xyz / outputs NULL or misaligned");
-  int key;
-  float kw;
-  key_blend(desc, params, time, &key, &kw);
-  const NetDev nd = make_net(desc, params->latent, params->weights, params->latent_dequant);
-  return launch_status(launch_points(nd, desc->precision, xyz, n, key, kw, out_density, out_grad, 0, stream),
-                       "fvsrn_grad_points");
-}
-
-fvsrn_status fvsrn_pred_grad_points(const fvsrn_net_desc* desc, const fvsrn_params* params, const float* xyz,
-                                    int64_t n, float time, float* out_density, float* out_grad, void* stream) {
-  g_err[0] = 0;
-  if (n > 0 && !out_grad) return fail(FVSRN_ERR_INVALID_ARGUMENT, "out_grad is NULL");
-  fvsrn_status s;
-  if ((s = check_desc(desc)) != FVSRN_OK) return s;
-  if ((s = check_params(desc, params)) != FVSRN_OK) return s;
-  if (n_outputs(*desc) != 4)
+  if (grad_mode != FVSRN_GRAD_FORWARD && grad_mode != FVSRN_GRAD_ADJOINT && grad_mode != FVSRN_GRAD_PREDICTED)
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "grad_mode must be FORWARD, ADJOINT or PREDICTED for points");
+  if (grad_mode == FVSRN_GRAD_PREDICTED && n_outputs(*desc) != 4)
     return fail(FVSRN_ERR_INVALID_ARGUMENT, "predicted gradients need a network with num_outputs == 4");
   if (n < 0) return fail(FVSRN_ERR_INVALID_ARGUMENT, "n < 0");
   if (n == 0) return FVSRN_OK;
@@ -328,8 +312,8 @@ fvsrn_status fvsrn_pred_grad_points(const fvsrn_net_desc* desc, const fvsrn_para
   float kw;
   key_blend(desc, params, time, &key, &kw);
   const NetDev nd = make_net(desc, params->latent, params->weights, params->latent_dequant);
-  return launch_status(launch_points(nd, desc->precision, xyz, n, key, kw, out_density, out_grad, 1, stream),
-                       "fvsrn_pred_grad_points");
+  return launch_status(launch_points(nd, desc->precision, xyz, n, key, kw, out_density, out_grad, grad_mode, stream),
+                       "fvsrn_grad_points");
 }
 
 size_t fvsrn_train_workspace_size(const fvsrn_net_desc* desc, int64_t n) {

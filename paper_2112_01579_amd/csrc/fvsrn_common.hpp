@@ -101,6 +101,15 @@ struct Geo {
   static constexpr int WOT = kF32Path ? 0 : 4 * HS16 * kWave * 8;
   static constexpr int BO = 16;
   __host__ __device__ static int weight_bytes(int H) { return W0A + W0T + (H - 1) * HID + WOA + WOT + BO; }
+  // transposed (backward) fragments of the adjoint pass: W_i^T of each hidden
+  // layer (same shape as W_i, no bias), W_0^T over MB0 16-row tiles covering
+  // the input row's columns, and the output weights (FP32)
+  static constexpr int MB0 = (KROW + 15) / 16;
+  static constexpr int WBH = WHA + WHT;
+  static constexpr int WB0A = kF32Path ? MB0 * 4 * MT * kWave * 4 : MB0 * HS32 * kWave * 16;
+  static constexpr int WB0 = WB0A + (kF32Path ? 0 : MB0 * HS16 * kWave * 8);
+  static constexpr int WOUT = C * 4;
+  __host__ __device__ static int back_bytes(int H) { return (H - 1) * WBH + WB0 + WOUT; }
   static constexpr int FEAT_BYTES = kWave * ROW_DW * 4;  // one wave's input tile
 };
 

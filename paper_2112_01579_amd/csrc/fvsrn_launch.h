@@ -68,10 +68,10 @@ enum Prec { kF32 = 0, kF16 = 1, kBF16 = 2, kU8 = 3 };
 // 2 on a HIP launch error. `stream` is a hipStream_t.
 int launch_render(const NetDev& net, int prec, const TFDev& tf, const ViewBatch& views,
                   const MarchDev& m, float* out, unsigned long long* stats, void* stream);
-// pred: out_g receives outputs 1..3 of a 4-output network (value mode);
-// otherwise a non-null out_g asks for the forward-mode gradient.
+// A non-null out_g receives the gradient by gmode: 0 forward mode, 2 outputs
+// 1..3 of a 4-output network (value mode), 3 the adjoint.
 int launch_points(const NetDev& net, int prec, const float* xyz, long long n, int key,
-                  float key_w, float* out_d, float* out_g, int pred, void* stream);
+                  float key_w, float* out_d, float* out_g, int gmode, void* stream);
 int launch_render_dense(const float* vol, int nx, int ny, int nz, const TFDev& tf,
                         const ViewBatch& views, const MarchDev& m, float* out,
                         unsigned long long* stats, void* stream);
@@ -108,5 +108,13 @@ int launch_render_p2(const NetDev&, const TFDev&, const ViewBatch&, const MarchD
 int launch_points_p0(const NetDev&, const float*, long long, int, float, float*, float*, int, void*);
 int launch_points_p1(const NetDev&, const float*, long long, int, float, float*, float*, int, void*);
 int launch_points_p2(const NetDev&, const float*, long long, int, float, float*, float*, int, void*);
+
+// Adjoint-gradient render and points (fvsrn_adjoint.hip, FP32 and FP16 networks).
+int launch_render_adj_p0(const NetDev&, const TFDev&, const ViewBatch&, const MarchDev&, float*,
+                         unsigned long long*, void*);
+int launch_render_adj_p1(const NetDev&, const TFDev&, const ViewBatch&, const MarchDev&, float*,
+                         unsigned long long*, void*);
+int launch_points_adj_p0(const NetDev&, const float*, long long, int, float, float*, float*, void*);
+int launch_points_adj_p1(const NetDev&, const float*, long long, int, float, float*, float*, void*);
 
 }  // namespace fvsrn_detail

@@ -1,18 +1,7 @@
-// Fused fV-SRN ray-march and point-evaluation kernels for one network
-// precision (compiled once per precision with FVSRN_PREC = 0 FP32, 1 FP16,
-// 2 BF16).
-//
-// Render: one wavefront owns a tile of rays -- 8x8 pixels without shading,
-// 4x4 pixels (four lanes per ray: value and three tangents) for forward-mode
-// gradients, 4x2 pixels (eight lanes per ray: centre and six central-difference
-// neighbours) for finite-difference gradients; a network that predicts its
-// own gradient (four outputs) shades from 8x8 tiles like the unshaded render.
-// Per march step every lane
-// builds its input row, the wave runs the MLP on the matrix cores, and the
-// ray-owning lanes map the density through the transfer function and
-// composite front to back (Sec. 3, Sec. 4), stopping when the transmittance
-// falls below the termination threshold.
-#include "fvsrn_net.hpp"
+// Per-precision instantiation and dispatch of the render and point kernels
+// (compiled once per precision with FVSRN_PREC = 0 FP32, 1 FP16, 2 BF16);
+// the adjoint shading mode lives in fvsrn_adjoint.hip.
+#include "fvsrn_march.hpp"
 
 #ifndef FVSRN_PREC
 #error "FVSRN_PREC must be defined (0 FP32, 1 FP16, 2 BF16)"
@@ -21,404 +10,6 @@
 namespace fvsrn_detail {
 
 namespace {
-
-// Shading modes of the render kernel: none, forward-mode gradient, central
-// differences, the network's predicted gradient (Sec. 6).
-enum { kShadeNone = 0, kShadeFwd = 1, kShadeFD = 2, kShadePred = 3 };
-
-// Waves per workgroup cap (sets the VGPR budget through the launch bounds):
-// value-mode networks with the packed FP16 latent path fit 4 waves per SIMD
-// (<= 128 VGPRs), other value-mode networks 3 (<= 168), forward mode 2.
-// Central differences add the neighbour offsets and the gradient gather to
-// the value-mode network; with F = 16 channels gathered in FP32 (c = 48, or
-// an FP16 network on an FP32 grid) that needs 2 waves per SIMD, c = 48 with
-// the packed latent path 3.
-template <class CF, int MODE>
-constexpr int max_waves() {
-  if (MODE == kShadeFwd) return 8;
-  if (MODE == kShadeFD) {
-    if (CF::F == 16 && (CF::C == 48 || (CF::P == kF16 && !CF::G16))) return 8;
-    return (CF::G16 && CF::C == 32) ? 16 : 12;
-  }
-  return CF::G16 ? 16 : 12;
-}
-
-// Render tile geometry per shading mode: lanes per ray and tile edges.
-template <int MODE>
-struct TileShape {
-  static constexpr int LPR = (MODE == kShadeNone || MODE == kShadePred) ? 1 : (MODE == kShadeFwd ? 4 : 8);
-  static constexpr int TW = LPR == 1 ? 8 : 4;
-  static constexpr int TH = 64 / LPR / TW;
-};
-constexpr int kLdsBytes = 160 * 1024;
-
-// Waves per workgroup. The VGPR budget of max_waves allows that many waves
-// on a CU; every workgroup holds the weights once plus one input tile per
-// wave in LDS. Pick the size that puts the most waves on a CU and, among
-// sizes that reach it, the smallest: several smaller workgroups per CU let
-// the dispatcher replace a finished one while another still runs its long
-// rays (measured: 3 x 4 waves beat 1 x 12 waves by 12% on the BF16 path).
-template <class CF, int MODE>
-int waves_per_block(int H) {
-  using G = typename CF::G;
-  constexpr int cap = max_waves<CF, MODE>();
-  const int wb = G::weight_bytes(H);
-  int best = 0, best_waves = 0;
-  for (int w = 1; w <= cap; ++w) {
-    const int per_cu = kLdsBytes / (wb + w * G::FEAT_BYTES);
-    const int waves = per_cu * w < cap ? per_cu * w : cap;
-    if (per_cu >= 1 && waves > best_waves) {
-      best = w;
-      best_waves = waves;
-    }
-  }
-  return best;
-}
-
-// ----------------------------------------------------- TF, camera, march
-
-__device__ inline void tf_eval(const TFDev& tf, float d, float rgba[4]) {
-#pragma unroll
-  for (int q = 0; q < 4; ++q) rgba[q] = tf.base[q];
-  for (int j = 0; j < tf.n_seg; ++j) {
-    const float w = __builtin_amdgcn_fmed3f(fmaf(d, tf.inv[j], tf.off[j]), 0.0f, 1.0f);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) rgba[q] = fmaf(w, tf.delta[j][q], rgba[q]);
-  }
-}
-
-struct Ray {
-  float o[3], d[3];
-  float t0, t1, ds;
-  int nseg;
-  bool hit;
-};
-
-__device__ inline Ray make_ray(const CamDev& cam, int px, int py, int W, int H, const MarchDev& m) {
-  Ray r;
-  const float nx = (2.0f * px + 1.0f) / (float)W - 1.0f;
-  const float ny = 1.0f - (2.0f * py + 1.0f) / (float)H;
-  const float sx = cam.aspect * nx;
-  if (cam.ortho) {
-    const float h = cam.half_extent;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      r.o[a] = cam.eye[a] + h * (sx * cam.right[a] + ny * cam.up[a]);
-      r.d[a] = cam.fwd[a];
-    }
-  } else {
-    float dd[3], l2 = 0.0f;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      dd[a] = cam.fwd[a] + cam.tan_half * (sx * cam.right[a] + ny * cam.up[a]);
-      l2 += dd[a] * dd[a];
-    }
-    const float inv = 1.0f / sqrtf(l2);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      r.o[a] = cam.eye[a];
-      r.d[a] = dd[a] * inv;
-    }
-  }
-  float tn = -INFINITY, tf = INFINITY;
-  bool miss = false;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    if (r.d[a] == 0.0f) {
-      if (r.o[a] < -1.0f || r.o[a] > 1.0f) miss = true;
-    } else {
-      float ta = (-1.0f - r.o[a]) / r.d[a], tb = (1.0f - r.o[a]) / r.d[a];
-      if (ta > tb) {
-        const float s = ta;
-        ta = tb;
-        tb = s;
-      }
-      tn = fmaxf(tn, ta);
-      tf = fminf(tf, tb);
-    }
-  }
-  tn = fmaxf(tn, 0.0f);
-  r.t0 = tn;
-  r.t1 = tf;
-  r.hit = !miss && tf > tn;
-  if (m.fixed_steps > 0) {
-    r.nseg = m.fixed_steps;
-    r.ds = (tf - tn) / (float)m.fixed_steps;
-  } else {
-    r.ds = m.step;
-    r.nseg = r.hit ? (int)ceilf((tf - tn) / m.step) : 0;
-  }
-  if (!r.hit) r.nseg = 0;
-  return r;
-}
-
-// Segment i of a ray: midpoint parameter and length (last one clipped).
-__device__ inline void segment(const Ray& r, int i, bool fixed, float& tm, float& len) {
-  const float a0 = r.t0 + (float)i * r.ds;
-  float a1 = r.t0 + (float)(i + 1) * r.ds;
-  if (!fixed) a1 = fminf(a1, r.t1);
-  len = a1 - a0;
-  tm = 0.5f * (a0 + a1);
-}
-
-// Headlight Blinn-Phong (Sec. 6): light and view along -dir, normal = the
-// normalized density gradient.
-__device__ inline void phong(float rgba[4], float gx, float gy, float gz, const float dir[3], const MarchDev& m) {
-  const float gl = sqrtf(gx * gx + gy * gy + gz * gz);
-  if (gl >= 1e-6f) {
-    const float ndl = fabsf(gx * dir[0] + gy * dir[1] + gz * dir[2]) / gl;
-    const float spec = m.ks * powf(ndl, m.shininess);
-    const float k = m.ka + m.kd * ndl;
-    rgba[0] = fmaf(rgba[0], k, spec);
-    rgba[1] = fmaf(rgba[1], k, spec);
-    rgba[2] = fmaf(rgba[2], k, spec);
-  }
-}
-
-// Front-to-back compositing of one segment (exact Beer-Lambert).
-struct Accum {
-  float T, C[3], A;
-};
-
-__device__ inline void composite(Accum& acc, const float rgba[4], float len) {
-  const float trn = fast_exp(-rgba[3] * len);
-  const float ta = acc.T * (1.0f - trn);
-  acc.C[0] = fmaf(ta, rgba[0], acc.C[0]);
-  acc.C[1] = fmaf(ta, rgba[1], acc.C[1]);
-  acc.C[2] = fmaf(ta, rgba[2], acc.C[2]);
-  acc.A += ta;
-  acc.T *= trn;
-}
-
-// ------------------------------------------------------------- kernels
-
-// Launched with one tile per wave (the tile loop also serves smaller grids).
-// The hardware dispatcher then balances the work: a persistent grid with a
-// static share of tiles per wave was measured 30% slower, because the
-// per-wave sums of tile costs (empty, short and long rays) vary and the
-// launch waits for the unluckiest wave.
-template <class CF, int MODE>
-__global__ __launch_bounds__((max_waves<CF, MODE>() * 64)) void march_kernel(NetDev nd, TFDev tf, ViewBatch vb,
-                                                                                  MarchDev m, float* out,
-                                                                                  unsigned long long* stats,
-                                                                                  int tiles_x, int tiles_y) {
-  using G = typename CF::G;
-  using E = typename CF::E;
-  constexpr bool GRAD = MODE == kShadeFwd;  // network run in forward (tangent) mode
-  constexpr bool FD = MODE == kShadeFD;
-  constexpr int LPR = TileShape<MODE>::LPR, TW = TileShape<MODE>::TW;
-  extern __shared__ __attribute__((aligned(16))) char smem[];
-  stage_weights<CF>(nd, smem);
-  __syncthreads();
-  // the wave index is wave-uniform; saying so keeps the tile, its camera and
-  // the latent grid's buffer resource in scalar registers
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int wpb = blockDim.x >> 6;
-  const int tiles_per_view = tiles_x * tiles_y;
-  const int n_tiles = tiles_per_view * vb.n_views;
-  const int n_waves = gridDim.x * wpb;
-  const int rl = lane / LPR;  // ray within the tile
-  const int q = lane % LPR;   // role of the lane within its ray
-  const LaneRole role = GRAD ? grad_role(q) : value_role();
-  // central differences: lane q = 1..6 evaluates the sample moved by +-h along
-  // axis (q-1)/2 (odd q: +h); q = 0 and 7 evaluate the sample itself
-  const float fh = (q & 1) ? m.fd_step : -m.fd_step;
-  const float fd_off[3] = {FD && (q == 1 || q == 2) ? fh : 0.0f, FD && (q == 3 || q == 4) ? fh : 0.0f,
-                           FD && (q == 5 || q == 6) ? fh : 0.0f};
-  const float inv_2h = FD ? 0.5f / m.fd_step : 0.0f;
-  const bool fixed = m.fixed_steps > 0;
-  E* feat = reinterpret_cast<E*>(smem + G::weight_bytes(nd.H) + wave * G::FEAT_BYTES);
-  E* myrow = feat + lane * G::ROW;
-  unsigned long long n_samp = 0, n_hit = 0, iters = 0;
-  for (int tile = blockIdx.x * wpb + wave; tile < n_tiles; tile += n_waves) {
-    const int v = tile / tiles_per_view;
-    const int tr = tile % tiles_per_view;
-    const int px = (tr % tiles_x) * TW + (rl % TW);
-    const int py = (tr / tiles_x) * TileShape<MODE>::TH + (rl / TW);
-    const CamDev& cam = vb.cam[v];
-    const LatentSrc ls = make_latent_src(nd, cam.key, cam.key_w);
-    const bool in_img = px < vb.width && py < vb.height;
-    const Ray ray = make_ray(cam, in_img ? px : 0, in_img ? py : 0, vb.width, vb.height, m);
-    bool active = in_img && ray.hit && ray.nseg > 0;
-    Accum acc = {1.0f, {0.0f, 0.0f, 0.0f}, 0.0f};
-    int i = 0;
-    while (__builtin_amdgcn_ballot_w64(active)) {
-      ++iters;
-      float tm, len;
-      segment(ray, i, fixed, tm, len);
-      float sx = ray.o[0] + tm * ray.d[0], sy = ray.o[1] + tm * ray.d[1], sz = ray.o[2] + tm * ray.d[2];
-      if constexpr (FD) {
-        sx += fd_off[0];
-        sy += fd_off[1];
-        sz += fd_off[2];
-      }
-      sx = active ? sx : 0.0f;
-      sy = active ? sy : 0.0f;
-      sz = active ? sz : 0.0f;
-      write_features<CF, GRAD>(myrow, ls, role, sx, sy, sz);
-      wave_lds_sync();
-      const f4 yo = mlp_tile<CF, GRAD>(smem, feat, nd.H, role);
-      wave_lds_sync();
-      const float y = yo[0];
-      float dens, gx = 0.0f, gy = 0.0f, gz = 0.0f;
-      if constexpr (MODE == kShadePred) {
-        // outputs 1..3 are the gradient itself
-        dens = sigmoid_f(y);
-        gx = yo[1];
-        gy = yo[2];
-        gz = yo[3];
-      } else if constexpr (GRAD) {
-        // the quad's value lane holds the logit, lanes 1..3 its derivatives
-        const float y0 = quad_bcast0(y);
-        const float t1 = quad_bcast<1>(y), t2 = quad_bcast<2>(y), t3 = quad_bcast<3>(y);
-        dens = sigmoid_f(y0);
-        const float sg = dens * (1.0f - dens);
-        gx = sg * t1;
-        gy = sg * t2;
-        gz = sg * t3;
-      } else if constexpr (FD) {
-        // gather the seven densities of the ray's lane group
-        const float dl = sigmoid_f(y);
-        const int b = lane & ~7;
-        dens = __shfl(dl, b, 64);
-        gx = (__shfl(dl, b + 1, 64) - __shfl(dl, b + 2, 64)) * inv_2h;
-        gy = (__shfl(dl, b + 3, 64) - __shfl(dl, b + 4, 64)) * inv_2h;
-        gz = (__shfl(dl, b + 5, 64) - __shfl(dl, b + 6, 64)) * inv_2h;
-      } else {
-        dens = sigmoid_f(y);
-      }
-      if (active) {
-        if (len <= 0.0f) {
-          active = false;
-        } else {
-          float rgba[4];
-          tf_eval(tf, dens, rgba);
-          if (m.phong) phong(rgba, gx, gy, gz, ray.d, m);
-          composite(acc, rgba, len);
-          ++i;
-          if (acc.T < m.ert_eps || i >= ray.nseg) active = false;
-        }
-      }
-    }
-    const bool owner = q == 0;
-    if (in_img && owner) {
-      float4* o = reinterpret_cast<float4*>(out) + ((long long)v * vb.height + py) * vb.width + px;
-      *o = make_float4(acc.C[0], acc.C[1], acc.C[2], acc.A);
-    }
-    n_samp += owner ? (unsigned long long)i : 0ull;
-    n_hit += (owner && in_img && ray.hit && ray.nseg > 0) ? 1ull : 0ull;
-  }
-  if (stats) {
-    for (int off = 32; off > 0; off >>= 1) {
-      n_samp += __shfl_xor(n_samp, off, 64);
-      n_hit += __shfl_xor(n_hit, off, 64);
-    }
-    if (lane == 0 && (n_samp | n_hit | iters)) {
-      atomicAdd(stats, n_samp);
-      atomicAdd(stats + 1, n_hit);
-      atomicAdd(stats + 2, iters * (unsigned long long)(64 / LPR));
-    }
-  }
-}
-
-// Point evaluation: density only, forward-mode gradient (GRAD), or the
-// predicted gradient of a 4-output network (value mode with out_g set).
-template <class CF, bool GRAD>
-__global__ __launch_bounds__((max_waves<CF, GRAD ? kShadeFwd : kShadeNone>() * 64)) void points_kernel(NetDev nd, const float* xyz, long long n, int key,
-                                                                float key_w, float* out_d, float* out_g) {
-  using G = typename CF::G;
-  using E = typename CF::E;
-  constexpr int PER = GRAD ? 16 : 64;  // points per wave step
-  extern __shared__ __attribute__((aligned(16))) char smem[];
-  stage_weights<CF>(nd, smem);
-  __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  E* feat = reinterpret_cast<E*>(smem + G::weight_bytes(nd.H) + wave * G::FEAT_BYTES);
-  E* myrow = feat + lane * G::ROW;
-  const LaneRole role = GRAD ? grad_role(lane & 3) : value_role();
-  const LatentSrc ls = make_latent_src(nd, key, key_w);
-  const long long nchunks = (n + PER - 1) / PER;
-  const int waves = blockDim.x >> 6;
-  for (long long c = (long long)blockIdx.x * waves + wave; c < nchunks; c += (long long)gridDim.x * waves) {
-    const long long idx = c * PER + (GRAD ? (lane >> 2) : lane);
-    const bool ok = idx < n;
-    float x = 0.0f, y = 0.0f, z = 0.0f;
-    if (ok) {
-      x = xyz[3 * idx];
-      y = xyz[3 * idx + 1];
-      z = xyz[3 * idx + 2];
-    }
-    write_features<CF, GRAD>(myrow, ls, role, x, y, z);
-    wave_lds_sync();
-    const f4 oo = mlp_tile<CF, GRAD>(smem, feat, nd.H, role);
-    wave_lds_sync();
-    const float o = oo[0];
-    if constexpr (GRAD) {
-      const float d = sigmoid_f(quad_bcast0(o));
-      if (ok) {
-        if (role.is_val) {
-          if (out_d) out_d[idx] = d;
-        } else {
-          out_g[3 * idx + role.axis] = d * (1.0f - d) * o;
-        }
-      }
-    } else if (ok) {
-      if (out_d) out_d[idx] = sigmoid_f(o);
-      if (out_g) {
-        out_g[3 * idx] = oo[1];
-        out_g[3 * idx + 1] = oo[2];
-        out_g[3 * idx + 2] = oo[3];
-      }
-    }
-  }
-}
-
-// ------------------------------------------------------------ launchers
-
-template <class CF, int MODE>
-int launch_render_t(const NetDev& nd, const TFDev& tf, const ViewBatch& vb, const MarchDev& m, float* out,
-                    unsigned long long* stats, hipStream_t st) {
-  using G = typename CF::G;
-  constexpr int TW = TileShape<MODE>::TW, TH = TileShape<MODE>::TH;
-  const int tx = (vb.width + TW - 1) / TW, ty = (vb.height + TH - 1) / TH;
-  const long long tiles = (long long)tx * ty * vb.n_views;
-  if (tiles > 0x7fffffffLL) return 1;
-  const int wpb = waves_per_block<CF, MODE>(nd.H);
-  if (wpb < 1) return 1;
-  const size_t shm = (size_t)G::weight_bytes(nd.H) + (size_t)wpb * G::FEAT_BYTES;
-  const long long blocks = (tiles + wpb - 1) / wpb;  // one tile per wave
-  if (blocks > 0x7fffffffLL) return 1;
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute((const void*)march_kernel<CF, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              kLdsBytes);
-    attr = true;
-  }
-  hipLaunchKernelGGL((march_kernel<CF, MODE>), dim3((unsigned)blocks), dim3(wpb * 64), shm, st, nd, tf, vb, m, out,
-                     stats, tx, ty);
-  return check_launch();
-}
-
-template <class CF, bool GRAD>
-int launch_points_t(const NetDev& nd, const float* xyz, long long n, int key, float key_w, float* out_d,
-                    float* out_g, hipStream_t st) {
-  using G = typename CF::G;
-  constexpr int PER = GRAD ? 16 : 64;
-  const int wpb = waves_per_block<CF, GRAD ? kShadeFwd : kShadeNone>(nd.H);
-  if (wpb < 1) return 1;
-  const size_t shm = (size_t)G::weight_bytes(nd.H) + (size_t)wpb * G::FEAT_BYTES;
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute((const void*)points_kernel<CF, GRAD>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              kLdsBytes);
-    attr = true;
-  }
-  // each wave walks several chunks so that the weight staging is amortised
-  const int blocks = grid_blocks((n + PER - 1) / PER, wpb * 8, device_cus() * 4);
-  hipLaunchKernelGGL((points_kernel<CF, GRAD>), dim3(blocks), dim3(wpb * 64), shm, st, nd, xyz, n, key, key_w,
-                     out_d, out_g);
-  return check_launch();
-}
 
 template <int C, int F, int L, int ACT, int MODE, int GK>
 struct Entry {
@@ -430,7 +21,7 @@ struct Entry {
   static int points(const NetDev& nd, const float* xyz, long long n, int key, float key_w, float* out_d,
                     float* out_g, hipStream_t st) {
     // predicted gradients use the value-mode kernel (its out_g holds outputs 1..3)
-    return launch_points_t<CF, MODE == kShadeFwd>(nd, xyz, n, key, key_w, out_d, out_g, st);
+    return launch_points_t<CF, MODE == kShadeFwd ? kShadeFwd : kShadeNone>(nd, xyz, n, key, key_w, out_d, out_g, st);
   }
 };
 
@@ -471,6 +62,13 @@ struct Entry {
 
 int FV_PASTE(launch_render_p, FVSRN_PREC)(const NetDev& nd, const TFDev& tf, const ViewBatch& vb, const MarchDev& m,
                                           float* out, unsigned long long* stats, void* stream) {
+  if (m.phong && m.grad_mode == 3) {
+#if FVSRN_PREC != 2
+    return FV_PASTE(launch_render_adj_p, FVSRN_PREC)(nd, tf, vb, m, out, stats, stream);
+#else
+    return 1;
+#endif
+  }
   const int mode = !m.phong ? kShadeNone : (m.grad_mode == 1 ? kShadeFD : (m.grad_mode == 2 ? kShadePred : kShadeFwd));
   // packed FP16 gathers for an FP16 network on an FP16 or uint8 grid
   const int gk = FVSRN_PREC != 1 ? 0 : (nd.grid_u8 ? 2 : (nd.grid_f16 ? 1 : 0));
@@ -489,8 +87,16 @@ int FV_PASTE(launch_render_p, FVSRN_PREC)(const NetDev& nd, const TFDev& tf, con
 }
 
 int FV_PASTE(launch_points_p, FVSRN_PREC)(const NetDev& nd, const float* xyz, long long n, int key, float key_w,
-                                          float* out_d, float* out_g, int pred, void* stream) {
-  const int mode = (out_g != nullptr && !pred) ? kShadeFwd : kShadeNone;
+                                          float* out_d, float* out_g, int gmode, void* stream) {
+  if (out_g && gmode == 3) {
+#if FVSRN_PREC != 2
+    return FV_PASTE(launch_points_adj_p, FVSRN_PREC)(nd, xyz, n, key, key_w, out_d, out_g, stream);
+#else
+    return 1;
+#endif
+  }
+  // gmode 2: a 4-output network's own gradient, from the value-mode kernel
+  const int mode = (out_g != nullptr && gmode == 0) ? kShadeFwd : kShadeNone;
   // packed FP16 gathers for an FP16 network on an FP16 or uint8 grid
   const int gk = FVSRN_PREC != 1 ? 0 : (nd.grid_u8 ? 2 : (nd.grid_f16 ? 1 : 0));
   const hipStream_t st = (hipStream_t)stream;

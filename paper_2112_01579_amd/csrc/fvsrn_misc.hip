@@ -379,11 +379,11 @@ int launch_render(const NetDev& net, int prec, const TFDev& tf, const ViewBatch&
 }
 
 int launch_points(const NetDev& net, int prec, const float* xyz, long long n, int key, float key_w, float* out_d,
-                  float* out_g, int pred, void* stream) {
+                  float* out_g, int gmode, void* stream) {
   switch (prec) {
-    case kF32: return launch_points_p0(net, xyz, n, key, key_w, out_d, out_g, pred, stream);
-    case kF16: return launch_points_p1(net, xyz, n, key, key_w, out_d, out_g, pred, stream);
-    case kBF16: return launch_points_p2(net, xyz, n, key, key_w, out_d, out_g, pred, stream);
+    case kF32: return launch_points_p0(net, xyz, n, key, key_w, out_d, out_g, gmode, stream);
+    case kF16: return launch_points_p1(net, xyz, n, key, key_w, out_d, out_g, gmode, stream);
+    case kBF16: return launch_points_p2(net, xyz, n, key, key_w, out_d, out_g, gmode, stream);
   }
   return 1;
 }

@@ -25,7 +25,7 @@ PREC = {"f32": F32, "fp32": F32, "f16": F16, "fp16": F16, "bf16": BF16}
 OK, ERR_INVALID_ARGUMENT, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_DEVICE = 0, 1, 2, 3, 4
 
 EXPORTS = (
-    "fvsrn_render", "fvsrn_eval_points", "fvsrn_grad_points", "fvsrn_pred_grad_points", "fvsrn_train_step",
+    "fvsrn_render", "fvsrn_eval_points", "fvsrn_grad_points", "fvsrn_train_step",
     "fvsrn_train_workspace_size", "fvsrn_render_dense", "fvsrn_dense_eval_points", "fvsrn_dense_grad_points",
     "fvsrn_sample_points", "fvsrn_cast_grid", "fvsrn_quantize_grid", "fvsrn_ssim_map", "fvsrn_num_weights",
     "fvsrn_status_str", "fvsrn_last_error",
@@ -89,8 +89,7 @@ def lib():
         sig = {
             "fvsrn_render": (st, [vp, vp, vp, vp, i32, vp, vp, vp, vp]),
             "fvsrn_eval_points": (st, [vp, vp, vp, i64, C.c_float, vp, vp]),
-            "fvsrn_grad_points": (st, [vp, vp, vp, i64, C.c_float, vp, vp, vp]),
-            "fvsrn_pred_grad_points": (st, [vp, vp, vp, i64, C.c_float, vp, vp, vp]),
+            "fvsrn_grad_points": (st, [vp, vp, vp, i64, C.c_float, i32, vp, vp, vp]),
             "fvsrn_train_step": (st, [vp, vp, vp, C.POINTER(C.c_float), vp, vp, vp, vp, i64, vp, vp, C.c_float,
                                       vp, vp, vp, vp, sz, vp]),
             "fvsrn_train_workspace_size": (sz, [vp, i64]),
@@ -230,27 +229,25 @@ def fvsrn_eval_points(net: Network, xyz: torch.Tensor, time: float = 0.0, precis
     return out
 
 
-def fvsrn_grad_points(net: Network, xyz: torch.Tensor, time: float = 0.0, precision="f32",
+GRAD_MODES = {"forward": 0, "central": 1, "predicted": 2, "adjoint": 3}
+
+
+def fvsrn_grad_points(net: Network, xyz: torch.Tensor, time: float = 0.0, precision="f32", mode="forward",
                       stream=None):
+    """Density and d density / d p at points: forward mode, adjoint (reverse
+    mode) or a 4-output network's predicted gradient (``mode``)."""
     n = xyz.shape[0]
     dens = torch.empty(n, dtype=torch.float32, device=xyz.device)
     grad = torch.empty((n, 3), dtype=torch.float32, device=xyz.device)
     d, p = net.desc(precision), net.params()
-    _check(lib().fvsrn_grad_points(C.byref(d), C.byref(p), _ptr(xyz), n, time, _ptr(dens), _ptr(grad),
-                                   _stream(stream)), "fvsrn_grad_points")
+    _check(lib().fvsrn_grad_points(C.byref(d), C.byref(p), _ptr(xyz), n, time, GRAD_MODES[mode], _ptr(dens),
+                                   _ptr(grad), _stream(stream)), "fvsrn_grad_points")
     return dens, grad
 
 
-def fvsrn_pred_grad_points(net: Network, xyz: torch.Tensor, time: float = 0.0, precision="f32",
-                           stream=None):
+def fvsrn_pred_grad_points(net: Network, xyz: torch.Tensor, time: float = 0.0, precision="f32", stream=None):
     """Density and the predicted gradient (outputs 1..3) of a 4-output network."""
-    n = xyz.shape[0]
-    dens = torch.empty(n, dtype=torch.float32, device=xyz.device)
-    grad = torch.empty((n, 3), dtype=torch.float32, device=xyz.device)
-    d, p = net.desc(precision), net.params()
-    _check(lib().fvsrn_pred_grad_points(C.byref(d), C.byref(p), _ptr(xyz), n, time, _ptr(dens), _ptr(grad),
-                                        _stream(stream)), "fvsrn_pred_grad_points")
-    return dens, grad
+    return fvsrn_grad_points(net, xyz, time, precision, "predicted", stream)
 
 
 def fvsrn_render_dense(vol: torch.Tensor, tf: I.TF, cams: Sequence[I.Camera], march: I.March,

@@ -128,10 +128,15 @@ def test_points_argument_errors_and_empty_noop():
         == FV.ERR_INVALID_ARGUMENT
     # n == 0 is a no-op that touches nothing
     assert L.fvsrn_eval_points(C.byref(d), C.byref(p), None, 0, 0.0, None, None) == FV.OK
-    assert L.fvsrn_grad_points(C.byref(d), C.byref(p), None, 0, 0.0, None, None, None) == FV.OK
+    for gm in (0, 3):
+        assert L.fvsrn_grad_points(C.byref(d), C.byref(p), None, 0, 0.0, gm, None, None, None) == FV.OK
+    # central differences are not offered for points; unknown modes are rejected
+    for gm in (1, 4, -1):
+        assert L.fvsrn_grad_points(C.byref(d), C.byref(p), C.c_void_p(FAKE), 5, 0.0, gm, None, C.c_void_p(FAKE),
+                                   None) == FV.ERR_INVALID_ARGUMENT
     assert L.fvsrn_eval_points(C.byref(d), C.byref(p), C.c_void_p(FAKE + 8), 5, 0.0, C.c_void_p(FAKE), None) \
         == FV.ERR_INVALID_ARGUMENT
-    assert L.fvsrn_grad_points(C.byref(d), C.byref(p), C.c_void_p(FAKE), 5, 0.0, None, None, None) \
+    assert L.fvsrn_grad_points(C.byref(d), C.byref(p), C.c_void_p(FAKE), 5, 0.0, 0, None, None, None) \
         == FV.ERR_INVALID_ARGUMENT
     assert L.fvsrn_dense_eval_points(C.c_void_p(FAKE), 1, 4, 4, C.c_void_p(FAKE), 3, C.c_void_p(FAKE), None) \
         == FV.ERR_INVALID_ARGUMENT
@@ -142,12 +147,12 @@ def test_points_argument_errors_and_empty_noop():
     assert L.fvsrn_dense_grad_points(C.c_void_p(FAKE), 4, 1, 4, C.c_void_p(FAKE), 3, None, C.c_void_p(FAKE),
                                      None) == FV.ERR_INVALID_ARGUMENT
     # predicted gradients need a 4-output network
-    assert L.fvsrn_pred_grad_points(C.byref(d), C.byref(p), C.c_void_p(FAKE), 5, 0.0, None, C.c_void_p(FAKE),
-                                    None) == FV.ERR_INVALID_ARGUMENT
+    assert L.fvsrn_grad_points(C.byref(d), C.byref(p), C.c_void_p(FAKE), 5, 0.0, 2, None, C.c_void_p(FAKE),
+                               None) == FV.ERR_INVALID_ARGUMENT
     assert b"num_outputs" in L.fvsrn_last_error()
     d4 = _desc(num_outputs=4)
-    assert L.fvsrn_pred_grad_points(C.byref(d4), C.byref(p), None, 0, 0.0, None, None, None) == FV.OK
-    assert L.fvsrn_pred_grad_points(C.byref(d4), C.byref(p), C.c_void_p(FAKE), 5, 0.0, None, None, None) \
+    assert L.fvsrn_grad_points(C.byref(d4), C.byref(p), None, 0, 0.0, 2, None, None, None) == FV.OK
+    assert L.fvsrn_grad_points(C.byref(d4), C.byref(p), C.c_void_p(FAKE), 5, 0.0, 2, None, None, None) \
         == FV.ERR_INVALID_ARGUMENT
     assert L.fvsrn_sample_points(1, 2, 0, None, None) == FV.OK
     assert L.fvsrn_sample_points(1, 2, -3, None, None) == FV.ERR_INVALID_ARGUMENT

@@ -559,3 +559,75 @@ def test_dense_grad_points(FV):
     assert np.abs(d.cpu().numpy() - dref).max() <= 1e-6
     # each component differences two FP32 samples over 2h (h >= 1/6 here)
     assert np.abs(g.cpu().numpy() - gref).max() <= 1e-5
+
+
+# ------------------------------------------- adjoint (reverse-mode) gradient
+
+def _rev_ref(onet, xyz, t=0.0):
+    d = np.empty(len(xyz))
+    g = np.empty((len(xyz), 3))
+    for i, p in enumerate(xyz):
+        d[i], g[i] = O.density_grad(onet, p, t, mode="rev")
+    return d, g
+
+
+@pytest.mark.parametrize("spec", [I.NET_SMALL, I.NET_STUDY, I.NET_SHADED, I.NetSpec(R=12, F=16, L=8, c=48, H=1),
+                                  I.NetSpec(R=12, F=8, L=4, c=48, H=2)],
+                         ids=["small", "study", "shaded", "c48H1", "c48H2"])
+def test_adjoint_grad_points(FV, spec):
+    """Reverse-mode gradient (Sec. 6's adjoint: one forward and one transposed
+    pass) against the oracle's reverse mode, at every layer count compiled
+    (H = 1..4), c = 32 and 48, FP32 and FP16 networks on FP32, FP16 and uint8
+    grids, a ragged point count with a few points outside the domain (the
+    latent part of the gradient vanishes there)."""
+    xyz = np.concatenate([I.uniform_points(64 * 5 + 13, 19, -0.999, 0.999),
+                          np.array([[1.2, 0.1, -0.3], [-0.5, -1.1, 0.9], [0.3, 0.2, 1.05]], np.float32)])
+    for gd in (FV.F32, FV.F16, FV.U8):
+        gnet, onet = _nets(FV, spec, 23, grid_dtype=gd)
+        dref, gref = _rev_ref(onet, xyz)
+        for prec, dtol, gtol in (("f32", FP32_TOL, 1e-4), ("f16", FP16_TOL, 1e-2)):
+            d, g = FV.fvsrn_grad_points(gnet, torch.from_numpy(xyz).cuda(), 0.0, prec, mode="adjoint")
+            derr, gerr = np.abs(d.cpu().numpy() - dref).max(), _grad_err(g.cpu().numpy(), gref)
+            _report("adjoint c=%d H=%d grid %d %s density" % (spec.c, spec.H, gd, prec), derr)
+            _report("adjoint c=%d H=%d grid %d %s gradient (rel.)" % (spec.c, spec.H, gd, prec), gerr)
+            assert derr <= dtol and gerr <= gtol
+
+
+def test_adjoint_grad_points_keyframes_edges_and_limits(FV):
+    spec = I.NetSpec(R=8, F=16, L=8, c=32, H=3, K=3)
+    gnet, onet = _nets(FV, spec, 7, key_times=(0.0, 1.0, 3.0))
+    for n in (1, 63, 64, 65):
+        xyz = I.uniform_points(n, n + 1, -0.99, 0.99)
+        for t in (0.5, 2.5):
+            dref, gref = _rev_ref(onet, xyz, t)
+            d, g = FV.fvsrn_grad_points(gnet, torch.from_numpy(xyz).cuda(), t, "f32", mode="adjoint")
+            assert np.abs(d.cpu().numpy() - dref).max() <= FP32_TOL
+            assert _grad_err(g.cpu().numpy(), gref) <= 1e-4
+    # H > 4, BF16 and other activations are not compiled for the adjoint
+    xyz = torch.from_numpy(I.uniform_points(10, 3)).cuda()
+    for spec, prec in ((I.NetSpec(R=8, F=8, L=4, c=32, H=5), "f32"), (I.NET_SMALL, "bf16"),
+                       (I.NetSpec(R=8, F=8, L=4, c=32, H=2, act="snakealt"), "f32")):
+        gnet, _ = _nets(FV, spec, 2)
+        with pytest.raises(FV.FvsrnError) as e:
+            FV.fvsrn_grad_points(gnet, xyz, 0.0, prec, mode="adjoint")
+        assert e.value.status == FV.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-4), ("f16", FP16_TOL)])
+def test_phong_render_adjoint(FV, prec, tol):
+    """Phong shading from the adjoint gradient on the shaded (c = 48) and
+    study (c = 32) networks, ragged views, against the oracle's reverse-mode
+    render; the same bounds as forward-mode shading."""
+    for spec, seed in ((I.NET_SHADED, I.SEED_SHADED), (I.NET_STUDY, I.SEED_STUDY)):
+        gnet, onet = _nets(FV, spec, seed, grid_dtype=FV.F16 if prec == "f16" else FV.F32)
+        tf = I.ramp_tf()
+        cams = I.orbit_cameras(2, 23, 15)
+        m = I.March(step=1 / 128, ert_eps=0.0, phong=True, grad_mode=3)
+        ref, ns = O.render(O.Field(net=onet), tf, cams, m)
+        stats = torch.zeros(3, dtype=torch.int64, device="cuda")
+        img = FV.fvsrn_render(gnet, tf, cams, m, prec, stats=stats).cpu().numpy()
+        err = np.abs(img - ref).max()
+        _report("phong adjoint c=%d %s" % (spec.c, prec), err)
+        assert err <= tol
+        assert abs(stats[0].item() - ns) <= 0.001 * ns
+        assert stats[2].item() % 64 == 0
