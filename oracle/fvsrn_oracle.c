@@ -22,7 +22,13 @@
 
 /* Input width of the first layer: position (3), latent vector (F) and the
    sine and cosine Fourier blocks (3L each) -- Sec. 3 Eq. 2 and Sec. 4.2. */
-int32_t orc_input_width(const orc_net* net) { return 3 + net->F + 6 * net->L; }
+/* Time inputs by encoding (Sec. 8): none, tau, four sin/cos octaves of tau, both. */
+static int time_inputs(const orc_net* net) {
+  static const int n[4] = {0, 1, 8, 9};
+  return (net->time_enc >= 0 && net->time_enc < 4) ? n[net->time_enc] : 0;
+}
+
+int32_t orc_input_width(const orc_net* net) { return 3 + net->F + 6 * net->L + time_inputs(net); }
 
 static int layer_in(const orc_net* net, int i) { return i == 0 ? orc_input_width(net) : net->c; }
 static int n_outputs(const orc_net* net) { return net->outputs > 1 ? net->outputs : 1; }
@@ -41,7 +47,8 @@ static int net_ok(const orc_net* net) {
   return net && net->R >= 2 && net->F >= 0 && net->K >= 1 && net->L >= 0 && net->c >= 1 &&
          (net->outputs <= 1 || net->outputs == 4) &&
          net->H >= 1 && net->weights && (net->F == 0 || net->latent || (net->latent_u8 && net->dequant)) &&
-         (net->K == 1 || net->key_times);
+         (net->K == 1 || net->key_times) && net->time_enc >= 0 && net->time_enc < 4 &&
+         (net->time_enc == 0 || net->time_hi > net->time_lo);
 }
 
 /* ------------------------------------------------------- latent grid (4.2) */
@@ -164,6 +171,18 @@ int orc_features(const orc_net* net, const double p[3], double t, double* v0, do
         dv[(c0 + 3 * k + a) * 3 + a] = -freq * sin(freq * p[a]);
       }
     }
+  /* time inputs (Sec. 8), after the spatial Fourier block; they do not
+     depend on p */
+  if (net->time_enc != 0) {
+    double tc = t < net->time_lo ? net->time_lo : (t > net->time_hi ? net->time_hi : t);
+    double tau = 2.0 * (tc - net->time_lo) / (net->time_hi - net->time_lo) - 1.0;
+    int j = 3 + F + 6 * L;
+    if (net->time_enc == 1 || net->time_enc == 3) v0[j++] = tau;
+    if (net->time_enc >= 2) {
+      for (int k = 0; k < 4; ++k) v0[j + k] = sin(M_PI * ldexp(1.0, k) * tau);
+      for (int k = 0; k < 4; ++k) v0[j + 4 + k] = cos(M_PI * ldexp(1.0, k) * tau);
+    }
+  }
   return 0;
 }
 

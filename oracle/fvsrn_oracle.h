@@ -51,6 +51,13 @@ typedef struct {
      vertex value = dequant[k][f][0] + dequant[k][f][1] * code[k][vertex][f] */
   const uint8_t* latent_u8;   /* [K][R][R][R][F] codes */
   const double* dequant;      /* [K][F][2] (offset, scale) */
+  /* time encoding of the network input (Sec. 8): 0 latent only, 1 direct
+     (the normalised time tau as one more input), 2 Fourier (sin and cos of
+     pi 2^k tau, k = 0..3), 3 both; tau = 2 (clamp(t) - time_lo) /
+     (time_hi - time_lo) - 1, t clamped to [time_lo, time_hi] */
+  int32_t time_enc;
+  int32_t pad_;
+  double time_lo, time_hi;
 } orc_net;
 
 typedef struct {            /* piecewise-linear transfer function */
@@ -94,7 +101,7 @@ typedef struct {
 } orc_field;
 
 int64_t orc_num_weights(const orc_net* net);
-int32_t orc_input_width(const orc_net* net);
+int32_t orc_input_width(const orc_net* net);  /* 3 + F + 6L + time inputs (0, 1, 8 or 9) */
 
 /* Trilinear latent vector at p and keyframe time t; dz (nullable) gets
    dz[f*3+a] = d z_f / d p_a. */

@@ -46,10 +46,11 @@ class NetSpec:
     K: int = 1        # latent keyframes
     act: str = "sine"
     outputs: int = 1  # 1 (density) or 4 (density and its predicted gradient)
+    time_enc: int = 0  # time input (Sec. 8): 0 latent only, 1 direct, 2 Fourier, 3 both
 
     @property
     def K0(self) -> int:
-        return 3 + self.F + 6 * self.L
+        return 3 + self.F + 6 * self.L + (0, 1, 8, 9)[self.time_enc]
 
     def layer_shapes(self) -> List[Tuple[int, int]]:
         """(out, in) of every weight matrix, input layer first."""

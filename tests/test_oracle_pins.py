@@ -871,3 +871,86 @@ def test_gradient_target_training_against_central_differences():
         e[idx] = 1
         fd = (L(net.latent + h * e, net.weights) - L(net.latent - h * e, net.weights)) / (2 * h)
         assert abs(dl[idx] - fd) < 1e-8 * max(1, abs(fd))
+
+
+# ------------------------------------------- time encodings (Sec. 8)
+
+def test_time_encoding_features_closed_form():
+    """The time inputs follow the spatial Fourier block: tau (direct), then
+    sin and cos of pi 2^k tau for k = 0..3 (Fourier), both for 'both'; tau
+    maps [time_lo, time_hi] onto [-1, 1] and clamps outside. Their rows of the
+    position Jacobian are zero."""
+    for te, width in ((0, 0), (1, 1), (2, 8), (3, 9)):
+        spec = I.NetSpec(R=4, F=2, L=1, c=4, H=1, time_enc=te)
+        assert spec.K0 == 3 + 2 + 6 + width
+        net = O.Net(spec, *I.net_params(spec, 1), time_range=(2.0, 6.0))
+        assert net.K0 == spec.K0
+        base = 3 + 2 + 6
+        for t, tau in ((2.0, -1.0), (6.0, 1.0), (4.0, 0.0), (5.0, 0.5), (0.0, -1.0), (9.0, 1.0)):
+            v0, dv = O.features(net, [0.1, -0.2, 0.3], t)
+            tail = v0[base:]
+            want = []
+            if te in (1, 3):
+                want.append(tau)
+            if te in (2, 3):
+                want += [math.sin(math.pi * 2 ** k * tau) for k in range(4)]
+                want += [math.cos(math.pi * 2 ** k * tau) for k in range(4)]
+            np.testing.assert_allclose(tail, want, atol=1e-15)
+            assert np.all(dv[base:] == 0)
+    # tau = 0.5: sin(pi/2) = 1, cos(pi) = -1, sin(2 pi) = 0 (exact values)
+    spec = I.NetSpec(R=4, F=2, L=1, c=4, H=1, time_enc=2)
+    v0, _ = O.features(O.Net(spec, *I.net_params(spec, 1), time_range=(0.0, 4.0)), [0, 0, 0], 3.0)
+    np.testing.assert_allclose(v0[11:19], [1, 0, 0, 0, 0, -1, 1, 1], atol=1e-15)
+
+
+def test_time_encoding_layer0_columns():
+    """A network whose time columns carry zero weight is the latent-only
+    network with the same remaining weights (the columns sit at the end of
+    the input, after the cosine block); with non-zero time weights the
+    density of a single-keyframe network changes with t."""
+    base = I.NetSpec(R=5, F=4, L=2, c=8, H=2)
+    lat, w0 = I.net_params(base, 9)
+    net0 = O.Net(base, lat, w0)
+    for te, nt in ((1, 1), (2, 8), (3, 9)):
+        spec = dataclasses_replace(base, time_enc=te)
+        K0 = base.K0
+        W0 = w0[:8 * K0].reshape(8, K0)
+        W0t = np.concatenate([W0, np.zeros((8, nt), np.float32)], axis=1)
+        w = np.concatenate([W0t.reshape(-1), w0[8 * K0:]])
+        net = O.Net(spec, lat, w, time_range=(0.0, 1.0))
+        wr = w.copy()
+        wr.reshape(-1)[:8 * (K0 + nt)].reshape(8, K0 + nt)[:, K0:] = RNG.normal(0, 1, (8, nt))
+        netr = O.Net(spec, lat, wr, time_range=(0.0, 1.0))
+        for p in RNG.uniform(-1, 1, (4, 3)):
+            for t in (0.0, 0.3, 1.0):
+                assert O.density(net, p, t) == O.density(net0, p, t)
+            assert abs(O.density(netr, p, 0.1) - O.density(netr, p, 0.9)) > 1e-6
+
+
+def test_time_encoding_training_gradient_by_central_differences():
+    """The loss gradient with respect to a time-column weight of layer 0 (and
+    the position gradient's independence of t's encoding) by central
+    differences of the oracle's own loss."""
+    spec = I.NetSpec(R=4, F=2, L=1, c=6, H=2, K=2, time_enc=3)
+    lat, w = I.net_params(spec, 12)
+    kt = (0.0, 2.0)
+    net = O.Net(spec, lat, w, kt)
+    n = 9
+    xyz = I.uniform_points(n, 3, -0.9, 0.9)
+    times = np.linspace(-0.5, 2.5, n)
+    up = RNG.normal(size=n)
+    _, dw, _ = O.train_grads(net, xyz, dloss_dd=up, times=times)
+    K0 = spec.K0
+    h = 1e-6
+    for col in (K0 - 9, K0 - 5, K0 - 1):   # tau, sin(pi tau), cos(8 pi tau) columns of output channel 2
+        j = 2 * K0 + col
+        wp, wm = w.astype(np.float64).copy(), w.astype(np.float64).copy()
+        wp[j] += h
+        wm[j] -= h
+        fp = sum(u * O.density(O.Net(spec, lat, wp, kt), p, t) for u, p, t in zip(up, xyz, times))
+        fm = sum(u * O.density(O.Net(spec, lat, wm, kt), p, t) for u, p, t in zip(up, xyz, times))
+        assert abs(dw[j] - (fp - fm) / (2 * h)) < 1e-7 * max(1.0, abs(dw[j]))
+    for p in RNG.uniform(-0.9, 0.9, (3, 3)):
+        d1, g1 = O.density_grad(net, p, 0.7, mode="fwd")
+        d2, g2 = O.density_grad(net, p, 0.7, mode="rev")
+        np.testing.assert_allclose(g1, g2, rtol=1e-11, atol=1e-14)
