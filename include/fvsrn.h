@@ -29,12 +29,13 @@
  *    R-2, so p = 1 hits the last vertex exactly.
  *  - Latent grid layout [K][R_z][R_y][R_x][F]: channel fastest, then x, y, z,
  *    then keyframe.
- *  - Network input v0 = [x, y, z, latent(F), sin-block(3L), cos-block(3L)];
- *    block entry 3k+a is sin / cos(pi * 2^k * p_a), k = 0..L-1 (Eq. 1 with the
- *    octave frequencies pi*2^k, Eq. 2's concatenation).
+ *  - Network input v0 = [x, y, z, latent(F), sin-block(3L), cos-block(3L),
+ *    time inputs (0, 1, 8 or 9, see fvsrn_time_encoding)]; block entry 3k+a is
+ *    sin / cos(pi * 2^k * p_a), k = 0..L-1 (Eq. 1 with the octave frequencies
+ *    pi*2^k, Eq. 2's concatenation).
  *  - Weights (FP32 master copy, the layout the trainer updates): for each
  *    layer i = 0..H, W_i[out][in] row-major, then b_i[out]. Layer 0 maps
- *    K0 = 3 + F + 6L inputs to c channels, layers 1..H-1 map c to c, layer H
+ *    K0 = 3 + F + 6L (+ time inputs) inputs to c channels, layers 1..H-1 map c to c, layer H
  *    maps c to num_outputs (1, or 4 for a predicted gradient). Layers 0..H-1
  *    apply the activation (sine: sin(x); SnakeAlt: 0.5x + sin^2(x), Sec. 5
  *    Eq. 3); the sigmoid of output 0 is the density in (0,1) (Sec. 3).
@@ -82,7 +83,23 @@ typedef struct {
                             density gradient d density / d p (Sec. 6). 0 means 1. The
                             output layer holds W_out [num_outputs][c] then b_out
                             [num_outputs]; the density is the sigmoid of output 0. */
+  int32_t time_encoding; /* fvsrn_time_encoding: extra network inputs from the time (Sec. 8),
+                            appended to layer 0's inputs after the cosine block */
+  float time_lo, time_hi; /* time range mapped onto tau in [-1, 1] (times clamped to it);
+                            used when time_encoding != FVSRN_TIME_LATENT_ONLY, time_hi > time_lo */
 } fvsrn_net_desc;
+
+/* Time encodings (Sec. 8): the latent grids are blended in time in every case;
+   DIRECT adds tau as one input, FOURIER adds sin and cos of pi 2^k tau for
+   k = 0..3 (8 inputs), BOTH adds tau then the 8 Fourier inputs. Networks with a
+   time input are built for the sine activation, FP32/FP16 arithmetic, the
+   unshaded render, point densities and training. */
+typedef enum {
+  FVSRN_TIME_LATENT_ONLY = 0,
+  FVSRN_TIME_DIRECT = 1,
+  FVSRN_TIME_FOURIER = 2,
+  FVSRN_TIME_BOTH = 3
+} fvsrn_time_encoding;
 
 typedef struct {
   const void* latent;       /* [K][R][R][R][F] in grid_dtype */

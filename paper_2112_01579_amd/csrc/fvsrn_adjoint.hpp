@@ -33,7 +33,7 @@ __device__ void stage_backward_adj(const NetDev& nd, char* p) {
   using G = typename CF::G;
   using E = typename CF::E;
   constexpr int C = CF::C, F = CF::F, L = CF::L, MT = G::MT, MB0 = G::MB0;
-  const int H = nd.H, K0 = 3 + F + 6 * L;
+  const int H = nd.H, K0 = G::K0IN;
   const float* w = nd.weights;
   const int tid = threadIdx.x, nt = blockDim.x;
   auto off_layer = [&](int i) -> long long {  // W_i for 1 <= i <= H
@@ -285,7 +285,7 @@ __device__ __attribute__((always_inline)) inline float mlp_tile_adj(const char* 
         VA b[NT];
 #pragma unroll
         for (int u = 0; u < NT; ++u)
-          b[u] = *reinterpret_cast<const VA*>(feat + (16 * (tp + u) + n) * G::ROW + G::KMAIN);
+          b[u] = *reinterpret_cast<const VA*>(feat + (16 * (tp + u) + n) * G::ROW + G::KMAIN + 8 * (g % (G::KT / 8)));
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
           const VA a = W0T[mt * kWave + lane];

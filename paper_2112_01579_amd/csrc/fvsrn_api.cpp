@@ -27,8 +27,14 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 int n_outputs(const fvsrn_net_desc& d) { return d.num_outputs == 0 ? 1 : d.num_outputs; }
 
+int time_inputs(const fvsrn_net_desc& d) {
+  static const int n[4] = {0, 1, 8, 9};
+  return (d.time_encoding >= 0 && d.time_encoding < 4) ? n[d.time_encoding] : 0;
+}
+
 int64_t num_weights(const fvsrn_net_desc& d) {
-  const int64_t K0 = 3 + d.grid_channels + 6 * (int64_t)d.num_freqs, c = d.hidden_width, no = n_outputs(d);
+  const int64_t K0 = 3 + d.grid_channels + 6 * (int64_t)d.num_freqs + time_inputs(d), c = d.hidden_width,
+                no = n_outputs(d);
   return c * K0 + c + (int64_t)(d.hidden_layers - 1) * (c * c + c) + no * c + no;
 }
 
@@ -55,6 +61,11 @@ fvsrn_status check_desc(const fvsrn_net_desc* d) {
   if (d->hidden_layers > 8) return fail(FVSRN_ERR_UNSUPPORTED, "hidden_layers %d > 8", d->hidden_layers);
   if (d->num_outputs != 0 && d->num_outputs != 1 && d->num_outputs != 4)
     return fail(FVSRN_ERR_INVALID_ARGUMENT, "num_outputs %d: must be 1 or 4 (0 means 1)", d->num_outputs);
+  if (d->time_encoding < FVSRN_TIME_LATENT_ONLY || d->time_encoding > FVSRN_TIME_BOTH)
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "time_encoding %d unknown", d->time_encoding);
+  if (d->time_encoding != FVSRN_TIME_LATENT_ONLY &&
+      !(d->time_hi > d->time_lo && d->time_hi - d->time_lo < 3.0e38f && d->time_lo > -3.0e38f))
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "time encodings need finite time_lo < time_hi");
   // the kernels address one keyframe grid with 32-bit byte offsets
   const long long grid_bytes = (long long)d->grid_res * d->grid_res * d->grid_res * d->grid_channels *
                                (d->grid_dtype == FVSRN_U8 ? 1 : (d->grid_dtype == FVSRN_F16 ? 2 : 4));
@@ -97,7 +108,19 @@ NetDev make_net(const fvsrn_net_desc* d, const void* latent, const float* weight
   n.grid_u8 = d->grid_dtype == FVSRN_U8;
   n.dequant = n.grid_u8 ? dequant : nullptr;
   n.NO = n_outputs(*d);
+  n.time_enc = d->time_encoding;
+  n.t_lo = d->time_lo;
+  n.t_hi = d->time_hi;
+  n.t_scale = d->time_encoding ? (float)(2.0 / ((double)d->time_hi - d->time_lo)) : 0.0f;
+  n.tau = 0.0f;
   return n;
+}
+
+// tau of time t for a time-encoded network: [lo, hi] onto [-1, 1], clamped.
+float time_tau(const fvsrn_net_desc* d, float t) {
+  if (!d->time_encoding) return 0.0f;
+  const double tc = t < d->time_lo ? d->time_lo : (t > d->time_hi ? d->time_hi : t);
+  return (float)(2.0 * (tc - d->time_lo) / ((double)d->time_hi - d->time_lo) - 1.0);
 }
 
 // Keyframe pair and blend weight for time t (clamped to the keyframe range).
@@ -172,6 +195,7 @@ fvsrn_status make_views(const fvsrn_camera* cams, int n_views, int first, int co
     o.aspect = (float)((double)c.width / (double)c.height);
     o.ortho = c.ortho ? 1 : 0;
     if (d && p) key_blend(d, p, c.time, &o.key, &o.key_w);
+    o.tau = d ? time_tau(d, c.time) : 0.0f;
   }
   return FVSRN_OK;
 }
@@ -287,7 +311,8 @@ fvsrn_status fvsrn_eval_points(const fvsrn_net_desc* desc, const fvsrn_params* p
   int key;
   float kw;
   key_blend(desc, params, time, &key, &kw);
-  const NetDev nd = make_net(desc, params->latent, params->weights, params->latent_dequant);
+  NetDev nd = make_net(desc, params->latent, params->weights, params->latent_dequant);
+  nd.tau = time_tau(desc, time);
   return launch_status(launch_points(nd, desc->precision, xyz, n, key, kw, out_density, nullptr, 0, stream),
                        "fvsrn_eval_points");
 }
@@ -311,7 +336,8 @@ fvsrn_status fvsrn_grad_points(const fvsrn_net_desc* desc, const fvsrn_params* p
   int key;
   float kw;
   key_blend(desc, params, time, &key, &kw);
-  const NetDev nd = make_net(desc, params->latent, params->weights, params->latent_dequant);
+  NetDev nd = make_net(desc, params->latent, params->weights, params->latent_dequant);
+  nd.tau = time_tau(desc, time);
   return launch_status(launch_points(nd, desc->precision, xyz, n, key, kw, out_density, out_grad, grad_mode, stream),
                        "fvsrn_grad_points");
 }

@@ -66,21 +66,31 @@ struct PrecT<kF32> {
 };
 
 // Compile-time geometry of one network configuration (precision P, hidden
-// width C, latent channels F, Fourier octaves L).
+// width C, latent channels F, Fourier octaves L, time encoding TE).
 //
 // Layer 0's input row, one per sample, lives in LDS in the order
-//   [latent F | sin 3L | cos 3L | zero pad to KMAIN | x y z 1 | zero pad to KROW]
+//   [latent F | sin 3L | cos 3L | zero pad to KMAIN | x y z 1 time | zero pad to KROW]
 // so its first KF columns are the packed FP32 inputs 3.. in order and the
-// constant-1 column carries the first layer's bias. For FP16/BF16 the tail
-// (8 columns) is a K32 MFMA step whose A operand is zero beyond column 7.
-template <int P, int C, int F, int L>
+// constant-1 column carries the first layer's bias. The time inputs (Sec. 8)
+// follow it: tau (direct), then sin and cos of pi 2^k tau, k < 4 (Fourier).
+// For FP16/BF16 the tail (8 or 16 columns) is one K32 MFMA step whose A
+// operand is zero beyond the used columns.
+template <int P, int C, int F, int L, int TE = 0>
 struct Geo {
   using PR = PrecT<P>;
   using E = typename PR::E;
   static constexpr int MT = C / 16;                       // M-tiles of a hidden layer
   static constexpr int KF = F + 6 * L;                    // latent + Fourier inputs
+  static constexpr int TIN = TE == 0 ? 0 : (TE == 1 ? 1 : (TE == 2 ? 8 : 9));  // time inputs
+  static constexpr int K0IN = 3 + KF + TIN;               // layer 0 inputs in the weight layout
   static constexpr int KMAIN = (KF + PR::KC - 1) / PR::KC * PR::KC;
-  static constexpr int KROW = KMAIN + PR::KT;
+  // tail: x y z 1 and the time inputs, rounded to the MFMA step's columns
+  static constexpr int KT = (4 + TIN + PR::KT - 1) / PR::KT * PR::KT;
+  static constexpr int KROW = KMAIN + KT;
+  // input-row column of input k of the weight layout [x y z | latent | sin | cos | time]
+  __host__ __device__ static constexpr int feat_col(int k) {
+    return k < 3 ? KMAIN + k : (k < 3 + KF ? k - 3 : KMAIN + 4 + (k - 3 - KF));
+  }
   static constexpr int S0 = KMAIN / PR::KC;               // main K steps of layer 0 (f16/bf16)
   static constexpr int Q0 = KROW / 4;                     // K4 steps of layer 0 (f32)
   // LDS row stride in dwords: the smallest >= the row with stride = 4 (mod 8),

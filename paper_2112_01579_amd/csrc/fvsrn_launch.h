@@ -35,6 +35,7 @@ struct CamDev {
   int ortho;
   int key;        // first keyframe of the latent blend
   float key_w;    // weight of keyframe key + 1
+  float tau;      // normalised time of the view (time-encoded networks)
 };
 
 struct MarchDev {
@@ -55,6 +56,9 @@ struct NetDev {
   int grid_u8;           // uint8 codes; dequant holds (offset, scale) [K][F][2]
   const float* dequant;
   int NO;                // outputs: 1 (density) or 4 (density, predicted gradient)
+  int time_enc;          // time inputs (Sec. 8): 0 none, 1 direct, 2 Fourier, 3 both
+  float t_lo, t_hi, t_scale;  // normalisation of times: tau = (clamp(t) - t_lo) t_scale - 1
+  float tau;             // normalised time of a point evaluation
 };
 
 struct ViewBatch {
@@ -116,5 +120,14 @@ int launch_render_adj_p1(const NetDev&, const TFDev&, const ViewBatch&, const Ma
                          unsigned long long*, void*);
 int launch_points_adj_p0(const NetDev&, const float*, long long, int, float, float*, float*, void*);
 int launch_points_adj_p1(const NetDev&, const float*, long long, int, float, float*, float*, void*);
+
+// Networks with a time encoding (fvsrn_time.hip, FP32 and FP16 networks,
+// sine activation): unshaded render and point densities.
+int launch_render_time_p0(const NetDev&, const TFDev&, const ViewBatch&, const MarchDev&, float*,
+                          unsigned long long*, void*);
+int launch_render_time_p1(const NetDev&, const TFDev&, const ViewBatch&, const MarchDev&, float*,
+                          unsigned long long*, void*);
+int launch_points_time_p0(const NetDev&, const float*, long long, int, float, float*, void*);
+int launch_points_time_p1(const NetDev&, const float*, long long, int, float, float*, void*);
 
 }  // namespace fvsrn_detail

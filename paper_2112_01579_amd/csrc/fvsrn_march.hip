@@ -62,6 +62,13 @@ struct Entry {
 
 int FV_PASTE(launch_render_p, FVSRN_PREC)(const NetDev& nd, const TFDev& tf, const ViewBatch& vb, const MarchDev& m,
                                           float* out, unsigned long long* stats, void* stream) {
+  if (nd.time_enc != 0) {
+#if FVSRN_PREC != 2
+    return FV_PASTE(launch_render_time_p, FVSRN_PREC)(nd, tf, vb, m, out, stats, stream);
+#else
+    return 1;
+#endif
+  }
   if (m.phong && m.grad_mode == 3) {
 #if FVSRN_PREC != 2
     return FV_PASTE(launch_render_adj_p, FVSRN_PREC)(nd, tf, vb, m, out, stats, stream);
@@ -88,6 +95,14 @@ int FV_PASTE(launch_render_p, FVSRN_PREC)(const NetDev& nd, const TFDev& tf, con
 
 int FV_PASTE(launch_points_p, FVSRN_PREC)(const NetDev& nd, const float* xyz, long long n, int key, float key_w,
                                           float* out_d, float* out_g, int gmode, void* stream) {
+  if (nd.time_enc != 0) {
+#if FVSRN_PREC != 2
+    if (out_g) return 1;  // gradients of time-encoded networks are not compiled
+    return FV_PASTE(launch_points_time_p, FVSRN_PREC)(nd, xyz, n, key, key_w, out_d, stream);
+#else
+    return 1;
+#endif
+  }
   if (out_g && gmode == 3) {
 #if FVSRN_PREC != 2
     return FV_PASTE(launch_points_adj_p, FVSRN_PREC)(nd, xyz, n, key, key_w, out_d, out_g, stream);

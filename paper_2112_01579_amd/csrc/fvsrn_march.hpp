@@ -251,6 +251,8 @@ __global__ __launch_bounds__((max_waves<CF, MODE>() * 64)) void march_kernel(Net
     const bool in_img = px < vb.width && py < vb.height;
     const Ray ray = make_ray(cam, in_img ? px : 0, in_img ? py : 0, vb.width, vb.height, m);
     bool active = in_img && ray.hit && ray.nseg > 0;
+    float tfe[G::TIN > 0 ? G::TIN : 1];  // the view's time inputs (time-encoded networks)
+    if constexpr (G::TIN > 0) time_features<CF::TE>(cam.tau, tfe);
     Accum acc = {1.0f, {0.0f, 0.0f, 0.0f}, 0.0f};
     int i = 0;
     while (__builtin_amdgcn_ballot_w64(active)) {
@@ -266,7 +268,7 @@ __global__ __launch_bounds__((max_waves<CF, MODE>() * 64)) void march_kernel(Net
       sx = active ? sx : 0.0f;
       sy = active ? sy : 0.0f;
       sz = active ? sz : 0.0f;
-      write_features<CF, GRAD>(myrow, ls, role, sx, sy, sz);
+      write_features<CF, GRAD>(myrow, ls, role, sx, sy, sz, tfe);
       wave_lds_sync();
       f4 yo;
       float ga[3] = {0.0f, 0.0f, 0.0f};
@@ -370,6 +372,8 @@ __global__ __launch_bounds__((max_waves<CF, PM>() * 64)) void points_kernel(NetD
   E* myrow = feat + lane * G::ROW;
   const LaneRole role = GRAD ? grad_role(lane & 3) : value_role();
   const LatentSrc ls = make_latent_src(nd, key, key_w);
+  float tfe[G::TIN > 0 ? G::TIN : 1];  // time inputs of the evaluation time
+  if constexpr (G::TIN > 0) time_features<CF::TE>(nd.tau, tfe);
   const long long nchunks = (n + PER - 1) / PER;
   const int waves = blockDim.x >> 6;
   for (long long c = (long long)blockIdx.x * waves + wave; c < nchunks; c += (long long)gridDim.x * waves) {
@@ -381,7 +385,7 @@ __global__ __launch_bounds__((max_waves<CF, PM>() * 64)) void points_kernel(NetD
       y = xyz[3 * idx + 1];
       z = xyz[3 * idx + 2];
     }
-    write_features<CF, GRAD>(myrow, ls, role, x, y, z);
+    write_features<CF, GRAD>(myrow, ls, role, x, y, z, tfe);
     wave_lds_sync();
     if constexpr (ADJ) {
       const float o = mlp_tile_adj<CF, HH>(smem, bsm, feat);

@@ -17,12 +17,14 @@ namespace fvsrn_detail {
 // accumulation, grid type chosen at run time), 1 FP16 grid and 2 uint8 grid,
 // both accumulated in packed FP16 (one gather path per instantiation keeps
 // the register peak down). G16 says that a packed path is used.
-template <int P_, int C_, int F_, int L_, int ACT_, int GK_ = 0>
+// TE: time encoding of the input (0 latent only, 1 direct, 2 Fourier, 3 both).
+template <int P_, int C_, int F_, int L_, int ACT_, int GK_ = 0, int TE_ = 0>
 struct Cfg {
   static constexpr int P = P_, C = C_, F = F_, L = L_, ACT = ACT_;
   static constexpr int GK = GK_;
+  static constexpr int TE = TE_;
   static constexpr bool G16 = GK_ != 0;
-  using G = Geo<P, C, F, L>;
+  using G = Geo<P, C, F, L, TE>;
   using E = typename G::E;
 };
 
@@ -61,7 +63,8 @@ __device__ void stage_weights(const NetDev& nd, char* smem) {
   using G = typename CF::G;
   using E = typename CF::E;
   constexpr int C = CF::C, F = CF::F, L = CF::L, MT = G::MT;
-  const int H = nd.H, K0 = 3 + F + 6 * L, NO = nd.NO;
+  constexpr int K0 = G::K0IN;
+  const int H = nd.H, NO = nd.NO;
   const float* w = nd.weights;
   const float sc = CF::ACT == kIdentity ? 1.0f : kInv2Pi;
   // a single uint8 keyframe on the packed path: the de-quantisation is folded
@@ -91,6 +94,7 @@ __device__ void stage_weights(const NetDev& nd, char* smem) {
         for (int ch = 0; ch < F; ++ch) b = fmaf(w[(long long)o * K0 + 3 + ch], dq[2 * ch], b);
       return b * sc;
     }
+    if (t < 4 + G::TIN) return w[(long long)o * K0 + 3 + G::KF + (t - 4)] * sc;  // time inputs
     return 0.0f;
   };
   char* p = smem;
@@ -464,10 +468,32 @@ __device__ inline void latent_column_q(const LatentSrc& ls, const LaneRole& role
   for (int j = 0; j < F / 2; ++j) z2[j] = h2{(_Float16)zf[2 * j], (_Float16)zf[2 * j + 1]};
 }
 
+// Time inputs (Sec. 8) of the normalised time tau, in the row's tail order:
+// tau (direct), then sin and cos of pi 2^k tau for k < 4 (Fourier).
+template <int TE>
+__device__ inline void time_features(float tau, float* tf) {
+  int j = 0;
+  if constexpr (TE == 1 || TE == 3) tf[j++] = tau;
+  if constexpr (TE >= 2) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      tf[j + k] = sin_rev(0.5f * (float)(1 << k) * tau);
+      tf[j + 4 + k] = cos_rev(0.5f * (float)(1 << k) * tau);
+    }
+  }
+}
+
+// Normalised time: [lo, hi] onto [-1, 1], clamped (scale = 2 / (hi - lo)).
+__device__ inline float time_tau(float t, float lo, float hi, float scale) {
+  return fmaf(__builtin_amdgcn_fmed3f(t, lo, hi) - lo, scale, -1.0f);
+}
+
 // Builds this lane's input row at position p and writes it to `row` (LDS).
+// tf: the sample's time inputs (Geo::TIN values; ignored without a time
+// encoding); they do not depend on p, so tangent rows get zeros there.
 template <class CF, bool GRAD>
 __device__ inline void write_features(typename CF::E* row, const LatentSrc& ls, const LaneRole& role, float px,
-                                      float py, float pz) {
+                                      float py, float pz, const float* tf = nullptr) {
   using G = typename CF::G;
   using E = typename CF::E;
   constexpr int F = CF::F, L = CF::L;
@@ -549,6 +575,8 @@ __device__ inline void write_features(typename CF::E* row, const LatentSrc& ls, 
     v[G::KMAIN + 2] = pz;
     v[G::KMAIN + 3] = 1.0f;
   }
+#pragma unroll
+  for (int j = 0; j < G::TIN; ++j) v[G::KMAIN + 4 + j] = (GRAD && !role.is_val) ? 0.0f : tf[j];
   if constexpr (CF::P == kF32) {
     float4* dst = reinterpret_cast<float4*>(row);
 #pragma unroll
@@ -720,15 +748,15 @@ __device__ inline f4 mlp_tile(const char* wsm, const typename CF::E* feat, int H
         }
       }
       {
-        // Tail step [x y z 1 0 0 0 0] as one more K32 step on the same
-        // accumulators (lanes g > 0 read the same 8 columns; their A slots
-        // are zero). Keeping one MFMA shape per accumulator matters: a
+        // Tail step [x y z 1 (time) 0 ...] as one more K32 step on the same
+        // accumulators (lanes past the tail's 8 or 16 columns read them again;
+        // their A slots are zero). Keeping one MFMA shape per accumulator matters: a
         // 16x16x32 result used as the accumulator of the next 16x16x16 MFMA
         // is not reliably interlocked.
         VA b[NT];
 #pragma unroll
         for (int u = 0; u < NT; ++u)
-          b[u] = *reinterpret_cast<const VA*>(feat + (16 * (tp + u) + n) * G::ROW + G::KMAIN);
+          b[u] = *reinterpret_cast<const VA*>(feat + (16 * (tp + u) + n) * G::ROW + G::KMAIN + 8 * (g % (G::KT / 8)));
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
           const VA a = W0T[mt * kWave + lane];

@@ -28,9 +28,9 @@ namespace {
 constexpr int kTrainMaxWaves = 2048;  // fixed number of waves (deterministic partition)
 constexpr int kTrainWavesPerBlock = 8;
 
-template <int C, int F, int L, int ACT>
+template <int C, int F, int L, int ACT, int TE = 0>
 struct TrainCfg {
-  using CF = Cfg<kF32, C, F, L, ACT>;
+  using CF = Cfg<kF32, C, F, L, ACT, 0, TE>;
   using G = typename CF::G;
   static constexpr int S = 16;                      // points per wave chunk (one N-tile)
   static constexpr int NTC = S / 16;
@@ -75,7 +75,7 @@ __device__ inline float act_d(float a) {  // d act / d x at pre-activation a (re
 template <class TC, int ACT>
 __device__ void stage_backward(const NetDev& nd, char* p) {
   constexpr int C = TC::CF::C, F = TC::CF::F, L = TC::CF::L, MT = TC::MT;
-  const int H = nd.H, K0 = 3 + F + 6 * L;
+  const int H = nd.H, K0 = TC::G::K0IN;
   const float* w = nd.weights;
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int i = 1; i < H; ++i) {
@@ -95,14 +95,14 @@ __device__ void stage_backward(const NetDev& nd, char* p) {
   }
 }
 
-template <int C, int F, int L, int ACT>
+template <int C, int F, int L, int ACT, int TE>
 __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDev nd, KeyTimes kt, const float* xyz,
                                                                             const float* times, long long n,
                                                                             const float* target,
                                                                             const float* target_grad, float gw3,
                                                       const float* dloss, float* d_latent, float* ws, int n_waves,
                                                       float inv_n) {
-  using TC = TrainCfg<C, F, L, ACT>;
+  using TC = TrainCfg<C, F, L, ACT, TE>;
   using CF = typename TC::CF;
   using G = typename TC::G;
   using PR = PrecT<kF32>;
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
   const float* WO = reinterpret_cast<const float*>(wout_p);
   const f4 b_out = *reinterpret_cast<const f4*>(wout_p + G::WOA);
   // output weights W_out[o][k] (unscaled) straight from global memory
-  const float* w_out = nd.weights + (long long)C * (3 + F + 6 * L) + C + (long long)(H - 1) * (C * C + C);
+  const float* w_out = nd.weights + (long long)C * G::K0IN + C + (long long)(H - 1) * (C * C + C);
   float loss_acc = 0.0f;
   f4 dbo_acc = {0.0f, 0.0f, 0.0f, 0.0f};
   const long long nchunks = (n + S - 1) / S;
@@ -174,13 +174,17 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
         kw = (pt - kt.t[key]) / (kt.t[key + 1] - kt.t[key]);
       }
     }
+    float tfe[G::TIN > 0 ? G::TIN : 1];  // the point's time inputs (Sec. 8)
+    if constexpr (G::TIN > 0) time_features<TE>(time_tau(pt, nd.t_lo, nd.t_hi, nd.t_scale), tfe);
     if (lane < S) {
       if (nd.K == 1) {
-        write_features<CF, false>(feat + lane * G::ROW, make_latent_src(nd, 0, 0.0f), value_role(), px, py, pz);
+        write_features<CF, false>(feat + lane * G::ROW, make_latent_src(nd, 0, 0.0f), value_role(), px, py, pz,
+                                  tfe);
       } else {
         // per-lane keyframes: the buffer loads of the gather then run once
         // per distinct keyframe present in the wave
-        write_features<CF, false>(feat + lane * G::ROW, make_latent_src(nd, key, kw), value_role(), px, py, pz);
+        write_features<CF, false>(feat + lane * G::ROW, make_latent_src(nd, key, kw), value_role(), px, py, pz,
+                                  tfe);
       }
     }
     wave_lds_sync();
@@ -434,12 +438,12 @@ __global__ void slice_sum_kernel(const float* ws, int n_waves, int sl, float* pa
   partial[(size_t)g * sl + e] = s;
 }
 
-template <int C, int F, int L, int ACT>
+template <int C, int F, int L, int ACT, int TE>
 __global__ void gather_kernel(int H, int NO, const float* partial, int n_groups, float* d_weights, float* out_loss,
                               float loss_scale) {
-  using TC = TrainCfg<C, F, L, ACT>;
+  using TC = TrainCfg<C, F, L, ACT, TE>;
   using G = typename TC::G;
-  const int K0 = 3 + F + 6 * L;
+  const int K0 = G::K0IN;
   const long long nw = (long long)C * K0 + C + (long long)(H - 1) * (C * C + C) + (long long)NO * (C + 1);
   const int SL = TC::slice(H);
   for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < nw + 1;
@@ -458,7 +462,7 @@ __global__ void gather_kernel(int H, int NO, const float* partial, int n_groups,
         if (r < l0) {
           o = (int)(r / K0);
           const int k = (int)(r % K0);
-          col = k < 3 ? G::KMAIN + k : k - 3;
+          col = G::feat_col(k);
         } else {
           o = (int)(r - l0);
           col = G::KMAIN + 3;
@@ -529,9 +533,9 @@ __global__ void adam_kernel(float* p, const float* g, float* m, float* v, long l
   }
 }
 
-template <int C, int F, int L, int ACT>
+template <int C, int F, int L, int ACT, int TE = 0>
 struct TrainEntry {
-  using TC = TrainCfg<C, F, L, ACT>;
+  using TC = TrainCfg<C, F, L, ACT, TE>;
   static int waves_per_block(int H) {
     const int fixed = TC::G::weight_bytes(H) + TC::back_bytes(H);
     int w = (160 * 1024 - fixed) / TC::wave_bytes(H);
@@ -562,7 +566,7 @@ struct TrainEntry {
     const size_t shm = (size_t)TC::block_bytes(H, wpb);
     static bool attr = false;
     if (!attr) {
-      (void)hipFuncSetAttribute((const void*)fwd_bwd_kernel<C, F, L, ACT>,
+      (void)hipFuncSetAttribute((const void*)fwd_bwd_kernel<C, F, L, ACT, TE>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
       attr = true;
     }
@@ -570,7 +574,7 @@ struct TrainEntry {
     nd2.latent = latent;
     nd2.grid_f16 = 0;
     if (n > 0) {
-      hipLaunchKernelGGL((fwd_bwd_kernel<C, F, L, ACT>), dim3((nw + wpb - 1) / wpb), dim3(wpb * 64), shm, st, nd2,
+      hipLaunchKernelGGL((fwd_bwd_kernel<C, F, L, ACT, TE>), dim3((nw + wpb - 1) / wpb), dim3(wpb * 64), shm, st, nd2,
                          kt, xyz, times, n, target, target_grad, grad_weight / 3.0f, dloss, d_latent, (float*)ws, nw,
                          1.0f / (float)n);
       rc = check_launch();
@@ -588,9 +592,9 @@ struct TrainEntry {
                        partial);
     rc = check_launch();
     if (rc) return rc;
-    const long long nwts = (long long)C * (3 + F + 6 * L) + C + (long long)(H - 1) * (C * C + C) +
+    const long long nwts = (long long)C * TC::G::K0IN + C + (long long)(H - 1) * (C * C + C) +
                            (long long)nd.NO * (C + 1);
-    hipLaunchKernelGGL((gather_kernel<C, F, L, ACT>), dim3(grid_blocks(nwts + 1, 128, 1024)), dim3(128), 0, st, H,
+    hipLaunchKernelGGL((gather_kernel<C, F, L, ACT, TE>), dim3(grid_blocks(nwts + 1, 128, 1024)), dim3(128), 0, st, H,
                        nd.NO, (const float*)partial, ng, d_weights, out_loss, target && n > 0 ? 1.0f / (float)n : 1.0f);
     return check_launch();
   }
@@ -607,6 +611,9 @@ struct TrainEntry {
 size_t train_workspace_bytes(const NetDev& nd, long long n) {
 #define X(C_, F_, L_)                                                            \
   if (nd.C == C_ && nd.F == F_ && nd.L == L_) {                                  \
+    if (nd.time_enc == 1) return TrainEntry<C_, F_, L_, kSine, 1>::ws_bytes(nd, n); \
+    if (nd.time_enc == 2) return TrainEntry<C_, F_, L_, kSine, 2>::ws_bytes(nd, n); \
+    if (nd.time_enc == 3) return TrainEntry<C_, F_, L_, kSine, 3>::ws_bytes(nd, n); \
     if (nd.act == kSine) return TrainEntry<C_, F_, L_, kSine>::ws_bytes(nd, n);  \
     if (nd.act == kSnakeAlt) return TrainEntry<C_, F_, L_, kSnakeAlt>::ws_bytes(nd, n); \
     return TrainEntry<C_, F_, L_, kIdentity>::ws_bytes(nd, n);                   \
@@ -625,27 +632,36 @@ int launch_train(const NetDev& nd, const KeyTimes& kt, float* latent, float* wei
   NetDev net = nd;
   net.weights = weights;
   int rc = 1;
-#define X(C_, F_, L_)                                                                                           \
-  if (nd.C == C_ && nd.F == F_ && nd.L == L_) {                                                                 \
-    if (nd.act == kSine)                                                                                        \
-      rc = TrainEntry<C_, F_, L_, kSine>::run(net, kt, latent, d_latent, d_weights, xyz, times, n, target,      \
-                                              target_grad, grad_weight, dloss_dy, out_loss, workspace, st);                               \
-    else if (nd.act == kSnakeAlt)                                                                               \
-      rc = TrainEntry<C_, F_, L_, kSnakeAlt>::run(net, kt, latent, d_latent, d_weights, xyz, times, n, target,  \
-                                                  target_grad, grad_weight, dloss_dy, out_loss, workspace, st);                           \
-    else                                                                                                        \
-      rc = TrainEntry<C_, F_, L_, kIdentity>::run(net, kt, latent, d_latent, d_weights, xyz, times, n, target,  \
-                                                  target_grad, grad_weight, dloss_dy, out_loss, workspace, st);                           \
+#define FV_TRAIN_RUN(C_, F_, L_, ACT_, TE_)                                                                  \
+  rc = TrainEntry<C_, F_, L_, ACT_, TE_>::run(net, kt, latent, d_latent, d_weights, xyz, times, n, target,     \
+                                              target_grad, grad_weight, dloss_dy, out_loss, workspace, st)
+#define X(C_, F_, L_)                                                        \
+  if (nd.C == C_ && nd.F == F_ && nd.L == L_) {                              \
+    if (nd.time_enc != 0) {                                                  \
+      /* time encodings are compiled for the sine activation */             \
+      if (nd.act != kSine) rc = 1;                                           \
+      else if (nd.time_enc == 1) FV_TRAIN_RUN(C_, F_, L_, kSine, 1);         \
+      else if (nd.time_enc == 2) FV_TRAIN_RUN(C_, F_, L_, kSine, 2);         \
+      else FV_TRAIN_RUN(C_, F_, L_, kSine, 3);                               \
+    } else if (nd.act == kSine) {                                            \
+      FV_TRAIN_RUN(C_, F_, L_, kSine, 0);                                    \
+    } else if (nd.act == kSnakeAlt) {                                        \
+      FV_TRAIN_RUN(C_, F_, L_, kSnakeAlt, 0);                                \
+    } else {                                                                 \
+      FV_TRAIN_RUN(C_, F_, L_, kIdentity, 0);                                \
+    }                                                                        \
   }
   FV_TRAIN_CASES(X)
 #undef X
+#undef FV_TRAIN_RUN
   (void)ws_bytes;
   if (rc != 0 || !use_adam) return rc;
   const double bc1 = 1.0 - pow((double)beta1, (double)step);
   const double bc2 = 1.0 - pow((double)beta2, (double)step);
   const long long nlat = (long long)nd.K * nd.R * nd.R * nd.R * nd.F;
-  const long long nw = (long long)nd.C * (3 + nd.F + 6 * nd.L) + nd.C + (long long)(nd.H - 1) * (nd.C * nd.C + nd.C) +
-                       (long long)nd.NO * (nd.C + 1);
+  static const int kTimeInputs[4] = {0, 1, 8, 9};
+  const long long nw = (long long)nd.C * (3 + nd.F + 6 * nd.L + kTimeInputs[nd.time_enc]) + nd.C +
+                       (long long)(nd.H - 1) * (nd.C * nd.C + nd.C) + (long long)nd.NO * (nd.C + 1);
   hipLaunchKernelGGL(adam_kernel, dim3(grid_blocks(nlat, 256, device_cus() * 8)), dim3(256), 0, st, latent, d_latent,
                      m_lat, v_lat, nlat, (float)(lr_grid / bc1), beta1, beta2, (float)(1.0 / sqrt(bc2)), eps);
   rc = check_launch();

@@ -42,7 +42,8 @@ class NetDesc(C.Structure):
     _fields_ = [("grid_res", C.c_int32), ("grid_channels", C.c_int32), ("grid_dtype", C.c_int32),
                 ("num_keyframes", C.c_int32), ("num_freqs", C.c_int32), ("hidden_width", C.c_int32),
                 ("hidden_layers", C.c_int32), ("activation", C.c_int32), ("precision", C.c_int32),
-                ("num_outputs", C.c_int32)]
+                ("num_outputs", C.c_int32), ("time_encoding", C.c_int32), ("time_lo", C.c_float),
+                ("time_hi", C.c_float)]
 
 
 class Params(C.Structure):
@@ -130,9 +131,10 @@ def _stream(stream=None):
 
 # ----------------------------------------------------------- structs
 
-def net_desc(spec: I.NetSpec, precision="f32", grid_dtype=F32) -> NetDesc:
+def net_desc(spec: I.NetSpec, precision="f32", grid_dtype=F32, time_range=(0.0, 1.0)) -> NetDesc:
     return NetDesc(spec.R, spec.F, grid_dtype, spec.K, spec.L, spec.c, spec.H, ACT[spec.act],
-                   PREC[precision] if isinstance(precision, str) else precision, spec.outputs)
+                   PREC[precision] if isinstance(precision, str) else precision, spec.outputs, spec.time_enc,
+                   float(time_range[0]), float(time_range[1]))
 
 
 def tf_struct(tf: I.TF) -> TFStruct:
@@ -167,8 +169,13 @@ class Network:
     per-channel offset and scale), FP32 weights and (host) keyframe times."""
 
     def __init__(self, spec: I.NetSpec, latent, weights, key_times=None, device="cuda",
-                 grid_dtype=F32):
+                 grid_dtype=F32, time_range=None):
+        """time_range (lo, hi): normalisation of the time input of a network
+        with a time encoding (default: the first and last key time)."""
         self.spec = spec
+        if time_range is None:
+            time_range = (key_times[0], key_times[-1]) if (spec.time_enc and key_times is not None) else (0.0, 1.0)
+        self.time_range = (float(time_range[0]), float(time_range[1]))
         lat = torch.as_tensor(latent, dtype=torch.float32).reshape(-1).contiguous().to(device)
         self.dequant = None
         if grid_dtype == F16:
@@ -195,7 +202,7 @@ class Network:
         assert self.latent.numel() == spec.n_latent
 
     def desc(self, precision="f32") -> NetDesc:
-        return net_desc(self.spec, precision, self.grid_dtype)
+        return net_desc(self.spec, precision, self.grid_dtype, self.time_range)
 
     def params(self) -> Params:
         return Params(self.latent.data_ptr(), self.weights.data_ptr(),

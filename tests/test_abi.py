@@ -41,6 +41,10 @@ def test_num_weights_matches_layout():
         assert FV.fvsrn_num_weights(spec) == spec.n_weights
     assert FV.fvsrn_num_weights(I.NET_SMALL) == 3297
     assert FV.fvsrn_num_weights(I.NET_STUDY) == 5377
+    # time inputs widen layer 0 by 1, 8 or 9 columns
+    for te, extra in ((1, 1), (2, 8), (3, 9)):
+        spec_t = I.NetSpec(R=32, F=16, L=8, c=32, H=4, time_enc=te)
+        assert FV.fvsrn_num_weights(spec_t) == spec_t.n_weights == 5377 + 32 * extra
     # four outputs add three output rows and three biases
     spec4 = I.NetSpec(R=32, F=16, L=8, c=32, H=4, outputs=4)
     assert FV.fvsrn_num_weights(spec4) == spec4.n_weights == 5377 + 3 * 33
@@ -102,6 +106,12 @@ def test_render_argument_errors():
     assert _render(_desc(), m=m) == FV.ERR_INVALID_ARGUMENT
     m = FV.march_struct(I.March(step=0.1, grad_mode=5))
     assert _render(_desc(), m=m) == FV.ERR_INVALID_ARGUMENT
+    # time encodings: known values and a proper time range
+    for te in (-1, 4):
+        assert _render(_desc(time_encoding=te)) == FV.ERR_INVALID_ARGUMENT
+    for lo, hi in ((1.0, 1.0), (2.0, 1.0), (0.0, float("nan")), (float("-inf"), 1.0)):
+        assert _render(_desc(time_encoding=1, time_lo=lo, time_hi=hi)) == FV.ERR_INVALID_ARGUMENT
+    assert b"time" in L.fvsrn_last_error()
     # network outputs: 1 or 4; predicted-gradient shading needs 4
     for no in (2, 3, 5, -1):
         assert _render(_desc(num_outputs=no)) == FV.ERR_INVALID_ARGUMENT

@@ -631,3 +631,56 @@ def test_phong_render_adjoint(FV, prec, tol):
         assert err <= tol
         assert abs(stats[0].item() - ns) <= 0.001 * ns
         assert stats[2].item() % 64 == 0
+
+
+# -------------------------------------------- time encodings (Sec. 8)
+
+@pytest.mark.parametrize("te", [1, 2, 3], ids=["direct", "fourier", "both"])
+def test_time_encoding_eval_and_render(FV, te):
+    """Networks with a time input (the normalised time tau directly, its
+    Fourier features, or both) on three keyframe grids: point densities at
+    times below, inside and above the key range (tau clamps), FP32 and FP16
+    networks on FP32, FP16 and uint8 grids, c = 32 and 48; an unshaded
+    two-view render at two times against the oracle."""
+    keys = (0.0, 1.0, 3.0)
+    for base in (I.NetSpec(R=10, F=16, L=8, c=32, H=3, K=3), I.NetSpec(R=10, F=8, L=4, c=48, H=2, K=3)):
+        spec = dataclasses.replace(base, time_enc=te)
+        xyz = I.uniform_points(64 * 3 + 5, te, -0.99, 0.99)
+        for gd in (FV.F32, FV.F16, FV.U8):
+            gnet, onet = _nets(FV, spec, 30 + te, key_times=keys, grid_dtype=gd)
+            for t in (-0.5, 0.4, 2.2, 4.0):
+                ref = O.eval_points(onet, xyz, t)
+                for prec, tol in (("f32", FP32_TOL), ("f16", FP16_TOL)):
+                    d = FV.fvsrn_eval_points(gnet, torch.from_numpy(xyz).cuda(), t, prec).cpu().numpy()
+                    err = np.abs(d - ref).max()
+                    assert err <= tol, (spec.c, gd, t, prec, err)
+        gnet, onet = _nets(FV, spec, 40 + te, key_times=keys)
+        cams = I.orbit_cameras(2, 20, 14)
+        cams = [dataclasses.replace(c, time=t) for c, t in zip(cams, (0.7, 2.6))]
+        m = I.March(step=1 / 64, ert_eps=0.0)
+        ref, ns = O.render(O.Field(net=onet), I.ramp_tf(), cams, m)
+        for prec, tol in (("f32", FP32_TOL), ("f16", FP16_TOL)):
+            img = FV.fvsrn_render(gnet, I.ramp_tf(), cams, m, prec).cpu().numpy()
+            err = np.abs(img - ref).max()
+            _report("time encoding %d c=%d render %s" % (te, spec.c, prec), err)
+            assert err <= tol
+
+
+def test_time_encoding_limits(FV):
+    """Shading, gradients, BF16 and non-sine activations are not compiled for
+    time-encoded networks."""
+    spec = I.NetSpec(R=8, F=8, L=4, c=32, H=2, K=2, time_enc=1)
+    gnet, _ = _nets(FV, spec, 3, key_times=(0.0, 1.0))
+    xyz = torch.from_numpy(I.uniform_points(8, 1)).cuda()
+    cams = I.orbit_cameras(1, 8, 8)
+    for call in (lambda: FV.fvsrn_render(gnet, I.ramp_tf(), cams, I.March(step=0.1, phong=True), "f32"),
+                 lambda: FV.fvsrn_grad_points(gnet, xyz, 0.5, "f32"),
+                 lambda: FV.fvsrn_eval_points(gnet, xyz, 0.5, "bf16")):
+        with pytest.raises(FV.FvsrnError) as e:
+            call()
+        assert e.value.status == FV.ERR_UNSUPPORTED
+    spec = I.NetSpec(R=8, F=8, L=4, c=32, H=2, time_enc=2, act="snakealt")
+    gnet, _ = _nets(FV, spec, 3)
+    with pytest.raises(FV.FvsrnError) as e:
+        FV.fvsrn_eval_points(gnet, xyz, 0.5, "f32")
+    assert e.value.status == FV.ERR_UNSUPPORTED

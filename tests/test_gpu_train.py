@@ -308,3 +308,28 @@ def test_trainer_learns_predicted_gradients(FV):
     print("predicted-gradient training: density L1 %.4f, gradient L1 %.4f -> density %.4f, gradient %.4f" %
           (e0 + e1), flush=True)
     assert e1[0] < 0.5 * e0[0] and e1[1] < 0.7 * e0[1]
+
+
+@pytest.mark.parametrize("te", [1, 2, 3], ids=["direct", "fourier", "both"])
+def test_train_gradients_time_encodings(FV, te):
+    """Training with a time input (Sec. 8): per-point times spanning and
+    exceeding the time range; dW (including layer 0's time columns), the
+    keyframe latent gradients and the loss against the oracle."""
+    spec = I.NetSpec(R=12, F=16, L=8, c=32, H=3, K=3, time_enc=te)
+    keys = (0.0, 2.0, 5.0)
+    n = 64 * 19 + 7
+    lat, w = I.net_params(spec, 50 + te)
+    gnet, onet = FV.Network(spec, lat, w, key_times=keys), O.Net(spec, lat, w, keys)
+    xyz = I.uniform_points(n, 3 + te, -0.99, 0.99)
+    times = np.random.default_rng(te).uniform(-1.0, 6.0, n).astype(np.float32)
+    up = np.random.default_rng(9).normal(size=n).astype(np.float32)
+    dl_ref, dw_ref, loss_ref = O.train_grads(onet, xyz, dloss_dd=up.astype(np.float64), times=times)
+    d_lat = torch.empty_like(gnet.latent)
+    d_w = torch.empty_like(gnet.weights)
+    loss = torch.zeros(1, device="cuda")
+    FV.fvsrn_train_step(gnet, d_lat, d_w, torch.from_numpy(xyz).cuda(), dloss_dy=torch.from_numpy(up).cuda(),
+                        times=torch.from_numpy(times).cuda(), out_loss=loss)
+    e_w, e_l = _rel(d_w.cpu().numpy(), dw_ref), _rel(d_lat.cpu().numpy(), dl_ref)
+    print("train time encoding %d: dW rel err %.3g, dG rel err %.3g" % (te, e_w, e_l), flush=True)
+    assert e_w <= 1e-4 and e_l <= 1e-4
+    assert abs(loss.item() - loss_ref) <= 1e-5 * max(1.0, abs(loss_ref))
