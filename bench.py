@@ -362,6 +362,35 @@ def main():
                 "view_times": [c.time for c in tcams],
                 "training": {"steps": tsteps, "batch": 1 << 18, "timesteps": 16, "final_l1": float(ttr.loss.item()),
                              "ms_per_step": t_train / tsteps * 1e3}}
+            # time encodings (Sec. 8): the same keyframe network with no time
+            # input, the normalised time as an input, its Fourier features, or
+            # both, trained on the even timesteps only and judged on the odd
+            # ones it never saw (mean |density error| over 2^18 points each)
+            enc = {}
+            train_frames = [f for f in frames if int(f[0]) % 2 == 0]
+            held_out = [f for f in frames if int(f[0]) % 2 == 1]
+            xe = FV.fvsrn_sample_points(I.SEED_TIME, 1 << 40, 1 << 18, device=dev)
+            esteps = max(1, args.train_steps // 4)
+            for te, name in ((0, "latent_only"), (1, "direct"), (2, "fourier"), (3, "both")):
+                espec = dataclasses.replace(tspec, time_enc=te)
+                elat, ew = I.net_params(espec, I.SEED_TIME)
+                enet = FV.Network(espec, elat, ew, key_times=I.TIME_KEYS, grid_dtype=FV.F32, device=dev)
+                etr = Trainer(enet, train_frames, batch=1 << 18, seed=I.SEED_TIME)
+                for _ in range(esteps):
+                    etr.step()
+
+                def mean_err(fr):
+                    return float(np.mean([torch.mean(torch.abs(FV.fvsrn_eval_points(enet, xe, t, "f32") -
+                                                               FV.fvsrn_dense_eval_points(v, xe))).item()
+                                          for t, v in fr]))
+                e16 = FV.Network(espec, enet.latent.cpu().numpy(), enet.weights.cpu().numpy(), key_times=I.TIME_KEYS,
+                                 grid_dtype=FV.F16, device=dev)
+                per_c, _ = time_launches(lambda: FV.fvsrn_render(e16, tf, tcams, march, "f16", out=out), 3, 1)
+                enc[name] = {"l1_trained_timesteps": mean_err(train_frames), "l1_unseen_timesteps": mean_err(held_out),
+                             "render_ms_per_frame_f16": float(np.mean(per_c)) / len(tcams)}
+                del etr, enet, e16
+            comp["time_encodings"] = {"train": "even timesteps 0..14, %d steps of 2^18 points" % esteps,
+                                      "judge": "odd timesteps 1..15", **enc}
             del frames, ttr, tnet32
         # fused point evaluation vs the framework-style layer-by-layer network (2^24 points)
         npts = 1 << 24
