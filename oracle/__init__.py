@@ -42,7 +42,7 @@ class _Net(C.Structure):
                 ("latent", C.POINTER(C.c_double)), ("weights", C.POINTER(C.c_double)),
                 ("key_times", C.POINTER(C.c_double)), ("latent_u8", C.POINTER(C.c_uint8)),
                 ("dequant", C.POINTER(C.c_double)), ("time_enc", C.c_int32), ("pad_", C.c_int32),
-                ("time_lo", C.c_double), ("time_hi", C.c_double)]
+                ("time_lo", C.c_double), ("time_hi", C.c_double), ("fourier_matrix", C.POINTER(C.c_double))]
 
 
 class _TF(C.Structure):
@@ -124,11 +124,13 @@ def _f64(a):
 class Net:
     """FP64 view of an fV-SRN: latent grid, packed weights, keyframe times."""
 
-    def __init__(self, spec, latent, weights, key_times=None, codes=None, dequant=None, time_range=None):
+    def __init__(self, spec, latent, weights, key_times=None, codes=None, dequant=None, time_range=None,
+                 fourier_matrix=None):
         """latent: FP values; or codes (uint8 [K][R^3][F]) with dequant
         ([K][F][2] offset, scale) for a uint8 grid (latent may then be None).
         time_range (lo, hi): normalisation of the time input of a network
-        with a time encoding (default: the first and last key time)."""
+        with a time encoding (default: the first and last key time).
+        fourier_matrix: [3L][3] angular frequencies (None: the octaves)."""
         self.spec = spec
         self.weights = _f64(weights).reshape(-1)
         self.key_times = _f64(key_times)
@@ -144,11 +146,13 @@ class Net:
             self.codes = self.dequant = None
             lat_p, cod_p = _dp(self.latent), None
         te = getattr(spec, "time_enc", 0)
+        self.fourier_matrix = None if fourier_matrix is None else _f64(fourier_matrix).reshape(-1)
+        assert self.fourier_matrix is None or self.fourier_matrix.size == 9 * spec.L
         if time_range is None:
             time_range = (key_times[0], key_times[-1]) if (te and key_times is not None) else (0.0, 1.0)
         self._s = _Net(spec.R, spec.F, spec.K, spec.L, spec.c, spec.H, ACT[spec.act], getattr(spec, "outputs", 1),
                        lat_p, _dp(self.weights), _dp(self.key_times), cod_p, _dp(self.dequant), te, 0,
-                       float(time_range[0]), float(time_range[1]))
+                       float(time_range[0]), float(time_range[1]), _dp(self.fourier_matrix))
         self.K0 = lib().orc_input_width(C.byref(self._s))
         self.n_weights = lib().orc_num_weights(C.byref(self._s))
         assert self.weights.size == self.n_weights, (self.weights.size, self.n_weights)

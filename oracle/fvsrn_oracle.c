@@ -143,7 +143,8 @@ int orc_latent(const orc_net* net, const double p[3], double t, double* z, doubl
 /* ----------------------------------------------- network input (Sec. 3) */
 
 /* v0 = p (+) z (+) sin(F p) (+) cos(F p) with the Fourier matrix rows ordered
-   octave-major: row 3k+a has frequency pi*2^k on axis a (Eq. 1, Eq. 2). */
+   octave-major: row 3k+a has frequency pi*2^k on axis a (Eq. 1, Eq. 2), or
+   the rows of a given matrix (random Fourier features). */
 int orc_features(const orc_net* net, const double p[3], double t, double* v0, double* dv) {
   if (!net_ok(net) || !v0) return -1;
   const int F = net->F, L = net->L, K0 = orc_input_width(net);
@@ -161,16 +162,31 @@ int orc_features(const orc_net* net, const double p[3], double t, double* v0, do
     free(dz);
   }
   const int s0 = 3 + F, c0 = 3 + F + 3 * L;
-  for (int k = 0; k < L; ++k)
-    for (int a = 0; a < 3; ++a) {
-      double freq = M_PI * ldexp(1.0, k);
-      v0[s0 + 3 * k + a] = sin(freq * p[a]);
-      v0[c0 + 3 * k + a] = cos(freq * p[a]);
-      if (dv) {
-        dv[(s0 + 3 * k + a) * 3 + a] = freq * cos(freq * p[a]);
-        dv[(c0 + 3 * k + a) * 3 + a] = -freq * sin(freq * p[a]);
-      }
+  if (net->fourier_matrix) {
+    /* a general Fourier matrix: phase_j = F_j . p, d phase_j / d p_a = F_ja */
+    for (int j = 0; j < 3 * L; ++j) {
+      const double* fj = net->fourier_matrix + 3 * j;
+      double ph = fj[0] * p[0] + fj[1] * p[1] + fj[2] * p[2];
+      v0[s0 + j] = sin(ph);
+      v0[c0 + j] = cos(ph);
+      if (dv)
+        for (int a = 0; a < 3; ++a) {
+          dv[(s0 + j) * 3 + a] = fj[a] * cos(ph);
+          dv[(c0 + j) * 3 + a] = -fj[a] * sin(ph);
+        }
     }
+  } else {
+    for (int k = 0; k < L; ++k)
+      for (int a = 0; a < 3; ++a) {
+        double freq = M_PI * ldexp(1.0, k);
+        v0[s0 + 3 * k + a] = sin(freq * p[a]);
+        v0[c0 + 3 * k + a] = cos(freq * p[a]);
+        if (dv) {
+          dv[(s0 + 3 * k + a) * 3 + a] = freq * cos(freq * p[a]);
+          dv[(c0 + 3 * k + a) * 3 + a] = -freq * sin(freq * p[a]);
+        }
+      }
+  }
   /* time inputs (Sec. 8), after the spatial Fourier block; they do not
      depend on p */
   if (net->time_enc != 0) {

@@ -58,6 +58,11 @@ typedef struct {
   int32_t time_enc;
   int32_t pad_;
   double time_lo, time_hi;
+  /* Fourier matrix (Sec. 3): [3L][3] rows of angular frequencies, the sin and
+     cos blocks holding sin / cos(row . p); NULL = the octave construction
+     (row 3k+a = pi 2^k e_a). Random Fourier features draw it from
+     N(0, (2 pi sigma)^2). */
+  const double* fourier_matrix;
 } orc_net;
 
 typedef struct {            /* piecewise-linear transfer function */

@@ -119,6 +119,22 @@ def net_params(spec: NetSpec, seed: int, latent_std: float = 0.1):
     return latent.astype(np.float32), weights.astype(np.float32)
 
 
+def random_fourier_matrix(L: int, sigma: float, seed: int) -> np.ndarray:
+    """[3L][3] Fourier matrix with entries ~ N(0, (2 pi sigma)^2) (random
+    Fourier features, Sec. 3), float32, rows in the sin/cos block order."""
+    rng = np.random.default_rng(seed)
+    return (2.0 * math.pi * sigma * rng.normal(size=(3 * L, 3))).astype(np.float32)
+
+
+def octave_fourier_matrix(L: int, dtype=np.float32) -> np.ndarray:
+    """The octave construction as a matrix: row 3k+a = pi 2^k e_a."""
+    m = np.zeros((3 * L, 3), dtype=dtype)
+    for k in range(L):
+        for a in range(3):
+            m[3 * k + a, a] = math.pi * 2 ** k
+    return m
+
+
 def uniform_points(n: int, seed: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return rng.uniform(lo, hi, size=(n, 3)).astype(np.float32)

@@ -954,3 +954,44 @@ def test_time_encoding_training_gradient_by_central_differences():
         d1, g1 = O.density_grad(net, p, 0.7, mode="fwd")
         d2, g2 = O.density_grad(net, p, 0.7, mode="rev")
         np.testing.assert_allclose(g1, g2, rtol=1e-11, atol=1e-14)
+
+
+# --------------------------------------- random Fourier features (Sec. 3)
+
+def test_fourier_matrix_octaves_reproduce_default_features():
+    """The octave construction written as a matrix gives the default
+    features bit for bit (the same products and sines), and the density."""
+    spec = I.NetSpec(R=5, F=4, L=3, c=8, H=2)
+    lat, w = I.net_params(spec, 4)
+    net0 = O.Net(spec, lat, w)
+    netm = O.Net(spec, lat, w, fourier_matrix=I.octave_fourier_matrix(3, np.float64))
+    for p in RNG.uniform(-1, 1, (6, 3)):
+        v0, dv0 = O.features(net0, p)
+        v1, dv1 = O.features(netm, p)
+        assert np.array_equal(v0, v1) and np.array_equal(dv0, dv1)
+        assert O.density(net0, p) == O.density(netm, p)
+
+
+def test_fourier_matrix_features_closed_form_and_jacobian():
+    """A general matrix: feature j is sin / cos of row j . p; a row along one
+    axis with frequency 2 pi gives sin(2 pi p_a) exactly; the forward, reverse
+    and central-difference gradients agree."""
+    spec = I.NetSpec(R=4, F=2, L=2, c=6, H=2)
+    fm = I.random_fourier_matrix(2, 1.5, 3).astype(np.float64)
+    fm[0] = [0.0, 2 * math.pi, 0.0]
+    net = O.Net(spec, *I.net_params(spec, 5), fourier_matrix=fm)
+    p = np.array([0.3, 0.125, -0.7])
+    v0, dv = O.features(net, p)
+    ph = fm @ p
+    np.testing.assert_allclose(v0[5:11], np.sin(ph), atol=1e-15)
+    np.testing.assert_allclose(v0[11:17], np.cos(ph), atol=1e-15)
+    assert abs(v0[5] - 1.0) < 1e-15                  # sin(2 pi / 8 * 2) = sin(pi / 2)
+    np.testing.assert_allclose(dv[5:11], fm * np.cos(ph)[:, None], atol=1e-15)
+    np.testing.assert_allclose(dv[11:17], -fm * np.sin(ph)[:, None], atol=1e-15)
+    for q in RNG.uniform(-0.9, 0.9, (4, 3)):
+        d1, g1 = O.density_grad(net, q, mode="fwd")
+        d2, g2 = O.density_grad(net, q, mode="rev")
+        np.testing.assert_allclose(g1, g2, rtol=1e-11, atol=1e-14)
+        h = 1e-6
+        fd = [(O.density(net, q + h * e) - O.density(net, q - h * e)) / (2 * h) for e in np.eye(3)]
+        np.testing.assert_allclose(g1, fd, rtol=1e-6, atol=1e-9)
