@@ -980,12 +980,12 @@ def test_fourier_matrix_features_closed_form_and_jacobian():
     fm = I.random_fourier_matrix(2, 1.5, 3).astype(np.float64)
     fm[0] = [0.0, 2 * math.pi, 0.0]
     net = O.Net(spec, *I.net_params(spec, 5), fourier_matrix=fm)
-    p = np.array([0.3, 0.125, -0.7])
+    p = np.array([0.3, 0.25, -0.7])
     v0, dv = O.features(net, p)
     ph = fm @ p
     np.testing.assert_allclose(v0[5:11], np.sin(ph), atol=1e-15)
     np.testing.assert_allclose(v0[11:17], np.cos(ph), atol=1e-15)
-    assert abs(v0[5] - 1.0) < 1e-15                  # sin(2 pi / 8 * 2) = sin(pi / 2)
+    assert abs(v0[5] - 1.0) < 1e-15 and abs(v0[11]) < 1e-15   # sin / cos(2 pi * 0.25)
     np.testing.assert_allclose(dv[5:11], fm * np.cos(ph)[:, None], atol=1e-15)
     np.testing.assert_allclose(dv[11:17], -fm * np.sin(ph)[:, None], atol=1e-15)
     for q in RNG.uniform(-0.9, 0.9, (4, 3)):
