@@ -32,7 +32,7 @@
  *  - Network input v0 = [x, y, z, latent(F), sin-block(3L), cos-block(3L),
  *    time inputs (0, 1, 8 or 9, see fvsrn_time_encoding)]; block entry 3k+a is
  *    sin / cos(pi * 2^k * p_a), k = 0..L-1 (Eq. 1 with the octave frequencies
- *    pi*2^k, Eq. 2's concatenation).
+ *    pi*2^k, Eq. 2's concatenation), unless a Fourier matrix is given.
  *  - Weights (FP32 master copy, the layout the trainer updates): for each
  *    layer i = 0..H, W_i[out][in] row-major, then b_i[out]. Layer 0 maps
  *    K0 = 3 + F + 6L (+ time inputs) inputs to c channels, layers 1..H-1 map c to c, layer H
@@ -87,6 +87,13 @@ typedef struct {
                             appended to layer 0's inputs after the cosine block */
   float time_lo, time_hi; /* time range mapped onto tau in [-1, 1] (times clamped to it);
                             used when time_encoding != FVSRN_TIME_LATENT_ONLY, time_hi > time_lo */
+  const float* fourier_matrix; /* [host] NULL: the octave Fourier features below. Otherwise
+                            [3L][3] rows of angular frequencies (radians per world unit): the
+                            sin and cos blocks hold sin / cos(row_j . p) (Sec. 3; random
+                            Fourier features draw the entries from N(0, (2 pi sigma)^2)).
+                            Read during the call. Built for the sine activation, FP32/FP16
+                            arithmetic, the unshaded render, point densities and training,
+                            without a time encoding. */
 } fvsrn_net_desc;
 
 /* Time encodings (Sec. 8): the latent grids are blended in time in every case;

@@ -1,8 +1,8 @@
 """Builds the gfx950 HIP library ``libfvsrn.so`` in-tree with hipcc.
 
 The network kernels are compiled once per precision (FP32, FP16, BF16) as
-separate translation units (the adjoint-gradient and time-encoded kernels in
-units of their own), in parallel, then linked with the C ABI and the utility kernels into
+separate translation units (the adjoint-gradient, time-encoded and
+Fourier-matrix kernels in units of their own), in parallel, then linked with the C ABI and the utility kernels into
 one shared library.
 """
 from __future__ import annotations
@@ -31,6 +31,8 @@ UNITS = [
     ("fvsrn_adjoint.hip", ["-DFVSRN_PREC=1"], "adj_f16.o"),
     ("fvsrn_time.hip", ["-DFVSRN_PREC=0"], "time_f32.o"),
     ("fvsrn_time.hip", ["-DFVSRN_PREC=1"], "time_f16.o"),
+    ("fvsrn_rff.hip", ["-DFVSRN_PREC=0"], "rff_f32.o"),
+    ("fvsrn_rff.hip", ["-DFVSRN_PREC=1"], "rff_f16.o"),
     ("fvsrn_train.hip", [], "train.o"),
 ]
 

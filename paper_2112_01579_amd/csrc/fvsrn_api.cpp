@@ -66,6 +66,13 @@ fvsrn_status check_desc(const fvsrn_net_desc* d) {
   if (d->time_encoding != FVSRN_TIME_LATENT_ONLY &&
       !(d->time_hi > d->time_lo && d->time_hi - d->time_lo < 3.0e38f && d->time_lo > -3.0e38f))
     return fail(FVSRN_ERR_INVALID_ARGUMENT, "time encodings need finite time_lo < time_hi");
+  if (d->fourier_matrix) {
+    for (int j = 0; j < 9 * d->num_freqs; ++j)
+      if (!(fabsf(d->fourier_matrix[j]) < 1.0e6f))
+        return fail(FVSRN_ERR_INVALID_ARGUMENT, "fourier_matrix entry %d not finite or above 1e6", j);
+    if (d->time_encoding != FVSRN_TIME_LATENT_ONLY)
+      return fail(FVSRN_ERR_UNSUPPORTED, "a Fourier matrix together with a time encoding is not compiled");
+  }
   // the kernels address one keyframe grid with 32-bit byte offsets
   const long long grid_bytes = (long long)d->grid_res * d->grid_res * d->grid_res * d->grid_channels *
                                (d->grid_dtype == FVSRN_U8 ? 1 : (d->grid_dtype == FVSRN_F16 ? 2 : 4));
@@ -113,6 +120,10 @@ NetDev make_net(const fvsrn_net_desc* d, const void* latent, const float* weight
   n.t_hi = d->time_hi;
   n.t_scale = d->time_encoding ? (float)(2.0 / ((double)d->time_hi - d->time_lo)) : 0.0f;
   n.tau = 0.0f;
+  n.fmat = d->fourier_matrix != nullptr;
+  for (int j = 0; j < kMaxFourierRows; ++j)
+    for (int a = 0; a < 3; ++a)
+      n.fm[j][a] = (n.fmat && j < 3 * d->num_freqs) ? (float)(d->fourier_matrix[3 * j + a] / (2.0 * M_PI)) : 0.0f;
   return n;
 }
 

@@ -9,6 +9,7 @@ namespace fvsrn_detail {
 
 constexpr int kMaxViewsPerLaunch = 16;
 constexpr int kMaxKeyframes = 64;
+constexpr int kMaxFourierRows = 24;  // 3L for L <= 8
 
 // Keyframe times for per-point keyframe selection in training.
 struct KeyTimes {
@@ -59,6 +60,8 @@ struct NetDev {
   int time_enc;          // time inputs (Sec. 8): 0 none, 1 direct, 2 Fourier, 3 both
   float t_lo, t_hi, t_scale;  // normalisation of times: tau = (clamp(t) - t_lo) t_scale - 1
   float tau;             // normalised time of a point evaluation
+  int fmat;              // Fourier features from fm (random Fourier features) instead of octaves
+  float fm[kMaxFourierRows][3];  // rows of the Fourier matrix, revolutions per world unit
 };
 
 struct ViewBatch {
@@ -120,6 +123,15 @@ int launch_render_adj_p1(const NetDev&, const TFDev&, const ViewBatch&, const Ma
                          unsigned long long*, void*);
 int launch_points_adj_p0(const NetDev&, const float*, long long, int, float, float*, float*, void*);
 int launch_points_adj_p1(const NetDev&, const float*, long long, int, float, float*, float*, void*);
+
+// Networks with a Fourier matrix (fvsrn_rff.hip, FP32 and FP16 networks,
+// sine activation): unshaded render and point densities.
+int launch_render_rff_p0(const NetDev&, const TFDev&, const ViewBatch&, const MarchDev&, float*,
+                         unsigned long long*, void*);
+int launch_render_rff_p1(const NetDev&, const TFDev&, const ViewBatch&, const MarchDev&, float*,
+                         unsigned long long*, void*);
+int launch_points_rff_p0(const NetDev&, const float*, long long, int, float, float*, void*);
+int launch_points_rff_p1(const NetDev&, const float*, long long, int, float, float*, void*);
 
 // Networks with a time encoding (fvsrn_time.hip, FP32 and FP16 networks,
 // sine activation): unshaded render and point densities.

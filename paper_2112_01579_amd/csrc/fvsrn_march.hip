@@ -62,6 +62,13 @@ struct Entry {
 
 int FV_PASTE(launch_render_p, FVSRN_PREC)(const NetDev& nd, const TFDev& tf, const ViewBatch& vb, const MarchDev& m,
                                           float* out, unsigned long long* stats, void* stream) {
+  if (nd.fmat) {
+#if FVSRN_PREC != 2
+    return FV_PASTE(launch_render_rff_p, FVSRN_PREC)(nd, tf, vb, m, out, stats, stream);
+#else
+    return 1;
+#endif
+  }
   if (nd.time_enc != 0) {
 #if FVSRN_PREC != 2
     return FV_PASTE(launch_render_time_p, FVSRN_PREC)(nd, tf, vb, m, out, stats, stream);
@@ -95,6 +102,14 @@ int FV_PASTE(launch_render_p, FVSRN_PREC)(const NetDev& nd, const TFDev& tf, con
 
 int FV_PASTE(launch_points_p, FVSRN_PREC)(const NetDev& nd, const float* xyz, long long n, int key, float key_w,
                                           float* out_d, float* out_g, int gmode, void* stream) {
+  if (nd.fmat) {
+#if FVSRN_PREC != 2
+    if (out_g) return 1;  // gradients with a Fourier matrix are not compiled
+    return FV_PASTE(launch_points_rff_p, FVSRN_PREC)(nd, xyz, n, key, key_w, out_d, stream);
+#else
+    return 1;
+#endif
+  }
   if (nd.time_enc != 0) {
 #if FVSRN_PREC != 2
     if (out_g) return 1;  // gradients of time-encoded networks are not compiled

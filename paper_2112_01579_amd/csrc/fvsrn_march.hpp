@@ -268,7 +268,7 @@ __global__ __launch_bounds__((max_waves<CF, MODE>() * 64)) void march_kernel(Net
       sx = active ? sx : 0.0f;
       sy = active ? sy : 0.0f;
       sz = active ? sz : 0.0f;
-      write_features<CF, GRAD>(myrow, ls, role, sx, sy, sz, tfe);
+      write_features<CF, GRAD>(myrow, ls, role, sx, sy, sz, tfe, nd.fm);
       wave_lds_sync();
       f4 yo;
       float ga[3] = {0.0f, 0.0f, 0.0f};
@@ -385,7 +385,7 @@ __global__ __launch_bounds__((max_waves<CF, PM>() * 64)) void points_kernel(NetD
       y = xyz[3 * idx + 1];
       z = xyz[3 * idx + 2];
     }
-    write_features<CF, GRAD>(myrow, ls, role, x, y, z, tfe);
+    write_features<CF, GRAD>(myrow, ls, role, x, y, z, tfe, nd.fm);
     wave_lds_sync();
     if constexpr (ADJ) {
       const float o = mlp_tile_adj<CF, HH>(smem, bsm, feat);

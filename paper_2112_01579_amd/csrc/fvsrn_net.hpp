@@ -18,11 +18,14 @@ namespace fvsrn_detail {
 // both accumulated in packed FP16 (one gather path per instantiation keeps
 // the register peak down). G16 says that a packed path is used.
 // TE: time encoding of the input (0 latent only, 1 direct, 2 Fourier, 3 both).
-template <int P_, int C_, int F_, int L_, int ACT_, int GK_ = 0, int TE_ = 0>
+// FM: the Fourier features come from a general matrix (random Fourier
+// features) instead of the octave construction.
+template <int P_, int C_, int F_, int L_, int ACT_, int GK_ = 0, int TE_ = 0, int FM_ = 0>
 struct Cfg {
   static constexpr int P = P_, C = C_, F = F_, L = L_, ACT = ACT_;
   static constexpr int GK = GK_;
   static constexpr int TE = TE_;
+  static constexpr bool FM = FM_ != 0;
   static constexpr bool G16 = GK_ != 0;
   using G = Geo<P, C, F, L, TE>;
   using E = typename G::E;
@@ -493,7 +496,8 @@ __device__ inline float time_tau(float t, float lo, float hi, float scale) {
 // encoding); they do not depend on p, so tangent rows get zeros there.
 template <class CF, bool GRAD>
 __device__ inline void write_features(typename CF::E* row, const LatentSrc& ls, const LaneRole& role, float px,
-                                      float py, float pz, const float* tf = nullptr) {
+                                      float py, float pz, const float* tf = nullptr,
+                                      const float (*fm)[3] = nullptr) {
   using G = typename CF::G;
   using E = typename CF::E;
   constexpr int F = CF::F, L = CF::L;
@@ -525,15 +529,33 @@ __device__ inline void write_features(typename CF::E* row, const LatentSrc& ls, 
   }
   constexpr float cs = CF::P == kF32 ? 1.0f : 2.0f;  // scale of the cosine block
   float sd[3], gd[3];
-  if constexpr (CF::P != kF32) {
+  if constexpr (CF::P != kF32 && !CF::FM) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       sd[a] = sin_rev(0.5f * pp[a]);
       gd[a] = 2.0f * cos_rev(0.5f * pp[a]);
     }
   }
+  if constexpr (CF::FM) {
+    // a general Fourier matrix (rows in revolutions per world unit): phase
+    // r_j = row_j . p, features sin / cs cos(2 pi r_j); tangent along axis a:
+    // 2 pi row_ja cos, -2 pi row_ja sin
 #pragma unroll
-  for (int k = 0; k < L; ++k) {
+    for (int j = 0; j < 3 * L; ++j) {
+      const float r = fmaf(fm[j][0], px, fmaf(fm[j][1], py, fm[j][2] * pz));
+      const float s = sin_rev(r), c = cs * cos_rev(r);
+      if constexpr (GRAD) {
+        const float wm = k2Pi * (ma[0] * fm[j][0] + ma[1] * fm[j][1] + ma[2] * fm[j][2]);
+        v[F + j] = fmaf(c, wm * (1.0f / cs), s * mv);
+        v[F + 3 * L + j] = fmaf(-s, wm * cs, c * mv);
+      } else {
+        v[F + j] = s;
+        v[F + 3 * L + j] = c;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < (CF::FM ? 0 : L); ++k) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       float s, c;  // sin and cs * cos of the octave's phase

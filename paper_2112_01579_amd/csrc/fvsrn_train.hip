@@ -28,9 +28,9 @@ namespace {
 constexpr int kTrainMaxWaves = 2048;  // fixed number of waves (deterministic partition)
 constexpr int kTrainWavesPerBlock = 8;
 
-template <int C, int F, int L, int ACT, int TE = 0>
+template <int C, int F, int L, int ACT, int TE = 0, int FM = 0>
 struct TrainCfg {
-  using CF = Cfg<kF32, C, F, L, ACT, 0, TE>;
+  using CF = Cfg<kF32, C, F, L, ACT, 0, TE, FM>;
   using G = typename CF::G;
   static constexpr int S = 16;                      // points per wave chunk (one N-tile)
   static constexpr int NTC = S / 16;
@@ -95,14 +95,14 @@ __device__ void stage_backward(const NetDev& nd, char* p) {
   }
 }
 
-template <int C, int F, int L, int ACT, int TE>
+template <int C, int F, int L, int ACT, int TE, int FM>
 __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDev nd, KeyTimes kt, const float* xyz,
                                                                             const float* times, long long n,
                                                                             const float* target,
                                                                             const float* target_grad, float gw3,
                                                       const float* dloss, float* d_latent, float* ws, int n_waves,
                                                       float inv_n) {
-  using TC = TrainCfg<C, F, L, ACT, TE>;
+  using TC = TrainCfg<C, F, L, ACT, TE, FM>;
   using CF = typename TC::CF;
   using G = typename TC::G;
   using PR = PrecT<kF32>;
@@ -179,12 +179,12 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
     if (lane < S) {
       if (nd.K == 1) {
         write_features<CF, false>(feat + lane * G::ROW, make_latent_src(nd, 0, 0.0f), value_role(), px, py, pz,
-                                  tfe);
+                                  tfe, nd.fm);
       } else {
         // per-lane keyframes: the buffer loads of the gather then run once
         // per distinct keyframe present in the wave
         write_features<CF, false>(feat + lane * G::ROW, make_latent_src(nd, key, kw), value_role(), px, py, pz,
-                                  tfe);
+                                  tfe, nd.fm);
       }
     }
     wave_lds_sync();
@@ -438,10 +438,10 @@ __global__ void slice_sum_kernel(const float* ws, int n_waves, int sl, float* pa
   partial[(size_t)g * sl + e] = s;
 }
 
-template <int C, int F, int L, int ACT, int TE>
+template <int C, int F, int L, int ACT, int TE, int FM>
 __global__ void gather_kernel(int H, int NO, const float* partial, int n_groups, float* d_weights, float* out_loss,
                               float loss_scale) {
-  using TC = TrainCfg<C, F, L, ACT, TE>;
+  using TC = TrainCfg<C, F, L, ACT, TE, FM>;
   using G = typename TC::G;
   const int K0 = G::K0IN;
   const long long nw = (long long)C * K0 + C + (long long)(H - 1) * (C * C + C) + (long long)NO * (C + 1);
@@ -533,9 +533,9 @@ __global__ void adam_kernel(float* p, const float* g, float* m, float* v, long l
   }
 }
 
-template <int C, int F, int L, int ACT, int TE = 0>
+template <int C, int F, int L, int ACT, int TE = 0, int FM = 0>
 struct TrainEntry {
-  using TC = TrainCfg<C, F, L, ACT, TE>;
+  using TC = TrainCfg<C, F, L, ACT, TE, FM>;
   static int waves_per_block(int H) {
     const int fixed = TC::G::weight_bytes(H) + TC::back_bytes(H);
     int w = (160 * 1024 - fixed) / TC::wave_bytes(H);
@@ -566,7 +566,7 @@ struct TrainEntry {
     const size_t shm = (size_t)TC::block_bytes(H, wpb);
     static bool attr = false;
     if (!attr) {
-      (void)hipFuncSetAttribute((const void*)fwd_bwd_kernel<C, F, L, ACT, TE>,
+      (void)hipFuncSetAttribute((const void*)fwd_bwd_kernel<C, F, L, ACT, TE, FM>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
       attr = true;
     }
@@ -574,7 +574,7 @@ struct TrainEntry {
     nd2.latent = latent;
     nd2.grid_f16 = 0;
     if (n > 0) {
-      hipLaunchKernelGGL((fwd_bwd_kernel<C, F, L, ACT, TE>), dim3((nw + wpb - 1) / wpb), dim3(wpb * 64), shm, st, nd2,
+      hipLaunchKernelGGL((fwd_bwd_kernel<C, F, L, ACT, TE, FM>), dim3((nw + wpb - 1) / wpb), dim3(wpb * 64), shm, st, nd2,
                          kt, xyz, times, n, target, target_grad, grad_weight / 3.0f, dloss, d_latent, (float*)ws, nw,
                          1.0f / (float)n);
       rc = check_launch();
@@ -594,7 +594,7 @@ struct TrainEntry {
     if (rc) return rc;
     const long long nwts = (long long)C * TC::G::K0IN + C + (long long)(H - 1) * (C * C + C) +
                            (long long)nd.NO * (C + 1);
-    hipLaunchKernelGGL((gather_kernel<C, F, L, ACT, TE>), dim3(grid_blocks(nwts + 1, 128, 1024)), dim3(128), 0, st, H,
+    hipLaunchKernelGGL((gather_kernel<C, F, L, ACT, TE, FM>), dim3(grid_blocks(nwts + 1, 128, 1024)), dim3(128), 0, st, H,
                        nd.NO, (const float*)partial, ng, d_weights, out_loss, target && n > 0 ? 1.0f / (float)n : 1.0f);
     return check_launch();
   }
@@ -632,23 +632,24 @@ int launch_train(const NetDev& nd, const KeyTimes& kt, float* latent, float* wei
   NetDev net = nd;
   net.weights = weights;
   int rc = 1;
-#define FV_TRAIN_RUN(C_, F_, L_, ACT_, TE_)                                                                  \
-  rc = TrainEntry<C_, F_, L_, ACT_, TE_>::run(net, kt, latent, d_latent, d_weights, xyz, times, n, target,     \
+#define FV_TRAIN_RUN(C_, F_, L_, ACT_, TE_, FM_)                                                             \
+  rc = TrainEntry<C_, F_, L_, ACT_, TE_, FM_>::run(net, kt, latent, d_latent, d_weights, xyz, times, n, target,     \
                                               target_grad, grad_weight, dloss_dy, out_loss, workspace, st)
 #define X(C_, F_, L_)                                                        \
   if (nd.C == C_ && nd.F == F_ && nd.L == L_) {                              \
-    if (nd.time_enc != 0) {                                                  \
-      /* time encodings are compiled for the sine activation */             \
-      if (nd.act != kSine) rc = 1;                                           \
-      else if (nd.time_enc == 1) FV_TRAIN_RUN(C_, F_, L_, kSine, 1);         \
-      else if (nd.time_enc == 2) FV_TRAIN_RUN(C_, F_, L_, kSine, 2);         \
-      else FV_TRAIN_RUN(C_, F_, L_, kSine, 3);                               \
+    if (nd.time_enc != 0 || nd.fmat) {                                       \
+      /* time encodings and Fourier matrices: sine activation, one at a time */ \
+      if (nd.act != kSine || (nd.time_enc != 0 && nd.fmat)) rc = 1;          \
+      else if (nd.fmat) FV_TRAIN_RUN(C_, F_, L_, kSine, 0, 1);               \
+      else if (nd.time_enc == 1) FV_TRAIN_RUN(C_, F_, L_, kSine, 1, 0);      \
+      else if (nd.time_enc == 2) FV_TRAIN_RUN(C_, F_, L_, kSine, 2, 0);      \
+      else FV_TRAIN_RUN(C_, F_, L_, kSine, 3, 0);                            \
     } else if (nd.act == kSine) {                                            \
-      FV_TRAIN_RUN(C_, F_, L_, kSine, 0);                                    \
+      FV_TRAIN_RUN(C_, F_, L_, kSine, 0, 0);                                 \
     } else if (nd.act == kSnakeAlt) {                                        \
-      FV_TRAIN_RUN(C_, F_, L_, kSnakeAlt, 0);                                \
+      FV_TRAIN_RUN(C_, F_, L_, kSnakeAlt, 0, 0);                             \
     } else {                                                                 \
-      FV_TRAIN_RUN(C_, F_, L_, kIdentity, 0);                                \
+      FV_TRAIN_RUN(C_, F_, L_, kIdentity, 0, 0);                             \
     }                                                                        \
   }
   FV_TRAIN_CASES(X)

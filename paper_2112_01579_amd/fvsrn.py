@@ -11,6 +11,7 @@ import math
 import os
 from typing import Optional, Sequence
 
+import numpy as np
 import torch
 
 from . import inputs as I
@@ -43,7 +44,7 @@ class NetDesc(C.Structure):
                 ("num_keyframes", C.c_int32), ("num_freqs", C.c_int32), ("hidden_width", C.c_int32),
                 ("hidden_layers", C.c_int32), ("activation", C.c_int32), ("precision", C.c_int32),
                 ("num_outputs", C.c_int32), ("time_encoding", C.c_int32), ("time_lo", C.c_float),
-                ("time_hi", C.c_float)]
+                ("time_hi", C.c_float), ("fourier_matrix", C.POINTER(C.c_float))]
 
 
 class Params(C.Structure):
@@ -131,10 +132,12 @@ def _stream(stream=None):
 
 # ----------------------------------------------------------- structs
 
-def net_desc(spec: I.NetSpec, precision="f32", grid_dtype=F32, time_range=(0.0, 1.0)) -> NetDesc:
+def net_desc(spec: I.NetSpec, precision="f32", grid_dtype=F32, time_range=(0.0, 1.0), fourier=None) -> NetDesc:
+    """fourier: a ctypes float array [3L*3] (the Fourier matrix) or None."""
     return NetDesc(spec.R, spec.F, grid_dtype, spec.K, spec.L, spec.c, spec.H, ACT[spec.act],
                    PREC[precision] if isinstance(precision, str) else precision, spec.outputs, spec.time_enc,
-                   float(time_range[0]), float(time_range[1]))
+                   float(time_range[0]), float(time_range[1]),
+                   C.cast(fourier, C.POINTER(C.c_float)) if fourier is not None else None)
 
 
 def tf_struct(tf: I.TF) -> TFStruct:
@@ -169,10 +172,17 @@ class Network:
     per-channel offset and scale), FP32 weights and (host) keyframe times."""
 
     def __init__(self, spec: I.NetSpec, latent, weights, key_times=None, device="cuda",
-                 grid_dtype=F32, time_range=None):
+                 grid_dtype=F32, time_range=None, fourier_matrix=None):
         """time_range (lo, hi): normalisation of the time input of a network
-        with a time encoding (default: the first and last key time)."""
+        with a time encoding (default: the first and last key time).
+        fourier_matrix: [3L][3] angular frequencies (random Fourier features);
+        None keeps the octave construction."""
         self.spec = spec
+        self._fm = None
+        if fourier_matrix is not None:
+            fm = np.asarray(fourier_matrix, dtype=np.float32).reshape(-1)
+            assert fm.size == 9 * spec.L
+            self._fm = (C.c_float * fm.size)(*fm.tolist())
         if time_range is None:
             time_range = (key_times[0], key_times[-1]) if (spec.time_enc and key_times is not None) else (0.0, 1.0)
         self.time_range = (float(time_range[0]), float(time_range[1]))
@@ -202,7 +212,7 @@ class Network:
         assert self.latent.numel() == spec.n_latent
 
     def desc(self, precision="f32") -> NetDesc:
-        return net_desc(self.spec, precision, self.grid_dtype, self.time_range)
+        return net_desc(self.spec, precision, self.grid_dtype, self.time_range, self._fm)
 
     def params(self) -> Params:
         return Params(self.latent.data_ptr(), self.weights.data_ptr(),

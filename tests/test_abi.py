@@ -112,6 +112,14 @@ def test_render_argument_errors():
     for lo, hi in ((1.0, 1.0), (2.0, 1.0), (0.0, float("nan")), (float("-inf"), 1.0)):
         assert _render(_desc(time_encoding=1, time_lo=lo, time_hi=hi)) == FV.ERR_INVALID_ARGUMENT
     assert b"time" in L.fvsrn_last_error()
+    # a Fourier matrix: finite entries, no time encoding alongside
+    fm = (C.c_float * 36)(*([1.0] * 35 + [float("inf")]))   # 3L x 3 entries for L = 4
+    d = _desc()
+    d.fourier_matrix = C.cast(fm, C.POINTER(C.c_float))
+    assert _render(d) == FV.ERR_INVALID_ARGUMENT
+    fm[35] = 2.0
+    d.time_encoding, d.time_lo, d.time_hi = 1, 0.0, 1.0
+    assert _render(d) == FV.ERR_UNSUPPORTED
     # network outputs: 1 or 4; predicted-gradient shading needs 4
     for no in (2, 3, 5, -1):
         assert _render(_desc(num_outputs=no)) == FV.ERR_INVALID_ARGUMENT

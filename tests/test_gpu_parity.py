@@ -684,3 +684,43 @@ def test_time_encoding_limits(FV):
     with pytest.raises(FV.FvsrnError) as e:
         FV.fvsrn_eval_points(gnet, xyz, 0.5, "f32")
     assert e.value.status == FV.ERR_UNSUPPORTED
+
+
+# ------------------------------------ random Fourier features (Sec. 3)
+
+@pytest.mark.parametrize("spec", [I.NetSpec(R=12, F=16, L=8, c=32, H=3), I.NetSpec(R=12, F=8, L=4, c=48, H=2, K=2)],
+                         ids=["c32", "c48_keyframes"])
+def test_fourier_matrix_eval_and_render(FV, spec):
+    """Random Fourier features (entries ~ N(0, (2 pi sigma)^2)) in place of
+    the octaves: point densities at FP32 and FP16 on FP32, FP16 and uint8
+    grids, and an unshaded render, against the oracle; the octave matrix
+    itself reproduces the default network's output."""
+    kt = (0.0, 1.0) if spec.K > 1 else None
+    fm = I.random_fourier_matrix(spec.L, 1.0, 5)
+    xyz = I.uniform_points(64 * 4 + 9, 8, -0.999, 0.999)
+    lat, w = I.net_params(spec, 17)
+    for gd in (FV.F32, FV.F16, FV.U8):
+        gnet = FV.Network(spec, lat, w, key_times=kt, grid_dtype=gd, fourier_matrix=fm)
+        _, onet0 = _nets(FV, spec, 17, key_times=kt, grid_dtype=gd)
+        onet = O.Net(spec, onet0.latent.reshape(-1) if onet0.latent is not None else None, w, kt,
+                     codes=onet0.codes, dequant=onet0.dequant, fourier_matrix=fm.astype(np.float64))
+        ref = O.eval_points(onet, xyz, 0.4)
+        for prec, tol in (("f32", FP32_TOL), ("f16", FP16_TOL)):
+            d = FV.fvsrn_eval_points(gnet, torch.from_numpy(xyz).cuda(), 0.4, prec).cpu().numpy()
+            err = np.abs(d - ref).max()
+            _report("fourier matrix c=%d grid %d %s" % (spec.c, gd, prec), err)
+            assert err <= tol
+    gnet = FV.Network(spec, lat, w, key_times=kt, fourier_matrix=fm)
+    onet = O.Net(spec, lat, w, kt, fourier_matrix=fm.astype(np.float64))
+    cams = I.orbit_cameras(2, 19, 13)
+    m = I.March(step=1 / 64, ert_eps=0.0)
+    ref, _ = O.render(O.Field(net=onet), I.ramp_tf(), cams, m)
+    for prec, tol in (("f32", FP32_TOL), ("f16", FP16_TOL)):
+        img = FV.fvsrn_render(gnet, I.ramp_tf(), cams, m, prec).cpu().numpy()
+        assert np.abs(img - ref).max() <= tol
+    # the octave construction as a matrix gives the default network's densities
+    octv = FV.Network(spec, lat, w, key_times=kt, fourier_matrix=I.octave_fourier_matrix(spec.L))
+    dflt = FV.Network(spec, lat, w, key_times=kt)
+    a = FV.fvsrn_eval_points(octv, torch.from_numpy(xyz).cuda(), 0.4, "f32")
+    b = FV.fvsrn_eval_points(dflt, torch.from_numpy(xyz).cuda(), 0.4, "f32")
+    assert torch.max(torch.abs(a - b)).item() <= 1e-5

@@ -333,3 +333,26 @@ def test_train_gradients_time_encodings(FV, te):
     print("train time encoding %d: dW rel err %.3g, dG rel err %.3g" % (te, e_w, e_l), flush=True)
     assert e_w <= 1e-4 and e_l <= 1e-4
     assert abs(loss.item() - loss_ref) <= 1e-5 * max(1.0, abs(loss_ref))
+
+
+def test_train_gradients_fourier_matrix(FV):
+    """Training with random Fourier features: dW, latent gradient and loss
+    against the oracle with the same matrix."""
+    spec = I.NetSpec(R=12, F=16, L=8, c=48, H=3)
+    n = 64 * 17 + 3
+    lat, w = I.net_params(spec, 71)
+    fm = I.random_fourier_matrix(spec.L, 0.8, 2)
+    gnet = FV.Network(spec, lat, w, fourier_matrix=fm)
+    onet = O.Net(spec, lat, w, fourier_matrix=fm.astype(np.float64))
+    xyz = I.uniform_points(n, 13, -0.99, 0.99)
+    up = np.random.default_rng(3).normal(size=n).astype(np.float32)
+    dl_ref, dw_ref, loss_ref = O.train_grads(onet, xyz, dloss_dd=up.astype(np.float64))
+    d_lat = torch.empty_like(gnet.latent)
+    d_w = torch.empty_like(gnet.weights)
+    loss = torch.zeros(1, device="cuda")
+    FV.fvsrn_train_step(gnet, d_lat, d_w, torch.from_numpy(xyz).cuda(), dloss_dy=torch.from_numpy(up).cuda(),
+                        out_loss=loss)
+    e_w, e_l = _rel(d_w.cpu().numpy(), dw_ref), _rel(d_lat.cpu().numpy(), dl_ref)
+    print("train fourier matrix: dW rel err %.3g, dG rel err %.3g" % (e_w, e_l), flush=True)
+    assert e_w <= 1e-4 and e_l <= 1e-4
+    assert abs(loss.item() - loss_ref) <= 1e-5 * max(1.0, abs(loss_ref))
