@@ -35,6 +35,11 @@ HBM_GBS = 8000.0
 PRED_GRAD_WEIGHT = 0.1
 
 
+def progress(msg: str):
+    """One line per bench section on stderr (the JSON result goes to stdout)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
 def flops_per_sample(spec) -> int:
     """Algorithmic multiply-adds x 2 of one network evaluation (unpadded K,
     biases excluded): 2 (K0 c + (H-1) c^2 + c)."""
@@ -65,7 +70,8 @@ def kernel_source_hash() -> str:
     """sha256 of the sources the render kernel is compiled from."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("fvsrn_common.hpp", "fvsrn_net.hpp", "fvsrn_march.hip", "fvsrn_launch.h"):
+    for f in ("fvsrn_common.hpp", "fvsrn_net.hpp", "fvsrn_adjoint.hpp", "fvsrn_march.hpp", "fvsrn_march.hip",
+              "fvsrn_launch.h"):
         with open(os.path.join(ROOT, "paper_2112_01579_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -156,6 +162,7 @@ def main():
     lat, w = I.net_params(spec, I.SEED_STUDY)
     train_info = None
     if args.train_steps > 0:
+        progress("training the study network")
         # fit the network to the dense volume with the library's own trainer
         from paper_2112_01579_amd.trainer import Trainer
         tnet = FV.Network(spec, lat, w, grid_dtype=FV.F32, device=dev)
@@ -187,6 +194,7 @@ def main():
     torch.cuda.synchronize()
     samples, rays, slots = int(stats[0].item()), int(stats[1].item()), int(stats[2].item())
 
+    progress("timing the study render")
     per, wall = time_launches(step, args.steps, args.warmup)
     ms_launch = float(np.mean(per))
     ms_step = wall / args.steps
@@ -232,6 +240,7 @@ def main():
         },
     }
 
+    progress("comparisons")
     if not args.no_compare:
         comp = {}
         # dense-grid DVR of the original 256^3 volume: the judge of image quality
@@ -270,6 +279,7 @@ def main():
             comp[name] = {"ms_per_frame": ms / len(cams), "samples_per_s": s / (ms * 1e-3),
                           "tflops": s * fps / (ms * 1e-3) / 1e12, "image_rmse_vs_dense": e,
                           "image_ssim_vs_dense": q}
+        progress("shading strategies")
         # gradient strategies for Phong shading (Sec. 6): no shading, forward
         # mode, central differences with a one-voxel step of the 256^3 volume;
         # image error against dense DVR shaded with one-voxel central differences
@@ -321,6 +331,7 @@ def main():
                 shade[k + "_over_predicted"] = shade[k]["ms_per_frame"] / shade["predicted"]["ms_per_frame"]
             del ptr, p32, pnet
         comp["shading_f16"] = shade
+        progress("time-varying workload")
         # time-varying workload (Sec. 8): keyframe latent grids every 4 timesteps
         # trained on all 16 timesteps of the 256^3 advected-blob field, then 8
         # views at fractional times in one launch; judged against dense DVR of
@@ -392,6 +403,32 @@ def main():
             comp["time_encodings"] = {"train": "even timesteps 0..14, %d steps of 2^18 points" % esteps,
                                       "judge": "odd timesteps 1..15", **enc}
             del frames, ttr, tnet32
+        progress("Fourier features")
+        # Fourier features (Sec. 3, Sec. 5.3): the octave construction against
+        # random Fourier features (entries ~ N(0, (2 pi sigma)^2)), the study
+        # network trained the same number of steps on the 256^3 volume; mean
+        # |density error| over 2^18 random points and the FP16 render time
+        if args.train_steps > 0:
+            from paper_2112_01579_amd.trainer import Trainer
+            ff = {}
+            fsteps = max(1, args.train_steps // 4)
+            xf = FV.fvsrn_sample_points(I.SEED_STUDY, 1 << 41, 1 << 18, device=dev)
+            dref = FV.fvsrn_dense_eval_points(vol, xf)
+            for name, sigma in (("octaves", None), ("random_sigma_2", 2.0), ("random_sigma_8", 8.0)):
+                fmx = None if sigma is None else I.random_fourier_matrix(spec.L, sigma, I.SEED_STUDY)
+                flat, fw = I.net_params(spec, I.SEED_STUDY)
+                fnet = FV.Network(spec, flat, fw, grid_dtype=FV.F32, device=dev, fourier_matrix=fmx)
+                ftr = Trainer(fnet, vol, batch=1 << 18, seed=I.SEED_TRAIN)
+                for _ in range(fsteps):
+                    ftr.step()
+                l1 = torch.mean(torch.abs(FV.fvsrn_eval_points(fnet, xf, 0.0, "f32") - dref)).item()
+                f16 = FV.Network(spec, fnet.latent.cpu().numpy(), fnet.weights.cpu().numpy(), grid_dtype=FV.F16,
+                                 device=dev, fourier_matrix=fmx)
+                per_c, _ = time_launches(lambda: FV.fvsrn_render(f16, tf, cams, march, "f16", out=out), 3, 1)
+                ff[name] = {"l1": l1, "render_ms_per_frame_f16": float(np.mean(per_c)) / len(cams)}
+                del ftr, fnet, f16
+            comp["fourier_features"] = {"train": "%d steps of 2^18 points on the 256^3 volume" % fsteps, **ff}
+        progress("point evaluation")
         # fused point evaluation vs the framework-style layer-by-layer network (2^24 points)
         npts = 1 << 24
         xyz = torch.rand((npts, 3), device=dev) * 2 - 1
@@ -414,6 +451,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         result["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
+    progress("CPU oracle baseline")
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(spec, lat.astype(np.float16), w, tf, cams, march)
     print(json.dumps(result))
