@@ -106,6 +106,10 @@ def lib():
             "orc_ssim": (D, [P, P, C.c_int, C.c_int, P]),
             "orc_quantize_grid": (C.c_int, [C.POINTER(C.c_float), I64, I32, C.POINTER(C.c_uint8),
                                             C.POINTER(C.c_float)]),
+            "orc_voxel_points": (C.c_int, [I32, I32, C.POINTER(C.c_uint32), C.POINTER(C.c_float)]),
+            "orc_error_grid": (C.c_int, [NP, P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_float), I64, I32, D, P]),
+            "orc_weighted_points": (C.c_int, [C.POINTER(C.c_float), I32, I64, C.POINTER(C.c_uint32),
+                                              C.POINTER(C.c_float)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(_lib, name)
@@ -353,6 +357,45 @@ def ssim(a, b, with_map=False):
     v = lib().orc_ssim(_dp(a), _dp(b), H, W, _dp(m))
     assert v != -1.0
     return (v, m) if with_map else v
+
+
+def _u32p(a):
+    return a.ctypes.data_as(C.POINTER(C.c_uint32))
+
+
+def _f32p(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def voxel_points(G, per_voxel, r):
+    """Positions of per_voxel points in each voxel of a G^3 grid (Sec. 5.4's
+    error grid) from random words r [G^3 per_voxel][3] (uint32)."""
+    r = np.ascontiguousarray(r, dtype=np.uint32).reshape(-1, 3)
+    assert r.shape[0] == G ** 3 * per_voxel
+    xyz = np.empty((r.shape[0], 3), dtype=np.float32)
+    assert lib().orc_voxel_points(G, per_voxel, _u32p(r), _f32p(xyz)) == 0
+    return xyz
+
+
+def error_grid(net, vol, xyz, per_voxel, t=0.0):
+    """Mean |density - trilinear target| per voxel over its per_voxel points."""
+    v = _f64(vol)
+    nz, ny, nx = v.shape
+    xyz = np.ascontiguousarray(xyz, dtype=np.float32).reshape(-1, 3)
+    nvox = xyz.shape[0] // per_voxel
+    E = np.empty(nvox)
+    assert lib().orc_error_grid(net.ref(), _dp(v), nx, ny, nz, _f32p(xyz), nvox, per_voxel, t, _dp(E)) == 0
+    return E
+
+
+def weighted_points(E, G, r):
+    """n training positions drawn in proportion to the error grid E [G^3]
+    (FP32) from random words r [n][4] (uint32)."""
+    E = np.ascontiguousarray(E, dtype=np.float32).reshape(-1)
+    r = np.ascontiguousarray(r, dtype=np.uint32).reshape(-1, 4)
+    xyz = np.empty((r.shape[0], 3), dtype=np.float32)
+    assert lib().orc_weighted_points(_f32p(E), G, r.shape[0], _u32p(r), _f32p(xyz)) == 0
+    return xyz
 
 
 def quantize_grid(grid, F):

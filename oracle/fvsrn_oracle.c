@@ -856,3 +856,69 @@ int orc_adam(double* param, const double* grad, double* m, double* v, int64_t n,
   }
   return 0;
 }
+
+/* --------------------------------------- adaptive resampling (Sec. 5.4) */
+
+/* Position inside voxel (ix, iy, iz) of a G^3 grid over [-1,1]^3 from three
+   32-bit random words, in FP32 as stated in the header. */
+static void voxel_position(int32_t G, int64_t v, const uint32_t* r3, float* p) {
+  const int64_t ix = v % G, iy = (v / G) % G, iz = v / ((int64_t)G * G);
+  const int64_t idx[3] = {ix, iy, iz};
+  const float step = 2.0f / (float)G;
+  for (int a = 0; a < 3; ++a) {
+    const float u = (float)(r3[a] >> 8) * 5.9604644775390625e-8f; /* 2^-24 */
+    p[a] = fmaf((float)idx[a] + u, step, -1.0f);
+  }
+}
+
+int orc_voxel_points(int32_t G, int32_t per_voxel, const uint32_t* r, float* xyz) {
+  if (G < 1 || per_voxel < 1 || !r || !xyz) return -1;
+  const int64_t n = (int64_t)G * G * G * per_voxel;
+  for (int64_t j = 0; j < n; ++j) voxel_position(G, j / per_voxel, r + 3 * j, xyz + 3 * j);
+  return 0;
+}
+
+int orc_error_grid(const orc_net* net, const double* vol, int nx, int ny, int nz, const float* xyz,
+                   int64_t n_voxels, int32_t per_voxel, double t, double* E) {
+  if (!net_ok(net) || !vol || !xyz || !E || n_voxels < 0 || per_voxel < 1) return -1;
+#pragma omp parallel for schedule(static)
+  for (int64_t v = 0; v < n_voxels; ++v) {
+    double s = 0.0;
+    for (int j = 0; j < per_voxel; ++j) {
+      const float* q = xyz + 3 * (v * per_voxel + j);
+      const double p[3] = {q[0], q[1], q[2]};
+      s += fabs(orc_density(net, p, t) - orc_dense_sample(vol, nx, ny, nz, p));
+    }
+    E[v] = s / (double)per_voxel;
+  }
+  return 0;
+}
+
+int orc_weighted_points(const float* E, int32_t G, int64_t n, const uint32_t* r, float* xyz) {
+  if (!E || G < 1 || n < 0 || (n > 0 && (!r || !xyz))) return -1;
+  const int64_t nv = (int64_t)G * G * G;
+  float emax = 0.0f;
+  for (int64_t v = 0; v < nv; ++v) {
+    if (!(E[v] >= 0.0f)) return -1;
+    if (E[v] > emax) emax = E[v];
+  }
+  if (!(emax > 0.0f)) return -1;
+  const float scale = 16777216.0f / emax;
+  uint64_t* Q = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)nv);
+  uint64_t total = 0;
+  for (int64_t v = 0; v < nv; ++v) {
+    total += (uint64_t)floorf(E[v] * scale);
+    Q[v] = total;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    const uint64_t target = (uint64_t)(((unsigned __int128)r[4 * i] * total) >> 32);
+    int64_t lo = 0, hi = nv - 1; /* first v with Q[v] > target */
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) / 2;
+      if (Q[mid] > target) hi = mid; else lo = mid + 1;
+    }
+    voxel_position(G, lo, r + 4 * i + 1, xyz + 3 * i);
+  }
+  free(Q);
+  return 0;
+}

@@ -170,6 +170,23 @@ int orc_render(const orc_field* field, const orc_tf* tf, const orc_camera* cams,
    returns the mean of the map (or -1 on an argument error). */
 double orc_ssim(const double* a, const double* b, int H, int W, double* map);
 
+/* Adaptive resampling of the training positions (Sec. 5.4): an error grid E
+   over G^3 voxels [-1,1]^3 (x fastest), per_voxel positions per voxel, and
+   training positions drawn in proportion to E. Random bits are inputs: r
+   holds the 32-bit outputs of a counter-based generator per point.
+   orc_voxel_points: point j = v * per_voxel + s lies in voxel v at
+     p_a = fma((float)i_a + u_a, 2/G, -1), u_a = (r[j][a] >> 8) 2^-24, in FP32.
+   orc_error_grid: E[v] = mean over the voxel's per_voxel points of
+     |density(p, t) - trilinear(vol, p)|.
+   orc_weighted_points: integer weights q_v = floor(E_v * (2^24 / max E)) in
+     FP32, total = sum q; point i takes the voxel v with
+     Q_{v-1} <= (r[i][0] * total) >> 32 < Q_v (Q the inclusive prefix sums) and
+     the position as in orc_voxel_points from r[i][1..3]. E >= 0, max E > 0. */
+int orc_voxel_points(int32_t G, int32_t per_voxel, const uint32_t* r, float* xyz);
+int orc_error_grid(const orc_net* net, const double* vol, int nx, int ny, int nz, const float* xyz,
+                   int64_t n_voxels, int32_t per_voxel, double t, double* E);
+int orc_weighted_points(const float* E, int32_t G, int64_t n, const uint32_t* r, float* xyz);
+
 /* Training (Sec. 3 world-space fitting; Sec. 8 for keyframe grids; Sec. 6
    for gradient-predicting networks). Gradients of
      L1 mode  (target != NULL): loss = mean_i |d(x_i, t_i) - target_i|

@@ -995,3 +995,67 @@ def test_fourier_matrix_features_closed_form_and_jacobian():
         h = 1e-6
         fd = [(O.density(net, q + h * e) - O.density(net, q - h * e)) / (2 * h) for e in np.eye(3)]
         np.testing.assert_allclose(g1, fd, rtol=1e-6, atol=1e-9)
+
+
+# --------------------------------------- adaptive resampling (Sec. 5.4)
+
+def test_voxel_points_stay_in_their_voxels():
+    """Point j of the error grid lies in (the closed) voxel j // per_voxel (x
+    fastest); random word 0 gives the voxel's lower corner exactly, the
+    largest word ends within FP32 rounding of the next corner."""
+    G, spp = 4, 3
+    rng = np.random.default_rng(1)
+    r = rng.integers(0, 2 ** 32, size=(G ** 3 * spp, 3), dtype=np.uint64).astype(np.uint32)
+    r[0] = 0
+    r[1] = 0xFFFFFFFF
+    xyz = O.voxel_points(G, spp, r)
+    v = np.arange(G ** 3 * spp) // spp
+    idx = np.stack([v % G, (v // G) % G, v // G ** 2], 1)
+    lo = -1 + 2 * idx / G
+    assert np.all(xyz >= lo) and np.all(xyz <= lo + 2 / G)
+    np.testing.assert_array_equal(xyz[0], [-1, -1, -1])
+    assert np.all(xyz[1] > -1 + 2 / G - 1e-6) and np.all(xyz[1] <= -1 + 2 / G)
+
+
+def test_error_grid_is_the_mean_abs_error_per_voxel():
+    spec = I.NetSpec(R=4, F=2, L=1, c=6, H=2)
+    net = make_net(spec, seed=6)
+    vol = RNG.uniform(0, 1, (5, 6, 7))
+    G, spp = 2, 4
+    r = np.random.default_rng(2).integers(0, 2 ** 32, size=(G ** 3 * spp, 3), dtype=np.uint64).astype(np.uint32)
+    xyz = O.voxel_points(G, spp, r)
+    E = O.error_grid(net, vol, xyz, spp)
+    want = [np.mean([abs(O.density(net, p.astype(np.float64)) - O.dense_sample(vol, p.astype(np.float64)))
+                     for p in xyz[v * spp:(v + 1) * spp]]) for v in range(G ** 3)]
+    np.testing.assert_allclose(E, want, rtol=1e-14, atol=1e-15)
+
+
+def test_weighted_points_follow_the_error_grid():
+    """One non-zero voxel takes every point; weights 1 : 3 split the points
+    1 : 3 (within 5 standard deviations); the inverse CDF's boundaries fall
+    where the integer prefix sums put them."""
+    G = 2
+    rng = np.random.default_rng(4)
+    n = 20000
+    r = rng.integers(0, 2 ** 32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    E = np.zeros(8, np.float32)
+    E[5] = 0.25
+    xyz = O.weighted_points(E, G, r)
+    assert np.all(xyz[:, 0] >= 0) and np.all(xyz[:, 1] < 0) and np.all(xyz[:, 2] >= 0)   # voxel (1, 0, 1)
+    E = np.zeros(8, np.float32)
+    E[2], E[7] = 0.1, 0.3
+    xyz = O.weighted_points(E, G, r)
+    in7 = np.all(xyz >= 0, axis=1)
+    in2 = (xyz[:, 0] < 0) & (xyz[:, 1] >= 0) & (xyz[:, 2] < 0)
+    assert np.all(in7 | in2)
+    frac = in2.mean()
+    assert abs(frac - 0.25) < 5 * math.sqrt(0.25 * 0.75 / n)
+    # integer weights: q2 = floor(0.1 * 2^24 / 0.3) (FP32), q7 = 2^24; the word
+    # r0 picks voxel 2 while (r0 * total) >> 32 < q2
+    q2 = int(np.floor(np.float32(0.1) * np.float32(np.float32(2 ** 24) / np.float32(0.3))))
+    total = q2 + 2 ** 24
+    r0_last2 = ((q2 << 32) - 1) // total          # largest word with target < q2
+    rr = np.array([[r0_last2, 0, 0, 0], [r0_last2 + 1, 0, 0, 0]], np.uint32)
+    p = O.weighted_points(E, G, rr)
+    np.testing.assert_array_equal(p[0], [-1, 0, -1])
+    np.testing.assert_array_equal(p[1], [0, 0, 0])
