@@ -897,27 +897,32 @@ int orc_error_grid(const orc_net* net, const double* vol, int nx, int ny, int nz
 int orc_weighted_points(const float* E, int32_t G, int64_t n, const uint32_t* r, float* xyz) {
   if (!E || G < 1 || n < 0 || (n > 0 && (!r || !xyz))) return -1;
   const int64_t nv = (int64_t)G * G * G;
+  /* weights: E where E >= 0, else 0 */
   float emax = 0.0f;
-  for (int64_t v = 0; v < nv; ++v) {
-    if (!(E[v] >= 0.0f)) return -1;
-    if (E[v] > emax) emax = E[v];
-  }
-  if (!(emax > 0.0f)) return -1;
-  const float scale = 16777216.0f / emax;
+  for (int64_t v = 0; v < nv; ++v)
+    if (E[v] >= 0.0f && E[v] > emax) emax = E[v];
+  const float scale = emax > 0.0f ? 16777216.0f / emax : 0.0f;
   uint64_t* Q = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)nv);
   uint64_t total = 0;
   for (int64_t v = 0; v < nv; ++v) {
-    total += (uint64_t)floorf(E[v] * scale);
+    if (E[v] >= 0.0f) total += (uint64_t)floorf(E[v] * scale);
     Q[v] = total;
   }
   for (int64_t i = 0; i < n; ++i) {
-    const uint64_t target = (uint64_t)(((unsigned __int128)r[4 * i] * total) >> 32);
-    int64_t lo = 0, hi = nv - 1; /* first v with Q[v] > target */
-    while (lo < hi) {
-      const int64_t mid = (lo + hi) / 2;
-      if (Q[mid] > target) hi = mid; else lo = mid + 1;
+    int64_t v;
+    if (total == 0) {
+      /* no weight anywhere: every voxel equally likely */
+      v = (int64_t)(((uint64_t)r[4 * i] * (uint64_t)nv) >> 32);
+    } else {
+      const uint64_t target = (uint64_t)(((unsigned __int128)r[4 * i] * total) >> 32);
+      int64_t lo = 0, hi = nv - 1; /* first v with Q[v] > target */
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if (Q[mid] > target) hi = mid; else lo = mid + 1;
+      }
+      v = lo;
     }
-    voxel_position(G, lo, r + 4 * i + 1, xyz + 3 * i);
+    voxel_position(G, v, r + 4 * i + 1, xyz + 3 * i);
   }
   free(Q);
   return 0;

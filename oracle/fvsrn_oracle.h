@@ -181,7 +181,8 @@ double orc_ssim(const double* a, const double* b, int H, int W, double* map);
    orc_weighted_points: integer weights q_v = floor(E_v * (2^24 / max E)) in
      FP32, total = sum q; point i takes the voxel v with
      Q_{v-1} <= (r[i][0] * total) >> 32 < Q_v (Q the inclusive prefix sums) and
-     the position as in orc_voxel_points from r[i][1..3]. E >= 0, max E > 0. */
+     the position as in orc_voxel_points from r[i][1..3]. Entries that are
+     not >= 0 weigh 0; with no weight at all, v = (r[i][0] * G^3) >> 32. */
 int orc_voxel_points(int32_t G, int32_t per_voxel, const uint32_t* r, float* xyz);
 int orc_error_grid(const orc_net* net, const double* vol, int nx, int ny, int nz, const float* xyz,
                    int64_t n_voxels, int32_t per_voxel, double t, double* E);

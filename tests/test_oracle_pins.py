@@ -1059,3 +1059,8 @@ def test_weighted_points_follow_the_error_grid():
     p = O.weighted_points(E, G, rr)
     np.testing.assert_array_equal(p[0], [-1, 0, -1])
     np.testing.assert_array_equal(p[1], [0, 0, 0])
+    # no weight anywhere (zeros, negatives, NaN): voxels equally likely
+    E = np.array([0, -1, np.nan, 0, 0, 0, 0, 0], np.float32)
+    rr = np.array([[0, 0, 0, 0], [2 ** 29, 0, 0, 0], [2 ** 32 - 1, 0, 0, 0]], np.uint32)
+    p = O.weighted_points(E, G, rr)
+    np.testing.assert_array_equal(p, [[-1, -1, -1], [0, -1, -1], [0, 0, 0]])
