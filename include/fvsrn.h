@@ -277,11 +277,43 @@ fvsrn_status fvsrn_dense_grad_points(const float* vol, int32_t nx, int32_t ny, i
                                      float* out_grad, void* stream);
 
 /* n uniform points in [-1,1)^3 from a Philox4x32-10 counter-based generator
-   (Salmon et al., SC'11): point i uses counter (i, counter_lo, counter_hi, 0)
-   and key (seed_lo, seed_hi); its three coordinates come from the first three
+   (Salmon et al., SC'11): point i uses counter (i mod 2^32, i div 2^32,
+   counter_lo, counter_hi) and key (seed_lo, seed_hi); its three coordinates come from the first three
    32-bit outputs u as -1 + (u >> 8) * 2^-23. xyz [n][3]. */
 fvsrn_status fvsrn_sample_points(uint64_t seed, uint64_t counter, int64_t n, float* xyz,
                                  void* stream);
+
+/* Adaptive resampling of training positions (Sec. 5.4: every N epochs an
+   error grid over G^3 voxels, a few positions per voxel, then new training
+   positions in proportion to the error). Voxel v = (ix, iy, iz), x fastest,
+   spans [-1 + 2 i_a / G, -1 + 2 (i_a + 1) / G] per axis. Random words come
+   from Philox4x32-10 as in fvsrn_sample_points; a position inside voxel v
+   from words r_a is p_a = fma((float)i_a + (r_a >> 8) 2^-24, 2/G, -1) in FP32.
+
+   fvsrn_voxel_points: point j = v * per_voxel + s of the G^3 * per_voxel
+   error-grid points (counter j, words 0..2). xyz [G^3 per_voxel][3];
+   G^3 * per_voxel < 2^32. */
+fvsrn_status fvsrn_voxel_points(uint64_t seed, uint64_t counter, int32_t G, int32_t per_voxel, float* xyz,
+                                void* stream);
+
+/* E[v] = mean over voxel v's per_voxel points xyz[v per_voxel + s] of
+   |fV-SRN density(p, time) - trilinear(vol, p)| (vol [nz][ny][nx] FP32, the
+   training target). scratch: n_voxels * per_voxel floats (device) for the
+   network densities. E [n_voxels] FP32. FP32 networks. */
+fvsrn_status fvsrn_error_grid(const fvsrn_net_desc* desc, const fvsrn_params* params, const float* vol,
+                              int32_t nx, int32_t ny, int32_t nz, const float* xyz, int64_t n_voxels,
+                              int32_t per_voxel, float time, float* E, float* scratch, void* stream);
+
+/* n training positions drawn in proportion to the error grid E [G^3]
+   (device FP32): integer weights q_v = floor(E_v * (2^24 / max E)) (FP32
+   arithmetic; entries that are not >= 0 weigh 0), Q their inclusive prefix
+   sums; point i (counter i) takes the voxel v with
+   Q_{v-1} <= (r_0 * Q_{G^3-1}) >> 32 < Q_v (with no weight at all,
+   v = (r_0 G^3) >> 32) and its position from words 1..3. workspace: device,
+   fvsrn_weighted_points_workspace_size(G) bytes. */
+fvsrn_status fvsrn_sample_points_weighted(uint64_t seed, uint64_t counter, const float* E, int32_t G, int64_t n,
+                                          float* xyz, void* workspace, size_t workspace_bytes, void* stream);
+size_t fvsrn_weighted_points_workspace_size(int32_t G);
 
 /* Round an FP32 array to FP16 or BF16 (round to nearest even), e.g. to store
    the latent grid in FP16. dst_dtype FVSRN_F16 or FVSRN_BF16. */

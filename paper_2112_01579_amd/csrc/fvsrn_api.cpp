@@ -494,6 +494,62 @@ fvsrn_status fvsrn_sample_points(uint64_t seed, uint64_t counter, int64_t n, flo
   return launch_status(launch_sample_points(seed, counter, n, xyz, stream), "fvsrn_sample_points");
 }
 
+fvsrn_status fvsrn_voxel_points(uint64_t seed, uint64_t counter, int32_t G, int32_t per_voxel, float* xyz,
+                                void* stream) {
+  g_err[0] = 0;
+  if (G < 1 || per_voxel < 1) return fail(FVSRN_ERR_INVALID_ARGUMENT, "G and per_voxel must be >= 1");
+  if ((long long)G * G * G * per_voxel >= (1LL << 32))
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "G^3 * per_voxel must stay below 2^32");
+  if (!xyz || !aligned16(xyz)) return fail(FVSRN_ERR_INVALID_ARGUMENT, "xyz NULL or misaligned");
+  return launch_status(launch_voxel_points(seed, counter, G, per_voxel, xyz, stream), "fvsrn_voxel_points");
+}
+
+fvsrn_status fvsrn_error_grid(const fvsrn_net_desc* desc, const fvsrn_params* params, const float* vol, int32_t nx,
+                              int32_t ny, int32_t nz, const float* xyz, int64_t n_voxels, int32_t per_voxel,
+                              float time, float* E, float* scratch, void* stream) {
+  g_err[0] = 0;
+  fvsrn_status s;
+  if ((s = check_desc(desc)) != FVSRN_OK) return s;
+  if ((s = check_params(desc, params)) != FVSRN_OK) return s;
+  if (desc->precision != FVSRN_F32) return fail(FVSRN_ERR_UNSUPPORTED, "the error grid uses an FP32 network");
+  if (!vol || !aligned16(vol)) return fail(FVSRN_ERR_INVALID_ARGUMENT, "vol NULL or misaligned");
+  if (nx < 2 || ny < 2 || nz < 2) return fail(FVSRN_ERR_INVALID_ARGUMENT, "volume needs >= 2 vertices per axis");
+  if (n_voxels < 0 || per_voxel < 1) return fail(FVSRN_ERR_INVALID_ARGUMENT, "n_voxels < 0 or per_voxel < 1");
+  if (n_voxels == 0) return FVSRN_OK;
+  if (!xyz || !E || !scratch || !aligned16(xyz) || !aligned16(scratch) || ((uintptr_t)E & 3u))
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "xyz, E, scratch NULL or misaligned");
+  int key;
+  float kw;
+  key_blend(desc, params, time, &key, &kw);
+  NetDev nd = make_net(desc, params->latent, params->weights, params->latent_dequant);
+  nd.tau = time_tau(desc, time);
+  const long long n = n_voxels * (long long)per_voxel;
+  if ((s = launch_status(launch_points(nd, desc->precision, xyz, n, key, kw, scratch, nullptr, 0, stream),
+                         "fvsrn_error_grid")) != FVSRN_OK)
+    return s;
+  return launch_status(launch_error_reduce(scratch, vol, nx, ny, nz, xyz, n_voxels, per_voxel, E, stream),
+                       "fvsrn_error_grid");
+}
+
+size_t fvsrn_weighted_points_workspace_size(int32_t G) {
+  if (G < 1 || G > 1024) return 0;
+  return weighted_points_workspace_bytes((long long)G * G * G);
+}
+
+fvsrn_status fvsrn_sample_points_weighted(uint64_t seed, uint64_t counter, const float* E, int32_t G, int64_t n,
+                                          float* xyz, void* workspace, size_t workspace_bytes, void* stream) {
+  g_err[0] = 0;
+  if (G < 1 || G > 1024) return fail(FVSRN_ERR_INVALID_ARGUMENT, "G outside [1, 1024]");
+  if (n < 0) return fail(FVSRN_ERR_INVALID_ARGUMENT, "n < 0");
+  if (!E || ((uintptr_t)E & 3u)) return fail(FVSRN_ERR_INVALID_ARGUMENT, "E NULL or misaligned");
+  if (n > 0 && (!xyz || !aligned16(xyz))) return fail(FVSRN_ERR_INVALID_ARGUMENT, "xyz NULL or misaligned");
+  const size_t need = weighted_points_workspace_bytes((long long)G * G * G);
+  if (!workspace || ((uintptr_t)workspace & 15u) || workspace_bytes < need)
+    return fail(FVSRN_ERR_WORKSPACE, "workspace of %zu bytes (16-byte aligned) required", need);
+  return launch_status(launch_weighted_points(seed, counter, E, G, n, xyz, workspace, stream),
+                       "fvsrn_sample_points_weighted");
+}
+
 fvsrn_status fvsrn_cast_grid(const float* src, void* dst, int64_t count, int32_t dst_dtype, void* stream) {
   g_err[0] = 0;
   if (count < 0) return fail(FVSRN_ERR_INVALID_ARGUMENT, "count < 0");

@@ -89,6 +89,14 @@ int launch_sample_points(uint64_t seed, uint64_t counter, long long n, float* xy
 int launch_cast(const float* src, void* dst, long long count, int dst_dtype, void* stream);
 int launch_ssim(const float* a, const float* b, int width, int height, int n_images, float* out, void* stream);
 int launch_quantize(const float* src, long long n, int channels, unsigned char* codes, float* dequant, void* stream);
+// Adaptive resampling (Sec. 5.4): error-grid positions, the per-voxel mean
+// absolute error, and positions drawn in proportion to an error grid.
+int launch_voxel_points(uint64_t seed, uint64_t counter, int G, int per_voxel, float* xyz, void* stream);
+int launch_error_reduce(const float* d, const float* vol, int nx, int ny, int nz, const float* xyz,
+                        long long n_voxels, int per_voxel, float* E, void* stream);
+size_t weighted_points_workspace_bytes(long long n_voxels);
+int launch_weighted_points(uint64_t seed, uint64_t counter, const float* E, int G, long long n, float* xyz,
+                           void* workspace, void* stream);
 
 // Training (FP32). Workspace layout is owned by the kernels file.
 size_t train_workspace_bytes(const NetDev& net, long long n);

@@ -214,19 +214,33 @@ __device__ inline void philox_round(uint32_t c[4], const uint32_t k[2]) {
   c[3] = lo0;
 }
 
+}  // namespace
+
+// Philox4x32-10 (Salmon et al., SC'11) of counter (i mod 2^32, i div 2^32,
+// c_lo, c_hi) and key (k0, k1): four 32-bit outputs in c.
+__device__ void philox4x32_10(long long i, uint32_t c_lo, uint32_t c_hi, uint32_t k0, uint32_t k1, uint32_t c[4]) {
+  c[0] = (uint32_t)i;
+  c[1] = (uint32_t)((unsigned long long)i >> 32);
+  c[2] = c_lo;
+  c[3] = c_hi;
+  uint32_t k[2] = {k0, k1};
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k[0] += 0x9E3779B9u;
+      k[1] += 0xBB67AE85u;
+    }
+    philox_round(c, k);
+  }
+}
+
+namespace {
+
 __global__ void sample_points_kernel(uint32_t k0, uint32_t k1, uint32_t c_lo, uint32_t c_hi,
                                      long long n, float* xyz) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
-    uint32_t c[4] = {(uint32_t)i, (uint32_t)((unsigned long long)i >> 32), c_lo, c_hi};
-    uint32_t k[2] = {k0, k1};
-    for (int r = 0; r < 10; ++r) {
-      if (r > 0) {
-        k[0] += 0x9E3779B9u;
-        k[1] += 0xBB67AE85u;
-      }
-      philox_round(c, k);
-    }
+    uint32_t c[4];
+    philox4x32_10(i, c_lo, c_hi, k0, k1, c);
     const float s = 1.0f / 8388608.0f;  // 2^-23
     xyz[3 * i + 0] = -1.0f + (float)(c[0] >> 8) * s;
     xyz[3 * i + 1] = -1.0f + (float)(c[1] >> 8) * s;
@@ -365,6 +379,195 @@ int device_cus() {
 namespace {
 
 }  // namespace
+
+// ------------------------------------------ adaptive resampling (Sec. 5.4)
+
+namespace {
+
+// Position inside voxel v of a G^3 grid over [-1,1]^3 (x fastest) from three
+// random words: p_a = fma((float)i_a + u_a, 2/G, -1), u_a = (r_a >> 8) 2^-24.
+__device__ inline void voxel_position(int G, long long v, const uint32_t* r, float* p) {
+  const long long iv[3] = {v % G, (v / G) % G, v / ((long long)G * G)};
+  const float step = 2.0f / (float)G;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float u = (float)(r[a] >> 8) * 5.9604644775390625e-8f;  // 2^-24
+    p[a] = fmaf((float)iv[a] + u, step, -1.0f);
+  }
+}
+
+__global__ void voxel_points_kernel(uint32_t k0, uint32_t k1, uint32_t c_lo, uint32_t c_hi, int G, int per_voxel,
+                                    long long n, float* xyz) {
+  for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+       j += (long long)gridDim.x * blockDim.x) {
+    uint32_t c[4];
+    philox4x32_10(j, c_lo, c_hi, k0, k1, c);
+    voxel_position(G, j / per_voxel, c, xyz + 3 * j);
+  }
+}
+
+// E[v] = mean over the voxel's points of |network density - trilinear target|.
+__global__ void error_reduce_kernel(const float* d, const float* vol, int nx, int ny, int nz, const float* xyz,
+                                    long long n_voxels, int per_voxel, float* E) {
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n_voxels;
+       v += (long long)gridDim.x * blockDim.x) {
+    float s = 0.0f;
+    for (int k = 0; k < per_voxel; ++k) {
+      const long long j = v * per_voxel + k;
+      s += fabsf(d[j] - dense_sample(vol, nx, ny, nz, xyz[3 * j], xyz[3 * j + 1], xyz[3 * j + 2]));
+    }
+    E[v] = s / (float)per_voxel;
+  }
+}
+
+// Largest weight (bits of non-negative floats order like unsigned integers;
+// entries that are not >= 0 count as 0). emax must start at 0.
+__global__ void weight_max_kernel(const float* E, long long nv, unsigned* emax) {
+  unsigned m = 0;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < nv;
+       v += (long long)gridDim.x * blockDim.x) {
+    const float e = E[v];
+    if (e >= 0.0f) m = max(m, __float_as_uint(e));
+  }
+  for (int off = 32; off > 0; off >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, off, 64));
+  if ((threadIdx.x & 63) == 0 && m) atomicMax(emax, m);
+}
+
+constexpr int kScanThreads = 256, kScanItems = 8, kScanBlock = kScanThreads * kScanItems;
+
+// Integer weights q_v = floor(E_v * (2^24 / max E)) and their inclusive
+// prefix sums within each block of kScanBlock voxels; block totals to S.
+__global__ __launch_bounds__(kScanThreads) void weight_scan_kernel(const float* E, long long nv, const unsigned* emax,
+                                                                   unsigned long long* Q, unsigned long long* S) {
+  __shared__ unsigned long long part[kScanThreads];
+  const float em = __uint_as_float(*emax);
+  const float scale = em > 0.0f ? 16777216.0f / em : 0.0f;
+  const long long base = (long long)blockIdx.x * kScanBlock + (long long)threadIdx.x * kScanItems;
+  unsigned long long q[kScanItems], run = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const long long v = base + k;
+    const float e = v < nv ? E[v] : 0.0f;
+    run += (e >= 0.0f) ? (unsigned long long)floorf(e * scale) : 0ull;
+    q[k] = run;
+  }
+  part[threadIdx.x] = run;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {  // inclusive scan of the thread totals
+    const unsigned long long x = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0ull;
+    __syncthreads();
+    part[threadIdx.x] += x;
+    __syncthreads();
+  }
+  const unsigned long long before = threadIdx.x ? part[threadIdx.x - 1] : 0ull;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < nv) Q[base + k] = q[k] + before;
+  if (threadIdx.x == kScanThreads - 1) S[blockIdx.x] = part[threadIdx.x];
+}
+
+// Exclusive prefix sums of the block totals (one workgroup, in place).
+__global__ __launch_bounds__(kScanThreads) void block_offsets_kernel(unsigned long long* S, long long nb) {
+  __shared__ unsigned long long part[kScanThreads];
+  unsigned long long carry = 0;
+  for (long long b0 = 0; b0 < nb; b0 += kScanThreads) {
+    const long long b = b0 + threadIdx.x;
+    const unsigned long long x = b < nb ? S[b] : 0ull;
+    part[threadIdx.x] = x;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+      const unsigned long long y = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0ull;
+      __syncthreads();
+      part[threadIdx.x] += y;
+      __syncthreads();
+    }
+    if (b < nb) S[b] = carry + part[threadIdx.x] - x;
+    const unsigned long long total = part[kScanThreads - 1];
+    __syncthreads();
+    carry += total;
+  }
+}
+
+__global__ void add_offsets_kernel(unsigned long long* Q, long long nv, const unsigned long long* S) {
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < nv;
+       v += (long long)gridDim.x * blockDim.x)
+    Q[v] += S[v / kScanBlock];
+}
+
+// Point i: voxel v with Q[v-1] <= (r0 total) >> 32 < Q[v] (all weights zero:
+// v = (r0 nv) >> 32), position inside it from r1..r3.
+__global__ void weighted_points_kernel(uint32_t k0, uint32_t k1, uint32_t c_lo, uint32_t c_hi,
+                                       const unsigned long long* Q, int G, long long nv, long long n, float* xyz) {
+  const unsigned long long total = Q[nv - 1];
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    uint32_t c[4];
+    philox4x32_10(i, c_lo, c_hi, k0, k1, c);
+    long long v;
+    if (total == 0) {
+      v = (long long)(((unsigned long long)c[0] * (unsigned long long)nv) >> 32);
+    } else {
+      const unsigned long long target = __umul64hi((unsigned long long)c[0] << 32, total);
+      long long lo = 0, hi = nv - 1;
+      while (lo < hi) {
+        const long long mid = (lo + hi) >> 1;
+        if (Q[mid] > target) hi = mid;
+        else lo = mid + 1;
+      }
+      v = lo;
+    }
+    voxel_position(G, v, c + 1, xyz + 3 * i);
+  }
+}
+
+__global__ void zero_u32_kernel(unsigned* p) { *p = 0u; }
+
+}  // namespace
+
+int launch_voxel_points(uint64_t seed, uint64_t counter, int G, int per_voxel, float* xyz, void* stream) {
+  const long long n = (long long)G * G * G * per_voxel;
+  hipLaunchKernelGGL(voxel_points_kernel, dim3(grid_blocks(n, 256, device_cus() * 16)), dim3(256), 0,
+                     (hipStream_t)stream, (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)counter,
+                     (uint32_t)(counter >> 32), G, per_voxel, n, xyz);
+  return check_launch();
+}
+
+int launch_error_reduce(const float* d, const float* vol, int nx, int ny, int nz, const float* xyz,
+                        long long n_voxels, int per_voxel, float* E, void* stream) {
+  hipLaunchKernelGGL(error_reduce_kernel, dim3(grid_blocks(n_voxels, 256, device_cus() * 16)), dim3(256), 0,
+                     (hipStream_t)stream, d, vol, nx, ny, nz, xyz, n_voxels, per_voxel, E);
+  return check_launch();
+}
+
+size_t weighted_points_workspace_bytes(long long nv) {
+  const long long nb = (nv + kScanBlock - 1) / kScanBlock;
+  return (size_t)(nv + nb) * 8 + 16;
+}
+
+int launch_weighted_points(uint64_t seed, uint64_t counter, const float* E, int G, long long n, float* xyz,
+                           void* workspace, void* stream) {
+  const hipStream_t st = (hipStream_t)stream;
+  const long long nv = (long long)G * G * G, nb = (nv + kScanBlock - 1) / kScanBlock;
+  unsigned long long* Q = (unsigned long long*)workspace;
+  unsigned long long* S = Q + nv;
+  unsigned* emax = (unsigned*)(S + nb);
+  hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, st, emax);
+  int rc = check_launch();
+  if (rc) return rc;
+  hipLaunchKernelGGL(weight_max_kernel, dim3(grid_blocks(nv, 256, device_cus() * 8)), dim3(256), 0, st, E, nv, emax);
+  if ((rc = check_launch())) return rc;
+  hipLaunchKernelGGL(weight_scan_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, st, E, nv, emax, Q, S);
+  if ((rc = check_launch())) return rc;
+  hipLaunchKernelGGL(block_offsets_kernel, dim3(1), dim3(kScanThreads), 0, st, S, nb);
+  if ((rc = check_launch())) return rc;
+  hipLaunchKernelGGL(add_offsets_kernel, dim3(grid_blocks(nv, 256, device_cus() * 8)), dim3(256), 0, st, Q, nv, S);
+  if ((rc = check_launch())) return rc;
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(weighted_points_kernel, dim3(grid_blocks(n, 256, device_cus() * 16)), dim3(256), 0, st,
+                     (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)counter, (uint32_t)(counter >> 32), Q, G, nv,
+                     n, xyz);
+  return check_launch();
+}
 
 const char* last_hip_error() { return g_hip_err; }
 

@@ -29,6 +29,7 @@ EXPORTS = (
     "fvsrn_render", "fvsrn_eval_points", "fvsrn_grad_points", "fvsrn_train_step",
     "fvsrn_train_workspace_size", "fvsrn_render_dense", "fvsrn_dense_eval_points", "fvsrn_dense_grad_points",
     "fvsrn_sample_points", "fvsrn_cast_grid", "fvsrn_quantize_grid", "fvsrn_ssim_map", "fvsrn_num_weights",
+    "fvsrn_voxel_points", "fvsrn_error_grid", "fvsrn_sample_points_weighted", "fvsrn_weighted_points_workspace_size",
     "fvsrn_status_str", "fvsrn_last_error",
 )
 
@@ -103,6 +104,10 @@ def lib():
             "fvsrn_quantize_grid": (st, [vp, i64, i32, vp, vp, vp]),
             "fvsrn_ssim_map": (st, [vp, vp, i32, i32, i32, vp, vp]),
             "fvsrn_num_weights": (i64, [vp]),
+            "fvsrn_voxel_points": (st, [C.c_uint64, C.c_uint64, i32, i32, vp, vp]),
+            "fvsrn_error_grid": (st, [vp, vp, vp, i32, i32, i32, vp, i64, i32, C.c_float, vp, vp, vp]),
+            "fvsrn_sample_points_weighted": (st, [C.c_uint64, C.c_uint64, vp, i32, i64, vp, vp, sz, vp]),
+            "fvsrn_weighted_points_workspace_size": (sz, [i32]),
             "fvsrn_status_str": (C.c_char_p, [st]),
             "fvsrn_last_error": (C.c_char_p, []),
         }
@@ -306,6 +311,41 @@ def fvsrn_sample_points(seed: int, counter: int, n: int, out=None, device="cuda"
     if out is None:
         out = torch.empty((n, 3), dtype=torch.float32, device=device)
     _check(lib().fvsrn_sample_points(seed, counter, n, _ptr(out), _stream(stream)), "fvsrn_sample_points")
+    return out
+
+
+def fvsrn_voxel_points(seed: int, counter: int, G: int, per_voxel: int, out=None, device="cuda", stream=None):
+    """per_voxel positions in each of the G^3 voxels (error-grid samples, Sec. 5.4)."""
+    if out is None:
+        out = torch.empty((G ** 3 * per_voxel, 3), dtype=torch.float32, device=device)
+    _check(lib().fvsrn_voxel_points(seed, counter, G, per_voxel, _ptr(out), _stream(stream)), "fvsrn_voxel_points")
+    return out
+
+
+def fvsrn_error_grid(net: "Network", vol: torch.Tensor, xyz: torch.Tensor, per_voxel: int, time: float = 0.0,
+                     out=None, scratch=None, stream=None):
+    """Mean |density - trilinear target| per voxel (Sec. 5.4), FP32 network."""
+    nz, ny, nx = vol.shape
+    nvox = xyz.shape[0] // per_voxel
+    if out is None:
+        out = torch.empty(nvox, dtype=torch.float32, device=xyz.device)
+    if scratch is None:
+        scratch = torch.empty(nvox * per_voxel, dtype=torch.float32, device=xyz.device)
+    d, p = net.desc("f32"), net.params()
+    _check(lib().fvsrn_error_grid(C.byref(d), C.byref(p), _ptr(vol), nx, ny, nz, _ptr(xyz), nvox, per_voxel, time,
+                                  _ptr(out), _ptr(scratch), _stream(stream)), "fvsrn_error_grid")
+    return out
+
+
+def fvsrn_sample_points_weighted(seed: int, counter: int, E: torch.Tensor, G: int, n: int, out=None,
+                                 workspace=None, stream=None):
+    """n positions drawn in proportion to the error grid E [G^3] (Sec. 5.4)."""
+    if out is None:
+        out = torch.empty((n, 3), dtype=torch.float32, device=E.device)
+    if workspace is None:
+        workspace = torch.empty(lib().fvsrn_weighted_points_workspace_size(G), dtype=torch.uint8, device=E.device)
+    _check(lib().fvsrn_sample_points_weighted(seed, counter, _ptr(E), G, n, _ptr(out), _ptr(workspace),
+                                              workspace.numel(), _stream(stream)), "fvsrn_sample_points_weighted")
     return out
 
 

@@ -30,11 +30,16 @@ class Trainer:
     A 4-output network (density and predicted gradient, Sec. 6) trained with
     ``grad_weight`` > 0 also fits its gradient outputs to one-voxel central
     differences of the volume (the gradients the dense renderer shades with),
-    weighted L1 next to the density's L1."""
+    weighted L1 next to the density's L1.
+
+    ``resample_every`` = N > 0 turns on adaptive resampling (Sec. 5.4, single
+    volume): after every N steps the mean absolute error of the network is
+    measured on an ``error_grid``^3 voxel grid (``per_voxel`` positions per
+    voxel), and the next N steps draw their positions in proportion to it."""
 
     def __init__(self, net: FV.Network, vol, batch: int = 1 << 18, lr_grid: float = 1e-2,
                  lr_mlp: float = 1e-3, betas=(0.9, 0.999), eps: float = 1e-8, seed: int = 0,
-                 grad_weight: float = 0.0):
+                 grad_weight: float = 0.0, resample_every: int = 0, error_grid: int = 128, per_voxel: int = 8):
         assert net.grid_dtype == FV.F32
         assert grad_weight == 0.0 or net.spec.outputs == 4
         if isinstance(vol, torch.Tensor):
@@ -64,11 +69,35 @@ class Trainer:
         self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
         ws = FV.fvsrn_train_workspace_size(net.spec, batch)
         self.workspace = torch.empty(max(ws, 16), dtype=torch.uint8, device=dev)
+        self.resample_every, self.G, self.per_voxel = int(resample_every), int(error_grid), int(per_voxel)
+        self.E = None
+        if self.resample_every:
+            assert len(self.frames) == 1, "adaptive resampling is for a single volume"
+            n_err = self.G ** 3 * self.per_voxel
+            self.err_xyz = torch.empty((n_err, 3), dtype=torch.float32, device=dev)
+            self.err_scratch = torch.empty(n_err, dtype=torch.float32, device=dev)
+            self.E = torch.empty(self.G ** 3, dtype=torch.float32, device=dev)
+            self.E_ready = False
+            self.sample_ws = torch.empty(FV.lib().fvsrn_weighted_points_workspace_size(self.G), dtype=torch.uint8,
+                                         device=dev)
+
+    def update_error_grid(self):
+        """Measure the error grid E of the current network (Sec. 5.4)."""
+        t, v = self.frames[0]
+        FV.fvsrn_voxel_points(self.seed ^ 0x5DEECE66D, self.opt["step"], self.G, self.per_voxel, out=self.err_xyz)
+        FV.fvsrn_error_grid(self.net, v, self.err_xyz, self.per_voxel, t, out=self.E, scratch=self.err_scratch)
+        self.E_ready = True
 
     def step(self) -> torch.Tensor:
         """One training step; returns the L1 loss of the batch (device scalar)."""
         self.opt["step"] += 1
-        FV.fvsrn_sample_points(self.seed, self.opt["step"], self.batch, out=self.xyz)
+        if self.resample_every and self.opt["step"] > 1 and (self.opt["step"] - 1) % self.resample_every == 0:
+            self.update_error_grid()
+        if self.E is not None and self.E_ready:
+            FV.fvsrn_sample_points_weighted(self.seed, self.opt["step"], self.E, self.G, self.batch, out=self.xyz,
+                                            workspace=self.sample_ws)
+        else:
+            FV.fvsrn_sample_points(self.seed, self.opt["step"], self.batch, out=self.xyz)
         for j, (_, v) in enumerate(self.frames):
             a, b = self.bounds[j], self.bounds[j + 1]
             if self.target_grad is None:

@@ -724,3 +724,57 @@ def test_fourier_matrix_eval_and_render(FV, spec):
     a = FV.fvsrn_eval_points(octv, torch.from_numpy(xyz).cuda(), 0.4, "f32")
     b = FV.fvsrn_eval_points(dflt, torch.from_numpy(xyz).cuda(), 0.4, "f32")
     assert torch.max(torch.abs(a - b)).item() <= 1e-5
+
+
+# ----------------------------------------- adaptive resampling (Sec. 5.4)
+
+def _philox_words(n, seed, counter):
+    i = np.arange(n, dtype=np.uint64)
+    ctr = [i & np.uint64(0xFFFFFFFF), i >> np.uint64(32), np.full(n, counter & 0xFFFFFFFF, np.uint64),
+           np.full(n, counter >> 32, np.uint64)]
+    c = _philox4x32_10(ctr, (seed & 0xFFFFFFFF, seed >> 32))
+    return np.stack([x.astype(np.uint32) for x in c], 1)
+
+
+def test_voxel_points_and_error_grid(FV):
+    """Error-grid positions bit for bit against the oracle fed with the same
+    Philox words (an independent numpy Philox), and the per-voxel mean
+    absolute error of an FP32 network against a dense target within FP32
+    rounding."""
+    G, spp, seed, counter = 6, 5, 0xABCDEF0123, (7 << 32) + 3
+    xyz = FV.fvsrn_voxel_points(seed, counter, G, spp).cpu().numpy()
+    want = O.voxel_points(G, spp, _philox_words(G ** 3 * spp, seed, counter)[:, :3])
+    assert np.array_equal(xyz, want)
+    gnet, onet = _nets(FV, I.NET_SMALL, 12)
+    vol = np.random.default_rng(3).uniform(0, 1, (9, 11, 10)).astype(np.float32)
+    E = FV.fvsrn_error_grid(gnet, torch.from_numpy(vol).cuda(), torch.from_numpy(xyz).cuda(), spp).cpu().numpy()
+    Eref = O.error_grid(onet, vol, xyz, spp)
+    assert np.abs(E - Eref).max() <= 1e-5
+
+
+def test_weighted_points_bit_exact(FV):
+    """Positions drawn in proportion to an error grid: the integer-weight
+    inverse CDF makes every voxel choice exact, so the points equal the
+    oracle's bit for bit -- a random grid with zero and negative entries, a
+    one-hot grid, an all-zero grid (uniform voxels) -- at a size that spans
+    several scan blocks."""
+    seed, counter, n = 99, 5, 50000
+    r = _philox_words(n, seed, counter)
+    rng = np.random.default_rng(8)
+    G = 24                                           # 13824 voxels: 7 scan blocks
+    E = rng.exponential(0.01, G ** 3).astype(np.float32)
+    E[rng.random(G ** 3) < 0.3] = 0.0
+    E[:5] = -1.0
+    cases = [E, np.zeros(G ** 3, np.float32), np.where(np.arange(G ** 3) == 777, 0.5, 0.0).astype(np.float32)]
+    for Ec in cases:
+        got = FV.fvsrn_sample_points_weighted(seed, counter, torch.from_numpy(Ec).cuda(), G, n).cpu().numpy()
+        want = O.weighted_points(Ec, G, r)
+        assert np.array_equal(got, want)
+    # the empirical voxel frequencies follow the weights
+    got = FV.fvsrn_sample_points_weighted(seed, counter + 1, torch.from_numpy(E).cuda(), G, 1 << 20).cpu().numpy()
+    idx = np.clip(((got + 1) * G / 2).astype(np.int64), 0, G - 1)
+    v = idx[:, 0] + G * idx[:, 1] + G * G * idx[:, 2]
+    freq = np.bincount(v, minlength=G ** 3) / (1 << 20)
+    w = np.maximum(E, 0) / np.maximum(E, 0).sum()
+    assert np.abs(freq - w).max() < 6 * np.sqrt(w.max() / (1 << 20))
+    assert freq[E <= 0].sum() == 0

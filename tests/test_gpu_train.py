@@ -356,3 +356,25 @@ def test_train_gradients_fourier_matrix(FV):
     print("train fourier matrix: dW rel err %.3g, dG rel err %.3g" % (e_w, e_l), flush=True)
     assert e_w <= 1e-4 and e_l <= 1e-4
     assert abs(loss.item() - loss_ref) <= 1e-5 * max(1.0, abs(loss_ref))
+
+
+def test_trainer_adaptive_resampling(FV):
+    """Adaptive resampling (Sec. 5.4): after the first N steps the trainer
+    measures the error grid and draws its positions from it; training still
+    converges and ends below the error it started from, and the sampled
+    positions concentrate where the error grid is large."""
+    from paper_2112_01579_amd.trainer import Trainer
+    vol = torch.from_numpy(I.gaussian_volume(48, 16, seed=4)).cuda()
+    lat, w = I.net_params(I.NET_SMALL, 2)
+    net = FV.Network(I.NET_SMALL, lat, w)
+    tr = Trainer(net, vol, batch=1 << 14, resample_every=25, error_grid=16, per_voxel=8)
+    losses = [tr.step().item() for _ in range(120)]
+    assert tr.E_ready and torch.isfinite(tr.E).all()
+    assert np.mean(losses[-10:]) < 0.7 * np.mean(losses[:10])
+    E = tr.E.cpu().numpy()
+    x = tr.xyz.cpu().numpy()
+    idx = np.clip(((x + 1) * 8).astype(np.int64), 0, 15)
+    ev = E[idx[:, 0] + 16 * idx[:, 1] + 256 * idx[:, 2]]
+    print("adaptive resampling: mean E at sampled positions %.4g vs grid mean %.4g" % (ev.mean(), E.mean()),
+          flush=True)
+    assert ev.mean() > 1.5 * E.mean()
