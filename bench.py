@@ -66,26 +66,32 @@ def time_launches(fn, steps, warmup):
     return per, wall
 
 
-def kernel_source_hash() -> str:
-    """sha256 of the sources the render kernel is compiled from."""
-    import hashlib
-    h = hashlib.sha256()
-    for f in ("fvsrn_common.hpp", "fvsrn_net.hpp", "fvsrn_adjoint.hpp", "fvsrn_march.hpp", "fvsrn_march.hip",
-              "fvsrn_launch.h"):
-        with open(os.path.join(ROOT, "paper_2112_01579_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
+# mangled name of the study render kernel (FP16 network, c = 32, F = 16, L = 8,
+# sine, FP16 latent grid, no time input or Fourier matrix, no shading)
+STUDY_KERNEL = ("_ZN12fvsrn_detail12_GLOBAL__N_112march_kernelINS_3CfgILi1ELi32ELi16ELi8ELi0ELi1ELi0ELi0EEELi0ELi0EEEvNS_"
+                "6NetDevENS_5TFDevENS_9ViewBatchENS_8MarchDevEPfPyii")
+
+
+def kernel_isa_hash():
+    """sha256 of the study render kernel's instructions, as recorded by the
+    build next to the library (None when the record is missing)."""
+    path = os.path.join(ROOT, "paper_2112_01579_amd", "libfvsrn_kernels.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        return json.load(fh).get(STUDY_KERNEL)
 
 
 def measured_traffic():
     """HBM bytes per launch of the FP16 render from the committed rocprofv3
-    counter record, if it was taken on the current kernel sources."""
+    counter record, if it was taken on the kernel code that is built now."""
     path = os.path.join(ROOT, "profiles", "march_f16_study_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("kernel_sha256") != kernel_source_hash():
+    h = kernel_isa_hash()
+    if h is None or rec.get("kernel_isa_sha256") != h:
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -429,6 +435,34 @@ def main():
                 del ftr, fnet, f16
             comp["fourier_features"] = {"train": "%d steps of 2^18 points on the 256^3 volume" % fsteps, **ff}
         progress("point evaluation")
+        # adaptive resampling (Sec. 5.4): the study network trained with
+        # uniform positions and with positions drawn from a 128^3 error grid
+        # refreshed every 50 steps, the same number of steps each; density
+        # error at uniform points and the FP16 image against dense DVR
+        if args.train_steps > 0:
+            progress("adaptive resampling")
+            ar = {}
+            rsteps = max(1, args.train_steps // 4)
+            FV.fvsrn_render_dense(vol, tf, cams, march, out=ref)
+            for name, every in (("uniform", 0), ("resampled_every_50", 50)):
+                rlat, rw = I.net_params(spec, I.SEED_STUDY)
+                rnet = FV.Network(spec, rlat, rw, grid_dtype=FV.F32, device=dev)
+                rtr = Trainer(rnet, vol, batch=1 << 18, seed=I.SEED_TRAIN, resample_every=every, error_grid=128,
+                              per_voxel=8)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(rsteps):
+                    rtr.step()
+                torch.cuda.synchronize()
+                t_r = time.perf_counter() - t0
+                l1 = torch.mean(torch.abs(FV.fvsrn_eval_points(rnet, xf, 0.0, "f32") - dref)).item()
+                r16 = FV.Network(spec, rnet.latent.cpu().numpy(), rnet.weights.cpu().numpy(), grid_dtype=FV.F16,
+                                 device=dev)
+                FV.fvsrn_render(r16, tf, cams, march, "f16", out=out)
+                ar[name] = {"l1_uniform_points": l1, "image_rmse_vs_dense": rmse(out), "image_ssim_vs_dense": ssim(out),
+                            "train_ms_per_step": t_r / rsteps * 1e3}
+                del rtr, rnet, r16
+            comp["adaptive_resampling"] = {"train": "%d steps of 2^18 points, error grid 128^3 x 8" % rsteps, **ar}
         # fused point evaluation vs the framework-style layer-by-layer network (2^24 points)
         npts = 1 << 24
         xyz = torch.rand((npts, 3), device=dev) * 2 - 1

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import glob
+import json
 import os
 import re
 import subprocess
@@ -139,6 +140,30 @@ def device_asm_files():
     return sorted(glob.glob(os.path.join(BUILD, "*", "*-hip-amdgcn-amd-amdhsa-gfx950.s")))
 
 
+KERNEL_HASHES = os.path.join(HERE, "libfvsrn_kernels.json")
+
+
+def kernel_isa_hashes(asm: str):
+    """sha256 of each kernel's instruction listing (label to end of function,
+    comments and directives dropped): it changes only when the kernel's code
+    does, unlike a hash of the source files."""
+    import hashlib
+    out, name, body = {}, None, []
+    for line in asm.splitlines():
+        head = line.split(";")[0].rstrip()
+        if head.startswith("_Z") and head.endswith(":"):
+            name, body = head[:-1], []
+        elif name is not None:
+            if line.startswith(".Lfunc_end"):
+                out[name] = hashlib.sha256("\n".join(body).encode()).hexdigest()
+                name = None
+                continue
+            t = line.split(";")[0].strip()
+            if t and not t.startswith("."):
+                body.append(t)
+    return out
+
+
 def build(force: bool = True, verbose: bool = False, jobs: int = 0) -> str:
     """Compile the library (always when force is set)."""
     if not force and os.path.exists(LIB):
@@ -173,6 +198,12 @@ def build(force: bool = True, verbose: bool = False, jobs: int = 0) -> str:
         if bad:
             raise RuntimeError("%s: memory instruction reads an MFMA result too early:\n%s" %
                                (path, "\n".join("%s: %s -> %s" % b for b in bad[:10])))
+    hashes = {}
+    for path in device_asm_files():
+        with open(path) as fh:
+            hashes.update(kernel_isa_hashes(fh.read()))
+    with open(KERNEL_HASHES, "w") as fh:
+        json.dump(hashes, fh, indent=0, sort_keys=True)
     tmp = LIB + ".tmp%d" % os.getpid()
     rc, text = _run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] +
                     [os.path.join(BUILD, u[2]) for u in units])
