@@ -240,11 +240,13 @@ typedef struct {
    blends the two neighbouring keyframes as in rendering, so a point's latent
    gradient goes to both with the blend weights.
    d_latent [K R^3 F] and d_weights [n_weights] are overwritten with the
-   gradients (d_weights bitwise reproducible; d_latent summed with float
-   atomics). With adam != NULL the latent grids and the weights are then
+   gradients (d_weights bitwise reproducible; d_latent gathered per vertex
+   over the points of its eight cells after a counting sort of the points by
+   cell, whose order within a cell may vary between calls, so d_latent is
+   reproducible to rounding). n < 2^31. With adam != NULL the latent grids and the weights are then
    updated in place (lr_grid for the latent grids, lr_mlp for the weights).
-   out_loss (nullable, device FP32 scalar) receives the loss. workspace must
-   hold fvsrn_train_workspace_size(desc, n) bytes. */
+   out_loss (nullable, device FP32 scalar) receives the loss. workspace
+   (16-byte aligned) must hold fvsrn_train_workspace_size(desc, n) bytes. */
 fvsrn_status fvsrn_train_step(const fvsrn_net_desc* desc, float* latent, float* weights,
                               const float* key_times, float* d_latent, float* d_weights,
                               const float* xyz, const float* times, int64_t n,

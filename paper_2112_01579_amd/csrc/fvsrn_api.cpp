@@ -398,9 +398,10 @@ fvsrn_status fvsrn_train_step(const fvsrn_net_desc* desc, float* latent, float* 
       return fail(FVSRN_ERR_INVALID_ARGUMENT, "adam moment buffers must be non-NULL");
   }
   const NetDev nd = make_net(desc, latent, weights);
+  if (n >= (1LL << 31)) return fail(FVSRN_ERR_INVALID_ARGUMENT, "training takes fewer than 2^31 points per step");
   const size_t need = train_workspace_bytes(nd, n);
-  if (need > 0 && (!workspace || workspace_bytes < need))
-    return fail(FVSRN_ERR_WORKSPACE, "workspace of %zu bytes required", need);
+  if (need > 0 && (!workspace || ((uintptr_t)workspace & 15u) || workspace_bytes < need))
+    return fail(FVSRN_ERR_WORKSPACE, "workspace of %zu bytes (16-byte aligned) required", need);
   KeyTimes kt;
   kt.K = desc->num_keyframes;
   for (int k = 0; k < kMaxKeyframes; ++k) kt.t[k] = (k < kt.K && key_times) ? key_times[k] : 0.0f;

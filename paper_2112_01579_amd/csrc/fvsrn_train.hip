@@ -13,8 +13,12 @@
 //   4. backward: delta_i = (W_{i+1}^T delta_{i+1}) * act'(a_i) on MFMA with
 //      transposed weight fragments; dW_i = delta_i h_i^T as an MFMA GEMM over
 //      the chunk's samples (A = delta, B = layer input, both read from LDS);
-//   5. dL/dz = W_0[:, latent]^T delta_0, scattered into the latent gradient
-//      with the trilinear weights (hardware float atomics).
+//   5. dL/dz = W_0[:, latent]^T delta_0, stored per point with the point's
+//      latent cell (and the cell's point count).
+// The latent gradient is then gathered, not scattered: the points are
+// counting-sorted by cell (cell_scan_kernel, bin_points_kernel) and every
+// grid vertex sums the trilinear-weighted dL/dz of the points in its (up to)
+// eight cells (latent_grad_kernel), with plain stores.
 // dW tiles are added into the wave's private workspace slice (no atomics, so
 // dW is bitwise reproducible). slice_sum_kernel and gather_kernel then sum the
 // slices in a fixed order into the packed gradient; adam_kernel applies the
@@ -95,13 +99,32 @@ __device__ void stage_backward(const NetDev& nd, char* p) {
   }
 }
 
+// Keyframe pair of time t (Sec. 8): the time clamped to the key range,
+// linear between the neighbouring keyframes; key = 0, kw = 0 for one keyframe.
+__device__ inline void key_pair(const KeyTimes& kt, int K, float t, int& key, float& kw) {
+  key = 0;
+  kw = 0.0f;
+  if (K > 1) {
+    if (t <= kt.t[0]) {
+      key = 0;
+      kw = 0.0f;
+    } else if (t >= kt.t[K - 1]) {
+      key = K - 2;
+      kw = 1.0f;
+    } else {
+      while (key + 1 < K - 1 && kt.t[key + 1] <= t) ++key;
+      kw = (t - kt.t[key]) / (kt.t[key + 1] - kt.t[key]);
+    }
+  }
+}
+
 template <int C, int F, int L, int ACT, int TE, int FM>
 __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDev nd, KeyTimes kt, const float* xyz,
                                                                             const float* times, long long n,
                                                                             const float* target,
                                                                             const float* target_grad, float gw3,
-                                                      const float* dloss, float* d_latent, float* ws, int n_waves,
-                                                      float inv_n) {
+                                                      const float* dloss, float* dz_out, int* cell_out,
+                                                      int* cell_count, float* ws, int n_waves, float inv_n) {
   using TC = TrainCfg<C, F, L, ACT, TE, FM>;
   using CF = typename TC::CF;
   using G = typename TC::G;
@@ -158,22 +181,10 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
       pz = xyz[3 * idx + 2];
       if (times) pt = times[idx];
     }
-    // this point's keyframe pair (Sec. 8): the time clamped to the key range,
-    // linear between the neighbouring keyframes
-    int key = 0;
-    float kw = 0.0f;
-    if (nd.K > 1) {
-      if (pt <= kt.t[0]) {
-        key = 0;
-        kw = 0.0f;
-      } else if (pt >= kt.t[nd.K - 1]) {
-        key = nd.K - 2;
-        kw = 1.0f;
-      } else {
-        while (key + 1 < nd.K - 1 && kt.t[key + 1] <= pt) ++key;
-        kw = (pt - kt.t[key]) / (kt.t[key + 1] - kt.t[key]);
-      }
-    }
+    // this point's keyframe pair (Sec. 8)
+    int key;
+    float kw;
+    key_pair(kt, nd.K, pt, key, kw);
     float tfe[G::TIN > 0 ? G::TIN : 1];  // the point's time inputs (Sec. 8)
     if constexpr (G::TIN > 0) time_features<TE>(time_tau(pt, nd.t_lo, nd.t_hi, nd.t_scale), tfe);
     if (lane < S) {
@@ -380,37 +391,21 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
       }
       wave_lds_sync();
     }
-    // ---------------- latent scatter with the trilinear weights
+    // ---------------- dL/dz and the latent cell of this lane's point
     if (ok) {
       int ix, iy, iz;
       float fx, fy, fz;
       axis_cell(px, nd.R, ix, fx);
       axis_cell(py, nd.R, iy, fy);
       axis_cell(pz, nd.R, iz, fz);
-      const unsigned R = (unsigned)nd.R;
-      const unsigned sx = F, sy = R * F, sz = R * R * F;
-      const unsigned base = (unsigned)iz * sz + (unsigned)iy * sy + (unsigned)ix * sx;
-      const float gx = 1.0f - fx, gy2 = 1.0f - fy, gz = 1.0f - fz;
-      const float w8[8] = {gx * gy2 * gz, fx * gy2 * gz, gx * fy * gz, fx * fy * gz,
-                           gx * gy2 * fz, fx * gy2 * fz, gx * fy * fz, fx * fy * fz};
-      const unsigned off[8] = {base, base + sx, base + sy, base + sx + sy,
-                               base + sz, base + sz + sx, base + sz + sy, base + sz + sx + sy};
-      float z[F];
+      const int cell = (iz * (nd.R - 1) + iy) * (nd.R - 1) + ix;
+      cell_out[idx] = cell;
+      atomicAdd(cell_count + cell, 1);
+      float4* dst = reinterpret_cast<float4*>(dz_out + idx * F);
 #pragma unroll
-      for (int f = 0; f < F; ++f) z[f] = zbuf[lane * TC::ZS + f];
-#pragma unroll
-      for (int cc = 0; cc < 8; ++cc)
-#pragma unroll
-        for (int f = 0; f < F; ++f) {
-          const float gz = w8[cc] * z[f];
-          if (nd.K > 1) {
-            // both keyframes around the point's time, with the blend weights
-            unsafeAtomicAdd(d_latent + (size_t)key * nd.key_stride + off[cc] + f, (1.0f - kw) * gz);
-            unsafeAtomicAdd(d_latent + (size_t)(key + 1) * nd.key_stride + off[cc] + f, kw * gz);
-          } else {
-            unsafeAtomicAdd(d_latent + off[cc] + f, gz);
-          }
-        }
+      for (int q = 0; q < F / 4; ++q)
+        dst[q] = make_float4(zbuf[lane * TC::ZS + 4 * q], zbuf[lane * TC::ZS + 4 * q + 1],
+                             zbuf[lane * TC::ZS + 4 * q + 2], zbuf[lane * TC::ZS + 4 * q + 3]);
     }
     first = false;
   }
@@ -533,6 +528,119 @@ __global__ void adam_kernel(float* p, const float* g, float* m, float* v, long l
   }
 }
 
+// ------------------------------------------ latent gradient by gathering
+
+constexpr int kScanThreads = 1024, kScanItems = 8;
+
+// Exclusive prefix sums of the per-cell point counts (one workgroup, eight
+// consecutive cells per thread and pass): off[c] = first sorted position of
+// cell c, off[ncell] = n; cursor gets a copy.
+__global__ __launch_bounds__(kScanThreads) void cell_scan_kernel(const int* count, int ncell, int* off, int* cursor) {
+  __shared__ int part[kScanThreads];
+  int carry = 0;
+  for (int c0 = 0; c0 < ncell; c0 += kScanThreads * kScanItems) {
+    const int base = c0 + threadIdx.x * kScanItems;
+    int x[kScanItems], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      x[k] = base + k < ncell ? count[base + k] : 0;
+      sum += x[k];
+    }
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (int o = 1; o < kScanThreads; o <<= 1) {
+      const int y = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
+      __syncthreads();
+      part[threadIdx.x] += y;
+      __syncthreads();
+    }
+    int run = carry + part[threadIdx.x] - sum;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      if (base + k < ncell) {
+        off[base + k] = run;
+        cursor[base + k] = run;
+      }
+      run += x[k];
+    }
+    const int total = part[kScanThreads - 1];
+    __syncthreads();
+    carry += total;
+  }
+  if (threadIdx.x == 0) off[ncell] = carry;
+}
+
+// Counting sort: point i goes to a free slot of its cell.
+__global__ void bin_points_kernel(const int* cell, long long n, int* cursor, int* order) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    order[atomicAdd(cursor + cell[i], 1)] = (int)i;
+}
+
+// d_latent[k][v][f] = sum over the points p of the (up to) eight cells
+// around vertex v of w_v(p) * b_k(p) * dz[p][f]: w_v the trilinear weight of
+// v as a corner of p's cell, b_k the blend weight of keyframe k at p's time
+// (Sec. 8; 1 for one keyframe). Eight consecutive threads share a (keyframe,
+// vertex), one cell each, and add their sums with lane shuffles; every entry
+// is written.
+template <int F>
+__global__ void latent_grad_kernel(const float* xyz, const float* times, KeyTimes kt, int K, int R,
+                                   long long key_stride, const int* off, const int* order, const float* dz,
+                                   float* d_latent) {
+  const long long nv = (long long)R * R * R;
+  const long long total = nv * K * 8;  // a multiple of 8: a lane group is active or idle as a whole
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int b = (int)(t & 7);
+    const long long kv = t >> 3;
+    const int k = (int)(kv / nv);
+    const long long v = kv % nv;
+    const int vx = (int)(v % R), vy = (int)((v / R) % R), vz = (int)(v / ((long long)R * R));
+    const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
+    const int cx = vx - bx, cy = vy - by, cz = vz - bz;  // the cell with v as corner (bx, by, bz)
+    float acc[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) acc[f] = 0.0f;
+    if (cx >= 0 && cx <= R - 2 && cy >= 0 && cy <= R - 2 && cz >= 0 && cz <= R - 2) {
+      const int c = (cz * (R - 1) + cy) * (R - 1) + cx;
+      for (int s = off[c]; s < off[c + 1]; ++s) {
+        const int p = order[s];
+        int ix, iy, iz;
+        float fx, fy, fz;
+        axis_cell(xyz[3 * p], R, ix, fx);
+        axis_cell(xyz[3 * p + 1], R, iy, fy);
+        axis_cell(xyz[3 * p + 2], R, iz, fz);
+        float w = (bx ? fx : 1.0f - fx) * (by ? fy : 1.0f - fy) * (bz ? fz : 1.0f - fz);
+        if (K > 1) {
+          int key;
+          float kw;
+          key_pair(kt, K, times ? times[p] : 0.0f, key, kw);
+          w *= (k == key ? 1.0f - kw : 0.0f) + (k == key + 1 ? kw : 0.0f);
+        }
+        const float4* src = reinterpret_cast<const float4*>(dz + (long long)p * F);
+#pragma unroll
+        for (int q = 0; q < F / 4; ++q) {
+          const float4 d4 = src[q];
+          acc[4 * q] = fmaf(w, d4.x, acc[4 * q]);
+          acc[4 * q + 1] = fmaf(w, d4.y, acc[4 * q + 1]);
+          acc[4 * q + 2] = fmaf(w, d4.z, acc[4 * q + 2]);
+          acc[4 * q + 3] = fmaf(w, d4.w, acc[4 * q + 3]);
+        }
+      }
+    }
+    // sum over the eight cells (fixed order: pairs, then quads, then the group)
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1)
+#pragma unroll
+      for (int f = 0; f < F; ++f) acc[f] += __shfl_xor(acc[f], o, 64);
+    if (b == 0) {
+      float4* dst = reinterpret_cast<float4*>(d_latent + (long long)k * key_stride + v * F);
+#pragma unroll
+      for (int q = 0; q < F / 4; ++q) dst[q] = make_float4(acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]);
+    }
+  }
+}
+
 template <int C, int F, int L, int ACT, int TE = 0, int FM = 0>
 struct TrainEntry {
   using TC = TrainCfg<C, F, L, ACT, TE, FM>;
@@ -546,9 +654,15 @@ struct TrainEntry {
     return (int)(c < kTrainMaxWaves ? (c < 1 ? 1 : c) : kTrainMaxWaves);
   }
   static int n_groups(long long n) { return (n_waves(n) + kGroup - 1) / kGroup; }
-  // wave slices, then the group partials of the reduction
+  // wave slices, then the group partials of the reduction, then the per-point
+  // dL/dz [n][F], cells [n] and sorted order [n], and per cell the point
+  // counts, the offsets (+1) and the sort cursors
+  static size_t slices_bytes(const NetDev& nd, long long n) {
+    return ((size_t)(n_waves(n) + n_groups(n)) * TC::slice(nd.H) * sizeof(float) + 15) / 16 * 16;
+  }
   static size_t ws_bytes(const NetDev& nd, long long n) {
-    return (size_t)(n_waves(n) + n_groups(n)) * TC::slice(nd.H) * sizeof(float);
+    const long long ncell = (long long)(nd.R - 1) * (nd.R - 1) * (nd.R - 1);
+    return slices_bytes(nd, n) + (size_t)n * F * 4 + (size_t)n * 8 + (size_t)(3 * ncell + 1) * 4;
   }
   static int run(const NetDev& nd, const KeyTimes& kt, float* latent, float* d_latent, float* d_weights,
                  const float* xyz, const float* times, long long n, const float* target,
@@ -557,9 +671,16 @@ struct TrainEntry {
     const int H = nd.H;
     const int wpb = waves_per_block(H);
     if (wpb < 1) return 1;
-    const long long nlat = (long long)nd.K * nd.R * nd.R * nd.R * nd.F;
-    hipLaunchKernelGGL(fill_kernel, dim3(grid_blocks(nlat, 256, device_cus() * 8)), dim3(256), 0, st, d_latent,
-                       nlat, 0.0f);
+    const int ncell = (nd.R - 1) * (nd.R - 1) * (nd.R - 1);
+    char* wsb = (char*)ws + slices_bytes(nd, n);
+    float* dz = (float*)wsb;
+    int* cell = (int*)(wsb + (size_t)n * F * 4);
+    int* order = cell + n;
+    int* count = order + n;
+    int* off = count + ncell;
+    int* cursor = off + ncell + 1;
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_blocks(ncell, 256, device_cus() * 8)), dim3(256), 0, st, (float*)count,
+                       (long long)ncell, 0.0f);  // zero bits: zero counts
     int rc = check_launch();
     if (rc) return rc;
     const int nw = n_waves(n);
@@ -575,8 +696,8 @@ struct TrainEntry {
     nd2.grid_f16 = 0;
     if (n > 0) {
       hipLaunchKernelGGL((fwd_bwd_kernel<C, F, L, ACT, TE, FM>), dim3((nw + wpb - 1) / wpb), dim3(wpb * 64), shm, st, nd2,
-                         kt, xyz, times, n, target, target_grad, grad_weight / 3.0f, dloss, d_latent, (float*)ws, nw,
-                         1.0f / (float)n);
+                         kt, xyz, times, n, target, target_grad, grad_weight / 3.0f, dloss, dz, cell, count, (float*)ws,
+                         nw, 1.0f / (float)n);
       rc = check_launch();
       if (rc) return rc;
     } else {
@@ -586,6 +707,19 @@ struct TrainEntry {
       rc = check_launch();
       if (rc) return rc;
     }
+    // latent gradient: sort the points by cell, then gather per vertex
+    hipLaunchKernelGGL(cell_scan_kernel, dim3(1), dim3(kScanThreads), 0, st, (const int*)count, ncell, off, cursor);
+    if ((rc = check_launch())) return rc;
+    if (n > 0) {
+      hipLaunchKernelGGL(bin_points_kernel, dim3(grid_blocks(n, 256, device_cus() * 8)), dim3(256), 0, st,
+                         (const int*)cell, n, cursor, order);
+      if ((rc = check_launch())) return rc;
+    }
+    const long long nthreads = (long long)nd.K * nd.R * nd.R * nd.R * 8;
+    hipLaunchKernelGGL((latent_grad_kernel<F>), dim3(grid_blocks(nthreads, 256, device_cus() * 32)), dim3(256), 0, st,
+                       xyz, times, kt, nd.K, nd.R, nd.key_stride, (const int*)off, (const int*)order, (const float*)dz,
+                       d_latent);
+    if ((rc = check_launch())) return rc;
     const int sl = TC::slice(H), ng = n_groups(n);
     float* partial = (float*)ws + (size_t)nw * sl;
     hipLaunchKernelGGL(slice_sum_kernel, dim3((sl + 255) / 256, ng), dim3(256), 0, st, (const float*)ws, nw, sl,
