@@ -228,6 +228,40 @@ def test_study_full_size_sampled_pixels(FV):
     assert err <= FP16_TOL
 
 
+@pytest.mark.parametrize("grad_mode", [0, 3], ids=["forward", "adjoint"])
+def test_shaded_full_size_sampled_pixels(FV, grad_mode):
+    """The shaded workload at its full size: the 64^3 x 16, 4 x 48 network on
+    a 1920 x 1080 view with Phong shading at step 1/512, FP16 MFMA on the
+    FP16 grid, gradients by forward mode or the adjoint, against the oracle
+    on sampled pixels."""
+    gnet, onet = _nets(FV, I.NET_SHADED, I.SEED_SHADED, grid_dtype=1)
+    tf = I.ramp_tf()
+    cams = [I.shaded_camera()]
+    m = dataclasses.replace(I.shaded_march(1e-3), grad_mode=grad_mode)
+    pix = np.random.default_rng(5).choice(1920 * 1080, 96, replace=False)
+    ref, _ = O.render(O.Field(net=onet), tf, cams, m, pixels=pix)
+    img = FV.fvsrn_render(gnet, tf, cams, m, "f16").cpu().numpy().reshape(-1, 4)
+    err = np.abs(img[pix] - ref.reshape(-1, 4)[pix]).max()
+    _report("shaded full-size f16 grad_mode %d sampled" % grad_mode, err)
+    assert err <= FP16_TOL
+
+
+def test_time_varying_full_size_sampled_pixels(FV):
+    """The time-varying workload at its full size: four 32^3 x 16 FP16
+    keyframe grids, 8 views of 1024^2 at fractional times in one launch, FP16
+    MFMA, against the oracle on sampled pixels."""
+    gnet, onet = _nets(FV, I.NET_TIME, I.SEED_TIME, key_times=I.TIME_KEYS, grid_dtype=1)
+    tf = I.ramp_tf()
+    cams = I.time_cameras(1024, 1024)
+    m = I.study_march(1e-3)
+    pix = np.random.default_rng(6).choice(8 * 1024 * 1024, 160, replace=False)
+    ref, _ = O.render(O.Field(net=onet), tf, cams, m, pixels=pix)
+    img = FV.fvsrn_render(gnet, tf, cams, m, "f16").cpu().numpy().reshape(-1, 4)
+    err = np.abs(img[pix] - ref.reshape(-1, 4)[pix]).max()
+    _report("time-varying full-size f16 sampled", err)
+    assert err <= FP16_TOL
+
+
 def test_c48_render(FV):
     spec = I.NetSpec(R=32, F=16, L=8, c=48, H=4)
     gnet, onet = _nets(FV, spec, 9)

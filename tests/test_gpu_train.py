@@ -378,3 +378,39 @@ def test_trainer_adaptive_resampling(FV):
     print("adaptive resampling: mean E at sampled positions %.4g vs grid mean %.4g" % (ev.mean(), E.mean()),
           flush=True)
     assert ev.mean() > 1.5 * E.mean()
+
+
+def test_train_gradients_against_central_differences(FV):
+    """The training gradient of the small network against central finite
+    differences (h = 1e-3) of the GPU's own FP32 densities on 64 points: for
+    the VJP loss sum_i u_i d(x_i), the derivative with respect to weights of
+    every layer and to latent entries of the cells the points touch."""
+    spec = I.NET_SMALL
+    lat, w = I.net_params(spec, 31)
+    n = 64
+    xyz = torch.from_numpy(I.uniform_points(n, 32, -0.9, 0.9)).cuda()
+    u = torch.from_numpy(np.random.default_rng(4).normal(size=n).astype(np.float32)).cuda()
+    net = FV.Network(spec, lat, w)
+    d_lat, d_w = torch.empty_like(net.latent), torch.empty_like(net.weights)
+    FV.fvsrn_train_step(net, d_lat, d_w, xyz, dloss_dy=u)
+    h = 1e-3
+
+    def loss(latent, weights):
+        m = FV.Network(spec, latent, weights)
+        return float(torch.sum(u.double() * FV.fvsrn_eval_points(m, xyz, 0.0, "f32").double()).item())
+
+    K0 = spec.K0
+    wi = [0, 5 * K0 + 7, 32 * K0 + 3, 32 * K0 + 32 + 100, spec.n_weights - 33, spec.n_weights - 1]
+    for j in wi:
+        wp, wm = w.copy(), w.copy()
+        wp[j] += h
+        wm[j] -= h
+        fd = (loss(lat, wp) - loss(lat, wm)) / (2 * h)
+        assert abs(fd - d_w[j].item()) <= 2e-3 * max(1.0, abs(fd)), (j, fd, d_w[j].item())
+    g = d_lat.cpu().numpy()
+    for j in np.argsort(-np.abs(g))[:6]:
+        lp, lm = lat.reshape(-1).copy(), lat.reshape(-1).copy()
+        lp[j] += h
+        lm[j] -= h
+        fd = (loss(lp, w) - loss(lm, w)) / (2 * h)
+        assert abs(fd - g[j]) <= 2e-3 * max(1.0, abs(fd)), (j, fd, g[j])
