@@ -421,16 +421,22 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
 // (partial[g][e], threads along e), gather_kernel then locates every weight's
 // terms in the slice layout and adds them over the groups. Both orders are
 // fixed, so the result is bitwise reproducible.
-constexpr int kGroup = 32;
+constexpr int kGroup = 256;
 
 __global__ void slice_sum_kernel(const float* ws, int n_waves, int sl, float* partial) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   const int g = blockIdx.y;
   if (e >= sl) return;
   const int w0 = g * kGroup, w1 = min(w0 + kGroup, n_waves);
-  float s = 0.0f;
-  for (int w = w0; w < w1; ++w) s += ws[(size_t)w * sl + e];
-  partial[(size_t)g * sl + e] = s;
+  // eight independent partial sums keep eight loads in flight; they are
+  // combined in a fixed order
+  float s8[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  int w = w0;
+  for (; w + 8 <= w1; w += 8)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s8[k] += ws[(size_t)(w + k) * sl + e];
+  for (; w < w1; ++w) s8[0] += ws[(size_t)w * sl + e];
+  partial[(size_t)g * sl + e] = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
 }
 
 template <int C, int F, int L, int ACT, int TE, int FM>
@@ -580,19 +586,23 @@ __global__ void bin_points_kernel(const int* cell, long long n, int* cursor, int
 // d_latent[k][v][f] = sum over the points p of the (up to) eight cells
 // around vertex v of w_v(p) * b_k(p) * dz[p][f]: w_v the trilinear weight of
 // v as a corner of p's cell, b_k the blend weight of keyframe k at p's time
-// (Sec. 8; 1 for one keyframe). Eight consecutive threads share a (keyframe,
-// vertex), one cell each, and add their sums with lane shuffles; every entry
-// is written.
+// (Sec. 8; 1 for one keyframe). A group of 8 lpc consecutive threads shares a
+// (keyframe, vertex): lpc threads per cell, each taking every lpc-th point
+// of it (lpc = 1..8, a power of two, from the mean points per cell), and the
+// group adds its sums with lane shuffles in a fixed order; every entry is
+// written.
 template <int F>
 __global__ void latent_grad_kernel(const float* xyz, const float* times, KeyTimes kt, int K, int R,
                                    long long key_stride, const int* off, const int* order, const float* dz,
-                                   float* d_latent) {
+                                   float* d_latent, int lpc_log2) {
   const long long nv = (long long)R * R * R;
-  const long long total = nv * K * 8;  // a multiple of 8: a lane group is active or idle as a whole
+  const int lpc = 1 << lpc_log2, gsz = 8 << lpc_log2;
+  const long long total = nv * K * gsz;  // a multiple of the group size: groups are active or idle as a whole
   for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (long long)gridDim.x * blockDim.x) {
-    const int b = (int)(t & 7);
-    const long long kv = t >> 3;
+    const int lig = (int)(t & (gsz - 1));
+    const int b = lig >> lpc_log2, sub = lig & (lpc - 1);
+    const long long kv = t >> (3 + lpc_log2);
     const int k = (int)(kv / nv);
     const long long v = kv % nv;
     const int vx = (int)(v % R), vy = (int)((v / R) % R), vz = (int)(v / ((long long)R * R));
@@ -603,7 +613,7 @@ __global__ void latent_grad_kernel(const float* xyz, const float* times, KeyTime
     for (int f = 0; f < F; ++f) acc[f] = 0.0f;
     if (cx >= 0 && cx <= R - 2 && cy >= 0 && cy <= R - 2 && cz >= 0 && cz <= R - 2) {
       const int c = (cz * (R - 1) + cy) * (R - 1) + cx;
-      for (int s = off[c]; s < off[c + 1]; ++s) {
+      for (int s = off[c] + sub; s < off[c + 1]; s += lpc) {
         const int p = order[s];
         int ix, iy, iz;
         float fx, fy, fz;
@@ -628,12 +638,11 @@ __global__ void latent_grad_kernel(const float* xyz, const float* times, KeyTime
         }
       }
     }
-    // sum over the eight cells (fixed order: pairs, then quads, then the group)
-#pragma unroll
-    for (int o = 1; o < 8; o <<= 1)
+    // sum over the group (fixed order: pairs, then quads, ...)
+    for (int o = 1; o < gsz; o <<= 1)
 #pragma unroll
       for (int f = 0; f < F; ++f) acc[f] += __shfl_xor(acc[f], o, 64);
-    if (b == 0) {
+    if (lig == 0) {
       float4* dst = reinterpret_cast<float4*>(d_latent + (long long)k * key_stride + v * F);
 #pragma unroll
       for (int q = 0; q < F / 4; ++q) dst[q] = make_float4(acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]);
@@ -715,10 +724,13 @@ struct TrainEntry {
                          (const int*)cell, n, cursor, order);
       if ((rc = check_launch())) return rc;
     }
-    const long long nthreads = (long long)nd.K * nd.R * nd.R * nd.R * 8;
+    // lanes per cell: about one per four points of an average cell, at most 8
+    int lpc_log2 = 0;
+    while (lpc_log2 < 3 && (4LL << lpc_log2) * ncell < n) ++lpc_log2;
+    const long long nthreads = (long long)nd.K * nd.R * nd.R * nd.R * (8 << lpc_log2);
     hipLaunchKernelGGL((latent_grad_kernel<F>), dim3(grid_blocks(nthreads, 256, device_cus() * 32)), dim3(256), 0, st,
                        xyz, times, kt, nd.K, nd.R, nd.key_stride, (const int*)off, (const int*)order, (const float*)dz,
-                       d_latent);
+                       d_latent, lpc_log2);
     if ((rc = check_launch())) return rc;
     const int sl = TC::slice(H), ng = n_groups(n);
     float* partial = (float*)ws + (size_t)nw * sl;
