@@ -463,6 +463,67 @@ def main():
                             "train_ms_per_step": t_r / rsteps * 1e3}
                 del rtr, rnet, r16
             comp["adaptive_resampling"] = {"train": "%d steps of 2^18 points, error grid 128^3 x 8" % rsteps, **ar}
+        # the training workload: the small network (16^3 x 8 grid, 3 x 32)
+        # fitted to the 256^3 power-law field, 2000 Adam steps of 2^18 points
+        if args.train_steps > 0:
+            progress("training workload")
+            pvol = I.power_law_volume_torch(256, 512, seed=I.SEED_TRAIN, device=dev)
+            slat, sw = I.net_params(I.NET_SMALL, I.SEED_SMALL)
+            snet = FV.Network(I.NET_SMALL, slat, sw, grid_dtype=FV.F32, device=dev)
+            xs = FV.fvsrn_sample_points(I.SEED_TRAIN, 1 << 42, 1 << 18, device=dev)
+            ps = FV.fvsrn_dense_eval_points(pvol, xs)
+            l1_0 = torch.mean(torch.abs(FV.fvsrn_eval_points(snet, xs, 0.0, "f32") - ps)).item()
+            str_ = Trainer(snet, pvol, batch=1 << 18, seed=I.SEED_TRAIN)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.train_steps):
+                str_.step()
+            torch.cuda.synchronize()
+            t_s = time.perf_counter() - t0
+            l1_1 = torch.mean(torch.abs(FV.fvsrn_eval_points(snet, xs, 0.0, "f32") - ps)).item()
+            comp["training_small_power_law"] = {"steps": args.train_steps, "batch": 1 << 18,
+                                                "ms_per_step": t_s / args.train_steps * 1e3,
+                                                "l1_untrained": l1_0, "l1_trained": l1_1}
+            del pvol, str_, snet
+            # the shaded workload: the 64^3 x 16, 4 x 48 network fitted to the
+            # 512^3 Marschner-Lobb field, one 1920 x 1080 view at step 1/512
+            # with Phong shading, FP16 MFMA; gradients by forward mode (the
+            # configured strategy) and by the adjoint; dense DVR of the 512^3
+            # field with one-voxel central differences as the judge
+            progress("shaded workload")
+            mvol = torch.from_numpy(I.marschner_lobb_volume(512)).to(dev)
+            mlat, mw = I.net_params(I.NET_SHADED, I.SEED_SHADED)
+            mnet32 = FV.Network(I.NET_SHADED, mlat, mw, grid_dtype=FV.F32, device=dev)
+            mtr = Trainer(mnet32, mvol, batch=1 << 18, seed=I.SEED_SHADED)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.train_steps):
+                mtr.step()
+            torch.cuda.synchronize()
+            t_m = time.perf_counter() - t0
+            mnet = FV.Network(I.NET_SHADED, mnet32.latent.cpu().numpy(), mnet32.weights.cpu().numpy(),
+                              grid_dtype=FV.F16, device=dev)
+            scam = [I.shaded_camera()]
+            smarch = I.shaded_march(1e-3)
+            sout = torch.empty((1, 1080, 1920, 4), dtype=torch.float32, device=dev)
+            sref = torch.empty_like(sout)
+            FV.fvsrn_render_dense(mvol, tf, scam, smarch, out=sref)
+            per_d, _ = time_launches(lambda: FV.fvsrn_render_dense(mvol, tf, scam, smarch, out=sref), 3, 1)
+            shaded = {"training": {"steps": args.train_steps, "ms_per_step": t_m / args.train_steps * 1e3,
+                                   "final_l1": float(mtr.loss.item())},
+                      "dense_dvr_512_ms_per_frame": float(np.mean(per_d))}
+            for name, gm in (("forward", 0), ("adjoint", 3)):
+                mm = dataclasses.replace(smarch, grad_mode=gm)
+                FV.fvsrn_render(mnet, tf, scam, mm, "f16", out=sout, stats=stats.zero_())
+                torch.cuda.synchronize()
+                ns = int(stats[0].item())
+                per_c, _ = time_launches(lambda: FV.fvsrn_render(mnet, tf, scam, mm, "f16", out=sout), 3, 1)
+                ms = float(np.mean(per_c))
+                shaded[name] = {"ms_per_frame": ms, "samples_per_s": ns / (ms * 1e-3),
+                                "image_rmse_vs_dense": float(torch.sqrt(torch.mean((sout - sref) ** 2)).item()),
+                                "image_ssim_vs_dense": FV.fvsrn_ssim(sout, sref)}
+            comp["shaded_1920x1080_marschner_lobb"] = shaded
+            del mvol, mtr, mnet32, mnet, sout, sref
         # fused point evaluation vs the framework-style layer-by-layer network (2^24 points)
         npts = 1 << 24
         xyz = torch.rand((npts, 3), device=dev) * 2 - 1

@@ -246,6 +246,33 @@ def power_law_volume(D: int = 256, n_modes: int = 512, seed: int = 1003,
     return vol
 
 
+def power_law_volume_torch(D: int = 256, n_modes: int = 512, seed: int = 1003, kmin: float = math.pi,
+                           kmax: float = 64 * math.pi, device="cuda"):
+    """``power_law_volume`` (the same modes, drawn in the same order)
+    evaluated with torch in FP64 on ``device``; FP32 [D][D][D]."""
+    import torch
+    rng = np.random.default_rng(seed)
+    dirs = rng.normal(size=(n_modes, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    kmag = np.exp(rng.uniform(math.log(kmin), math.log(kmax), size=n_modes))
+    kv = torch.as_tensor(dirs * kmag[:, None], dtype=torch.float64, device=device)
+    amp = torch.as_tensor(kmag ** (-1.0 / 3.0), dtype=torch.float64, device=device)
+    phase = torch.as_tensor(rng.uniform(0.0, 2.0 * math.pi, size=n_modes), dtype=torch.float64, device=device)
+    ax = torch.as_tensor(_axis(D).astype(np.float32), dtype=torch.float64, device=device)
+    Y, X = torch.meshgrid(ax, ax, indexing="ij")
+    vol = torch.empty((D, D, D), dtype=torch.float64, device=device)
+    for z in range(D):
+        acc = torch.zeros((D, D), dtype=torch.float64, device=device)
+        for j0 in range(0, n_modes, 64):
+            kk = kv[j0:j0 + 64]
+            arg = X[..., None] * kk[:, 0] + Y[..., None] * kk[:, 1] + ax[z] * kk[:, 2] + phase[j0:j0 + 64]
+            acc += (torch.cos(arg) * amp[j0:j0 + 64]).sum(-1)
+        vol[z] = acc
+    vol -= vol.min()
+    vol /= vol.max()
+    return vol.float().contiguous()
+
+
 def marschner_lobb_volume(D: int, fm: float = 6.0, alpha: float = 0.25) -> np.ndarray:
     """Marschner-Lobb test signal sampled at the D^3 vertices of [-1,1]^3.
     float32 [D][D][D] in [0, 1]."""
