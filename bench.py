@@ -249,7 +249,7 @@ def main():
     progress("comparisons")
     if not args.no_compare:
         comp = {}
-        # dense-grid DVR of the original 256^3 volume: the judge of image quality
+        # dense-grid DVR of the original 256^3 volume: the reference for image quality
         ref = torch.empty_like(out)
 
         def dense():
@@ -340,7 +340,7 @@ def main():
         progress("time-varying workload")
         # time-varying workload (Sec. 8): keyframe latent grids every 4 timesteps
         # trained on all 16 timesteps of the 256^3 advected-blob field, then 8
-        # views at fractional times in one launch; judged against dense DVR of
+        # views at fractional times in one launch; compared with dense DVR of
         # the field at each view's time
         if args.train_steps > 0:
             from paper_2112_01579_amd.trainer import Trainer
@@ -381,7 +381,7 @@ def main():
                              "ms_per_step": t_train / tsteps * 1e3}}
             # time encodings (Sec. 8): the same keyframe network with no time
             # input, the normalised time as an input, its Fourier features, or
-            # both, trained on the even timesteps only and judged on the odd
+            # both, trained on the even timesteps only and evaluated on the odd
             # ones it never saw (mean |density error| over 2^18 points each)
             enc = {}
             train_frames = [f for f in frames if int(f[0]) % 2 == 0]
@@ -407,7 +407,7 @@ def main():
                              "render_ms_per_frame_f16": float(np.mean(per_c)) / len(tcams)}
                 del etr, enet, e16
             comp["time_encodings"] = {"train": "even timesteps 0..14, %d steps of 2^18 points" % esteps,
-                                      "judge": "odd timesteps 1..15", **enc}
+                                      "evaluated_on": "odd timesteps 1..15", **enc}
             del frames, ttr, tnet32
         progress("Fourier features")
         # Fourier features (Sec. 3, Sec. 5.3): the octave construction against
@@ -489,7 +489,7 @@ def main():
             # 512^3 Marschner-Lobb field, one 1920 x 1080 view at step 1/512
             # with Phong shading, FP16 MFMA; gradients by forward mode (the
             # configured strategy) and by the adjoint; dense DVR of the 512^3
-            # field with one-voxel central differences as the judge
+            # field with one-voxel central differences as the image reference
             progress("shaded workload")
             mvol = torch.from_numpy(I.marschner_lobb_volume(512)).to(dev)
             mlat, mw = I.net_params(I.NET_SHADED, I.SEED_SHADED)

@@ -10,7 +10,7 @@
  * All arrays are host memory, FP64, owned by the caller. Functions return 0 on
  * success and a negative value on an argument error.
  *
- * Conventions (readings of the paper, listed in the design doc):
+ * Conventions (readings of the paper where it is silent or ambiguous):
  *  - Domain [-1,1]^3. Latent grid: R vertices per axis, vertex i at
  *    -1 + 2i/(R-1) (Sec. 4.2 defines R as vertices per axis). Layout
  *    [K][z][y][x][F], channel fastest.

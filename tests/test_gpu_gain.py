@@ -1,7 +1,7 @@
 """What the learned part gains (Sec. 5.2): an fV-SRN trained on the GPU by the
 library's own kernels against (i) the same model untrained and (ii) a dense
 grid of the same memory, low-pass filtered and downsampled from the original
-(the paper's "off" control). Judge: dense-grid DVR of the original volume
+(the paper's "off" control). Reference: dense-grid DVR of the original volume
 (image RMSE) and point samples of it (density RMSE). (i) is asserted; (ii)
 is the paper's qualitative claim and is reported."""
 import math
