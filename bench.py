@@ -524,6 +524,28 @@ def main():
                                 "image_ssim_vs_dense": FV.fvsrn_ssim(sout, sref)}
             comp["shaded_1920x1080_marschner_lobb"] = shaded
             del mvol, mtr, mnet32, mnet, sout, sref
+        # where the MFMA ceiling lies: the same render with networks of more
+        # matrix work per activation (c = 48) and without transcendental
+        # activations (identity), random weights, the same cameras and grid
+        progress("MFMA fraction by network")
+        mf = {}
+        for name, sp in (("c32_sine", spec), ("c48_sine", dataclasses.replace(spec, c=48)),
+                         ("c32_identity", dataclasses.replace(spec, act="identity")),
+                         ("c48_identity", dataclasses.replace(spec, c=48, act="identity"))):
+            qlat, qw = I.net_params(sp, I.SEED_STUDY)
+            if sp.act == "identity":
+                qw = qw * 0.5   # keep the linear network's densities away from saturation
+            qnet = FV.Network(sp, qlat, qw, grid_dtype=FV.F16, device=dev)
+            stats.zero_()
+            FV.fvsrn_render(qnet, tf, cams, march, "f16", out=out, stats=stats)
+            torch.cuda.synchronize()
+            qs = int(stats[0].item())
+            per_c, _ = time_launches(lambda: FV.fvsrn_render(qnet, tf, cams, march, "f16", out=out), 3, 1)
+            ms = float(np.mean(per_c))
+            tfl = qs * flops_per_sample(sp) / (ms * 1e-3) / 1e12
+            mf[name] = {"samples_per_s": qs / (ms * 1e-3), "tflops": tfl, "frac_of_fp16_peak": tfl / P16_TFLOPS}
+            del qnet
+        comp["mfma_fraction_by_network"] = mf
         # fused point evaluation vs the framework-style layer-by-layer network (2^24 points)
         npts = 1 << 24
         xyz = torch.rand((npts, 3), device=dev) * 2 - 1
