@@ -16,6 +16,7 @@ import pytest
 import torch
 
 import oracle as O
+from philox_ref import philox4x32_10
 from paper_2112_01579_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -336,32 +337,13 @@ def test_dense_render_and_points(FV):
 
 # ------------------------------------------------------------ utilities
 
-def _philox4x32_10(ctr, key):
-    """Philox4x32-10 (Salmon et al., SC'11) in numpy uint64 arithmetic."""
-    M0, M1 = np.uint64(0xD2511F53), np.uint64(0xCD9E8D57)
-    W0, W1 = np.uint64(0x9E3779B9), np.uint64(0xBB67AE85)
-    mask = np.uint64(0xFFFFFFFF)
-    c = [x.astype(np.uint64) for x in ctr]
-    k0, k1 = np.uint64(key[0]), np.uint64(key[1])
-    for r in range(10):
-        if r:
-            k0 = (k0 + W0) & mask
-            k1 = (k1 + W1) & mask
-        p0 = M0 * c[0]
-        p1 = M1 * c[2]
-        hi0, lo0 = p0 >> np.uint64(32), p0 & mask
-        hi1, lo1 = p1 >> np.uint64(32), p1 & mask
-        c = [hi1 ^ c[1] ^ k0, lo1, hi0 ^ c[3] ^ k1, lo0]
-    return c
-
-
 def test_sample_points_bit_exact(FV):
     n, seed, counter = 100003, 0x123456789ABCDEF, 42
     xyz = FV.fvsrn_sample_points(seed, counter, n).cpu().numpy()
     i = np.arange(n, dtype=np.uint64)
     ctr = [i & np.uint64(0xFFFFFFFF), i >> np.uint64(32), np.full(n, counter, np.uint64),
            np.zeros(n, np.uint64)]
-    c = _philox4x32_10(ctr, (seed & 0xFFFFFFFF, seed >> 32))
+    c = philox4x32_10(ctr, (seed & 0xFFFFFFFF, seed >> 32))
     want = np.stack([-1.0 + (c[a] >> np.uint64(8)).astype(np.float64) * 2.0 ** -23 for a in range(3)], 1)
     assert np.array_equal(xyz.astype(np.float64), want)
     assert xyz.min() >= -1.0 and xyz.max() < 1.0
@@ -766,7 +748,7 @@ def _philox_words(n, seed, counter):
     i = np.arange(n, dtype=np.uint64)
     ctr = [i & np.uint64(0xFFFFFFFF), i >> np.uint64(32), np.full(n, counter & 0xFFFFFFFF, np.uint64),
            np.full(n, counter >> 32, np.uint64)]
-    c = _philox4x32_10(ctr, (seed & 0xFFFFFFFF, seed >> 32))
+    c = philox4x32_10(ctr, (seed & 0xFFFFFFFF, seed >> 32))
     return np.stack([x.astype(np.uint32) for x in c], 1)
 
 

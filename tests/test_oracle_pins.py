@@ -1064,3 +1064,26 @@ def test_weighted_points_follow_the_error_grid():
     rr = np.array([[0, 0, 0, 0], [2 ** 29, 0, 0, 0], [2 ** 32 - 1, 0, 0, 0]], np.uint32)
     p = O.weighted_points(E, G, rr)
     np.testing.assert_array_equal(p, [[-1, -1, -1], [0, -1, -1], [0, 0, 0]])
+
+
+# ------------------------------------------- counter-based generator pin
+
+def test_philox_known_answer_vectors():
+    """The numpy Philox4x32-10 that draws the oracle's random words (and that
+    the library's generator is checked against bit for bit) reproduces the
+    known-answer vectors published with the generator (Salmon et al., SC'11,
+    Random123 distribution): all-zero input, all-ones input, and the digits
+    of pi as counter and key."""
+    from philox_ref import philox4x32_10
+    cases = [((0, 0, 0, 0), (0, 0), (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
+             ((0xFFFFFFFF,) * 4, (0xFFFFFFFF,) * 2, (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
+             ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0),
+              (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1))]
+    for ctr, key, want in cases:
+        got = philox4x32_10([np.array([x], np.uint64) for x in ctr], key)
+        assert tuple(int(g[0]) for g in got) == want
+    # and its words are uniform: each of the 32 bits is set half the time
+    i = np.arange(1 << 16, dtype=np.uint64)
+    c = philox4x32_10([i, np.zeros_like(i), np.full_like(i, 7), np.zeros_like(i)], (1, 2))
+    bits = np.stack([(c[0] >> np.uint64(b)) & np.uint64(1) for b in range(32)]).astype(np.float64)
+    assert np.all(np.abs(bits.mean(axis=1) - 0.5) < 0.01)
