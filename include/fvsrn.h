@@ -189,8 +189,10 @@ typedef struct {
    differences. Phong shading needs the density gradient, obtained as
    march->grad_mode selects (Sec. 6). Forward mode, central differences and
    the adjoint are built for FP32/FP16 networks (central differences,
-   predicted gradients and the adjoint for the sine activation only, the
-   adjoint for H <= 4); other combinations return FVSRN_ERR_UNSUPPORTED.
+   predicted gradients and the adjoint for the sine activation only; the
+   adjoint of an FP32 network whose weight fragments, forward and transposed,
+   exceed the 160 KiB of LDS -- c = 48 with H = 8, or with F = 16 and H >= 7 --
+   is not available); other combinations return FVSRN_ERR_UNSUPPORTED.
    Predicted gradients need num_outputs == 4. */
 fvsrn_status fvsrn_render(const fvsrn_net_desc* desc, const fvsrn_params* params,
                           const fvsrn_tf* tf, const fvsrn_camera* cams, int32_t n_views,

@@ -1,7 +1,8 @@
 // Adjoint (reverse-mode) gradient shading and point gradients (Sec. 6),
 // compiled once per precision with FVSRN_PREC = 0 FP32 or 1 FP16. The layer
 // count is a template parameter (the saved activation derivatives are
-// registers), instantiated for H = 1..4 and the sine activation.
+// registers), instantiated for H = 1..8 and the sine activation; above four
+// layers the first ones are evaluated twice (see mlp_tile_adj).
 #include "fvsrn_march.hpp"
 
 #ifndef FVSRN_PREC
@@ -12,7 +13,7 @@ namespace fvsrn_detail {
 
 namespace {
 
-constexpr int kAdjMaxLayers = 4;
+constexpr int kAdjMaxLayers = 8;
 
 template <int C, int F, int L, int GK, int HH>
 struct AdjEntry {
@@ -27,7 +28,9 @@ struct AdjEntry {
   }
 };
 
-#define FV_ADJ_H(X, C, F, L, GK) X(C, F, L, GK, 1) X(C, F, L, GK, 2) X(C, F, L, GK, 3) X(C, F, L, GK, 4)
+#define FV_ADJ_H(X, C, F, L, GK)                                                             \
+  X(C, F, L, GK, 1) X(C, F, L, GK, 2) X(C, F, L, GK, 3) X(C, F, L, GK, 4) X(C, F, L, GK, 5) \
+  X(C, F, L, GK, 6) X(C, F, L, GK, 7) X(C, F, L, GK, 8)
 #if FVSRN_PREC == 1
 #define FV_ADJ_G(X, C, F, L) FV_ADJ_H(X, C, F, L, 0) FV_ADJ_H(X, C, F, L, 1) FV_ADJ_H(X, C, F, L, 2)
 #else

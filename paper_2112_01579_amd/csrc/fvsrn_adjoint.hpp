@@ -104,10 +104,18 @@ __device__ void stage_backward_adj(const NetDev& nd, char* p) {
   for (int e = tid; e < C; e += nt) WO[e] = Wo[e];  // output 0: the density logit
 }
 
+// Layers whose activation derivatives the first forward pass of the adjoint
+// keeps in registers. A deeper network's first H - kAdjKeep layers are run a
+// second time, from the input rows, once the backward pass has reached them.
+constexpr int kAdjKeep = 4;
+
 // Forward and adjoint pass of the wave's 64 input rows through a network of
 // HH activated layers (wsm: forward fragments, bsm: stage_backward_adj). On
 // return the 64 rows of `feat` hold dy/d(input row) in the input-row column
 // order (y: output 0, the logit), and the lane's own logit is returned.
+// With HH > kAdjKeep the first pass keeps the derivatives of the last
+// kAdjKeep layers only; after the backward pass through them, a second
+// forward pass over the first S = HH - kAdjKeep layers supplies theirs.
 template <class CF, int HH>
 __device__ __attribute__((always_inline)) inline float mlp_tile_adj(const char* wsm, const char* bsm,
                                                                   typename CF::E* feat) {
@@ -117,6 +125,7 @@ __device__ __attribute__((always_inline)) inline float mlp_tile_adj(const char* 
   // N-tiles per pass: two interleaved chains, one for the FP32 c = 48
   // network (whose saved derivatives would not fit the registers twice)
   constexpr int MT = G::MT, MB0 = G::MB0, NT = (CF::P == kF32 && CF::C == 48) ? 1 : 2, ACT = CF::ACT;
+  constexpr int S = HH > kAdjKeep ? HH - kAdjKeep : 0, HD = HH - S;
   const int lane = threadIdx.x & 63;
   const int g = lane >> 4, n = lane & 15;
   const LaneRole role = value_role();
@@ -132,73 +141,47 @@ __device__ __attribute__((always_inline)) inline float mlp_tile_adj(const char* 
     const float* W0 = reinterpret_cast<const float*>(wsm);
     for (int tp = 0; tp < 4; tp += NT) {
       f4 acc[NT][MT];
-#pragma unroll
-      for (int u = 0; u < NT; ++u)
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) acc[u][mt] = zero;
-#pragma unroll
-      for (int q = 0; q < G::Q0; ++q) {
-        float b[NT];
-#pragma unroll
-        for (int u = 0; u < NT; ++u) b[u] = feat[(16 * (tp + u) + n) * G::ROW + g * G::Q0 + q];
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          const float a = W0[(mt * G::Q0 + q) * kWave + lane];
-#pragma unroll
-          for (int u = 0; u < NT; ++u) acc[u][mt] = PR::mma(a, b[u], acc[u][mt]);
-        }
-      }
-      // forward, keeping act' of every activated layer
-      f4 der[HH][NT][MT];
-      const char* p = wsm + G::W0A;
-#pragma unroll
-      for (int i = 0; i < HH; ++i) {
-        f4 hb[NT][MT];
+      // layer 0 pre-activations of the pair's input rows
+      auto layer0 = [&]() __attribute__((always_inline)) {
 #pragma unroll
         for (int u = 0; u < NT; ++u)
 #pragma unroll
-          for (int mt = 0; mt < MT; ++mt)
+          for (int mt = 0; mt < MT; ++mt) acc[u][mt] = zero;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const float r = acc[u][mt][j];
-              hb[u][mt][j] = act_el<ACT, false>(r, role);
-              der[i][u][mt][j] = act_deriv<ACT>(r);
-            }
-        if (i + 1 < HH) {
-          const float* WH = reinterpret_cast<const float*>(p);
-          const float* BHp = reinterpret_cast<const float*>(p + G::WHA);
+        for (int q = 0; q < G::Q0; ++q) {
+          float b[NT];
+#pragma unroll
+          for (int u = 0; u < NT; ++u) b[u] = feat[(16 * (tp + u) + n) * G::ROW + g * G::Q0 + q];
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) {
-            const f4 bias = *reinterpret_cast<const f4*>(BHp + 16 * mt + 4 * g);
+            const float a = W0[(mt * G::Q0 + q) * kWave + lane];
 #pragma unroll
-            for (int u = 0; u < NT; ++u) acc[u][mt] = bias;
+            for (int u = 0; u < NT; ++u) acc[u][mt] = PR::mma(a, b[u], acc[u][mt]);
           }
-#pragma unroll
-          for (int q = 0; q < 4 * MT; ++q)
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-              const float a = WH[(mt * 4 * MT + q) * kWave + lane];
-#pragma unroll
-              for (int u = 0; u < NT; ++u) acc[u][mt] = PR::mma(a, hb[u][q / 4][q % 4], acc[u][mt]);
-            }
-          p += G::HID;
-        } else {
-          const float* WO = reinterpret_cast<const float*>(p);
-#pragma unroll
-          for (int q = 0; q < 4 * MT; ++q)
-#pragma unroll
-            for (int u = 0; u < NT; ++u)
-              out[u] = PR::mma(WO[((tp + u) * 4 * MT + q) * kWave + lane], hb[u][q / 4][q % 4], out[u]);
         }
-      }
-      // backward: e_i = dy/dh_{i+1} * act'(x_i), dy/dh_i = W_i^T e_i
+      };
+      // pre-activations of the hidden layer at p from the activations hb
+      auto hidden = [&](const char* p, const f4 (&hb)[NT][MT]) __attribute__((always_inline)) {
+        const float* WH = reinterpret_cast<const float*>(p);
+        const float* BHp = reinterpret_cast<const float*>(p + G::WHA);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const f4 bias = *reinterpret_cast<const f4*>(BHp + 16 * mt + 4 * g);
+#pragma unroll
+          for (int u = 0; u < NT; ++u) acc[u][mt] = bias;
+        }
+#pragma unroll
+        for (int q = 0; q < 4 * MT; ++q)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            const float a = WH[(mt * 4 * MT + q) * kWave + lane];
+#pragma unroll
+            for (int u = 0; u < NT; ++u) acc[u][mt] = PR::mma(a, hb[u][q / 4][q % 4], acc[u][mt]);
+          }
+      };
       f4 e[NT][MT];
-#pragma unroll
-      for (int u = 0; u < NT; ++u)
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) e[u][mt] = wo[mt] * der[HH - 1][u][mt];
-#pragma unroll
-      for (int i = HH - 1; i >= 1; --i) {
+      // e <- (W_i^T e) * act'(x_{i-1})
+      auto back = [&](int i, const f4 (&d)[NT][MT]) __attribute__((always_inline)) {
         const float* WB = reinterpret_cast<const float*>(bsm + (i - 1) * G::WBH);
         f4 nu[NT][MT];
 #pragma unroll
@@ -216,7 +199,72 @@ __device__ __attribute__((always_inline)) inline float mlp_tile_adj(const char* 
 #pragma unroll
         for (int u = 0; u < NT; ++u)
 #pragma unroll
-          for (int mt = 0; mt < MT; ++mt) e[u][mt] = nu[u][mt] * der[i - 1][u][mt];
+          for (int mt = 0; mt < MT; ++mt) e[u][mt] = nu[u][mt] * d[u][mt];
+      };
+      layer0();
+      // forward, keeping act' of the last HD activated layers
+      f4 der[HD][NT][MT];
+      const char* p = wsm + G::W0A;
+#pragma unroll
+      for (int i = 0; i < HH; ++i) {
+        f4 hb[NT][MT];
+#pragma unroll
+        for (int u = 0; u < NT; ++u)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const float r = acc[u][mt][j];
+              hb[u][mt][j] = act_el<ACT, false>(r, role);
+              if (i >= S) der[i - S][u][mt][j] = act_deriv<ACT>(r);
+            }
+        if (i + 1 < HH) {
+          hidden(p, hb);
+          p += G::HID;
+        } else {
+          const float* WO = reinterpret_cast<const float*>(p);
+#pragma unroll
+          for (int q = 0; q < 4 * MT; ++q)
+#pragma unroll
+            for (int u = 0; u < NT; ++u)
+              out[u] = PR::mma(WO[((tp + u) * 4 * MT + q) * kWave + lane], hb[u][q / 4][q % 4], out[u]);
+        }
+      }
+      // backward: e_i = dy/dh_{i+1} * act'(x_i), dy/dh_i = W_i^T e_i
+#pragma unroll
+      for (int u = 0; u < NT; ++u)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) e[u][mt] = wo[mt] * der[HD - 1][u][mt];
+#pragma unroll
+      for (int i = HH - 1; i > S; --i) back(i, der[i - 1 - S]);
+      if constexpr (S > 0) {
+        // second forward pass over the first S layers for their act'; the
+        // memory clobber makes it reload its operands, so the compiler
+        // cannot keep the first pass's values alive to reuse them
+        asm volatile("" ::: "memory");
+        f4 der0[S][NT][MT];
+        layer0();
+        const char* p0 = wsm + G::W0A;
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+          f4 hb[NT][MT];
+#pragma unroll
+          for (int u = 0; u < NT; ++u)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                const float r = acc[u][mt][j];
+                der0[i][u][mt][j] = act_deriv<ACT>(r);
+                hb[u][mt][j] = i + 1 < S ? act_el<ACT, false>(r, role) : 0.0f;
+              }
+          if (i + 1 < S) {
+            hidden(p0, hb);
+            p0 += G::HID;
+          }
+        }
+#pragma unroll
+        for (int i = S; i >= 1; --i) back(i, der0[i - 1]);
       }
       // dy/d(input row) = W_0^T e_0, written over the pair's rows
       const float* WB0 = reinterpret_cast<const float*>(bsm + (HH - 1) * G::WBH);
@@ -264,24 +312,25 @@ __device__ __attribute__((always_inline)) inline float mlp_tile_adj(const char* 
     const VA* W0T = reinterpret_cast<const VA*>(wsm + G::W0A);
     for (int tp = 0; tp < 4; tp += NT) {
       f4 acc[NT][MT];
-#pragma unroll
-      for (int u = 0; u < NT; ++u)
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) acc[u][mt] = zero;
-#pragma unroll
-      for (int s = 0; s < G::S0; ++s) {
-        VA b[NT];
+      // layer 0 pre-activations of the pair's input rows
+      auto layer0 = [&]() __attribute__((always_inline)) {
 #pragma unroll
         for (int u = 0; u < NT; ++u)
-          b[u] = *reinterpret_cast<const VA*>(feat + (16 * (tp + u) + n) * G::ROW + 32 * s + 8 * g);
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          const VA a = W0A[(mt * G::S0 + s) * kWave + lane];
+          for (int mt = 0; mt < MT; ++mt) acc[u][mt] = zero;
 #pragma unroll
-          for (int u = 0; u < NT; ++u) acc[u][mt] = PR::mma(a, b[u], acc[u][mt]);
+        for (int s = 0; s < G::S0; ++s) {
+          VA b[NT];
+#pragma unroll
+          for (int u = 0; u < NT; ++u)
+            b[u] = *reinterpret_cast<const VA*>(feat + (16 * (tp + u) + n) * G::ROW + 32 * s + 8 * g);
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            const VA a = W0A[(mt * G::S0 + s) * kWave + lane];
+#pragma unroll
+            for (int u = 0; u < NT; ++u) acc[u][mt] = PR::mma(a, b[u], acc[u][mt]);
+          }
         }
-      }
-      {
         VA b[NT];
 #pragma unroll
         for (int u = 0; u < NT; ++u)
@@ -292,15 +341,33 @@ __device__ __attribute__((always_inline)) inline float mlp_tile_adj(const char* 
 #pragma unroll
           for (int u = 0; u < NT; ++u) acc[u][mt] = PR::mma(a, b[u], acc[u][mt]);
         }
-      }
-      // forward, keeping act' of every activated layer in the packed B order
-      VA dA[HH][NT][HS32];
-      VT dT[HH][NT];
-      VA bA[NT][HS32];
-      VT bT[NT];
-      const char* p = wsm + G::W0A + G::W0T;
+      };
+      // pre-activations of the hidden layer at p from the activations bA, bT
+      auto hidden = [&](const char* p, const VA (&bA)[NT][HS32], const VT (&bT)[NT]) __attribute__((always_inline)) {
+        const VA* WA = reinterpret_cast<const VA*>(p);
+        const VT* WT = reinterpret_cast<const VT*>(p + G::WHA);
+        const float* BHp = reinterpret_cast<const float*>(p + G::WHA + G::WHT);
 #pragma unroll
-      for (int i = 0; i < HH; ++i) {
+        for (int mt = 0; mt < MT; ++mt) {
+          const f4 bias = *reinterpret_cast<const f4*>(BHp + 16 * mt + 4 * g);
+#pragma unroll
+          for (int u = 0; u < NT; ++u) acc[u][mt] = bias;
+#pragma unroll
+          for (int s = 0; s < HS32; ++s) {
+            const VA a = WA[(mt * HS32 + s) * kWave + lane];
+#pragma unroll
+            for (int u = 0; u < NT; ++u) acc[u][mt] = PR::mma(a, bA[u][s], acc[u][mt]);
+          }
+          if constexpr (G::HS16) {
+            const VT a = WT[mt * kWave + lane];
+#pragma unroll
+            for (int u = 0; u < NT; ++u) acc[u][mt] += PR::mmt(a, bT[u], zero);
+          }
+        }
+      };
+      // activations (packed B order) and, with d set, act' of acc
+      auto activate = [&](VA (&bA)[NT][HS32], VT (&bT)[NT], VA* dA, VT* dT, bool want_h)
+          __attribute__((always_inline)) {
 #pragma unroll
         for (int u = 0; u < NT; ++u) {
 #pragma unroll
@@ -308,66 +375,29 @@ __device__ __attribute__((always_inline)) inline float mlp_tile_adj(const char* 
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
               const float r0 = acc[u][2 * s][j], r1 = acc[u][2 * s + 1][j];
-              bA[u][s][j] = to_e<E>(act_el<ACT, false>(r0, role));
-              bA[u][s][j + 4] = to_e<E>(act_el<ACT, false>(r1, role));
-              dA[i][u][s][j] = to_e<E>(act_deriv<ACT>(r0));
-              dA[i][u][s][j + 4] = to_e<E>(act_deriv<ACT>(r1));
+              if (want_h) {
+                bA[u][s][j] = to_e<E>(act_el<ACT, false>(r0, role));
+                bA[u][s][j + 4] = to_e<E>(act_el<ACT, false>(r1, role));
+              }
+              if (dA) {
+                dA[u * HS32 + s][j] = to_e<E>(act_deriv<ACT>(r0));
+                dA[u * HS32 + s][j + 4] = to_e<E>(act_deriv<ACT>(r1));
+              }
             }
           if constexpr (G::HS16) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
               const float r = acc[u][MT - 1][j];
-              bT[u][j] = to_e<E>(act_el<ACT, false>(r, role));
-              dT[i][u][j] = to_e<E>(act_deriv<ACT>(r));
+              if (want_h) bT[u][j] = to_e<E>(act_el<ACT, false>(r, role));
+              if (dT) dT[u][j] = to_e<E>(act_deriv<ACT>(r));
             }
           }
         }
-        if (i + 1 < HH) {
-          const VA* WA = reinterpret_cast<const VA*>(p);
-          const VT* WT = reinterpret_cast<const VT*>(p + G::WHA);
-          const float* BHp = reinterpret_cast<const float*>(p + G::WHA + G::WHT);
-#pragma unroll
-          for (int mt = 0; mt < MT; ++mt) {
-            const f4 bias = *reinterpret_cast<const f4*>(BHp + 16 * mt + 4 * g);
-#pragma unroll
-            for (int u = 0; u < NT; ++u) acc[u][mt] = bias;
-#pragma unroll
-            for (int s = 0; s < HS32; ++s) {
-              const VA a = WA[(mt * HS32 + s) * kWave + lane];
-#pragma unroll
-              for (int u = 0; u < NT; ++u) acc[u][mt] = PR::mma(a, bA[u][s], acc[u][mt]);
-            }
-            if constexpr (G::HS16) {
-              const VT a = WT[mt * kWave + lane];
-#pragma unroll
-              for (int u = 0; u < NT; ++u) acc[u][mt] += PR::mmt(a, bT[u], zero);
-            }
-          }
-          p += G::HID;
-        } else {
-#pragma unroll
-          for (int u = 0; u < NT; ++u) {
-            const VA* WOA = reinterpret_cast<const VA*>(p) + (tp + u) * HS32 * kWave;
-#pragma unroll
-            for (int s = 0; s < HS32; ++s) out[u] = PR::mma(WOA[s * kWave + lane], bA[u][s], out[u]);
-            if constexpr (G::HS16) {
-              const VT* WOT = reinterpret_cast<const VT*>(p + G::WOA) + (tp + u) * kWave;
-              out_t[u] = PR::mmt(WOT[lane], bT[u], out_t[u]);
-            }
-          }
-        }
-      }
-      // backward in the packed B order: e_i = dy/dh_{i+1} * act'(x_i)
+      };
       VA eA[NT][HS32];
       VT eT[NT];
-#pragma unroll
-      for (int u = 0; u < NT; ++u) {
-#pragma unroll
-        for (int s = 0; s < HS32; ++s) eA[u][s] = woA[s] * dA[HH - 1][u][s];
-        if constexpr (G::HS16) eT[u] = woT * dT[HH - 1][u];
-      }
-#pragma unroll
-      for (int i = HH - 1; i >= 1; --i) {
+      // e <- (W_i^T e) * act'(x_{i-1})
+      auto back = [&](int i, const VA (&dA)[NT][HS32], const VT (&dT)[NT]) __attribute__((always_inline)) {
         const VA* WBA = reinterpret_cast<const VA*>(bsm + (i - 1) * G::WBH);
         const VT* WBT = reinterpret_cast<const VT*>(bsm + (i - 1) * G::WBH + G::WHA);
         f4 nu[NT][MT];
@@ -397,15 +427,71 @@ __device__ __attribute__((always_inline)) inline float mlp_tile_adj(const char* 
               x[j] = to_e<E>(nu[u][2 * s][j]);
               x[j + 4] = to_e<E>(nu[u][2 * s + 1][j]);
             }
-            eA[u][s] = x * dA[i - 1][u][s];
+            eA[u][s] = x * dA[u][s];
           }
           if constexpr (G::HS16) {
             VT x;
 #pragma unroll
             for (int j = 0; j < 4; ++j) x[j] = to_e<E>(nu[u][MT - 1][j]);
-            eT[u] = x * dT[i - 1][u];
+            eT[u] = x * dT[u];
           }
         }
+      };
+      layer0();
+      // forward, keeping act' of the last HD activated layers in the packed B order
+      VA dA[HD][NT][HS32];
+      VT dT[HD][NT];
+      VA bA[NT][HS32];
+      VT bT[NT];
+      const char* p = wsm + G::W0A + G::W0T;
+#pragma unroll
+      for (int i = 0; i < HH; ++i) {
+        if (i >= S) activate(bA, bT, &dA[i - S][0][0], dT[i - S], true);
+        else activate(bA, bT, nullptr, nullptr, true);
+        if (i + 1 < HH) {
+          hidden(p, bA, bT);
+          p += G::HID;
+        } else {
+#pragma unroll
+          for (int u = 0; u < NT; ++u) {
+            const VA* WOA = reinterpret_cast<const VA*>(p) + (tp + u) * HS32 * kWave;
+#pragma unroll
+            for (int s = 0; s < HS32; ++s) out[u] = PR::mma(WOA[s * kWave + lane], bA[u][s], out[u]);
+            if constexpr (G::HS16) {
+              const VT* WOT = reinterpret_cast<const VT*>(p + G::WOA) + (tp + u) * kWave;
+              out_t[u] = PR::mmt(WOT[lane], bT[u], out_t[u]);
+            }
+          }
+        }
+      }
+      // backward in the packed B order: e_i = dy/dh_{i+1} * act'(x_i)
+#pragma unroll
+      for (int u = 0; u < NT; ++u) {
+#pragma unroll
+        for (int s = 0; s < HS32; ++s) eA[u][s] = woA[s] * dA[HD - 1][u][s];
+        if constexpr (G::HS16) eT[u] = woT * dT[HD - 1][u];
+      }
+#pragma unroll
+      for (int i = HH - 1; i > S; --i) back(i, dA[i - 1 - S], dT[i - 1 - S]);
+      if constexpr (S > 0) {
+        // second forward pass over the first S layers for their act'; the
+        // memory clobber makes it reload its operands, so the compiler
+        // cannot keep the first pass's values alive to reuse them
+        asm volatile("" ::: "memory");
+        VA dA0[S][NT][HS32];
+        VT dT0[S][NT];
+        layer0();
+        const char* p0 = wsm + G::W0A + G::W0T;
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+          activate(bA, bT, &dA0[i][0][0], dT0[i], i + 1 < S);
+          if (i + 1 < S) {
+            hidden(p0, bA, bT);
+            p0 += G::HID;
+          }
+        }
+#pragma unroll
+        for (int i = S; i >= 1; --i) back(i, dA0[i - 1], dT0[i - 1]);
       }
       // dy/d(input row) = W_0^T e_0, written over the pair's rows
       const VA* WB0A = reinterpret_cast<const VA*>(bsm + (HH - 1) * G::WBH);

@@ -592,8 +592,8 @@ def _rev_ref(onet, xyz, t=0.0):
                          ids=["small", "study", "shaded", "c48H1", "c48H2"])
 def test_adjoint_grad_points(FV, spec):
     """Reverse-mode gradient (Sec. 6's adjoint: one forward and one transposed
-    pass) against the oracle's reverse mode, at every layer count compiled
-    (H = 1..4), c = 32 and 48, FP32 and FP16 networks on FP32, FP16 and uint8
+    pass) against the oracle's reverse mode, at the layer counts whose
+    derivatives all stay in registers (H = 1..4), c = 32 and 48, FP32 and FP16 networks on FP32, FP16 and uint8
     grids, a ragged point count with a few points outside the domain (the
     latent part of the gradient vanishes there)."""
     xyz = np.concatenate([I.uniform_points(64 * 5 + 13, 19, -0.999, 0.999),
@@ -619,14 +619,58 @@ def test_adjoint_grad_points_keyframes_edges_and_limits(FV):
             d, g = FV.fvsrn_grad_points(gnet, torch.from_numpy(xyz).cuda(), t, "f32", mode="adjoint")
             assert np.abs(d.cpu().numpy() - dref).max() <= FP32_TOL
             assert _grad_err(g.cpu().numpy(), gref) <= 1e-4
-    # H > 4, BF16 and other activations are not compiled for the adjoint
+    # BF16 and other activations are not compiled for the adjoint, and the
+    # FP32 fragments of a c = 48 network of 8 layers exceed the LDS
     xyz = torch.from_numpy(I.uniform_points(10, 3)).cuda()
-    for spec, prec in ((I.NetSpec(R=8, F=8, L=4, c=32, H=5), "f32"), (I.NET_SMALL, "bf16"),
-                       (I.NetSpec(R=8, F=8, L=4, c=32, H=2, act="snakealt"), "f32")):
+    for spec, prec in ((I.NET_SMALL, "bf16"), (I.NetSpec(R=8, F=8, L=4, c=32, H=2, act="snakealt"), "f32"),
+                       (I.NetSpec(R=8, F=16, L=8, c=48, H=8), "f32")):
         gnet, _ = _nets(FV, spec, 2)
         with pytest.raises(FV.FvsrnError) as e:
             FV.fvsrn_grad_points(gnet, xyz, 0.0, prec, mode="adjoint")
         assert e.value.status == FV.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("spec,precs", [
+    (I.NetSpec(R=12, F=8, L=4, c=32, H=5), ("f32", "f16")),
+    (I.NetSpec(R=12, F=16, L=8, c=32, H=8), ("f32", "f16")),
+    (I.NetSpec(R=12, F=16, L=8, c=48, H=6), ("f32", "f16")),
+    (I.NetSpec(R=12, F=8, L=4, c=48, H=7), ("f32", "f16")),
+    (I.NetSpec(R=12, F=8, L=4, c=48, H=8), ("f16",))], ids=["c32H5", "c32H8", "c48H6", "c48H7", "c48H8"])
+def test_adjoint_grad_points_deep(FV, spec, precs):
+    """Networks of more than four layers: the adjoint keeps the derivatives
+    of the last four and runs the first H - 4 layers a second time. Against
+    the oracle's reverse mode on FP32 and FP16 grids, a ragged point count
+    with points outside the domain."""
+    xyz = np.concatenate([I.uniform_points(64 * 3 + 29, 41, -0.999, 0.999),
+                          np.array([[1.2, 0.1, -0.3], [-0.5, -1.1, 0.9]], np.float32)])
+    for gd in (FV.F32, FV.F16):
+        gnet, onet = _nets(FV, spec, 29, grid_dtype=gd)
+        dref, gref = _rev_ref(onet, xyz)
+        for prec in precs:
+            dtol, gtol = (FP32_TOL, 1e-4) if prec == "f32" else (FP16_TOL, 1e-2)
+            d, g = FV.fvsrn_grad_points(gnet, torch.from_numpy(xyz).cuda(), 0.0, prec, mode="adjoint")
+            derr, gerr = np.abs(d.cpu().numpy() - dref).max(), _grad_err(g.cpu().numpy(), gref)
+            _report("adjoint c=%d H=%d grid %d %s density" % (spec.c, spec.H, gd, prec), derr)
+            _report("adjoint c=%d H=%d grid %d %s gradient (rel.)" % (spec.c, spec.H, gd, prec), gerr)
+            assert derr <= dtol and gerr <= gtol
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-4), ("f16", FP16_TOL)])
+def test_phong_render_adjoint_deep(FV, prec, tol):
+    """Adjoint Phong shading of a six-layer network (two layers evaluated
+    twice) against the oracle's reverse-mode render."""
+    spec = I.NetSpec(R=16, F=16, L=8, c=32, H=6)
+    gnet, onet = _nets(FV, spec, 31, grid_dtype=FV.F16 if prec == "f16" else FV.F32)
+    tf = I.ramp_tf()
+    cams = I.orbit_cameras(2, 21, 13)
+    m = I.March(step=1 / 96, ert_eps=0.0, phong=True, grad_mode=3)
+    ref, ns = O.render(O.Field(net=onet), tf, cams, m)
+    stats = torch.zeros(3, dtype=torch.int64, device="cuda")
+    img = FV.fvsrn_render(gnet, tf, cams, m, prec, stats=stats).cpu().numpy()
+    err = np.abs(img - ref).max()
+    _report("phong adjoint c=%d H=%d %s" % (spec.c, spec.H, prec), err)
+    assert err <= tol
+    assert abs(stats[0].item() - ns) <= 0.001 * ns
 
 
 @pytest.mark.parametrize("prec,tol", [("f32", 1e-4), ("f16", FP16_TOL)])
