@@ -254,6 +254,9 @@ MarchDev make_march(const fvsrn_march* m) {
 fvsrn_status launch_status(int rc, const char* what) {
   if (rc == 0) return FVSRN_OK;
   if (rc == 1) return fail(FVSRN_ERR_UNSUPPORTED, "%s: configuration not compiled", what);
+  if (rc == kLaunchNoLds)
+    return fail(FVSRN_ERR_UNSUPPORTED, "%s: the network's weight fragments do not fit the 160 KiB of LDS", what);
+  if (rc == kLaunchTooLarge) return fail(FVSRN_ERR_UNSUPPORTED, "%s: launch exceeds a 32-bit grid", what);
   return fail(FVSRN_ERR_DEVICE, "%s: launch failed: %s", what, last_hip_error());
 }
 

@@ -108,6 +108,13 @@ int launch_train(const NetDev& net, const KeyTimes& kt, float* latent, float* we
 
 const char* last_hip_error();
 
+// Launcher results: 0 launched; 1 configuration not compiled; 2 the launch
+// failed (last_hip_error); kLaunchNoLds the network's weight fragments leave
+// no room for a wave's input tile in LDS; kLaunchTooLarge the work exceeds
+// a 32-bit grid.
+constexpr int kLaunchNoLds = 3;
+constexpr int kLaunchTooLarge = 4;
+
 // Shared host helpers (defined in fvsrn_misc.hip).
 int check_launch();                                   // 0 or 2 after a launch
 int grid_blocks(long long work, int per_block, int cap);

@@ -434,12 +434,12 @@ int launch_render_t(const NetDev& nd, const TFDev& tf, const ViewBatch& vb, cons
   constexpr int TW = TileShape<MODE>::TW, TH = TileShape<MODE>::TH;
   const int tx = (vb.width + TW - 1) / TW, ty = (vb.height + TH - 1) / TH;
   const long long tiles = (long long)tx * ty * vb.n_views;
-  if (tiles > 0x7fffffffLL) return 1;
+  if (tiles > 0x7fffffffLL) return kLaunchTooLarge;
   const int wpb = waves_per_block<CF, MODE>(nd.H);
-  if (wpb < 1) return 1;
+  if (wpb < 1) return kLaunchNoLds;
   const size_t shm = (size_t)fixed_lds_bytes<CF, MODE>(nd.H) + (size_t)wpb * G::FEAT_BYTES;
   const long long blocks = (tiles + wpb - 1) / wpb;  // one tile per wave
-  if (blocks > 0x7fffffffLL) return 1;
+  if (blocks > 0x7fffffffLL) return kLaunchTooLarge;
   static bool attr = false;
   if (!attr) {
     (void)hipFuncSetAttribute((const void*)march_kernel<CF, MODE, HH>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -457,7 +457,7 @@ int launch_points_t(const NetDev& nd, const float* xyz, long long n, int key, fl
   using G = typename CF::G;
   constexpr int PER = PM == kShadeFwd ? 16 : 64;
   const int wpb = waves_per_block<CF, PM>(nd.H);
-  if (wpb < 1) return 1;
+  if (wpb < 1) return kLaunchNoLds;
   const size_t shm = (size_t)fixed_lds_bytes<CF, PM>(nd.H) + (size_t)wpb * G::FEAT_BYTES;
   static bool attr = false;
   if (!attr) {

@@ -679,7 +679,7 @@ struct TrainEntry {
                  hipStream_t st) {
     const int H = nd.H;
     const int wpb = waves_per_block(H);
-    if (wpb < 1) return 1;
+    if (wpb < 1) return kLaunchNoLds;
     const int ncell = (nd.R - 1) * (nd.R - 1) * (nd.R - 1);
     char* wsb = (char*)ws + slices_bytes(nd, n);
     float* dz = (float*)wsb;

@@ -628,6 +628,7 @@ def test_adjoint_grad_points_keyframes_edges_and_limits(FV):
         with pytest.raises(FV.FvsrnError) as e:
             FV.fvsrn_grad_points(gnet, xyz, 0.0, prec, mode="adjoint")
         assert e.value.status == FV.ERR_UNSUPPORTED
+        assert ("LDS" in str(e.value)) == (spec.c == 48)
 
 
 @pytest.mark.parametrize("spec,precs", [
