@@ -97,7 +97,7 @@ class March:
     kd: float = 0.7
     ks: float = 0.2
     shininess: float = 32.0
-    grad_mode: int = 0      # Phong gradient: 0 forward mode, 1 central differences
+    grad_mode: int = 0      # Phong gradient: 0 forward mode, 1 central differences, 2 predicted, 3 adjoint
     fd_step: float = 0.0    # central-difference step (world units)
 
 
