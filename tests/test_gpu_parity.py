@@ -335,6 +335,55 @@ def test_dense_render_and_points(FV):
     assert np.abs(out - O.dense_eval_points(vol, xyz)).max() <= 1e-6
 
 
+def test_render_more_views_than_one_launch_and_widest_image(FV):
+    """Edge sizes of fvsrn_render / fvsrn_render_dense: more views than one
+    launch carries (the host splits them; each view keeps its own time on a
+    two-keyframe network), and an image of the largest accepted width."""
+    spec = I.NetSpec(R=10, F=8, L=4, c=32, H=3, K=2)
+    gnet, onet = _nets(FV, spec, 37, key_times=(0.0, 1.0))
+    tf = I.ramp_tf()
+    n_views = 18
+    cams = I.orbit_cameras(n_views, 9, 7, times=[v / (n_views - 1) for v in range(n_views)])
+    m = I.March(step=1 / 48)
+    ref, ns = O.render(O.Field(net=onet), tf, cams, m)
+    stats = torch.zeros(3, dtype=torch.int64, device="cuda")
+    img = FV.fvsrn_render(gnet, tf, cams, m, "f32", stats=stats).cpu().numpy()
+    per_view = np.abs(img - ref).reshape(n_views, -1).max(axis=1)
+    _report("render %d views (worst view %d)" % (n_views, int(per_view.argmax())), per_view.max())
+    # a wrong camera, time or output slot in the second launch would be off by
+    # far more than rounding; these nearly opaque rays composite up to 166
+    # FP32 samples of a keyframe-blended grid, so the bound is 2.5x FP32_TOL
+    assert img.shape == (n_views, 7, 9, 4) and per_view.max() <= 2.5 * FP32_TOL
+    assert abs(stats[0].item() - ns) <= 0.001 * ns
+    vol = I.gaussian_volume(24, 6, seed=9)
+    dcams = I.orbit_cameras(17, 8, 6)
+    dref, _ = O.render(O.Field(vol=vol), tf, dcams, m)
+    dimg = FV.fvsrn_render_dense(torch.from_numpy(vol).cuda(), tf, dcams, m).cpu().numpy()
+    assert np.abs(dimg - dref).max() <= FP32_TOL
+    # a perspective camera inside the domain: rays start at the eye
+    icam = [I.Camera(ortho=False, eye=(0.1, -0.2, 0.3), target=(0.15, -0.1, -1.0), up=(0.0, 1.0, 0.0),
+                     fov_y_deg=70.0, width=11, height=9, time=0.4)]
+    iref, ins = O.render(O.Field(net=onet), tf, icam, m)
+    stats.zero_()
+    iimg = FV.fvsrn_render(gnet, tf, icam, m, "f32", stats=stats).cpu().numpy()
+    _report("render from inside the domain", np.abs(iimg - iref).max())
+    assert np.abs(iimg - iref).max() <= 2.5 * FP32_TOL and stats[1].item() == 99
+    assert abs(stats[0].item() - ins) <= 0.001 * ins
+    # widest image (16384 columns): two rows, eight fixed steps per ray; the
+    # orthographic half height 1/8192 makes the half width 1, so every ray
+    # crosses the domain
+    wcam = [I.Camera(ortho=True, eye=(0.0, 0.0, 2.0), target=(0.0, 0.0, 0.0), up=(0.0, 1.0, 0.0),
+                     width=16384, height=2, ortho_half_extent=1.0 / 8192)]
+    wm = I.March(step=0.0, fixed_steps=8)
+    net0, onet0 = _nets(FV, I.NET_SMALL, 38)
+    wref, wns = O.render(O.Field(net=onet0), tf, wcam, wm)
+    assert wns == 16384 * 2 * 8
+    wimg = FV.fvsrn_render(net0, tf, wcam, wm, "f16").cpu().numpy()
+    err = np.abs(wimg - wref).max()
+    _report("render 16384 x 2 f16", err)
+    assert err <= FP16_TOL
+
+
 # ------------------------------------------------------------ utilities
 
 def test_sample_points_bit_exact(FV):
