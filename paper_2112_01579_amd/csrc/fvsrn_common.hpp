@@ -143,9 +143,11 @@ __device__ inline float cos_rev(float r) { return __builtin_amdgcn_cosf(r); }  /
 __device__ inline float fast_exp(float x) { return __builtin_amdgcn_exp2f(x * kLog2e); }
 __device__ inline float sigmoid_f(float y) { return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-y * kLog2e)); }
 
-// Value of lane 4*floor(lane/4) (the first lane of each quad).
+// Value of lane 4*floor(lane/4) (the first lane of each quad). Called with
+// every lane active; bound_ctrl lets the compiler fold the move into the
+// instruction that consumes it as a DPP source operand.
 __device__ inline float quad_bcast0(float x) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x00, 0xF, 0xF, false));
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x00, 0xF, 0xF, true));
 }
 // Value of lane 4*floor(lane/4) + k for k = 1, 2, 3.
 template <int K>
