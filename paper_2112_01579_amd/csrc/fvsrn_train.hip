@@ -16,7 +16,7 @@
 //   5. dL/dz = W_0[:, latent]^T delta_0, stored per point with the point's
 //      latent cell (and the cell's point count).
 // The latent gradient is then gathered, not scattered: the points are
-// counting-sorted by cell (cell_scan_kernel, bin_points_kernel) and every
+// counting-sorted by cell (the cell scan kernels, bin_points_kernel) and every
 // grid vertex sums the trilinear-weighted dL/dz of the points in its (up to)
 // eight cells (latent_grad_kernel), with plain stores.
 // dW tiles are added into the wave's private workspace slice (no atomics, so
@@ -536,44 +536,105 @@ __global__ void adam_kernel(float* p, const float* g, float* m, float* v, long l
 
 // ------------------------------------------ latent gradient by gathering
 
-constexpr int kScanThreads = 1024, kScanItems = 8;
+// Exclusive prefix sums of the per-cell point counts, off[c] = first sorted
+// position of cell c, off[ncell] = n, cursor a copy of off: blocks of
+// kCellBlock consecutive cells are summed (cell_block_sum_kernel), the block
+// sums scanned by one workgroup (cell_block_scan_kernel), then every block
+// scans its own cells from its block's offset (cell_scan_kernel).
+constexpr int kCellThreads = 256, kCellItems = 16, kCellBlock = kCellThreads * kCellItems;
 
-// Exclusive prefix sums of the per-cell point counts (one workgroup, eight
-// consecutive cells per thread and pass): off[c] = first sorted position of
-// cell c, off[ncell] = n; cursor gets a copy.
-__global__ __launch_bounds__(kScanThreads) void cell_scan_kernel(const int* count, int ncell, int* off, int* cursor) {
-  __shared__ int part[kScanThreads];
-  int carry = 0;
-  for (int c0 = 0; c0 < ncell; c0 += kScanThreads * kScanItems) {
-    const int base = c0 + threadIdx.x * kScanItems;
-    int x[kScanItems], sum = 0;
+int cell_blocks(long long ncell) { return (int)((ncell + kCellBlock - 1) / kCellBlock); }
+
+// Exclusive scan of v over the workgroup; *total receives the sum. wsum:
+// LDS of one int per wave. Every thread of the workgroup must call it.
+template <int kThreads>
+__device__ inline int block_exclusive_scan(int v, int* wsum, int* total) {
+  constexpr int kWaves = kThreads / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int incl = v;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-      x[k] = base + k < ncell ? count[base + k] : 0;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  int before = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    const int t = wsum[w];
+    before += w < wave ? t : 0;
+    tot += t;
+  }
+  __syncthreads();  // wsum may be rewritten by the next call
+  *total = tot;
+  return before + incl - v;
+}
+
+__global__ __launch_bounds__(kCellThreads) void cell_block_sum_kernel(const int* count, int ncell, int* bsum) {
+  __shared__ int wsum[kCellThreads / 64];
+  const int b0 = blockIdx.x * kCellBlock;
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < kCellItems; ++k) {  // striped: coalesced
+    const int c = b0 + k * kCellThreads + threadIdx.x;
+    s += c < ncell ? count[c] : 0;
+  }
+  int total;
+  (void)block_exclusive_scan<kCellThreads>(s, wsum, &total);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// One workgroup: exclusive scan of the nb block sums in place; off[ncell]
+// receives the grand total.
+constexpr int kBlockScanThreads = 1024, kBlockScanItems = 8;
+__global__ __launch_bounds__(kBlockScanThreads) void cell_block_scan_kernel(int* bsum, int nb, int* off_end) {
+  __shared__ int wsum[kBlockScanThreads / 64];
+  int carry = 0;
+  for (int c0 = 0; c0 < nb; c0 += kBlockScanThreads * kBlockScanItems) {
+    const int base = c0 + threadIdx.x * kBlockScanItems;
+    int x[kBlockScanItems], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kBlockScanItems; ++k) {
+      x[k] = base + k < nb ? bsum[base + k] : 0;
       sum += x[k];
     }
-    part[threadIdx.x] = sum;
-    __syncthreads();
-    for (int o = 1; o < kScanThreads; o <<= 1) {
-      const int y = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
-      __syncthreads();
-      part[threadIdx.x] += y;
-      __syncthreads();
-    }
-    int run = carry + part[threadIdx.x] - sum;
+    int total;
+    int run = carry + block_exclusive_scan<kBlockScanThreads>(sum, wsum, &total);
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-      if (base + k < ncell) {
-        off[base + k] = run;
-        cursor[base + k] = run;
-      }
+    for (int k = 0; k < kBlockScanItems; ++k) {
+      if (base + k < nb) bsum[base + k] = run;
       run += x[k];
     }
-    const int total = part[kScanThreads - 1];
-    __syncthreads();
     carry += total;
   }
-  if (threadIdx.x == 0) off[ncell] = carry;
+  if (threadIdx.x == 0) *off_end = carry;
+}
+
+// Block b: its cells' exclusive prefix sums from its block offset (bsum,
+// or 0 when bsum is null); each thread takes kCellItems consecutive cells.
+// With a single block (off_end set) the kernel also writes the total.
+__global__ __launch_bounds__(kCellThreads) void cell_scan_kernel(const int* count, int ncell, const int* bsum, int* off,
+                                                                 int* cursor, int* off_end) {
+  __shared__ int wsum[kCellThreads / 64];
+  const int base = blockIdx.x * kCellBlock + threadIdx.x * kCellItems;
+  int x[kCellItems], sum = 0;
+#pragma unroll
+  for (int k = 0; k < kCellItems; ++k) {
+    x[k] = base + k < ncell ? count[base + k] : 0;
+    sum += x[k];
+  }
+  int total;
+  int run = (bsum ? bsum[blockIdx.x] : 0) + block_exclusive_scan<kCellThreads>(sum, wsum, &total);
+#pragma unroll
+  for (int k = 0; k < kCellItems; ++k) {
+    if (base + k < ncell) {
+      off[base + k] = run;
+      cursor[base + k] = run;
+    }
+    run += x[k];
+  }
+  if (off_end && threadIdx.x == 0) *off_end = total;
 }
 
 // Counting sort: point i goes to a free slot of its cell.
@@ -671,7 +732,7 @@ struct TrainEntry {
   }
   static size_t ws_bytes(const NetDev& nd, long long n) {
     const long long ncell = (long long)(nd.R - 1) * (nd.R - 1) * (nd.R - 1);
-    return slices_bytes(nd, n) + (size_t)n * F * 4 + (size_t)n * 8 + (size_t)(3 * ncell + 1) * 4;
+    return slices_bytes(nd, n) + (size_t)n * F * 4 + (size_t)n * 8 + (size_t)(3 * ncell + 1 + cell_blocks(ncell)) * 4;
   }
   static int run(const NetDev& nd, const KeyTimes& kt, float* latent, float* d_latent, float* d_weights,
                  const float* xyz, const float* times, long long n, const float* target,
@@ -688,6 +749,7 @@ struct TrainEntry {
     int* count = order + n;
     int* off = count + ncell;
     int* cursor = off + ncell + 1;
+    int* bsum = cursor + ncell;  // cell_blocks(ncell) block sums
     hipLaunchKernelGGL(fill_kernel, dim3(grid_blocks(ncell, 256, device_cus() * 8)), dim3(256), 0, st, (float*)count,
                        (long long)ncell, 0.0f);  // zero bits: zero counts
     int rc = check_launch();
@@ -717,7 +779,15 @@ struct TrainEntry {
       if (rc) return rc;
     }
     // latent gradient: sort the points by cell, then gather per vertex
-    hipLaunchKernelGGL(cell_scan_kernel, dim3(1), dim3(kScanThreads), 0, st, (const int*)count, ncell, off, cursor);
+    const int nb = cell_blocks(ncell);
+    if (nb > 1) {
+      hipLaunchKernelGGL(cell_block_sum_kernel, dim3(nb), dim3(kCellThreads), 0, st, (const int*)count, ncell, bsum);
+      if ((rc = check_launch())) return rc;
+      hipLaunchKernelGGL(cell_block_scan_kernel, dim3(1), dim3(kBlockScanThreads), 0, st, bsum, nb, off + ncell);
+      if ((rc = check_launch())) return rc;
+    }
+    hipLaunchKernelGGL(cell_scan_kernel, dim3(nb), dim3(kCellThreads), 0, st, (const int*)count, ncell,
+                       nb > 1 ? (const int*)bsum : nullptr, off, cursor, nb > 1 ? nullptr : off + ncell);
     if ((rc = check_launch())) return rc;
     if (n > 0) {
       hipLaunchKernelGGL(bin_points_kernel, dim3(grid_blocks(n, 256, device_cus() * 8)), dim3(256), 0, st,
