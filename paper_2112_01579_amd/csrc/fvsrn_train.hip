@@ -502,9 +502,12 @@ __global__ void gather_kernel(int H, int NO, const float* partial, int n_groups,
         }
       }
     }
+    // sequential adds in a fixed order; the unrolled loads of a group's terms
+    // are issued together (the loss and the output biases have 64 per group)
     float s = 0.0f;
     for (int g = 0; g < n_groups; ++g) {
       const float* pg = partial + (size_t)g * SL + base;
+#pragma unroll 8
       for (int c = 0; c < count; ++c) s += pg[c * stride];
     }
     if (j == nw) {
