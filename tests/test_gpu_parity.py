@@ -569,6 +569,55 @@ def test_pred_grad_points(FV, spec):
     assert _grad_err(g.cpu().numpy(), fgref) <= 1e-4
 
 
+def _integer_net(spec, seed):
+    """Latent values and weights that keep every value of the network an
+    exact small integer: latent in [-3, 3], two +-1 entries per weight row
+    (layer 0 reads latent columns only), integer biases in [-2, 2]; with the
+    identity activation no value exceeds 2^7, so FP16 and BF16 hold all of
+    them exactly."""
+    rng = np.random.default_rng(seed)
+    lat = rng.integers(-3, 4, size=(spec.K, spec.R, spec.R, spec.R, spec.F)).astype(np.float32)
+    parts = []
+    for li, (o, i) in enumerate(spec.layer_shapes()):
+        W = np.zeros((o, i), np.float32)
+        cols = np.arange(3, 3 + spec.F) if li == 0 else np.arange(i)
+        for r in range(o):
+            W[r, rng.choice(cols, 2, replace=False)] = rng.choice([-1.0, 1.0], 2)
+        parts += [W.ravel(), rng.integers(-2, 3, size=o).astype(np.float32)]
+    return lat, np.concatenate(parts)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16", "bf16"])
+def test_mlp_fragments_bit_exact(FV, prec):
+    """Every value exact: an identity-activation four-output network with
+    small integer latents, +-1 weights and integer biases, evaluated at grid
+    vertices (trilinear weights exactly 0 or 1). Outputs 1..3 have no
+    activation, so they must equal the oracle's integers bit for bit -- a
+    check of every fragment permutation of the input row, the hidden layers
+    and the output rows that no rounding can hide. Density (output 0 through
+    the sigmoid) within the precision's tolerance."""
+    spec = I.NetSpec(R=17, F=16, L=8, c=32, H=4, outputs=4, act="identity")
+    lat, w = _integer_net(spec, 43)
+    grid_dtype = FV.F32 if prec == "f32" else FV.F16
+    gnet = FV.Network(spec, lat, w, grid_dtype=grid_dtype)
+    onet = O.Net(spec, lat.astype(np.float64), w)
+    rng = np.random.default_rng(44)
+    xyz = (-1.0 + rng.integers(0, spec.R, size=(64 * 3 + 7, 3)) * (2.0 / (spec.R - 1))).astype(np.float32)
+    dref, gref = _pred_ref(onet, xyz)
+    assert np.all(gref == np.round(gref)) and np.abs(gref).max() < 128 and np.abs(gref).max() >= 8
+    d, g = FV.fvsrn_pred_grad_points(gnet, torch.from_numpy(xyz).cuda(), 0.0, prec)
+    assert np.array_equal(g.cpu().numpy(), gref.astype(np.float32))
+    dtol = {"f32": FP32_TOL, "f16": FP16_TOL, "bf16": BF16_TOL}[prec]
+    assert np.abs(d.cpu().numpy() - dref).max() <= dtol
+    # c = 48 (an odd number of 16-row tiles) on the FP16 path
+    spec48 = dataclasses.replace(spec, c=48)
+    lat, w = _integer_net(spec48, 45)
+    gnet = FV.Network(spec48, lat, w, grid_dtype=grid_dtype)
+    dref, gref = _pred_ref(O.Net(spec48, lat.astype(np.float64), w), xyz)
+    d, g = FV.fvsrn_pred_grad_points(gnet, torch.from_numpy(xyz).cuda(), 0.0, prec)
+    assert np.array_equal(g.cpu().numpy(), gref.astype(np.float32))
+
+
 def test_pred_grad_points_keyframes_and_edges(FV):
     spec = I.NetSpec(R=8, F=8, L=4, c=32, H=2, K=3, outputs=4)
     gnet, onet = _nets(FV, spec, 6, key_times=(0.0, 1.0, 3.0))
