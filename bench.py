@@ -124,20 +124,32 @@ def torch_layerwise(spec, lat, w, xyz, dtype):
     return run
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(spec, lat16, w, tf, cams, march):
-    """The FP64 oracle on the host cores, on a 256x256 centre crop of view 0."""
+    """The FP64 oracle on the host cores this process may use (at most 16),
+    on a 352x352 centre crop of view 0."""
     import oracle as O
-    threads = os.cpu_count() or 1
+    threads = max(1, min(len(os.sched_getaffinity(0)), 16))
     net = O.Net(spec, lat16.astype(np.float64), w)
     W, H = cams[0].width, cams[0].height
-    c = 128
+    c = 176
     pix = np.array([(H // 2 - c + y) * W + (W // 2 - c + x) for y in range(2 * c) for x in range(2 * c)],
                    dtype=np.int64)
     t0 = time.perf_counter()
     _, ns = O.render(O.Field(net=net), tf, cams, march, pixels=pix, threads=threads)
     dt = time.perf_counter() - t0
     return {"value": ns / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
-            "sample": "256x256 centre crop of view 0 (%d samples, %.1f s)" % (ns, dt)}
+            "sample": "%dx%d centre crop of view 0 (%d samples, %.1f s)" % (2 * c, 2 * c, ns, dt),
+            "cpu_model": cpu_model()}
 
 
 def main():
