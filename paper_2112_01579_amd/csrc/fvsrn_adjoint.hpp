@@ -592,6 +592,60 @@ __device__ inline void latent_vjp(const LatentSrc& ls, float px, float py, float
   }
 }
 
+// latent_vjp for an FP16 network on an FP16 grid: the row's FP16 latent
+// entries u are dotted with each corner's FP16 vector two channels per
+// v_dot2_f32_f16 (FP32 accumulation, the products exact as in latent_vjp),
+// and the trilinear derivative is taken from the eight corner sums by
+// differences along each axis: dy/dp_x = dx * sum over (y, z) of
+// Y Z (d[1,y,z] - d[0,y,z]), likewise for y and z.
+template <int F>
+__device__ inline void latent_vjp_h(const LatentSrc& ls, float px, float py, float pz, const h2* u2, float g[3]) {
+  int ix, iy, iz;
+  float fx, fy, fz, dx, dy, dz;
+  axis_cell(px, ls.R, ix, fx, dx);
+  axis_cell(py, ls.R, iy, fy, dy);
+  axis_cell(pz, ls.R, iz, fz, dz);
+  const float X[2] = {1.0f - fx, fx}, Y[2] = {1.0f - fy, fy}, Z[2] = {1.0f - fz, fz};
+  const float yz[4] = {Y[0] * Z[0], Y[1] * Z[0], Y[0] * Z[1], Y[1] * Z[1]};  // [by + 2 bz]
+  const float xz[4] = {X[0] * Z[0], X[1] * Z[0], X[0] * Z[1], X[1] * Z[1]};  // [bx + 2 bz]
+  const float xy[4] = {X[0] * Y[0], X[1] * Y[0], X[0] * Y[1], X[1] * Y[1]};  // [bx + 2 by]
+  const unsigned R = (unsigned)ls.R;
+  const unsigned sx = F, sy = R * F, sz = R * R * F;
+  const unsigned base = (unsigned)iz * sz + (unsigned)iy * sy + (unsigned)ix * sx;
+  unsigned off[8];
+  corner_offsets(sx, sy, sz, off);
+#pragma unroll
+  for (int key = 0; key < 2; ++key) {
+    const void* grid = key == 0 ? ls.g0 : ls.g1;
+    if (key == 1 && !grid) break;
+    const __amdgpu_buffer_rsrc_t r = grid_rsrc(grid, ls.bytes);
+    float d[8];  // corner c = bx + 2 by + 4 bz
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      float s = 0.0f;
+#pragma unroll
+      for (int q = 0; q < F / 8; ++q) {
+        const h8 hv = __builtin_bit_cast(h8, load16(r, base * 2u + 16u * q, off[c] * 2u));
+#pragma unroll
+        for (int j = 0; j < 4; ++j) s = __builtin_amdgcn_fdot2(u2[4 * q + j], h2{hv[2 * j], hv[2 * j + 1]}, s, false);
+      }
+      d[c] = s;
+    }
+    float tx = 0.0f, ty = 0.0f, tz = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int lo = i & 1, hi = i >> 1;
+      tx = fmaf(yz[i], d[1 + 2 * lo + 4 * hi] - d[2 * lo + 4 * hi], tx);
+      ty = fmaf(xz[i], d[lo + 2 + 4 * hi] - d[lo + 4 * hi], ty);
+      tz = fmaf(xy[i], d[lo + 2 * hi + 4] - d[lo + 2 * hi], tz);
+    }
+    const float kw = key == 0 ? ls.w0 : ls.w1;
+    g[0] = fmaf(kw * dx, tx, g[0]);
+    g[1] = fmaf(kw * dy, ty, g[1]);
+    g[2] = fmaf(kw * dz, tz, g[2]);
+  }
+}
+
 // The lane's gradient dy/dp from its row u = dy/d(input row) (left by
 // mlp_tile_adj) and the Jacobian of the input row at p: x, y, z directly;
 // Fourier columns d sin(w p_a)/dp_a = w cos(w p_a), d cos(w p_a)/dp_a =
@@ -656,7 +710,11 @@ __device__ inline void input_vjp(const typename CF::E* row, const LatentSrc& ls,
       g[a] = fmaf(wk, fmaf(u[F + 3 * k + a], c, -u[F + 3 * L + 3 * k + a] * s), g[a]);
     }
   }
-  latent_vjp<F>(ls, px, py, pz, u, g);
+  if constexpr (CF::P == kF16 && CF::GK == 1) {  // FP16 network on an FP16 grid
+    latent_vjp_h<F>(ls, px, py, pz, reinterpret_cast<const h2*>(row), g);
+  } else {
+    latent_vjp<F>(ls, px, py, pz, u, g);
+  }
 }
 
 }  // namespace fvsrn_detail
