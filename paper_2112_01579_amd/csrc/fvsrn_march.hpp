@@ -25,7 +25,10 @@ enum { kShadeNone = 0, kShadeFwd = 1, kShadeFD = 2, kShadePred = 3, kShadeAdj = 
 
 // Waves per workgroup cap (sets the VGPR budget through the launch bounds):
 // value-mode networks with the packed FP16 latent path fit 4 waves per SIMD
-// (<= 128 VGPRs), other value-mode networks 3 (<= 168), forward mode 2.
+// (<= 128 VGPRs), other value-mode networks 3 (<= 168). Forward mode: 3 for
+// the c = 32 FP16 network on a packed grid (a few spills outside the hot
+// loop; measured 9% faster than 2), 2 otherwise (c = 48 spills inside the
+// sample loop at 168 VGPRs and was measured 15% slower).
 // Central differences add the neighbour offsets and the gradient gather to
 // the value-mode network; with F = 16 channels gathered in FP32 (c = 48, or
 // an FP16 network on an FP32 grid) that needs 2 waves per SIMD, c = 48 with
@@ -33,7 +36,8 @@ enum { kShadeNone = 0, kShadeFwd = 1, kShadeFD = 2, kShadePred = 3, kShadeAdj = 
 // derivatives of two N-tiles in registers: 2 waves per SIMD.
 template <class CF, int MODE>
 constexpr int max_waves() {
-  if (MODE == kShadeFwd || MODE == kShadeAdj) return 8;
+  if (MODE == kShadeAdj) return 8;
+  if (MODE == kShadeFwd) return (CF::P == kF16 && CF::C == 32 && CF::G16) ? 12 : 8;
   if (MODE == kShadeFD) {
     if (CF::F == 16 && (CF::C == 48 || (CF::P == kF16 && !CF::G16))) return 8;
     return (CF::G16 && CF::C == 32) ? 16 : 12;

@@ -585,6 +585,9 @@ __device__ inline void write_features(typename CF::E* row, const LatentSrc& ls, 
         v[F + 3 * L + 3 * k + a] = c;
       }
     }
+    // forward mode: keep each octave's work together, which lowers the
+    // register peak of the feature build
+    if constexpr (GRAD) __builtin_amdgcn_sched_barrier(0);
   }
   if constexpr (GRAD) {
     v[G::KMAIN + 0] = role.is_val ? px : (role.axis == 0 ? 1.0f : 0.0f);
