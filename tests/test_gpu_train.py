@@ -57,6 +57,30 @@ def test_train_gradients_l1(FV, spec_name):
     assert abs(loss.item() - loss_ref) <= 1e-5 * abs(loss_ref) + 1e-7
 
 
+def test_train_gradients_full_batch(FV):
+    """The training workload's launch configuration: the 16^3 x 8, 3 x 32
+    network and a full batch of 2^18 points (2048 waves of eight 16-point
+    chunks, eight reduction groups, the cell scan over 3,375 cells) against
+    the oracle's gradients and loss for the same points and targets."""
+    spec = I.NET_SMALL
+    n = 1 << 18
+    gnet, onet, xyz = _setup(FV, spec, 17, n)
+    d = O.eval_points(onet, xyz)
+    rng = np.random.default_rng(18)
+    off = rng.uniform(0.01, 0.3, n) * rng.choice([-1, 1], n)
+    target = (d + off).astype(np.float32)
+    dl_ref, dw_ref, loss_ref = O.train_grads(onet, xyz, target=target.astype(np.float64))
+    d_lat = torch.empty_like(gnet.latent)
+    d_w = torch.empty_like(gnet.weights)
+    loss = torch.zeros(1, device="cuda")
+    FV.fvsrn_train_step(gnet, d_lat, d_w, torch.from_numpy(xyz).cuda(), target=torch.from_numpy(target).cuda(),
+                        out_loss=loss)
+    e_w, e_l = _rel(d_w.cpu().numpy(), dw_ref), _rel(d_lat.cpu().numpy(), dl_ref)
+    print("train full batch: dW rel err %.3g, dG rel err %.3g" % (e_w, e_l), flush=True)
+    assert e_w <= 1e-4 and e_l <= 1e-4
+    assert abs(loss.item() - loss_ref) <= 1e-5 * abs(loss_ref) + 1e-7
+
+
 def test_train_gradients_many_chunks_per_wave(FV):
     """More points than waves x chunk: waves walk several chunks and the
     reduction runs over every group of wave slices."""
