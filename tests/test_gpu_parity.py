@@ -191,6 +191,23 @@ def test_eval_points_edge_sizes(FV):
     assert out.numel() == 0
 
 
+def test_eval_points_full_size_sampled(FV):
+    """The point-evaluation workload at its full size: 2^24 uniform points
+    through the study network (FP16 network on the FP16 grid, and FP32), in
+    one call as the benchmark makes it; 20,000 sampled points against the
+    oracle, among them the first and last (grid-stride tail)."""
+    n = 1 << 24
+    for prec, gd, tol in (("f16", FV.F16, FP16_TOL), ("f32", FV.F32, FP32_TOL)):
+        gnet, onet = _nets(FV, I.NET_STUDY, I.SEED_STUDY, grid_dtype=gd)
+        xyz = torch.rand((n, 3), generator=torch.Generator().manual_seed(46)) * 2 - 1
+        out = FV.fvsrn_eval_points(gnet, xyz.cuda(), 0.0, prec).cpu().numpy()
+        idx = np.concatenate([[0, n - 1], np.random.default_rng(47).integers(0, n, 19998)])
+        ref = O.eval_points(onet, xyz.numpy()[idx])
+        err = np.abs(out[idx] - ref).max()
+        _report("eval_points 2^24 %s sampled" % prec, err)
+        assert out.shape == (n,) and err <= tol
+
+
 # -------------------------------------------------- study-network renders
 
 def test_study_render_small_ragged(FV):
