@@ -246,6 +246,28 @@ def test_study_full_size_sampled_pixels(FV):
     assert err <= FP16_TOL
 
 
+def test_study_full_size_fp32_and_dense_sampled_pixels(FV):
+    """The other two renders of the benchmark at full size: the FP32 network
+    (FP32 grid) with ERT off, and dense-grid DVR of the 256^3 volume, on
+    sampled pixels against the oracle."""
+    gnet, onet = _nets(FV, I.NET_STUDY, I.SEED_STUDY)
+    tf = I.ramp_tf()
+    cams = I.study_cameras(1024, 1024, 8)
+    m = I.study_march(0.0)
+    pix = np.random.default_rng(4).choice(8 * 1024 * 1024, 128, replace=False)
+    ref, _ = O.render(O.Field(net=onet), tf, cams, m, pixels=pix)
+    img = FV.fvsrn_render(gnet, tf, cams, m, "f32").cpu().numpy().reshape(-1, 4)
+    err = np.abs(img[pix] - ref.reshape(-1, 4)[pix]).max()
+    _report("study full-size f32 sampled", err)
+    assert err <= FP32_TOL
+    vol = I.gaussian_volume(256, 64, seed=I.SEED_STUDY)
+    dref, _ = O.render(O.Field(vol=vol), tf, cams, m, pixels=pix)
+    dimg = FV.fvsrn_render_dense(torch.from_numpy(vol).cuda(), tf, cams, m).cpu().numpy().reshape(-1, 4)
+    err = np.abs(dimg[pix] - dref.reshape(-1, 4)[pix]).max()
+    _report("dense 256^3 full-size sampled", err)
+    assert err <= FP32_TOL
+
+
 @pytest.mark.parametrize("grad_mode", [0, 3], ids=["forward", "adjoint"])
 def test_shaded_full_size_sampled_pixels(FV, grad_mode):
     """The shaded workload at its full size: the 64^3 x 16, 4 x 48 network on
