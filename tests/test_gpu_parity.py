@@ -268,6 +268,23 @@ def test_study_full_size_fp32_and_dense_sampled_pixels(FV):
     assert err <= FP32_TOL
 
 
+def test_study_full_size_bf16_and_uint8_sampled_pixels(FV):
+    """The BF16 network and the FP16 network on the uint8 grid at the
+    benchmark's full size (8 x 1024^2, ERT 1e-3), sampled pixels against the
+    oracle (which reads the same codes and de-quantisation)."""
+    tf = I.ramp_tf()
+    cams = I.study_cameras(1024, 1024, 8)
+    m = I.study_march(1e-3)
+    pix = np.random.default_rng(5).choice(8 * 1024 * 1024, 128, replace=False)
+    for prec, gd, tol in (("bf16", FV.F16, BF16_TOL), ("f16", FV.U8, FP16_TOL)):
+        gnet, onet = _nets(FV, I.NET_STUDY, I.SEED_STUDY, grid_dtype=gd)
+        ref, _ = O.render(O.Field(net=onet), tf, cams, m, pixels=pix)
+        img = FV.fvsrn_render(gnet, tf, cams, m, prec).cpu().numpy().reshape(-1, 4)
+        err = np.abs(img[pix] - ref.reshape(-1, 4)[pix]).max()
+        _report("study full-size %s grid %d sampled" % (prec, gd), err)
+        assert err <= tol
+
+
 @pytest.mark.parametrize("grad_mode", [0, 3], ids=["forward", "adjoint"])
 def test_shaded_full_size_sampled_pixels(FV, grad_mode):
     """The shaded workload at its full size: the 64^3 x 16, 4 x 48 network on
