@@ -34,7 +34,9 @@ UNITS = [
     ("fvsrn_time.hip", ["-DFVSRN_PREC=1"], "time_f16.o"),
     ("fvsrn_rff.hip", ["-DFVSRN_PREC=0"], "rff_f32.o"),
     ("fvsrn_rff.hip", ["-DFVSRN_PREC=1"], "rff_f16.o"),
-    ("fvsrn_train.hip", [], "train.o"),
+    # the training kernels schedule for instruction-level parallelism (measured
+    # 5% faster per step; the render kernels are faster with the default)
+    ("fvsrn_train.hip", ["-mllvm", "-amdgpu-sched-strategy=max-ilp"], "train.o"),
 ]
 
 HIPCC_FLAGS = [
