@@ -308,11 +308,13 @@ def main():
         for name, m in (("none", march), ("forward", m_dense),
                         ("central", dataclasses.replace(m_dense, grad_mode=1, fd_step=2.0 / 255)),
                         ("adjoint", dataclasses.replace(m_dense, grad_mode=3))):
-            FV.fvsrn_render(net, tf, cams, m, "f16", out=out)
+            FV.fvsrn_render(net, tf, cams, m, "f16", out=out, stats=stats.zero_())
             torch.cuda.synchronize()
+            ns = int(stats[0].item())
             e, q = rmse(out), ssim(out)
             per_c, _ = time_launches(lambda: FV.fvsrn_render(net, tf, cams, m, "f16", out=out), 3, 1)
-            shade[name] = {"ms_per_frame": float(np.mean(per_c)) / len(cams)}
+            shade[name] = {"ms_per_frame": float(np.mean(per_c)) / len(cams),
+                           "samples_per_s": ns / (float(np.mean(per_c)) * 1e-3)}
             if m.phong:
                 shade[name]["image_rmse_vs_dense_phong"] = e
                 shade[name]["image_ssim_vs_dense_phong"] = q
@@ -336,11 +338,13 @@ def main():
             pnet = FV.Network(spec4, p32.latent.cpu().numpy(), p32.weights.cpu().numpy(), grid_dtype=FV.F16,
                               device=dev)
             m_pred = dataclasses.replace(m_dense, grad_mode=2)
-            FV.fvsrn_render(pnet, tf, cams, m_pred, "f16", out=out)
+            FV.fvsrn_render(pnet, tf, cams, m_pred, "f16", out=out, stats=stats.zero_())
             torch.cuda.synchronize()
+            ns = int(stats[0].item())
             e, q = rmse(out), ssim(out)
             per_c, _ = time_launches(lambda: FV.fvsrn_render(pnet, tf, cams, m_pred, "f16", out=out), 3, 1)
             shade["predicted"] = {"ms_per_frame": float(np.mean(per_c)) / len(cams),
+                                  "samples_per_s": ns / (float(np.mean(per_c)) * 1e-3),
                                   "image_rmse_vs_dense_phong": e, "image_ssim_vs_dense_phong": q,
                                   "training": {"steps": args.train_steps, "batch": 1 << 18,
                                                "grad_weight": PRED_GRAD_WEIGHT, "final_loss": float(ptr.loss.item()),

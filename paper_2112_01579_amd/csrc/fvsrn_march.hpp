@@ -174,10 +174,14 @@ __device__ inline void segment(const Ray& r, int i, bool fixed, float& tm, float
 // Headlight Blinn-Phong (Sec. 6): light and view along -dir, normal = the
 // normalized density gradient.
 __device__ inline void phong(float rgba[4], float gx, float gy, float gz, const float dir[3], const MarchDev& m) {
-  const float gl = sqrtf(gx * gx + gy * gy + gz * gz);
-  if (gl >= 1e-6f) {
-    const float ndl = fabsf(gx * dir[0] + gy * dir[1] + gz * dir[2]) / gl;
-    const float spec = m.ks * powf(ndl, m.shininess);
+  const float g2 = gx * gx + gy * gy + gz * gz;
+  if (g2 >= 1e-12f) {  // |g| >= 1e-6
+    // |n . l| with n = g / |g| by the hardware reciprocal square root, and
+    // |n . l|^shininess as exp2(shininess * log2(.)) on the hardware
+    // transcendentals (the library sqrt, divide and powf cost about 200
+    // instructions per sample); the floor keeps log2 finite, so 0^0 = 1
+    const float ndl = fabsf(gx * dir[0] + gy * dir[1] + gz * dir[2]) * __builtin_amdgcn_rsqf(g2);
+    const float spec = m.ks * __builtin_amdgcn_exp2f(m.shininess * __builtin_amdgcn_logf(fmaxf(ndl, 1e-30f)));
     const float k = m.ka + m.kd * ndl;
     rgba[0] = fmaf(rgba[0], k, spec);
     rgba[1] = fmaf(rgba[1], k, spec);
