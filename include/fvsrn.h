@@ -152,7 +152,8 @@ typedef struct {
    march stops after a sample once T < ert_eps (0 disables early ray
    termination). phong != 0 shades rgb with a headlight Blinn-Phong term from
    the normalized density gradient n: rgb (ka + kd |n.l|) + ks |n.l|^shininess
-   (Sec. 6), gradients below 1e-6 in length leave rgb unshaded. For the
+   (Sec. 6), gradients below 1e-6 in length leave rgb unshaded; ka, kd, ks
+   and shininess must be finite, non-negative and at most 1e6. For the
    network, grad_mode selects how the gradient is obtained (Sec. 6):
    FVSRN_GRAD_FORWARD differentiates the network in forward mode;
    FVSRN_GRAD_CENTRAL takes central differences of the network density with
@@ -350,6 +351,11 @@ int64_t fvsrn_num_weights(const fvsrn_net_desc* desc);
 
 const char* fvsrn_status_str(fvsrn_status s);
 const char* fvsrn_last_error(void); /* thread-local detail of the last failing call */
+
+/* SHA-256 (hex) of the sources this library was built from (this header and
+   the HIP/C++ sources), so that a caller can refuse a library that is older
+   than the sources next to it. Static string, never NULL. */
+const char* fvsrn_build_id(void);
 
 #ifdef __cplusplus
 }

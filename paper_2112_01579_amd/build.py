@@ -54,9 +54,23 @@ def hipcc() -> str:
 
 def _sources():
     out = [os.path.join(ROOT, "include", "fvsrn.h")]
-    for f in os.listdir(CSRC):
+    for f in sorted(os.listdir(CSRC)):
         out.append(os.path.join(CSRC, f))
     return out
+
+
+def source_hash() -> str:
+    """SHA-256 over the header and every file of csrc/ (names and contents):
+    the library records it at build time (fvsrn_build_id), and the binding
+    refuses a library whose record differs from the sources beside it."""
+    import hashlib
+    h = hashlib.sha256()
+    for path in _sources():
+        h.update(os.path.relpath(path, ROOT).encode() + b"\0")
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+        h.update(b"\0")
+    return h.hexdigest()
 
 
 def _run(cmd, cwd=None):
@@ -174,7 +188,10 @@ def build(force: bool = True, verbose: bool = False, jobs: int = 0) -> str:
     os.makedirs(BUILD, exist_ok=True)
     units = [u for u in UNITS if os.path.exists(os.path.join(CSRC, u[0]))]
     cmds = []
+    src_hash = source_hash()
     for src, defs, obj in units:
+        if src == "fvsrn_api.cpp":
+            defs = defs + ['-DFVSRN_SOURCE_HASH="%s"' % src_hash]
         # each unit keeps its intermediate files (device assembly included) in
         # a folder of its own
         tmp = os.path.join(BUILD, obj[:-2])

@@ -233,6 +233,15 @@ fvsrn_status check_cams(const fvsrn_camera* cams, int32_t n_views, const fvsrn_m
     return fail(FVSRN_ERR_INVALID_ARGUMENT, "grad_mode unknown");
   if (m->phong && m->grad_mode == FVSRN_GRAD_CENTRAL && !(m->fd_step > 0.0f && m->fd_step < 1.0f))
     return fail(FVSRN_ERR_INVALID_ARGUMENT, "fd_step must be in (0, 1) for central differences");
+  // Phong coefficients: finite and non-negative (a negative shininess would
+  // raise |n.l| = 0 to an infinite power)
+  if (m->phong) {
+    const float k[4] = {m->ka, m->kd, m->ks, m->shininess};
+    static const char* names[4] = {"ka", "kd", "ks", "shininess"};
+    for (int j = 0; j < 4; ++j)
+      if (!(k[j] >= 0.0f && k[j] <= 1.0e6f))
+        return fail(FVSRN_ERR_INVALID_ARGUMENT, "phong %s must be finite, >= 0 and <= 1e6", names[j]);
+  }
   return FVSRN_OK;
 }
 
@@ -283,6 +292,11 @@ const char* fvsrn_status_str(fvsrn_status s) {
 }
 
 const char* fvsrn_last_error(void) { return g_err; }
+
+#ifndef FVSRN_SOURCE_HASH
+#error "FVSRN_SOURCE_HASH must be defined by the build (hash of the sources)"
+#endif
+const char* fvsrn_build_id(void) { return FVSRN_SOURCE_HASH; }
 
 fvsrn_status fvsrn_render(const fvsrn_net_desc* desc, const fvsrn_params* params, const fvsrn_tf* tf,
                           const fvsrn_camera* cams, int32_t n_views, const fvsrn_march* march,

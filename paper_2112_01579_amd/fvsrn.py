@@ -30,7 +30,7 @@ EXPORTS = (
     "fvsrn_train_workspace_size", "fvsrn_render_dense", "fvsrn_dense_eval_points", "fvsrn_dense_grad_points",
     "fvsrn_sample_points", "fvsrn_cast_grid", "fvsrn_quantize_grid", "fvsrn_ssim_map", "fvsrn_num_weights",
     "fvsrn_voxel_points", "fvsrn_error_grid", "fvsrn_sample_points_weighted", "fvsrn_weighted_points_workspace_size",
-    "fvsrn_status_str", "fvsrn_last_error",
+    "fvsrn_status_str", "fvsrn_last_error", "fvsrn_build_id",
 )
 
 
@@ -38,6 +38,13 @@ class FvsrnError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(msg)
         self.status = status
+
+
+class FvsrnArgumentError(FvsrnError, ValueError):
+    """A tensor argument the binding refuses before anything reaches the library."""
+
+    def __init__(self, msg: str):
+        super().__init__(ERR_INVALID_ARGUMENT, msg)
 
 
 class NetDesc(C.Structure):
@@ -110,10 +117,16 @@ def lib():
             "fvsrn_weighted_points_workspace_size": (sz, [i32]),
             "fvsrn_status_str": (C.c_char_p, [st]),
             "fvsrn_last_error": (C.c_char_p, []),
+            "fvsrn_build_id": (C.c_char_p, []),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
             f.restype, f.argtypes = res, args
+        from .build import source_hash
+        built, here = L.fvsrn_build_id().decode(), source_hash()
+        if built != here:
+            raise RuntimeError("libfvsrn.so was built from other sources (build id %s..., sources %s...); "
+                               "rebuild with paper_2112_01579_amd.build.build()" % (built[:12], here[:12]))
         _lib = L
     return _lib
 
@@ -127,6 +140,44 @@ def _check(status: int, what: str):
 
 def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def check_tensor(t, name: str, dtype=torch.float32, shape=None, numel=None, device=None):
+    """Validates a tensor handed to the library: a torch tensor of ``dtype``,
+    of the given shape (None entries match any size) or element count,
+    contiguous, and on a GPU (``device`` when given). Raises
+    FvsrnArgumentError before any library call."""
+    if not isinstance(t, torch.Tensor):
+        raise FvsrnArgumentError("%s must be a torch tensor, got %s" % (name, type(t).__name__))
+    if t.dtype != dtype:
+        raise FvsrnArgumentError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if shape is not None and (t.dim() != len(shape) or
+                              any(w is not None and w != g for w, g in zip(shape, t.shape))):
+        raise FvsrnArgumentError("%s must have shape %s, got %s" % (
+            name, tuple("*" if w is None else w for w in shape), tuple(t.shape)))
+    if numel is not None and t.numel() != numel:
+        raise FvsrnArgumentError("%s must hold %d elements, got %d" % (name, numel, t.numel()))
+    if not t.is_contiguous():
+        raise FvsrnArgumentError("%s must be contiguous" % name)
+    if t.device.type != "cuda":
+        raise FvsrnArgumentError("%s must be on a GPU, got %s" % (name, t.device))
+    if device is not None and t.device != torch.device(device):
+        raise FvsrnArgumentError("%s must be on %s, got %s" % (name, device, t.device))
+    return t
+
+
+def _check_net(net: "Network"):
+    check_tensor(net.weights, "net.weights", numel=net.spec.n_weights)
+    dev = net.weights.device
+    want = {F32: torch.float32, F16: torch.float16, U8: torch.uint8}[net.grid_dtype]
+    check_tensor(net.latent, "net.latent", dtype=want, numel=net.spec.n_latent, device=dev)
+    if net.dequant is not None:
+        check_tensor(net.dequant, "net.dequant", numel=net.spec.K * net.spec.F * 2, device=dev)
+    return dev
+
+
+def _check_points(xyz, dev):
+    return check_tensor(xyz, "xyz", shape=(None, 3), device=dev)
 
 
 def _stream(stream=None):
@@ -231,9 +282,12 @@ def fvsrn_render(net: Network, tf: I.TF, cams: Sequence[I.Camera], march: I.Marc
                  precision="f32", out: Optional[torch.Tensor] = None,
                  stats: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
     cams = list(cams)
+    dev = _check_net(net)
     if out is None:
-        out = torch.empty((len(cams), cams[0].height, cams[0].width, 4), dtype=torch.float32,
-                          device=net.weights.device)
+        out = torch.empty((len(cams), cams[0].height, cams[0].width, 4), dtype=torch.float32, device=dev)
+    check_tensor(out, "out", shape=(len(cams), cams[0].height, cams[0].width, 4), device=dev)
+    if stats is not None:
+        check_tensor(stats, "stats", dtype=torch.int64, numel=3, device=dev)
     d, p, t, cs, m = net.desc(precision), net.params(), tf_struct(tf), camera_structs(cams), march_struct(march)
     _check(lib().fvsrn_render(C.byref(d), C.byref(p), C.byref(t), cs, len(cams), C.byref(m), _ptr(out),
                               _ptr(stats), _stream(stream)), "fvsrn_render")
@@ -242,9 +296,12 @@ def fvsrn_render(net: Network, tf: I.TF, cams: Sequence[I.Camera], march: I.Marc
 
 def fvsrn_eval_points(net: Network, xyz: torch.Tensor, time: float = 0.0, precision="f32",
                       out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    dev = _check_net(net)
+    _check_points(xyz, dev)
     n = xyz.shape[0]
     if out is None:
         out = torch.empty(n, dtype=torch.float32, device=xyz.device)
+    check_tensor(out, "out", numel=n, device=dev)
     d, p = net.desc(precision), net.params()
     _check(lib().fvsrn_eval_points(C.byref(d), C.byref(p), _ptr(xyz), n, time, _ptr(out), _stream(stream)),
            "fvsrn_eval_points")
@@ -258,6 +315,10 @@ def fvsrn_grad_points(net: Network, xyz: torch.Tensor, time: float = 0.0, precis
                       stream=None):
     """Density and d density / d p at points: forward mode, adjoint (reverse
     mode) or a 4-output network's predicted gradient (``mode``)."""
+    dev = _check_net(net)
+    _check_points(xyz, dev)
+    if mode not in GRAD_MODES:
+        raise FvsrnArgumentError("mode must be one of %s" % sorted(GRAD_MODES))
     n = xyz.shape[0]
     dens = torch.empty(n, dtype=torch.float32, device=xyz.device)
     grad = torch.empty((n, 3), dtype=torch.float32, device=xyz.device)
@@ -276,10 +337,14 @@ def fvsrn_render_dense(vol: torch.Tensor, tf: I.TF, cams: Sequence[I.Camera], ma
                        out: Optional[torch.Tensor] = None, stats: Optional[torch.Tensor] = None,
                        stream=None) -> torch.Tensor:
     cams = list(cams)
+    check_tensor(vol, "vol", shape=(None, None, None))
     nz, ny, nx = vol.shape
     if out is None:
         out = torch.empty((len(cams), cams[0].height, cams[0].width, 4), dtype=torch.float32,
                           device=vol.device)
+    check_tensor(out, "out", shape=(len(cams), cams[0].height, cams[0].width, 4), device=vol.device)
+    if stats is not None:
+        check_tensor(stats, "stats", dtype=torch.int64, numel=3, device=vol.device)
     t, cs, m = tf_struct(tf), camera_structs(cams), march_struct(march)
     _check(lib().fvsrn_render_dense(_ptr(vol), nx, ny, nz, C.byref(t), cs, len(cams), C.byref(m), _ptr(out),
                                     _ptr(stats), _stream(stream)), "fvsrn_render_dense")
@@ -287,10 +352,13 @@ def fvsrn_render_dense(vol: torch.Tensor, tf: I.TF, cams: Sequence[I.Camera], ma
 
 
 def fvsrn_dense_eval_points(vol: torch.Tensor, xyz: torch.Tensor, out=None, stream=None):
+    check_tensor(vol, "vol", shape=(None, None, None))
+    _check_points(xyz, vol.device)
     nz, ny, nx = vol.shape
     n = xyz.shape[0]
     if out is None:
         out = torch.empty(n, dtype=torch.float32, device=xyz.device)
+    check_tensor(out, "out", numel=n, device=vol.device)
     _check(lib().fvsrn_dense_eval_points(_ptr(vol), nx, ny, nz, _ptr(xyz), n, _ptr(out), _stream(stream)),
            "fvsrn_dense_eval_points")
     return out
@@ -298,10 +366,14 @@ def fvsrn_dense_eval_points(vol: torch.Tensor, xyz: torch.Tensor, out=None, stre
 
 def fvsrn_dense_grad_points(vol: torch.Tensor, xyz: torch.Tensor, out=None, out_grad=None, stream=None):
     """Trilinear samples of a dense grid and their one-voxel central-difference gradients."""
+    check_tensor(vol, "vol", shape=(None, None, None))
+    _check_points(xyz, vol.device)
     nz, ny, nx = vol.shape
     n = xyz.shape[0]
     dens = out if out is not None else torch.empty(n, dtype=torch.float32, device=xyz.device)
     grad = out_grad if out_grad is not None else torch.empty((n, 3), dtype=torch.float32, device=xyz.device)
+    check_tensor(dens, "out", numel=n, device=vol.device)
+    check_tensor(grad, "out_grad", shape=(n, 3), device=vol.device)
     _check(lib().fvsrn_dense_grad_points(_ptr(vol), nx, ny, nz, _ptr(xyz), n, _ptr(dens), _ptr(grad),
                                          _stream(stream)), "fvsrn_dense_grad_points")
     return dens, grad
@@ -310,6 +382,7 @@ def fvsrn_dense_grad_points(vol: torch.Tensor, xyz: torch.Tensor, out=None, out_
 def fvsrn_sample_points(seed: int, counter: int, n: int, out=None, device="cuda", stream=None):
     if out is None:
         out = torch.empty((n, 3), dtype=torch.float32, device=device)
+    check_tensor(out, "out", shape=(n, 3))
     _check(lib().fvsrn_sample_points(seed, counter, n, _ptr(out), _stream(stream)), "fvsrn_sample_points")
     return out
 
@@ -318,6 +391,7 @@ def fvsrn_voxel_points(seed: int, counter: int, G: int, per_voxel: int, out=None
     """per_voxel positions in each of the G^3 voxels (error-grid samples, Sec. 5.4)."""
     if out is None:
         out = torch.empty((G ** 3 * per_voxel, 3), dtype=torch.float32, device=device)
+    check_tensor(out, "out", shape=(G ** 3 * per_voxel, 3))
     _check(lib().fvsrn_voxel_points(seed, counter, G, per_voxel, _ptr(out), _stream(stream)), "fvsrn_voxel_points")
     return out
 
@@ -325,12 +399,19 @@ def fvsrn_voxel_points(seed: int, counter: int, G: int, per_voxel: int, out=None
 def fvsrn_error_grid(net: "Network", vol: torch.Tensor, xyz: torch.Tensor, per_voxel: int, time: float = 0.0,
                      out=None, scratch=None, stream=None):
     """Mean |density - trilinear target| per voxel (Sec. 5.4), FP32 network."""
+    dev = _check_net(net)
+    check_tensor(vol, "vol", shape=(None, None, None), device=dev)
+    _check_points(xyz, dev)
+    if per_voxel < 1 or xyz.shape[0] % per_voxel:
+        raise FvsrnArgumentError("xyz must hold a whole number of voxels of per_voxel points")
     nz, ny, nx = vol.shape
     nvox = xyz.shape[0] // per_voxel
     if out is None:
         out = torch.empty(nvox, dtype=torch.float32, device=xyz.device)
     if scratch is None:
         scratch = torch.empty(nvox * per_voxel, dtype=torch.float32, device=xyz.device)
+    check_tensor(out, "out", numel=nvox, device=dev)
+    check_tensor(scratch, "scratch", numel=nvox * per_voxel, device=dev)
     d, p = net.desc("f32"), net.params()
     _check(lib().fvsrn_error_grid(C.byref(d), C.byref(p), _ptr(vol), nx, ny, nz, _ptr(xyz), nvox, per_voxel, time,
                                   _ptr(out), _ptr(scratch), _stream(stream)), "fvsrn_error_grid")
@@ -340,16 +421,24 @@ def fvsrn_error_grid(net: "Network", vol: torch.Tensor, xyz: torch.Tensor, per_v
 def fvsrn_sample_points_weighted(seed: int, counter: int, E: torch.Tensor, G: int, n: int, out=None,
                                  workspace=None, stream=None):
     """n positions drawn in proportion to the error grid E [G^3] (Sec. 5.4)."""
+    check_tensor(E, "E", numel=G ** 3)
     if out is None:
         out = torch.empty((n, 3), dtype=torch.float32, device=E.device)
+    check_tensor(out, "out", shape=(n, 3), device=E.device)
     if workspace is None:
         workspace = torch.empty(lib().fvsrn_weighted_points_workspace_size(G), dtype=torch.uint8, device=E.device)
+    check_tensor(workspace, "workspace", dtype=torch.uint8, device=E.device)
     _check(lib().fvsrn_sample_points_weighted(seed, counter, _ptr(E), G, n, _ptr(out), _ptr(workspace),
                                               workspace.numel(), _stream(stream)), "fvsrn_sample_points_weighted")
     return out
 
 
 def fvsrn_cast_grid(src: torch.Tensor, dst: torch.Tensor, dtype: int = F16, stream=None):
+    if dtype not in (F16, BF16):
+        raise FvsrnArgumentError("dtype must be F16 or BF16")
+    check_tensor(src, "src")
+    check_tensor(dst, "dst", dtype=torch.float16 if dtype == F16 else torch.bfloat16, numel=src.numel(),
+                 device=src.device)
     _check(lib().fvsrn_cast_grid(_ptr(src), _ptr(dst), src.numel(), dtype, _stream(stream)),
            "fvsrn_cast_grid")
     return dst
@@ -357,10 +446,15 @@ def fvsrn_cast_grid(src: torch.Tensor, dst: torch.Tensor, dtype: int = F16, stre
 
 def fvsrn_ssim_map(a: torch.Tensor, b: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None):
     """SSIM maps of [n][H][W][4] (or [H][W][4]) image pairs: [n][H-10][W-10]."""
+    if a.dim() < 3 or a.shape[-1] != 4:
+        raise FvsrnArgumentError("images must be [..., H, W, 4] RGBA")
+    check_tensor(a, "a")
+    check_tensor(b, "b", shape=tuple(a.shape), device=a.device)
     a4 = a.reshape(-1, a.shape[-3], a.shape[-2], 4)
     n, H, W = a4.shape[0], a4.shape[1], a4.shape[2]
     if out is None:
         out = torch.empty((n, H - 10, W - 10), dtype=torch.float32, device=a.device)
+    check_tensor(out, "out", numel=n * max(H - 10, 0) * max(W - 10, 0), device=a.device)
     _check(lib().fvsrn_ssim_map(_ptr(a), _ptr(b), W, H, n, _ptr(out), _stream(stream)), "fvsrn_ssim_map")
     return out
 
@@ -374,11 +468,16 @@ def fvsrn_quantize_grid(src: torch.Tensor, channels: int, codes: Optional[torch.
                         dequant: Optional[torch.Tensor] = None, stream=None):
     """uint8 codes and (offset, scale) per channel of one keyframe grid
     (src FP32 [..., channels] on the device)."""
+    if channels < 1 or src.numel() % channels:
+        raise FvsrnArgumentError("src must hold a whole number of %d-channel vertices" % channels)
+    check_tensor(src, "src")
     n = src.numel() // channels
     if codes is None:
         codes = torch.empty(src.numel(), dtype=torch.uint8, device=src.device)
     if dequant is None:
         dequant = torch.empty((channels, 2), dtype=torch.float32, device=src.device)
+    check_tensor(codes, "codes", dtype=torch.uint8, numel=src.numel(), device=src.device)
+    check_tensor(dequant, "dequant", numel=channels * 2, device=src.device)
     _check(lib().fvsrn_quantize_grid(_ptr(src), n, channels, _ptr(codes), _ptr(dequant), _stream(stream)),
            "fvsrn_quantize_grid")
     return codes, dequant
@@ -405,11 +504,28 @@ def fvsrn_train_step(net: Network, d_latent: torch.Tensor, d_weights: torch.Tens
     gradient, weighted by ``grad_weight``. ``adam`` is a dict with
     lr_grid, lr_mlp, beta1, beta2, eps, step and the four moment tensors
     m_latent, v_latent, m_weights, v_weights; None computes gradients only."""
+    dev = _check_net(net)
+    if net.grid_dtype != F32:
+        raise FvsrnArgumentError("training needs an FP32 latent grid")
+    _check_points(xyz, dev)
     n = xyz.shape[0]
+    check_tensor(d_latent, "d_latent", numel=net.spec.n_latent, device=dev)
+    check_tensor(d_weights, "d_weights", numel=net.spec.n_weights, device=dev)
+    for name, t, shp in (("target", target, (n,)), ("dloss_dy", dloss_dy, (n,)), ("times", times, (n,)),
+                         ("target_grad", target_grad, (n, 3))):
+        if t is not None:
+            check_tensor(t, name, shape=shp, device=dev)
+    if out_loss is not None:
+        check_tensor(out_loss, "out_loss", numel=1, device=dev)
+    if adam is not None:
+        for k, cnt in (("m_latent", net.spec.n_latent), ("v_latent", net.spec.n_latent),
+                       ("m_weights", net.spec.n_weights), ("v_weights", net.spec.n_weights)):
+            check_tensor(adam[k], "adam[%s]" % k, numel=cnt, device=dev)
     d = net.desc("f32")
     if workspace is None:
         ws = lib().fvsrn_train_workspace_size(C.byref(d), n)
         workspace = torch.empty(max(ws, 16), dtype=torch.uint8, device=xyz.device)
+    check_tensor(workspace, "workspace", dtype=torch.uint8, device=dev)
     a = None
     if adam is not None:
         a = AdamStruct(adam["lr_grid"], adam["lr_mlp"], adam.get("beta1", 0.9), adam.get("beta2", 0.999),

@@ -5,8 +5,9 @@ network. Every step runs in the HIP library: point sampling, target lookup,
 the fused forward/backward kernel, the gradient reduction and Adam.
 
 Also provides ``FvsrnPoints``, a torch.autograd.Function whose forward is
-fvsrn_eval_points and whose backward is fvsrn_train_step in VJP mode, so the
-fV-SRN can sit inside any torch loss.
+fvsrn_eval_points and whose backward is fvsrn_train_step in VJP mode (latent
+grid and weights) and fvsrn_grad_points (positions), so the fV-SRN can sit
+inside any torch loss.
 """
 from __future__ import annotations
 
@@ -130,27 +131,45 @@ class Trainer:
 
 
 class FvsrnPoints(torch.autograd.Function):
-    """density = fV-SRN(xyz) with gradients for the latent grid and weights.
+    """density = fV-SRN(xyz, time), differentiable in xyz, the latent grid and
+    the weights.
 
-    ``latent`` and ``weights`` are the network's own tensors (passed so that
-    autograd tracks them); gradients w.r.t. ``xyz`` are not provided."""
+    ``latent`` and ``weights`` must be the network's own tensors (passed so
+    that autograd tracks them and torch's version counters catch an in-place
+    update between forward and backward). Forward runs fvsrn_eval_points in
+    ``precision``; the parameter gradients come from fvsrn_train_step in VJP
+    mode (the FP32 network, each point at ``time``), the position gradient
+    from fvsrn_grad_points in reverse mode (adjoint) at ``precision``, scaled
+    by the upstream gradient."""
 
     @staticmethod
-    def forward(ctx, xyz: torch.Tensor, latent: torch.Tensor, weights: torch.Tensor, net: FV.Network):
-        assert latent.data_ptr() == net.latent.data_ptr() and weights.data_ptr() == net.weights.data_ptr()
-        ctx.net = net
-        ctx.save_for_backward(xyz)
-        return FV.fvsrn_eval_points(net, xyz.contiguous(), 0.0, "f32")
+    def forward(ctx, xyz: torch.Tensor, latent: torch.Tensor, weights: torch.Tensor, net: FV.Network,
+                time: float = 0.0, precision: str = "f32"):
+        if latent.data_ptr() != net.latent.data_ptr() or weights.data_ptr() != net.weights.data_ptr():
+            raise FV.FvsrnArgumentError("latent and weights must be the network's own tensors")
+        ctx.net, ctx.time, ctx.precision = net, float(time), precision
+        xyz = xyz.contiguous()
+        ctx.save_for_backward(xyz, latent, weights)
+        return FV.fvsrn_eval_points(net, xyz, ctx.time, precision)
 
     @staticmethod
     def backward(ctx, grad_out: torch.Tensor):
-        (xyz,) = ctx.saved_tensors
+        xyz, latent, weights = ctx.saved_tensors  # raises if modified in place since forward
         net = ctx.net
-        d_lat = torch.empty_like(net.latent)
-        d_w = torch.empty_like(net.weights)
-        FV.fvsrn_train_step(net, d_lat, d_w, xyz.contiguous(), dloss_dy=grad_out.contiguous().float())
-        return None, d_lat, d_w, None
+        g = grad_out.contiguous().float()
+        d_xyz = d_lat = d_w = None
+        if ctx.needs_input_grad[1] or ctx.needs_input_grad[2]:
+            d_lat = torch.empty_like(latent)
+            d_w = torch.empty_like(weights)
+            times = None
+            if net.spec.K > 1 or net.spec.time_enc:
+                times = torch.full((xyz.shape[0],), ctx.time, dtype=torch.float32, device=xyz.device)
+            FV.fvsrn_train_step(net, d_lat, d_w, xyz, dloss_dy=g, times=times)
+        if ctx.needs_input_grad[0]:
+            _, grad = FV.fvsrn_grad_points(net, xyz, ctx.time, ctx.precision, mode="adjoint")
+            d_xyz = grad * g[:, None]
+        return d_xyz, d_lat, d_w, None, None, None
 
 
-def fvsrn_points(net: FV.Network, xyz: torch.Tensor) -> torch.Tensor:
-    return FvsrnPoints.apply(xyz, net.latent, net.weights, net)
+def fvsrn_points(net: FV.Network, xyz: torch.Tensor, time: float = 0.0, precision: str = "f32") -> torch.Tensor:
+    return FvsrnPoints.apply(xyz, net.latent, net.weights, net, time, precision)

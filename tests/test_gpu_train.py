@@ -180,14 +180,64 @@ def test_training_reduces_loss_and_autograd(FV):
     (dens * u).sum().backward()
     d_lat, d_w = torch.empty_like(net.latent), torch.empty_like(net.weights)
     FV.fvsrn_train_step(net, d_lat, d_w, xyz, dloss_dy=u)
-    # dW is reduced in a fixed order (bitwise equal); the latent gradient is
-    # scattered with float atomics, whose order varies between launches, so
-    # the two agree to FP32 rounding of the largest entries
+    # dW is reduced in a fixed order (bitwise equal); the latent gradient sums
+    # each cell's points in the order the counting sort placed them, which
+    # varies between launches, so the two agree to FP32 rounding of the
+    # largest entries
     assert torch.equal(w_p.grad, d_w)
     scale = d_lat.abs().max().item()
     assert torch.allclose(lat_p.grad, d_lat, rtol=0.0, atol=1e-6 * scale)
     net.latent.requires_grad_(False)
     net.weights.requires_grad_(False)
+
+
+def test_autograd_position_gradient_and_time(FV):
+    """fvsrn_points as a torch function of the positions, the latent grids
+    and the weights at a time between two keyframes: d(sum u d)/dxyz is
+    u * grad d (reverse mode through the network, the Fourier features and the
+    trilinear weights, Sec. 6) and the parameter gradients are the VJP of the
+    oracle, both against the FP64 oracle; an in-place update of the weights
+    between forward and backward is refused."""
+    from paper_2112_01579_amd.trainer import fvsrn_points
+    spec = I.NetSpec(R=12, F=8, L=4, c=32, H=3, K=2)
+    keys = [0.0, 4.0]
+    lat, w = I.net_params(spec, 29)
+    net = FV.Network(spec, lat, w, key_times=keys)
+    onet = O.Net(spec, lat, w, key_times=keys)
+    t = 1.3
+    pts = I.uniform_points(901, 5)
+    u = np.random.default_rng(2).normal(size=901).astype(np.float32)
+    xyz = torch.from_numpy(pts).cuda().requires_grad_(True)
+    uu = torch.from_numpy(u).cuda()
+    net.latent.requires_grad_(True)
+    net.weights.requires_grad_(True)
+    try:
+        dens = fvsrn_points(net, xyz, time=t)
+        (dens * uu).sum().backward()
+        d_ref, g_ref = O.grad_points(onet, pts, t)
+        assert np.abs(dens.detach().cpu().numpy() - d_ref).max() <= 1e-5
+        want = u[:, None] * g_ref
+        err = np.abs(xyz.grad.cpu().numpy() - want).max() / np.abs(want).max()
+        print("autograd d/dxyz error (relative to max) %.3g" % err, flush=True)
+        assert err <= 1e-4
+        dl, dw, _ = O.train_grads(onet, pts, dloss_dd=u, times=np.full(901, t))
+        assert np.abs(net.weights.grad.cpu().numpy() - dw).max() <= 1e-4 * np.abs(dw).max()
+        assert np.abs(net.latent.grad.cpu().numpy() - dl).max() <= 1e-4 * np.abs(dl).max()
+        # an in-place change of a saved parameter is caught by torch's version check
+        dens = fvsrn_points(net, xyz, time=t)
+        with torch.no_grad():
+            net.weights.mul_(1.0)
+        with pytest.raises(RuntimeError, match="modified by an inplace operation"):
+            dens.sum().backward()
+        # only the positions: no parameter gradient is computed
+        net.latent.requires_grad_(False)
+        net.weights.requires_grad_(False)
+        xyz.grad = None
+        (fvsrn_points(net, xyz, time=t) * uu).sum().backward()
+        assert np.abs(xyz.grad.cpu().numpy() - want).max() <= 1e-4 * np.abs(want).max()
+    finally:
+        net.latent.requires_grad_(False)
+        net.weights.requires_grad_(False)
 
 
 def test_keyframe_train_gradients(FV):

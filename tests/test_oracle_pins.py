@@ -249,6 +249,65 @@ def test_gradient_against_richardson_central_differences():
         np.testing.assert_allclose(g, fd, rtol=1e-6, atol=1e-8)
 
 
+def test_snakealt_gradient_against_richardson_central_differences():
+    """The SnakeAlt derivative (Sec. 5 Eq. 3) pinned independently of the
+    oracle's derivative code: forward- and reverse-mode position gradients
+    against Richardson central differences of the density, which uses only
+    the activation itself (pinned by its closed form above)."""
+    spec = I.NetSpec(R=8, F=4, L=3, c=12, H=3, act="snakealt")
+    net = make_net(spec, seed=12)
+    h = 1e-3
+    for p in _away_from_faces(spec.R, 12, h):
+        fd = np.zeros(3)
+        for a in range(3):
+            e = np.zeros(3)
+            e[a] = 1
+            c1 = (O.density(net, p + h * e) - O.density(net, p - h * e)) / (2 * h)
+            c2 = (O.density(net, p + h / 2 * e) - O.density(net, p - h / 2 * e)) / h
+            fd[a] = (4 * c2 - c1) / 3
+        for mode in ("fwd", "rev"):
+            _, g = O.density_grad(net, p, mode=mode)
+            np.testing.assert_allclose(g, fd, rtol=1e-6, atol=1e-8)
+    # a wrong derivative of the periodic part (e.g. sin x cos x without the
+    # factor 2, or cos 2x in place of sin 2x) is far outside that bound: the
+    # check above sees gradients of this size
+    _, g = O.density_grad(net, np.array([0.3, -0.2, 0.1]))
+    assert np.abs(g).max() > 1e-2
+
+
+def test_snakealt_train_gradients_against_central_differences():
+    """VJP of sum_i w_i d(x_i) for a SnakeAlt network: weights and latent
+    entries against Richardson central differences (the training side of the
+    SnakeAlt derivative)."""
+    spec = I.NetSpec(R=4, F=3, L=2, c=6, H=2, act="snakealt")
+    net = make_net(spec, seed=23)
+    xyz = RNG.uniform(-1, 1, size=(12, 3))
+    wv = RNG.normal(size=12)
+    dl, dw, _ = O.train_grads(net, xyz, dloss_dd=wv)
+
+    def functional(lat, w):
+        n2 = make_net(spec, latent=lat.reshape(1, 4, 4, 4, 3), weights=w)
+        return float(np.dot(wv, O.eval_points(n2, xyz)))
+
+    h = 1e-4
+
+    def richardson(f, base, e):
+        c1 = (f(base + h * e) - f(base - h * e)) / (2 * h)
+        c2 = (f(base + h / 2 * e) - f(base - h / 2 * e)) / h
+        return (4 * c2 - c1) / 3
+
+    for idx in RNG.choice(spec.n_weights, 25, replace=False):
+        e = np.zeros(spec.n_weights)
+        e[idx] = 1
+        want = richardson(lambda W_: functional(net.latent, W_), net.weights, e)
+        assert abs(dw[idx] - want) < 1e-8 * max(1, abs(want))
+    for idx in RNG.choice(net.latent.size, 25, replace=False):
+        e = np.zeros(net.latent.size)
+        e[idx] = 1
+        want = richardson(lambda L_: functional(L_, net.weights), net.latent, e)
+        assert abs(dl[idx] - want) < 1e-8 * max(1, abs(want))
+
+
 def test_gradient_of_affine_logit_is_closed_form():
     """No Fourier features, identity activation: the logit is affine in p
     inside a latent cell, so grad d = d (1 - d) (a_p + A_z a_z)."""
