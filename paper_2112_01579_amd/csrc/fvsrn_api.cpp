@@ -197,13 +197,13 @@ fvsrn_status make_views(const fvsrn_camera* cams, int n_views, int first, int co
     double u[3] = {r[1] * f[2] - r[2] * f[1], r[2] * f[0] - r[0] * f[2], r[0] * f[1] - r[1] * f[0]};
     for (int a = 0; a < 3; ++a) {
       o.eye[a] = c.eye[a];
-      o.fwd[a] = (float)f[a];
-      o.right[a] = (float)r[a];
-      o.up[a] = (float)u[a];
+      o.fwd[a] = f[a];
+      o.right[a] = r[a];
+      o.up[a] = u[a];
     }
-    o.tan_half = (float)tan((double)c.fov_y_deg * M_PI / 360.0);
+    o.tan_half = tan((double)c.fov_y_deg * M_PI / 360.0);
     o.half_extent = c.ortho_half_extent;
-    o.aspect = (float)((double)c.width / (double)c.height);
+    o.aspect = (double)c.width / (double)c.height;
     o.ortho = c.ortho ? 1 : 0;
     if (d && p) key_blend(d, p, c.time, &o.key, &o.key_w);
     o.tau = d ? time_tau(d, c.time) : 0.0f;

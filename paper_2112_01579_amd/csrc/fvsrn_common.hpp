@@ -175,4 +175,115 @@ __device__ inline void axis_cell(float p, int R, int& i, float& f) {
   axis_cell(p, R, i, f, d);
 }
 
+// ------------------------------------------------------------- rays
+
+// One view ray: origin, unit direction, the chord [t0, t1] inside [-1,1]^3
+// (t0 >= 0), the segment length and count; RayD in FP64, Ray rounded once.
+struct RayD {
+  double o[3], d[3];
+  double t0, t1, ds;
+  int nseg;
+  bool hit;
+};
+
+struct Ray {
+  float o[3], d[3];
+  float t0, t1, ds;
+  int nseg;
+  bool hit;
+};
+
+// Ray of pixel (px, py), row 0 at the top, set up in FP64 (once per ray).
+// Rounded once to FP32 (make_ray), a small direction component keeps its
+// relative precision, where an FP32 set-up leaves it an absolute error that
+// moves a grazing ray's entry into the box by up to that error over the
+// component (1e-5 world units and more). Perspective rays start at the eye;
+// orthographic rays at eye + h (aspect nx right + ny up), along forward.
+// Fixed-step marches cut the chord into m.fixed_steps equal segments, others
+// into ceil(chord / m.step) segments, the last one clipped at t1.
+__device__ inline RayD make_ray_d(const CamDev& cam, int px, int py, int W, int H, const MarchDev& m) {
+  RayD r;
+  const double nx = (2.0 * px + 1.0) / (double)W - 1.0;
+  const double ny = 1.0 - (2.0 * py + 1.0) / (double)H;
+  const double sx = cam.aspect * nx;
+  if (cam.ortho) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      r.o[a] = (double)cam.eye[a] + cam.half_extent * (sx * cam.right[a] + ny * cam.up[a]);
+      r.d[a] = cam.fwd[a];
+    }
+  } else {
+    double l2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      r.o[a] = cam.eye[a];
+      r.d[a] = cam.fwd[a] + cam.tan_half * (sx * cam.right[a] + ny * cam.up[a]);
+      l2 += r.d[a] * r.d[a];
+    }
+    const double inv = 1.0 / sqrt(l2);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) r.d[a] *= inv;
+  }
+  double tn = -INFINITY, tf = INFINITY;
+  bool miss = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (r.d[a] == 0.0) {
+      if (r.o[a] < -1.0 || r.o[a] > 1.0) miss = true;
+    } else {
+      double ta = (-1.0 - r.o[a]) / r.d[a], tb = (1.0 - r.o[a]) / r.d[a];
+      if (ta > tb) {
+        const double s = ta;
+        ta = tb;
+        tb = s;
+      }
+      tn = fmax(tn, ta);
+      tf = fmin(tf, tb);
+    }
+  }
+  tn = fmax(tn, 0.0);
+  r.hit = !miss && tf > tn;
+  r.t0 = tn;
+  r.t1 = r.hit ? tf : tn;
+  if (m.fixed_steps > 0) {
+    r.nseg = r.hit ? m.fixed_steps : 0;
+    r.ds = (r.t1 - r.t0) / (double)m.fixed_steps;
+  } else {
+    r.ds = m.step;
+    r.nseg = r.hit ? (int)ceil((r.t1 - r.t0) / (double)m.step) : 0;
+  }
+  return r;
+}
+
+__device__ inline Ray round_ray(const RayD& rd) {
+  Ray r;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    r.o[a] = (float)rd.o[a];
+    r.d[a] = (float)rd.d[a];
+  }
+  r.t0 = (float)rd.t0;
+  r.t1 = (float)rd.t1;
+  r.ds = (float)rd.ds;
+  r.nseg = rd.nseg;
+  r.hit = rd.hit;
+  return r;
+}
+
+__device__ inline Ray make_ray(const CamDev& cam, int px, int py, int W, int H, const MarchDev& m) {
+  return round_ray(make_ray_d(cam, px, py, W, H, m));
+}
+
+// Segment i of an FP64 ray: its midpoint (plus an offset `off`, world
+// units) rounded once to FP32, and its length (the last one clipped).
+__device__ inline void segment_d(const RayD& r, int i, bool fixed, const float off[3], float p[3], float& len) {
+  const double a0 = r.t0 + (double)i * r.ds;
+  double a1 = r.t0 + (double)(i + 1) * r.ds;
+  if (!fixed) a1 = fmin(a1, r.t1);
+  len = (float)(a1 - a0);
+  const double tm = 0.5 * (a0 + a1);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) p[a] = (float)(r.o[a] + tm * r.d[a] + (double)off[a]);
+}
+
 }  // namespace fvsrn_detail

@@ -29,10 +29,12 @@ struct TFDev {
   float delta[kMaxTFPoints - 1][4];
 };
 
-// Camera with its orthonormal basis precomputed on the host.
+// Camera with its orthonormal basis precomputed on the host (FP64: each ray
+// is set up in FP64 and rounded once, see ray_setup).
 struct CamDev {
-  float eye[3], fwd[3], right[3], up[3];
-  float tan_half, half_extent, aspect;
+  double fwd[3], right[3], up[3];
+  double tan_half, half_extent, aspect;
+  float eye[3];
   int ortho;
   int key;        // first keyframe of the latent blend
   float key_w;    // weight of keyframe key + 1

@@ -34,6 +34,8 @@ enum { kShadeNone = 0, kShadeFwd = 1, kShadeFD = 2, kShadePred = 3, kShadeAdj = 
 // an FP16 network on an FP32 grid) that needs 2 waves per SIMD, c = 48 with
 // the packed latent path 3. The adjoint keeps every layer's activation
 // derivatives of two N-tiles in registers: 2 waves per SIMD.
+// FP32 networks add the FP64 ray of their sample positions (about 10
+// registers).
 template <class CF, int MODE>
 constexpr int max_waves() {
   if (MODE == kShadeAdj) return 8;
@@ -42,6 +44,9 @@ constexpr int max_waves() {
     if (CF::F == 16 && (CF::C == 48 || (CF::P == kF16 && !CF::G16))) return 8;
     return (CF::G16 && CF::C == 32) ? 16 : 12;
   }
+  // FP32 c = 48 network with F = 16: the FP64 sample positions need a few
+  // more registers than 168
+  if (CF::P == kF32 && CF::C == 48 && CF::F == 16) return 8;
   return CF::G16 ? 16 : 12;
 }
 
@@ -95,71 +100,6 @@ __device__ inline void tf_eval(const TFDev& tf, float d, float rgba[4]) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) rgba[q] = fmaf(w, tf.delta[j][q], rgba[q]);
   }
-}
-
-struct Ray {
-  float o[3], d[3];
-  float t0, t1, ds;
-  int nseg;
-  bool hit;
-};
-
-__device__ inline Ray make_ray(const CamDev& cam, int px, int py, int W, int H, const MarchDev& m) {
-  Ray r;
-  const float nx = (2.0f * px + 1.0f) / (float)W - 1.0f;
-  const float ny = 1.0f - (2.0f * py + 1.0f) / (float)H;
-  const float sx = cam.aspect * nx;
-  if (cam.ortho) {
-    const float h = cam.half_extent;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      r.o[a] = cam.eye[a] + h * (sx * cam.right[a] + ny * cam.up[a]);
-      r.d[a] = cam.fwd[a];
-    }
-  } else {
-    float dd[3], l2 = 0.0f;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      dd[a] = cam.fwd[a] + cam.tan_half * (sx * cam.right[a] + ny * cam.up[a]);
-      l2 += dd[a] * dd[a];
-    }
-    const float inv = 1.0f / sqrtf(l2);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      r.o[a] = cam.eye[a];
-      r.d[a] = dd[a] * inv;
-    }
-  }
-  float tn = -INFINITY, tf = INFINITY;
-  bool miss = false;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    if (r.d[a] == 0.0f) {
-      if (r.o[a] < -1.0f || r.o[a] > 1.0f) miss = true;
-    } else {
-      float ta = (-1.0f - r.o[a]) / r.d[a], tb = (1.0f - r.o[a]) / r.d[a];
-      if (ta > tb) {
-        const float s = ta;
-        ta = tb;
-        tb = s;
-      }
-      tn = fmaxf(tn, ta);
-      tf = fminf(tf, tb);
-    }
-  }
-  tn = fmaxf(tn, 0.0f);
-  r.t0 = tn;
-  r.t1 = tf;
-  r.hit = !miss && tf > tn;
-  if (m.fixed_steps > 0) {
-    r.nseg = m.fixed_steps;
-    r.ds = (tf - tn) / (float)m.fixed_steps;
-  } else {
-    r.ds = m.step;
-    r.nseg = r.hit ? (int)ceilf((tf - tn) / m.step) : 0;
-  }
-  if (!r.hit) r.nseg = 0;
-  return r;
 }
 
 // Segment i of a ray: midpoint parameter and length (last one clipped).
@@ -257,7 +197,13 @@ __global__ __launch_bounds__((max_waves<CF, MODE>() * 64)) void march_kernel(Net
     const CamDev& cam = vb.cam[v];
     const LatentSrc ls = make_latent_src(nd, cam.key, cam.key_w);
     const bool in_img = px < vb.width && py < vb.height;
-    const Ray ray = make_ray(cam, in_img ? px : 0, in_img ? py : 0, vb.width, vb.height, m);
+    // FP32 networks take every sample position from the FP64 ray, rounded
+    // once: an FP32 o + t d (the eye a few units from the box) is off by a
+    // few 1e-7, which the highest Fourier octaves turn into visible density
+    // and shading-normal errors; FP16/BF16 rounding dwarfs it
+    constexpr bool kPosF64 = CF::P == kF32;
+    const RayD rayd = make_ray_d(cam, in_img ? px : 0, in_img ? py : 0, vb.width, vb.height, m);
+    const Ray ray = round_ray(rayd);
     bool active = in_img && ray.hit && ray.nseg > 0;
     float tfe[G::TIN > 0 ? G::TIN : 1];  // the view's time inputs (time-encoded networks)
     if constexpr (G::TIN > 0) time_features<CF::TE>(cam.tau, tfe);
@@ -265,13 +211,24 @@ __global__ __launch_bounds__((max_waves<CF, MODE>() * 64)) void march_kernel(Net
     int i = 0;
     while (__builtin_amdgcn_ballot_w64(active)) {
       ++iters;
-      float tm, len;
-      segment(ray, i, fixed, tm, len);
-      float sx = ray.o[0] + tm * ray.d[0], sy = ray.o[1] + tm * ray.d[1], sz = ray.o[2] + tm * ray.d[2];
-      if constexpr (FD) {
-        sx += fd_off[0];
-        sy += fd_off[1];
-        sz += fd_off[2];
+      float len, sx, sy, sz;
+      if constexpr (kPosF64) {
+        float pp[3];
+        segment_d(rayd, i, fixed, fd_off, pp, len);
+        sx = pp[0];
+        sy = pp[1];
+        sz = pp[2];
+      } else {
+        float tm;
+        segment(ray, i, fixed, tm, len);
+        sx = ray.o[0] + tm * ray.d[0];
+        sy = ray.o[1] + tm * ray.d[1];
+        sz = ray.o[2] + tm * ray.d[2];
+        if constexpr (FD) {
+          sx += fd_off[0];
+          sy += fd_off[1];
+          sz += fd_off[2];
+        }
       }
       sx = active ? sx : 0.0f;
       sy = active ? sy : 0.0f;

@@ -19,71 +19,6 @@ __device__ inline void tf_eval_d(const TFDev& tf, float d, float rgba[4]) {
   }
 }
 
-struct DRay {
-  float o[3], d[3];
-  float t0, t1, ds;
-  int nseg;
-  bool hit;
-};
-
-__device__ inline DRay make_dray(const CamDev& cam, int px, int py, int W, int H, const MarchDev& m) {
-  DRay r;
-  const float nx = (2.0f * px + 1.0f) / (float)W - 1.0f;
-  const float ny = 1.0f - (2.0f * py + 1.0f) / (float)H;
-  const float sx = cam.aspect * nx;
-  if (cam.ortho) {
-    const float h = cam.half_extent;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      r.o[a] = cam.eye[a] + h * (sx * cam.right[a] + ny * cam.up[a]);
-      r.d[a] = cam.fwd[a];
-    }
-  } else {
-    float dd[3], l2 = 0.0f;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      dd[a] = cam.fwd[a] + cam.tan_half * (sx * cam.right[a] + ny * cam.up[a]);
-      l2 += dd[a] * dd[a];
-    }
-    const float inv = 1.0f / sqrtf(l2);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      r.o[a] = cam.eye[a];
-      r.d[a] = dd[a] * inv;
-    }
-  }
-  float tn = -INFINITY, tf = INFINITY;
-  bool miss = false;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    if (r.d[a] == 0.0f) {
-      if (r.o[a] < -1.0f || r.o[a] > 1.0f) miss = true;
-    } else {
-      float ta = (-1.0f - r.o[a]) / r.d[a], tb = (1.0f - r.o[a]) / r.d[a];
-      if (ta > tb) {
-        const float s = ta;
-        ta = tb;
-        tb = s;
-      }
-      tn = fmaxf(tn, ta);
-      tf = fminf(tf, tb);
-    }
-  }
-  tn = fmaxf(tn, 0.0f);
-  r.t0 = tn;
-  r.t1 = tf;
-  r.hit = !miss && tf > tn;
-  if (m.fixed_steps > 0) {
-    r.nseg = m.fixed_steps;
-    r.ds = (tf - tn) / (float)m.fixed_steps;
-  } else {
-    r.ds = m.step;
-    r.nseg = r.hit ? (int)ceilf((tf - tn) / m.step) : 0;
-  }
-  if (!r.hit) r.nseg = 0;
-  return r;
-}
-
 __device__ inline int xcd_block_d(int nblocks) {
   const int b = blockIdx.x;
   if (nblocks % 8 != 0) return b;
@@ -128,7 +63,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_march_kernel(const float*
   const int py = (tr / tiles_x) * 8 + (lane >> 3);
   if (px >= vb.width || py >= vb.height) return;
   const CamDev& cam = vb.cam[v];
-  DRay ray = make_dray(cam, px, py, vb.width, vb.height, m);
+  Ray ray = make_ray(cam, px, py, vb.width, vb.height, m);
   const bool fixed = m.fixed_steps > 0;
   float T = 1.0f, Cr = 0.0f, Cg = 0.0f, Cb = 0.0f, A = 0.0f;
   int i = 0;

@@ -6,7 +6,9 @@ from a seed, transfer-function control points, camera placements, march
 settings and synthetic density volumes. It contains none of the method's own
 arithmetic (no interpolation, encoding, network, shading or compositing), so
 that both sides can consume the same inputs without sharing any of the code
-under test.
+under test. Transfer functions, cameras and march settings hold FP32 values
+(the precision of the library's interface), so the oracle receives exactly
+what the library receives.
 
 Workloads (stand-ins for the paper's datasets, which are not available):
   * small ortho  -- 16^3 x 8 latent grid, 4 octaves, 35->32->32->32->1 sine
@@ -35,6 +37,20 @@ import numpy as np
 
 
 # --------------------------------------------------------------- plain data
+
+def _f32(x: float) -> float:
+    """The FP32 value nearest to x, as a Python float. The library receives
+    transfer functions, cameras and march settings as FP32; rounding them
+    here gives the oracle the very values the library sees (a camera eye
+    rounded on one side only moves a grazing ray's entry point by up to
+    1/|d_axis| times the rounding, which is visible in the image)."""
+    return float(np.float32(x))
+
+
+def _round_fields(obj, names):
+    for n in names:
+        v = getattr(obj, n)
+        object.__setattr__(obj, n, tuple(_f32(x) for x in v) if isinstance(v, tuple) else _f32(v))
 
 @dataclasses.dataclass(frozen=True)
 class NetSpec:
@@ -73,6 +89,10 @@ class TF:
     points: Tuple[Tuple[float, float, float, float, float], ...]
     opacity_scale: float = 20.0
 
+    def __post_init__(self):
+        object.__setattr__(self, "points", tuple(tuple(_f32(x) for x in p) for p in self.points))
+        _round_fields(self, ("opacity_scale",))
+
 
 @dataclasses.dataclass(frozen=True)
 class Camera:
@@ -85,6 +105,9 @@ class Camera:
     fov_y_deg: float = 45.0
     ortho_half_extent: float = 1.0
     time: float = 0.0
+
+    def __post_init__(self):
+        _round_fields(self, ("eye", "target", "up", "fov_y_deg", "ortho_half_extent", "time"))
 
 
 @dataclasses.dataclass(frozen=True)
@@ -99,6 +122,9 @@ class March:
     shininess: float = 32.0
     grad_mode: int = 0      # Phong gradient: 0 forward mode, 1 central differences, 2 predicted, 3 adjoint
     fd_step: float = 0.0    # central-difference step (world units)
+
+    def __post_init__(self):
+        _round_fields(self, ("step", "ert_eps", "ka", "kd", "ks", "shininess", "fd_step"))
 
 
 # ------------------------------------------------------- random parameters
