@@ -338,8 +338,9 @@ def test_tf_control_points_linearity_and_clamp():
     for d, *rgba in tf.points:
         np.testing.assert_array_equal(O.tf_eval(tf, d), rgba)
     a, b = np.array(tf.points[1][1:]), np.array(tf.points[2][1:])
-    np.testing.assert_allclose(O.tf_eval(tf, 0.45), 0.5 * (a + b), atol=1e-15)
-    np.testing.assert_allclose(O.tf_eval(tf, 0.36), 0.8 * a + 0.2 * b, atol=1e-15)
+    d1, d2 = tf.points[1][0], tf.points[2][0]
+    np.testing.assert_allclose(O.tf_eval(tf, 0.5 * (d1 + d2)), 0.5 * (a + b), atol=1e-15)
+    np.testing.assert_allclose(O.tf_eval(tf, d1 + 0.2 * (d2 - d1)), 0.8 * a + 0.2 * b, atol=1e-15)
     np.testing.assert_array_equal(O.tf_eval(tf, -3.0), tf.points[0][1:])
     np.testing.assert_array_equal(O.tf_eval(tf, 7.0), tf.points[-1][1:])
 
@@ -459,7 +460,8 @@ def test_opacity_telescopes_for_any_profile():
     vol = RNG.uniform(0, 1, size=(6, 7, 8))
     cams = I.orbit_cameras(2, 6, 5)
     img, _ = O.render(O.Field(vol=vol), tf, cams, I.March(step=0.03))
-    np.testing.assert_allclose(img[..., :3], np.repeat(0.6 * img[..., 3:4], 3, axis=-1), rtol=1e-13, atol=1e-16)
+    grey = tf.points[0][1]   # 0.6 as the FP32 value the TF holds
+    np.testing.assert_allclose(img[..., :3], np.repeat(grey * img[..., 3:4], 3, axis=-1), rtol=1e-13, atol=1e-16)
     # and the exact optical depth of a vertical ray through a z-only profile
     prof = np.array([0.1, 0.9, 0.3, 0.5, 0.2])
     vol = np.broadcast_to(prof[:, None, None], (5, 4, 4)).copy()
@@ -475,8 +477,9 @@ def test_segments_cover_chord_with_clipped_last_step():
     """Constant density with a step that does not divide the chord: the
     clipped last segment makes the optical depth exactly kappa * chord."""
     tf = I.ramp_tf()
-    net = _constant_net(I.NET_SMALL, 0.3)
-    kappa = tf.opacity_scale * 0.1
+    d1, alpha1 = tf.points[1][0], tf.points[1][4]   # control point (0.3; alpha 0.1) as FP32 values
+    net = _constant_net(I.NET_SMALL, d1)
+    kappa = tf.opacity_scale * alpha1
     m = I.March(step=0.37)
     img, ns = O.render(O.Field(net=net), tf, [I.ortho_camera(2, 2)], m)
     assert ns == 4 * math.ceil(2.0 / 0.37)
@@ -689,10 +692,11 @@ def test_phong_headlight_closed_form():
     along = np.broadcast_to((0.5 + 0.4 * ax)[:, None, None], (9, 9, 9)).copy()
     across = np.broadcast_to((0.5 + 0.4 * ax)[None, None, :], (9, 9, 9)).copy()
     img, _ = O.render(O.Field(vol=along), tf, [cam], m)
-    k = 0.6 * (m.ka + m.kd) + m.ks
+    grey = tf.points[0][1]   # 0.6 as the FP32 value the TF holds
+    k = grey * (m.ka + m.kd) + m.ks
     np.testing.assert_allclose(img[0, ..., :3], np.repeat(k * img[0, ..., 3:4], 3, -1), rtol=1e-12)
     img, _ = O.render(O.Field(vol=across), tf, [cam], m)
-    np.testing.assert_allclose(img[0, ..., :3], np.repeat(0.6 * m.ka * img[0, ..., 3:4], 3, -1), rtol=1e-12)
+    np.testing.assert_allclose(img[0, ..., :3], np.repeat(grey * m.ka * img[0, ..., 3:4], 3, -1), rtol=1e-12)
 
 
 def test_fd_shading_converges_to_forward_mode_at_second_order():
