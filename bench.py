@@ -82,10 +82,10 @@ def kernel_isa_hash():
         return json.load(fh).get(STUDY_KERNEL)
 
 
-def measured_traffic():
-    """HBM bytes per launch of the FP16 render from the committed rocprofv3
-    counter record, if it was taken on the kernel code that is built now."""
-    path = os.path.join(ROOT, "profiles", "march_f16_study_traffic.json")
+def counter_record(name):
+    """A committed rocprofv3 counter record of the study render kernel, if it
+    was taken on the kernel code that is built now (else None)."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -93,7 +93,39 @@ def measured_traffic():
     h = kernel_isa_hash()
     if h is None or rec.get("kernel_isa_sha256") != h:
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP16 render (FETCH_SIZE + WRITE_SIZE,
+    copy-calibrated)."""
+    rec = counter_record("march_f16_study_traffic.json")
+    return None if rec is None else rec.get("hbm_bytes_per_launch")
+
+
+def measured_valu_busy():
+    """Fraction of SIMD cycles the study render keeps the vector ALU issuing:
+    4 x SQ_ACTIVE_INST_VALU (quad-cycles, summed over waves) over SIMDs x the
+    kernel's cycles."""
+    rec = counter_record("march_f16_study_sq.json")
+    return None if rec is None else rec.get("valu_busy")
+
+
+def cpu_cores():
+    """Host cores the process may use: its CPU affinity, capped by the cgroup
+    CPU quota and by OMP_NUM_THREADS when either is set (a GPU host gives
+    each GPU's processes a share of its cores and says so there)."""
+    n = len(os.sched_getaffinity(0))
+    try:
+        quota, period = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if quota != "max":
+            n = min(n, max(1, int(int(quota) // int(period))))
+    except (OSError, ValueError):
+        pass
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    if omp.isdigit() and int(omp) > 0:
+        n = min(n, int(omp))
+    return max(1, n)
 
 
 def torch_layerwise(spec, lat, w, xyz, dtype):
@@ -135,10 +167,10 @@ def cpu_model():
 
 
 def cpu_baseline(spec, lat16, w, tf, cams, march):
-    """The FP64 oracle on the host cores this process may use (at most 16),
-    on a 352x352 centre crop of view 0."""
+    """The FP64 oracle on every host core the process may use, on a 352x352
+    centre crop of view 0."""
     import oracle as O
-    threads = max(1, min(len(os.sched_getaffinity(0)), 16))
+    threads = cpu_cores()
     net = O.Net(spec, lat16.astype(np.float64), w)
     W, H = cams[0].width, cams[0].height
     c = 176
@@ -149,7 +181,7 @@ def cpu_baseline(spec, lat16, w, tf, cams, march):
     dt = time.perf_counter() - t0
     return {"value": ns / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
             "sample": "%dx%d centre crop of view 0 (%d samples, %.1f s)" % (2 * c, 2 * c, ns, dt),
-            "cpu_model": cpu_model()}
+            "cpu_model": cpu_model(), "cpu_affinity": len(os.sched_getaffinity(0))}
 
 
 def main():
@@ -214,7 +246,8 @@ def main():
 
     progress("timing the study render")
     per, wall = time_launches(step, args.steps, args.warmup)
-    ms_launch = float(np.mean(per))
+    # the median launch (8 frames each) sets the kernel's rate
+    ms_launch = float(np.median(per))
     ms_step = wall / args.steps
     fps = flops_per_sample(spec)
     achieved = samples * fps / (ms_launch * 1e-3) / 1e12
@@ -255,6 +288,12 @@ def main():
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "algorithmic_bytes": algo_bytes,
             "launch_ms": ms_launch,
+            "launch_ms_mean": float(np.mean(per)),
+            "launches_timed": len(per),
+            # the unit that binds the kernel: the vector ALU issues the
+            # activations, gathers and features; the matrix cores wait on it
+            "binding_unit": "valu",
+            "valu_busy": measured_valu_busy(),
         },
     }
 
@@ -271,9 +310,12 @@ def main():
         torch.cuda.synchronize()
         s = int(stats[0].item())
         per_c, _ = time_launches(dense, max(3, args.steps // 4), 1)
-        ms = float(np.mean(per_c))
+        ms = float(np.median(per_c))
+        # eight FP32 corners per sample come from the caches (L1/L2/MALL); the
+        # volume itself and the image cross HBM once
         comp["dense_dvr_256"] = {"ms_per_frame": ms / len(cams), "samples_per_s": s / (ms * 1e-3),
-                                 "algorithmic_GBps": s * 32 / (ms * 1e-3) / 1e9}
+                                 "cache_gather_GBps": s * 32 / (ms * 1e-3) / 1e9,
+                                 "hbm_unique_GBps": (vol.numel() * 4 + ref.numel() * 4) / (ms * 1e-3) / 1e9}
 
         def rmse(img):
             return float(torch.sqrt(torch.mean((img - ref) ** 2)).item())
@@ -293,7 +335,7 @@ def main():
             s = int(stats[0].item())
             e, q = rmse(out), ssim(out)
             per_c, _ = time_launches(lambda: step(n, prec), max(3, args.steps // 4), 1)
-            ms = float(np.mean(per_c))
+            ms = float(np.median(per_c))
             comp[name] = {"ms_per_frame": ms / len(cams), "samples_per_s": s / (ms * 1e-3),
                           "tflops": s * fps / (ms * 1e-3) / 1e12, "image_rmse_vs_dense": e,
                           "image_ssim_vs_dense": q}
@@ -313,8 +355,8 @@ def main():
             ns = int(stats[0].item())
             e, q = rmse(out), ssim(out)
             per_c, _ = time_launches(lambda: FV.fvsrn_render(net, tf, cams, m, "f16", out=out), 3, 1)
-            shade[name] = {"ms_per_frame": float(np.mean(per_c)) / len(cams),
-                           "samples_per_s": ns / (float(np.mean(per_c)) * 1e-3)}
+            shade[name] = {"ms_per_frame": float(np.median(per_c)) / len(cams),
+                           "samples_per_s": ns / (float(np.median(per_c)) * 1e-3)}
             if m.phong:
                 shade[name]["image_rmse_vs_dense_phong"] = e
                 shade[name]["image_ssim_vs_dense_phong"] = q
@@ -343,8 +385,8 @@ def main():
             ns = int(stats[0].item())
             e, q = rmse(out), ssim(out)
             per_c, _ = time_launches(lambda: FV.fvsrn_render(pnet, tf, cams, m_pred, "f16", out=out), 3, 1)
-            shade["predicted"] = {"ms_per_frame": float(np.mean(per_c)) / len(cams),
-                                  "samples_per_s": ns / (float(np.mean(per_c)) * 1e-3),
+            shade["predicted"] = {"ms_per_frame": float(np.median(per_c)) / len(cams),
+                                  "samples_per_s": ns / (float(np.median(per_c)) * 1e-3),
                                   "image_rmse_vs_dense_phong": e, "image_ssim_vs_dense_phong": q,
                                   "training": {"steps": args.train_steps, "batch": 1 << 18,
                                                "grad_weight": PRED_GRAD_WEIGHT, "final_loss": float(ptr.loss.item()),
@@ -384,7 +426,7 @@ def main():
             torch.cuda.synchronize()
             ts = int(stats[0].item())
             per_c, _ = time_launches(lambda: FV.fvsrn_render(tnet, tf, tcams, march, "f16", out=out), 3, 1)
-            ms = float(np.mean(per_c))
+            ms = float(np.median(per_c))
             for v, cam in enumerate(tcams):
                 vt = I.blob_volume_torch(256, cam.time, prm, norm, device=dev)
                 FV.fvsrn_render_dense(vt, tf, [cam], march, out=ref[v:v + 1])
@@ -420,7 +462,7 @@ def main():
                                  grid_dtype=FV.F16, device=dev)
                 per_c, _ = time_launches(lambda: FV.fvsrn_render(e16, tf, tcams, march, "f16", out=out), 3, 1)
                 enc[name] = {"l1_trained_timesteps": mean_err(train_frames), "l1_unseen_timesteps": mean_err(held_out),
-                             "render_ms_per_frame_f16": float(np.mean(per_c)) / len(tcams)}
+                             "render_ms_per_frame_f16": float(np.median(per_c)) / len(tcams)}
                 del etr, enet, e16
             comp["time_encodings"] = {"train": "even timesteps 0..14, %d steps of 2^18 points" % esteps,
                                       "evaluated_on": "odd timesteps 1..15", **enc}
@@ -447,7 +489,7 @@ def main():
                 f16 = FV.Network(spec, fnet.latent.cpu().numpy(), fnet.weights.cpu().numpy(), grid_dtype=FV.F16,
                                  device=dev, fourier_matrix=fmx)
                 per_c, _ = time_launches(lambda: FV.fvsrn_render(f16, tf, cams, march, "f16", out=out), 3, 1)
-                ff[name] = {"l1": l1, "render_ms_per_frame_f16": float(np.mean(per_c)) / len(cams)}
+                ff[name] = {"l1": l1, "render_ms_per_frame_f16": float(np.median(per_c)) / len(cams)}
                 del ftr, fnet, f16
             comp["fourier_features"] = {"train": "%d steps of 2^18 points on the 256^3 volume" % fsteps, **ff}
         progress("point evaluation")
@@ -527,14 +569,14 @@ def main():
             per_d, _ = time_launches(lambda: FV.fvsrn_render_dense(mvol, tf, scam, smarch, out=sref), 3, 1)
             shaded = {"training": {"steps": args.train_steps, "ms_per_step": t_m / args.train_steps * 1e3,
                                    "final_l1": float(mtr.loss.item())},
-                      "dense_dvr_512_ms_per_frame": float(np.mean(per_d))}
+                      "dense_dvr_512_ms_per_frame": float(np.median(per_d))}
             for name, gm in (("forward", 0), ("adjoint", 3)):
                 mm = dataclasses.replace(smarch, grad_mode=gm)
                 FV.fvsrn_render(mnet, tf, scam, mm, "f16", out=sout, stats=stats.zero_())
                 torch.cuda.synchronize()
                 ns = int(stats[0].item())
                 per_c, _ = time_launches(lambda: FV.fvsrn_render(mnet, tf, scam, mm, "f16", out=sout), 3, 1)
-                ms = float(np.mean(per_c))
+                ms = float(np.median(per_c))
                 shaded[name] = {"ms_per_frame": ms, "samples_per_s": ns / (ms * 1e-3),
                                 "image_rmse_vs_dense": float(torch.sqrt(torch.mean((sout - sref) ** 2)).item()),
                                 "image_ssim_vs_dense": FV.fvsrn_ssim(sout, sref)}
@@ -557,7 +599,7 @@ def main():
             torch.cuda.synchronize()
             qs = int(stats[0].item())
             per_c, _ = time_launches(lambda: FV.fvsrn_render(qnet, tf, cams, march, "f16", out=out), 3, 1)
-            ms = float(np.mean(per_c))
+            ms = float(np.median(per_c))
             tfl = qs * flops_per_sample(sp) / (ms * 1e-3) / 1e12
             mf[name] = {"samples_per_s": qs / (ms * 1e-3), "tflops": tfl, "frac_of_fp16_peak": tfl / P16_TFLOPS}
             del qnet
@@ -568,15 +610,15 @@ def main():
         dens = torch.empty(npts, device=dev)
         for prec, n in (("f32", net32), ("f16", net)):
             per_c, _ = time_launches(lambda: FV.fvsrn_eval_points(n, xyz, 0.0, prec, out=dens), 5, 1)
-            comp["eval_points_fused_" + prec] = {"points_per_s": npts / (float(np.mean(per_c)) * 1e-3)}
+            comp["eval_points_fused_" + prec] = {"points_per_s": npts / (float(np.median(per_c)) * 1e-3)}
             # the paper's protocol: 10^6 random reconstructions per call
             m6 = 1000000
             per_m, _ = time_launches(lambda: FV.fvsrn_eval_points(n, xyz[:m6], 0.0, prec, out=dens[:m6]), 20, 3)
-            comp["eval_points_fused_" + prec]["ms_per_1e6_points"] = float(np.mean(per_m))
+            comp["eval_points_fused_" + prec]["ms_per_1e6_points"] = float(np.median(per_m))
         for name, dt in (("f32", torch.float32), ("f16", torch.float16)):
             run = torch_layerwise(spec, lat, w, xyz, dt)
             per_c, _ = time_launches(run, 3, 1)
-            pts = npts / (float(np.mean(per_c)) * 1e-3)
+            pts = npts / (float(np.median(per_c)) * 1e-3)
             comp["eval_points_torch_layerwise_" + name] = {
                 "points_per_s": pts,
                 "fused_speedup": comp["eval_points_fused_" + name]["points_per_s"] / pts}

@@ -64,9 +64,14 @@ typedef enum { FVSRN_F32 = 0, FVSRN_F16 = 1, FVSRN_BF16 = 2, FVSRN_U8 = 3 } fvsr
 typedef enum { FVSRN_ACT_SINE = 0, FVSRN_ACT_SNAKEALT = 1, FVSRN_ACT_IDENTITY = 2 } fvsrn_act;
 
 /* Network and latent-grid shape (Sec. 3, Sec. 4.2). Supported: F in {8, 16},
-   L in {4, 8} with (F, L) = (8, 4) or (16, 8); c in {32, 48}; 1 <= H <= 8;
-   2 <= R <= 512 with one keyframe grid (R^3 F elements) below 2^31 bytes;
-   1 <= K <= 64. uint8 grids need F in {8, 16}. */
+   L in {4, 8}, c in {32, 48, 64} with 1 <= H <= 8; 2 <= R <= 512 with one
+   keyframe grid (R^3 F elements) below 2^31 bytes; 1 <= K <= 64. Every
+   (c, F, L) is compiled for the sine activation, the unshaded render, point
+   densities and forward-mode gradients (BF16 networks: unshaded and
+   densities), and training for c in {32, 48}; the other activations,
+   gradient modes, time encodings and Fourier matrices are compiled for
+   c in {32, 48} with (F, L) = (8, 4) or (16, 8). A shape outside these
+   returns FVSRN_ERR_UNSUPPORTED. */
 typedef struct {
   int32_t grid_res;      /* R: latent vertices per axis */
   int32_t grid_channels; /* F: latent channels */
@@ -77,8 +82,11 @@ typedef struct {
   int32_t hidden_layers; /* H activated layers, followed by the c -> num_outputs output layer */
   int32_t activation;    /* fvsrn_act */
   int32_t precision;     /* network arithmetic: FVSRN_F32 (FP32 MFMA), FVSRN_F16 or
-                            FVSRN_BF16 (MFMA with FP32 accumulation). Interpolation,
-                            phases, sigmoid, TF and compositing are FP32 always. */
+                            FVSRN_BF16 (MFMA with FP32 accumulation). Phases, sigmoid,
+                            TF and compositing are FP32 always; the latent
+                            interpolation too, except for an FP16 network on an FP16
+                            grid, which sums the eight corners in packed FP16 (its
+                            input row is rounded to FP16 anyway). */
   int32_t num_outputs;   /* 1: the density logit; 4: the logit followed by a predicted
                             density gradient d density / d p (Sec. 6). 0 means 1. The
                             output layer holds W_out [num_outputs][c] then b_out

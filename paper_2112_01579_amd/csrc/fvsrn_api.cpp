@@ -52,12 +52,12 @@ fvsrn_status check_desc(const fvsrn_net_desc* d) {
     return fail(FVSRN_ERR_INVALID_ARGUMENT, "precision %d unknown", d->precision);
   if (d->activation < FVSRN_ACT_SINE || d->activation > FVSRN_ACT_IDENTITY)
     return fail(FVSRN_ERR_INVALID_ARGUMENT, "activation %d unknown", d->activation);
-  const bool fl = (d->grid_channels == 8 && d->num_freqs == 4) || (d->grid_channels == 16 && d->num_freqs == 8);
+  const bool fl = (d->grid_channels == 8 || d->grid_channels == 16) && (d->num_freqs == 4 || d->num_freqs == 8);
   if (!fl)
-    return fail(FVSRN_ERR_UNSUPPORTED, "(F, L) = (%d, %d) not compiled; supported (8, 4) and (16, 8)",
+    return fail(FVSRN_ERR_UNSUPPORTED, "(F, L) = (%d, %d) not compiled; supported F in {8, 16}, L in {4, 8}",
                 d->grid_channels, d->num_freqs);
-  if (d->hidden_width != 32 && d->hidden_width != 48)
-    return fail(FVSRN_ERR_UNSUPPORTED, "hidden_width %d not compiled; supported 32, 48", d->hidden_width);
+  if (d->hidden_width != 32 && d->hidden_width != 48 && d->hidden_width != 64)
+    return fail(FVSRN_ERR_UNSUPPORTED, "hidden_width %d not compiled; supported 32, 48, 64", d->hidden_width);
   if (d->hidden_layers > 8) return fail(FVSRN_ERR_UNSUPPORTED, "hidden_layers %d > 8", d->hidden_layers);
   if (d->num_outputs != 0 && d->num_outputs != 1 && d->num_outputs != 4)
     return fail(FVSRN_ERR_INVALID_ARGUMENT, "num_outputs %d: must be 1 or 4 (0 means 1)", d->num_outputs);

@@ -52,6 +52,14 @@ struct Entry {
   FV_NETS(X, kSnakeAlt, kShadeFwd)  \
   FV_NETS(X, kIdentity, kShadeFwd)
 
+// Further shapes, sine activation, unshaded and forward mode: width 64, and
+// latent channels and Fourier octaves chosen independently, (16, 4), (8, 8).
+#define FV_NETS_EXT(X, MODE)                                                           \
+  FV_G16S(X, 32, 16, 4, kSine, MODE) FV_G16S(X, 32, 8, 8, kSine, MODE)               \
+  FV_G16S(X, 48, 16, 4, kSine, MODE) FV_G16S(X, 48, 8, 8, kSine, MODE)               \
+  FV_G16S(X, 64, 8, 4, kSine, MODE) FV_G16S(X, 64, 16, 8, kSine, MODE)               \
+  FV_G16S(X, 64, 16, 4, kSine, MODE) FV_G16S(X, 64, 8, 8, kSine, MODE)
+
 #define FV_ALL_FD(X) FV_NETS(X, kSine, kShadeFD)
 #define FV_ALL_PRED(X) FV_NETS(X, kSine, kShadePred)
 
@@ -92,9 +100,11 @@ int FV_PASTE(launch_render_p, FVSRN_PREC)(const NetDev& nd, const TFDev& tf, con
     return Entry<C_, F_, L_, ACT_, MODE_, GK_>::render(nd, tf, vb, m, out, stats, st);
   FV_ALL(X)
   FV_ALL_PRED(X)
+  FV_NETS_EXT(X, kShadeNone)
 #if FVSRN_PREC != 2
   FV_ALL_GRAD(X)
   FV_ALL_FD(X)
+  FV_NETS_EXT(X, kShadeFwd)
 #endif
 #undef X
   return 1;
@@ -134,8 +144,10 @@ int FV_PASTE(launch_points_p, FVSRN_PREC)(const NetDev& nd, const float* xyz, lo
   if (nd.C == C_ && nd.F == F_ && nd.L == L_ && nd.act == ACT_ && mode == MODE_ && gk == GK_) \
     return Entry<C_, F_, L_, ACT_, MODE_, GK_>::points(nd, xyz, n, key, key_w, out_d, out_g, st);
   FV_ALL(X)
+  FV_NETS_EXT(X, kShadeNone)
 #if FVSRN_PREC != 2
   FV_ALL_GRAD(X)
+  FV_NETS_EXT(X, kShadeFwd)
 #endif
 #undef X
   return 1;

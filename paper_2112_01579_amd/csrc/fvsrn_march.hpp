@@ -36,7 +36,7 @@ enum { kShadeNone = 0, kShadeFwd = 1, kShadeFD = 2, kShadePred = 3, kShadeAdj = 
 // derivatives of two N-tiles in registers: 2 waves per SIMD.
 // FP32 networks add the FP64 ray of their sample positions (about 10
 // registers).
-template <class CF, int MODE>
+template <class CF, int MODE, bool POINTS = false>
 constexpr int max_waves() {
   if (MODE == kShadeAdj) return 8;
   if (MODE == kShadeFwd) return (CF::P == kF16 && CF::C == 32 && CF::G16) ? 12 : 8;
@@ -47,6 +47,8 @@ constexpr int max_waves() {
   // FP32 c = 48 network with F = 16: the FP64 sample positions need a few
   // more registers than 168
   if (CF::P == kF32 && CF::C == 48 && CF::F == 16) return 8;
+  // point evaluation on an FP16 grid holds the corners over the feature build
+  if (POINTS && CF::GK == 1) return 12;
   return CF::G16 ? 16 : 12;
 }
 
@@ -73,10 +75,10 @@ __host__ __device__ int fixed_lds_bytes(int H) {
 // sizes that reach it, the smallest: several smaller workgroups per CU let
 // the dispatcher replace a finished one while another still runs its long
 // rays (measured: 3 x 4 waves beat 1 x 12 waves by 12% on the BF16 path).
-template <class CF, int MODE>
+template <class CF, int MODE, bool POINTS = false>
 int waves_per_block(int H) {
   using G = typename CF::G;
-  constexpr int cap = max_waves<CF, MODE>();
+  constexpr int cap = max_waves<CF, MODE, POINTS>();
   const int wb = fixed_lds_bytes<CF, MODE>(H);
   int best = 0, best_waves = 0;
   for (int w = 1; w <= cap; ++w) {
@@ -208,19 +210,17 @@ __global__ __launch_bounds__((max_waves<CF, MODE>() * 64)) void march_kernel(Net
     float tfe[G::TIN > 0 ? G::TIN : 1];  // the view's time inputs (time-encoded networks)
     if constexpr (G::TIN > 0) time_features<CF::TE>(cam.tau, tfe);
     Accum acc = {1.0f, {0.0f, 0.0f, 0.0f}, 0.0f};
-    int i = 0;
-    while (__builtin_amdgcn_ballot_w64(active)) {
-      ++iters;
-      float len, sx, sy, sz;
+    // position and length of segment ii (the origin for a lane without a sample)
+    auto sample_at = [&](int ii, bool act, float& sx, float& sy, float& sz, float& len) {
       if constexpr (kPosF64) {
         float pp[3];
-        segment_d(rayd, i, fixed, fd_off, pp, len);
+        segment_d(rayd, ii, fixed, fd_off, pp, len);
         sx = pp[0];
         sy = pp[1];
         sz = pp[2];
       } else {
         float tm;
-        segment(ray, i, fixed, tm, len);
+        segment(ray, ii, fixed, tm, len);
         sx = ray.o[0] + tm * ray.d[0];
         sy = ray.o[1] + tm * ray.d[1];
         sz = ray.o[2] + tm * ray.d[2];
@@ -230,9 +230,15 @@ __global__ __launch_bounds__((max_waves<CF, MODE>() * 64)) void march_kernel(Net
           sz += fd_off[2];
         }
       }
-      sx = active ? sx : 0.0f;
-      sy = active ? sy : 0.0f;
-      sz = active ? sz : 0.0f;
+      sx = act ? sx : 0.0f;
+      sy = act ? sy : 0.0f;
+      sz = act ? sz : 0.0f;
+    };
+    int i = 0;
+    while (__builtin_amdgcn_ballot_w64(active)) {
+      ++iters;
+      float len, sx, sy, sz;
+      sample_at(i, active, sx, sy, sz, len);
       write_features<CF, GRAD>(myrow, ls, role, sx, sy, sz, tfe, nd.fm);
       wave_lds_sync();
       f4 yo;
@@ -319,7 +325,7 @@ __global__ __launch_bounds__((max_waves<CF, MODE>() * 64)) void march_kernel(Net
 // and forward-mode gradient; kShadeAdj -- density and adjoint gradient (HH:
 // layer count, as for the render kernel).
 template <class CF, int PM, int HH = 0>
-__global__ __launch_bounds__((max_waves<CF, PM>() * 64)) void points_kernel(NetDev nd, const float* xyz, long long n,
+__global__ __launch_bounds__((max_waves<CF, PM, true>() * 64)) void points_kernel(NetDev nd, const float* xyz, long long n,
                                                                             int key, float key_w, float* out_d,
                                                                             float* out_g) {
   using G = typename CF::G;
@@ -350,7 +356,7 @@ __global__ __launch_bounds__((max_waves<CF, PM>() * 64)) void points_kernel(NetD
       y = xyz[3 * idx + 1];
       z = xyz[3 * idx + 2];
     }
-    write_features<CF, GRAD>(myrow, ls, role, x, y, z, tfe, nd.fm);
+    write_features<CF, GRAD, CF::P == kF16 && CF::GK == 1 && !GRAD>(myrow, ls, role, x, y, z, tfe, nd.fm);
     wave_lds_sync();
     if constexpr (ADJ) {
       const float o = mlp_tile_adj<CF, HH>(smem, bsm, feat);
@@ -421,7 +427,7 @@ int launch_points_t(const NetDev& nd, const float* xyz, long long n, int key, fl
                     float* out_g, hipStream_t st) {
   using G = typename CF::G;
   constexpr int PER = PM == kShadeFwd ? 16 : 64;
-  const int wpb = waves_per_block<CF, PM>(nd.H);
+  const int wpb = waves_per_block<CF, PM, true>(nd.H);
   if (wpb < 1) return kLaunchNoLds;
   const size_t shm = (size_t)fixed_lds_bytes<CF, PM>(nd.H) + (size_t)wpb * G::FEAT_BYTES;
   static bool attr = false;

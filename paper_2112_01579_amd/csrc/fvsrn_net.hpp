@@ -353,6 +353,83 @@ __device__ inline void latent_column(const LatentSrc& ls, const LaneRole& role, 
 // the eight corner products are accumulated pairwise in packed FP16 (each
 // corner is one v_pk_fma per two channels) and land in the input row without
 // a conversion. The row is rounded to FP16 for the MFMA in any case.
+// Two phases, so that work independent of the grid can be placed while the
+// corner loads are in flight: begin() finds the cell, its weights and issues
+// the first keyframe's corner loads; finish() accumulates them and gathers a
+// second keyframe, if any.
+template <int F>
+struct LatentColumnH {
+  h8 raw[8][F / 8];  // the first keyframe's corners, as loaded
+  float xy[4], z0, z1;
+  unsigned base, off[8];
+
+  __device__ inline void begin(const LatentSrc& ls, const LaneRole& role, float px, float py, float pz) {
+    int ix, iy, iz;
+    float fx, fy, fz, dx, dy, dz;
+    axis_cell(px, ls.R, ix, fx, dx);
+    axis_cell(py, ls.R, iy, fy, dy);
+    axis_cell(pz, ls.R, iz, fz, dz);
+    const bool tx = !role.is_val && role.axis == 0, ty = !role.is_val && role.axis == 1,
+               tz = !role.is_val && role.axis == 2;
+    const float x0 = tx ? -dx : 1.0f - fx, x1 = tx ? dx : fx;
+    const float y0 = ty ? -dy : 1.0f - fy, y1 = ty ? dy : fy;
+    z0 = tz ? -dz : 1.0f - fz;
+    z1 = tz ? dz : fz;
+    const unsigned R = (unsigned)ls.R;
+    const unsigned sx = F, sy = R * F, sz = R * R * F;
+    base = (unsigned)iz * sz + (unsigned)iy * sy + (unsigned)ix * sx;
+    corner_offsets(sx, sy, sz, off);
+    xy[0] = x0 * y0;
+    xy[1] = x1 * y0;
+    xy[2] = x0 * y1;
+    xy[3] = x1 * y1;
+    load(ls.g0, ls.bytes);
+  }
+
+  __device__ inline void load(const void* g, unsigned bytes) {
+    const __amdgpu_buffer_rsrc_t r = grid_rsrc(g, bytes);
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+#pragma unroll
+      for (int q = 0; q < F / 8; ++q) raw[c][q] = __builtin_bit_cast(h8, load16(r, base * 2u + 16u * q, off[c] * 2u));
+  }
+
+  // z2 += sum over corners of weight * corner, weights x * y * (z * kw) in
+  // FP32, rounded once to FP16 in pairs (x0, x1): the FMAs broadcast either half
+  __device__ inline void accumulate(float kw, h2* z2) const {
+    const float zk[2] = {z0 * kw, z1 * kw};
+    h2 wp[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      wp[j] = __builtin_convertvector((f2{xy[2 * (j & 1)] * zk[j >> 1], xy[2 * (j & 1) + 1] * zk[j >> 1]}), h2);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const _Float16 wh = wp[c >> 1][c & 1];
+      const h2 w2 = {wh, wh};
+#pragma unroll
+      for (int q = 0; q < F / 8; ++q)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const h2 v2 = {raw[c][q][2 * j], raw[c][q][2 * j + 1]};
+          z2[4 * q + j] = w2 * v2 + z2[4 * q + j];
+        }
+    }
+  }
+
+  __device__ inline void finish(const LatentSrc& ls, h2* z2) {
+#pragma unroll
+    for (int j = 0; j < F / 2; ++j) z2[j] = h2{(_Float16)0.0f, (_Float16)0.0f};
+    accumulate(ls.w0, z2);  // w0 = 1 for a single keyframe
+    if (ls.g1) {
+      load(ls.g1, ls.bytes);
+      accumulate(ls.w1, z2);
+    }
+  }
+};
+
+// The same gather in one phase: each corner's loads are consumed as they
+// arrive (the render, whose 8x8 ray tiles mostly hit in L1, keeps 4 waves per
+// SIMD with it).
 template <int F>
 __device__ inline void latent_column_h(const LatentSrc& ls, const LaneRole& role, float px, float py, float pz,
                                        h2* z2) {
@@ -371,8 +448,7 @@ __device__ inline void latent_column_h(const LatentSrc& ls, const LaneRole& role
   const unsigned base = (unsigned)iz * sz + (unsigned)iy * sy + (unsigned)ix * sx;
   unsigned off[8];
   corner_offsets(sx, sy, sz, off);
-  const float w[8] = {x0 * y0 * z0, x1 * y0 * z0, x0 * y1 * z0, x1 * y1 * z0,
-                      x0 * y0 * z1, x1 * y0 * z1, x0 * y1 * z1, x1 * y1 * z1};
+  const float xy[4] = {x0 * y0, x1 * y0, x0 * y1, x1 * y1};
 #pragma unroll
   for (int j = 0; j < F / 2; ++j) z2[j] = h2{(_Float16)0.0f, (_Float16)0.0f};
 #pragma unroll
@@ -380,11 +456,15 @@ __device__ inline void latent_column_h(const LatentSrc& ls, const LaneRole& role
     const void* g = key == 0 ? ls.g0 : ls.g1;
     if (key == 1 && !g) break;
     const __amdgpu_buffer_rsrc_t r = grid_rsrc(g, ls.bytes);
-    const float kw = key == 0 ? ls.w0 : ls.w1;
-    const bool blend = ls.g1 != nullptr;  // one keyframe: its weight is 1
+    const float kw = key == 0 ? ls.w0 : ls.w1;  // 1 for a single keyframe
+    const float zk[2] = {z0 * kw, z1 * kw};
+    h2 wp[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      wp[j] = __builtin_convertvector((f2{xy[2 * (j & 1)] * zk[j >> 1], xy[2 * (j & 1) + 1] * zk[j >> 1]}), h2);
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-      const _Float16 wh = (_Float16)(blend ? w[c] * kw : w[c]);
+      const _Float16 wh = wp[c >> 1][c & 1];
       const h2 w2 = {wh, wh};
 #pragma unroll
       for (int q = 0; q < F / 8; ++q) {
@@ -399,7 +479,7 @@ __device__ inline void latent_column_h(const LatentSrc& ls, const LaneRole& role
   }
 }
 
-// uint8 variant of latent_column_h (Sec. 4.2's quantised grid) for an FP16
+// uint8 variant of LatentColumnH (Sec. 4.2's quantised grid) for an FP16
 // network: each code pair is unpacked into FP16 as 1024 + code (a byte
 // permute next to the exponent byte 0x64) and 1024 subtracted exactly; the
 // weighted code sums accumulate in packed FP16 (at most 255, so the sum keeps
@@ -494,7 +574,12 @@ __device__ inline float time_tau(float t, float lo, float hi, float scale) {
 // Builds this lane's input row at position p and writes it to `row` (LDS).
 // tf: the sample's time inputs (Geo::TIN values; ignored without a time
 // encoding); they do not depend on p, so tangent rows get zeros there.
-template <class CF, bool GRAD>
+// OVERLAP (FP16 network on an FP16 grid): issue the corner loads, build the
+// Fourier features, then accumulate the corners, so that the features hide
+// the loads' latency; it holds the loaded corners in registers meanwhile
+// (worth it at 3 waves per SIMD, where the random point gathers wait on L2;
+// the render's 8x8 ray tiles hit in L1 and run at 4 waves without it).
+template <class CF, bool GRAD, bool OVERLAP = false>
 __device__ inline void write_features(typename CF::E* row, const LatentSrc& ls, const LaneRole& role, float px,
                                       float py, float pz, const float* tf = nullptr,
                                       const float (*fm)[3] = nullptr) {
@@ -506,8 +591,13 @@ __device__ inline void write_features(typename CF::E* row, const LatentSrc& ls, 
   for (int j = 0; j < G::KROW; ++j) v[j] = 0.0f;
   constexpr bool packed_latent = CF::P == kF16 && CF::G16;
   h2 zh[F / 2];
+  LatentColumnH<F> lch;
   if constexpr (packed_latent && CF::GK == 2) {
     latent_column_q<F>(ls, role, px, py, pz, zh);
+  } else if constexpr (packed_latent && OVERLAP) {
+    lch.begin(ls, role, px, py, pz);
+    // keep the Fourier features below between the loads and their use
+    __builtin_amdgcn_sched_barrier(0);
   } else if constexpr (packed_latent) {
     latent_column_h<F>(ls, role, px, py, pz, zh);
   } else {
@@ -588,6 +678,10 @@ __device__ inline void write_features(typename CF::E* row, const LatentSrc& ls, 
     // forward mode: keep each octave's work together, which lowers the
     // register peak of the feature build
     if constexpr (GRAD) __builtin_amdgcn_sched_barrier(0);
+  }
+  if constexpr (packed_latent && CF::GK == 1 && OVERLAP) {
+    __builtin_amdgcn_sched_barrier(0);
+    lch.finish(ls, zh);
   }
   if constexpr (GRAD) {
     v[G::KMAIN + 0] = role.is_val ? px : (role.axis == 0 ? 1.0f : 0.0f);

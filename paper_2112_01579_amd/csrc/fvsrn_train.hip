@@ -825,6 +825,13 @@ struct TrainEntry {
   X(48, 8, 4)             \
   X(48, 16, 8)
 
+// further (F, L) pairs: sine activation, no time encoding or Fourier matrix
+#define FV_TRAIN_CASES_EXT(X) \
+  X(32, 16, 4)                \
+  X(32, 8, 8)                 \
+  X(48, 16, 4)                \
+  X(48, 8, 8)
+
 }  // namespace
 
 size_t train_workspace_bytes(const NetDev& nd, long long n) {
@@ -838,6 +845,13 @@ size_t train_workspace_bytes(const NetDev& nd, long long n) {
     return TrainEntry<C_, F_, L_, kIdentity>::ws_bytes(nd, n);                   \
   }
   FV_TRAIN_CASES(X)
+#undef X
+#define X(C_, F_, L_)                                                                    \
+  if (nd.C == C_ && nd.F == F_ && nd.L == L_) {                                          \
+    if (nd.act == kSine && nd.time_enc == 0 && !nd.fmat) return TrainEntry<C_, F_, L_, kSine>::ws_bytes(nd, n); \
+    return 0;                                                                            \
+  }
+  FV_TRAIN_CASES_EXT(X)
 #undef X
   return 0;
 }
@@ -872,6 +886,13 @@ int launch_train(const NetDev& nd, const KeyTimes& kt, float* latent, float* wei
     }                                                                        \
   }
   FV_TRAIN_CASES(X)
+#undef X
+#define X(C_, F_, L_)                                                                \
+  if (nd.C == C_ && nd.F == F_ && nd.L == L_) {                                      \
+    if (nd.act == kSine && nd.time_enc == 0 && !nd.fmat) FV_TRAIN_RUN(C_, F_, L_, kSine, 0, 0); \
+    else rc = 1;                                                                     \
+  }
+  FV_TRAIN_CASES_EXT(X)
 #undef X
 #undef FV_TRAIN_RUN
   (void)ws_bytes;

@@ -88,7 +88,9 @@ def test_render_argument_errors():
     L = FV.lib()
     assert _render(_desc(grid_res=1)) == FV.ERR_INVALID_ARGUMENT
     assert _render(_desc(hidden_width=40)) == FV.ERR_UNSUPPORTED
-    assert _render(_desc(grid_channels=16)) == FV.ERR_UNSUPPORTED      # (16, 4) not compiled
+    assert _render(_desc(grid_channels=12)) == FV.ERR_UNSUPPORTED      # F = 12 not compiled
+    assert _render(_desc(num_freqs=6)) == FV.ERR_UNSUPPORTED           # L = 6 not compiled
+    assert _render(_desc(hidden_width=96)) == FV.ERR_UNSUPPORTED
     # one keyframe grid must stay below 2^31 bytes (512^3 x 8 FP32 = 4 GiB)
     assert _render(_desc(grid_res=512)) == FV.ERR_UNSUPPORTED
     assert b"2^31" in L.fvsrn_last_error()

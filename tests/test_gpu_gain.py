@@ -2,8 +2,10 @@
 library's own kernels against (i) the same model untrained and (ii) a dense
 grid of the same memory, low-pass filtered and downsampled from the original
 (the paper's "off" control). Reference: dense-grid DVR of the original volume
-(image RMSE) and point samples of it (density RMSE). (i) is asserted; (ii)
-is the paper's qualitative claim and is reported."""
+(image RMSE) and point samples of it (density RMSE). Both are asserted: the
+trained network beats the untrained one by far, and the equal-memory grid
+on both errors (measured image RMSE 0.0175 against 0.0268, density RMSE
+0.0130 against 0.0147 on this 128^3 volume after 600 steps)."""
 import math
 
 import numpy as np
@@ -70,3 +72,5 @@ def test_trained_network_gain(FV):
         print("%-24s image RMSE %.4f  density RMSE %.4f" % (k, a, b), flush=True)
     assert res["trained"][0] < 0.5 * res["untrained"][0]
     assert res["trained"][1] < 0.5 * res["untrained"][1]
+    grid = res["equal-memory %d^3 grid" % side]
+    assert res["trained"][0] < grid[0] and res["trained"][1] < grid[1]

@@ -24,6 +24,15 @@ pytestmark = pytest.mark.gpu
 FP32_TOL = 1e-5
 FP16_TOL = 3e-3
 BF16_TOL = 3e-2
+# density gradients, relative to the largest |gradient| of the set
+GRAD32_TOL = 1e-5
+GRAD16_TOL = 1e-2
+# Phong-shaded FP32 images: the specular term |n.l|^32 multiplies the shading
+# normal's relative error (FP32 network gradients with the hardware
+# transcendentals, ~5e-7) by 32 and by k_s, and the rays composite hundreds of
+# such samples; measured 1.3e-6 to 1.04e-5 over the forward-mode, central
+# difference, predicted and adjoint renders
+PHONG32_TOL = 2e-5
 
 
 @pytest.fixture(scope="module")
@@ -154,7 +163,7 @@ def test_uint8_grid_keyframes_render_and_gradients(FV):
     dref, gref = O.grad_points(onet, xyz, 0.35)
     d, g = FV.fvsrn_grad_points(gnet, torch.from_numpy(xyz).cuda(), 0.35, "f32")
     assert np.abs(d.cpu().numpy() - dref).max() <= FP32_TOL
-    assert _grad_err(g.cpu().numpy(), gref) <= 1e-4
+    assert _grad_err(g.cpu().numpy(), gref) <= GRAD32_TOL
     cams = [dataclasses.replace(c, time=0.6) for c in I.orbit_cameras(1, 23, 19)]
     tf = I.ramp_tf()
     m = I.March(step=1 / 64, ert_eps=0.0)
@@ -244,6 +253,39 @@ def test_study_full_size_sampled_pixels(FV):
     err = np.abs(img[pix] - ref.reshape(-1, 4)[pix]).max()
     _report("study full-size f16 sampled", err)
     assert err <= FP16_TOL
+
+
+def test_fp16_interpolation_error(FV):
+    """The FP16 network on an FP16 latent grid interpolates the eight corners
+    in packed FP16 (corner weights rounded to FP16, products summed in FP16);
+    on an FP32 grid holding the same FP16 values it interpolates in FP32. Both
+    read what the oracle reads, so the difference of their errors is what
+    the FP16 interpolation adds: measured on 2^16 point densities and the
+    study network's full-size render (sampled pixels, ERT off)."""
+    spec = I.NET_STUDY
+    lat, w = I.net_params(spec, I.SEED_STUDY)
+    lat16 = lat.astype(np.float16)
+    onet = O.Net(spec, lat16.astype(np.float64), w)
+    packed = FV.Network(spec, lat, w, grid_dtype=FV.F16)
+    wide = FV.Network(spec, lat16.astype(np.float32), w, grid_dtype=FV.F32)
+    xyz = I.uniform_points(1 << 16, 23)
+    dref = O.eval_points(onet, xyz)
+    xt = torch.from_numpy(xyz).cuda()
+    e_pk = np.abs(FV.fvsrn_eval_points(packed, xt, 0.0, "f16").cpu().numpy() - dref).max()
+    e_wd = np.abs(FV.fvsrn_eval_points(wide, xt, 0.0, "f16").cpu().numpy() - dref).max()
+    _report("density, FP16 interpolation", e_pk)
+    _report("density, FP32 interpolation", e_wd)
+    tf = I.ramp_tf()
+    cams = I.study_cameras(1024, 1024, 8)
+    m = I.study_march(0.0)
+    pix = np.random.default_rng(6).choice(8 * 1024 * 1024, 128, replace=False)
+    ref, _ = O.render(O.Field(net=onet), tf, cams, m, pixels=pix)
+    ref = ref.reshape(-1, 4)[pix]
+    i_pk = np.abs(FV.fvsrn_render(packed, tf, cams, m, "f16").cpu().numpy().reshape(-1, 4)[pix] - ref).max()
+    i_wd = np.abs(FV.fvsrn_render(wide, tf, cams, m, "f16").cpu().numpy().reshape(-1, 4)[pix] - ref).max()
+    _report("study full-size image, FP16 interpolation", i_pk)
+    _report("study full-size image, FP32 interpolation", i_wd)
+    assert max(e_pk, e_wd, i_pk, i_wd) <= FP16_TOL
 
 
 def test_study_full_size_fp32_and_dense_sampled_pixels(FV):
@@ -406,10 +448,7 @@ def test_render_more_views_than_one_launch_and_widest_image(FV):
     img = FV.fvsrn_render(gnet, tf, cams, m, "f32", stats=stats).cpu().numpy()
     per_view = np.abs(img - ref).reshape(n_views, -1).max(axis=1)
     _report("render %d views (worst view %d)" % (n_views, int(per_view.argmax())), per_view.max())
-    # a wrong camera, time or output slot in the second launch would be off by
-    # far more than rounding; these nearly opaque rays composite up to 166
-    # FP32 samples of a keyframe-blended grid, so the bound is 2.5x FP32_TOL
-    assert img.shape == (n_views, 7, 9, 4) and per_view.max() <= 2.5 * FP32_TOL
+    assert img.shape == (n_views, 7, 9, 4) and per_view.max() <= FP32_TOL
     assert abs(stats[0].item() - ns) <= 0.001 * ns
     vol = I.gaussian_volume(24, 6, seed=9)
     dcams = I.orbit_cameras(17, 8, 6)
@@ -423,7 +462,7 @@ def test_render_more_views_than_one_launch_and_widest_image(FV):
     stats.zero_()
     iimg = FV.fvsrn_render(gnet, tf, icam, m, "f32", stats=stats).cpu().numpy()
     _report("render from inside the domain", np.abs(iimg - iref).max())
-    assert np.abs(iimg - iref).max() <= 2.5 * FP32_TOL and stats[1].item() == 99
+    assert np.abs(iimg - iref).max() <= FP32_TOL and stats[1].item() == 99
     assert abs(stats[0].item() - ins) <= 0.001 * ins
     # widest image (16384 columns): two rows, eight fixed steps per ray; the
     # orthographic half height 1/8192 makes the half width 1, so every ray
@@ -477,7 +516,7 @@ def test_grad_points(FV, spec_name):
     gnet, onet = _nets(FV, spec, 31)
     xyz = I.uniform_points(16 * 41 + 7, 9, -0.999, 0.999)
     dref, gref = O.grad_points(onet, xyz)
-    for prec, dtol, gtol in (("f32", FP32_TOL, 1e-4), ("f16", FP16_TOL, 1e-2)):
+    for prec, dtol, gtol in (("f32", FP32_TOL, GRAD32_TOL), ("f16", FP16_TOL, GRAD16_TOL)):
         d, g = FV.fvsrn_grad_points(gnet, torch.from_numpy(xyz).cuda(), 0.0, prec)
         d, g = d.cpu().numpy(), g.cpu().numpy()
         derr, gerr = np.abs(d - dref).max(), _grad_err(g, gref)
@@ -494,7 +533,7 @@ def test_grad_points_time_and_activations(FV):
         dref, gref = O.grad_points(onet, xyz, t)
         d, g = FV.fvsrn_grad_points(gnet, torch.from_numpy(xyz).cuda(), t, "f32")
         assert np.abs(d.cpu().numpy() - dref).max() <= FP32_TOL
-        assert _grad_err(g.cpu().numpy(), gref) <= 1e-4
+        assert _grad_err(g.cpu().numpy(), gref) <= GRAD32_TOL
     for act in ("snakealt", "identity"):
         spec = I.NetSpec(R=16, F=8, L=4, c=32, H=3, act=act)
         lat, w = I.net_params(spec, 3)
@@ -505,7 +544,7 @@ def test_grad_points_time_and_activations(FV):
         d, g = FV.fvsrn_grad_points(gnet, torch.from_numpy(xyz).cuda(), 0.0, "f32")
         _report("grad act=%s" % act, _grad_err(g.cpu().numpy(), gref))
         assert np.abs(d.cpu().numpy() - dref).max() <= FP32_TOL
-        assert _grad_err(g.cpu().numpy(), gref) <= 1e-4
+        assert _grad_err(g.cpu().numpy(), gref) <= GRAD32_TOL
 
 
 def test_grad_points_edge_sizes(FV):
@@ -515,7 +554,7 @@ def test_grad_points_edge_sizes(FV):
         dref, gref = O.grad_points(onet, xyz)
         d, g = FV.fvsrn_grad_points(gnet, torch.from_numpy(xyz).cuda())
         assert np.abs(d.cpu().numpy() - dref).max() <= FP32_TOL
-        assert _grad_err(g.cpu().numpy(), gref) <= 1e-4
+        assert _grad_err(g.cpu().numpy(), gref) <= GRAD32_TOL
 
 
 @pytest.mark.parametrize("prec", ["f32", "f16"])
@@ -523,8 +562,10 @@ def test_phong_render_central_differences(FV, prec):
     """Phong shading from central differences of the network (Sec. 6: seven
     evaluations per sample), c = 32 and c = 48 networks, ragged views. The
     density error e of the precision enters each gradient component as at
-    most e/h, so the FP16 tolerance scales FP16's by 1/h relative to the
-    one-voxel step; FP32 keeps the forward-mode bound."""
+    most e/h, but the neighbouring evaluations' errors are correlated (the
+    same weights and nearby inputs), and the images stay within FP16's image
+    bound (measured 6.7e-4 at c = 48, 1.2e-3 at c = 32); FP32 within the
+    Phong bound."""
     h = 1.0 / 32
     for spec, seed in ((I.NET_SHADED, I.SEED_SHADED), (I.NET_STUDY, I.SEED_STUDY)):
         gnet, onet = _nets(FV, spec, seed)
@@ -536,13 +577,13 @@ def test_phong_render_central_differences(FV, prec):
         img = FV.fvsrn_render(gnet, tf, cams, m, prec, stats=stats).cpu().numpy()
         err = np.abs(img - ref).max()
         _report("phong FD c=%d %s" % (spec.c, prec), err)
-        assert err <= (1e-4 if prec == "f32" else 10 * FP16_TOL)
+        assert err <= (PHONG32_TOL if prec == "f32" else FP16_TOL)
         assert abs(stats[0].item() - ns) <= 0.001 * ns
         # eight evaluation lanes per ray sample
         assert stats[2].item() % 8 == 0
 
 
-@pytest.mark.parametrize("prec,tol", [("f32", 1e-4), ("f16", FP16_TOL)])
+@pytest.mark.parametrize("prec,tol", [("f32", PHONG32_TOL), ("f16", FP16_TOL)])
 def test_phong_render(FV, prec, tol):
     """shaded network (64^3 x 16 grid, 4 x 48) with headlight Phong from
     the forward-mode gradient, on a ragged small view."""
@@ -581,6 +622,8 @@ def test_ssim_map_against_oracle(FV):
     got = FV.fvsrn_ssim(i16, i32)
     want = O.ssim(i16[0].cpu().numpy(), i32[0].cpu().numpy())
     _report("ssim f16 vs f32 render (%.6f)" % want, abs(got - want))
+    # the mean of map values that are each within the map bound (1e-5) is
+    # within it too (measured 1.6e-6 on this pair)
     assert abs(got - want) <= 1e-5 and want > 0.99
 
 
@@ -622,7 +665,7 @@ def test_pred_grad_points(FV, spec):
     fref, fgref = O.grad_points(onet, xyz)
     d, g = FV.fvsrn_grad_points(gnet, torch.from_numpy(xyz).cuda(), 0.0, "f32")
     assert np.abs(d.cpu().numpy() - fref).max() <= FP32_TOL
-    assert _grad_err(g.cpu().numpy(), fgref) <= 1e-4
+    assert _grad_err(g.cpu().numpy(), fgref) <= GRAD32_TOL
 
 
 def _integer_net(spec, seed):
@@ -686,7 +729,7 @@ def test_pred_grad_points_keyframes_and_edges(FV):
             assert _grad_err(g.cpu().numpy(), gref) <= 1e-5
 
 
-@pytest.mark.parametrize("prec,tol", [("f32", 1e-4), ("f16", 10 * FP16_TOL), ("bf16", 0.1)])
+@pytest.mark.parametrize("prec,tol", [("f32", PHONG32_TOL), ("f16", FP16_TOL), ("bf16", BF16_TOL)])
 def test_phong_render_predicted(FV, prec, tol):
     """Phong shading from the predicted gradient (one evaluation per sample)
     on c = 32 and c = 48 four-output networks, ragged views; then forward
@@ -755,7 +798,7 @@ def test_adjoint_grad_points(FV, spec):
     for gd in (FV.F32, FV.F16, FV.U8):
         gnet, onet = _nets(FV, spec, 23, grid_dtype=gd)
         dref, gref = _rev_ref(onet, xyz)
-        for prec, dtol, gtol in (("f32", FP32_TOL, 1e-4), ("f16", FP16_TOL, 1e-2)):
+        for prec, dtol, gtol in (("f32", FP32_TOL, GRAD32_TOL), ("f16", FP16_TOL, GRAD16_TOL)):
             d, g = FV.fvsrn_grad_points(gnet, torch.from_numpy(xyz).cuda(), 0.0, prec, mode="adjoint")
             derr, gerr = np.abs(d.cpu().numpy() - dref).max(), _grad_err(g.cpu().numpy(), gref)
             _report("adjoint c=%d H=%d grid %d %s density" % (spec.c, spec.H, gd, prec), derr)
@@ -772,7 +815,7 @@ def test_adjoint_grad_points_keyframes_edges_and_limits(FV):
             dref, gref = _rev_ref(onet, xyz, t)
             d, g = FV.fvsrn_grad_points(gnet, torch.from_numpy(xyz).cuda(), t, "f32", mode="adjoint")
             assert np.abs(d.cpu().numpy() - dref).max() <= FP32_TOL
-            assert _grad_err(g.cpu().numpy(), gref) <= 1e-4
+            assert _grad_err(g.cpu().numpy(), gref) <= GRAD32_TOL
     # BF16 and other activations are not compiled for the adjoint, and the
     # FP32 fragments of a c = 48 network of 8 layers exceed the LDS
     xyz = torch.from_numpy(I.uniform_points(10, 3)).cuda()
@@ -802,7 +845,7 @@ def test_adjoint_grad_points_deep(FV, spec, precs):
         gnet, onet = _nets(FV, spec, 29, grid_dtype=gd)
         dref, gref = _rev_ref(onet, xyz)
         for prec in precs:
-            dtol, gtol = (FP32_TOL, 1e-4) if prec == "f32" else (FP16_TOL, 1e-2)
+            dtol, gtol = (FP32_TOL, GRAD32_TOL) if prec == "f32" else (FP16_TOL, GRAD16_TOL)
             d, g = FV.fvsrn_grad_points(gnet, torch.from_numpy(xyz).cuda(), 0.0, prec, mode="adjoint")
             derr, gerr = np.abs(d.cpu().numpy() - dref).max(), _grad_err(g.cpu().numpy(), gref)
             _report("adjoint c=%d H=%d grid %d %s density" % (spec.c, spec.H, gd, prec), derr)
@@ -810,7 +853,7 @@ def test_adjoint_grad_points_deep(FV, spec, precs):
             assert derr <= dtol and gerr <= gtol
 
 
-@pytest.mark.parametrize("prec,tol", [("f32", 1e-4), ("f16", FP16_TOL)])
+@pytest.mark.parametrize("prec,tol", [("f32", PHONG32_TOL), ("f16", FP16_TOL)])
 def test_phong_render_adjoint_deep(FV, prec, tol):
     """Adjoint Phong shading of a six-layer network (two layers evaluated
     twice) against the oracle's reverse-mode render."""
@@ -828,7 +871,7 @@ def test_phong_render_adjoint_deep(FV, prec, tol):
     assert abs(stats[0].item() - ns) <= 0.001 * ns
 
 
-@pytest.mark.parametrize("prec,tol", [("f32", 1e-4), ("f16", FP16_TOL)])
+@pytest.mark.parametrize("prec,tol", [("f32", PHONG32_TOL), ("f16", FP16_TOL)])
 def test_phong_render_adjoint(FV, prec, tol):
     """Phong shading from the adjoint gradient on the shaded (c = 48) and
     study (c = 32) networks, ragged views, against the oracle's reverse-mode
@@ -993,3 +1036,71 @@ def test_weighted_points_bit_exact(FV):
     w = np.maximum(E, 0) / np.maximum(E, 0).sum()
     assert np.abs(freq - w).max() < 6 * np.sqrt(w.max() / (1 << 20))
     assert freq[E <= 0].sum() == 0
+
+
+# ------------------------------ width 64 and independent (F, L) pairs
+
+# (c, F, L): hidden width 64, and latent channels chosen independently of the
+# Fourier octaves (Sec. 3 Eq. 1-2 and Sec. 4.2 set them separately)
+EXT_SHAPES = [(64, 16, 8), (64, 8, 4), (32, 16, 4), (32, 8, 8), (48, 16, 4), (48, 8, 8), (64, 16, 4), (64, 8, 8)]
+
+
+@pytest.mark.parametrize("c,F,L", EXT_SHAPES)
+def test_extended_shapes_eval_render(FV, c, F, L):
+    """Point densities (FP32, FP16, BF16 networks; FP32 and FP16 grids) and a
+    ragged 2-view render (FP32 at 1e-5 with ERT off, FP16 on the FP16 grid)
+    against the oracle."""
+    spec = I.NetSpec(R=17, F=F, L=L, c=c, H=4)
+    xyz = I.uniform_points(64 * 21 + 5, 8, -1.02, 1.02)
+    xt = torch.from_numpy(xyz).cuda()
+    tf = I.ramp_tf()
+    cams = I.orbit_cameras(2, 19, 13)
+    m = I.March(step=1 / 128, ert_eps=0.0)
+    for gd in (FV.F32, FV.F16):
+        gnet, onet = _nets(FV, spec, 40 + c + F + L, grid_dtype=gd)
+        ref = O.eval_points(onet, xyz)
+        for prec, tol in (("f32", FP32_TOL), ("f16", FP16_TOL), ("bf16", BF16_TOL)):
+            err = np.abs(FV.fvsrn_eval_points(gnet, xt, 0.0, prec).cpu().numpy() - ref).max()
+            _report("eval c=%d F=%d L=%d grid %d %s" % (c, F, L, gd, prec), err)
+            assert err <= tol
+        iref, ns = O.render(O.Field(net=onet), tf, cams, m)
+        stats = torch.zeros(3, dtype=torch.int64, device="cuda")
+        for prec, tol in ((("f32", FP32_TOL),) if gd == FV.F32 else (("f16", FP16_TOL),)):
+            img = FV.fvsrn_render(gnet, tf, cams, m, prec, stats=stats.zero_()).cpu().numpy()
+            err = np.abs(img - iref).max()
+            _report("render c=%d F=%d L=%d %s" % (c, F, L, prec), err)
+            assert err <= tol
+            assert abs(stats[0].item() - ns) <= 0.001 * ns
+
+
+@pytest.mark.parametrize("c,F,L", [(64, 16, 8), (32, 16, 4), (48, 8, 8)])
+def test_extended_shapes_forward_mode_gradient(FV, c, F, L):
+    """Forward-mode density gradients and a Phong render of the new shapes."""
+    spec = I.NetSpec(R=13, F=F, L=L, c=c, H=3)
+    gnet, onet = _nets(FV, spec, 3 + c)
+    xyz = I.uniform_points(16 * 23 + 9, 4, -0.999, 0.999)
+    dref, gref = O.grad_points(onet, xyz)
+    for prec, dtol, gtol in (("f32", FP32_TOL, GRAD32_TOL), ("f16", FP16_TOL, GRAD16_TOL)):
+        d, g = FV.fvsrn_grad_points(gnet, torch.from_numpy(xyz).cuda(), 0.0, prec)
+        derr, gerr = np.abs(d.cpu().numpy() - dref).max(), _grad_err(g.cpu().numpy(), gref)
+        _report("grad c=%d F=%d L=%d %s density / gradient" % (c, F, L, prec), max(derr, gerr))
+        assert derr <= dtol and gerr <= gtol
+    tf = I.ramp_tf()
+    cams = I.orbit_cameras(1, 15, 11)
+    m = I.March(step=1 / 96, ert_eps=0.0, phong=True)
+    ref, _ = O.render(O.Field(net=onet), tf, cams, m)
+    img = FV.fvsrn_render(gnet, tf, cams, m, "f16").cpu().numpy()
+    err = np.abs(img - ref).max()
+    _report("phong c=%d F=%d L=%d f16" % (c, F, L), err)
+    assert err <= FP16_TOL
+
+
+def test_extended_shapes_unsupported_combinations(FV):
+    """Shapes compiled for the sine activation only report the others as not
+    compiled, before any launch."""
+    spec = I.NetSpec(R=9, F=16, L=4, c=32, H=2, act="snakealt")
+    lat, w = I.net_params(spec, 1)
+    net = FV.Network(spec, lat, w)
+    with pytest.raises(FV.FvsrnError) as e:
+        FV.fvsrn_eval_points(net, torch.zeros((64, 3), device="cuda"), 0.0, "f32")
+    assert e.value.status == FV.ERR_UNSUPPORTED

@@ -488,3 +488,24 @@ def test_train_gradients_against_central_differences(FV):
         lm[j] -= h
         fd = (loss(lp, w) - loss(lm, w)) / (2 * h)
         assert abs(fd - g[j]) <= 2e-3 * max(1.0, abs(fd)), (j, fd, g[j])
+
+
+@pytest.mark.parametrize("c,F,L", [(32, 16, 4), (48, 8, 8)])
+def test_train_gradients_extended_shapes(FV, c, F, L):
+    """One L1 training step of networks whose latent channels and Fourier
+    octaves are chosen independently, against the oracle."""
+    spec = I.NetSpec(R=12, F=F, L=L, c=c, H=3)
+    n = 16 * 53 + 11
+    gnet, onet, xyz = _setup(FV, spec, 17, n)
+    d = O.eval_points(onet, xyz)
+    rng = np.random.default_rng(5)
+    target = (d + rng.uniform(0.01, 0.3, n) * rng.choice([-1, 1], n)).astype(np.float32)
+    dl_ref, dw_ref, loss_ref = O.train_grads(onet, xyz, target=target.astype(np.float64))
+    d_lat, d_w = torch.empty_like(gnet.latent), torch.empty_like(gnet.weights)
+    loss = torch.zeros(1, device="cuda")
+    FV.fvsrn_train_step(gnet, d_lat, d_w, torch.from_numpy(xyz).cuda(), target=torch.from_numpy(target).cuda(),
+                        out_loss=loss)
+    e_w, e_l = _rel(d_w.cpu().numpy(), dw_ref), _rel(d_lat.cpu().numpy(), dl_ref)
+    print("train c=%d F=%d L=%d: dW %.3g, dG %.3g" % (c, F, L, e_w, e_l), flush=True)
+    assert e_w <= 1e-4 and e_l <= 1e-4
+    assert abs(loss.item() - loss_ref) <= 1e-5 * abs(loss_ref) + 1e-7
