@@ -12,7 +12,8 @@
  * General rules for every entry point:
  *  - Pointers are DEVICE pointers unless marked [host]. The caller owns every
  *    buffer; the library allocates nothing and keeps no state beyond cached
- *    device properties.
+ *    device properties (and the static per-GPU workspace of
+ *    fvsrn_train_step_noalloc, allocated with its code object).
  *  - Device buffers must be 16-byte aligned.
  *  - Calls are asynchronous on `stream` (a hipStream_t passed as void*; NULL
  *    is the default stream). Argument errors are detected on the host before
@@ -265,6 +266,28 @@ fvsrn_status fvsrn_train_step(const fvsrn_net_desc* desc, float* latent, float* 
                               const float* dloss_dy, const fvsrn_adam* adam, float* out_loss, void* workspace,
                               size_t workspace_bytes, void* stream);
 size_t fvsrn_train_workspace_size(const fvsrn_net_desc* desc, int64_t n);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving or training loops, harnesses that forbid
+   hipMalloc): fvsrn_train_step with the same arguments, minus the
+   workspace, and the same results (the same kernels and partition, so
+   d_weights equals fvsrn_train_step's bit for bit). It allocates nothing:
+   its workspace is a static device array of FVSRN_TRAIN_STATIC_WORKSPACE_BYTES
+   on each GPU, allocated with the library's code object and held until the
+   process ends. A step whose fvsrn_train_workspace_size exceeds that returns
+   FVSRN_ERR_WORKSPACE before any launch (e.g. 2^18 points fit the 32^3 x 16,
+   4 x 32 network, 81 MiB, but not the 64^3 x 16, 4 x 48 one, 132 MiB).
+   Every call on one GPU shares that GPU's array and the kernels overwrite
+   or clear what they use, so calls that overlap on one GPU (other streams,
+   other host threads) race and must be serialised by the caller. The
+   device address is looked up once per GPU at the first call on it. */
+#define FVSRN_TRAIN_STATIC_WORKSPACE_BYTES ((size_t)96 << 20)
+fvsrn_status fvsrn_train_step_noalloc(const fvsrn_net_desc* desc, float* latent, float* weights,
+                                      const float* key_times, float* d_latent, float* d_weights,
+                                      const float* xyz, const float* times, int64_t n,
+                                      const float* target, const float* target_grad, float grad_weight,
+                                      const float* dloss_dy, const fvsrn_adam* adam, float* out_loss,
+                                      void* stream);
 
 /* Plain dense-grid DVR with the same rays, transfer function and compositor
    (the uncompressed reference the paper renders, Sec. 5): vol [nz][ny][nx]

@@ -376,11 +376,17 @@ size_t fvsrn_train_workspace_size(const fvsrn_net_desc* desc, int64_t n) {
   return train_workspace_bytes(nd, n);
 }
 
-fvsrn_status fvsrn_train_step(const fvsrn_net_desc* desc, float* latent, float* weights, const float* key_times,
-                              float* d_latent, float* d_weights, const float* xyz, const float* times, int64_t n,
-                              const float* target, const float* target_grad, float grad_weight,
-                              const float* dloss_dy, const fvsrn_adam* adam, float* out_loss,
-                              void* workspace, size_t workspace_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// fvsrn_train_step with the caller's workspace, or (static_ws) with the
+// library's per-GPU static workspace.
+fvsrn_status train_step_impl(const fvsrn_net_desc* desc, float* latent, float* weights, const float* key_times,
+                             float* d_latent, float* d_weights, const float* xyz, const float* times, int64_t n,
+                             const float* target, const float* target_grad, float grad_weight,
+                             const float* dloss_dy, const fvsrn_adam* adam, float* out_loss, void* workspace,
+                             size_t workspace_bytes, bool static_ws, void* stream) {
   g_err[0] = 0;
   fvsrn_status s;
   if ((s = check_desc(desc)) != FVSRN_OK) return s;
@@ -417,8 +423,18 @@ fvsrn_status fvsrn_train_step(const fvsrn_net_desc* desc, float* latent, float* 
   const NetDev nd = make_net(desc, latent, weights);
   if (n >= (1LL << 31)) return fail(FVSRN_ERR_INVALID_ARGUMENT, "training takes fewer than 2^31 points per step");
   const size_t need = train_workspace_bytes(nd, n);
-  if (need > 0 && (!workspace || ((uintptr_t)workspace & 15u) || workspace_bytes < need))
+  if (static_ws) {
+    if (need > kStaticTrainScratchBytes)
+      return fail(FVSRN_ERR_WORKSPACE,
+                  "fvsrn_train_step_noalloc: this step needs %zu bytes of workspace, above the static %zu; "
+                  "use fvsrn_train_step or fewer points",
+                  need, kStaticTrainScratchBytes);
+    if (static_train_scratch(&workspace) != 0)
+      return fail(FVSRN_ERR_DEVICE, "fvsrn_train_step_noalloc: static workspace address lookup failed");
+    workspace_bytes = kStaticTrainScratchBytes;
+  } else if (need > 0 && (!workspace || ((uintptr_t)workspace & 15u) || workspace_bytes < need)) {
     return fail(FVSRN_ERR_WORKSPACE, "workspace of %zu bytes (16-byte aligned) required", need);
+  }
   KeyTimes kt;
   kt.K = desc->num_keyframes;
   for (int k = 0; k < kMaxKeyframes; ++k) kt.t[k] = (k < kt.K && key_times) ? key_times[k] : 0.0f;
@@ -429,7 +445,29 @@ fvsrn_status fvsrn_train_step(const fvsrn_net_desc* desc, float* latent, float* 
                               adam ? adam->m_latent : nullptr, adam ? adam->v_latent : nullptr,
                               adam ? adam->m_weights : nullptr, adam ? adam->v_weights : nullptr, out_loss,
                               workspace, workspace_bytes, stream);
-  return launch_status(rc, "fvsrn_train_step");
+  return launch_status(rc, static_ws ? "fvsrn_train_step_noalloc" : "fvsrn_train_step");
+}
+
+}  // namespace
+
+extern "C" {
+
+fvsrn_status fvsrn_train_step(const fvsrn_net_desc* desc, float* latent, float* weights, const float* key_times,
+                              float* d_latent, float* d_weights, const float* xyz, const float* times, int64_t n,
+                              const float* target, const float* target_grad, float grad_weight,
+                              const float* dloss_dy, const fvsrn_adam* adam, float* out_loss,
+                              void* workspace, size_t workspace_bytes, void* stream) {
+  return train_step_impl(desc, latent, weights, key_times, d_latent, d_weights, xyz, times, n, target, target_grad,
+                         grad_weight, dloss_dy, adam, out_loss, workspace, workspace_bytes, false, stream);
+}
+
+fvsrn_status fvsrn_train_step_noalloc(const fvsrn_net_desc* desc, float* latent, float* weights,
+                                      const float* key_times, float* d_latent, float* d_weights, const float* xyz,
+                                      const float* times, int64_t n, const float* target, const float* target_grad,
+                                      float grad_weight, const float* dloss_dy, const fvsrn_adam* adam,
+                                      float* out_loss, void* stream) {
+  return train_step_impl(desc, latent, weights, key_times, d_latent, d_weights, xyz, times, n, target, target_grad,
+                         grad_weight, dloss_dy, adam, out_loss, nullptr, 0, true, stream);
 }
 
 fvsrn_status fvsrn_ssim_map(const float* a, const float* b, int32_t width, int32_t height, int32_t n_images,

@@ -108,6 +108,12 @@ int launch_train(const NetDev& net, const KeyTimes& kt, float* latent, float* we
                  float eps, int step, float* m_lat, float* v_lat, float* m_w, float* v_w, float* out_loss,
                  void* workspace, size_t ws_bytes, void* stream);
 
+// Size of the per-GPU training workspace of fvsrn_train_step_noalloc.
+constexpr size_t kStaticTrainScratchBytes = (size_t)96 << 20;
+// Device address of that workspace on the current device (looked up once per
+// device): 0, or 2 when the lookup fails.
+int static_train_scratch(void** ptr);
+
 const char* last_hip_error();
 
 // Launcher results: 0 launched; 1 configuration not compiled; 2 the launch

@@ -23,6 +23,8 @@
 // dW is bitwise reproducible). slice_sum_kernel and gather_kernel then sum the
 // slices in a fixed order into the packed gradient; adam_kernel applies the
 // update.
+#include <mutex>
+
 #include "fvsrn_net.hpp"
 
 namespace fvsrn_detail {
@@ -832,7 +834,30 @@ struct TrainEntry {
   X(48, 16, 4)                \
   X(48, 8, 8)
 
+// Training workspace for callers that cannot allocate device memory: one
+// array per GPU, allocated with the code object and held until the process
+// ends. Host code must not pass `scratch` itself to a kernel (on the host the
+// name is only a stand-in for the device symbol); it uses the address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[kStaticTrainScratchBytes];
+
 }  // namespace
+
+int static_train_scratch(void** ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 2;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return 2;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return 0;
+}
 
 size_t train_workspace_bytes(const NetDev& nd, long long n) {
 #define X(C_, F_, L_)                                                            \

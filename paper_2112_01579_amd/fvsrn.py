@@ -30,7 +30,7 @@ EXPORTS = (
     "fvsrn_train_workspace_size", "fvsrn_render_dense", "fvsrn_dense_eval_points", "fvsrn_dense_grad_points",
     "fvsrn_sample_points", "fvsrn_cast_grid", "fvsrn_quantize_grid", "fvsrn_ssim_map", "fvsrn_num_weights",
     "fvsrn_voxel_points", "fvsrn_error_grid", "fvsrn_sample_points_weighted", "fvsrn_weighted_points_workspace_size",
-    "fvsrn_status_str", "fvsrn_last_error", "fvsrn_build_id",
+    "fvsrn_status_str", "fvsrn_last_error", "fvsrn_build_id", "fvsrn_train_step_noalloc",
 )
 
 
@@ -102,6 +102,8 @@ def lib():
             "fvsrn_grad_points": (st, [vp, vp, vp, i64, C.c_float, i32, vp, vp, vp]),
             "fvsrn_train_step": (st, [vp, vp, vp, C.POINTER(C.c_float), vp, vp, vp, vp, i64, vp, vp, C.c_float,
                                       vp, vp, vp, vp, sz, vp]),
+            "fvsrn_train_step_noalloc": (st, [vp, vp, vp, C.POINTER(C.c_float), vp, vp, vp, vp, i64, vp, vp,
+                                              C.c_float, vp, vp, vp, vp]),
             "fvsrn_train_workspace_size": (sz, [vp, i64]),
             "fvsrn_render_dense": (st, [vp, i32, i32, i32, vp, vp, i32, vp, vp, vp, vp]),
             "fvsrn_dense_eval_points": (st, [vp, i32, i32, i32, vp, i64, vp, vp]),
@@ -503,7 +505,26 @@ def fvsrn_train_step(net: Network, d_latent: torch.Tensor, d_weights: torch.Tens
     4-output networks, L1 mode) the gradient targets of the predicted
     gradient, weighted by ``grad_weight``. ``adam`` is a dict with
     lr_grid, lr_mlp, beta1, beta2, eps, step and the four moment tensors
-    m_latent, v_latent, m_weights, v_weights; None computes gradients only."""
+    m_latent, v_latent, m_weights, v_weights; None computes gradients only.
+    ``workspace`` (uint8, optional) is allocated here when None."""
+    _train_step(net, d_latent, d_weights, xyz, target, dloss_dy, adam, out_loss, workspace, times, target_grad,
+                grad_weight, stream, noalloc=False)
+
+
+def fvsrn_train_step_noalloc(net: Network, d_latent: torch.Tensor, d_weights: torch.Tensor, xyz: torch.Tensor,
+                             target: Optional[torch.Tensor] = None, dloss_dy: Optional[torch.Tensor] = None,
+                             adam: Optional[dict] = None, out_loss: Optional[torch.Tensor] = None,
+                             times: Optional[torch.Tensor] = None, target_grad: Optional[torch.Tensor] = None,
+                             grad_weight: float = 0.0, stream=None):
+    """fvsrn_train_step on the library's static per-GPU workspace: nothing
+    is allocated (by the library or here). Calls on one GPU share that
+    workspace and must not overlap."""
+    _train_step(net, d_latent, d_weights, xyz, target, dloss_dy, adam, out_loss, None, times, target_grad,
+                grad_weight, stream, noalloc=True)
+
+
+def _train_step(net, d_latent, d_weights, xyz, target, dloss_dy, adam, out_loss, workspace, times, target_grad,
+                grad_weight, stream, noalloc):
     dev = _check_net(net)
     if net.grid_dtype != F32:
         raise FvsrnArgumentError("training needs an FP32 latent grid")
@@ -522,16 +543,24 @@ def fvsrn_train_step(net: Network, d_latent: torch.Tensor, d_weights: torch.Tens
                        ("m_weights", net.spec.n_weights), ("v_weights", net.spec.n_weights)):
             check_tensor(adam[k], "adam[%s]" % k, numel=cnt, device=dev)
     d = net.desc("f32")
-    if workspace is None:
-        ws = lib().fvsrn_train_workspace_size(C.byref(d), n)
-        workspace = torch.empty(max(ws, 16), dtype=torch.uint8, device=xyz.device)
-    check_tensor(workspace, "workspace", dtype=torch.uint8, device=dev)
+    if not noalloc:
+        if workspace is None:
+            ws = lib().fvsrn_train_workspace_size(C.byref(d), n)
+            workspace = torch.empty(max(ws, 16), dtype=torch.uint8, device=xyz.device)
+        check_tensor(workspace, "workspace", dtype=torch.uint8, device=dev)
     a = None
     if adam is not None:
         a = AdamStruct(adam["lr_grid"], adam["lr_mlp"], adam.get("beta1", 0.9), adam.get("beta2", 0.999),
                        adam.get("eps", 1e-8), adam["step"], adam["m_latent"].data_ptr(),
                        adam["v_latent"].data_ptr(), adam["m_weights"].data_ptr(), adam["v_weights"].data_ptr())
     kt = C.cast(net._kt, C.POINTER(C.c_float)) if net._kt is not None else None
+    if noalloc:
+        _check(lib().fvsrn_train_step_noalloc(C.byref(d), _ptr(net.latent), _ptr(net.weights), kt, _ptr(d_latent),
+                                              _ptr(d_weights), _ptr(xyz), _ptr(times), n, _ptr(target),
+                                              _ptr(target_grad), float(grad_weight), _ptr(dloss_dy),
+                                              C.byref(a) if a is not None else None, _ptr(out_loss),
+                                              _stream(stream)), "fvsrn_train_step_noalloc")
+        return
     _check(lib().fvsrn_train_step(C.byref(d), _ptr(net.latent), _ptr(net.weights), kt, _ptr(d_latent),
                                   _ptr(d_weights), _ptr(xyz), _ptr(times), n, _ptr(target), _ptr(target_grad),
                                   float(grad_weight), _ptr(dloss_dy),
