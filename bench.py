@@ -184,6 +184,24 @@ def cpu_baseline(spec, lat16, w, tf, cams, march):
             "cpu_model": cpu_model(), "cpu_affinity": len(os.sched_getaffinity(0))}
 
 
+def eval_points_only(args, spec, dev):
+    """2^24 uniform points through fvsrn_eval_points, FP16 network on the FP16
+    grid and FP32 network on the FP32 grid: one JSON line of points/s."""
+    import torch
+    from paper_2112_01579_amd import inputs as I
+    from paper_2112_01579_amd import fvsrn as FV
+    lat, w = I.net_params(spec, I.SEED_STUDY)
+    npts = 1 << 24
+    xyz = FV.fvsrn_sample_points(I.SEED_STUDY, 1 << 43, npts, device=dev)
+    dens = torch.empty(npts, device=dev)
+    res = {"metric": "fused point evaluation, 2^24 uniform points", "unit": "points/s"}
+    for prec, gd in (("f16", FV.F16), ("f32", FV.F32)):
+        net = FV.Network(spec, lat, w, grid_dtype=gd, device=dev)
+        per, _ = time_launches(lambda: FV.fvsrn_eval_points(net, xyz, 0.0, prec, out=dens), args.steps, args.warmup)
+        res[prec] = {"points_per_s": npts / (float(np.median(per)) * 1e-3), "ms": float(np.median(per))}
+    print(json.dumps(res))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -195,6 +213,9 @@ def main():
                     help="also run a plain 256 MiB device-to-device copy (reference for rocprofv3 byte counters)")
     ap.add_argument("--train-steps", type=int, default=2000,
                     help="Adam steps (2^18 points each) fitting the network before timing")
+    ap.add_argument("--eval-points-only", action="store_true",
+                    help="time only the fused point evaluation of 2^24 uniform points (FP16 and FP32 networks, "
+                         "the study network with its initial weights); for profiling that kernel")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the fV-SRN path is single-GPU (rays and points are "
@@ -208,6 +229,9 @@ def main():
     FV.lib()
     dev = torch.device("cuda:0")
     spec = I.NET_STUDY
+    if args.eval_points_only:
+        eval_points_only(args, spec, dev)
+        return
     vol = torch.from_numpy(I.gaussian_volume(256, 64, seed=I.SEED_STUDY)).to(dev)
     lat, w = I.net_params(spec, I.SEED_STUDY)
     train_info = None

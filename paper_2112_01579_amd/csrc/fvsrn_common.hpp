@@ -176,6 +176,26 @@ __device__ inline void axis_cell(float p, int R, int& i, float& f) {
   axis_cell(p, R, i, f, d);
 }
 
+// axis_cell for the packed FP16 gathers: the coordinate is clamped to the
+// float just below R-1, so its integer part is at most R-2 without a separate
+// cap and its fraction is one v_fract (on the top face the fraction is then
+// 1 - 2^-24 (R-1) instead of 1, far below the FP16 rounding of the weights).
+__device__ inline void axis_cell_h(float p, int R, int& i, float& f, float& dfdp) {
+  const float scale = 0.5f * (float)(R - 1);
+  dfdp = (p < -1.0f || p > 1.0f) ? 0.0f : scale;
+  const float top = __uint_as_float(__float_as_uint((float)(R - 1)) - 1u);
+  const float u = __builtin_amdgcn_fmed3f(fmaf(p, scale, scale), 0.0f, top);
+  i = (int)u;
+  f = __builtin_amdgcn_fractf(u);
+}
+
+// Element offset of a vertex, x fastest: ix sx + iy sy + iz sz, the y and z
+// terms on the 24-bit multipliers (every index and stride of a grid below
+// 2^31 bytes fits 24 bits; sx is the channel count, a power of two).
+__device__ inline unsigned vertex_offset(int ix, int iy, int iz, unsigned sx, unsigned sy, unsigned sz) {
+  return __umul24((unsigned)iz, sz) + __umul24((unsigned)iy, sy) + (unsigned)ix * sx;
+}
+
 // ------------------------------------------------------------- rays
 
 // One view ray: origin, unit direction, the chord [t0, t1] inside [-1,1]^3

@@ -104,13 +104,13 @@ __device__ inline void tf_eval(const TFDev& tf, float d, float rgba[4]) {
   }
 }
 
-// Segment i of a ray: midpoint parameter and length (last one clipped).
-__device__ inline void segment(const Ray& r, int i, bool fixed, float& tm, float& len) {
-  const float a0 = r.t0 + (float)i * r.ds;
-  float a1 = r.t0 + (float)(i + 1) * r.ds;
-  if (!fixed) a1 = fminf(a1, r.t1);
-  len = a1 - a0;
-  tm = 0.5f * (a0 + a1);
+// Segment i of a ray: midpoint parameter and length, the segment ending at
+// t_end (the chord's end, or +inf for fixed-count marches: the last of their
+// equal segments already ends there).
+__device__ inline void segment(const Ray& r, int i, float t_end, float& tm, float& len) {
+  const float a0 = fmaf((float)i, r.ds, r.t0);
+  len = fminf(a0 + r.ds, t_end) - a0;
+  tm = fmaf(0.5f, len, a0);
 }
 
 // Headlight Blinn-Phong (Sec. 6): light and view along -dir, normal = the
@@ -210,29 +210,30 @@ __global__ __launch_bounds__((max_waves<CF, MODE>() * 64)) void march_kernel(Net
     float tfe[G::TIN > 0 ? G::TIN : 1];  // the view's time inputs (time-encoded networks)
     if constexpr (G::TIN > 0) time_features<CF::TE>(cam.tau, tfe);
     Accum acc = {1.0f, {0.0f, 0.0f, 0.0f}, 0.0f};
-    // position and length of segment ii (the origin for a lane without a sample)
+    const float t_end = fixed ? INFINITY : ray.t1;
+    // position and length of segment ii. A lane whose ray has ended keeps
+    // sampling its (finite) ray past the end: the cell clamps keep its loads
+    // inside the grid and its result is not composited. The FP64 positions
+    // of FP32 networks are zeroed for such lanes.
     auto sample_at = [&](int ii, bool act, float& sx, float& sy, float& sz, float& len) {
       if constexpr (kPosF64) {
         float pp[3];
         segment_d(rayd, ii, fixed, fd_off, pp, len);
-        sx = pp[0];
-        sy = pp[1];
-        sz = pp[2];
+        sx = act ? pp[0] : 0.0f;
+        sy = act ? pp[1] : 0.0f;
+        sz = act ? pp[2] : 0.0f;
       } else {
         float tm;
-        segment(ray, ii, fixed, tm, len);
-        sx = ray.o[0] + tm * ray.d[0];
-        sy = ray.o[1] + tm * ray.d[1];
-        sz = ray.o[2] + tm * ray.d[2];
+        segment(ray, ii, t_end, tm, len);
+        sx = fmaf(tm, ray.d[0], ray.o[0]);
+        sy = fmaf(tm, ray.d[1], ray.o[1]);
+        sz = fmaf(tm, ray.d[2], ray.o[2]);
         if constexpr (FD) {
           sx += fd_off[0];
           sy += fd_off[1];
           sz += fd_off[2];
         }
       }
-      sx = act ? sx : 0.0f;
-      sy = act ? sy : 0.0f;
-      sz = act ? sz : 0.0f;
     };
     int i = 0;
     while (__builtin_amdgcn_ballot_w64(active)) {
@@ -286,18 +287,15 @@ __global__ __launch_bounds__((max_waves<CF, MODE>() * 64)) void march_kernel(Net
       } else {
         dens = sigmoid_f(y);
       }
-      if (active) {
-        if (len <= 0.0f) {
-          active = false;
-        } else {
-          float rgba[4];
-          tf_eval(tf, dens, rgba);
-          if (m.phong) phong(rgba, gx, gy, gz, ray.d, m);
-          composite(acc, rgba, len);
-          ++i;
-          if (acc.T < m.ert_eps || i >= ray.nseg) active = false;
-        }
-      }
+      // branch-free: a lane without a sample composites a zero-length
+      // segment, which changes nothing (transmittance factor exp(0) = 1)
+      const bool comp = active && len > 0.0f;
+      float rgba[4];
+      tf_eval(tf, dens, rgba);
+      if (m.phong) phong(rgba, gx, gy, gz, ray.d, m);
+      composite(acc, rgba, comp ? len : 0.0f);
+      i += comp ? 1 : 0;
+      active = comp && !(acc.T < m.ert_eps) && i < ray.nseg;
     }
     const bool owner = q == 0;
     if (in_img && owner) {

@@ -366,9 +366,9 @@ struct LatentColumnH {
   __device__ inline void begin(const LatentSrc& ls, const LaneRole& role, float px, float py, float pz) {
     int ix, iy, iz;
     float fx, fy, fz, dx, dy, dz;
-    axis_cell(px, ls.R, ix, fx, dx);
-    axis_cell(py, ls.R, iy, fy, dy);
-    axis_cell(pz, ls.R, iz, fz, dz);
+    axis_cell_h(px, ls.R, ix, fx, dx);
+    axis_cell_h(py, ls.R, iy, fy, dy);
+    axis_cell_h(pz, ls.R, iz, fz, dz);
     const bool tx = !role.is_val && role.axis == 0, ty = !role.is_val && role.axis == 1,
                tz = !role.is_val && role.axis == 2;
     const float x0 = tx ? -dx : 1.0f - fx, x1 = tx ? dx : fx;
@@ -377,7 +377,7 @@ struct LatentColumnH {
     z1 = tz ? dz : fz;
     const unsigned R = (unsigned)ls.R;
     const unsigned sx = F, sy = R * F, sz = R * R * F;
-    base = (unsigned)iz * sz + (unsigned)iy * sy + (unsigned)ix * sx;
+    base = vertex_offset(ix, iy, iz, sx, sy, sz);
     corner_offsets(sx, sy, sz, off);
     xy[0] = x0 * y0;
     xy[1] = x1 * y0;
@@ -435,9 +435,9 @@ __device__ inline void latent_column_h(const LatentSrc& ls, const LaneRole& role
                                        h2* z2) {
   int ix, iy, iz;
   float fx, fy, fz, dx, dy, dz;
-  axis_cell(px, ls.R, ix, fx, dx);
-  axis_cell(py, ls.R, iy, fy, dy);
-  axis_cell(pz, ls.R, iz, fz, dz);
+  axis_cell_h(px, ls.R, ix, fx, dx);
+  axis_cell_h(py, ls.R, iy, fy, dy);
+  axis_cell_h(pz, ls.R, iz, fz, dz);
   const bool tx = !role.is_val && role.axis == 0, ty = !role.is_val && role.axis == 1,
              tz = !role.is_val && role.axis == 2;
   const float x0 = tx ? -dx : 1.0f - fx, x1 = tx ? dx : fx;
@@ -445,7 +445,7 @@ __device__ inline void latent_column_h(const LatentSrc& ls, const LaneRole& role
   const float z0 = tz ? -dz : 1.0f - fz, z1 = tz ? dz : fz;
   const unsigned R = (unsigned)ls.R;
   const unsigned sx = F, sy = R * F, sz = R * R * F;
-  const unsigned base = (unsigned)iz * sz + (unsigned)iy * sy + (unsigned)ix * sx;
+  const unsigned base = vertex_offset(ix, iy, iz, sx, sy, sz);
   unsigned off[8];
   corner_offsets(sx, sy, sz, off);
   const float xy[4] = {x0 * y0, x1 * y0, x0 * y1, x1 * y1};
