@@ -52,11 +52,20 @@ struct TrainCfg {
   static_assert(4 * S <= 64, "four outputs of S samples must fit the dL/dy buffer");
   static constexpr int ZBUF = S * ZS * 4;
   __host__ __device__ static int wave_bytes(int H) { return FEAT + abuf_bytes(H) + DBUF + DY + ZBUF; }
-  // backward weight fragments (block-level, after the forward ones)
+  // The backward pass needs W^T. For c = 32 a transposed copy of each hidden
+  // layer and of W_0's latent columns is staged once per workgroup (14 KiB at
+  // H = 4: one wave of seven fewer per CU, but lane-contiguous reads); wider
+  // networks read W^T from the forward fragments instead (strided reads with
+  // bank conflicts, but for c = 48 the copy would cost a quarter of the
+  // waves: measured 0.80 -> 0.62 ms per 2^18-point Adam step, while c = 32
+  // measured 0.415 with the copy against 0.433 without).
+  static constexpr bool kBackCopy = C == 32;
   static constexpr int WB = MT * 4 * MT * 64 * 4;   // one hidden layer's W^T
   static constexpr int WZ = 4 * MT * 64 * 4;        // latent columns of W_0, transposed
-  __host__ __device__ static int back_bytes(int H) { return (H - 1) * WB + WZ; }
-  __host__ __device__ static int block_bytes(int H, int waves) { return G::weight_bytes(H) + back_bytes(H) + waves * wave_bytes(H); }
+  __host__ __device__ static int back_bytes(int H) { return kBackCopy ? (H - 1) * WB + WZ : 0; }
+  __host__ __device__ static int block_bytes(int H, int waves) {
+    return G::weight_bytes(H) + back_bytes(H) + waves * wave_bytes(H);
+  }
   // workspace slice (floats)
   __host__ __device__ static int tiles(int H) { return MT * NK0 + (H - 1) * MT * MT + MT + (H - 1) * MT; }
   // after the tiles: per-lane partials of the four output biases, then of the loss
@@ -136,7 +145,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
   extern __shared__ __attribute__((aligned(16))) char smem[];
   stage_weights<CF>(nd, smem);
   char* back = smem + G::weight_bytes(H);
-  stage_backward<TC, ACT>(nd, back);
+  if constexpr (TC::kBackCopy) stage_backward<TC, ACT>(nd, back);
   __syncthreads();
   const int wave_l = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wave = blockIdx.x * (blockDim.x >> 6) + wave_l;
@@ -157,6 +166,15 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
   const float* w_out = nd.weights + (long long)C * G::K0IN + C + (long long)(H - 1) * (C * C + C);
   float loss_acc = 0.0f;
   f4 dbo_acc = {0.0f, 0.0f, 0.0f, 0.0f};
+  // Without the copy, W^T from the forward A fragments. Hidden layer i holds W_i[o][k] * sc at
+  // ((o / 16) 4MT + 4 (k / 16) + k % 4) 64 + 16 ((k % 16) / 4) + o % 16; the
+  // backward A operand of lane (g, n) at step q, M-tile mk is W_i[o][k] with
+  // o = 16 (q / 4) + 4 g + q % 4 and k = 16 mk + n. Layer 0's latent column m
+  // sits at input-row column m. sc is the 1 / (2 pi) the forward fragments
+  // carry for periodic activations; the deltas are multiplied by its inverse.
+  const int wt_lane = (nn & 3) * kWave + 16 * (nn >> 2) + 4 * g;
+  const int wz_lane = ((nn % G::Q0) * kWave + 16 * (nn / G::Q0) + 4 * g);
+  const float inv_sc = ACT == kIdentity ? 1.0f : k2Pi;
   const long long nchunks = (n + S - 1) / S;
   bool first = true;
   // Branch-free on purpose: the stored value is always produced by a VALU
@@ -365,6 +383,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
       }
       if (i >= 1) {
         // d L / d h_{i-1} = W_i^T delta_i (MFMA, B = delta in D layout)
+        const float* WH = reinterpret_cast<const float*>(smem + G::W0A + (i - 1) * G::HID);
         const float* WB = reinterpret_cast<const float*>(back + (i - 1) * TC::WB);
 #pragma unroll
         for (int t = 0; t < NTC; ++t) {
@@ -373,21 +392,35 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
           for (int mk = 0; mk < MT; ++mk) nd2[mk] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
           for (int q = 0; q < 4 * MT; ++q) {
-            const float b = dh[t][q / 4][q % 4];
+            if constexpr (TC::kBackCopy) {
+              const float b = dh[t][q / 4][q % 4];
 #pragma unroll
-            for (int mk = 0; mk < MT; ++mk) nd2[mk] = PR::mma(WB[(mk * 4 * MT + q) * kWave + lane], b, nd2[mk]);
+              for (int mk = 0; mk < MT; ++mk) nd2[mk] = PR::mma(WB[(mk * 4 * MT + q) * kWave + lane], b, nd2[mk]);
+            } else {
+              const float b = dh[t][q / 4][q % 4] * inv_sc;
+#pragma unroll
+              for (int mk = 0; mk < MT; ++mk)
+                nd2[mk] = PR::mma(WH[((q / 4) * 4 * MT + 4 * mk) * kWave + (q % 4) + wt_lane], b, nd2[mk]);
+            }
           }
 #pragma unroll
           for (int mk = 0; mk < MT; ++mk) dh[t][mk] = nd2[mk];
         }
       } else {
         // d L / d z = W_0[:, latent]^T delta_0 -> zbuf[s][f]
-        const float* WZ = reinterpret_cast<const float*>(back + (H - 1) * TC::WB);
 #pragma unroll
         for (int t = 0; t < NTC; ++t) {
           f4 dz = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-          for (int q = 0; q < 4 * MT; ++q) dz = PR::mma(WZ[q * kWave + lane], dh[t][q / 4][q % 4], dz);
+          for (int q = 0; q < 4 * MT; ++q) {
+            if constexpr (TC::kBackCopy) {
+              const float* WZ = reinterpret_cast<const float*>(back + (H - 1) * TC::WB);
+              dz = PR::mma(WZ[q * kWave + lane], dh[t][q / 4][q % 4], dz);
+            } else {
+              const float a = nn < F ? W0[(q / 4) * G::Q0 * kWave + (q % 4) + wz_lane] : 0.0f;
+              dz = PR::mma(a, dh[t][q / 4][q % 4] * inv_sc, dz);
+            }
+          }
           if (4 * g < F) *reinterpret_cast<f4*>(zbuf + (16 * t + nn) * TC::ZS + 4 * g) = dz;
         }
       }
