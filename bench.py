@@ -490,6 +490,28 @@ def main():
                 del etr, enet, e16
             comp["time_encodings"] = {"train": "even timesteps 0..14, %d steps of 2^18 points" % esteps,
                                       "evaluated_on": "odd timesteps 1..15", **enc}
+            # adaptive resampling of the time-varying network (Sec. 5.4 with
+            # Sec. 8): uniform positions against one error grid per timestep
+            # (64^3 voxels x 8 positions, refreshed every 50 steps), the same
+            # steps each; mean |density error| over all 16 timesteps
+            tvr = {}
+            for name, every in (("uniform", 0), ("resampled_every_50", 50)):
+                rlat, rw = I.net_params(tspec, I.SEED_TIME)
+                rnet = FV.Network(tspec, rlat, rw, key_times=I.TIME_KEYS, grid_dtype=FV.F32, device=dev)
+                rtr = Trainer(rnet, frames, batch=1 << 18, seed=I.SEED_TIME, resample_every=every, error_grid=64,
+                              per_voxel=8)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(esteps):
+                    rtr.step()
+                torch.cuda.synchronize()
+                t_r = time.perf_counter() - t0
+                l1 = float(np.mean([torch.mean(torch.abs(FV.fvsrn_eval_points(rnet, xe, t, "f32") -
+                                                         FV.fvsrn_dense_eval_points(v, xe))).item() for t, v in frames]))
+                tvr[name] = {"l1_all_timesteps": l1, "train_ms_per_step": t_r / esteps * 1e3}
+                del rtr, rnet
+            comp["time_varying_adaptive_resampling"] = {
+                "train": "16 timesteps, %d steps of 2^18 points, error grids 64^3 x 8 per timestep" % esteps, **tvr}
             del frames, ttr, tnet32
         progress("Fourier features")
         # Fourier features (Sec. 3, Sec. 5.3): the octave construction against

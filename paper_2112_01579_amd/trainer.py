@@ -33,10 +33,13 @@ class Trainer:
     differences of the volume (the gradients the dense renderer shades with),
     weighted L1 next to the density's L1.
 
-    ``resample_every`` = N > 0 turns on adaptive resampling (Sec. 5.4, single
-    volume): after every N steps the mean absolute error of the network is
-    measured on an ``error_grid``^3 voxel grid (``per_voxel`` positions per
-    voxel), and the next N steps draw their positions in proportion to it."""
+    ``resample_every`` = N > 0 turns on adaptive resampling (Sec. 5.4): after
+    every N steps the mean absolute error of the network is measured on an
+    ``error_grid``^3 voxel grid (``per_voxel`` positions per voxel), and the
+    next N steps draw their positions in proportion to it. A time-varying
+    network keeps one error grid per timestep (the network at that time
+    against that timestep's volume), and each timestep's part of the batch
+    is drawn from its own grid."""
 
     def __init__(self, net: FV.Network, vol, batch: int = 1 << 18, lr_grid: float = 1e-2,
                  lr_mlp: float = 1e-3, betas=(0.9, 0.999), eps: float = 1e-8, seed: int = 0,
@@ -73,20 +76,23 @@ class Trainer:
         self.resample_every, self.G, self.per_voxel = int(resample_every), int(error_grid), int(per_voxel)
         self.E = None
         if self.resample_every:
-            assert len(self.frames) == 1, "adaptive resampling is for a single volume"
             n_err = self.G ** 3 * self.per_voxel
             self.err_xyz = torch.empty((n_err, 3), dtype=torch.float32, device=dev)
             self.err_scratch = torch.empty(n_err, dtype=torch.float32, device=dev)
-            self.E = torch.empty(self.G ** 3, dtype=torch.float32, device=dev)
+            # one error grid per timestep ([T][G^3]); E is the first one
+            self.E_all = torch.empty((len(self.frames), self.G ** 3), dtype=torch.float32, device=dev)
+            self.E = self.E_all[0]
             self.E_ready = False
             self.sample_ws = torch.empty(FV.lib().fvsrn_weighted_points_workspace_size(self.G), dtype=torch.uint8,
                                          device=dev)
 
     def update_error_grid(self):
-        """Measure the error grid E of the current network (Sec. 5.4)."""
-        t, v = self.frames[0]
+        """Measure the error grid of the current network at every timestep
+        (Sec. 5.4), all on the same voxel positions."""
         FV.fvsrn_voxel_points(self.seed ^ 0x5DEECE66D, self.opt["step"], self.G, self.per_voxel, out=self.err_xyz)
-        FV.fvsrn_error_grid(self.net, v, self.err_xyz, self.per_voxel, t, out=self.E, scratch=self.err_scratch)
+        for j, (t, v) in enumerate(self.frames):
+            FV.fvsrn_error_grid(self.net, v, self.err_xyz, self.per_voxel, t, out=self.E_all[j],
+                                scratch=self.err_scratch)
         self.E_ready = True
 
     def step(self) -> torch.Tensor:
@@ -95,8 +101,12 @@ class Trainer:
         if self.resample_every and self.opt["step"] > 1 and (self.opt["step"] - 1) % self.resample_every == 0:
             self.update_error_grid()
         if self.E is not None and self.E_ready:
-            FV.fvsrn_sample_points_weighted(self.seed, self.opt["step"], self.E, self.G, self.batch, out=self.xyz,
-                                            workspace=self.sample_ws)
+            # timestep j's rows from its own error grid; counters step * T + j
+            T = len(self.frames)
+            for j in range(T):
+                a, b = self.bounds[j], self.bounds[j + 1]
+                FV.fvsrn_sample_points_weighted(self.seed, self.opt["step"] * T + j, self.E_all[j], self.G, b - a,
+                                                out=self.xyz[a:b], workspace=self.sample_ws)
         else:
             FV.fvsrn_sample_points(self.seed, self.opt["step"], self.batch, out=self.xyz)
         for j, (_, v) in enumerate(self.frames):
