@@ -100,16 +100,19 @@ typedef struct {
                             [3L][3] rows of angular frequencies (radians per world unit): the
                             sin and cos blocks hold sin / cos(row_j . p) (Sec. 3; random
                             Fourier features draw the entries from N(0, (2 pi sigma)^2)).
-                            Read during the call. Built for the sine activation, FP32/FP16
-                            arithmetic, the unshaded render, point densities and training,
-                            without a time encoding. */
+                            Read during the call. Built for the sine activation without a
+                            time encoding: the unshaded render and point densities
+                            (FP32/FP16/BF16), forward-mode gradients and Phong shading
+                            from them (FP32/FP16), and training. */
 } fvsrn_net_desc;
 
 /* Time encodings (Sec. 8): the latent grids are blended in time in every case;
    DIRECT adds tau as one input, FOURIER adds sin and cos of pi 2^k tau for
    k = 0..3 (8 inputs), BOTH adds tau then the 8 Fourier inputs. Networks with a
-   time input are built for the sine activation, FP32/FP16 arithmetic, the
-   unshaded render, point densities and training. */
+   time input are built for the sine activation: the unshaded render and point
+   densities (FP32/FP16/BF16), forward-mode gradients and Phong shading from
+   them (FP32/FP16; the time inputs have no position derivative), and
+   training. */
 typedef enum {
   FVSRN_TIME_LATENT_ONLY = 0,
   FVSRN_TIME_DIRECT = 1,
@@ -197,9 +200,10 @@ typedef struct {
    [0]/[2] is the occupancy of the matrix tiles). A wave marches 64 rays
    without shading, 16 with forward-mode gradients and 8 with central
    differences. Phong shading needs the density gradient, obtained as
-   march->grad_mode selects (Sec. 6). Forward mode, central differences and
-   the adjoint are built for FP32/FP16 networks (central differences,
-   predicted gradients and the adjoint for the sine activation only; the
+   march->grad_mode selects (Sec. 6). Forward mode and central differences
+   are built for FP32/FP16 networks, the adjoint for FP32/FP16/BF16 ones
+   (central differences, predicted gradients and the adjoint for the sine
+   activation with the octave Fourier features and no time input; the
    adjoint of an FP32 network whose weight fragments, forward and transposed,
    exceed the 160 KiB of LDS -- c = 48 with H = 8, or with F = 16 and H >= 7 --
    is not available); other combinations return FVSRN_ERR_UNSUPPORTED.

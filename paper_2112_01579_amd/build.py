@@ -2,8 +2,8 @@
 
 The network kernels are compiled once per precision (FP32, FP16, BF16) as
 separate translation units (the adjoint-gradient, time-encoded and
-Fourier-matrix kernels in units of their own), in parallel, then linked with the C ABI and the utility kernels into
-one shared library.
+Fourier-matrix kernels in units of their own), in parallel, then linked with
+the C ABI and the utility kernels into one shared library.
 """
 from __future__ import annotations
 
@@ -30,10 +30,13 @@ UNITS = [
     ("fvsrn_march.hip", ["-DFVSRN_PREC=2"], "march_bf16.o"),
     ("fvsrn_adjoint.hip", ["-DFVSRN_PREC=0"], "adj_f32.o"),
     ("fvsrn_adjoint.hip", ["-DFVSRN_PREC=1"], "adj_f16.o"),
+    ("fvsrn_adjoint.hip", ["-DFVSRN_PREC=2"], "adj_bf16.o"),
     ("fvsrn_time.hip", ["-DFVSRN_PREC=0"], "time_f32.o"),
     ("fvsrn_time.hip", ["-DFVSRN_PREC=1"], "time_f16.o"),
+    ("fvsrn_time.hip", ["-DFVSRN_PREC=2"], "time_bf16.o"),
     ("fvsrn_rff.hip", ["-DFVSRN_PREC=0"], "rff_f32.o"),
     ("fvsrn_rff.hip", ["-DFVSRN_PREC=1"], "rff_f16.o"),
+    ("fvsrn_rff.hip", ["-DFVSRN_PREC=2"], "rff_bf16.o"),
     # the training kernels schedule for instruction-level parallelism (measured
     # 5% faster per step; the render kernels are faster with the default)
     ("fvsrn_train.hip", ["-mllvm", "-amdgpu-sched-strategy=max-ilp"], "train.o"),

@@ -1,12 +1,12 @@
 // Adjoint (reverse-mode) gradient shading and point gradients (Sec. 6),
-// compiled once per precision with FVSRN_PREC = 0 FP32 or 1 FP16. The layer
+// compiled once per precision with FVSRN_PREC = 0 FP32, 1 FP16 or 2 BF16. The layer
 // count is a template parameter (the saved activation derivatives are
 // registers), instantiated for H = 1..8 and the sine activation; above four
 // layers the first ones are evaluated twice (see mlp_tile_adj).
 #include "fvsrn_march.hpp"
 
 #ifndef FVSRN_PREC
-#error "FVSRN_PREC must be defined (0 FP32, 1 FP16)"
+#error "FVSRN_PREC must be defined (0 FP32, 1 FP16, 2 BF16)"
 #endif
 
 namespace fvsrn_detail {

@@ -139,30 +139,24 @@ int launch_points_p0(const NetDev&, const float*, long long, int, float, float*,
 int launch_points_p1(const NetDev&, const float*, long long, int, float, float*, float*, int, void*);
 int launch_points_p2(const NetDev&, const float*, long long, int, float, float*, float*, int, void*);
 
-// Adjoint-gradient render and points (fvsrn_adjoint.hip, FP32 and FP16 networks).
-int launch_render_adj_p0(const NetDev&, const TFDev&, const ViewBatch&, const MarchDev&, float*,
-                         unsigned long long*, void*);
-int launch_render_adj_p1(const NetDev&, const TFDev&, const ViewBatch&, const MarchDev&, float*,
-                         unsigned long long*, void*);
-int launch_points_adj_p0(const NetDev&, const float*, long long, int, float, float*, float*, void*);
-int launch_points_adj_p1(const NetDev&, const float*, long long, int, float, float*, float*, void*);
-
-// Networks with a Fourier matrix (fvsrn_rff.hip, FP32 and FP16 networks,
-// sine activation): unshaded render and point densities.
-int launch_render_rff_p0(const NetDev&, const TFDev&, const ViewBatch&, const MarchDev&, float*,
-                         unsigned long long*, void*);
-int launch_render_rff_p1(const NetDev&, const TFDev&, const ViewBatch&, const MarchDev&, float*,
-                         unsigned long long*, void*);
-int launch_points_rff_p0(const NetDev&, const float*, long long, int, float, float*, void*);
-int launch_points_rff_p1(const NetDev&, const float*, long long, int, float, float*, void*);
-
-// Networks with a time encoding (fvsrn_time.hip, FP32 and FP16 networks,
-// sine activation): unshaded render and point densities.
-int launch_render_time_p0(const NetDev&, const TFDev&, const ViewBatch&, const MarchDev&, float*,
-                          unsigned long long*, void*);
-int launch_render_time_p1(const NetDev&, const TFDev&, const ViewBatch&, const MarchDev&, float*,
-                          unsigned long long*, void*);
-int launch_points_time_p0(const NetDev&, const float*, long long, int, float, float*, void*);
-int launch_points_time_p1(const NetDev&, const float*, long long, int, float, float*, void*);
+// Adjoint-gradient render and points (fvsrn_adjoint.hip, FP32, FP16 and BF16
+// networks).
+#define FV_DECL_ADJ(P)                                                                                         \
+  int launch_render_adj_p##P(const NetDev&, const TFDev&, const ViewBatch&, const MarchDev&, float*,          \
+                             unsigned long long*, void*);                                                       \
+  int launch_points_adj_p##P(const NetDev&, const float*, long long, int, float, float*, float*, void*);
+// Networks with a Fourier matrix (fvsrn_rff.hip) and with a time encoding
+// (fvsrn_time.hip), sine activation: unshaded render and point densities
+// (FP32, FP16, BF16), forward-mode gradients and Phong (FP32, FP16); out_g
+// nullable, gmode as for launch_points.
+#define FV_DECL_XF(NAME, P)                                                                                    \
+  int launch_render_##NAME##_p##P(const NetDev&, const TFDev&, const ViewBatch&, const MarchDev&, float*,     \
+                                  unsigned long long*, void*);                                                  \
+  int launch_points_##NAME##_p##P(const NetDev&, const float*, long long, int, float, float*, float*, int, void*);
+FV_DECL_ADJ(0) FV_DECL_ADJ(1) FV_DECL_ADJ(2)
+FV_DECL_XF(rff, 0) FV_DECL_XF(rff, 1) FV_DECL_XF(rff, 2)
+FV_DECL_XF(time, 0) FV_DECL_XF(time, 1) FV_DECL_XF(time, 2)
+#undef FV_DECL_ADJ
+#undef FV_DECL_XF
 
 }  // namespace fvsrn_detail

@@ -70,27 +70,9 @@ struct Entry {
 
 int FV_PASTE(launch_render_p, FVSRN_PREC)(const NetDev& nd, const TFDev& tf, const ViewBatch& vb, const MarchDev& m,
                                           float* out, unsigned long long* stats, void* stream) {
-  if (nd.fmat) {
-#if FVSRN_PREC != 2
-    return FV_PASTE(launch_render_rff_p, FVSRN_PREC)(nd, tf, vb, m, out, stats, stream);
-#else
-    return 1;
-#endif
-  }
-  if (nd.time_enc != 0) {
-#if FVSRN_PREC != 2
-    return FV_PASTE(launch_render_time_p, FVSRN_PREC)(nd, tf, vb, m, out, stats, stream);
-#else
-    return 1;
-#endif
-  }
-  if (m.phong && m.grad_mode == 3) {
-#if FVSRN_PREC != 2
-    return FV_PASTE(launch_render_adj_p, FVSRN_PREC)(nd, tf, vb, m, out, stats, stream);
-#else
-    return 1;
-#endif
-  }
+  if (nd.fmat) return FV_PASTE(launch_render_rff_p, FVSRN_PREC)(nd, tf, vb, m, out, stats, stream);
+  if (nd.time_enc != 0) return FV_PASTE(launch_render_time_p, FVSRN_PREC)(nd, tf, vb, m, out, stats, stream);
+  if (m.phong && m.grad_mode == 3) return FV_PASTE(launch_render_adj_p, FVSRN_PREC)(nd, tf, vb, m, out, stats, stream);
   const int mode = !m.phong ? kShadeNone : (m.grad_mode == 1 ? kShadeFD : (m.grad_mode == 2 ? kShadePred : kShadeFwd));
   // packed FP16 gathers for an FP16 network on an FP16 or uint8 grid
   const int gk = FVSRN_PREC != 1 ? 0 : (nd.grid_u8 ? 2 : (nd.grid_f16 ? 1 : 0));
@@ -112,29 +94,10 @@ int FV_PASTE(launch_render_p, FVSRN_PREC)(const NetDev& nd, const TFDev& tf, con
 
 int FV_PASTE(launch_points_p, FVSRN_PREC)(const NetDev& nd, const float* xyz, long long n, int key, float key_w,
                                           float* out_d, float* out_g, int gmode, void* stream) {
-  if (nd.fmat) {
-#if FVSRN_PREC != 2
-    if (out_g) return 1;  // gradients with a Fourier matrix are not compiled
-    return FV_PASTE(launch_points_rff_p, FVSRN_PREC)(nd, xyz, n, key, key_w, out_d, stream);
-#else
-    return 1;
-#endif
-  }
-  if (nd.time_enc != 0) {
-#if FVSRN_PREC != 2
-    if (out_g) return 1;  // gradients of time-encoded networks are not compiled
-    return FV_PASTE(launch_points_time_p, FVSRN_PREC)(nd, xyz, n, key, key_w, out_d, stream);
-#else
-    return 1;
-#endif
-  }
-  if (out_g && gmode == 3) {
-#if FVSRN_PREC != 2
-    return FV_PASTE(launch_points_adj_p, FVSRN_PREC)(nd, xyz, n, key, key_w, out_d, out_g, stream);
-#else
-    return 1;
-#endif
-  }
+  if (nd.fmat) return FV_PASTE(launch_points_rff_p, FVSRN_PREC)(nd, xyz, n, key, key_w, out_d, out_g, gmode, stream);
+  if (nd.time_enc != 0)
+    return FV_PASTE(launch_points_time_p, FVSRN_PREC)(nd, xyz, n, key, key_w, out_d, out_g, gmode, stream);
+  if (out_g && gmode == 3) return FV_PASTE(launch_points_adj_p, FVSRN_PREC)(nd, xyz, n, key, key_w, out_d, out_g, stream);
   // gmode 2: a 4-output network's own gradient, from the value-mode kernel
   const int mode = (out_g != nullptr && gmode == 0) ? kShadeFwd : kShadeNone;
   // packed FP16 gathers for an FP16 network on an FP16 or uint8 grid

@@ -1,11 +1,13 @@
 // Networks with a time encoding of their input (Sec. 8: the normalised time
 // as a direct input, its Fourier features, or both), compiled once per
-// precision with FVSRN_PREC = 0 FP32 or 1 FP16: the unshaded render and point
-// densities, sine activation.
+// precision with FVSRN_PREC = 0 FP32, 1 FP16 or 2 BF16, sine activation: the
+// unshaded render and point densities, and for FP32/FP16 forward-mode density
+// gradients and Phong shading from them (the time inputs do not depend on the
+// position, so their tangent columns are zero).
 #include "fvsrn_march.hpp"
 
 #ifndef FVSRN_PREC
-#error "FVSRN_PREC must be defined (0 FP32, 1 FP16)"
+#error "FVSRN_PREC must be defined (0 FP32, 1 FP16, 2 BF16)"
 #endif
 
 namespace fvsrn_detail {
@@ -17,11 +19,19 @@ struct TimeEntry {
   using CF = Cfg<FVSRN_PREC, C, F, L, kSine, GK, TE>;
   static int render(const NetDev& nd, const TFDev& tf, const ViewBatch& vb, const MarchDev& m, float* out,
                     unsigned long long* stats, hipStream_t st) {
-    return launch_render_t<CF, kShadeNone>(nd, tf, vb, m, out, stats, st);
+    if (!m.phong) return launch_render_t<CF, kShadeNone>(nd, tf, vb, m, out, stats, st);
+#if FVSRN_PREC != 2
+    if (m.grad_mode == 0) return launch_render_t<CF, kShadeFwd>(nd, tf, vb, m, out, stats, st);
+#endif
+    return 1;
   }
   static int points(const NetDev& nd, const float* xyz, long long n, int key, float key_w, float* out_d,
-                    hipStream_t st) {
-    return launch_points_t<CF, kShadeNone>(nd, xyz, n, key, key_w, out_d, nullptr, st);
+                    float* out_g, int gmode, hipStream_t st) {
+    if (!out_g) return launch_points_t<CF, kShadeNone>(nd, xyz, n, key, key_w, out_d, nullptr, st);
+#if FVSRN_PREC != 2
+    if (gmode == 0) return launch_points_t<CF, kShadeFwd>(nd, xyz, n, key, key_w, out_d, out_g, st);
+#endif
+    return 1;
   }
 };
 
@@ -45,7 +55,7 @@ struct TimeEntry {
 int FV_PASTE(launch_render_time_p, FVSRN_PREC)(const NetDev& nd, const TFDev& tf, const ViewBatch& vb,
                                                const MarchDev& m, float* out, unsigned long long* stats,
                                                void* stream) {
-  if (nd.act != kSine || m.phong) return 1;
+  if (nd.act != kSine) return 1;
   const int gk = FVSRN_PREC != 1 ? 0 : (nd.grid_u8 ? 2 : (nd.grid_f16 ? 1 : 0));
   const hipStream_t st = (hipStream_t)stream;
 #define X(C_, F_, L_, GK_, TE_)                                                       \
@@ -57,13 +67,13 @@ int FV_PASTE(launch_render_time_p, FVSRN_PREC)(const NetDev& nd, const TFDev& tf
 }
 
 int FV_PASTE(launch_points_time_p, FVSRN_PREC)(const NetDev& nd, const float* xyz, long long n, int key,
-                                               float key_w, float* out_d, void* stream) {
+                                               float key_w, float* out_d, float* out_g, int gmode, void* stream) {
   if (nd.act != kSine) return 1;
   const int gk = FVSRN_PREC != 1 ? 0 : (nd.grid_u8 ? 2 : (nd.grid_f16 ? 1 : 0));
   const hipStream_t st = (hipStream_t)stream;
 #define X(C_, F_, L_, GK_, TE_)                                                       \
   if (nd.C == C_ && nd.F == F_ && nd.L == L_ && gk == GK_ && nd.time_enc == TE_) \
-    return TimeEntry<C_, F_, L_, GK_, TE_>::points(nd, xyz, n, key, key_w, out_d, st);
+    return TimeEntry<C_, F_, L_, GK_, TE_>::points(nd, xyz, n, key, key_w, out_d, out_g, gmode, st);
   FV_TIME_ALL(X)
 #undef X
   return 1;

@@ -27,6 +27,7 @@ BF16_TOL = 3e-2
 # density gradients, relative to the largest |gradient| of the set
 GRAD32_TOL = 1e-5
 GRAD16_TOL = 1e-2
+GRADBF16_TOL = 3e-2
 # Phong-shaded FP32 images: the specular term |n.l|^32 multiplies the shading
 # normal's relative error (FP32 network gradients with the hardware
 # transcendentals, ~5e-7) by 32 and by k_s, and the rays composite hundreds of
@@ -790,15 +791,17 @@ def _rev_ref(onet, xyz, t=0.0):
 def test_adjoint_grad_points(FV, spec):
     """Reverse-mode gradient (Sec. 6's adjoint: one forward and one transposed
     pass) against the oracle's reverse mode, at the layer counts whose
-    derivatives all stay in registers (H = 1..4), c = 32 and 48, FP32 and FP16 networks on FP32, FP16 and uint8
-    grids, a ragged point count with a few points outside the domain (the
-    latent part of the gradient vanishes there)."""
+    derivatives all stay in registers (H = 1..4), c = 32 and 48, FP32, FP16
+    and BF16 networks on FP32, FP16 and uint8 grids, a ragged point count
+    with a few points outside the domain (the latent part of the gradient
+    vanishes there)."""
     xyz = np.concatenate([I.uniform_points(64 * 5 + 13, 19, -0.999, 0.999),
                           np.array([[1.2, 0.1, -0.3], [-0.5, -1.1, 0.9], [0.3, 0.2, 1.05]], np.float32)])
     for gd in (FV.F32, FV.F16, FV.U8):
         gnet, onet = _nets(FV, spec, 23, grid_dtype=gd)
         dref, gref = _rev_ref(onet, xyz)
-        for prec, dtol, gtol in (("f32", FP32_TOL, GRAD32_TOL), ("f16", FP16_TOL, GRAD16_TOL)):
+        for prec, dtol, gtol in (("f32", FP32_TOL, GRAD32_TOL), ("f16", FP16_TOL, GRAD16_TOL),
+                                 ("bf16", BF16_TOL, GRADBF16_TOL)):
             d, g = FV.fvsrn_grad_points(gnet, torch.from_numpy(xyz).cuda(), 0.0, prec, mode="adjoint")
             derr, gerr = np.abs(d.cpu().numpy() - dref).max(), _grad_err(g.cpu().numpy(), gref)
             _report("adjoint c=%d H=%d grid %d %s density" % (spec.c, spec.H, gd, prec), derr)
@@ -816,10 +819,10 @@ def test_adjoint_grad_points_keyframes_edges_and_limits(FV):
             d, g = FV.fvsrn_grad_points(gnet, torch.from_numpy(xyz).cuda(), t, "f32", mode="adjoint")
             assert np.abs(d.cpu().numpy() - dref).max() <= FP32_TOL
             assert _grad_err(g.cpu().numpy(), gref) <= GRAD32_TOL
-    # BF16 and other activations are not compiled for the adjoint, and the
-    # FP32 fragments of a c = 48 network of 8 layers exceed the LDS
+    # other activations are not compiled for the adjoint, and the FP32
+    # fragments of a c = 48 network of 8 layers exceed the LDS
     xyz = torch.from_numpy(I.uniform_points(10, 3)).cuda()
-    for spec, prec in ((I.NET_SMALL, "bf16"), (I.NetSpec(R=8, F=8, L=4, c=32, H=2, act="snakealt"), "f32"),
+    for spec, prec in ((I.NetSpec(R=8, F=8, L=4, c=32, H=2, act="snakealt"), "f32"),
                        (I.NetSpec(R=8, F=16, L=8, c=48, H=8), "f32")):
         gnet, _ = _nets(FV, spec, 2)
         with pytest.raises(FV.FvsrnError) as e:
@@ -833,7 +836,7 @@ def test_adjoint_grad_points_keyframes_edges_and_limits(FV):
     (I.NetSpec(R=12, F=16, L=8, c=32, H=8), ("f32", "f16")),
     (I.NetSpec(R=12, F=16, L=8, c=48, H=6), ("f32", "f16")),
     (I.NetSpec(R=12, F=8, L=4, c=48, H=7), ("f32", "f16")),
-    (I.NetSpec(R=12, F=8, L=4, c=48, H=8), ("f16",))], ids=["c32H5", "c32H8", "c48H6", "c48H7", "c48H8"])
+    (I.NetSpec(R=12, F=8, L=4, c=48, H=8), ("f16", "bf16"))], ids=["c32H5", "c32H8", "c48H6", "c48H7", "c48H8"])
 def test_adjoint_grad_points_deep(FV, spec, precs):
     """Networks of more than four layers: the adjoint keeps the derivatives
     of the last four and runs the first H - 4 layers a second time. Against
@@ -845,7 +848,8 @@ def test_adjoint_grad_points_deep(FV, spec, precs):
         gnet, onet = _nets(FV, spec, 29, grid_dtype=gd)
         dref, gref = _rev_ref(onet, xyz)
         for prec in precs:
-            dtol, gtol = (FP32_TOL, GRAD32_TOL) if prec == "f32" else (FP16_TOL, GRAD16_TOL)
+            dtol, gtol = {"f32": (FP32_TOL, GRAD32_TOL), "f16": (FP16_TOL, GRAD16_TOL),
+                          "bf16": (BF16_TOL, GRADBF16_TOL)}[prec]
             d, g = FV.fvsrn_grad_points(gnet, torch.from_numpy(xyz).cuda(), 0.0, prec, mode="adjoint")
             derr, gerr = np.abs(d.cpu().numpy() - dref).max(), _grad_err(g.cpu().numpy(), gref)
             _report("adjoint c=%d H=%d grid %d %s density" % (spec.c, spec.H, gd, prec), derr)
@@ -871,13 +875,13 @@ def test_phong_render_adjoint_deep(FV, prec, tol):
     assert abs(stats[0].item() - ns) <= 0.001 * ns
 
 
-@pytest.mark.parametrize("prec,tol", [("f32", PHONG32_TOL), ("f16", FP16_TOL)])
+@pytest.mark.parametrize("prec,tol", [("f32", PHONG32_TOL), ("f16", FP16_TOL), ("bf16", BF16_TOL)])
 def test_phong_render_adjoint(FV, prec, tol):
     """Phong shading from the adjoint gradient on the shaded (c = 48) and
     study (c = 32) networks, ragged views, against the oracle's reverse-mode
     render; the same bounds as forward-mode shading."""
     for spec, seed in ((I.NET_SHADED, I.SEED_SHADED), (I.NET_STUDY, I.SEED_STUDY)):
-        gnet, onet = _nets(FV, spec, seed, grid_dtype=FV.F16 if prec == "f16" else FV.F32)
+        gnet, onet = _nets(FV, spec, seed, grid_dtype=FV.F32 if prec == "f32" else FV.F16)
         tf = I.ramp_tf()
         cams = I.orbit_cameras(2, 23, 15)
         m = I.March(step=1 / 128, ert_eps=0.0, phong=True, grad_mode=3)
@@ -898,8 +902,8 @@ def test_time_encoding_eval_and_render(FV, te):
     """Networks with a time input (the normalised time tau directly, its
     Fourier features, or both) on three keyframe grids: point densities at
     times below, inside and above the key range (tau clamps), FP32 and FP16
-    networks on FP32, FP16 and uint8 grids, c = 32 and 48; an unshaded
-    two-view render at two times against the oracle."""
+    and BF16 networks on FP32, FP16 and uint8 grids, c = 32 and 48; an
+    unshaded two-view render at two times against the oracle."""
     keys = (0.0, 1.0, 3.0)
     for base in (I.NetSpec(R=10, F=16, L=8, c=32, H=3, K=3), I.NetSpec(R=10, F=8, L=4, c=48, H=2, K=3)):
         spec = dataclasses.replace(base, time_enc=te)
@@ -908,7 +912,8 @@ def test_time_encoding_eval_and_render(FV, te):
             gnet, onet = _nets(FV, spec, 30 + te, key_times=keys, grid_dtype=gd)
             for t in (-0.5, 0.4, 2.2, 4.0):
                 ref = O.eval_points(onet, xyz, t)
-                for prec, tol in (("f32", FP32_TOL), ("f16", FP16_TOL)):
+                precs = (("f32", FP32_TOL), ("f16", FP16_TOL), ("bf16", BF16_TOL))
+                for prec, tol in precs:
                     d = FV.fvsrn_eval_points(gnet, torch.from_numpy(xyz).cuda(), t, prec).cpu().numpy()
                     err = np.abs(d - ref).max()
                     assert err <= tol, (spec.c, gd, t, prec, err)
@@ -917,23 +922,57 @@ def test_time_encoding_eval_and_render(FV, te):
         cams = [dataclasses.replace(c, time=t) for c, t in zip(cams, (0.7, 2.6))]
         m = I.March(step=1 / 64, ert_eps=0.0)
         ref, ns = O.render(O.Field(net=onet), I.ramp_tf(), cams, m)
-        for prec, tol in (("f32", FP32_TOL), ("f16", FP16_TOL)):
+        for prec, tol in (("f32", FP32_TOL), ("f16", FP16_TOL), ("bf16", BF16_TOL)):
             img = FV.fvsrn_render(gnet, I.ramp_tf(), cams, m, prec).cpu().numpy()
             err = np.abs(img - ref).max()
             _report("time encoding %d c=%d render %s" % (te, spec.c, prec), err)
             assert err <= tol
 
 
+@pytest.mark.parametrize("kind", ["time_direct", "time_both", "fourier_matrix"])
+def test_time_encoding_and_fourier_matrix_gradients(FV, kind):
+    """Forward-mode density gradients and Phong shading of networks with a
+    time input or a Fourier matrix (the time inputs have no position
+    derivative; a matrix row j contributes 2 pi row_ja cos / -sin), FP32 and
+    FP16, against the oracle's forward mode."""
+    if kind == "fourier_matrix":
+        spec = I.NetSpec(R=10, F=8, L=4, c=32, H=3, K=2)
+        fm = I.random_fourier_matrix(spec.L, 1.0, 3)
+        lat, w = I.net_params(spec, 9)
+        gnet = FV.Network(spec, lat, w, key_times=(0.0, 1.0), fourier_matrix=fm)
+        onet = O.Net(spec, lat, w, (0.0, 1.0), fourier_matrix=fm.astype(np.float64))
+    else:
+        spec = I.NetSpec(R=10, F=16, L=8, c=48, H=2, K=3, time_enc=1 if kind == "time_direct" else 3)
+        gnet, onet = _nets(FV, spec, 12, key_times=(0.0, 1.0, 3.0))
+    xyz = I.uniform_points(16 * 19 + 3, 7, -0.99, 0.99)
+    for t in (0.3, 2.5):
+        dref, gref = O.grad_points(onet, xyz, t)
+        for prec, dtol, gtol in (("f32", FP32_TOL, GRAD32_TOL), ("f16", FP16_TOL, GRAD16_TOL)):
+            d, g = FV.fvsrn_grad_points(gnet, torch.from_numpy(xyz).cuda(), t, prec)
+            derr, gerr = np.abs(d.cpu().numpy() - dref).max(), _grad_err(g.cpu().numpy(), gref)
+            _report("grad %s t=%.1f %s density" % (kind, t, prec), derr)
+            _report("grad %s t=%.1f %s gradient (rel.)" % (kind, t, prec), gerr)
+            assert derr <= dtol and gerr <= gtol
+    cams = [dataclasses.replace(c, time=0.8) for c in I.orbit_cameras(1, 17, 12)]
+    m = I.March(step=1 / 96, ert_eps=0.0, phong=True)
+    ref, _ = O.render(O.Field(net=onet), I.ramp_tf(), cams, m)
+    for prec, tol in (("f32", PHONG32_TOL), ("f16", FP16_TOL)):
+        img = FV.fvsrn_render(gnet, I.ramp_tf(), cams, m, prec).cpu().numpy()
+        err = np.abs(img - ref).max()
+        _report("phong %s %s" % (kind, prec), err)
+        assert err <= tol
+
+
 def test_time_encoding_limits(FV):
-    """Shading, gradients, BF16 and non-sine activations are not compiled for
-    time-encoded networks."""
+    """Central-difference, predicted and adjoint gradients, BF16 shading and
+    non-sine activations are not compiled for time-encoded networks."""
     spec = I.NetSpec(R=8, F=8, L=4, c=32, H=2, K=2, time_enc=1)
     gnet, _ = _nets(FV, spec, 3, key_times=(0.0, 1.0))
     xyz = torch.from_numpy(I.uniform_points(8, 1)).cuda()
     cams = I.orbit_cameras(1, 8, 8)
-    for call in (lambda: FV.fvsrn_render(gnet, I.ramp_tf(), cams, I.March(step=0.1, phong=True), "f32"),
-                 lambda: FV.fvsrn_grad_points(gnet, xyz, 0.5, "f32"),
-                 lambda: FV.fvsrn_eval_points(gnet, xyz, 0.5, "bf16")):
+    for call in (lambda: FV.fvsrn_render(gnet, I.ramp_tf(), cams, I.March(step=0.1, phong=True), "bf16"),
+                 lambda: FV.fvsrn_render(gnet, I.ramp_tf(), cams, I.March(step=0.1, phong=True, grad_mode=3), "f32"),
+                 lambda: FV.fvsrn_grad_points(gnet, xyz, 0.5, "f32", mode="adjoint")):
         with pytest.raises(FV.FvsrnError) as e:
             call()
         assert e.value.status == FV.ERR_UNSUPPORTED
@@ -950,8 +989,8 @@ def test_time_encoding_limits(FV):
                          ids=["c32", "c48_keyframes"])
 def test_fourier_matrix_eval_and_render(FV, spec):
     """Random Fourier features (entries ~ N(0, (2 pi sigma)^2)) in place of
-    the octaves: point densities at FP32 and FP16 on FP32, FP16 and uint8
-    grids, and an unshaded render, against the oracle; the octave matrix
+    the octaves: point densities at FP32, FP16 and BF16 on FP32, FP16 and
+    uint8 grids, and an unshaded render, against the oracle; the octave matrix
     itself reproduces the default network's output."""
     kt = (0.0, 1.0) if spec.K > 1 else None
     fm = I.random_fourier_matrix(spec.L, 1.0, 5)
@@ -963,7 +1002,8 @@ def test_fourier_matrix_eval_and_render(FV, spec):
         onet = O.Net(spec, onet0.latent.reshape(-1) if onet0.latent is not None else None, w, kt,
                      codes=onet0.codes, dequant=onet0.dequant, fourier_matrix=fm.astype(np.float64))
         ref = O.eval_points(onet, xyz, 0.4)
-        for prec, tol in (("f32", FP32_TOL), ("f16", FP16_TOL)):
+        precs = (("f32", FP32_TOL), ("f16", FP16_TOL), ("bf16", BF16_TOL))
+        for prec, tol in precs:
             d = FV.fvsrn_eval_points(gnet, torch.from_numpy(xyz).cuda(), 0.4, prec).cpu().numpy()
             err = np.abs(d - ref).max()
             _report("fourier matrix c=%d grid %d %s" % (spec.c, gd, prec), err)
@@ -973,7 +1013,7 @@ def test_fourier_matrix_eval_and_render(FV, spec):
     cams = I.orbit_cameras(2, 19, 13)
     m = I.March(step=1 / 64, ert_eps=0.0)
     ref, _ = O.render(O.Field(net=onet), I.ramp_tf(), cams, m)
-    for prec, tol in (("f32", FP32_TOL), ("f16", FP16_TOL)):
+    for prec, tol in (("f32", FP32_TOL), ("f16", FP16_TOL), ("bf16", BF16_TOL)):
         img = FV.fvsrn_render(gnet, I.ramp_tf(), cams, m, prec).cpu().numpy()
         assert np.abs(img - ref).max() <= tol
     # the octave construction as a matrix gives the default network's densities
