@@ -12,8 +12,9 @@
  * General rules for every entry point:
  *  - Pointers are DEVICE pointers unless marked [host]. The caller owns every
  *    buffer; the library allocates nothing and keeps no state beyond cached
- *    device properties (and the static per-GPU workspace of
- *    fvsrn_train_step_noalloc, allocated with its code object).
+ *    device properties and two static per-GPU arrays allocated with its
+ *    code object: the workspace of fvsrn_train_step_noalloc and the tile
+ *    counters of fvsrn_render (see there).
  *  - Device buffers must be 16-byte aligned.
  *  - Calls are asynchronous on `stream` (a hipStream_t passed as void*; NULL
  *    is the default stream). Argument errors are detected on the host before
@@ -207,7 +208,12 @@ typedef struct {
    adjoint of an FP32 network whose weight fragments, forward and transposed,
    exceed the 160 KiB of LDS -- c = 48 with H = 8, or with F = 16 and H >= 7 --
    is not available); other combinations return FVSRN_ERR_UNSUPPORTED.
-   Predicted gradients need num_outputs == 4. */
+   Predicted gradients need num_outputs == 4.
+   Each launch is persistent (as many workgroups as the GPU holds at once)
+   and hands its tiles out through a pair of counters in a static per-GPU
+   array of 1024 pairs; successive calls on a device take successive pairs,
+   so at most 1024 fvsrn_render launches (one per 16 views of a call)
+   may be in flight on one GPU at once. */
 fvsrn_status fvsrn_render(const fvsrn_net_desc* desc, const fvsrn_params* params,
                           const fvsrn_tf* tf, const fvsrn_camera* cams, int32_t n_views,
                           const fvsrn_march* march, float* out_rgba,

@@ -134,6 +134,26 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Dynamic tile queue of a persistent launch: q[0] counts the tiles handed
+// out, q[1] the waves that have finished. Called by every lane of a wave
+// (wave-uniform result).
+__device__ inline int next_tile(unsigned int* q, int lane) {
+  unsigned int t = 0;
+  if (lane == 0) t = atomicAdd(q, 1u);
+  return (int)__builtin_amdgcn_readfirstlane(t);
+}
+// After a wave's last next_tile: counts it as done; the launch's last wave
+// sets the pair back to zero for the next launch that uses it.
+__device__ inline void release_queue(unsigned int* q, int lane, unsigned int total_waves) {
+  if (lane == 0) {
+    __threadfence();
+    if (atomicAdd(q + 1, 1u) == total_waves - 1) {
+      atomicExch(q, 0u);
+      atomicExch(q + 1, 0u);
+    }
+  }
+}
+
 template <typename E>
 __device__ inline E to_e(float x) {
   return (E)x;

@@ -127,6 +127,14 @@ constexpr int kLaunchTooLarge = 4;
 int check_launch();                                   // 0 or 2 after a launch
 int grid_blocks(long long work, int per_block, int cap);
 int device_cus();
+// Dynamic tile queue of the render launches: a pair of counters [next tile,
+// waves done] on the current device, zero when handed out (the launch that
+// uses it sets it back to zero as its last wave ends). Calls rotate over
+// kTileQueueSlots pairs, so up to that many render launches may be in flight
+// on one device at once. nullptr when the device's counters cannot be
+// located (last_hip_error).
+constexpr int kTileQueueSlots = 1024;
+unsigned int* tile_queue_slot();
 
 // Per-precision network launchers (fvsrn_march.hip compiled per precision).
 int launch_render_p0(const NetDev&, const TFDev&, const ViewBatch&, const MarchDev&, float*, unsigned long long*,

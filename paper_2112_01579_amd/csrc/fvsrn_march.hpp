@@ -148,17 +148,20 @@ __device__ inline void composite(Accum& acc, const float rgba[4], float len) {
 
 // ------------------------------------------------------------- kernels
 
-// Launched with one tile per wave (the tile loop also serves smaller grids).
-// The hardware dispatcher then balances the work: a persistent grid with a
-// static share of tiles per wave was measured 30% slower, because the
-// per-wave sums of tile costs (empty, short and long rays) vary and the
-// launch waits for the unluckiest wave.
+// Persistent: as many workgroups as the CUs hold at once, each wave taking
+// tiles from a device-wide counter until none is left (queue[0]: the next
+// tile; queue[1]: waves done, so that the last one sets both back to zero).
+// Tile costs vary (empty, short and long rays): a static share of tiles per
+// wave was measured 30% slower, and one tile per wave keeps a workgroup's
+// LDS until its slowest wave ends, so the CUs ran at two thirds of their
+// wave slots on average.
 // HH: the network's layer count, compiled in for the adjoint (its saved
 // activation derivatives are registers); 0 for the other modes.
 template <class CF, int MODE, int HH = 0>
 __global__ __launch_bounds__((max_waves<CF, MODE>() * 64)) void march_kernel(NetDev nd, TFDev tf, ViewBatch vb,
                                                                                   MarchDev m, float* out,
                                                                                   unsigned long long* stats,
+                                                                                  unsigned int* queue,
                                                                                   int tiles_x, int tiles_y) {
   using G = typename CF::G;
   using E = typename CF::E;
@@ -177,7 +180,6 @@ __global__ __launch_bounds__((max_waves<CF, MODE>() * 64)) void march_kernel(Net
   const int wpb = blockDim.x >> 6;
   const int tiles_per_view = tiles_x * tiles_y;
   const int n_tiles = tiles_per_view * vb.n_views;
-  const int n_waves = gridDim.x * wpb;
   const int rl = lane / LPR;  // ray within the tile
   const int q = lane % LPR;   // role of the lane within its ray
   const LaneRole role = GRAD ? grad_role(q) : value_role();
@@ -191,7 +193,7 @@ __global__ __launch_bounds__((max_waves<CF, MODE>() * 64)) void march_kernel(Net
   E* feat = reinterpret_cast<E*>(smem + fixed_lds_bytes<CF, MODE>(nd.H) + wave * G::FEAT_BYTES);
   E* myrow = feat + lane * G::ROW;
   unsigned long long n_samp = 0, n_hit = 0, iters = 0;
-  for (int tile = blockIdx.x * wpb + wave; tile < n_tiles; tile += n_waves) {
+  for (int tile = next_tile(queue, lane); tile < n_tiles; tile = next_tile(queue, lane)) {
     const int v = tile / tiles_per_view;
     const int tr = tile % tiles_per_view;
     const int px = (tr % tiles_x) * TW + (rl % TW);
@@ -316,6 +318,7 @@ __global__ __launch_bounds__((max_waves<CF, MODE>() * 64)) void march_kernel(Net
       atomicAdd(stats + 2, iters * (unsigned long long)(64 / LPR));
     }
   }
+  release_queue(queue, lane, gridDim.x * wpb);
 }
 
 // Point evaluation (PM): kShadeNone -- density, and with out_g set outputs
@@ -407,8 +410,15 @@ int launch_render_t(const NetDev& nd, const TFDev& tf, const ViewBatch& vb, cons
   const int wpb = waves_per_block<CF, MODE>(nd.H);
   if (wpb < 1) return kLaunchNoLds;
   const size_t shm = (size_t)fixed_lds_bytes<CF, MODE>(nd.H) + (size_t)wpb * G::FEAT_BYTES;
-  const long long blocks = (tiles + wpb - 1) / wpb;  // one tile per wave
-  if (blocks > 0x7fffffffLL) return kLaunchTooLarge;
+  // the workgroups the CUs hold at once (LDS and the VGPR budget), fewer for
+  // small launches
+  const int per_cu_lds = (int)(kLdsBytes / shm), per_cu_regs = max_waves<CF, MODE>() / wpb;
+  const long long resident = (long long)device_cus() * (per_cu_lds < per_cu_regs ? per_cu_lds : per_cu_regs);
+  const long long want = (tiles + wpb - 1) / wpb;
+  const long long blocks = want < resident ? want : resident;
+  if (blocks < 1) return 0;
+  unsigned int* queue = tile_queue_slot();
+  if (!queue) return 2;
   static bool attr = false;
   if (!attr) {
     (void)hipFuncSetAttribute((const void*)march_kernel<CF, MODE, HH>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -416,7 +426,7 @@ int launch_render_t(const NetDev& nd, const TFDev& tf, const ViewBatch& vb, cons
     attr = true;
   }
   hipLaunchKernelGGL((march_kernel<CF, MODE, HH>), dim3((unsigned)blocks), dim3(wpb * 64), shm, st, nd, tf, vb, m,
-                     out, stats, tx, ty);
+                     out, stats, queue, tx, ty);
   return check_launch();
 }
 

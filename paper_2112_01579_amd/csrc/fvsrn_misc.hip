@@ -3,6 +3,9 @@
 // network launchers.
 #include <stdio.h>
 
+#include <atomic>
+#include <mutex>
+
 #include "fvsrn_common.hpp"
 
 namespace fvsrn_detail {
@@ -310,10 +313,36 @@ int device_cus() {
   return cus;
 }
 
-
 namespace {
-
+__device__ __align__(256) unsigned int tile_queues[2 * kTileQueueSlots];
 }  // namespace
+
+unsigned int* tile_queue_slot() {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static unsigned int* base[kMaxDevices] = {};
+  static std::atomic<unsigned int> next{0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    snprintf(g_hip_err, sizeof(g_hip_err), "no current device for the tile queue");
+    return nullptr;
+  }
+  unsigned int* b = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    if (!base[dev]) {
+      void* p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(tile_queues));
+      if (e != hipSuccess || !p) {
+        snprintf(g_hip_err, sizeof(g_hip_err), "tile queue: %s", hipGetErrorString(e));
+        return nullptr;
+      }
+      base[dev] = static_cast<unsigned int*>(p);
+    }
+    b = base[dev];
+  }
+  return b + 2 * (next.fetch_add(1u) % kTileQueueSlots);
+}
 
 // ------------------------------------------ adaptive resampling (Sec. 5.4)
 

@@ -99,6 +99,48 @@ def test_render_is_deterministic(FV, small_ortho):
     assert torch.equal(a, b)
 
 
+def test_render_tile_queue_reuse_streams_and_graph(FV, small_ortho):
+    """The render's persistent launch takes its tiles from a per-GPU pair of
+    counters that the launch's last wave sets back to zero; calls rotate
+    over 1024 pairs. 1100 launches in a row (every pair used, some twice),
+    launches on two streams at once, and a captured graph replayed several
+    times must all give the eager image exactly (and the oracle's)."""
+    gnet, onet, tf, cams, m, ref, ns = small_ortho
+    first = FV.fvsrn_render(gnet, tf, cams, m, "f16")
+    assert np.abs(first.cpu().numpy() - ref).max() <= FP16_TOL
+    outs = torch.empty((1100,) + tuple(first.shape), dtype=torch.float32, device="cuda")
+    for k in range(1100):
+        FV.fvsrn_render(gnet, tf, cams, m, "f16", out=outs[k])
+    assert bool(torch.all(outs == first.unsqueeze(0)).item())
+    # two streams: a 2-view render of the study network beside the small one
+    sgnet, _ = _nets(FV, I.NET_STUDY, I.SEED_STUDY)
+    scams = I.orbit_cameras(2, 96, 80)
+    smarch = I.March(step=1 / 128, ert_eps=1e-3)
+    sfirst = FV.fvsrn_render(sgnet, I.ramp_tf(), scams, smarch, "f16")
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    a = torch.empty((8,) + tuple(first.shape), dtype=torch.float32, device="cuda")
+    b = torch.empty((8,) + tuple(sfirst.shape), dtype=torch.float32, device="cuda")
+    for k in range(8):
+        FV.fvsrn_render(gnet, tf, cams, m, "f16", out=a[k], stream=s1)
+        FV.fvsrn_render(sgnet, I.ramp_tf(), scams, smarch, "f16", out=b[k], stream=s2)
+    torch.cuda.synchronize()
+    assert bool(torch.all(a == first.unsqueeze(0)).item())
+    assert bool(torch.all(b == sfirst.unsqueeze(0)).item())
+    # graph replays, with eager work and synchronisations between them
+    gout = torch.zeros_like(first)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        FV.fvsrn_render(gnet, tf, cams, m, "f16", out=gout)
+    for k in range(4):
+        gout.zero_()
+        g.replay()
+        e = FV.fvsrn_render(sgnet, I.ramp_tf(), scams, smarch, "f16")
+        torch.cuda.synchronize()
+        assert torch.equal(gout, first), k
+        assert torch.equal(e, sfirst), k
+
+
 @pytest.mark.parametrize("prec,tol", [("f32", FP32_TOL), ("f16", FP16_TOL), ("bf16", BF16_TOL)])
 @pytest.mark.parametrize("spec_name", ["NET_SMALL", "NET_STUDY", "NET_SHADED"])
 def test_eval_points(FV, spec_name, prec, tol):
