@@ -69,7 +69,7 @@ def time_launches(fn, steps, warmup):
 # mangled name of the study render kernel (FP16 network, c = 32, F = 16, L = 8,
 # sine, FP16 latent grid, no time input or Fourier matrix, no shading)
 STUDY_KERNEL = ("_ZN12fvsrn_detail12_GLOBAL__N_112march_kernelINS_3CfgILi1ELi32ELi16ELi8ELi0ELi1ELi0ELi0EEELi0ELi0EEEvNS_"
-                "6NetDevENS_5TFDevENS_9ViewBatchENS_8MarchDevEPfPyii")
+                "6NetDevENS_5TFDevENS_9ViewBatchENS_8MarchDevEPfPyPjii")
 
 
 def kernel_isa_hash():
