@@ -92,6 +92,14 @@ int waves_per_block(int H) {
   return best;
 }
 
+// Workgroups of wpb waves and shm bytes of LDS that the GPU holds at once (by
+// LDS and by the VGPR budget of max_waves).
+template <class CF, int MODE, bool POINTS = false>
+long long resident_blocks(int wpb, size_t shm) {
+  const int per_cu_lds = (int)(kLdsBytes / shm), per_cu_regs = max_waves<CF, MODE, POINTS>() / wpb;
+  return (long long)device_cus() * (per_cu_lds < per_cu_regs ? per_cu_lds : per_cu_regs);
+}
+
 // ----------------------------------------------------- TF, camera, march
 
 __device__ inline void tf_eval(const TFDev& tf, float d, float rgba[4]) {
@@ -410,10 +418,8 @@ int launch_render_t(const NetDev& nd, const TFDev& tf, const ViewBatch& vb, cons
   const int wpb = waves_per_block<CF, MODE>(nd.H);
   if (wpb < 1) return kLaunchNoLds;
   const size_t shm = (size_t)fixed_lds_bytes<CF, MODE>(nd.H) + (size_t)wpb * G::FEAT_BYTES;
-  // the workgroups the CUs hold at once (LDS and the VGPR budget), fewer for
-  // small launches
-  const int per_cu_lds = (int)(kLdsBytes / shm), per_cu_regs = max_waves<CF, MODE>() / wpb;
-  const long long resident = (long long)device_cus() * (per_cu_lds < per_cu_regs ? per_cu_lds : per_cu_regs);
+  // the workgroups the CUs hold at once, fewer for small launches
+  const long long resident = resident_blocks<CF, MODE>(wpb, shm);
   const long long want = (tiles + wpb - 1) / wpb;
   const long long blocks = want < resident ? want : resident;
   if (blocks < 1) return 0;
@@ -444,8 +450,10 @@ int launch_points_t(const NetDev& nd, const float* xyz, long long n, int key, fl
                               kLdsBytes);
     attr = true;
   }
-  // each wave walks several chunks so that the weight staging is amortised
-  const int blocks = grid_blocks((n + PER - 1) / PER, wpb * 8, device_cus() * 4);
+  // persistent: the workgroups the GPU holds at once walk the chunks (equal
+  // cost), so the weights are staged once per workgroup and no workgroup
+  // waits for another to release its LDS
+  const int blocks = grid_blocks((n + PER - 1) / PER, wpb, (int)resident_blocks<CF, PM, true>(wpb, shm));
   hipLaunchKernelGGL((points_kernel<CF, PM, HH>), dim3(blocks), dim3(wpb * 64), shm, st, nd, xyz, n, key, key_w,
                      out_d, out_g);
   return check_launch();
