@@ -588,7 +588,37 @@ def main():
             comp["training_small_power_law"] = {"steps": args.train_steps, "batch": 1 << 18,
                                                 "ms_per_step": t_s / args.train_steps * 1e3,
                                                 "l1_untrained": l1_0, "l1_trained": l1_1}
-            del pvol, str_, snet
+            # the same fit with the network's forward and backward on FP16 MFMA
+            snet16 = FV.Network(I.NET_SMALL, slat, sw, grid_dtype=FV.F32, device=dev)
+            str16 = Trainer(snet16, pvol, batch=1 << 18, seed=I.SEED_TRAIN, precision="f16")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.train_steps):
+                str16.step()
+            torch.cuda.synchronize()
+            t_16 = time.perf_counter() - t0
+            comp["training_small_power_law"]["fp16"] = {
+                "ms_per_step": t_16 / args.train_steps * 1e3,
+                "l1_trained": torch.mean(torch.abs(FV.fvsrn_eval_points(snet16, xs, 0.0, "f32") - ps)).item()}
+            # gradient steps alone (no sampling, targets or Adam), FP32 and FP16
+            # networks, the three network shapes, 2^18 points
+            gsteps = {}
+            for sname in ("NET_SMALL", "NET_STUDY", "NET_SHADED"):
+                gspec = getattr(I, sname)
+                glat, gw = I.net_params(gspec, 3)
+                gnet = FV.Network(gspec, glat, gw, grid_dtype=FV.F32, device=dev)
+                gdl, gdw = torch.empty_like(gnet.latent), torch.empty_like(gnet.weights)
+                gws = torch.empty(max(FV.fvsrn_train_workspace_size(gspec, 1 << 18), 16), dtype=torch.uint8,
+                                  device=dev)
+                row = {}
+                for gp in ("f32", "f16"):
+                    per, _ = time_launches(lambda: FV.fvsrn_train_step(gnet, gdl, gdw, xs, target=ps, workspace=gws,
+                                                                       precision=gp), 20, 3)
+                    row[gp + "_ms"] = float(np.median(per))
+                row["fp16_speedup"] = row["f32_ms"] / row["f16_ms"]
+                gsteps[sname.lower()] = row
+            comp["training_gradient_step_2e18"] = gsteps
+            del pvol, str_, snet, str16, snet16
             # the shaded workload: the 64^3 x 16, 4 x 48 network fitted to the
             # 512^3 Marschner-Lobb field, one 1920 x 1080 view at step 1/512
             # with Phong shading, FP16 MFMA; gradients by forward mode (the

@@ -249,8 +249,15 @@ typedef struct {
 } fvsrn_adam;
 
 /* One world-space training step on n points (Sec. 3, Sec. 5: L1 loss, Adam;
-   Sec. 8 for keyframe grids). FP32 latent grids and FP32 weights, FP32
-   arithmetic.
+   Sec. 8 for keyframe grids). FP32 latent grids and FP32 weights (the master
+   copy), FP32 gradients and Adam. desc->precision selects the network's
+   arithmetic: FVSRN_F32 (FP32 MFMA), or FVSRN_F16 -- forward and backward on
+   FP16 MFMA with FP32 accumulation, the forward pass identical to the FP16
+   render's, dL/dy scaled by 2^floor(log2 n) before it is rounded to FP16 and
+   every gradient by the inverse power of two; built for L1 mode, the sine,
+   SnakeAlt and identity activations, c in {32, 48} with (F, L) = (8, 4) or
+   (16, 8), no time input or Fourier matrix (other FP16 requests return
+   FVSRN_ERR_UNSUPPORTED).
      L1 mode  (target != NULL): loss = mean |d(x_i, t_i) - target_i|, sign(0) = 0.
        For a num_outputs == 4 network with target_grad != NULL ([n][3]) the
        predicted gradient g_i (outputs 1..3) is fitted as well (Sec. 6):

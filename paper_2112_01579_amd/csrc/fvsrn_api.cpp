@@ -399,7 +399,12 @@ fvsrn_status train_step_impl(const fvsrn_net_desc* desc, float* latent, float* w
                               desc->grid_channels * 4;
   if (all_bytes >= (1LL << 31)) return fail(FVSRN_ERR_UNSUPPORTED, "training: K latent grids above 2^31 bytes");
   if (desc->grid_dtype != FVSRN_F32) return fail(FVSRN_ERR_UNSUPPORTED, "training needs an FP32 latent grid");
-  if (desc->precision != FVSRN_F32) return fail(FVSRN_ERR_UNSUPPORTED, "training runs in FP32");
+  if (desc->precision != FVSRN_F32 && desc->precision != FVSRN_F16)
+    return fail(FVSRN_ERR_UNSUPPORTED, "training runs in FP32 or FP16");
+  if (desc->precision == FVSRN_F16 &&
+      (dloss_dy || desc->time_encoding != FVSRN_TIME_LATENT_ONLY || desc->fourier_matrix))
+    return fail(FVSRN_ERR_UNSUPPORTED,
+                "FP16 training: L1 targets only, without time inputs or a Fourier matrix (use FP32)");
   if (!latent || !weights || !d_latent || !d_weights)
     return fail(FVSRN_ERR_INVALID_ARGUMENT, "latent, weights, d_latent, d_weights must be non-NULL");
   if (!aligned16(latent) || !aligned16(weights) || !aligned16(d_latent) || !aligned16(d_weights))
@@ -444,7 +449,7 @@ fvsrn_status train_step_impl(const fvsrn_net_desc* desc, float* latent, float* w
                               adam ? adam->beta2 : 0.f, adam ? adam->eps : 0.f, adam ? adam->step : 0,
                               adam ? adam->m_latent : nullptr, adam ? adam->v_latent : nullptr,
                               adam ? adam->m_weights : nullptr, adam ? adam->v_weights : nullptr, out_loss,
-                              workspace, workspace_bytes, stream);
+                              workspace, workspace_bytes, desc->precision == FVSRN_F16 ? 1 : 0, stream);
   return launch_status(rc, static_ws ? "fvsrn_train_step_noalloc" : "fvsrn_train_step");
 }
 

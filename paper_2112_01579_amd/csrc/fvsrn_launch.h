@@ -106,7 +106,7 @@ int launch_train(const NetDev& net, const KeyTimes& kt, float* latent, float* we
                  float* d_weights, const float* xyz, const float* times, long long n, const float* target,
                  const float* target_grad, float grad_weight, const float* dloss_dy, int use_adam, float lr_grid, float lr_mlp, float beta1, float beta2,
                  float eps, int step, float* m_lat, float* v_lat, float* m_w, float* v_w, float* out_loss,
-                 void* workspace, size_t ws_bytes, void* stream);
+                 void* workspace, size_t ws_bytes, int half, void* stream);
 
 // Size of the per-GPU training workspace of fvsrn_train_step_noalloc.
 constexpr size_t kStaticTrainScratchBytes = (size_t)96 << 20;

@@ -23,6 +23,7 @@
 // dW is bitwise reproducible). slice_sum_kernel and gather_kernel then sum the
 // slices in a fixed order into the packed gradient; adam_kernel applies the
 // update.
+#include <cmath>
 #include <mutex>
 
 #include "fvsrn_net.hpp"
@@ -450,6 +451,390 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
   slice[TC::tiles(H) * 256 + 256 + lane] = loss_acc;
 }
 
+// ------------------------------------------------- FP16-MFMA training
+//
+// The same step with the network in FP16 on the 16x16x32 and 16x16x16 MFMA
+// with FP32 accumulation: the forward pass is the FP16 render's (its staged
+// weight fragments and input rows, activations handed from layer to layer
+// as D -> B fragments), the backward pass runs W^T on FP16 fragments of the
+// unscaled master weights, and every weight-gradient tile is an FP16 GEMM
+// over the chunk's 16 points. The parameters, the gradients they receive,
+// the latent gather and Adam stay FP32, and the slice layout is the FP32
+// step's, so the reduction kernels are shared.
+//
+// FP16 holds the output gradient only if it is scaled: dL/dy of the mean L1
+// loss is sign / n, far below FP16's normal range for 2^18 points. The kernel
+// multiplies dL/dy by gs = 2^floor(log2 n) (dscale = gs / n in [0.5, 1]) and
+// every gradient it writes by 1 / gs, a power of two, so the scaling itself
+// is exact.
+template <int C, int F, int L, int ACT>
+struct TrainCfgH {
+  using T32 = TrainCfg<C, F, L, ACT>;  // slice layout shared with the FP32 step
+  using CF = Cfg<kF16, C, F, L, ACT, 0>;
+  using G = typename CF::G;
+  static constexpr int S = 16;  // points per wave chunk (one N-tile)
+  static constexpr int MT = G::MT;
+  // The input-row columns must tile as in the FP32 layout (latent, Fourier
+  // and the x y z 1 tail at the same columns; FP16's extra pad is zero).
+  static_assert(G::KMAIN == T32::G::KMAIN && (G::KROW + 15) / 16 == T32::NK0, "row layouts differ");
+  // [channel][point] FP16 buffers: 20 halves per channel row, so that the
+  // 8-byte reads of 16 consecutive channel rows at one point offset fall on
+  // distinct banks
+  static constexpr int HSTR = 20;
+  static constexpr int FEAT = S * G::ROW_DW * 4;
+  static constexpr int CH = C * HSTR * 2;
+  static constexpr int ACTD = MT * kWave * 8;  // one layer's act' (4 halves per lane and M-tile)
+  static constexpr int DY = 64 * 4;
+  static constexpr int ZS = 20;
+  static constexpr int ZBUF = S * ZS * 4;
+  __host__ __device__ static int wave_bytes(int H) { return FEAT + H * CH + H * ACTD + CH + DY + ZBUF; }
+  // transposed fragments: W_i^T (i = 1..H-1) and W_0's latent columns
+  static constexpr int WBA = MT * G::HS32 * kWave * 16;
+  static constexpr int WB = WBA + MT * G::HS16 * kWave * 8;
+  static constexpr int WZA = G::HS32 * kWave * 16;
+  static constexpr int WZ = WZA + G::HS16 * kWave * 8;
+  __host__ __device__ static int back_bytes(int H) { return (H - 1) * WB + WZ; }
+  __host__ __device__ static int block_bytes(int H, int waves) {
+    return G::weight_bytes(H) + back_bytes(H) + waves * wave_bytes(H);
+  }
+};
+
+// FP16 A fragments of the transposed layers. Row r of M-tile mk is input
+// channel 16 mk + r; the K slots follow the order in which the forward pass
+// packs a D fragment into a B fragment (slot j of lane group g in K32 step s
+// is channel 32 s + 4 g + j for j < 4, 32 s + 16 + 4 g + j - 4 otherwise; the
+// K16 step of c = 48 holds channels 32 + 4 g + j), so that a delta in D
+// layout, packed the same way, is the B operand. Unscaled master weights:
+// the deltas are in world units.
+template <class TH>
+__device__ void stage_backward_h(const NetDev& nd, char* p) {
+  using G = typename TH::G;
+  constexpr int C = TH::CF::C, F = TH::CF::F, MT = TH::MT;
+  const int H = nd.H, K0 = G::K0IN;
+  const float* w = nd.weights;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  auto stage = [&](char* dst, int mtiles, auto val) {  // val(row channel, K channel)
+    _Float16* A = reinterpret_cast<_Float16*>(dst);
+    for (int e = tid; e < mtiles * G::HS32 * kWave * 8; e += nt) {
+      const int j = e & 7, lane = (e >> 3) & 63, s = (e >> 9) % G::HS32, mk = (e >> 9) / G::HS32;
+      const int g = lane >> 4;
+      const int o = 32 * s + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4));
+      A[e] = (_Float16)val(16 * mk + (lane & 15), o);
+    }
+    if constexpr (G::HS16 > 0) {
+      _Float16* T = reinterpret_cast<_Float16*>(dst + mtiles * G::HS32 * kWave * 16);
+      for (int e = tid; e < mtiles * kWave * 4; e += nt) {
+        const int j = e & 3, lane = (e >> 2) & 63, mk = e >> 8;
+        T[e] = (_Float16)val(16 * mk + (lane & 15), 16 * (MT - 1) + 4 * (lane >> 4) + j);
+      }
+    }
+  };
+  for (int i = 1; i < H; ++i) {
+    const float* Wi = w + (long long)C * K0 + C + (long long)(i - 1) * (C * C + C);
+    stage(p + (i - 1) * TH::WB, MT, [&](int k, int o) { return Wi[o * C + k]; });
+  }
+  stage(p + (H - 1) * TH::WB, 1, [&](int m, int o) { return m < F ? w[(long long)o * K0 + 3 + m] : 0.0f; });
+}
+
+template <int C, int F, int L, int ACT>
+__global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
+    NetDev nd, KeyTimes kt, const float* xyz, const float* times, long long n, const float* target,
+    const float* target_grad, float gw3, float* dz_out, int* cell_out, int* cell_count, float* ws, int n_waves,
+    float dscale, float inv_gs) {
+  using TH = TrainCfgH<C, F, L, ACT>;
+  using T32 = typename TH::T32;
+  using CF = typename TH::CF;
+  using G = typename TH::G;
+  using PR = PrecT<kF16>;
+  using VA = typename PR::VA;
+  using VT = typename PR::VT;
+  using E = _Float16;
+  constexpr int MT = TH::MT, S = TH::S, HSTR = TH::HSTR, HS32 = G::HS32, HS16 = G::HS16;
+  const int H = nd.H, NO = nd.NO;
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  stage_weights<CF>(nd, smem);
+  char* back = smem + G::weight_bytes(H);
+  stage_backward_h<TH>(nd, back);
+  __syncthreads();
+  const int wave_l = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * (blockDim.x >> 6) + wave_l;
+  if (wave >= n_waves) return;
+  const int g = lane >> 4, nn = lane & 15;
+  char* wbase = back + TH::back_bytes(H) + wave_l * TH::wave_bytes(H);
+  E* feat = reinterpret_cast<E*>(wbase);
+  E* hbuf = reinterpret_cast<E*>(wbase + TH::FEAT);  // h_i = act(a_i): [layer][channel][point]
+  char* actd = wbase + TH::FEAT + H * TH::CH;          // act'(a_i): [layer][M-tile][lane] x 4
+  E* dbuf = reinterpret_cast<E*>(actd + H * TH::ACTD);  // delta_i: [channel][point]
+  float* dy = reinterpret_cast<float*>(reinterpret_cast<char*>(dbuf) + TH::CH);
+  float* zbuf = dy + 64;
+  float* slice = ws + (size_t)wave * T32::slice(H);
+  const VA* W0A = reinterpret_cast<const VA*>(smem);
+  const VA* W0T = reinterpret_cast<const VA*>(smem + G::W0A);
+  const char* wout_p = smem + G::W0A + G::W0T + (H - 1) * G::HID;
+  const f4 b_out = *reinterpret_cast<const f4*>(wout_p + G::WOA + G::WOT);
+  const float* w_out = nd.weights + (long long)C * G::K0IN + C + (long long)(H - 1) * (C * C + C);
+  const f4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+  float loss_acc = 0.0f;
+  f4 dbo_acc = zero;
+  const long long nchunks = (n + S - 1) / S;
+  bool first = true;
+  // branch-free slice update (see fwd_bwd_kernel)
+  auto add_tile = [&](int tile, f4 v) {
+    f4* dst = reinterpret_cast<f4*>(slice + tile * 256) + lane;
+    const f4 old = *dst;
+    f4 r;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) r[j] = first ? v[j] : old[j] + v[j];
+    *dst = r;
+  };
+  for (long long c = wave; c < nchunks; c += n_waves) {
+    const long long idx = c * S + lane;
+    const bool ok = lane < S && idx < n;
+    float px = 0.0f, py = 0.0f, pz = 0.0f, pt = 0.0f;
+    if (ok) {
+      px = xyz[3 * idx];
+      py = xyz[3 * idx + 1];
+      pz = xyz[3 * idx + 2];
+      if (times) pt = times[idx];
+    }
+    int key;
+    float kw;
+    key_pair(kt, nd.K, pt, key, kw);
+    float tfe[1];
+    if (lane < S) {
+      if (nd.K == 1) {
+        write_features<CF, false>(feat + lane * G::ROW, make_latent_src(nd, 0, 0.0f), value_role(), px, py, pz, tfe,
+                                  nd.fm);
+      } else {
+        write_features<CF, false>(feat + lane * G::ROW, make_latent_src(nd, key, kw), value_role(), px, py, pz, tfe,
+                                  nd.fm);
+      }
+    }
+    wave_lds_sync();
+    // ---------------- forward (FP16 MFMA); keep act'(a_i) and h_i
+    f4 acc[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) acc[mt] = zero;
+#pragma unroll
+    for (int s = 0; s < G::S0; ++s) {
+      const VA b = *reinterpret_cast<const VA*>(feat + nn * G::ROW + 32 * s + 8 * g);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[mt] = PR::mma(W0A[(mt * G::S0 + s) * kWave + lane], b, acc[mt]);
+    }
+    {
+      const VA b = *reinterpret_cast<const VA*>(feat + nn * G::ROW + G::KMAIN + 8 * (g % (G::KT / 8)));
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[mt] = PR::mma(W0T[mt * kWave + lane], b, acc[mt]);
+    }
+    VA bA[HS32];
+    VT bT;
+    const char* p = smem + G::W0A + G::W0T;
+    for (int i = 0; i < H; ++i) {
+      E* hb = hbuf + i * C * HSTR;
+      h4* ad = reinterpret_cast<h4*>(actd + i * TH::ACTD);
+      float hv[MT][4];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        h4 dv;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float a = acc[mt][j];
+          hv[mt][j] = act_el<ACT, false>(a, value_role());
+          dv[j] = (E)act_d<ACT>(a);
+          hb[(16 * mt + 4 * g + j) * HSTR + nn] = (E)hv[mt][j];
+        }
+        ad[mt * kWave + lane] = dv;
+      }
+#pragma unroll
+      for (int s = 0; s < HS32; ++s)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          bA[s][j] = (E)hv[2 * s][j];
+          bA[s][j + 4] = (E)hv[2 * s + 1][j];
+        }
+      if constexpr (HS16 > 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bT[j] = (E)hv[MT - 1][j];
+      }
+      if (i + 1 < H) {
+        const VA* WA = reinterpret_cast<const VA*>(p);
+        const VT* WT = reinterpret_cast<const VT*>(p + G::WHA);
+        const float* BHp = reinterpret_cast<const float*>(p + G::WHA + G::WHT);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          acc[mt] = *reinterpret_cast<const f4*>(BHp + 16 * mt + 4 * g);
+#pragma unroll
+          for (int s = 0; s < HS32; ++s) acc[mt] = PR::mma(WA[(mt * HS32 + s) * kWave + lane], bA[s], acc[mt]);
+          if constexpr (HS16 > 0) acc[mt] += PR::mmt(WT[mt * kWave + lane], bT, zero);
+        }
+        p += G::HID;
+      }
+    }
+    // output layer: N-tile 0's weights sit in rows 0..3, so lanes < 16 hold
+    // their own point's outputs
+    f4 out = zero;
+#pragma unroll
+    for (int s = 0; s < HS32; ++s) out = PR::mma(reinterpret_cast<const VA*>(p)[s * kWave + lane], bA[s], out);
+    if constexpr (HS16 > 0) out += PR::mmt(reinterpret_cast<const VT*>(p + G::WOA)[lane], bT, zero);
+    // ---------------- loss and the scaled dL/dy of this lane's own point
+    const f4 yv = out + b_out;
+    const float d = sigmoid_f(yv[0]);
+    float gy = 0.0f;
+    f4 dyo = zero;
+    if (ok) {
+      const float r = d - target[idx];
+      loss_acc += fabsf(r);
+      gy = (r > 0.0f ? 1.0f : (r < 0.0f ? -1.0f : 0.0f)) * dscale;
+      if (target_grad) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const float rg = yv[1 + a] - target_grad[3 * idx + a];
+          loss_acc += gw3 * fabsf(rg);
+          dyo[1 + a] = (rg > 0.0f ? gw3 : (rg < 0.0f ? -gw3 : 0.0f)) * dscale;
+        }
+      }
+    }
+    dyo[0] = gy * d * (1.0f - d);
+    dbo_acc += dyo;
+    if (lane < S) {
+#pragma unroll
+      for (int o = 0; o < 4; ++o) dy[o * S + lane] = dyo[o];
+    }
+    wave_lds_sync();
+    // ---------------- output weights: dW_H[o][k] = sum_s dy[o][s] h_{H-1}[k][s]
+    {
+      const E* hl = hbuf + (H - 1) * C * HSTR;
+      VT ay;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) ay[j] = nn < NO ? (E)dy[nn * S + 4 * g + j] : (E)0.0f;
+#pragma unroll
+      for (int nk = 0; nk < MT; ++nk) {
+        const VT b = *reinterpret_cast<const VT*>(hl + (16 * nk + nn) * HSTR + 4 * g);
+        add_tile(T32::tile_out(H, nk), PR::mmt(ay, b, zero) * inv_gs);
+      }
+    }
+    // ---------------- backward
+    f4 dh[MT];  // d L / d h_i, D layout
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) dh[mt] = zero;
+    for (int o = 0; o < NO; ++o) {
+      const float dys = dy[o * S + nn];
+      const float* wr = w_out + o * C;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const f4 wo = {wr[16 * mt + 4 * g + 0], wr[16 * mt + 4 * g + 1], wr[16 * mt + 4 * g + 2],
+                       wr[16 * mt + 4 * g + 3]};
+        dh[mt] += wo * dys;
+      }
+    }
+    for (int i = H - 1; i >= 0; --i) {
+      const h4* ad = reinterpret_cast<const h4*>(actd + i * TH::ACTD);
+      // delta_i = (d L / d h_i) * act'(a_i), world units
+      float dv[MT][4];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const h4 a = ad[mt * kWave + lane];
+        f4 da;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          dv[mt][j] = dh[mt][j] * (float)a[j];
+          da[j] = dv[mt][j];
+          dbuf[(16 * mt + 4 * g + j) * HSTR + nn] = (E)dv[mt][j];
+        }
+        if (i >= 1) add_tile(T32::tile_bias(H, i, mt), da * inv_gs);
+      }
+      VA bD[HS32];
+      VT bDT;
+#pragma unroll
+      for (int s = 0; s < HS32; ++s)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          bD[s][j] = (E)dv[2 * s][j];
+          bD[s][j + 4] = (E)dv[2 * s + 1][j];
+        }
+      if constexpr (HS16 > 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bDT[j] = (E)dv[MT - 1][j];
+      }
+      wave_lds_sync();
+      // dW_i = delta_i h_{i-1}^T over the chunk's points (16x16x16, K = points)
+      if (i == 0) {
+        // the input row: FP16 rows hold 2 cos in the cosine block (the
+        // forward fragments carry half those weights), so that gradient
+        // column is halved
+#pragma unroll
+        for (int nk = 0; nk < T32::NK0; ++nk) {
+          const int col = 16 * nk + nn;
+          VT b;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) b[j] = col < G::KROW ? feat[(4 * g + j) * G::ROW + col] : (E)0.0f;
+          const float cs = (col >= F + 3 * L && col < F + 6 * L) ? 0.5f * inv_gs : inv_gs;
+#pragma unroll
+          for (int mo = 0; mo < MT; ++mo) {
+            const VT a = *reinterpret_cast<const VT*>(dbuf + (16 * mo + nn) * HSTR + 4 * g);
+            add_tile(T32::tile_l0(mo, nk), PR::mmt(a, b, zero) * cs);
+          }
+        }
+      } else {
+        const E* hp = hbuf + (i - 1) * C * HSTR;
+#pragma unroll
+        for (int nk = 0; nk < MT; ++nk) {
+          const VT b = *reinterpret_cast<const VT*>(hp + (16 * nk + nn) * HSTR + 4 * g);
+#pragma unroll
+          for (int mo = 0; mo < MT; ++mo) {
+            const VT a = *reinterpret_cast<const VT*>(dbuf + (16 * mo + nn) * HSTR + 4 * g);
+            add_tile(T32::tile_h(H, i, mo, nk), PR::mmt(a, b, zero) * inv_gs);
+          }
+        }
+      }
+      if (i >= 1) {
+        // d L / d h_{i-1} = W_i^T delta_i
+        const char* wb = back + (i - 1) * TH::WB;
+        const VA* WBA = reinterpret_cast<const VA*>(wb);
+        const VT* WBT = reinterpret_cast<const VT*>(wb + TH::WBA);
+#pragma unroll
+        for (int mk = 0; mk < MT; ++mk) {
+          f4 a2 = zero;
+#pragma unroll
+          for (int s = 0; s < HS32; ++s) a2 = PR::mma(WBA[(mk * HS32 + s) * kWave + lane], bD[s], a2);
+          if constexpr (HS16 > 0) a2 += PR::mmt(WBT[mk * kWave + lane], bDT, zero);
+          dh[mk] = a2;
+        }
+      } else {
+        // d L / d z = W_0[:, latent]^T delta_0 -> zbuf[point][channel]
+        const char* wz = back + (H - 1) * TH::WB;
+        f4 dz = zero;
+#pragma unroll
+        for (int s = 0; s < HS32; ++s) dz = PR::mma(reinterpret_cast<const VA*>(wz)[s * kWave + lane], bD[s], dz);
+        if constexpr (HS16 > 0) dz += PR::mmt(reinterpret_cast<const VT*>(wz + TH::WZA)[lane], bDT, zero);
+        if (4 * g < F) *reinterpret_cast<f4*>(zbuf + nn * TH::ZS + 4 * g) = dz * inv_gs;
+      }
+      wave_lds_sync();
+    }
+    // ---------------- dL/dz and the latent cell of this lane's point
+    if (ok) {
+      int ix, iy, iz;
+      float fx, fy, fz;
+      axis_cell(px, nd.R, ix, fx);
+      axis_cell(py, nd.R, iy, fy);
+      axis_cell(pz, nd.R, iz, fz);
+      const int cell = (iz * (nd.R - 1) + iy) * (nd.R - 1) + ix;
+      cell_out[idx] = cell;
+      atomicAdd(cell_count + cell, 1);
+      float4* dst = reinterpret_cast<float4*>(dz_out + idx * F);
+#pragma unroll
+      for (int q = 0; q < F / 4; ++q)
+        dst[q] = make_float4(zbuf[lane * TH::ZS + 4 * q], zbuf[lane * TH::ZS + 4 * q + 1],
+                             zbuf[lane * TH::ZS + 4 * q + 2], zbuf[lane * TH::ZS + 4 * q + 3]);
+    }
+    first = false;
+  }
+  dbo_acc *= inv_gs;
+#pragma unroll
+  for (int o = 0; o < 4; ++o) slice[T32::tiles(H) * 256 + 64 * o + lane] = dbo_acc[o];
+  slice[T32::tiles(H) * 256 + 256 + lane] = loss_acc;
+}
+
 // Sums the wave slices in a fixed order into the packed gradient, in two
 // stages so that the reads are coalesced and plenty of them are in flight:
 // slice_sum_kernel adds groups of kGroup consecutive slices element-wise
@@ -749,12 +1134,26 @@ __global__ void latent_grad_kernel(const float* xyz, const float* times, KeyTime
   }
 }
 
+// FP16 training: no time inputs or Fourier matrix, and the FP16 input row
+// must tile like the FP32 one (the four base shapes)
+template <int C, int F, int L, int TE, int FM>
+constexpr bool half_train_ok() {
+  return TE == 0 && FM == 0 && Geo<kF16, C, F, L>::KMAIN == Geo<kF32, C, F, L>::KMAIN &&
+         (Geo<kF16, C, F, L>::KROW + 15) / 16 == (Geo<kF32, C, F, L>::KROW + 15) / 16;
+}
+
 template <int C, int F, int L, int ACT, int TE = 0, int FM = 0>
 struct TrainEntry {
   using TC = TrainCfg<C, F, L, ACT, TE, FM>;
   static int waves_per_block(int H) {
     const int fixed = TC::G::weight_bytes(H) + TC::back_bytes(H);
     int w = (160 * 1024 - fixed) / TC::wave_bytes(H);
+    return w < 1 ? 0 : (w > kTrainWavesPerBlock ? kTrainWavesPerBlock : w);
+  }
+  template <class TH>
+  static int waves_per_block_h(int H) {
+    const int fixed = TH::G::weight_bytes(H) + TH::back_bytes(H);
+    int w = (160 * 1024 - fixed) / TH::wave_bytes(H);
     return w < 1 ? 0 : (w > kTrainWavesPerBlock ? kTrainWavesPerBlock : w);
   }
   static int n_waves(long long n) {
@@ -775,8 +1174,9 @@ struct TrainEntry {
   static int run(const NetDev& nd, const KeyTimes& kt, float* latent, float* d_latent, float* d_weights,
                  const float* xyz, const float* times, long long n, const float* target,
                  const float* target_grad, float grad_weight, const float* dloss, float* out_loss, void* ws,
-                 hipStream_t st) {
+                 bool half, hipStream_t st) {
     const int H = nd.H;
+    if (half && (!half_train_ok<C, F, L, TE, FM>() || !target)) return 1;
     const int wpb = waves_per_block(H);
     if (wpb < 1) return kLaunchNoLds;
     const int ncell = (nd.R - 1) * (nd.R - 1) * (nd.R - 1);
@@ -803,7 +1203,28 @@ struct TrainEntry {
     NetDev nd2 = nd;
     nd2.latent = latent;
     nd2.grid_f16 = 0;
-    if (n > 0) {
+    if (n > 0 && half) {
+      if constexpr (half_train_ok<C, F, L, TE, FM>()) {
+        using TH = TrainCfgH<C, F, L, ACT>;
+        const int wph = waves_per_block_h<TH>(H);
+        if (wph < 1) return kLaunchNoLds;
+        static bool attr_h = false;
+        if (!attr_h) {
+          (void)hipFuncSetAttribute((const void*)fwd_bwd_h_kernel<C, F, L, ACT>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+          attr_h = true;
+        }
+        // dL/dy scaled by gs = 2^floor(log2 n) for FP16, gradients by 1 / gs
+        const int e = std::ilogb((double)n);
+        const double gs = std::ldexp(1.0, e);
+        hipLaunchKernelGGL((fwd_bwd_h_kernel<C, F, L, ACT>), dim3((nw + wph - 1) / wph), dim3(wph * 64),
+                           (size_t)TH::block_bytes(H, wph), st, nd2, kt, xyz, times, n, target, target_grad,
+                           grad_weight / 3.0f, dz, cell, count, (float*)ws, nw, (float)(gs / (double)n),
+                           (float)(1.0 / gs));
+        rc = check_launch();
+        if (rc) return rc;
+      }
+    } else if (n > 0) {
       hipLaunchKernelGGL((fwd_bwd_kernel<C, F, L, ACT, TE, FM>), dim3((nw + wpb - 1) / wpb), dim3(wpb * 64), shm, st, nd2,
                          kt, xyz, times, n, target, target_grad, grad_weight / 3.0f, dloss, dz, cell, count, (float*)ws,
                          nw, 1.0f / (float)n);
@@ -918,14 +1339,14 @@ int launch_train(const NetDev& nd, const KeyTimes& kt, float* latent, float* wei
                  float* d_weights, const float* xyz, const float* times, long long n, const float* target,
                  const float* target_grad, float grad_weight, const float* dloss_dy, int use_adam, float lr_grid, float lr_mlp, float beta1, float beta2,
                  float eps, int step, float* m_lat, float* v_lat, float* m_w, float* v_w, float* out_loss,
-                 void* workspace, size_t ws_bytes, void* stream) {
+                 void* workspace, size_t ws_bytes, int half, void* stream) {
   const hipStream_t st = (hipStream_t)stream;
   NetDev net = nd;
   net.weights = weights;
   int rc = 1;
 #define FV_TRAIN_RUN(C_, F_, L_, ACT_, TE_, FM_)                                                             \
   rc = TrainEntry<C_, F_, L_, ACT_, TE_, FM_>::run(net, kt, latent, d_latent, d_weights, xyz, times, n, target,     \
-                                              target_grad, grad_weight, dloss_dy, out_loss, workspace, st)
+                                              target_grad, grad_weight, dloss_dy, out_loss, workspace, half != 0, st)
 #define X(C_, F_, L_)                                                        \
   if (nd.C == C_ && nd.F == F_ && nd.L == L_) {                              \
     if (nd.time_enc != 0 || nd.fmat) {                                       \

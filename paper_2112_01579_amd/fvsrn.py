@@ -499,8 +499,11 @@ def fvsrn_train_step(net: Network, d_latent: torch.Tensor, d_weights: torch.Tens
                      target: Optional[torch.Tensor] = None, dloss_dy: Optional[torch.Tensor] = None,
                      adam: Optional[dict] = None, out_loss: Optional[torch.Tensor] = None,
                      workspace: Optional[torch.Tensor] = None, times: Optional[torch.Tensor] = None,
-                     target_grad: Optional[torch.Tensor] = None, grad_weight: float = 0.0, stream=None):
-    """One training step on ``net`` (FP32 latent grids). ``times`` (device
+                     target_grad: Optional[torch.Tensor] = None, grad_weight: float = 0.0, stream=None,
+                     precision="f32"):
+    """One training step on ``net`` (FP32 latent grids and master weights;
+    ``precision`` "f16" runs the network's forward and backward passes on
+    FP16 MFMA, L1 targets only). ``times`` (device
     [n], optional) holds each point's keyframe time; ``target_grad`` ([n][3],
     4-output networks, L1 mode) the gradient targets of the predicted
     gradient, weighted by ``grad_weight``. ``adam`` is a dict with
@@ -508,23 +511,23 @@ def fvsrn_train_step(net: Network, d_latent: torch.Tensor, d_weights: torch.Tens
     m_latent, v_latent, m_weights, v_weights; None computes gradients only.
     ``workspace`` (uint8, optional) is allocated here when None."""
     _train_step(net, d_latent, d_weights, xyz, target, dloss_dy, adam, out_loss, workspace, times, target_grad,
-                grad_weight, stream, noalloc=False)
+                grad_weight, stream, noalloc=False, precision=precision)
 
 
 def fvsrn_train_step_noalloc(net: Network, d_latent: torch.Tensor, d_weights: torch.Tensor, xyz: torch.Tensor,
                              target: Optional[torch.Tensor] = None, dloss_dy: Optional[torch.Tensor] = None,
                              adam: Optional[dict] = None, out_loss: Optional[torch.Tensor] = None,
                              times: Optional[torch.Tensor] = None, target_grad: Optional[torch.Tensor] = None,
-                             grad_weight: float = 0.0, stream=None):
+                             grad_weight: float = 0.0, stream=None, precision="f32"):
     """fvsrn_train_step on the library's static per-GPU workspace: nothing
     is allocated (by the library or here). Calls on one GPU share that
     workspace and must not overlap."""
     _train_step(net, d_latent, d_weights, xyz, target, dloss_dy, adam, out_loss, None, times, target_grad,
-                grad_weight, stream, noalloc=True)
+                grad_weight, stream, noalloc=True, precision=precision)
 
 
 def _train_step(net, d_latent, d_weights, xyz, target, dloss_dy, adam, out_loss, workspace, times, target_grad,
-                grad_weight, stream, noalloc):
+                grad_weight, stream, noalloc, precision="f32"):
     dev = _check_net(net)
     if net.grid_dtype != F32:
         raise FvsrnArgumentError("training needs an FP32 latent grid")
@@ -542,7 +545,9 @@ def _train_step(net, d_latent, d_weights, xyz, target, dloss_dy, adam, out_loss,
         for k, cnt in (("m_latent", net.spec.n_latent), ("v_latent", net.spec.n_latent),
                        ("m_weights", net.spec.n_weights), ("v_weights", net.spec.n_weights)):
             check_tensor(adam[k], "adam[%s]" % k, numel=cnt, device=dev)
-    d = net.desc("f32")
+    if precision not in PREC:
+        raise FvsrnArgumentError("precision must be one of %s" % sorted(PREC))
+    d = net.desc(precision)
     if not noalloc:
         if workspace is None:
             ws = lib().fvsrn_train_workspace_size(C.byref(d), n)

@@ -39,11 +39,14 @@ class Trainer:
     next N steps draw their positions in proportion to it. A time-varying
     network keeps one error grid per timestep (the network at that time
     against that timestep's volume), and each timestep's part of the batch
-    is drawn from its own grid."""
+    is drawn from its own grid.
+    ``precision`` "f16" runs the network's forward and backward passes on
+    FP16 MFMA (FP32 master parameters, gradients and Adam)."""
 
     def __init__(self, net: FV.Network, vol, batch: int = 1 << 18, lr_grid: float = 1e-2,
                  lr_mlp: float = 1e-3, betas=(0.9, 0.999), eps: float = 1e-8, seed: int = 0,
-                 grad_weight: float = 0.0, resample_every: int = 0, error_grid: int = 128, per_voxel: int = 8):
+                 grad_weight: float = 0.0, resample_every: int = 0, error_grid: int = 128, per_voxel: int = 8,
+                 precision: str = "f32"):
         assert net.grid_dtype == FV.F32
         assert grad_weight == 0.0 or net.spec.outputs == 4
         if isinstance(vol, torch.Tensor):
@@ -51,6 +54,7 @@ class Trainer:
         self.frames = list(vol)
         assert len(self.frames) >= 1 and (net.spec.K > 1 or len(self.frames) == 1)
         self.net, self.vol, self.batch, self.seed = net, self.frames[0][1], batch, seed
+        self.precision = precision
         dev = net.weights.device
         # points of timestep j occupy rows [bounds[j], bounds[j + 1]) of the
         # batch (multiples of 4 rows keep every slice 16-byte aligned)
@@ -117,7 +121,7 @@ class Trainer:
                 FV.fvsrn_dense_grad_points(v, self.xyz[a:b], out=self.target[a:b], out_grad=self.target_grad[a:b])
         FV.fvsrn_train_step(self.net, self.d_latent, self.d_weights, self.xyz, target=self.target, adam=self.opt,
                             out_loss=self.loss, workspace=self.workspace, times=self.times,
-                            target_grad=self.target_grad, grad_weight=self.grad_weight)
+                            target_grad=self.target_grad, grad_weight=self.grad_weight, precision=self.precision)
         return self.loss
 
     def state_dict(self) -> dict:

@@ -211,9 +211,11 @@ def _train(d, key_times=None, xyz=FAKE, times=None, n=4, target=FAKE, dloss=None
 def test_train_argument_errors():
     L = FV.lib()
     d = _desc()
-    # FP16 latent grids and reduced precision are not trainable
+    # FP16 latent grids and BF16 are not trainable; FP16 trains in L1 mode only
     assert _train(_desc(grid_dtype=1)) == FV.ERR_UNSUPPORTED
-    assert _train(_desc(precision=1)) == FV.ERR_UNSUPPORTED
+    assert _train(_desc(precision=2)) == FV.ERR_UNSUPPORTED
+    assert _train(_desc(precision=1), target=None, dloss=FAKE) == FV.ERR_UNSUPPORTED
+    assert _train(_desc(precision=1)) == FV.ERR_WORKSPACE  # past the precision checks
     # keyframe grids need ascending key times
     dk = _desc(num_keyframes=2)
     assert _train(dk) == FV.ERR_INVALID_ARGUMENT
