@@ -363,7 +363,11 @@ fvsrn_status fvsrn_error_grid(const fvsrn_net_desc* desc, const fvsrn_params* pa
    sums; point i (counter i) takes the voxel v with
    Q_{v-1} <= (r_0 * Q_{G^3-1}) >> 32 < Q_v (with no weight at all,
    v = (r_0 G^3) >> 32) and its position from words 1..3. workspace: device,
-   fvsrn_weighted_points_workspace_size(G) bytes. */
+   fvsrn_weighted_points_workspace_size(G) bytes; it keeps Q after the call.
+   E == NULL draws from the Q already in the workspace (left there by an
+   earlier call with the same G and an error grid, unchanged since): the
+   same positions as passing that grid again, without rebuilding Q -- for
+   the steps between two refreshes of the error grid. */
 fvsrn_status fvsrn_sample_points_weighted(uint64_t seed, uint64_t counter, const float* E, int32_t G, int64_t n,
                                           float* xyz, void* workspace, size_t workspace_bytes, void* stream);
 size_t fvsrn_weighted_points_workspace_size(int32_t G);

@@ -602,7 +602,7 @@ fvsrn_status fvsrn_sample_points_weighted(uint64_t seed, uint64_t counter, const
   g_err[0] = 0;
   if (G < 1 || G > 1024) return fail(FVSRN_ERR_INVALID_ARGUMENT, "G outside [1, 1024]");
   if (n < 0) return fail(FVSRN_ERR_INVALID_ARGUMENT, "n < 0");
-  if (!E || ((uintptr_t)E & 3u)) return fail(FVSRN_ERR_INVALID_ARGUMENT, "E NULL or misaligned");
+  if ((uintptr_t)E & 3u) return fail(FVSRN_ERR_INVALID_ARGUMENT, "E misaligned");
   if (n > 0 && (!xyz || !aligned16(xyz))) return fail(FVSRN_ERR_INVALID_ARGUMENT, "xyz NULL or misaligned");
   const size_t need = weighted_points_workspace_bytes((long long)G * G * G);
   if (!workspace || ((uintptr_t)workspace & 15u) || workspace_bytes < need)

@@ -515,17 +515,21 @@ int launch_weighted_points(uint64_t seed, uint64_t counter, const float* E, int 
   unsigned long long* Q = (unsigned long long*)workspace;
   unsigned long long* S = Q + nv;
   unsigned* emax = (unsigned*)(S + nb);
-  hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, st, emax);
-  int rc = check_launch();
-  if (rc) return rc;
-  hipLaunchKernelGGL(weight_max_kernel, dim3(grid_blocks(nv, 256, device_cus() * 8)), dim3(256), 0, st, E, nv, emax);
-  if ((rc = check_launch())) return rc;
-  hipLaunchKernelGGL(weight_scan_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, st, E, nv, emax, Q, S);
-  if ((rc = check_launch())) return rc;
-  hipLaunchKernelGGL(block_offsets_kernel, dim3(1), dim3(kScanThreads), 0, st, S, nb);
-  if ((rc = check_launch())) return rc;
-  hipLaunchKernelGGL(add_offsets_kernel, dim3(grid_blocks(nv, 256, device_cus() * 8)), dim3(256), 0, st, Q, nv, S);
-  if ((rc = check_launch())) return rc;
+  int rc = 0;
+  if (E) {  // else the prefix sums of an earlier call are in the workspace
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, st, emax);
+    if ((rc = check_launch())) return rc;
+    hipLaunchKernelGGL(weight_max_kernel, dim3(grid_blocks(nv, 256, device_cus() * 8)), dim3(256), 0, st, E, nv,
+                       emax);
+    if ((rc = check_launch())) return rc;
+    hipLaunchKernelGGL(weight_scan_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, st, E, nv, emax, Q, S);
+    if ((rc = check_launch())) return rc;
+    hipLaunchKernelGGL(block_offsets_kernel, dim3(1), dim3(kScanThreads), 0, st, S, nb);
+    if ((rc = check_launch())) return rc;
+    hipLaunchKernelGGL(add_offsets_kernel, dim3(grid_blocks(nv, 256, device_cus() * 8)), dim3(256), 0, st, Q, nv,
+                       S);
+    if ((rc = check_launch())) return rc;
+  }
   if (n == 0) return 0;
   hipLaunchKernelGGL(weighted_points_kernel, dim3(grid_blocks(n, 256, device_cus() * 16)), dim3(256), 0, st,
                      (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)counter, (uint32_t)(counter >> 32), Q, G, nv,

@@ -420,16 +420,24 @@ def fvsrn_error_grid(net: "Network", vol: torch.Tensor, xyz: torch.Tensor, per_v
     return out
 
 
-def fvsrn_sample_points_weighted(seed: int, counter: int, E: torch.Tensor, G: int, n: int, out=None,
+def fvsrn_sample_points_weighted(seed: int, counter: int, E: Optional[torch.Tensor], G: int, n: int, out=None,
                                  workspace=None, stream=None):
-    """n positions drawn in proportion to the error grid E [G^3] (Sec. 5.4)."""
-    check_tensor(E, "E", numel=G ** 3)
+    """n positions drawn in proportion to the error grid E [G^3] (Sec. 5.4).
+    E None draws from the prefix sums an earlier call left in ``workspace``
+    (same G, the grid unchanged since)."""
+    if E is None:
+        if workspace is None:
+            raise FvsrnArgumentError("E None needs the workspace of an earlier call")
+        dev = workspace.device
+    else:
+        check_tensor(E, "E", numel=G ** 3)
+        dev = E.device
     if out is None:
-        out = torch.empty((n, 3), dtype=torch.float32, device=E.device)
-    check_tensor(out, "out", shape=(n, 3), device=E.device)
+        out = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    check_tensor(out, "out", shape=(n, 3), device=dev)
     if workspace is None:
-        workspace = torch.empty(lib().fvsrn_weighted_points_workspace_size(G), dtype=torch.uint8, device=E.device)
-    check_tensor(workspace, "workspace", dtype=torch.uint8, device=E.device)
+        workspace = torch.empty(lib().fvsrn_weighted_points_workspace_size(G), dtype=torch.uint8, device=dev)
+    check_tensor(workspace, "workspace", dtype=torch.uint8, device=dev)
     _check(lib().fvsrn_sample_points_weighted(seed, counter, _ptr(E), G, n, _ptr(out), _ptr(workspace),
                                               workspace.numel(), _stream(stream)), "fvsrn_sample_points_weighted")
     return out

@@ -87,8 +87,11 @@ class Trainer:
             self.E_all = torch.empty((len(self.frames), self.G ** 3), dtype=torch.float32, device=dev)
             self.E = self.E_all[0]
             self.E_ready = False
-            self.sample_ws = torch.empty(FV.lib().fvsrn_weighted_points_workspace_size(self.G), dtype=torch.uint8,
-                                         device=dev)
+            # one sampling workspace per timestep: its prefix sums are built
+            # from the error grid once per refresh and reused until the next
+            wsz = FV.lib().fvsrn_weighted_points_workspace_size(self.G)
+            self.sample_ws = [torch.empty(wsz, dtype=torch.uint8, device=dev) for _ in self.frames]
+            self.cdf_fresh = False
 
     def update_error_grid(self):
         """Measure the error grid of the current network at every timestep
@@ -98,6 +101,7 @@ class Trainer:
             FV.fvsrn_error_grid(self.net, v, self.err_xyz, self.per_voxel, t, out=self.E_all[j],
                                 scratch=self.err_scratch)
         self.E_ready = True
+        self.cdf_fresh = False
 
     def step(self) -> torch.Tensor:
         """One training step; returns the L1 loss of the batch (device scalar)."""
@@ -109,8 +113,10 @@ class Trainer:
             T = len(self.frames)
             for j in range(T):
                 a, b = self.bounds[j], self.bounds[j + 1]
-                FV.fvsrn_sample_points_weighted(self.seed, self.opt["step"] * T + j, self.E_all[j], self.G, b - a,
-                                                out=self.xyz[a:b], workspace=self.sample_ws)
+                FV.fvsrn_sample_points_weighted(self.seed, self.opt["step"] * T + j,
+                                                self.E_all[j] if not self.cdf_fresh else None, self.G, b - a,
+                                                out=self.xyz[a:b], workspace=self.sample_ws[j])
+            self.cdf_fresh = True
         else:
             FV.fvsrn_sample_points(self.seed, self.opt["step"], self.batch, out=self.xyz)
         for j, (_, v) in enumerate(self.frames):

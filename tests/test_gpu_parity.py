@@ -1106,10 +1106,16 @@ def test_weighted_points_bit_exact(FV):
     E[rng.random(G ** 3) < 0.3] = 0.0
     E[:5] = -1.0
     cases = [E, np.zeros(G ** 3, np.float32), np.where(np.arange(G ** 3) == 777, 0.5, 0.0).astype(np.float32)]
+    ws = torch.empty(FV.lib().fvsrn_weighted_points_workspace_size(G), dtype=torch.uint8, device="cuda")
+    r2 = _philox_words(n, seed, counter + 7)
     for Ec in cases:
-        got = FV.fvsrn_sample_points_weighted(seed, counter, torch.from_numpy(Ec).cuda(), G, n).cpu().numpy()
+        got = FV.fvsrn_sample_points_weighted(seed, counter, torch.from_numpy(Ec).cuda(), G, n,
+                                              workspace=ws).cpu().numpy()
         want = O.weighted_points(Ec, G, r)
         assert np.array_equal(got, want)
+        # E None: the prefix sums kept in the workspace serve the next draws
+        got = FV.fvsrn_sample_points_weighted(seed, counter + 7, None, G, n, workspace=ws).cpu().numpy()
+        assert np.array_equal(got, O.weighted_points(Ec, G, r2))
     # the empirical voxel frequencies follow the weights
     got = FV.fvsrn_sample_points_weighted(seed, counter + 1, torch.from_numpy(E).cuda(), G, 1 << 20).cpu().numpy()
     idx = np.clip(((got + 1) * G / 2).astype(np.int64), 0, G - 1)
