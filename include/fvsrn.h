@@ -69,11 +69,10 @@ typedef enum { FVSRN_ACT_SINE = 0, FVSRN_ACT_SNAKEALT = 1, FVSRN_ACT_IDENTITY = 
    L in {4, 8}, c in {32, 48, 64} with 1 <= H <= 8; 2 <= R <= 512 with one
    keyframe grid (R^3 F elements) below 2^31 bytes; 1 <= K <= 64. Every
    (c, F, L) is compiled for the sine activation, the unshaded render, point
-   densities and forward-mode gradients (BF16 networks: unshaded and
-   densities), and training for c in {32, 48}; the other activations,
-   gradient modes, time encodings and Fourier matrices are compiled for
-   c in {32, 48} with (F, L) = (8, 4) or (16, 8). A shape outside these
-   returns FVSRN_ERR_UNSUPPORTED. */
+   densities and forward-mode gradients, and training for c in {32, 48}; the
+   other activations, gradient modes, time encodings and Fourier matrices are
+   compiled for c in {32, 48} with (F, L) = (8, 4) or (16, 8). A shape
+   outside these returns FVSRN_ERR_UNSUPPORTED. */
 typedef struct {
   int32_t grid_res;      /* R: latent vertices per axis */
   int32_t grid_channels; /* F: latent channels */
@@ -102,17 +101,17 @@ typedef struct {
                             sin and cos blocks hold sin / cos(row_j . p) (Sec. 3; random
                             Fourier features draw the entries from N(0, (2 pi sigma)^2)).
                             Read during the call. Built for the sine activation without a
-                            time encoding: the unshaded render and point densities
-                            (FP32/FP16/BF16), forward-mode gradients and Phong shading
-                            from them (FP32/FP16), and training. */
+                            time encoding: the unshaded render and point densities,
+                            forward-mode gradients and Phong shading from them
+                            (FP32/FP16/BF16), and training. */
 } fvsrn_net_desc;
 
 /* Time encodings (Sec. 8): the latent grids are blended in time in every case;
    DIRECT adds tau as one input, FOURIER adds sin and cos of pi 2^k tau for
    k = 0..3 (8 inputs), BOTH adds tau then the 8 Fourier inputs. Networks with a
    time input are built for the sine activation: the unshaded render and point
-   densities (FP32/FP16/BF16), forward-mode gradients and Phong shading from
-   them (FP32/FP16; the time inputs have no position derivative), and
+   densities, forward-mode gradients and Phong shading from them
+   (FP32/FP16/BF16; the time inputs have no position derivative), and
    training. */
 typedef enum {
   FVSRN_TIME_LATENT_ONLY = 0,
@@ -201,8 +200,7 @@ typedef struct {
    [0]/[2] is the occupancy of the matrix tiles). A wave marches 64 rays
    without shading, 16 with forward-mode gradients and 8 with central
    differences. Phong shading needs the density gradient, obtained as
-   march->grad_mode selects (Sec. 6). Forward mode and central differences
-   are built for FP32/FP16 networks, the adjoint for FP32/FP16/BF16 ones
+   march->grad_mode selects (Sec. 6), for FP32, FP16 and BF16 networks
    (central differences, predicted gradients and the adjoint for the sine
    activation with the octave Fourier features and no time input; the
    adjoint of an FP32 network whose weight fragments, forward and transposed,

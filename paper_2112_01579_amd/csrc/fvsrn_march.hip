@@ -25,8 +25,8 @@ struct Entry {
   }
 };
 
-// Gradient modes are compiled for FP32 and FP16 networks; central differences
-// for the sine activation only.
+// Gradient modes are compiled for every precision; central differences and
+// predicted gradients for the sine activation only.
 
 // The FP16 network has separate instantiations for FP32 (generic), FP16 and
 // uint8 latent grids.
@@ -83,11 +83,9 @@ int FV_PASTE(launch_render_p, FVSRN_PREC)(const NetDev& nd, const TFDev& tf, con
   FV_ALL(X)
   FV_ALL_PRED(X)
   FV_NETS_EXT(X, kShadeNone)
-#if FVSRN_PREC != 2
   FV_ALL_GRAD(X)
   FV_ALL_FD(X)
   FV_NETS_EXT(X, kShadeFwd)
-#endif
 #undef X
   return 1;
 }
@@ -108,10 +106,8 @@ int FV_PASTE(launch_points_p, FVSRN_PREC)(const NetDev& nd, const float* xyz, lo
     return Entry<C_, F_, L_, ACT_, MODE_, GK_>::points(nd, xyz, n, key, key_w, out_d, out_g, st);
   FV_ALL(X)
   FV_NETS_EXT(X, kShadeNone)
-#if FVSRN_PREC != 2
   FV_ALL_GRAD(X)
   FV_NETS_EXT(X, kShadeFwd)
-#endif
 #undef X
   return 1;
 }

@@ -41,7 +41,7 @@ constexpr int max_waves() {
   if (MODE == kShadeAdj) return 8;
   if (MODE == kShadeFwd) return (CF::P == kF16 && CF::C == 32 && CF::G16) ? 12 : 8;
   if (MODE == kShadeFD) {
-    if (CF::F == 16 && (CF::C == 48 || (CF::P == kF16 && !CF::G16))) return 8;
+    if (CF::F == 16 && (CF::C == 48 || (CF::P != kF32 && !CF::G16))) return 8;
     return (CF::G16 && CF::C == 32) ? 16 : 12;
   }
   // FP32 c = 48 network with F = 16: the FP64 sample positions need a few

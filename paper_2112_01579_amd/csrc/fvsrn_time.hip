@@ -1,9 +1,9 @@
 // Networks with a time encoding of their input (Sec. 8: the normalised time
 // as a direct input, its Fourier features, or both), compiled once per
 // precision with FVSRN_PREC = 0 FP32, 1 FP16 or 2 BF16, sine activation: the
-// unshaded render and point densities, and for FP32/FP16 forward-mode density
-// gradients and Phong shading from them (the time inputs do not depend on the
-// position, so their tangent columns are zero).
+// unshaded render and point densities, forward-mode density gradients and
+// Phong shading from them (the time inputs do not depend on the position, so
+// their tangent columns are zero).
 #include "fvsrn_march.hpp"
 
 #ifndef FVSRN_PREC
@@ -20,17 +20,13 @@ struct TimeEntry {
   static int render(const NetDev& nd, const TFDev& tf, const ViewBatch& vb, const MarchDev& m, float* out,
                     unsigned long long* stats, hipStream_t st) {
     if (!m.phong) return launch_render_t<CF, kShadeNone>(nd, tf, vb, m, out, stats, st);
-#if FVSRN_PREC != 2
     if (m.grad_mode == 0) return launch_render_t<CF, kShadeFwd>(nd, tf, vb, m, out, stats, st);
-#endif
     return 1;
   }
   static int points(const NetDev& nd, const float* xyz, long long n, int key, float key_w, float* out_d,
                     float* out_g, int gmode, hipStream_t st) {
     if (!out_g) return launch_points_t<CF, kShadeNone>(nd, xyz, n, key, key_w, out_d, nullptr, st);
-#if FVSRN_PREC != 2
     if (gmode == 0) return launch_points_t<CF, kShadeFwd>(nd, xyz, n, key, key_w, out_d, out_g, st);
-#endif
     return 1;
   }
 };

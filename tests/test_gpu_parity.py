@@ -559,7 +559,8 @@ def test_grad_points(FV, spec_name):
     gnet, onet = _nets(FV, spec, 31)
     xyz = I.uniform_points(16 * 41 + 7, 9, -0.999, 0.999)
     dref, gref = O.grad_points(onet, xyz)
-    for prec, dtol, gtol in (("f32", FP32_TOL, GRAD32_TOL), ("f16", FP16_TOL, GRAD16_TOL)):
+    for prec, dtol, gtol in (("f32", FP32_TOL, GRAD32_TOL), ("f16", FP16_TOL, GRAD16_TOL),
+                             ("bf16", BF16_TOL, GRADBF16_TOL)):
         d, g = FV.fvsrn_grad_points(gnet, torch.from_numpy(xyz).cuda(), 0.0, prec)
         d, g = d.cpu().numpy(), g.cpu().numpy()
         derr, gerr = np.abs(d - dref).max(), _grad_err(g, gref)
@@ -600,7 +601,7 @@ def test_grad_points_edge_sizes(FV):
         assert _grad_err(g.cpu().numpy(), gref) <= GRAD32_TOL
 
 
-@pytest.mark.parametrize("prec", ["f32", "f16"])
+@pytest.mark.parametrize("prec", ["f32", "f16", "bf16"])
 def test_phong_render_central_differences(FV, prec):
     """Phong shading from central differences of the network (Sec. 6: seven
     evaluations per sample), c = 32 and c = 48 networks, ragged views. The
@@ -620,13 +621,13 @@ def test_phong_render_central_differences(FV, prec):
         img = FV.fvsrn_render(gnet, tf, cams, m, prec, stats=stats).cpu().numpy()
         err = np.abs(img - ref).max()
         _report("phong FD c=%d %s" % (spec.c, prec), err)
-        assert err <= (PHONG32_TOL if prec == "f32" else FP16_TOL)
+        assert err <= {"f32": PHONG32_TOL, "f16": FP16_TOL, "bf16": BF16_TOL}[prec]
         assert abs(stats[0].item() - ns) <= 0.001 * ns
         # eight evaluation lanes per ray sample
         assert stats[2].item() % 8 == 0
 
 
-@pytest.mark.parametrize("prec,tol", [("f32", PHONG32_TOL), ("f16", FP16_TOL)])
+@pytest.mark.parametrize("prec,tol", [("f32", PHONG32_TOL), ("f16", FP16_TOL), ("bf16", BF16_TOL)])
 def test_phong_render(FV, prec, tol):
     """shaded network (64^3 x 16 grid, 4 x 48) with headlight Phong from
     the forward-mode gradient, on a ragged small view."""
@@ -975,8 +976,8 @@ def test_time_encoding_eval_and_render(FV, te):
 def test_time_encoding_and_fourier_matrix_gradients(FV, kind):
     """Forward-mode density gradients and Phong shading of networks with a
     time input or a Fourier matrix (the time inputs have no position
-    derivative; a matrix row j contributes 2 pi row_ja cos / -sin), FP32 and
-    FP16, against the oracle's forward mode."""
+    derivative; a matrix row j contributes 2 pi row_ja cos / -sin), FP32,
+    FP16 and BF16, against the oracle's forward mode."""
     if kind == "fourier_matrix":
         spec = I.NetSpec(R=10, F=8, L=4, c=32, H=3, K=2)
         fm = I.random_fourier_matrix(spec.L, 1.0, 3)
@@ -989,7 +990,8 @@ def test_time_encoding_and_fourier_matrix_gradients(FV, kind):
     xyz = I.uniform_points(16 * 19 + 3, 7, -0.99, 0.99)
     for t in (0.3, 2.5):
         dref, gref = O.grad_points(onet, xyz, t)
-        for prec, dtol, gtol in (("f32", FP32_TOL, GRAD32_TOL), ("f16", FP16_TOL, GRAD16_TOL)):
+        for prec, dtol, gtol in (("f32", FP32_TOL, GRAD32_TOL), ("f16", FP16_TOL, GRAD16_TOL),
+                                 ("bf16", BF16_TOL, GRADBF16_TOL)):
             d, g = FV.fvsrn_grad_points(gnet, torch.from_numpy(xyz).cuda(), t, prec)
             derr, gerr = np.abs(d.cpu().numpy() - dref).max(), _grad_err(g.cpu().numpy(), gref)
             _report("grad %s t=%.1f %s density" % (kind, t, prec), derr)
@@ -998,7 +1000,7 @@ def test_time_encoding_and_fourier_matrix_gradients(FV, kind):
     cams = [dataclasses.replace(c, time=0.8) for c in I.orbit_cameras(1, 17, 12)]
     m = I.March(step=1 / 96, ert_eps=0.0, phong=True)
     ref, _ = O.render(O.Field(net=onet), I.ramp_tf(), cams, m)
-    for prec, tol in (("f32", PHONG32_TOL), ("f16", FP16_TOL)):
+    for prec, tol in (("f32", PHONG32_TOL), ("f16", FP16_TOL), ("bf16", BF16_TOL)):
         img = FV.fvsrn_render(gnet, I.ramp_tf(), cams, m, prec).cpu().numpy()
         err = np.abs(img - ref).max()
         _report("phong %s %s" % (kind, prec), err)
@@ -1006,13 +1008,14 @@ def test_time_encoding_and_fourier_matrix_gradients(FV, kind):
 
 
 def test_time_encoding_limits(FV):
-    """Central-difference, predicted and adjoint gradients, BF16 shading and
-    non-sine activations are not compiled for time-encoded networks."""
+    """Central-difference, predicted and adjoint gradients and non-sine
+    activations are not compiled for time-encoded networks."""
     spec = I.NetSpec(R=8, F=8, L=4, c=32, H=2, K=2, time_enc=1)
     gnet, _ = _nets(FV, spec, 3, key_times=(0.0, 1.0))
     xyz = torch.from_numpy(I.uniform_points(8, 1)).cuda()
     cams = I.orbit_cameras(1, 8, 8)
-    for call in (lambda: FV.fvsrn_render(gnet, I.ramp_tf(), cams, I.March(step=0.1, phong=True), "bf16"),
+    fd = I.March(step=0.1, phong=True, grad_mode=1, fd_step=1 / 32)
+    for call in (lambda: FV.fvsrn_render(gnet, I.ramp_tf(), cams, fd, "bf16"),
                  lambda: FV.fvsrn_render(gnet, I.ramp_tf(), cams, I.March(step=0.1, phong=True, grad_mode=3), "f32"),
                  lambda: FV.fvsrn_grad_points(gnet, xyz, 0.5, "f32", mode="adjoint")):
         with pytest.raises(FV.FvsrnError) as e:
