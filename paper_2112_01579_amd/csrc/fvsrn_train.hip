@@ -183,13 +183,16 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
   // reached through a branch was issued without the wait states the result
   // needs and stored a partly written tile.) The first chunk's load reads
   // stale workspace and is discarded by the select.
-  auto add_tile = [&](int tile, f4 v) {
-    f4* dst = reinterpret_cast<f4*>(slice + tile * 256) + lane;
-    const f4 old = *dst;
+  // A layer's running tile sums are loaded together before its gradient
+  // MFMAs, so the loads are in flight meanwhile.
+  auto load_tiles = [&](int t0, int cnt, f4* old) {
+    for (int k = 0; k < cnt; ++k) old[k] = reinterpret_cast<const f4*>(slice + (t0 + k) * 256)[lane];
+  };
+  auto put_tile = [&](int tile, f4 old, f4 v) {
     f4 r;
 #pragma unroll
     for (int j = 0; j < 4; ++j) r[j] = first ? v[j] : old[j] + v[j];
-    *dst = r;
+    reinterpret_cast<f4*>(slice + tile * 256)[lane] = r;
   };
   for (long long c = wave; c < nchunks; c += n_waves) {
     // lane l < S owns point c * S + l
@@ -294,6 +297,8 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
     wave_lds_sync();
     // ---------------- output layer weights: dW_H[o][k] = sum_s dy[o][s] h[k][s]
     const float* alast = abuf + (H - 1) * S * AS;
+    f4 oldo[MT];
+    load_tiles(TC::tile_out(H, 0), MT, oldo);
 #pragma unroll
     for (int nk = 0; nk < MT; ++nk) {
       f4 dw = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -304,7 +309,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
         const float b = act_el<ACT, false>(alast[s * AS + 16 * nk + nn], value_role());
         dw = PR::mma(a, b, dw);
       }
-      add_tile(TC::tile_out(H, nk), dw);
+      put_tile(TC::tile_out(H, nk), oldo[nk], dw);
     }
     // ---------------- backward through the activated layers
     f4 dh[NTC][MT];  // d L / d h_i in D layout, per N-tile
@@ -324,6 +329,14 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
       }
     }
     for (int i = H - 1; i >= 0; --i) {
+      constexpr int NW = MT * (TC::NK0 > MT ? TC::NK0 : MT);
+      f4 oldw[NW], oldb[MT];
+      if (i == 0) {
+        load_tiles(TC::tile_l0(0, 0), MT * TC::NK0, oldw);
+      } else {
+        load_tiles(TC::tile_h(H, i, 0, 0), MT * MT, oldw);
+        load_tiles(TC::tile_bias(H, i, 0), MT, oldb);
+      }
       const float* ai = abuf + i * S * AS;
       // delta_i = d L / d x_i = (d L / d h_i) * act'(x_i), x = W h + b in
       // world units (a_i holds x / (2 pi) for the periodic activations)
@@ -345,7 +358,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
       if (i >= 1) {
         // partial bias gradient of this lane's 4 samples (summed over lanes by the reduction)
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) add_tile(TC::tile_bias(H, i, mt), dbias[mt]);
+        for (int mt = 0; mt < MT; ++mt) put_tile(TC::tile_bias(H, i, mt), oldb[mt], dbias[mt]);
       }
       wave_lds_sync();
       // dW_i = delta_i h_i^T over the chunk's samples
@@ -363,7 +376,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
               const float b = col < G::KROW ? feat[s * G::ROW + col] : 0.0f;
               dw = PR::mma(a, b, dw);
             }
-            add_tile(TC::tile_l0(mo, nk), dw);
+            put_tile(TC::tile_l0(mo, nk), oldw[mo * TC::NK0 + nk], dw);
           }
       } else {
         const float* ap = abuf + (i - 1) * S * AS;
@@ -379,7 +392,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
               const float b = act_el<ACT, false>(ap[s * AS + 16 * nk + nn], value_role());
               dw = PR::mma(a, b, dw);
             }
-            add_tile(TC::tile_h(H, i, mo, nk), dw);
+            put_tile(TC::tile_h(H, i, mo, nk), oldw[mo * MT + nk], dw);
           }
       }
       if (i >= 1) {
@@ -578,14 +591,18 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
   f4 dbo_acc = zero;
   const long long nchunks = (n + S - 1) / S;
   bool first = true;
-  // branch-free slice update (see fwd_bwd_kernel)
-  auto add_tile = [&](int tile, f4 v) {
-    f4* dst = reinterpret_cast<f4*>(slice + tile * 256) + lane;
-    const f4 old = *dst;
+  // Slice updates: a layer's running tile sums are loaded together before
+  // its gradient MFMAs (the loads are in flight meanwhile), then each sum is
+  // stored branch-free from a VALU select (see fwd_bwd_kernel); the first
+  // chunk's loads read stale workspace and are discarded by the select.
+  auto load_tiles = [&](int t0, int cnt, f4* old) {
+    for (int k = 0; k < cnt; ++k) old[k] = reinterpret_cast<const f4*>(slice + (t0 + k) * 256)[lane];
+  };
+  auto put_tile = [&](int tile, f4 old, f4 v) {
     f4 r;
 #pragma unroll
     for (int j = 0; j < 4; ++j) r[j] = first ? v[j] : old[j] + v[j];
-    *dst = r;
+    reinterpret_cast<f4*>(slice + tile * 256)[lane] = r;
   };
   for (long long c = wave; c < nchunks; c += n_waves) {
     const long long idx = c * S + lane;
@@ -703,6 +720,9 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
     wave_lds_sync();
     // ---------------- output weights: dW_H[o][k] = sum_s dy[o][s] h_{H-1}[k][s]
     {
+      f4 old[MT];
+#pragma unroll
+      for (int nk = 0; nk < MT; ++nk) old[nk] = reinterpret_cast<const f4*>(slice + T32::tile_out(H, nk) * 256)[lane];
       const E* hl = hbuf + (H - 1) * C * HSTR;
       VT ay;
 #pragma unroll
@@ -710,7 +730,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
 #pragma unroll
       for (int nk = 0; nk < MT; ++nk) {
         const VT b = *reinterpret_cast<const VT*>(hl + (16 * nk + nn) * HSTR + 4 * g);
-        add_tile(T32::tile_out(H, nk), PR::mmt(ay, b, zero) * inv_gs);
+        put_tile(T32::tile_out(H, nk), old[nk], PR::mmt(ay, b, zero) * inv_gs);
       }
     }
     // ---------------- backward
@@ -728,6 +748,15 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
       }
     }
     for (int i = H - 1; i >= 0; --i) {
+      // this layer's running sums: dW_i, and for i >= 1 the bias partials
+      constexpr int NW = MT * (T32::NK0 > MT ? T32::NK0 : MT);
+      f4 oldw[NW], oldb[MT];
+      if (i == 0) {
+        load_tiles(T32::tile_l0(0, 0), MT * T32::NK0, oldw);
+      } else {
+        load_tiles(T32::tile_h(H, i, 0, 0), MT * MT, oldw);
+        load_tiles(T32::tile_bias(H, i, 0), MT, oldb);
+      }
       const h4* ad = reinterpret_cast<const h4*>(actd + i * TH::ACTD);
       // delta_i = (d L / d h_i) * act'(a_i), world units
       float dv[MT][4];
@@ -741,7 +770,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
           da[j] = dv[mt][j];
           dbuf[(16 * mt + 4 * g + j) * HSTR + nn] = (E)dv[mt][j];
         }
-        if (i >= 1) add_tile(T32::tile_bias(H, i, mt), da * inv_gs);
+        if (i >= 1) put_tile(T32::tile_bias(H, i, mt), oldb[mt], da * inv_gs);
       }
       VA bD[HS32];
       VT bDT;
@@ -772,7 +801,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
 #pragma unroll
           for (int mo = 0; mo < MT; ++mo) {
             const VT a = *reinterpret_cast<const VT*>(dbuf + (16 * mo + nn) * HSTR + 4 * g);
-            add_tile(T32::tile_l0(mo, nk), PR::mmt(a, b, zero) * cs);
+            put_tile(T32::tile_l0(mo, nk), oldw[mo * T32::NK0 + nk], PR::mmt(a, b, zero) * cs);
           }
         }
       } else {
@@ -783,7 +812,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
 #pragma unroll
           for (int mo = 0; mo < MT; ++mo) {
             const VT a = *reinterpret_cast<const VT*>(dbuf + (16 * mo + nn) * HSTR + 4 * g);
-            add_tile(T32::tile_h(H, i, mo, nk), PR::mmt(a, b, zero) * inv_gs);
+            put_tile(T32::tile_h(H, i, mo, nk), oldw[mo * MT + nk], PR::mmt(a, b, zero) * inv_gs);
           }
         }
       }
