@@ -1,5 +1,7 @@
 // Training step of the fV-SRN (world-space fitting with L1 loss and Adam,
-// Sec. 3 and Sec. 5), FP32 throughout.
+// Sec. 3 and Sec. 5): FP32 parameters, gradients and Adam; the network's
+// forward and backward passes in FP32 (fwd_bwd_kernel) or FP16
+// (fwd_bwd_h_kernel, further below) MFMA.
 //
 // fwd_bwd_kernel: each wave takes chunks of S = 16 points (fixed,
 // grid-independent assignment: chunk c goes to wave c mod n_waves; one MFMA
