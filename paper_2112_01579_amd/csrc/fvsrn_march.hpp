@@ -26,20 +26,22 @@ enum { kShadeNone = 0, kShadeFwd = 1, kShadeFD = 2, kShadePred = 3, kShadeAdj = 
 // Waves per workgroup cap (sets the VGPR budget through the launch bounds):
 // value-mode networks with the packed FP16 latent path fit 4 waves per SIMD
 // (<= 128 VGPRs), other value-mode networks 3 (<= 168). Forward mode: 3 for
-// the c = 32 FP16 network on a packed grid (a few spills outside the hot
-// loop; measured 9% faster than 2), 2 otherwise (c = 48 spills inside the
-// sample loop at 168 VGPRs and was measured 15% slower).
+// the c = 32 and c = 48 FP16 networks on a packed grid (spills of a few
+// registers; with the persistent launch the third wave hides more than the
+// spills cost: c = 48 measured 122 -> 106 ms per frame), 2 otherwise.
 // Central differences add the neighbour offsets and the gradient gather to
 // the value-mode network; with F = 16 channels gathered in FP32 (c = 48, or
 // an FP16 network on an FP32 grid) that needs 2 waves per SIMD, c = 48 with
 // the packed latent path 3. The adjoint keeps every layer's activation
-// derivatives of two N-tiles in registers: 2 waves per SIMD.
+// derivatives of two N-tiles in registers: 3 waves per SIMD for the c = 32
+// FP16 network on a packed grid (151 -> 138 ms on the study views), 2
+// otherwise (c = 48 measured 47 -> 48 ms at 3).
 // FP32 networks add the FP64 ray of their sample positions (about 10
 // registers).
 template <class CF, int MODE, bool POINTS = false>
 constexpr int max_waves() {
-  if (MODE == kShadeAdj) return 8;
-  if (MODE == kShadeFwd) return (CF::P == kF16 && CF::C == 32 && CF::G16) ? 12 : 8;
+  if (MODE == kShadeAdj) return (CF::P == kF16 && CF::C == 32 && CF::G16) ? 12 : 8;
+  if (MODE == kShadeFwd) return (CF::P == kF16 && CF::C <= 48 && CF::G16) ? 12 : 8;
   if (MODE == kShadeFD) {
     if (CF::F == 16 && (CF::C == 48 || (CF::P != kF32 && !CF::G16))) return 8;
     return (CF::G16 && CF::C == 32) ? 16 : 12;
