@@ -953,8 +953,10 @@ __global__ void gather_kernel(int H, int NO, const float* partial, int n_groups,
         }
       }
     }
-    // sequential adds in a fixed order; the unrolled loads of a group's terms
-    // are issued together (the loss and the output biases have 64 per group)
+    // sums of 16 or 64 terms per group (the hidden and output biases, the
+    // loss) are gather_long_kernel's
+    if (count > 1) continue;
+    // sequential adds in a fixed order
     float s = 0.0f;
     for (int g = 0; g < n_groups; ++g) {
       const float* pg = partial + (size_t)g * SL + base;
@@ -965,6 +967,52 @@ __global__ void gather_kernel(int H, int NO, const float* partial, int n_groups,
       if (out_loss) *out_loss = s * loss_scale;
     } else {
       d_weights[j] = s;
+    }
+  }
+}
+
+// The weights whose gradient sums many partials per group, one wave each:
+// the hidden-layer biases (16 lane partials per group), the output biases and
+// the loss (64). Lane l adds its term over the groups in order, then the wave
+// adds the lanes in a fixed butterfly, so the result is bitwise reproducible.
+template <int C, int F, int L, int ACT, int TE, int FM>
+__global__ __launch_bounds__(64) void gather_long_kernel(int H, int NO, const float* partial, int n_groups,
+                                                          float* d_weights, float* out_loss, float loss_scale) {
+  using TC = TrainCfg<C, F, L, ACT, TE, FM>;
+  using G = typename TC::G;
+  const int e = blockIdx.x, lane = threadIdx.x;
+  const int SL = TC::slice(H);
+  const long long first_bias = (long long)C * G::K0IN + C;  // W_1 in the packed weights
+  const long long per = (long long)C * C + C;
+  int base, count, stride;
+  long long j;  // destination weight (-1: the loss)
+  if (e < (H - 1) * C) {
+    const int i = 1 + e / C, o = e % C;
+    j = first_bias + (long long)(i - 1) * per + (long long)C * C + o;
+    base = TC::tile_bias(H, i, o / 16) * 256 + (16 * ((o % 16) / 4)) * 4 + o % 4;
+    count = 16;
+    stride = 4;
+  } else if (e < (H - 1) * C + NO) {
+    const int o = e - (H - 1) * C;
+    j = first_bias + (long long)(H - 1) * per + (long long)NO * C + o;
+    base = TC::tiles(H) * 256 + 64 * o;
+    count = 64;
+    stride = 1;
+  } else {
+    j = -1;
+    base = TC::tiles(H) * 256 + 256;
+    count = 64;
+    stride = 1;
+  }
+  float a = 0.0f;
+  if (lane < count)
+    for (int g = 0; g < n_groups; ++g) a += partial[(size_t)g * SL + base + lane * stride];
+  for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+  if (lane == 0) {
+    if (j < 0) {
+      if (out_loss) *out_loss = a * loss_scale;
+    } else {
+      d_weights[j] = a;
     }
   }
 }
@@ -1300,8 +1348,12 @@ struct TrainEntry {
     if (rc) return rc;
     const long long nwts = (long long)C * TC::G::K0IN + C + (long long)(H - 1) * (C * C + C) +
                            (long long)nd.NO * (C + 1);
+    const float loss_scale = target && n > 0 ? 1.0f / (float)n : 1.0f;
     hipLaunchKernelGGL((gather_kernel<C, F, L, ACT, TE, FM>), dim3(grid_blocks(nwts + 1, 128, 1024)), dim3(128), 0, st, H,
-                       nd.NO, (const float*)partial, ng, d_weights, out_loss, target && n > 0 ? 1.0f / (float)n : 1.0f);
+                       nd.NO, (const float*)partial, ng, d_weights, out_loss, loss_scale);
+    if ((rc = check_launch())) return rc;
+    hipLaunchKernelGGL((gather_long_kernel<C, F, L, ACT, TE, FM>), dim3((H - 1) * C + nd.NO + 1), dim3(64), 0, st, H,
+                       nd.NO, (const float*)partial, ng, d_weights, out_loss, loss_scale);
     return check_launch();
   }
 };
