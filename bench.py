@@ -202,6 +202,29 @@ def eval_points_only(args, spec, dev):
     print(json.dumps(res))
 
 
+def train_only(args, dev):
+    """2^18-point gradient steps (no sampling, targets or Adam) of the three
+    network shapes in FP32 and FP16: one JSON line of ms per step."""
+    import torch
+    from paper_2112_01579_amd import inputs as I
+    from paper_2112_01579_amd import fvsrn as FV
+    n = 1 << 18
+    xyz = FV.fvsrn_sample_points(I.SEED_TRAIN, 1 << 42, n, device=dev)
+    target = torch.rand(n, device=dev)
+    res = {"metric": "training gradient step, 2^18 uniform points", "unit": "ms"}
+    for sname in ("NET_SMALL", "NET_STUDY", "NET_SHADED"):
+        spec = getattr(I, sname)
+        lat, w = I.net_params(spec, 3)
+        net = FV.Network(spec, lat, w, grid_dtype=FV.F32, device=dev)
+        d_lat, d_w = torch.empty_like(net.latent), torch.empty_like(net.weights)
+        ws = torch.empty(max(FV.fvsrn_train_workspace_size(spec, n), 16), dtype=torch.uint8, device=dev)
+        for prec in ("f32", "f16"):
+            per, _ = time_launches(lambda: FV.fvsrn_train_step(net, d_lat, d_w, xyz, target=target, workspace=ws,
+                                                               precision=prec), args.steps, args.warmup)
+            res["%s_%s_ms" % (sname.lower(), prec)] = float(np.median(per))
+    print(json.dumps(res))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,6 +239,9 @@ def main():
     ap.add_argument("--eval-points-only", action="store_true",
                     help="time only the fused point evaluation of 2^24 uniform points (FP16 and FP32 networks, "
                          "the study network with its initial weights); for profiling that kernel")
+    ap.add_argument("--train-only", action="store_true",
+                    help="time only 2^18-point training gradient steps of the three network shapes in FP32 and FP16; "
+                         "for profiling the training kernels")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the fV-SRN path is single-GPU (rays and points are "
@@ -231,6 +257,9 @@ def main():
     spec = I.NET_STUDY
     if args.eval_points_only:
         eval_points_only(args, spec, dev)
+        return
+    if args.train_only:
+        train_only(args, dev)
         return
     vol = torch.from_numpy(I.gaussian_volume(256, 64, seed=I.SEED_STUDY)).to(dev)
     lat, w = I.net_params(spec, I.SEED_STUDY)
