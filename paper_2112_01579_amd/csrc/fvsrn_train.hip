@@ -138,7 +138,8 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
                                                                             const float* target,
                                                                             const float* target_grad, float gw3,
                                                       const float* dloss, float* dz_out, int* cell_out,
-                                                      int* cell_count, float* ws, int n_waves, float inv_n) {
+                                                      int* cell_count, int* rank_out, float* ws, int n_waves,
+                                                      float inv_n) {
   using TC = TrainCfg<C, F, L, ACT, TE, FM>;
   using CF = typename TC::CF;
   using G = typename TC::G;
@@ -451,7 +452,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
       axis_cell(pz, nd.R, iz, fz);
       const int cell = (iz * (nd.R - 1) + iy) * (nd.R - 1) + ix;
       cell_out[idx] = cell;
-      atomicAdd(cell_count + cell, 1);
+      rank_out[idx] = atomicAdd(cell_count + cell, 1);
       float4* dst = reinterpret_cast<float4*>(dz_out + idx * F);
 #pragma unroll
       for (int q = 0; q < F / 4; ++q)
@@ -554,8 +555,8 @@ __device__ void stage_backward_h(const NetDev& nd, char* p) {
 template <int C, int F, int L, int ACT>
 __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
     NetDev nd, KeyTimes kt, const float* xyz, const float* times, long long n, const float* target,
-    const float* target_grad, float gw3, float* dz_out, int* cell_out, int* cell_count, float* ws, int n_waves,
-    float dscale, float inv_gs) {
+    const float* target_grad, float gw3, float* dz_out, int* cell_out, int* cell_count, int* rank_out, float* ws,
+    int n_waves, float dscale, float inv_gs) {
   using TH = TrainCfgH<C, F, L, ACT>;
   using T32 = typename TH::T32;
   using CF = typename TH::CF;
@@ -851,7 +852,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
       axis_cell(pz, nd.R, iz, fz);
       const int cell = (iz * (nd.R - 1) + iy) * (nd.R - 1) + ix;
       cell_out[idx] = cell;
-      atomicAdd(cell_count + cell, 1);
+      rank_out[idx] = atomicAdd(cell_count + cell, 1);
       float4* dst = reinterpret_cast<float4*>(dz_out + idx * F);
 #pragma unroll
       for (int q = 0; q < F / 4; ++q)
@@ -1039,7 +1040,7 @@ __global__ void adam_kernel(float* p, const float* g, float* m, float* v, long l
 // ------------------------------------------ latent gradient by gathering
 
 // Exclusive prefix sums of the per-cell point counts, off[c] = first sorted
-// position of cell c, off[ncell] = n, cursor a copy of off: blocks of
+// position of cell c, off[ncell] = n, cursor (when given) a copy of off: blocks of
 // kCellBlock consecutive cells are summed (cell_block_sum_kernel), the block
 // sums scanned by one workgroup (cell_block_scan_kernel), then every block
 // scans its own cells from its block's offset (cell_scan_kernel).
@@ -1132,18 +1133,19 @@ __global__ __launch_bounds__(kCellThreads) void cell_scan_kernel(const int* coun
   for (int k = 0; k < kCellItems; ++k) {
     if (base + k < ncell) {
       off[base + k] = run;
-      cursor[base + k] = run;
+      if (cursor) cursor[base + k] = run;
     }
     run += x[k];
   }
   if (off_end && threadIdx.x == 0) *off_end = total;
 }
 
-// Counting sort: point i goes to a free slot of its cell.
-__global__ void bin_points_kernel(const int* cell, long long n, int* cursor, int* order) {
+// Counting sort: point i goes to the slot its cell count gave it when the
+// forward-backward kernel counted it (its rank among the cell's points).
+__global__ void bin_points_kernel(const int* cell, const int* rank, const int* off, long long n, int* order) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
-    order[atomicAdd(cursor + cell[i], 1)] = (int)i;
+    order[off[cell[i]] + rank[i]] = (int)i;
 }
 
 // d_latent[k][v][f] = sum over the points p of the (up to) eight cells
@@ -1241,14 +1243,14 @@ struct TrainEntry {
   }
   static int n_groups(long long n) { return (n_waves(n) + kGroup - 1) / kGroup; }
   // wave slices, then the group partials of the reduction, then the per-point
-  // dL/dz [n][F], cells [n] and sorted order [n], and per cell the point
-  // counts, the offsets (+1) and the sort cursors
+  // dL/dz [n][F], cells [n], sorted order [n] and ranks within the cell [n],
+  // and per cell the point counts and the offsets (+1)
   static size_t slices_bytes(const NetDev& nd, long long n) {
     return ((size_t)(n_waves(n) + n_groups(n)) * TC::slice(nd.H) * sizeof(float) + 15) / 16 * 16;
   }
   static size_t ws_bytes(const NetDev& nd, long long n) {
     const long long ncell = (long long)(nd.R - 1) * (nd.R - 1) * (nd.R - 1);
-    return slices_bytes(nd, n) + (size_t)n * F * 4 + (size_t)n * 8 + (size_t)(3 * ncell + 1 + cell_blocks(ncell)) * 4;
+    return slices_bytes(nd, n) + (size_t)n * F * 4 + (size_t)n * 12 + (size_t)(2 * ncell + 1 + cell_blocks(ncell)) * 4;
   }
   static int run(const NetDev& nd, const KeyTimes& kt, float* latent, float* d_latent, float* d_weights,
                  const float* xyz, const float* times, long long n, const float* target,
@@ -1263,10 +1265,10 @@ struct TrainEntry {
     float* dz = (float*)wsb;
     int* cell = (int*)(wsb + (size_t)n * F * 4);
     int* order = cell + n;
-    int* count = order + n;
+    int* rank = order + n;
+    int* count = rank + n;
     int* off = count + ncell;
-    int* cursor = off + ncell + 1;
-    int* bsum = cursor + ncell;  // cell_blocks(ncell) block sums
+    int* bsum = off + ncell + 1;  // cell_blocks(ncell) block sums
     hipLaunchKernelGGL(fill_kernel, dim3(grid_blocks(ncell, 256, device_cus() * 8)), dim3(256), 0, st, (float*)count,
                        (long long)ncell, 0.0f);  // zero bits: zero counts
     int rc = check_launch();
@@ -1298,15 +1300,15 @@ struct TrainEntry {
         const double gs = std::ldexp(1.0, e);
         hipLaunchKernelGGL((fwd_bwd_h_kernel<C, F, L, ACT>), dim3((nw + wph - 1) / wph), dim3(wph * 64),
                            (size_t)TH::block_bytes(H, wph), st, nd2, kt, xyz, times, n, target, target_grad,
-                           grad_weight / 3.0f, dz, cell, count, (float*)ws, nw, (float)(gs / (double)n),
+                           grad_weight / 3.0f, dz, cell, count, rank, (float*)ws, nw, (float)(gs / (double)n),
                            (float)(1.0 / gs));
         rc = check_launch();
         if (rc) return rc;
       }
     } else if (n > 0) {
       hipLaunchKernelGGL((fwd_bwd_kernel<C, F, L, ACT, TE, FM>), dim3((nw + wpb - 1) / wpb), dim3(wpb * 64), shm, st, nd2,
-                         kt, xyz, times, n, target, target_grad, grad_weight / 3.0f, dloss, dz, cell, count, (float*)ws,
-                         nw, 1.0f / (float)n);
+                         kt, xyz, times, n, target, target_grad, grad_weight / 3.0f, dloss, dz, cell, count, rank,
+                         (float*)ws, nw, 1.0f / (float)n);
       rc = check_launch();
       if (rc) return rc;
     } else {
@@ -1325,11 +1327,11 @@ struct TrainEntry {
       if ((rc = check_launch())) return rc;
     }
     hipLaunchKernelGGL(cell_scan_kernel, dim3(nb), dim3(kCellThreads), 0, st, (const int*)count, ncell,
-                       nb > 1 ? (const int*)bsum : nullptr, off, cursor, nb > 1 ? nullptr : off + ncell);
+                       nb > 1 ? (const int*)bsum : nullptr, off, nullptr, nb > 1 ? nullptr : off + ncell);
     if ((rc = check_launch())) return rc;
     if (n > 0) {
       hipLaunchKernelGGL(bin_points_kernel, dim3(grid_blocks(n, 256, device_cus() * 8)), dim3(256), 0, st,
-                         (const int*)cell, n, cursor, order);
+                         (const int*)cell, (const int*)rank, (const int*)off, n, order);
       if ((rc = check_launch())) return rc;
     }
     // lanes per cell: about one per four points of an average cell, at most 8
