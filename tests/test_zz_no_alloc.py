@@ -2,11 +2,11 @@
 per-GPU workspace, for callers that cannot allocate) against fvsrn_train_step
 with a caller workspace: the same kernels and partition, so the weight
 gradients and the loss agree bit for bit and the latent gradients to the
-rounding of the per-cell summation order. Three calls in a row share the
+rounding of the per-cell summation order. Four calls in a row share the
 static workspace, each on a smaller input than the one before it (the
-study network at 2^18 points with Adam, the same network at a ragged
-batch, then the small network), so stale workspace contents from a larger
-call must not leak into a smaller one."""
+study network at 2^18 points with Adam, the same network at ragged batches
+in FP16 and FP32 network arithmetic, then the small network), so stale
+workspace contents from a larger call must not leak into a smaller one."""
 import numpy as np
 import pytest
 import torch
@@ -31,7 +31,7 @@ def _moments(net):
             "v_weights": z(net.weights)}
 
 
-def _pair(FV, spec, seed, n, adam):
+def _pair(FV, spec, seed, n, adam, prec="f32"):
     """The same step through both entry points on two copies of one network;
     returns (reference, static) tuples of gradients, loss and parameters."""
     lat, w = I.net_params(spec, seed)
@@ -47,19 +47,19 @@ def _pair(FV, spec, seed, n, adam):
         if adam:
             opt = dict(lr_grid=1e-2, lr_mlp=1e-3, step=1, **_moments(net))
         fn = FV.fvsrn_train_step_noalloc if noalloc else FV.fvsrn_train_step
-        fn(net, d_lat, d_w, xyz, target=target, adam=opt, out_loss=loss)
+        fn(net, d_lat, d_w, xyz, target=target, adam=opt, out_loss=loss, precision=prec)
         torch.cuda.synchronize()
         out.append((d_lat, d_w, loss, net.latent.clone(), net.weights.clone()))
     return out
 
 
-@pytest.mark.parametrize("calls", [[("NET_STUDY", 1 << 18, True), ("NET_STUDY", 50_001, False),
-                                    ("NET_SMALL", 4097, True)]])
+@pytest.mark.parametrize("calls", [[("NET_STUDY", 1 << 18, True, "f32"), ("NET_STUDY", 50_001, False, "f16"),
+                                    ("NET_STUDY", 20_001, False, "f32"), ("NET_SMALL", 4097, True, "f32")]])
 def test_train_step_noalloc_matches_workspace_entry(FV, calls):
-    for spec_name, n, adam in calls:
+    for spec_name, n, adam, prec in calls:
         spec = getattr(I, spec_name)
-        print("noalloc call: %s n=%d adam=%s" % (spec_name, n, adam), flush=True)
-        (dl_a, dw_a, l_a, lat_a, w_a), (dl_b, dw_b, l_b, lat_b, w_b) = _pair(FV, spec, 5, n, adam)
+        print("noalloc call: %s n=%d adam=%s %s" % (spec_name, n, adam, prec), flush=True)
+        (dl_a, dw_a, l_a, lat_a, w_a), (dl_b, dw_b, l_b, lat_b, w_b) = _pair(FV, spec, 5, n, adam, prec)
         assert torch.isfinite(dl_b).all() and torch.isfinite(dw_b).all() and torch.isfinite(l_b).all()
         # the weight gradient and the loss are reduced in a fixed order
         assert torch.equal(dw_a, dw_b)
