@@ -29,9 +29,11 @@ struct Entry {
 // predicted gradients for the sine activation only.
 
 // The FP16 network has separate instantiations for FP32 (generic), FP16 and
-// uint8 latent grids.
+// uint8 latent grids, the BF16 network for the generic path and FP16 grids.
 #if FVSRN_PREC == 1
 #define FV_G16S(X, C, F, L, ACT, MODE) X(C, F, L, ACT, MODE, 0) X(C, F, L, ACT, MODE, 1) X(C, F, L, ACT, MODE, 2)
+#elif FVSRN_PREC == 2
+#define FV_G16S(X, C, F, L, ACT, MODE) X(C, F, L, ACT, MODE, 0) X(C, F, L, ACT, MODE, 1)
 #else
 #define FV_G16S(X, C, F, L, ACT, MODE) X(C, F, L, ACT, MODE, 0)
 #endif
@@ -75,7 +77,9 @@ int FV_PASTE(launch_render_p, FVSRN_PREC)(const NetDev& nd, const TFDev& tf, con
   if (m.phong && m.grad_mode == 3) return FV_PASTE(launch_render_adj_p, FVSRN_PREC)(nd, tf, vb, m, out, stats, stream);
   const int mode = !m.phong ? kShadeNone : (m.grad_mode == 1 ? kShadeFD : (m.grad_mode == 2 ? kShadePred : kShadeFwd));
   // packed FP16 gathers for an FP16 network on an FP16 or uint8 grid
-  const int gk = FVSRN_PREC != 1 ? 0 : (nd.grid_u8 ? 2 : (nd.grid_f16 ? 1 : 0));
+  const int gk = FVSRN_PREC == 0 ? 0
+                 : FVSRN_PREC == 2 ? (nd.grid_f16 && !nd.grid_u8 ? 1 : 0)
+                                   : (nd.grid_u8 ? 2 : (nd.grid_f16 ? 1 : 0));
   const hipStream_t st = (hipStream_t)stream;
 #define X(C_, F_, L_, ACT_, MODE_, GK_)                                                           \
   if (nd.C == C_ && nd.F == F_ && nd.L == L_ && nd.act == ACT_ && mode == MODE_ && gk == GK_) \
@@ -99,7 +103,9 @@ int FV_PASTE(launch_points_p, FVSRN_PREC)(const NetDev& nd, const float* xyz, lo
   // gmode 2: a 4-output network's own gradient, from the value-mode kernel
   const int mode = (out_g != nullptr && gmode == 0) ? kShadeFwd : kShadeNone;
   // packed FP16 gathers for an FP16 network on an FP16 or uint8 grid
-  const int gk = FVSRN_PREC != 1 ? 0 : (nd.grid_u8 ? 2 : (nd.grid_f16 ? 1 : 0));
+  const int gk = FVSRN_PREC == 0 ? 0
+                 : FVSRN_PREC == 2 ? (nd.grid_f16 && !nd.grid_u8 ? 1 : 0)
+                                   : (nd.grid_u8 ? 2 : (nd.grid_f16 ? 1 : 0));
   const hipStream_t st = (hipStream_t)stream;
 #define X(C_, F_, L_, ACT_, MODE_, GK_)                                                           \
   if (nd.C == C_ && nd.F == F_ && nd.L == L_ && nd.act == ACT_ && mode == MODE_ && gk == GK_) \

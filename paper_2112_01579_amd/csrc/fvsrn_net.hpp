@@ -16,7 +16,9 @@ namespace fvsrn_detail {
 // GK selects the latent gather of an FP16 network: 0 generic (FP32
 // accumulation, grid type chosen at run time), 1 FP16 grid and 2 uint8 grid,
 // both accumulated in packed FP16 (one gather path per instantiation keeps
-// the register peak down). G16 says that a packed path is used.
+// the register peak down). A BF16 network on an FP16 grid (GK 1) also sums
+// the corners in packed FP16 and rounds the sums to BF16 for its row (FP16
+// keeps three more bits than the row). G16 says that a packed path is used.
 // TE: time encoding of the input (0 latent only, 1 direct, 2 Fourier, 3 both).
 // FM: the Fourier features come from a general matrix (random Fourier
 // features) instead of the octave construction.
@@ -589,7 +591,7 @@ __device__ inline void write_features(typename CF::E* row, const LatentSrc& ls, 
   float v[G::KROW];
 #pragma unroll
   for (int j = 0; j < G::KROW; ++j) v[j] = 0.0f;
-  constexpr bool packed_latent = CF::P == kF16 && CF::G16;
+  constexpr bool packed_latent = CF::G16 && (CF::P == kF16 || (CF::P == kBF16 && CF::GK == 1));
   h2 zh[F / 2];
   LatentColumnH<F> lch;
   if constexpr (packed_latent && CF::GK == 2) {
@@ -711,8 +713,13 @@ __device__ inline void write_features(typename CF::E* row, const LatentSrc& ls, 
         if (q < F / 8) {
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            x[2 * j] = zh[4 * q + j][0];
-            x[2 * j + 1] = zh[4 * q + j][1];
+            if constexpr (CF::P == kF16) {
+              x[2 * j] = zh[4 * q + j][0];
+              x[2 * j + 1] = zh[4 * q + j][1];
+            } else {
+              x[2 * j] = to_e<E>((float)zh[4 * q + j][0]);
+              x[2 * j + 1] = to_e<E>((float)zh[4 * q + j][1]);
+            }
           }
           done = true;
         }
