@@ -85,9 +85,9 @@ typedef struct {
   int32_t precision;     /* network arithmetic: FVSRN_F32 (FP32 MFMA), FVSRN_F16 or
                             FVSRN_BF16 (MFMA with FP32 accumulation). Phases, sigmoid,
                             TF and compositing are FP32 always; the latent
-                            interpolation too, except for an FP16 network on an FP16
-                            grid, which sums the eight corners in packed FP16 (its
-                            input row is rounded to FP16 anyway). */
+                            interpolation too, except for an FP16 or BF16 network on
+                            an FP16 grid, which sums the eight corners in packed FP16
+                            (its input row is rounded to FP16 or BF16 anyway). */
   int32_t num_outputs;   /* 1: the density logit; 4: the logit followed by a predicted
                             density gradient d density / d p (Sec. 6). 0 means 1. The
                             output layer holds W_out [num_outputs][c] then b_out
