@@ -358,17 +358,29 @@ __global__ __launch_bounds__((max_waves<CF, PM, true>() * 64)) void points_kerne
   if constexpr (G::TIN > 0) time_features<CF::TE>(nd.tau, tfe);
   const long long nchunks = (n + PER - 1) / PER;
   const int waves = blockDim.x >> 6;
-  for (long long c = (long long)blockIdx.x * waves + wave; c < nchunks; c += (long long)gridDim.x * waves) {
+  const long long stride = (long long)gridDim.x * waves;
+  // Each chunk's positions are loaded one chunk ahead, after the latent
+  // gather of the chunk before and consumed after its MLP, so that the
+  // HBM read is not in series with the gather it addresses.
+  float nx = 0.0f, ny = 0.0f, nz = 0.0f;
+  auto load_pos = [&](long long cc) {
+    const long long j = cc * PER + (GRAD ? (lane >> 2) : lane);
+    nx = ny = nz = 0.0f;
+    if (cc < nchunks && j < n) {
+      nx = xyz[3 * j];
+      ny = xyz[3 * j + 1];
+      nz = xyz[3 * j + 2];
+    }
+  };
+  long long c = (long long)blockIdx.x * waves + wave;
+  load_pos(c);
+  for (; c < nchunks; c += stride) {
     const long long idx = c * PER + (GRAD ? (lane >> 2) : lane);
     const bool ok = idx < n;
-    float x = 0.0f, y = 0.0f, z = 0.0f;
-    if (ok) {
-      x = xyz[3 * idx];
-      y = xyz[3 * idx + 1];
-      z = xyz[3 * idx + 2];
-    }
-    write_features<CF, GRAD, CF::P == kF16 && CF::GK == 1 && !GRAD>(myrow, ls, role, x, y, z, tfe, nd.fm);
+    const float x = nx, y = ny, z = nz;
+    write_features<CF, GRAD, CF::P != kF32 && CF::GK == 1 && !GRAD>(myrow, ls, role, x, y, z, tfe, nd.fm);
     wave_lds_sync();
+    load_pos(c + stride);
     if constexpr (ADJ) {
       const float o = mlp_tile_adj<CF, HH>(smem, bsm, feat);
       wave_lds_sync();

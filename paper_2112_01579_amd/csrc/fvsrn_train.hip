@@ -197,17 +197,27 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
     for (int j = 0; j < 4; ++j) r[j] = first ? v[j] : old[j] + v[j];
     reinterpret_cast<f4*>(slice + tile * 256)[lane] = r;
   };
+  // A chunk's positions, times and targets (or loss gradients) are loaded
+  // one chunk ahead, after the input rows of the chunk before are built, so
+  // that these HBM reads overlap its passes instead of preceding the gather.
+  float npx, npy, npz, npt, ntg;
+  auto load_point = [&](long long cc) {
+    const long long j = cc * S + lane;
+    npx = npy = npz = npt = ntg = 0.0f;
+    if (lane < S && cc < nchunks && j < n) {
+      npx = xyz[3 * j];
+      npy = xyz[3 * j + 1];
+      npz = xyz[3 * j + 2];
+      if (times) npt = times[j];
+      ntg = target ? target[j] : dloss[j];
+    }
+  };
+  load_point(wave);
   for (long long c = wave; c < nchunks; c += n_waves) {
     // lane l < S owns point c * S + l
     const long long idx = c * S + lane;
     const bool ok = lane < S && idx < n;
-    float px = 0.0f, py = 0.0f, pz = 0.0f, pt = 0.0f;
-    if (ok) {
-      px = xyz[3 * idx];
-      py = xyz[3 * idx + 1];
-      pz = xyz[3 * idx + 2];
-      if (times) pt = times[idx];
-    }
+    const float px = npx, py = npy, pz = npz, pt = npt, tg = ntg;
     // this point's keyframe pair (Sec. 8)
     int key;
     float kw;
@@ -226,6 +236,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
       }
     }
     wave_lds_sync();
+    load_point(c + n_waves);
     // ---------------- forward: store pre-activations a_i[s][o]
     f4 out = {0.0f, 0.0f, 0.0f, 0.0f};
     for (int t = 0; t < NTC; ++t) {
@@ -274,7 +285,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
     f4 dyo = {0.0f, 0.0f, 0.0f, 0.0f};
     if (ok) {
       if (target) {
-        const float r = d - target[idx];
+        const float r = d - tg;
         loss_acc += fabsf(r);
         gy = (r > 0.0f ? 1.0f : (r < 0.0f ? -1.0f : 0.0f)) * inv_n;
         if (target_grad) {
@@ -287,8 +298,8 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
           }
         }
       } else {
-        loss_acc += dloss[idx] * d;
-        gy = dloss[idx];
+        loss_acc += tg * d;
+        gy = tg;
       }
     }
     dyo[0] = gy * d * (1.0f - d);
@@ -607,16 +618,24 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
     for (int j = 0; j < 4; ++j) r[j] = first ? v[j] : old[j] + v[j];
     reinterpret_cast<f4*>(slice + tile * 256)[lane] = r;
   };
+  // positions, times and targets one chunk ahead (see fwd_bwd_kernel)
+  float npx, npy, npz, npt, ntg;
+  auto load_point = [&](long long cc) {
+    const long long j = cc * S + lane;
+    npx = npy = npz = npt = ntg = 0.0f;
+    if (lane < S && cc < nchunks && j < n) {
+      npx = xyz[3 * j];
+      npy = xyz[3 * j + 1];
+      npz = xyz[3 * j + 2];
+      if (times) npt = times[j];
+      ntg = target[j];
+    }
+  };
+  load_point(wave);
   for (long long c = wave; c < nchunks; c += n_waves) {
     const long long idx = c * S + lane;
     const bool ok = lane < S && idx < n;
-    float px = 0.0f, py = 0.0f, pz = 0.0f, pt = 0.0f;
-    if (ok) {
-      px = xyz[3 * idx];
-      py = xyz[3 * idx + 1];
-      pz = xyz[3 * idx + 2];
-      if (times) pt = times[idx];
-    }
+    const float px = npx, py = npy, pz = npz, pt = npt, tg = ntg;
     int key;
     float kw;
     key_pair(kt, nd.K, pt, key, kw);
@@ -631,6 +650,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
       }
     }
     wave_lds_sync();
+    load_point(c + n_waves);
     // ---------------- forward (FP16 MFMA); keep act'(a_i) and h_i
     f4 acc[MT];
 #pragma unroll
@@ -702,7 +722,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
     float gy = 0.0f;
     f4 dyo = zero;
     if (ok) {
-      const float r = d - target[idx];
+      const float r = d - tg;
       loss_acc += fabsf(r);
       gy = (r > 0.0f ? 1.0f : (r < 0.0f ? -1.0f : 0.0f)) * dscale;
       if (target_grad) {
