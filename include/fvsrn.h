@@ -201,7 +201,8 @@ typedef struct {
    without shading, 16 with forward-mode gradients and 8 with central
    differences. Phong shading needs the density gradient, obtained as
    march->grad_mode selects (Sec. 6), for FP32, FP16 and BF16 networks
-   (central differences, predicted gradients and the adjoint for the sine
+   (central differences and predicted gradients for the sine activation,
+   also with a time encoding or a Fourier matrix; the adjoint for the sine
    activation with the octave Fourier features and no time input; the
    adjoint of an FP32 network whose weight fragments, forward and transposed,
    exceed the 160 KiB of LDS -- c = 48 with H = 8, or with F = 16 and H >= 7 --

@@ -2,7 +2,8 @@
 // random Fourier features, rows drawn from N(0, (2 pi sigma)^2)), compiled
 // once per precision with FVSRN_PREC = 0 FP32, 1 FP16 or 2 BF16, sine
 // activation: the unshaded render and point densities, forward-mode density
-// gradients and Phong shading from them.
+// gradients and Phong shading from them, Phong shading from central
+// differences and, for four-output networks, from the predicted gradient.
 #include "fvsrn_march.hpp"
 
 #ifndef FVSRN_PREC
@@ -20,12 +21,16 @@ struct RffEntry {
                     unsigned long long* stats, hipStream_t st) {
     if (!m.phong) return launch_render_t<CF, kShadeNone>(nd, tf, vb, m, out, stats, st);
     if (m.grad_mode == 0) return launch_render_t<CF, kShadeFwd>(nd, tf, vb, m, out, stats, st);
+    if (m.grad_mode == 1) return launch_render_t<CF, kShadeFD>(nd, tf, vb, m, out, stats, st);
+    if (m.grad_mode == 2) return launch_render_t<CF, kShadePred>(nd, tf, vb, m, out, stats, st);
     return 1;
   }
   static int points(const NetDev& nd, const float* xyz, long long n, int key, float key_w, float* out_d,
                     float* out_g, int gmode, hipStream_t st) {
     if (!out_g) return launch_points_t<CF, kShadeNone>(nd, xyz, n, key, key_w, out_d, nullptr, st);
     if (gmode == 0) return launch_points_t<CF, kShadeFwd>(nd, xyz, n, key, key_w, out_d, out_g, st);
+    // a four-output network's own gradient (outputs 1..3) from the value-mode kernel
+    if (gmode == 2) return launch_points_t<CF, kShadeNone>(nd, xyz, n, key, key_w, out_d, out_g, st);
     return 1;
   }
 };

@@ -1007,15 +1007,62 @@ def test_time_encoding_and_fourier_matrix_gradients(FV, kind):
         assert err <= tol
 
 
+def _te_fm_nets(FV, kind, outputs=1):
+    if kind == "fourier_matrix":
+        spec = I.NetSpec(R=10, F=8, L=4, c=32, H=3, K=2, outputs=outputs)
+        fm = I.random_fourier_matrix(spec.L, 1.0, 3)
+        lat, w = I.net_params(spec, 9)
+        return (FV.Network(spec, lat, w, key_times=(0.0, 1.0), fourier_matrix=fm),
+                O.Net(spec, lat, w, (0.0, 1.0), fourier_matrix=fm.astype(np.float64)))
+    spec = I.NetSpec(R=10, F=16, L=8, c=48, H=2, K=3, time_enc=1 if kind == "time_direct" else 3, outputs=outputs)
+    return _nets(FV, spec, 12, key_times=(0.0, 1.0, 3.0))
+
+
+@pytest.mark.parametrize("kind", ["time_direct", "time_both", "fourier_matrix"])
+def test_time_encoding_and_fourier_matrix_fd_and_predicted(FV, kind):
+    """Phong shading of networks with a time input or a Fourier matrix from
+    central differences of the density (seven evaluations per sample) and,
+    on their four-output variants, from the predicted gradient (Sec. 6 with
+    Sec. 8 and Sec. 3); the predicted gradient of points too. FP32, FP16 and
+    BF16 against the oracle, at the bounds of the plain networks' tests."""
+    cams = [dataclasses.replace(c, time=0.8) for c in I.orbit_cameras(1, 17, 12)]
+    tf = I.ramp_tf()
+    gnet, onet = _te_fm_nets(FV, kind)
+    m = I.March(step=1 / 96, ert_eps=0.0, phong=True, grad_mode=1, fd_step=1 / 32)
+    ref, ns = O.render(O.Field(net=onet), tf, cams, m)
+    for prec, tol in (("f32", PHONG32_TOL), ("f16", FP16_TOL), ("bf16", BF16_TOL)):
+        stats = torch.zeros(3, dtype=torch.int64, device="cuda")
+        img = FV.fvsrn_render(gnet, tf, cams, m, prec, stats=stats).cpu().numpy()
+        err = np.abs(img - ref).max()
+        _report("phong FD %s %s" % (kind, prec), err)
+        assert err <= tol
+        assert abs(stats[0].item() - ns) <= 0.001 * ns
+    gnet, onet = _te_fm_nets(FV, kind, outputs=4)
+    m = I.March(step=1 / 96, ert_eps=0.0, phong=True, grad_mode=2)
+    ref, ns = O.render(O.Field(net=onet), tf, cams, m)
+    for prec, tol in (("f32", PHONG32_TOL), ("f16", FP16_TOL), ("bf16", BF16_TOL)):
+        img = FV.fvsrn_render(gnet, tf, cams, m, prec).cpu().numpy()
+        err = np.abs(img - ref).max()
+        _report("phong predicted %s %s" % (kind, prec), err)
+        assert err <= tol
+    xyz = I.uniform_points(64 * 5 + 11, 8, -0.99, 0.99)
+    for t in (0.3, 2.5):
+        dref, gref = _pred_ref(onet, xyz, t)
+        for prec, dtol, gtol in (("f32", FP32_TOL, 1e-5), ("f16", FP16_TOL, 3e-3), ("bf16", BF16_TOL, 3e-2)):
+            d, g = FV.fvsrn_pred_grad_points(gnet, torch.from_numpy(xyz).cuda(), t, prec)
+            derr, gerr = np.abs(d.cpu().numpy() - dref).max(), _grad_err(g.cpu().numpy(), gref)
+            _report("pred points %s t=%.1f %s density / gradient (rel.)" % (kind, t, prec), max(derr, gerr))
+            assert derr <= dtol and gerr <= gtol
+
+
 def test_time_encoding_limits(FV):
-    """Central-difference, predicted and adjoint gradients and non-sine
-    activations are not compiled for time-encoded networks."""
+    """Adjoint gradients and non-sine activations are not compiled for
+    time-encoded networks."""
     spec = I.NetSpec(R=8, F=8, L=4, c=32, H=2, K=2, time_enc=1)
     gnet, _ = _nets(FV, spec, 3, key_times=(0.0, 1.0))
     xyz = torch.from_numpy(I.uniform_points(8, 1)).cuda()
     cams = I.orbit_cameras(1, 8, 8)
-    fd = I.March(step=0.1, phong=True, grad_mode=1, fd_step=1 / 32)
-    for call in (lambda: FV.fvsrn_render(gnet, I.ramp_tf(), cams, fd, "bf16"),
+    for call in (lambda: FV.fvsrn_render(gnet, I.ramp_tf(), cams, I.March(step=0.1, phong=True, grad_mode=3), "bf16"),
                  lambda: FV.fvsrn_render(gnet, I.ramp_tf(), cams, I.March(step=0.1, phong=True, grad_mode=3), "f32"),
                  lambda: FV.fvsrn_grad_points(gnet, xyz, 0.5, "f32", mode="adjoint")):
         with pytest.raises(FV.FvsrnError) as e:
