@@ -369,6 +369,21 @@ fvsrn_status fvsrn_error_grid(const fvsrn_net_desc* desc, const fvsrn_params* pa
    the steps between two refreshes of the error grid. */
 fvsrn_status fvsrn_sample_points_weighted(uint64_t seed, uint64_t counter, const float* E, int32_t G, int64_t n,
                                           float* xyz, void* workspace, size_t workspace_bytes, void* stream);
+
+/* The draws of n_grids calls of fvsrn_sample_points_weighted with E == NULL,
+   in one launch: for a batch taken from several error grids (one per
+   timestep of a time-varying volume, Sec. 5.4 with Sec. 8), where separate
+   calls would each cost a launch. Grid k draws n_per_grid[k] points (host
+   array, each in [0, 2^40]) with counter + k from the prefix sums in
+   workspace slice k (workspace + k * workspace_stride bytes, left there by
+   an earlier fvsrn_sample_points_weighted call with the same G and that
+   grid's E), written to xyz + 3 (n_per_grid[0] + ... + n_per_grid[k-1]):
+   the same positions as those n_grids calls. 1 <= n_grids <= 64;
+   workspace and workspace_stride 16-byte aligned, the stride at least
+   fvsrn_weighted_points_workspace_size(G); xyz [sum n_per_grid][3]. */
+fvsrn_status fvsrn_sample_points_weighted_multi(uint64_t seed, uint64_t counter, int32_t G, int32_t n_grids,
+                                                const int64_t* n_per_grid, float* xyz, const void* workspace,
+                                                size_t workspace_stride, void* stream);
 size_t fvsrn_weighted_points_workspace_size(int32_t G);
 
 /* Round an FP32 array to FP16 or BF16 (round to nearest even), e.g. to store

@@ -611,6 +611,29 @@ fvsrn_status fvsrn_sample_points_weighted(uint64_t seed, uint64_t counter, const
                        "fvsrn_sample_points_weighted");
 }
 
+fvsrn_status fvsrn_sample_points_weighted_multi(uint64_t seed, uint64_t counter, int32_t G, int32_t n_grids,
+                                                const int64_t* n_per_grid, float* xyz, const void* workspace,
+                                                size_t workspace_stride, void* stream) {
+  g_err[0] = 0;
+  if (G < 1 || G > 1024) return fail(FVSRN_ERR_INVALID_ARGUMENT, "G outside [1, 1024]");
+  if (n_grids < 1 || n_grids > kMaxDrawGrids)
+    return fail(FVSRN_ERR_INVALID_ARGUMENT, "n_grids outside [1, %d]", kMaxDrawGrids);
+  if (!n_per_grid) return fail(FVSRN_ERR_INVALID_ARGUMENT, "n_per_grid NULL");
+  long long n = 0;
+  for (int k = 0; k < n_grids; ++k) {
+    if (n_per_grid[k] < 0 || n_per_grid[k] > (1LL << 40))
+      return fail(FVSRN_ERR_INVALID_ARGUMENT, "n_per_grid[%d] outside [0, 2^40]", k);
+    n += n_per_grid[k];
+  }
+  if (n > 0 && (!xyz || !aligned16(xyz))) return fail(FVSRN_ERR_INVALID_ARGUMENT, "xyz NULL or misaligned");
+  const size_t need = weighted_points_workspace_bytes((long long)G * G * G);
+  if (!workspace || ((uintptr_t)workspace & 15u) || (workspace_stride & 15u) || workspace_stride < need)
+    return fail(FVSRN_ERR_WORKSPACE, "workspace slices of at least %zu bytes, 16-byte aligned, required", need);
+  return launch_status(
+      launch_weighted_points_multi(seed, counter, G, n_grids, n_per_grid, xyz, workspace, workspace_stride, stream),
+      "fvsrn_sample_points_weighted_multi");
+}
+
 fvsrn_status fvsrn_cast_grid(const float* src, void* dst, int64_t count, int32_t dst_dtype, void* stream) {
   g_err[0] = 0;
   if (count < 0) return fail(FVSRN_ERR_INVALID_ARGUMENT, "count < 0");

@@ -9,6 +9,7 @@ namespace fvsrn_detail {
 
 constexpr int kMaxViewsPerLaunch = 16;
 constexpr int kMaxKeyframes = 64;
+constexpr int kMaxDrawGrids = 64;  // error grids per batched weighted draw
 constexpr int kMaxFourierRows = 24;  // 3L for L <= 8
 
 // Keyframe times for per-point keyframe selection in training.
@@ -99,6 +100,8 @@ int launch_error_reduce(const float* d, const float* vol, int nx, int ny, int nz
 size_t weighted_points_workspace_bytes(long long n_voxels);
 int launch_weighted_points(uint64_t seed, uint64_t counter, const float* E, int G, long long n, float* xyz,
                            void* workspace, void* stream);
+int launch_weighted_points_multi(uint64_t seed, uint64_t counter, int G, int n_grids, const int64_t* n_per_grid,
+                                 float* xyz, const void* workspace, size_t stride, void* stream);
 
 // Training (FP32). Workspace layout is owned by the kernels file.
 size_t train_workspace_bytes(const NetDev& net, long long n);

@@ -458,29 +458,58 @@ __global__ void add_offsets_kernel(unsigned long long* Q, long long nv, const un
     Q[v] += S[v / kScanBlock];
 }
 
-// Point i: voxel v with Q[v-1] <= (r0 total) >> 32 < Q[v] (all weights zero:
-// v = (r0 nv) >> 32), position inside it from r1..r3.
+// Point i (Philox counter words c_lo, c_hi): voxel v with
+// Q[v-1] <= (r0 total) >> 32 < Q[v] (all weights zero: v = (r0 nv) >> 32),
+// position inside it from r1..r3.
+__device__ inline void draw_weighted(uint32_t k0, uint32_t k1, uint32_t c_lo, uint32_t c_hi,
+                                     const unsigned long long* Q, unsigned long long total, int G, long long nv,
+                                     long long i, float* out) {
+  uint32_t c[4];
+  philox4x32_10(i, c_lo, c_hi, k0, k1, c);
+  long long v;
+  if (total == 0) {
+    v = (long long)(((unsigned long long)c[0] * (unsigned long long)nv) >> 32);
+  } else {
+    const unsigned long long target = __umul64hi((unsigned long long)c[0] << 32, total);
+    long long lo = 0, hi = nv - 1;
+    while (lo < hi) {
+      const long long mid = (lo + hi) >> 1;
+      if (Q[mid] > target) hi = mid;
+      else lo = mid + 1;
+    }
+    v = lo;
+  }
+  voxel_position(G, v, c + 1, out);
+}
+
 __global__ void weighted_points_kernel(uint32_t k0, uint32_t k1, uint32_t c_lo, uint32_t c_hi,
                                        const unsigned long long* Q, int G, long long nv, long long n, float* xyz) {
   const unsigned long long total = Q[nv - 1];
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    draw_weighted(k0, k1, c_lo, c_hi, Q, total, G, nv, i, xyz + 3 * i);
+}
+
+// Several grids' draws in one launch: point i of the batch belongs to grid
+// k with start[k] <= i < start[k + 1], draws with counter + k and local
+// index i - start[k] from the prefix sums at ws + k stride bytes.
+struct MultiDraw {
+  int n;
+  long long start[kMaxDrawGrids + 1];
+};
+
+__global__ void weighted_points_multi_kernel(uint32_t k0, uint32_t k1, unsigned long long counter, const char* ws,
+                                             unsigned long long stride, int G, long long nv, MultiDraw md,
+                                             float* xyz) {
+  const long long n = md.start[md.n];
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
-    uint32_t c[4];
-    philox4x32_10(i, c_lo, c_hi, k0, k1, c);
-    long long v;
-    if (total == 0) {
-      v = (long long)(((unsigned long long)c[0] * (unsigned long long)nv) >> 32);
-    } else {
-      const unsigned long long target = __umul64hi((unsigned long long)c[0] << 32, total);
-      long long lo = 0, hi = nv - 1;
-      while (lo < hi) {
-        const long long mid = (lo + hi) >> 1;
-        if (Q[mid] > target) hi = mid;
-        else lo = mid + 1;
-      }
-      v = lo;
-    }
-    voxel_position(G, v, c + 1, xyz + 3 * i);
+    int k = 0;
+#pragma unroll
+    for (int j = 1; j < kMaxDrawGrids; ++j) k += (j < md.n && i >= md.start[j]) ? 1 : 0;
+    const unsigned long long* Q = reinterpret_cast<const unsigned long long*>(ws + (unsigned long long)k * stride);
+    const unsigned long long ck = counter + (unsigned long long)k;
+    draw_weighted(k0, k1, (uint32_t)ck, (uint32_t)(ck >> 32), Q, Q[nv - 1], G, nv, i - md.start[k], xyz + 3 * i);
   }
 }
 
@@ -534,6 +563,21 @@ int launch_weighted_points(uint64_t seed, uint64_t counter, const float* E, int 
   hipLaunchKernelGGL(weighted_points_kernel, dim3(grid_blocks(n, 256, device_cus() * 16)), dim3(256), 0, st,
                      (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)counter, (uint32_t)(counter >> 32), Q, G, nv,
                      n, xyz);
+  return check_launch();
+}
+
+int launch_weighted_points_multi(uint64_t seed, uint64_t counter, int G, int n_grids, const int64_t* n_per_grid,
+                                 float* xyz, const void* workspace, size_t stride, void* stream) {
+  MultiDraw md;
+  md.n = n_grids;
+  md.start[0] = 0;
+  for (int k = 0; k < n_grids; ++k) md.start[k + 1] = md.start[k] + n_per_grid[k];
+  for (int k = n_grids + 1; k <= kMaxDrawGrids; ++k) md.start[k] = md.start[n_grids];
+  const long long n = md.start[n_grids];
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(weighted_points_multi_kernel, dim3(grid_blocks(n, 256, device_cus() * 16)), dim3(256), 0,
+                     (hipStream_t)stream, (uint32_t)seed, (uint32_t)(seed >> 32), (unsigned long long)counter,
+                     (const char*)workspace, (unsigned long long)stride, G, (long long)G * G * G, md, xyz);
   return check_launch();
 }
 

@@ -31,6 +31,7 @@ EXPORTS = (
     "fvsrn_sample_points", "fvsrn_cast_grid", "fvsrn_quantize_grid", "fvsrn_ssim_map", "fvsrn_num_weights",
     "fvsrn_voxel_points", "fvsrn_error_grid", "fvsrn_sample_points_weighted", "fvsrn_weighted_points_workspace_size",
     "fvsrn_status_str", "fvsrn_last_error", "fvsrn_build_id", "fvsrn_train_step_noalloc",
+    "fvsrn_sample_points_weighted_multi",
 )
 
 
@@ -116,6 +117,8 @@ def lib():
             "fvsrn_voxel_points": (st, [C.c_uint64, C.c_uint64, i32, i32, vp, vp]),
             "fvsrn_error_grid": (st, [vp, vp, vp, i32, i32, i32, vp, i64, i32, C.c_float, vp, vp, vp]),
             "fvsrn_sample_points_weighted": (st, [C.c_uint64, C.c_uint64, vp, i32, i64, vp, vp, sz, vp]),
+            "fvsrn_sample_points_weighted_multi": (st, [C.c_uint64, C.c_uint64, i32, i32, C.POINTER(C.c_int64), vp,
+                                                        vp, sz, vp]),
             "fvsrn_weighted_points_workspace_size": (sz, [i32]),
             "fvsrn_status_str": (C.c_char_p, [st]),
             "fvsrn_last_error": (C.c_char_p, []),
@@ -440,6 +443,31 @@ def fvsrn_sample_points_weighted(seed: int, counter: int, E: Optional[torch.Tens
     check_tensor(workspace, "workspace", dtype=torch.uint8, device=dev)
     _check(lib().fvsrn_sample_points_weighted(seed, counter, _ptr(E), G, n, _ptr(out), _ptr(workspace),
                                               workspace.numel(), _stream(stream)), "fvsrn_sample_points_weighted")
+    return out
+
+
+def weighted_points_stride(G: int) -> int:
+    """Bytes of one workspace slice for fvsrn_sample_points_weighted_multi."""
+    return (lib().fvsrn_weighted_points_workspace_size(G) + 15) // 16 * 16
+
+
+def fvsrn_sample_points_weighted_multi(seed: int, counter: int, G: int, n_per_grid: Sequence[int],
+                                       workspace: torch.Tensor, out=None, stream=None):
+    """The draws of len(n_per_grid) calls of fvsrn_sample_points_weighted
+    with E None in one launch: grid k draws n_per_grid[k] points with
+    counter + k from the prefix sums in workspace slice k (``workspace``
+    [n_grids][weighted_points_stride(G)] bytes, each slice left by an earlier
+    call with that grid), the grids' points one after the other in ``out``."""
+    counts = [int(x) for x in n_per_grid]
+    stride = weighted_points_stride(G)
+    check_tensor(workspace, "workspace", dtype=torch.uint8, shape=(len(counts), stride))
+    n = sum(counts)
+    if out is None:
+        out = torch.empty((n, 3), dtype=torch.float32, device=workspace.device)
+    check_tensor(out, "out", shape=(n, 3), device=workspace.device)
+    arr = (C.c_int64 * max(len(counts), 1))(*counts)
+    _check(lib().fvsrn_sample_points_weighted_multi(seed, counter, G, len(counts), arr, _ptr(out), _ptr(workspace),
+                                                    stride, _stream(stream)), "fvsrn_sample_points_weighted_multi")
     return out
 
 

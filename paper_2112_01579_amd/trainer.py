@@ -89,8 +89,8 @@ class Trainer:
             self.E_ready = False
             # one sampling workspace per timestep: its prefix sums are built
             # from the error grid once per refresh and reused until the next
-            wsz = FV.lib().fvsrn_weighted_points_workspace_size(self.G)
-            self.sample_ws = [torch.empty(wsz, dtype=torch.uint8, device=dev) for _ in self.frames]
+            self.sample_ws = torch.empty((len(self.frames), FV.weighted_points_stride(self.G)), dtype=torch.uint8,
+                                         device=dev)
             self.cdf_fresh = False
 
     def update_error_grid(self):
@@ -111,12 +111,17 @@ class Trainer:
         if self.E is not None and self.E_ready:
             # timestep j's rows from its own error grid; counters step * T + j
             T = len(self.frames)
-            for j in range(T):
-                a, b = self.bounds[j], self.bounds[j + 1]
-                FV.fvsrn_sample_points_weighted(self.seed, self.opt["step"] * T + j,
-                                                self.E_all[j] if not self.cdf_fresh else None, self.G, b - a,
-                                                out=self.xyz[a:b], workspace=self.sample_ws[j])
-            self.cdf_fresh = True
+            if not self.cdf_fresh:
+                for j in range(T):
+                    a, b = self.bounds[j], self.bounds[j + 1]
+                    FV.fvsrn_sample_points_weighted(self.seed, self.opt["step"] * T + j, self.E_all[j], self.G,
+                                                    b - a, out=self.xyz[a:b], workspace=self.sample_ws[j])
+                self.cdf_fresh = True
+            else:
+                # the same draws from the kept prefix sums, in one launch
+                FV.fvsrn_sample_points_weighted_multi(
+                    self.seed, self.opt["step"] * T, self.G,
+                    [self.bounds[j + 1] - self.bounds[j] for j in range(T)], self.sample_ws, out=self.xyz)
         else:
             FV.fvsrn_sample_points(self.seed, self.opt["step"], self.batch, out=self.xyz)
         for j, (_, v) in enumerate(self.frames):

@@ -197,6 +197,31 @@ def test_points_argument_errors_and_empty_noop():
     assert L.fvsrn_cast_grid(None, None, 0, 1, None) == FV.OK
 
 
+def test_weighted_multi_draw_argument_errors():
+    """The batched weighted draw checks its grid count, point counts and
+    workspace slices on the host; all-zero counts launch nothing."""
+    L = FV.lib()
+    P = C.c_void_p
+    stride = FV.weighted_points_stride(8)
+    assert stride % 16 == 0 and stride >= L.fvsrn_weighted_points_workspace_size(8)
+
+    def call(counts, G=8, n_grids=None, stride=stride, ws=FAKE, xyz=FAKE):
+        arr = (C.c_int64 * max(len(counts), 1))(*counts)
+        return L.fvsrn_sample_points_weighted_multi(1, 2, G, len(counts) if n_grids is None else n_grids, arr,
+                                                    P(xyz) if xyz else None, P(ws) if ws else None, stride, None)
+    assert call([0, 0, 0]) == FV.OK
+    assert call([4], n_grids=0) == FV.ERR_INVALID_ARGUMENT
+    assert call([4] * 65) == FV.ERR_INVALID_ARGUMENT
+    assert call([4, -1]) == FV.ERR_INVALID_ARGUMENT
+    assert call([4], G=0) == FV.ERR_INVALID_ARGUMENT
+    assert call([4], xyz=None) == FV.ERR_INVALID_ARGUMENT
+    assert call([4], stride=stride - 16) == FV.ERR_WORKSPACE
+    assert call([4], stride=stride + 8) == FV.ERR_WORKSPACE
+    assert call([4], ws=None) == FV.ERR_WORKSPACE
+    assert L.fvsrn_sample_points_weighted_multi(1, 2, 8, 1, None, P(FAKE), P(FAKE), stride, None) \
+        == FV.ERR_INVALID_ARGUMENT
+
+
 def _train(d, key_times=None, xyz=FAKE, times=None, n=4, target=FAKE, dloss=None, adam=None, target_grad=None,
            grad_weight=0.0):
     L = FV.lib()

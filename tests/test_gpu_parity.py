@@ -1147,7 +1147,7 @@ def test_weighted_points_bit_exact(FV):
     inverse CDF makes every voxel choice exact, so the points equal the
     oracle's bit for bit -- a random grid with zero and negative entries, a
     one-hot grid, an all-zero grid (uniform voxels) -- at a size that spans
-    several scan blocks."""
+    several scan blocks, and on grids of 1 to 64 voxels."""
     seed, counter, n = 99, 5, 50000
     r = _philox_words(n, seed, counter)
     rng = np.random.default_rng(8)
@@ -1166,6 +1166,12 @@ def test_weighted_points_bit_exact(FV):
         # E None: the prefix sums kept in the workspace serve the next draws
         got = FV.fvsrn_sample_points_weighted(seed, counter + 7, None, G, n, workspace=ws).cpu().numpy()
         assert np.array_equal(got, O.weighted_points(Ec, G, r2))
+    # grids of 1 to 64 voxels: fewer than 16 candidates from the start, or one level of the search
+    for Gs in (1, 2, 3, 4):
+        Es = rng.exponential(0.01, Gs ** 3).astype(np.float32)
+        Es[rng.random(Gs ** 3) < 0.3] = 0.0
+        got = FV.fvsrn_sample_points_weighted(seed, counter, torch.from_numpy(Es).cuda(), Gs, n).cpu().numpy()
+        assert np.array_equal(got, O.weighted_points(Es, Gs, r))
     # the empirical voxel frequencies follow the weights
     got = FV.fvsrn_sample_points_weighted(seed, counter + 1, torch.from_numpy(E).cuda(), G, 1 << 20).cpu().numpy()
     idx = np.clip(((got + 1) * G / 2).astype(np.int64), 0, G - 1)
@@ -1174,6 +1180,32 @@ def test_weighted_points_bit_exact(FV):
     w = np.maximum(E, 0) / np.maximum(E, 0).sum()
     assert np.abs(freq - w).max() < 6 * np.sqrt(w.max() / (1 << 20))
     assert freq[E <= 0].sum() == 0
+
+
+def test_weighted_points_multi_draw_matches_single_draws(FV):
+    """One launch drawing from several grids' kept prefix sums equals the
+    separate E-None draws bit for bit (grid k with counter + k, the grids'
+    points one after the other), with a grid that draws no points, and the
+    oracle's draws for each grid."""
+    seed, counter = 17, 40
+    rng = np.random.default_rng(21)
+    for G, counts in ((24, [5000, 0, 777, 3001]), (3, [64, 65])):
+        T = len(counts)
+        ws = torch.zeros((T, FV.weighted_points_stride(G)), dtype=torch.uint8, device="cuda")
+        Es = []
+        for k in range(T):
+            E = rng.exponential(0.01, G ** 3).astype(np.float32)
+            E[rng.random(G ** 3) < 0.3] = 0.0
+            Es.append(E)
+            FV.fvsrn_sample_points_weighted(seed, 0, torch.from_numpy(E).cuda(), G, 1, workspace=ws[k])
+        got = FV.fvsrn_sample_points_weighted_multi(seed, counter, G, counts, ws).cpu().numpy()
+        assert got.shape == (sum(counts), 3)
+        a = 0
+        for k, n in enumerate(counts):
+            single = FV.fvsrn_sample_points_weighted(seed, counter + k, None, G, n, workspace=ws[k]).cpu().numpy()
+            assert np.array_equal(got[a:a + n], single)
+            assert np.array_equal(single, O.weighted_points(Es[k], G, _philox_words(n, seed, counter + k)))
+            a += n
 
 
 # ------------------------------ width 64 and independent (F, L) pairs
