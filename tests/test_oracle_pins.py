@@ -429,6 +429,53 @@ def test_beer_lambert_constant_density():
                 assert img[v, py, px, 3] == pytest.approx(1 - math.exp(-kappa * L), rel=1e-12, abs=1e-15)
 
 
+def test_network_render_front_to_back_closed_form():
+    """A network field whose density varies along the ray: the single-path
+    sine network of test_mlp_single_path_closed_form depends on z only, so
+    on vertical orthographic rays every sample's density, colour and
+    extinction follow in closed form, and the image is their front-to-back
+    composite (a = 1 - exp(-kappa ds), C += T a rgb, A += T a,
+    T *= 1 - a) at the segment midpoints, top first."""
+    spec = I.NetSpec(R=2, F=0, L=0, c=4, H=3)
+    w = np.zeros(spec.n_weights)
+    w[1 * 3 + 2] = 0.7
+    off = 4 * 3
+    w[off + 1] = 0.1
+    off += 4
+    w[off + 3 * 4 + 1] = 1.3
+    off += 16 + 4
+    w[off + 0 * 4 + 3] = -0.9
+    off += 16 + 4
+    w[off + 0] = 2.0
+    w[off + 4] = 0.25
+    net = make_net(spec, weights=w)
+    tf = I.ramp_tf()
+    m = I.March(fixed_steps=8, step=0.0)
+    img, ns = O.render(O.Field(net=net), tf, [I.ortho_camera(2, 2)], m)
+    T, C, A = 1.0, np.zeros(3), 0.0
+    for i in range(8):
+        z = 1 - (i + 0.5) / 4
+        y = 2.0 * math.sin(-0.9 * math.sin(1.3 * math.sin(0.7 * z + 0.1))) + 0.25
+        rgba = O.tf_eval(tf, 1 / (1 + math.exp(-y)))
+        a = 1 - math.exp(-tf.opacity_scale * rgba[3] * 0.25)
+        C += T * a * np.asarray(rgba[:3])
+        A += T * a
+        T *= 1 - a
+    assert ns == 4 * 8
+    np.testing.assert_allclose(img[0, ..., :3], np.broadcast_to(C, (2, 2, 3)), rtol=1e-13)
+    np.testing.assert_allclose(img[0, ..., 3], A, rtol=1e-13)
+    # the reversed order composites to a different colour: the pin sees the order
+    T2, C2 = 1.0, np.zeros(3)
+    for i in reversed(range(8)):
+        z = 1 - (i + 0.5) / 4
+        y = 2.0 * math.sin(-0.9 * math.sin(1.3 * math.sin(0.7 * z + 0.1))) + 0.25
+        rgba = O.tf_eval(tf, 1 / (1 + math.exp(-y)))
+        a = 1 - math.exp(-tf.opacity_scale * rgba[3] * 0.25)
+        C2 += T2 * a * np.asarray(rgba[:3])
+        T2 *= 1 - a
+    assert np.abs(C2 - C).max() > 1e-3
+
+
 def test_zero_density_is_transparent():
     tf = I.ramp_tf()
     vol = np.zeros((5, 5, 5))
