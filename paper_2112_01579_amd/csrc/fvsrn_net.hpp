@@ -58,6 +58,10 @@ __device__ inline LaneRole grad_role(int q) {
 
 // ------------------------------------------------------ weight staging
 
+// The packed uint8 gather hands the row its weighted code sums times this
+// power of two (see latent_column_q).
+constexpr float kCodeSumScale = 1.0f / 1024.0f;
+
 // Converts the FP32 master weights into A fragments in LDS (lane order), with
 // the first layer's columns permuted to the input-row order and each hidden
 // layer's columns permuted so that the previous layer's D fragments are this
@@ -74,7 +78,8 @@ __device__ void stage_weights(const NetDev& nd, char* smem) {
   const float sc = CF::ACT == kIdentity ? 1.0f : kInv2Pi;
   // a single uint8 keyframe on the packed path: the de-quantisation is folded
   // into layer 0 (latent columns times the channel scale, the channel offsets
-  // into the bias), so the input row carries the weighted code sums
+  // into the bias), so the input row carries the weighted code sums (times
+  // kCodeSumScale, which the latent columns undo)
   const bool fold = CF::GK == 2 && nd.grid_u8 && nd.K == 1;
   const float* dq = nd.dequant;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -87,7 +92,7 @@ __device__ void stage_weights(const NetDev& nd, char* smem) {
   auto w0 = [&](int o, int col) -> float {
     if (col < G::KF) {
       const float half = (CF::P != kF32 && col >= F + 3 * L) ? 0.5f : 1.0f;
-      const float qs = (fold && col < F) ? dq[2 * col + 1] : 1.0f;
+      const float qs = (fold && col < F) ? dq[2 * col + 1] * (1.0f / kCodeSumScale) : 1.0f;
       return w[(long long)o * K0 + 3 + col] * qs * sc * half;
     }
     if (col < G::KMAIN) return 0.0f;
@@ -482,11 +487,16 @@ __device__ inline void latent_column_h(const LatentSrc& ls, const LaneRole& role
 }
 
 // uint8 variant of LatentColumnH (Sec. 4.2's quantised grid) for an FP16
-// network: each code pair is unpacked into FP16 as 1024 + code (a byte
-// permute next to the exponent byte 0x64) and 1024 subtracted exactly; the
-// weighted code sums accumulate in packed FP16 (at most 255, so the sum keeps
-// 1/8 of a code). With one keyframe they go to the row as they are (layer 0
-// holds the de-quantisation); with two they are de-quantised and blended.
+// network. A byte permute next to a zero byte turns each code pair into two
+// FP16 subnormals code * 2^-24 (exact: the FP16 denormals are kept), and the
+// corner weights carry 2^14, so each packed FMA adds w * code * 2^-10 with
+// one rounding, as w * code would be: the row receives the weighted code sums
+// times 2^-10 (kCodeSumScale), and no per-corner subtraction is needed.
+// Tangent lanes (forward mode, weights up to (R - 1) / 2) carry 2^7 instead
+// and scale their sums by 2^7 at the end. The sums keep 1/8 of a code at the
+// top of the range. With one keyframe they go to the row as they are (layer 0
+// holds the de-quantisation, times 2^10); with two they are de-quantised and
+// blended.
 template <int F>
 __device__ inline void latent_column_q(const LatentSrc& ls, const LaneRole& role, float px, float py, float pz,
                                        h2* z2) {
@@ -507,7 +517,7 @@ __device__ inline void latent_column_q(const LatentSrc& ls, const LaneRole& role
   corner_offsets(sx, sy, sz, off);
   const float w[8] = {x0 * y0 * z0, x1 * y0 * z0, x0 * y1 * z0, x1 * y1 * z0,
                       x0 * y0 * z1, x1 * y0 * z1, x0 * y1 * z1, x1 * y1 * z1};
-  const h2 bias = {(_Float16)-1024.0f, (_Float16)-1024.0f};
+  const float wscale = role.is_val ? 16384.0f : 128.0f;
   float zf[F];
 #pragma unroll
   for (int j = 0; j < F; ++j) zf[j] = 0.0f;
@@ -523,17 +533,22 @@ __device__ inline void latent_column_q(const LatentSrc& ls, const LaneRole& role
     for (int j = 0; j < F / 2; ++j) acc[j] = h2{(_Float16)0.0f, (_Float16)0.0f};
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-      const _Float16 wh = (_Float16)w[c];
+      const _Float16 wh = (_Float16)(w[c] * wscale);
       const h2 w2 = {wh, wh};
       unsigned d[F / 4];
       load_codes<F>(r, base, off[c], d);
 #pragma unroll
       for (int q = 0; q < F / 4; ++q) {
-        const h2 lo = __builtin_bit_cast(h2, __builtin_amdgcn_perm(0x64646464u, d[q], 0x04010400u)) + bias;
-        const h2 hi = __builtin_bit_cast(h2, __builtin_amdgcn_perm(0x64646464u, d[q], 0x04030402u)) + bias;
+        const h2 lo = __builtin_bit_cast(h2, __builtin_amdgcn_perm(0u, d[q], 0x04010400u));
+        const h2 hi = __builtin_bit_cast(h2, __builtin_amdgcn_perm(0u, d[q], 0x04030402u));
         acc[2 * q] = w2 * lo + acc[2 * q];
         acc[2 * q + 1] = w2 * hi + acc[2 * q + 1];
       }
+    }
+    if (!role.is_val) {
+      const h2 up = {(_Float16)128.0f, (_Float16)128.0f};
+#pragma unroll
+      for (int j = 0; j < F / 2; ++j) acc[j] *= up;
     }
     if (!ls.g1) {
       // one keyframe: layer 0 holds the de-quantisation (see stage_weights)
@@ -545,8 +560,9 @@ __device__ inline void latent_column_q(const LatentSrc& ls, const LaneRole& role
     const float wsum = ((w[0] + w[1]) + (w[2] + w[3])) + ((w[4] + w[5]) + (w[6] + w[7]));
 #pragma unroll
     for (int j = 0; j < F / 2; ++j) {
-      zf[2 * j] = fmaf(kw, fmaf(dq[4 * j + 1], (float)acc[j][0], dq[4 * j] * wsum), zf[2 * j]);
-      zf[2 * j + 1] = fmaf(kw, fmaf(dq[4 * j + 3], (float)acc[j][1], dq[4 * j + 2] * wsum), zf[2 * j + 1]);
+      const float a0 = (float)acc[j][0] * (1.0f / kCodeSumScale), a1 = (float)acc[j][1] * (1.0f / kCodeSumScale);
+      zf[2 * j] = fmaf(kw, fmaf(dq[4 * j + 1], a0, dq[4 * j] * wsum), zf[2 * j]);
+      zf[2 * j + 1] = fmaf(kw, fmaf(dq[4 * j + 3], a1, dq[4 * j + 2] * wsum), zf[2 * j + 1]);
     }
   }
 #pragma unroll

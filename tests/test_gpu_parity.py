@@ -217,6 +217,29 @@ def test_uint8_grid_keyframes_render_and_gradients(FV):
         assert np.abs(img - ref).max() <= tol
 
 
+def test_uint8_grid_fp16_forward_mode(FV):
+    """FP16 forward-mode gradients on uint8 grids (the tangent lanes of the
+    packed code gather, whose corner weights are derivatives up to (R-1)/2)
+    and Phong shading from them, one keyframe and two, against the oracle
+    reading the same codes."""
+    for spec, kt, seed in ((I.NET_STUDY, None, 14), (I.NetSpec(R=16, F=16, L=8, c=32, H=3, K=2), [0.0, 1.0], 15)):
+        gnet, onet = _nets(FV, spec, seed, key_times=kt, grid_dtype=FV.U8)
+        xyz = I.uniform_points(16 * 37 + 5, 9, -0.99, 0.99)
+        t = 0.35 if kt else 0.0
+        dref, gref = O.grad_points(onet, xyz, t)
+        d, g = FV.fvsrn_grad_points(gnet, torch.from_numpy(xyz).cuda(), t, "f16")
+        derr, gerr = np.abs(d.cpu().numpy() - dref).max(), _grad_err(g.cpu().numpy(), gref)
+        _report("uint8 forward mode K=%d f16 density" % spec.K, derr)
+        _report("uint8 forward mode K=%d f16 gradient (rel.)" % spec.K, gerr)
+        assert derr <= FP16_TOL and gerr <= GRAD16_TOL
+        cams = [dataclasses.replace(c, time=0.6) for c in I.orbit_cameras(1, 21, 15)]
+        m = I.March(step=1 / 96, ert_eps=0.0, phong=True)
+        ref, _ = O.render(O.Field(net=onet), I.ramp_tf(), cams, m)
+        img = FV.fvsrn_render(gnet, I.ramp_tf(), cams, m, "f16").cpu().numpy()
+        _report("uint8 phong K=%d f16" % spec.K, np.abs(img - ref).max())
+        assert np.abs(img - ref).max() <= FP16_TOL
+
+
 def test_eval_points_activations(FV):
     for act in ("snakealt", "identity"):
         spec = I.NetSpec(R=16, F=8, L=4, c=32, H=3, act=act)
