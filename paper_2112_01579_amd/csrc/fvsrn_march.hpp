@@ -359,9 +359,9 @@ __global__ __launch_bounds__((max_waves<CF, PM, true>() * 64)) void points_kerne
   const long long nchunks = (n + PER - 1) / PER;
   const int waves = blockDim.x >> 6;
   const long long stride = (long long)gridDim.x * waves;
-  // Each chunk's positions are loaded one chunk ahead, after the latent
-  // gather of the chunk before and consumed after its MLP, so that the
-  // HBM read is not in series with the gather it addresses.
+  // The next chunk's positions are read once this chunk's input rows are
+  // built: the HBM read then runs behind this chunk's MLP instead of in
+  // series with the latent gather that it addresses.
   float nx = 0.0f, ny = 0.0f, nz = 0.0f;
   auto load_pos = [&](long long cc) {
     const long long j = cc * PER + (GRAD ? (lane >> 2) : lane);
