@@ -132,6 +132,86 @@ __device__ inline void key_pair(const KeyTimes& kt, int K, float t, int& key, fl
   }
 }
 
+// The input rows of a chunk's 16 points (Sec. 3: latent, Fourier features,
+// x y z 1), built by all 64 lanes: lane q of quad p writes channels
+// [q F/4, (q + 1) F/4) of point p's latent vector (its corner loads are one
+// quarter of the point's), octaves q, q + 4, ... of its Fourier features, and
+// lane 0 of the quad the tail and the zero padding. Octave phases are exact
+// powers of two times p (no double-angle recurrence); FP16/BF16 rows hold
+// 2 cos like the render's. The latent sums run over the corners in the
+// per-lane gather's order, so FP32 rows are the same bits. FP32 latent grids
+// (the training parameters).
+template <class CF>
+__device__ inline void write_row_quad(typename CF::E* row, const LatentSrc& ls, int q, float px, float py, float pz) {
+  using G = typename CF::G;
+  using E = typename CF::E;
+  constexpr int F = CF::F, L = CF::L, FQ = F / 4;
+  int ix, iy, iz;
+  float fx, fy, fz;
+  axis_cell(px, ls.R, ix, fx);
+  axis_cell(py, ls.R, iy, fy);
+  axis_cell(pz, ls.R, iz, fz);
+  const float x0 = 1.0f - fx, x1 = fx, y0 = 1.0f - fy, y1 = fy, z0 = 1.0f - fz, z1 = fz;
+  const unsigned R = (unsigned)ls.R;
+  const unsigned sx = F, sy = R * F, sz = R * R * F;
+  const unsigned base = (unsigned)iz * sz + (unsigned)iy * sy + (unsigned)ix * sx;
+  unsigned off[8];
+  corner_offsets(sx, sy, sz, off);
+  const float w[8] = {x0 * y0 * z0, x1 * y0 * z0, x0 * y1 * z0, x1 * y1 * z0,
+                      x0 * y0 * z1, x1 * y0 * z1, x0 * y1 * z1, x1 * y1 * z1};
+  float z[FQ];
+#pragma unroll
+  for (int j = 0; j < FQ; ++j) z[j] = 0.0f;
+#pragma unroll
+  for (int key = 0; key < 2; ++key) {
+    const void* g = key == 0 ? ls.g0 : ls.g1;
+    if (key == 1 && !g) break;
+    const float kw = key == 0 ? ls.w0 : ls.w1;
+    const __amdgpu_buffer_rsrc_t r = grid_rsrc(g, ls.bytes);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const float wc = w[c] * kw;
+      if constexpr (FQ == 4) {
+        const float4 v = __builtin_bit_cast(float4, load16(r, base * 4u + 16u * (unsigned)q, off[c] * 4u));
+        z[0] = fmaf(wc, v.x, z[0]);
+        z[1] = fmaf(wc, v.y, z[1]);
+        z[2] = fmaf(wc, v.z, z[2]);
+        z[3] = fmaf(wc, v.w, z[3]);
+      } else {
+        static_assert(FQ == 2, "F = 8 or 16");
+        const float2 v = __builtin_bit_cast(float2, load8(r, base * 4u + 8u * (unsigned)q, off[c] * 4u));
+        z[0] = fmaf(wc, v.x, z[0]);
+        z[1] = fmaf(wc, v.y, z[1]);
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < FQ; ++j) row[FQ * q + j] = to_e<E>(z[j]);
+  constexpr float cs = CF::P == kF32 ? 1.0f : 2.0f;  // scale of the cosine block
+  const float pp[3] = {px, py, pz};
+#pragma unroll
+  for (int i = 0; i < L / 4; ++i) {
+    const int k = q + 4 * i;
+    const float sc = (float)(1 << k) * 0.5f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float ph = pp[a] * sc;
+      row[F + 3 * k + a] = to_e<E>(sin_rev(ph));
+      row[F + 3 * L + 3 * k + a] = to_e<E>(cs * cos_rev(ph));
+    }
+  }
+  if (q == 0) {
+#pragma unroll
+    for (int j = G::KF; j < G::KMAIN; ++j) row[j] = to_e<E>(0.0f);
+    row[G::KMAIN + 0] = to_e<E>(px);
+    row[G::KMAIN + 1] = to_e<E>(py);
+    row[G::KMAIN + 2] = to_e<E>(pz);
+    row[G::KMAIN + 3] = to_e<E>(1.0f);
+#pragma unroll
+    for (int j = G::KMAIN + 4; j < G::KROW; ++j) row[j] = to_e<E>(0.0f);
+  }
+}
+
 template <int C, int F, int L, int ACT, int TE, int FM>
 __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDev nd, KeyTimes kt, const float* xyz,
                                                                             const float* times, long long n,
@@ -218,21 +298,36 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
     const long long idx = c * S + lane;
     const bool ok = lane < S && idx < n;
     const float px = npx, py = npy, pz = npz, pt = npt, tg = ntg;
-    // this point's keyframe pair (Sec. 8)
-    int key;
-    float kw;
-    key_pair(kt, nd.K, pt, key, kw);
-    float tfe[G::TIN > 0 ? G::TIN : 1];  // the point's time inputs (Sec. 8)
-    if constexpr (G::TIN > 0) time_features<TE>(time_tau(pt, nd.t_lo, nd.t_hi, nd.t_scale), tfe);
-    if (lane < S) {
+    if constexpr (TE == 0 && FM == 0) {
+      // quad lane >> 2 builds that point's row
+      const int src = lane >> 2;
+      const float qx = __shfl(px, src, 64), qy = __shfl(py, src, 64), qz = __shfl(pz, src, 64);
       if (nd.K == 1) {
-        write_features<CF, false>(feat + lane * G::ROW, make_latent_src(nd, 0, 0.0f), value_role(), px, py, pz,
-                                  tfe, nd.fm);
+        write_row_quad<CF>(feat + src * G::ROW, make_latent_src(nd, 0, 0.0f), lane & 3, qx, qy, qz);
       } else {
-        // per-lane keyframes: the buffer loads of the gather then run once
-        // per distinct keyframe present in the wave
-        write_features<CF, false>(feat + lane * G::ROW, make_latent_src(nd, key, kw), value_role(), px, py, pz,
-                                  tfe, nd.fm);
+        // this point's keyframe pair (Sec. 8)
+        int key;
+        float kw;
+        key_pair(kt, nd.K, __shfl(pt, src, 64), key, kw);
+        write_row_quad<CF>(feat + src * G::ROW, make_latent_src(nd, key, kw), lane & 3, qx, qy, qz);
+      }
+    } else {
+      // this point's keyframe pair (Sec. 8)
+      int key;
+      float kw;
+      key_pair(kt, nd.K, pt, key, kw);
+      float tfe[G::TIN > 0 ? G::TIN : 1];  // the point's time inputs (Sec. 8)
+      if constexpr (G::TIN > 0) time_features<TE>(time_tau(pt, nd.t_lo, nd.t_hi, nd.t_scale), tfe);
+      if (lane < S) {
+        if (nd.K == 1) {
+          write_features<CF, false>(feat + lane * G::ROW, make_latent_src(nd, 0, 0.0f), value_role(), px, py, pz,
+                                    tfe, nd.fm);
+        } else {
+          // per-lane keyframes: the buffer loads of the gather then run once
+          // per distinct keyframe present in the wave
+          write_features<CF, false>(feat + lane * G::ROW, make_latent_src(nd, key, kw), value_role(), px, py, pz,
+                                    tfe, nd.fm);
+        }
       }
     }
     wave_lds_sync();
@@ -636,17 +731,17 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
     const long long idx = c * S + lane;
     const bool ok = lane < S && idx < n;
     const float px = npx, py = npy, pz = npz, pt = npt, tg = ntg;
-    int key;
-    float kw;
-    key_pair(kt, nd.K, pt, key, kw);
-    float tfe[1];
-    if (lane < S) {
+    {
+      // quad lane >> 2 builds that point's row (see fwd_bwd_kernel)
+      const int src = lane >> 2;
+      const float qx = __shfl(px, src, 64), qy = __shfl(py, src, 64), qz = __shfl(pz, src, 64);
       if (nd.K == 1) {
-        write_features<CF, false>(feat + lane * G::ROW, make_latent_src(nd, 0, 0.0f), value_role(), px, py, pz, tfe,
-                                  nd.fm);
+        write_row_quad<CF>(feat + src * G::ROW, make_latent_src(nd, 0, 0.0f), lane & 3, qx, qy, qz);
       } else {
-        write_features<CF, false>(feat + lane * G::ROW, make_latent_src(nd, key, kw), value_role(), px, py, pz, tfe,
-                                  nd.fm);
+        int key;
+        float kw;
+        key_pair(kt, nd.K, __shfl(pt, src, 64), key, kw);
+        write_row_quad<CF>(feat + src * G::ROW, make_latent_src(nd, key, kw), lane & 3, qx, qy, qz);
       }
     }
     wave_lds_sync();
