@@ -292,6 +292,13 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
       ntg = target ? target[j] : dloss[j];
     }
   };
+  // For c = 32 the layer-0 weight-gradient tiles (the largest group) stay in
+  // registers over the wave's chunks and go to the slice once at the end:
+  // the same sums in the same order as the slice's read-modify-write.
+  constexpr bool kResident0 = C == 32;
+  f4 acc0[kResident0 ? MT * TC::NK0 : 1];
+#pragma unroll
+  for (int k = 0; k < (kResident0 ? MT * TC::NK0 : 1); ++k) acc0[k] = f4{0.0f, 0.0f, 0.0f, 0.0f};
   load_point(wave);
   for (long long c = wave; c < nchunks; c += n_waves) {
     // lane l < S owns point c * S + l
@@ -441,7 +448,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
       constexpr int NW = MT * (TC::NK0 > MT ? TC::NK0 : MT);
       f4 oldw[NW], oldb[MT];
       if (i == 0) {
-        load_tiles(TC::tile_l0(0, 0), MT * TC::NK0, oldw);
+        if (!kResident0) load_tiles(TC::tile_l0(0, 0), MT * TC::NK0, oldw);
       } else {
         load_tiles(TC::tile_h(H, i, 0, 0), MT * MT, oldw);
         load_tiles(TC::tile_bias(H, i, 0), MT, oldb);
@@ -485,7 +492,11 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
               const float b = col < G::KROW ? feat[s * G::ROW + col] : 0.0f;
               dw = PR::mma(a, b, dw);
             }
-            put_tile(TC::tile_l0(mo, nk), oldw[mo * TC::NK0 + nk], dw);
+            if constexpr (kResident0) {
+              acc0[mo * TC::NK0 + nk] += dw;
+            } else {
+              put_tile(TC::tile_l0(mo, nk), oldw[mo * TC::NK0 + nk], dw);
+            }
           }
       } else {
         const float* ap = abuf + (i - 1) * S * AS;
@@ -566,6 +577,10 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
                              zbuf[lane * TC::ZS + 4 * q + 2], zbuf[lane * TC::ZS + 4 * q + 3]);
     }
     first = false;
+  }
+  if constexpr (kResident0) {
+#pragma unroll
+    for (int k = 0; k < MT * TC::NK0; ++k) reinterpret_cast<f4*>(slice + TC::tile_l0(k / TC::NK0, k % TC::NK0) * 256)[lane] = acc0[k];
   }
   // ---------------- per-wave partials of the output biases and the loss
 #pragma unroll
@@ -726,6 +741,11 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
       ntg = target[j];
     }
   };
+  // layer-0 weight-gradient tiles in registers for c = 32 (see fwd_bwd_kernel)
+  constexpr bool kResident0 = C == 32;
+  f4 acc0[kResident0 ? MT * T32::NK0 : 1];
+#pragma unroll
+  for (int k = 0; k < (kResident0 ? MT * T32::NK0 : 1); ++k) acc0[k] = zero;
   load_point(wave);
   for (long long c = wave; c < nchunks; c += n_waves) {
     const long long idx = c * S + lane;
@@ -870,7 +890,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
       constexpr int NW = MT * (T32::NK0 > MT ? T32::NK0 : MT);
       f4 oldw[NW], oldb[MT];
       if (i == 0) {
-        load_tiles(T32::tile_l0(0, 0), MT * T32::NK0, oldw);
+        if (!kResident0) load_tiles(T32::tile_l0(0, 0), MT * T32::NK0, oldw);
       } else {
         load_tiles(T32::tile_h(H, i, 0, 0), MT * MT, oldw);
         load_tiles(T32::tile_bias(H, i, 0), MT, oldb);
@@ -919,7 +939,11 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
 #pragma unroll
           for (int mo = 0; mo < MT; ++mo) {
             const VT a = *reinterpret_cast<const VT*>(dbuf + (16 * mo + nn) * HSTR + 4 * g);
-            put_tile(T32::tile_l0(mo, nk), oldw[mo * T32::NK0 + nk], PR::mmt(a, b, zero) * cs);
+            if constexpr (kResident0) {
+              acc0[mo * T32::NK0 + nk] += PR::mmt(a, b, zero) * cs;
+            } else {
+              put_tile(T32::tile_l0(mo, nk), oldw[mo * T32::NK0 + nk], PR::mmt(a, b, zero) * cs);
+            }
           }
         }
       } else {
@@ -975,6 +999,11 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
                              zbuf[lane * TH::ZS + 4 * q + 2], zbuf[lane * TH::ZS + 4 * q + 3]);
     }
     first = false;
+  }
+  if constexpr (kResident0) {
+#pragma unroll
+    for (int k = 0; k < MT * T32::NK0; ++k)
+      reinterpret_cast<f4*>(slice + T32::tile_l0(k / T32::NK0, k % T32::NK0) * 256)[lane] = acc0[k];
   }
   dbo_acc *= inv_gs;
 #pragma unroll
