@@ -295,10 +295,16 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
   // For c = 32 the layer-0 weight-gradient tiles (the largest group) stay in
   // registers over the wave's chunks and go to the slice once at the end:
   // the same sums in the same order as the slice's read-modify-write.
+  // So do the output layer's and the last hidden layer's.
   constexpr bool kResident0 = C == 32;
-  f4 acc0[kResident0 ? MT * TC::NK0 : 1];
+  constexpr int NR0 = kResident0 ? MT * TC::NK0 : 1, NRO = kResident0 ? MT : 1, NRH = kResident0 ? MT * MT : 1;
+  f4 acc0[NR0], accO[NRO], accH[NRH];
 #pragma unroll
-  for (int k = 0; k < (kResident0 ? MT * TC::NK0 : 1); ++k) acc0[k] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k = 0; k < NR0; ++k) acc0[k] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int k = 0; k < NRO; ++k) accO[k] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int k = 0; k < NRH; ++k) accH[k] = f4{0.0f, 0.0f, 0.0f, 0.0f};
   load_point(wave);
   for (long long c = wave; c < nchunks; c += n_waves) {
     // lane l < S owns point c * S + l
@@ -414,7 +420,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
     // ---------------- output layer weights: dW_H[o][k] = sum_s dy[o][s] h[k][s]
     const float* alast = abuf + (H - 1) * S * AS;
     f4 oldo[MT];
-    load_tiles(TC::tile_out(H, 0), MT, oldo);
+    if (!kResident0) load_tiles(TC::tile_out(H, 0), MT, oldo);
 #pragma unroll
     for (int nk = 0; nk < MT; ++nk) {
       f4 dw = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -425,7 +431,11 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
         const float b = act_el<ACT, false>(alast[s * AS + 16 * nk + nn], value_role());
         dw = PR::mma(a, b, dw);
       }
-      put_tile(TC::tile_out(H, nk), oldo[nk], dw);
+      if constexpr (kResident0) {
+        accO[nk] += dw;
+      } else {
+        put_tile(TC::tile_out(H, nk), oldo[nk], dw);
+      }
     }
     // ---------------- backward through the activated layers
     f4 dh[NTC][MT];  // d L / d h_i in D layout, per N-tile
@@ -450,7 +460,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
       if (i == 0) {
         if (!kResident0) load_tiles(TC::tile_l0(0, 0), MT * TC::NK0, oldw);
       } else {
-        load_tiles(TC::tile_h(H, i, 0, 0), MT * MT, oldw);
+        if (!kResident0 || i != H - 1) load_tiles(TC::tile_h(H, i, 0, 0), MT * MT, oldw);
         load_tiles(TC::tile_bias(H, i, 0), MT, oldb);
       }
       const float* ai = abuf + i * S * AS;
@@ -512,7 +522,11 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
               const float b = act_el<ACT, false>(ap[s * AS + 16 * nk + nn], value_role());
               dw = PR::mma(a, b, dw);
             }
-            put_tile(TC::tile_h(H, i, mo, nk), oldw[mo * MT + nk], dw);
+            if (kResident0 && i == H - 1) {
+              accH[mo * MT + nk] += dw;
+            } else {
+              put_tile(TC::tile_h(H, i, mo, nk), oldw[mo * MT + nk], dw);
+            }
           }
       }
       if (i >= 1) {
@@ -580,7 +594,15 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
   }
   if constexpr (kResident0) {
 #pragma unroll
-    for (int k = 0; k < MT * TC::NK0; ++k) reinterpret_cast<f4*>(slice + TC::tile_l0(k / TC::NK0, k % TC::NK0) * 256)[lane] = acc0[k];
+    for (int k = 0; k < MT * TC::NK0; ++k)
+      reinterpret_cast<f4*>(slice + TC::tile_l0(k / TC::NK0, k % TC::NK0) * 256)[lane] = acc0[k];
+#pragma unroll
+    for (int k = 0; k < MT; ++k) reinterpret_cast<f4*>(slice + TC::tile_out(H, k) * 256)[lane] = accO[k];
+    if (H >= 2) {
+#pragma unroll
+      for (int k = 0; k < MT * MT; ++k)
+        reinterpret_cast<f4*>(slice + TC::tile_h(H, H - 1, k / MT, k % MT) * 256)[lane] = accH[k];
+    }
   }
   // ---------------- per-wave partials of the output biases and the loss
 #pragma unroll
@@ -743,9 +765,14 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
   };
   // layer-0 weight-gradient tiles in registers for c = 32 (see fwd_bwd_kernel)
   constexpr bool kResident0 = C == 32;
-  f4 acc0[kResident0 ? MT * T32::NK0 : 1];
+  constexpr int NR0 = kResident0 ? MT * T32::NK0 : 1, NRO = kResident0 ? MT : 1, NRH = kResident0 ? MT * MT : 1;
+  f4 acc0[NR0], accO[NRO], accH[NRH];
 #pragma unroll
-  for (int k = 0; k < (kResident0 ? MT * T32::NK0 : 1); ++k) acc0[k] = zero;
+  for (int k = 0; k < NR0; ++k) acc0[k] = zero;
+#pragma unroll
+  for (int k = 0; k < NRO; ++k) accO[k] = zero;
+#pragma unroll
+  for (int k = 0; k < NRH; ++k) accH[k] = zero;
   load_point(wave);
   for (long long c = wave; c < nchunks; c += n_waves) {
     const long long idx = c * S + lane;
@@ -860,7 +887,8 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
     {
       f4 old[MT];
 #pragma unroll
-      for (int nk = 0; nk < MT; ++nk) old[nk] = reinterpret_cast<const f4*>(slice + T32::tile_out(H, nk) * 256)[lane];
+      for (int nk = 0; nk < MT; ++nk)
+        if (!kResident0) old[nk] = reinterpret_cast<const f4*>(slice + T32::tile_out(H, nk) * 256)[lane];
       const E* hl = hbuf + (H - 1) * C * HSTR;
       VT ay;
 #pragma unroll
@@ -868,7 +896,11 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
 #pragma unroll
       for (int nk = 0; nk < MT; ++nk) {
         const VT b = *reinterpret_cast<const VT*>(hl + (16 * nk + nn) * HSTR + 4 * g);
-        put_tile(T32::tile_out(H, nk), old[nk], PR::mmt(ay, b, zero) * inv_gs);
+        if constexpr (kResident0) {
+          accO[nk] += PR::mmt(ay, b, zero) * inv_gs;
+        } else {
+          put_tile(T32::tile_out(H, nk), old[nk], PR::mmt(ay, b, zero) * inv_gs);
+        }
       }
     }
     // ---------------- backward
@@ -892,7 +924,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
       if (i == 0) {
         if (!kResident0) load_tiles(T32::tile_l0(0, 0), MT * T32::NK0, oldw);
       } else {
-        load_tiles(T32::tile_h(H, i, 0, 0), MT * MT, oldw);
+        if (!kResident0 || i != H - 1) load_tiles(T32::tile_h(H, i, 0, 0), MT * MT, oldw);
         load_tiles(T32::tile_bias(H, i, 0), MT, oldb);
       }
       const h4* ad = reinterpret_cast<const h4*>(actd + i * TH::ACTD);
@@ -954,7 +986,11 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
 #pragma unroll
           for (int mo = 0; mo < MT; ++mo) {
             const VT a = *reinterpret_cast<const VT*>(dbuf + (16 * mo + nn) * HSTR + 4 * g);
-            put_tile(T32::tile_h(H, i, mo, nk), oldw[mo * MT + nk], PR::mmt(a, b, zero) * inv_gs);
+            if (kResident0 && i == H - 1) {
+              accH[mo * MT + nk] += PR::mmt(a, b, zero) * inv_gs;
+            } else {
+              put_tile(T32::tile_h(H, i, mo, nk), oldw[mo * MT + nk], PR::mmt(a, b, zero) * inv_gs);
+            }
           }
         }
       }
@@ -1004,6 +1040,13 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
 #pragma unroll
     for (int k = 0; k < MT * T32::NK0; ++k)
       reinterpret_cast<f4*>(slice + T32::tile_l0(k / T32::NK0, k % T32::NK0) * 256)[lane] = acc0[k];
+#pragma unroll
+    for (int k = 0; k < MT; ++k) reinterpret_cast<f4*>(slice + T32::tile_out(H, k) * 256)[lane] = accO[k];
+    if (H >= 2) {
+#pragma unroll
+      for (int k = 0; k < MT * MT; ++k)
+        reinterpret_cast<f4*>(slice + T32::tile_h(H, H - 1, k / MT, k % MT) * 256)[lane] = accH[k];
+    }
   }
   dbo_acc *= inv_gs;
 #pragma unroll
