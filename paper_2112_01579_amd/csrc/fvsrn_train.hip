@@ -54,7 +54,8 @@ struct TrainCfg {
   static constexpr int DY = 64 * 4;                 // dL/dy [output][sample]
   static_assert(4 * S <= 64, "four outputs of S samples must fit the dL/dy buffer");
   static constexpr int ZBUF = S * ZS * 4;
-  __host__ __device__ static int wave_bytes(int H) { return FEAT + abuf_bytes(H) + DBUF + DY + ZBUF; }
+  static constexpr int BACC = MT * 4 * 16;          // one layer's bias sums: [M-tile][row group] f4
+  __host__ __device__ static int wave_bytes(int H) { return FEAT + abuf_bytes(H) + DBUF + DY + ZBUF + (H - 1) * BACC; }
   // The backward pass needs W^T. For c = 32 a transposed copy of each hidden
   // layer and of W_0's latent columns is staged once per workgroup (14 KiB at
   // H = 4: one wave of seven fewer per CU, but lane-contiguous reads); wider
@@ -78,6 +79,29 @@ struct TrainCfg {
   __host__ __device__ static int tile_out(int H, int nk) { return MT * NK0 + (H - 1) * MT * MT + nk; }
   __host__ __device__ static int tile_bias(int H, int i, int mt) { return MT * NK0 + (H - 1) * MT * MT + MT + (i - 1) * MT + mt; }
 };
+
+// Sum over the 16 lanes of this lane's row (lanes with the same lane >> 4),
+// in DPP steps that every lane takes alike: pairs (quad_perm 1 0 3 2), quads
+// (quad_perm 2 3 0 1), halves of the row (row_half_mirror), the row
+// (row_mirror); every lane of the row receives the same sum.
+__device__ inline float dpp_add(float v, int ctrl_sel) {
+  int t;
+  switch (ctrl_sel) {
+    case 0: t = __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false); break;
+    case 1: t = __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, false); break;
+    case 2: t = __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x141, 0xF, 0xF, false); break;
+    default: t = __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x140, 0xF, 0xF, false); break;
+  }
+  return v + __builtin_bit_cast(float, t);
+}
+
+__device__ inline f4 row16_sum(f4 v) {
+#pragma unroll
+  for (int st = 0; st < 4; ++st)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = dpp_add(v[j], st);
+  return v;
+}
 
 template <int ACT>
 __device__ inline float act_d(float a) {  // d act / d x at pre-activation a (revolutions for periodic acts)
@@ -241,6 +265,10 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
   float* dbuf = reinterpret_cast<float*>(wbase + TC::FEAT + TC::abuf_bytes(H));
   float* dy = reinterpret_cast<float*>(wbase + TC::FEAT + TC::abuf_bytes(H) + TC::DBUF);
   float* zbuf = reinterpret_cast<float*>(wbase + TC::FEAT + TC::abuf_bytes(H) + TC::DBUF + TC::DY);
+  // bias gradients of the hidden layers, summed over the chunk's points in the
+  // wave and accumulated here over its chunks ([layer][M-tile][row group])
+  f4* bacc = reinterpret_cast<f4*>(wbase + TC::FEAT + TC::abuf_bytes(H) + TC::DBUF + TC::DY + TC::ZBUF);
+  for (int e = lane; e < (H - 1) * MT * 4; e += kWave) bacc[e] = f4{0.0f, 0.0f, 0.0f, 0.0f};
   float* slice = ws + (size_t)wave * TC::slice(H);
   const float* W0 = reinterpret_cast<const float*>(smem);
   const char* wout_p = smem + G::W0A + (H - 1) * G::HID;
@@ -456,12 +484,11 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
     }
     for (int i = H - 1; i >= 0; --i) {
       constexpr int NW = MT * (TC::NK0 > MT ? TC::NK0 : MT);
-      f4 oldw[NW], oldb[MT];
+      f4 oldw[NW];
       if (i == 0) {
         if (!kResident0) load_tiles(TC::tile_l0(0, 0), MT * TC::NK0, oldw);
       } else {
         if (!kResident0 || i != H - 1) load_tiles(TC::tile_h(H, i, 0, 0), MT * MT, oldw);
-        load_tiles(TC::tile_bias(H, i, 0), MT, oldb);
       }
       const float* ai = abuf + i * S * AS;
       // delta_i = d L / d x_i = (d L / d h_i) * act'(x_i), x = W h + b in
@@ -482,9 +509,12 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
           dbias[mt] += da;
         }
       if (i >= 1) {
-        // partial bias gradient of this lane's 4 samples (summed over lanes by the reduction)
+        // bias gradient: this lane's samples, summed over the row's 16 points
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) put_tile(TC::tile_bias(H, i, mt), oldb[mt], dbias[mt]);
+        for (int mt = 0; mt < MT; ++mt) {
+          const f4 sum = row16_sum(dbias[mt]);
+          if (nn == 0) bacc[((i - 1) * MT + mt) * 4 + g] += sum;
+        }
       }
       wave_lds_sync();
       // dW_i = delta_i h_i^T over the chunk's samples
@@ -604,6 +634,15 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
         reinterpret_cast<f4*>(slice + TC::tile_h(H, H - 1, k / MT, k % MT) * 256)[lane] = accH[k];
     }
   }
+  // the bias sums into the slice's per-lane partial layout: lane 16 g holds
+  // row group g's sums, the row's other lanes zero
+  for (int i = 1; i < H; ++i)
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const f4 b = bacc[((i - 1) * MT + mt) * 4 + g];
+      const f4 zero4 = {0.0f, 0.0f, 0.0f, 0.0f};
+      reinterpret_cast<f4*>(slice + TC::tile_bias(H, i, mt) * 256)[lane] = nn == 0 ? b : zero4;
+    }
   // ---------------- per-wave partials of the output biases and the loss
 #pragma unroll
   for (int o = 0; o < 4; ++o) slice[TC::tiles(H) * 256 + 64 * o + lane] = dbo_acc[o];
@@ -646,7 +685,8 @@ struct TrainCfgH {
   static constexpr int DY = 64 * 4;
   static constexpr int ZS = 20;
   static constexpr int ZBUF = S * ZS * 4;
-  __host__ __device__ static int wave_bytes(int H) { return FEAT + H * CH + H * ACTD + CH + DY + ZBUF; }
+  static constexpr int BACC = MT * 4 * 16;     // one layer's bias sums: [M-tile][row group] f4
+  __host__ __device__ static int wave_bytes(int H) { return FEAT + H * CH + H * ACTD + CH + DY + ZBUF + (H - 1) * BACC; }
   // transposed fragments: W_i^T (i = 1..H-1) and W_0's latent columns
   static constexpr int WBA = MT * G::HS32 * kWave * 16;
   static constexpr int WB = WBA + MT * G::HS16 * kWave * 8;
@@ -726,6 +766,9 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
   E* dbuf = reinterpret_cast<E*>(actd + H * TH::ACTD);  // delta_i: [channel][point]
   float* dy = reinterpret_cast<float*>(reinterpret_cast<char*>(dbuf) + TH::CH);
   float* zbuf = dy + 64;
+  // hidden layers' bias gradients over the wave's chunks (see fwd_bwd_kernel)
+  f4* bacc = reinterpret_cast<f4*>(reinterpret_cast<char*>(zbuf) + TH::ZBUF);
+  for (int e = lane; e < (H - 1) * MT * 4; e += kWave) bacc[e] = f4{0.0f, 0.0f, 0.0f, 0.0f};
   float* slice = ws + (size_t)wave * T32::slice(H);
   const VA* W0A = reinterpret_cast<const VA*>(smem);
   const VA* W0T = reinterpret_cast<const VA*>(smem + G::W0A);
@@ -920,12 +963,11 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
     for (int i = H - 1; i >= 0; --i) {
       // this layer's running sums: dW_i, and for i >= 1 the bias partials
       constexpr int NW = MT * (T32::NK0 > MT ? T32::NK0 : MT);
-      f4 oldw[NW], oldb[MT];
+      f4 oldw[NW];
       if (i == 0) {
         if (!kResident0) load_tiles(T32::tile_l0(0, 0), MT * T32::NK0, oldw);
       } else {
         if (!kResident0 || i != H - 1) load_tiles(T32::tile_h(H, i, 0, 0), MT * MT, oldw);
-        load_tiles(T32::tile_bias(H, i, 0), MT, oldb);
       }
       const h4* ad = reinterpret_cast<const h4*>(actd + i * TH::ACTD);
       // delta_i = (d L / d h_i) * act'(a_i), world units
@@ -940,7 +982,10 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
           da[j] = dv[mt][j];
           dbuf[(16 * mt + 4 * g + j) * HSTR + nn] = (E)dv[mt][j];
         }
-        if (i >= 1) put_tile(T32::tile_bias(H, i, mt), oldb[mt], da * inv_gs);
+        if (i >= 1) {
+          const f4 sum = row16_sum(da * inv_gs);
+          if (nn == 0) bacc[((i - 1) * MT + mt) * 4 + g] += sum;
+        }
       }
       VA bD[HS32];
       VT bDT;
@@ -1048,6 +1093,12 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
         reinterpret_cast<f4*>(slice + T32::tile_h(H, H - 1, k / MT, k % MT) * 256)[lane] = accH[k];
     }
   }
+  for (int i = 1; i < H; ++i)
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const f4 b = bacc[((i - 1) * MT + mt) * 4 + g];
+      reinterpret_cast<f4*>(slice + T32::tile_bias(H, i, mt) * 256)[lane] = nn == 0 ? b : zero;
+    }
   dbo_acc *= inv_gs;
 #pragma unroll
   for (int o = 0; o < 4; ++o) slice[T32::tiles(H) * 256 + 64 * o + lane] = dbo_acc[o];
