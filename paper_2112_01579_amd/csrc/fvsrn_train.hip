@@ -323,9 +323,9 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
   // For c = 32 the layer-0 weight-gradient tiles (the largest group) stay in
   // registers over the wave's chunks and go to the slice once at the end:
   // the same sums in the same order as the slice's read-modify-write.
-  // So do the output layer's and the last hidden layer's.
+  // So do the last hidden layer's, and at every width the output layer's.
   constexpr bool kResident0 = C == 32;
-  constexpr int NR0 = kResident0 ? MT * TC::NK0 : 1, NRO = kResident0 ? MT : 1, NRH = kResident0 ? MT * MT : 1;
+  constexpr int NR0 = kResident0 ? MT * TC::NK0 : 1, NRO = MT, NRH = kResident0 ? MT * MT : 1;
   f4 acc0[NR0], accO[NRO], accH[NRH];
 #pragma unroll
   for (int k = 0; k < NR0; ++k) acc0[k] = f4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -447,8 +447,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
     wave_lds_sync();
     // ---------------- output layer weights: dW_H[o][k] = sum_s dy[o][s] h[k][s]
     const float* alast = abuf + (H - 1) * S * AS;
-    f4 oldo[MT];
-    if (!kResident0) load_tiles(TC::tile_out(H, 0), MT, oldo);
+
 #pragma unroll
     for (int nk = 0; nk < MT; ++nk) {
       f4 dw = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -459,11 +458,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
         const float b = act_el<ACT, false>(alast[s * AS + 16 * nk + nn], value_role());
         dw = PR::mma(a, b, dw);
       }
-      if constexpr (kResident0) {
-        accO[nk] += dw;
-      } else {
-        put_tile(TC::tile_out(H, nk), oldo[nk], dw);
-      }
+      accO[nk] += dw;
     }
     // ---------------- backward through the activated layers
     f4 dh[NTC][MT];  // d L / d h_i in D layout, per N-tile
@@ -626,14 +621,14 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
 #pragma unroll
     for (int k = 0; k < MT * TC::NK0; ++k)
       reinterpret_cast<f4*>(slice + TC::tile_l0(k / TC::NK0, k % TC::NK0) * 256)[lane] = acc0[k];
-#pragma unroll
-    for (int k = 0; k < MT; ++k) reinterpret_cast<f4*>(slice + TC::tile_out(H, k) * 256)[lane] = accO[k];
     if (H >= 2) {
 #pragma unroll
       for (int k = 0; k < MT * MT; ++k)
         reinterpret_cast<f4*>(slice + TC::tile_h(H, H - 1, k / MT, k % MT) * 256)[lane] = accH[k];
     }
   }
+#pragma unroll
+  for (int k = 0; k < MT; ++k) reinterpret_cast<f4*>(slice + TC::tile_out(H, k) * 256)[lane] = accO[k];
   // the bias sums into the slice's per-lane partial layout: lane 16 g holds
   // row group g's sums, the row's other lanes zero
   for (int i = 1; i < H; ++i)
@@ -806,9 +801,10 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
       ntg = target[j];
     }
   };
-  // layer-0 weight-gradient tiles in registers for c = 32 (see fwd_bwd_kernel)
+  // layer-0 and last hidden layer's weight-gradient tiles in registers for
+  // c = 32, the output layer's at every width (see fwd_bwd_kernel)
   constexpr bool kResident0 = C == 32;
-  constexpr int NR0 = kResident0 ? MT * T32::NK0 : 1, NRO = kResident0 ? MT : 1, NRH = kResident0 ? MT * MT : 1;
+  constexpr int NR0 = kResident0 ? MT * T32::NK0 : 1, NRO = MT, NRH = kResident0 ? MT * MT : 1;
   f4 acc0[NR0], accO[NRO], accH[NRH];
 #pragma unroll
   for (int k = 0; k < NR0; ++k) acc0[k] = zero;
@@ -928,10 +924,6 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
     wave_lds_sync();
     // ---------------- output weights: dW_H[o][k] = sum_s dy[o][s] h_{H-1}[k][s]
     {
-      f4 old[MT];
-#pragma unroll
-      for (int nk = 0; nk < MT; ++nk)
-        if (!kResident0) old[nk] = reinterpret_cast<const f4*>(slice + T32::tile_out(H, nk) * 256)[lane];
       const E* hl = hbuf + (H - 1) * C * HSTR;
       VT ay;
 #pragma unroll
@@ -939,11 +931,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
 #pragma unroll
       for (int nk = 0; nk < MT; ++nk) {
         const VT b = *reinterpret_cast<const VT*>(hl + (16 * nk + nn) * HSTR + 4 * g);
-        if constexpr (kResident0) {
-          accO[nk] += PR::mmt(ay, b, zero) * inv_gs;
-        } else {
-          put_tile(T32::tile_out(H, nk), old[nk], PR::mmt(ay, b, zero) * inv_gs);
-        }
+        accO[nk] += PR::mmt(ay, b, zero) * inv_gs;
       }
     }
     // ---------------- backward
@@ -1085,14 +1073,14 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
 #pragma unroll
     for (int k = 0; k < MT * T32::NK0; ++k)
       reinterpret_cast<f4*>(slice + T32::tile_l0(k / T32::NK0, k % T32::NK0) * 256)[lane] = acc0[k];
-#pragma unroll
-    for (int k = 0; k < MT; ++k) reinterpret_cast<f4*>(slice + T32::tile_out(H, k) * 256)[lane] = accO[k];
     if (H >= 2) {
 #pragma unroll
       for (int k = 0; k < MT * MT; ++k)
         reinterpret_cast<f4*>(slice + T32::tile_h(H, H - 1, k / MT, k % MT) * 256)[lane] = accH[k];
     }
   }
+#pragma unroll
+  for (int k = 0; k < MT; ++k) reinterpret_cast<f4*>(slice + T32::tile_out(H, k) * 256)[lane] = accO[k];
   for (int i = 1; i < H; ++i)
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
