@@ -1449,6 +1449,67 @@ constexpr bool half_train_ok() {
          (Geo<kF16, C, F, L>::KROW + 15) / 16 == (Geo<kF32, C, F, L>::KROW + 15) / 16;
 }
 
+// The latent gradient in two passes, for a single keyframe whose cells hold
+// few points each (an average of at most 16): cell_partials_kernel sums, per
+// cell and corner, the trilinear-weighted dL/dz of the cell's points (each
+// point read once, by the F/4 threads of its cell), and vertex_sum_kernel adds
+// every vertex's (up to) eight cell-corner sums in a fixed order. Against the
+// one-pass gather (latent_grad_kernel), which reads each point once per
+// vertex of its cell, this moves about a third of the bytes.
+template <int F>
+__global__ void cell_partials_kernel(const float* xyz, int R, long long ncell, const int* off, const int* order,
+                                     const float* dz, float* part) {
+  constexpr int NQ = F / 4;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < ncell * NQ;
+       t += (long long)gridDim.x * blockDim.x) {
+    const long long c = t / NQ;
+    const int qd = (int)(t % NQ);
+    f4 acc[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) acc[b] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int s = off[c]; s < off[c + 1]; ++s) {
+      const int p = order[s];
+      int ix, iy, iz;
+      float fx, fy, fz;
+      axis_cell(xyz[3 * p], R, ix, fx);
+      axis_cell(xyz[3 * p + 1], R, iy, fy);
+      axis_cell(xyz[3 * p + 2], R, iz, fz);
+      const f4 d = reinterpret_cast<const f4*>(dz + (long long)p * F)[qd];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
+        const float w = (bx ? fx : 1.0f - fx) * (by ? fy : 1.0f - fy) * (bz ? fz : 1.0f - fz);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[b][j] = fmaf(w, d[j], acc[b][j]);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < 8; ++b) reinterpret_cast<f4*>(part + (c * 8 + b) * F)[qd] = acc[b];
+  }
+}
+
+template <int F>
+__global__ void vertex_sum_kernel(int R, const float* part, float* d_latent) {
+  constexpr int NQ = F / 4;
+  const long long nv = (long long)R * R * R;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < nv * NQ;
+       t += (long long)gridDim.x * blockDim.x) {
+    const long long v = t / NQ;
+    const int qd = (int)(t % NQ);
+    const int vx = (int)(v % R), vy = (int)((v / R) % R), vz = (int)(v / ((long long)R * R));
+    f4 sum = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int cx = vx - (b & 1), cy = vy - ((b >> 1) & 1), cz = vz - (b >> 2);
+      if (cx >= 0 && cx <= R - 2 && cy >= 0 && cy <= R - 2 && cz >= 0 && cz <= R - 2) {
+        const long long c = ((long long)cz * (R - 1) + cy) * (R - 1) + cx;
+        sum += reinterpret_cast<const f4*>(part + (c * 8 + b) * F)[qd];
+      }
+    }
+    reinterpret_cast<f4*>(d_latent + v * F)[qd] = sum;
+  }
+}
+
 template <int C, int F, int L, int ACT, int TE = 0, int FM = 0>
 struct TrainEntry {
   using TC = TrainCfg<C, F, L, ACT, TE, FM>;
@@ -1560,20 +1621,33 @@ struct TrainEntry {
                          (const int*)cell, (const int*)rank, (const int*)off, n, order);
       if ((rc = check_launch())) return rc;
     }
-    // lanes per cell: about one per four points of an average cell, at most 8
-    int lpc_log2 = 0;
-    while (lpc_log2 < 3 && (4LL << lpc_log2) * ncell < n) ++lpc_log2;
-    const long long nthreads = (long long)nd.K * nd.R * nd.R * nd.R * (8 << lpc_log2);
-    hipLaunchKernelGGL((latent_grad_kernel<F>), dim3(grid_blocks(nthreads, 256, device_cus() * 32)), dim3(256), 0, st,
-                       xyz, times, kt, nd.K, nd.R, nd.key_stride, (const int*)off, (const int*)order, (const float*)dz,
-                       d_latent, lpc_log2);
-    if ((rc = check_launch())) return rc;
     const int sl = TC::slice(H), ng = n_groups(n);
     float* partial = (float*)ws + (size_t)nw * sl;
     hipLaunchKernelGGL(slice_sum_kernel, dim3((sl + 255) / 256, ng), dim3(256), 0, st, (const float*)ws, nw, sl,
                        partial);
     rc = check_launch();
     if (rc) return rc;
+    // the latent gradient; the two-pass form writes its cell-corner sums over
+    // the wave slices, which slice_sum_kernel has finished reading
+    const long long nv = (long long)nd.R * nd.R * nd.R;
+    if (nd.K == 1 && n <= 16LL * ncell && (long long)ncell * 8 * F <= (long long)nw * sl) {
+      hipLaunchKernelGGL((cell_partials_kernel<F>), dim3(grid_blocks((long long)ncell * (F / 4), 256, device_cus() * 32)),
+                         dim3(256), 0, st, xyz, nd.R, (long long)ncell, (const int*)off, (const int*)order,
+                         (const float*)dz, (float*)ws);
+      if ((rc = check_launch())) return rc;
+      hipLaunchKernelGGL((vertex_sum_kernel<F>), dim3(grid_blocks(nv * (F / 4), 256, device_cus() * 32)), dim3(256), 0,
+                         st, nd.R, (const float*)ws, d_latent);
+      if ((rc = check_launch())) return rc;
+    } else {
+      // lanes per cell: about one per four points of an average cell, at most 8
+      int lpc_log2 = 0;
+      while (lpc_log2 < 3 && (4LL << lpc_log2) * ncell < n) ++lpc_log2;
+      const long long nthreads = (long long)nd.K * nv * (8 << lpc_log2);
+      hipLaunchKernelGGL((latent_grad_kernel<F>), dim3(grid_blocks(nthreads, 256, device_cus() * 32)), dim3(256), 0,
+                         st, xyz, times, kt, nd.K, nd.R, nd.key_stride, (const int*)off, (const int*)order,
+                         (const float*)dz, d_latent, lpc_log2);
+      if ((rc = check_launch())) return rc;
+    }
     const long long nwts = (long long)C * TC::G::K0IN + C + (long long)(H - 1) * (C * C + C) +
                            (long long)nd.NO * (C + 1);
     const float loss_scale = target && n > 0 ? 1.0f / (float)n : 1.0f;
