@@ -1449,25 +1449,29 @@ constexpr bool half_train_ok() {
          (Geo<kF16, C, F, L>::KROW + 15) / 16 == (Geo<kF32, C, F, L>::KROW + 15) / 16;
 }
 
-// The latent gradient in two passes, for a single keyframe whose cells hold
-// few points each (an average of at most 16): cell_partials_kernel sums, per
-// cell and corner, the trilinear-weighted dL/dz of the cell's points (each
-// point read once, by the F/4 threads of its cell), and vertex_sum_kernel adds
-// every vertex's (up to) eight cell-corner sums in a fixed order. Against the
-// one-pass gather (latent_grad_kernel), which reads each point once per
-// vertex of its cell, this moves about a third of the bytes.
+// The latent gradient in two passes, for a single keyframe:
+// cell_partials_kernel sums, per cell, corner and point subset (points
+// off[c] + sub, + 2^sub_log2, ...: 2^sub_log2 subsets keep dense cells'
+// loops short), the trilinear-weighted dL/dz of the cell's points (each point
+// read once, by the F/4 threads of its subset), and vertex_sum_kernel adds
+// every vertex's cell-corner sums over its (up to) eight cells and their
+// subsets in a fixed order. Against the one-pass gather (latent_grad_kernel),
+// which reads each point once per vertex of its cell, this moves about a
+// third of the bytes.
 template <int F>
-__global__ void cell_partials_kernel(const float* xyz, int R, long long ncell, const int* off, const int* order,
-                                     const float* dz, float* part) {
+__global__ void cell_partials_kernel(const float* xyz, int R, long long ncell, int sub_log2, const int* off,
+                                     const int* order, const float* dz, float* part) {
   constexpr int NQ = F / 4;
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < ncell * NQ;
+  const int nsub = 1 << sub_log2;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < ncell * nsub * NQ;
        t += (long long)gridDim.x * blockDim.x) {
-    const long long c = t / NQ;
-    const int qd = (int)(t % NQ);
+    const long long cs = t / NQ;  // cell * nsub + subset
+    const long long c = cs >> sub_log2;
+    const int sub = (int)(cs & (nsub - 1)), qd = (int)(t % NQ);
     f4 acc[8];
 #pragma unroll
     for (int b = 0; b < 8; ++b) acc[b] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int s = off[c]; s < off[c + 1]; ++s) {
+    for (int s = off[c] + sub; s < off[c + 1]; s += nsub) {
       const int p = order[s];
       int ix, iy, iz;
       float fx, fy, fz;
@@ -1484,12 +1488,12 @@ __global__ void cell_partials_kernel(const float* xyz, int R, long long ncell, c
       }
     }
 #pragma unroll
-    for (int b = 0; b < 8; ++b) reinterpret_cast<f4*>(part + (c * 8 + b) * F)[qd] = acc[b];
+    for (int b = 0; b < 8; ++b) reinterpret_cast<f4*>(part + (((c * 8 + b) << sub_log2) + sub) * F)[qd] = acc[b];
   }
 }
 
 template <int F>
-__global__ void vertex_sum_kernel(int R, const float* part, float* d_latent) {
+__global__ void vertex_sum_kernel(int R, int sub_log2, const float* part, float* d_latent) {
   constexpr int NQ = F / 4;
   const long long nv = (long long)R * R * R;
   for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < nv * NQ;
@@ -1503,7 +1507,8 @@ __global__ void vertex_sum_kernel(int R, const float* part, float* d_latent) {
       const int cx = vx - (b & 1), cy = vy - ((b >> 1) & 1), cz = vz - (b >> 2);
       if (cx >= 0 && cx <= R - 2 && cy >= 0 && cy <= R - 2 && cz >= 0 && cz <= R - 2) {
         const long long c = ((long long)cz * (R - 1) + cy) * (R - 1) + cx;
-        sum += reinterpret_cast<const f4*>(part + (c * 8 + b) * F)[qd];
+        for (int sub = 0; sub < (1 << sub_log2); ++sub)
+          sum += reinterpret_cast<const f4*>(part + (((c * 8 + b) << sub_log2) + sub) * F)[qd];
       }
     }
     reinterpret_cast<f4*>(d_latent + v * F)[qd] = sum;
@@ -1630,13 +1635,17 @@ struct TrainEntry {
     // the latent gradient; the two-pass form writes its cell-corner sums over
     // the wave slices, which slice_sum_kernel has finished reading
     const long long nv = (long long)nd.R * nd.R * nd.R;
-    if (nd.K == 1 && n <= 16LL * ncell && (long long)ncell * 8 * F <= (long long)nw * sl) {
-      hipLaunchKernelGGL((cell_partials_kernel<F>), dim3(grid_blocks((long long)ncell * (F / 4), 256, device_cus() * 32)),
-                         dim3(256), 0, st, xyz, nd.R, (long long)ncell, (const int*)off, (const int*)order,
+    // point subsets per cell: about one per 16 points of an average cell, at most 8
+    int sub_log2 = 0;
+    while (sub_log2 < 3 && (16LL << sub_log2) * ncell < n) ++sub_log2;
+    if (nd.K == 1 && ((long long)ncell * 8 * F << sub_log2) <= (long long)nw * sl) {
+      hipLaunchKernelGGL((cell_partials_kernel<F>),
+                         dim3(grid_blocks(((long long)ncell << sub_log2) * (F / 4), 256, device_cus() * 32)), dim3(256),
+                         0, st, xyz, nd.R, (long long)ncell, sub_log2, (const int*)off, (const int*)order,
                          (const float*)dz, (float*)ws);
       if ((rc = check_launch())) return rc;
       hipLaunchKernelGGL((vertex_sum_kernel<F>), dim3(grid_blocks(nv * (F / 4), 256, device_cus() * 32)), dim3(256), 0,
-                         st, nd.R, (const float*)ws, d_latent);
+                         st, nd.R, sub_log2, (const float*)ws, d_latent);
       if ((rc = check_launch())) return rc;
     } else {
       // lanes per cell: about one per four points of an average cell, at most 8
