@@ -801,17 +801,18 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
       ntg = target[j];
     }
   };
-  // layer-0 and last hidden layer's weight-gradient tiles in registers for
-  // c = 32, the output layer's at every width (see fwd_bwd_kernel)
+  // layer-0 and the last two hidden layers' weight-gradient tiles in
+  // registers for c = 32, the output layer's at every width (see
+  // fwd_bwd_kernel, which keeps one hidden layer's: a second spills there)
   constexpr bool kResident0 = C == 32;
   constexpr int NR0 = kResident0 ? MT * T32::NK0 : 1, NRO = MT, NRH = kResident0 ? MT * MT : 1;
-  f4 acc0[NR0], accO[NRO], accH[NRH];
+  f4 acc0[NR0], accO[NRO], accH[NRH], accH2[NRH];
 #pragma unroll
   for (int k = 0; k < NR0; ++k) acc0[k] = zero;
 #pragma unroll
   for (int k = 0; k < NRO; ++k) accO[k] = zero;
 #pragma unroll
-  for (int k = 0; k < NRH; ++k) accH[k] = zero;
+  for (int k = 0; k < NRH; ++k) accH[k] = accH2[k] = zero;
   load_point(wave);
   for (long long c = wave; c < nchunks; c += n_waves) {
     const long long idx = c * S + lane;
@@ -955,7 +956,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
       if (i == 0) {
         if (!kResident0) load_tiles(T32::tile_l0(0, 0), MT * T32::NK0, oldw);
       } else {
-        if (!kResident0 || i != H - 1) load_tiles(T32::tile_h(H, i, 0, 0), MT * MT, oldw);
+        if (!kResident0 || i < H - 2) load_tiles(T32::tile_h(H, i, 0, 0), MT * MT, oldw);
       }
       const h4* ad = reinterpret_cast<const h4*>(actd + i * TH::ACTD);
       // delta_i = (d L / d h_i) * act'(a_i), world units
@@ -1021,6 +1022,8 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
             const VT a = *reinterpret_cast<const VT*>(dbuf + (16 * mo + nn) * HSTR + 4 * g);
             if (kResident0 && i == H - 1) {
               accH[mo * MT + nk] += PR::mmt(a, b, zero) * inv_gs;
+            } else if (kResident0 && i == H - 2) {
+              accH2[mo * MT + nk] += PR::mmt(a, b, zero) * inv_gs;
             } else {
               put_tile(T32::tile_h(H, i, mo, nk), oldw[mo * MT + nk], PR::mmt(a, b, zero) * inv_gs);
             }
@@ -1077,6 +1080,11 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
 #pragma unroll
       for (int k = 0; k < MT * MT; ++k)
         reinterpret_cast<f4*>(slice + T32::tile_h(H, H - 1, k / MT, k % MT) * 256)[lane] = accH[k];
+    }
+    if (H >= 3) {
+#pragma unroll
+      for (int k = 0; k < MT * MT; ++k)
+        reinterpret_cast<f4*>(slice + T32::tile_h(H, H - 2, k / MT, k % MT) * 256)[lane] = accH2[k];
     }
   }
 #pragma unroll
