@@ -270,8 +270,9 @@ typedef struct {
    d_latent [K R^3 F] and d_weights [n_weights] are overwritten with the
    gradients (d_weights bitwise reproducible; d_latent gathered per vertex
    over the points of its eight cells after a counting sort of the points by
-   cell, whose order within a cell may vary between calls, so d_latent is
-   reproducible to rounding). n < 2^31. With adam != NULL the latent grids and the weights are then
+   cell (for a single keyframe summed per cell and corner first), whose order
+   within a cell may vary between calls, so d_latent is reproducible to
+   rounding). n < 2^31. With adam != NULL the latent grids and the weights are then
    updated in place (lr_grid for the latent grids, lr_mlp for the weights).
    out_loss (nullable, device FP32 scalar) receives the loss. workspace
    (16-byte aligned) must hold fvsrn_train_workspace_size(desc, n) bytes. */
