@@ -325,7 +325,8 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
   // the same sums in the same order as the slice's read-modify-write.
   // So do the last hidden layer's, and at every width the output layer's.
   constexpr bool kResident0 = C == 32;
-  constexpr int NR0 = kResident0 ? MT * TC::NK0 : 1, NRO = MT, NRH = kResident0 ? MT * MT : 1;
+  constexpr int R0 = kResident0 ? MT : 1;  // layer-0 M-tiles held (the first one at c = 48)
+  constexpr int NR0 = R0 * TC::NK0, NRO = MT, NRH = kResident0 ? MT * MT : 1;
   f4 acc0[NR0], accO[NRO], accH[NRH];
 #pragma unroll
   for (int k = 0; k < NR0; ++k) acc0[k] = f4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -481,7 +482,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
       constexpr int NW = MT * (TC::NK0 > MT ? TC::NK0 : MT);
       f4 oldw[NW];
       if (i == 0) {
-        if (!kResident0) load_tiles(TC::tile_l0(0, 0), MT * TC::NK0, oldw);
+        if (R0 < MT) load_tiles(TC::tile_l0(R0, 0), (MT - R0) * TC::NK0, oldw + R0 * TC::NK0);
       } else {
         if (!kResident0 || i != H - 1) load_tiles(TC::tile_h(H, i, 0, 0), MT * MT, oldw);
       }
@@ -527,7 +528,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
               const float b = col < G::KROW ? feat[s * G::ROW + col] : 0.0f;
               dw = PR::mma(a, b, dw);
             }
-            if constexpr (kResident0) {
+            if (mo < R0) {
               acc0[mo * TC::NK0 + nk] += dw;
             } else {
               put_tile(TC::tile_l0(mo, nk), oldw[mo * TC::NK0 + nk], dw);
@@ -617,10 +618,10 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_kernel(NetDe
     }
     first = false;
   }
-  if constexpr (kResident0) {
 #pragma unroll
-    for (int k = 0; k < MT * TC::NK0; ++k)
-      reinterpret_cast<f4*>(slice + TC::tile_l0(k / TC::NK0, k % TC::NK0) * 256)[lane] = acc0[k];
+  for (int k = 0; k < NR0; ++k)
+    reinterpret_cast<f4*>(slice + TC::tile_l0(k / TC::NK0, k % TC::NK0) * 256)[lane] = acc0[k];
+  if constexpr (kResident0) {
     if (H >= 2) {
 #pragma unroll
       for (int k = 0; k < MT * MT; ++k)
@@ -805,7 +806,8 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
   // registers for c = 32, the output layer's at every width (see
   // fwd_bwd_kernel, which keeps one hidden layer's: a second spills there)
   constexpr bool kResident0 = C == 32;
-  constexpr int NR0 = kResident0 ? MT * T32::NK0 : 1, NRO = MT, NRH = kResident0 ? MT * MT : 1;
+  constexpr int R0 = kResident0 ? MT : 1;  // layer-0 M-tiles held (the first one at c = 48)
+  constexpr int NR0 = R0 * T32::NK0, NRO = MT, NRH = kResident0 ? MT * MT : 1;
   f4 acc0[NR0], accO[NRO], accH[NRH], accH2[NRH];
 #pragma unroll
   for (int k = 0; k < NR0; ++k) acc0[k] = zero;
@@ -954,7 +956,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
       constexpr int NW = MT * (T32::NK0 > MT ? T32::NK0 : MT);
       f4 oldw[NW];
       if (i == 0) {
-        if (!kResident0) load_tiles(T32::tile_l0(0, 0), MT * T32::NK0, oldw);
+        if (R0 < MT) load_tiles(T32::tile_l0(R0, 0), (MT - R0) * T32::NK0, oldw + R0 * T32::NK0);
       } else {
         if (!kResident0 || i < H - 2) load_tiles(T32::tile_h(H, i, 0, 0), MT * MT, oldw);
       }
@@ -1005,7 +1007,7 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
 #pragma unroll
           for (int mo = 0; mo < MT; ++mo) {
             const VT a = *reinterpret_cast<const VT*>(dbuf + (16 * mo + nn) * HSTR + 4 * g);
-            if constexpr (kResident0) {
+            if (mo < R0) {
               acc0[mo * T32::NK0 + nk] += PR::mmt(a, b, zero) * cs;
             } else {
               put_tile(T32::tile_l0(mo, nk), oldw[mo * T32::NK0 + nk], PR::mmt(a, b, zero) * cs);
@@ -1072,10 +1074,10 @@ __global__ __launch_bounds__(kTrainWavesPerBlock * 64) void fwd_bwd_h_kernel(
     }
     first = false;
   }
-  if constexpr (kResident0) {
 #pragma unroll
-    for (int k = 0; k < MT * T32::NK0; ++k)
-      reinterpret_cast<f4*>(slice + T32::tile_l0(k / T32::NK0, k % T32::NK0) * 256)[lane] = acc0[k];
+  for (int k = 0; k < NR0; ++k)
+    reinterpret_cast<f4*>(slice + T32::tile_l0(k / T32::NK0, k % T32::NK0) * 256)[lane] = acc0[k];
+  if constexpr (kResident0) {
     if (H >= 2) {
 #pragma unroll
       for (int k = 0; k < MT * MT; ++k)
