@@ -7,7 +7,8 @@
 // grid-independent assignment: chunk c goes to wave c mod n_waves; one MFMA
 // N-tile per chunk keeps the per-wave LDS small enough for six waves per CU).
 // Per chunk:
-//   1. every lane writes its point's input row to LDS (as in evaluation);
+//   1. the wave's 64 lanes write the chunk's 16 input rows to LDS, four lanes
+//      per point (write_row_quad);
 //   2. forward through the layers on 16x16x4 FP32 MFMA, keeping every
 //      pre-activation a_i in LDS (sample-major);
 //   3. output sigmoid, loss and dL/dy (for a 4-output network fitted with
@@ -17,14 +18,17 @@
 //      the chunk's samples (A = delta, B = layer input, both read from LDS);
 //   5. dL/dz = W_0[:, latent]^T delta_0, stored per point with the point's
 //      latent cell (and the cell's point count).
-// The latent gradient is then gathered, not scattered: the points are
+// dW tiles are summed per wave over its chunks (no atomics, so dW is bitwise
+// reproducible): the tiles that fit stay in registers, the hidden layers'
+// bias gradients in a small LDS area, the rest are added into the wave's
+// workspace slice; each wave writes its sums to its slice at the end.
+// slice_sum_kernel and gather_kernel then sum the slices in a fixed order
+// into the packed gradient; adam_kernel applies the update.
+// The latent gradient is gathered, not scattered: the points are
 // counting-sorted by cell (the cell scan kernels, bin_points_kernel) and every
 // grid vertex sums the trilinear-weighted dL/dz of the points in its (up to)
-// eight cells (latent_grad_kernel), with plain stores.
-// dW tiles are added into the wave's private workspace slice (no atomics, so
-// dW is bitwise reproducible). slice_sum_kernel and gather_kernel then sum the
-// slices in a fixed order into the packed gradient; adam_kernel applies the
-// update.
+// eight cells, in two passes (cell_partials_kernel, vertex_sum_kernel) or one
+// (latent_grad_kernel), with plain stores.
 #include <cmath>
 #include <mutex>
 
