@@ -81,6 +81,32 @@ def test_train_gradients_full_batch(FV):
     assert abs(loss.item() - loss_ref) <= 1e-5 * abs(loss_ref) + 1e-7
 
 
+@pytest.mark.parametrize("spec_name", ["NET_STUDY", "NET_SHADED"])
+def test_train_gradients_full_batch_study_and_shaded(FV, spec_name):
+    """A full 2^18-point batch on the 32^3 x 16 study grid (8.8 points per
+    cell: the latent gradient's two-pass form, per-cell corner sums then per
+    vertex) and on the 64^3 x 16 grid of the 4 x 48 network (about one point
+    per cell: the one-pass gather; layer 0's first tile row in registers),
+    FP32 and FP16 network passes, against the oracle."""
+    spec = getattr(I, spec_name)
+    n = 1 << 18
+    gnet, onet, xyz = _setup(FV, spec, 23, n)
+    d = O.eval_points(onet, xyz)
+    rng = np.random.default_rng(24)
+    target = (d + rng.uniform(0.01, 0.3, n) * rng.choice([-1, 1], n)).astype(np.float32)
+    dl_ref, dw_ref, loss_ref = O.train_grads(onet, xyz, target=target.astype(np.float64))
+    for prec, tol in (("f32", 1e-4), ("f16", 3e-3)):
+        d_lat = torch.empty_like(gnet.latent)
+        d_w = torch.empty_like(gnet.weights)
+        loss = torch.zeros(1, device="cuda")
+        FV.fvsrn_train_step(gnet, d_lat, d_w, torch.from_numpy(xyz).cuda(), target=torch.from_numpy(target).cuda(),
+                            out_loss=loss, precision=prec)
+        e_w, e_l = _rel(d_w.cpu().numpy(), dw_ref), _rel(d_lat.cpu().numpy(), dl_ref)
+        print("train full batch %s %s: dW rel err %.3g, dG rel err %.3g" % (spec_name, prec, e_w, e_l), flush=True)
+        assert e_w <= tol and e_l <= tol
+        assert abs(loss.item() - loss_ref) <= 2e-5
+
+
 def test_train_gradients_many_chunks_per_wave(FV):
     """More points than waves x chunk: waves walk several chunks and the
     reduction runs over every group of wave slices."""
