@@ -293,7 +293,8 @@ size_t fvsrn_train_workspace_size(const fvsrn_net_desc* desc, int64_t n);
    on each GPU, allocated with the library's code object and held until the
    process ends. A step whose fvsrn_train_workspace_size exceeds that returns
    FVSRN_ERR_WORKSPACE before any launch (e.g. 2^18 points fit the 32^3 x 16,
-   4 x 32 network, 82 MiB, but not the 64^3 x 16, 4 x 48 one, 132 MiB).
+   4 x 32 network, 82 MiB, and the 64^3 x 16, 4 x 48 one, 76 MiB; 3 x 2^18
+   points on the latter, 114 MiB, do not).
    Every call on one GPU shares that GPU's array and the kernels overwrite
    or clear what they use, so calls that overlap on one GPU (other streams,
    other host threads) race and must be serialised by the caller. The

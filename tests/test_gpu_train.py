@@ -86,7 +86,8 @@ def test_train_gradients_full_batch_study_and_shaded(FV, spec_name):
     """A full 2^18-point batch on the 32^3 x 16 study grid (8.8 points per
     cell: the latent gradient's two-pass form, per-cell corner sums then per
     vertex) and on the 64^3 x 16 grid of the 4 x 48 network (about one point
-    per cell: the one-pass gather; layer 0's first tile row in registers),
+    per cell: the one-pass gather; layer 0's first tile row in registers;
+    1024 waves of sixteen 16-point chunks),
     FP32 and FP16 network passes, against the oracle."""
     spec = getattr(I, spec_name)
     n = 1 << 18

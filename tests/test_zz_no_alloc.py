@@ -82,8 +82,8 @@ def test_train_step_noalloc_matches_workspace_entry(FV, calls):
 
 
 def test_train_step_noalloc_refuses_a_step_above_its_workspace(FV):
-    spec = I.NET_SHADED  # 2^18 points need 132 MiB of workspace
-    n = 1 << 18
+    spec = I.NET_SHADED  # 3 x 2^18 points need 114 MiB of workspace
+    n = 3 << 18
     assert FV.fvsrn_train_workspace_size(spec, n) > (96 << 20)
     lat, w = I.net_params(spec, 3)
     net = FV.Network(spec, lat, w, device="cuda")
